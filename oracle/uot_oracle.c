@@ -1,0 +1,388 @@
+/*
+ * FP64 CPU oracle for entropic KL-unbalanced optimal transport
+ * (Sejourne, Vialard, Peyre, "Faster Unbalanced Optimal Transport:
+ * Translation invariant Sinkhorn and 1-D Frank-Wolfe", AISTATS 2022).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do. It shares no code with the GPU path.
+ *
+ * Written to be checked by eye against the paper: every quantity is the plain
+ * definition, evaluated in double precision with std libm exp/log, a
+ * log-sum-exp with an explicit max, no blocking, no fusion, no fast-math.
+ * OpenMP only splits independent outer loops (one row or one column each).
+ *
+ * Notation (Sec. 1 and Sec. 3 of the paper):
+ *   Smin_w^s(h)  = -s log sum_k w_k exp(-h_k / s)            (softmin)
+ *   k1 = rho1/(eps+rho1), k2 = rho2/(eps+rho2)               (KL anisotropic prox)
+ *   tau1 = rho1/(rho1+rho2), tau2 = rho2/(rho1+rho2)         (Prop. 3)
+ * Weights enter as log-weights; a zero weight (log = -inf) drops its term from
+ * every sum (the nu_i = 0 convention of the Csiszar divergence, Sec. 1).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int n, m, d;          /* n source points (alpha), m target points (beta), point dimension */
+  const double *C;      /* dense cost, row-major n x m with leading dimension ldc; NULL => points */
+  long ldc;
+  const double *x;      /* points mode: x [n, d] row-major */
+  const double *y;      /* points mode: y [m, d] row-major */
+  double p;             /* points mode: C_ij = ||x_i - y_j||_2^p */
+} or_cost;
+
+/* Cost entry C_ij (Sec. 1: C_ij = d(x_i, y_j)^p when built from points). */
+static double or_c(const or_cost *k, int i, int j) {
+  if (k->C) return k->C[(long)i * k->ldc + j];
+  double s = 0.0;
+  for (int t = 0; t < k->d; ++t) {
+    double u = k->x[(long)i * k->d + t] - k->y[(long)j * k->d + t];
+    s += u * u;
+  }
+  if (k->p == 2.0) return s;
+  return pow(sqrt(s), k->p);
+}
+
+/* log sum_k exp(v_k) over entries with v_k > -inf; -inf if there are none. */
+static double or_lse(int n, const double *v) {
+  double mx = -INFINITY;
+  for (int k = 0; k < n; ++k)
+    if (v[k] > mx) mx = v[k];
+  if (mx == -INFINITY) return -INFINITY;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k)
+    if (v[k] > -INFINITY) acc += exp(v[k] - mx);
+  return mx + log(acc);
+}
+
+/* Softmin of Sec. 3 on a vector: Smin_w^s(h) = -s log sum_k w_k exp(-h_k/s). */
+double or_smin_vec(int n, const double *logw, const double *h, double s) {
+  double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int k = 0; k < n; ++k) v[k] = (logw[k] == -INFINITY) ? -INFINITY : logw[k] - h[k] / s;
+  double r = -s * or_lse(n, v);
+  free(v);
+  return r;
+}
+
+/* Column softmin (g-side half-step): out_j = Smin_alpha^eps(C_{:,j} - h)
+ *   = -eps log sum_i alpha_i exp((h_i - C_ij)/eps),  j = 0..m-1. */
+void or_smin_cols(const or_cost *k, const double *loga, const double *h, double eps, double *out) {
+  const int n = k->n, m = k->m;
+#pragma omp parallel
+  {
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+    for (int j = 0; j < m; ++j) {
+      for (int i = 0; i < n; ++i)
+        v[i] = (loga[i] == -INFINITY) ? -INFINITY : loga[i] + (h[i] - or_c(k, i, j)) / eps;
+      out[j] = -eps * or_lse(n, v);
+    }
+    free(v);
+  }
+}
+
+/* Row softmin (f-side half-step): out_i = Smin_beta^eps(C_{i,:} - h)
+ *   = -eps log sum_j beta_j exp((h_j - C_ij)/eps),  i = 0..n-1. */
+void or_smin_rows(const or_cost *k, const double *logb, const double *h, double eps, double *out) {
+  const int n = k->n, m = k->m;
+#pragma omp parallel
+  {
+    double *v = (double *)malloc(sizeof(double) * (size_t)m);
+#pragma omp for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < m; ++j)
+        v[j] = (logb[j] == -INFINITY) ? -INFINITY : logb[j] + (h[j] - or_c(k, i, j)) / eps;
+      out[i] = -eps * or_lse(m, v);
+    }
+    free(v);
+  }
+}
+
+static double sup_diff(int n, const double *a, const double *b) {
+  double r = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double u = fabs(a[k] - b[k]);
+    if (u > r) r = u;
+  }
+  return r;
+}
+
+/* Optimal translation lambda*(fb, gb) of Prop. 2, written through softmins:
+ * lambda* = tau1 * Smin_beta^rho2(gb) - tau2 * Smin_alpha^rho1(fb). */
+double or_lambda_star(int n, int m, const double *loga, const double *logb, const double *fb,
+                      const double *gb, double rho1, double rho2) {
+  const double tau1 = rho1 / (rho1 + rho2), tau2 = rho2 / (rho1 + rho2);
+  return tau1 * or_smin_vec(m, logb, gb, rho2) - tau2 * or_smin_vec(n, loga, fb, rho1);
+}
+
+/*
+ * Sinkhorn solver.
+ *   ti = 0: F-Sinkhorn (Sec. 3): g <- k2 Smin_alpha^eps(C - f), then f <- k1 Smin_beta^eps(C - g).
+ *           The g-update uses rho2 and the f-update rho1 (first-order conditions of F_eps in g and f).
+ *   ti = 1: H-Sinkhorn, general rho1, rho2 (App. B, derivation of Prop. 4, eq. general-iter-h-sink):
+ *           gh = k2 Smin_alpha^eps(C - fb) - eps*rho2/((eps+rho2)(rho1+rho2)) Smin_alpha^rho1(fb)
+ *           gb = gh + kg/(1-kg) Smin_beta^rho2(gh),   kg = eps*rho1/((eps+rho2)(rho1+rho2))
+ *           fh = k1 Smin_beta^eps(C - gb) - eps*rho1/((eps+rho1)(rho1+rho2)) Smin_beta^rho2(gb)
+ *           fb = fh + kf/(1-kf) Smin_alpha^rho1(fh),  kf = eps*rho2/((eps+rho1)(rho1+rho2))
+ *           and reports Phi(fb, gb) = (fb + lambda*, gb - lambda*) (Sec. 1 / App. B map Phi).
+ * One iteration = g-step then f-step; f starts at 0 unless warm_start (f then holds f_0,
+ * or fb_0 for ti = 1). After each iteration t the change
+ *   delta_t = max(||f_t - f_{t-1}||_inf, ||g_t - g_{t-1}||_inf)
+ * is computed on the reported (translated) potentials; if tol > 0 the solver stops at the
+ * first t with t % check_every == 0 and delta_t < tol. delta_1 uses g_0 = the g the first
+ * half-step would see as "previous": it is defined as +inf.
+ * Optional histories (NULL to skip): hist_delta[max_iter], hist_f[max_iter*n], hist_g[max_iter*m].
+ * Returns the number of iterations run; writes f, g, *lambda_out (0 for ti = 0), *last_delta.
+ */
+int or_sinkhorn(const or_cost *k, const double *alpha, const double *beta, double eps, double rho1,
+                double rho2, int ti, int max_iter, double tol, int check_every, int warm_start,
+                double *f, double *g, double *lambda_out, double *last_delta, double *hist_delta,
+                double *hist_f, double *hist_g) {
+  const int n = k->n, m = k->m;
+  double *loga = (double *)malloc(sizeof(double) * (size_t)n);
+  double *logb = (double *)malloc(sizeof(double) * (size_t)m);
+  for (int i = 0; i < n; ++i) loga[i] = log(alpha[i]);
+  for (int j = 0; j < m; ++j) logb[j] = log(beta[j]);
+  const double k1 = rho1 / (eps + rho1), k2 = rho2 / (eps + rho2);
+  double *fb = (double *)malloc(sizeof(double) * (size_t)n);  /* f (plain) or fb (TI) */
+  double *gb = (double *)malloc(sizeof(double) * (size_t)m);
+  double *S = (double *)malloc(sizeof(double) * (size_t)(n > m ? n : m));
+  double *fo = (double *)malloc(sizeof(double) * (size_t)n);  /* reported f, previous iteration */
+  double *go = (double *)malloc(sizeof(double) * (size_t)m);
+  double *fr = (double *)malloc(sizeof(double) * (size_t)n);  /* reported f, this iteration */
+  double *gr = (double *)malloc(sizeof(double) * (size_t)m);
+  for (int i = 0; i < n; ++i) fb[i] = warm_start ? f[i] : 0.0;
+  for (int j = 0; j < m; ++j) gb[j] = 0.0;
+  double lam = 0.0, delta = INFINITY;
+  int t = 0;
+  for (t = 1; t <= max_iter; ++t) {
+    if (!ti) {
+      or_smin_cols(k, loga, fb, eps, S);
+      for (int j = 0; j < m; ++j) gb[j] = k2 * S[j];
+      or_smin_rows(k, logb, gb, eps, S);
+      for (int i = 0; i < n; ++i) fb[i] = k1 * S[i];
+      memcpy(fr, fb, sizeof(double) * (size_t)n);
+      memcpy(gr, gb, sizeof(double) * (size_t)m);
+    } else {
+      const double cg = eps * rho2 / ((eps + rho2) * (rho1 + rho2));
+      const double kg = eps * rho1 / ((eps + rho2) * (rho1 + rho2));
+      const double cf = eps * rho1 / ((eps + rho1) * (rho1 + rho2));
+      const double kf = eps * rho2 / ((eps + rho1) * (rho1 + rho2));
+      double sA = or_smin_vec(n, loga, fb, rho1);
+      or_smin_cols(k, loga, fb, eps, S);
+      for (int j = 0; j < m; ++j) gb[j] = k2 * S[j] - cg * sA;          /* gh */
+      double tg = kg / (1.0 - kg) * or_smin_vec(m, logb, gb, rho2);
+      for (int j = 0; j < m; ++j) gb[j] += tg;                          /* gb */
+      double sB = or_smin_vec(m, logb, gb, rho2);
+      or_smin_rows(k, logb, gb, eps, S);
+      for (int i = 0; i < n; ++i) fb[i] = k1 * S[i] - cf * sB;          /* fh */
+      double tf = kf / (1.0 - kf) * or_smin_vec(n, loga, fb, rho1);
+      for (int i = 0; i < n; ++i) fb[i] += tf;                          /* fb */
+      lam = or_lambda_star(n, m, loga, logb, fb, gb, rho1, rho2);
+      for (int i = 0; i < n; ++i) fr[i] = fb[i] + lam;
+      for (int j = 0; j < m; ++j) gr[j] = gb[j] - lam;
+    }
+    if (t == 1) {
+      delta = INFINITY;
+    } else {
+      double a = sup_diff(n, fr, fo), b = sup_diff(m, gr, go);
+      delta = a > b ? a : b;
+    }
+    if (hist_delta) hist_delta[t - 1] = delta;
+    if (hist_f) memcpy(hist_f + (size_t)(t - 1) * n, fr, sizeof(double) * (size_t)n);
+    if (hist_g) memcpy(hist_g + (size_t)(t - 1) * m, gr, sizeof(double) * (size_t)m);
+    memcpy(fo, fr, sizeof(double) * (size_t)n);
+    memcpy(go, gr, sizeof(double) * (size_t)m);
+    if (tol > 0 && check_every > 0 && t % check_every == 0 && delta < tol) break;
+  }
+  if (t > max_iter) t = max_iter;
+  memcpy(f, fo, sizeof(double) * (size_t)n);
+  memcpy(g, go, sizeof(double) * (size_t)m);
+  if (lambda_out) *lambda_out = ti ? lam : 0.0;
+  if (last_delta) *last_delta = delta;
+  free(loga); free(logb); free(fb); free(gb); free(S); free(fo); free(go); free(fr); free(gr);
+  return t;
+}
+
+/* Plan entry pi_ij = alpha_i beta_j exp((f_i + g_j - C_ij)/eps) (primal-dual link of the dual problem). */
+static double or_pi(const or_cost *k, const double *alpha, const double *beta, double eps,
+                    const double *f, const double *g, int i, int j) {
+  if (alpha[i] == 0.0 || beta[j] == 0.0) return 0.0;
+  return alpha[i] * beta[j] * exp((f[i] + g[j] - or_c(k, i, j)) / eps);
+}
+
+/* Plan application: transpose = 0: out[i, c] = sum_j pi_ij V[j, c]  (V is m x kc, out n x kc);
+ *                   transpose = 1: out[j, c] = sum_i pi_ij V[i, c]  (V is n x kc, out m x kc).
+ * With V = ones this gives the marginals pi_1 = pi 1 and pi_2 = pi^T 1 (Sec. 1). */
+void or_plan_apply(const or_cost *k, const double *alpha, const double *beta, double eps,
+                   const double *f, const double *g, int transpose, const double *V, int kc,
+                   double *out) {
+  const int n = k->n, m = k->m;
+  if (!transpose) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      for (int c = 0; c < kc; ++c) out[(long)i * kc + c] = 0.0;
+      for (int j = 0; j < m; ++j) {
+        double p = or_pi(k, alpha, beta, eps, f, g, i, j);
+        for (int c = 0; c < kc; ++c) out[(long)i * kc + c] += p * V[(long)j * kc + c];
+      }
+    }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; ++j) {
+      for (int c = 0; c < kc; ++c) out[(long)j * kc + c] = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double p = or_pi(k, alpha, beta, eps, f, g, i, j);
+        for (int c = 0; c < kc; ++c) out[(long)j * kc + c] += p * V[(long)i * kc + c];
+      }
+    }
+  }
+}
+
+/* Total plan mass m(pi) = sum_ij pi_ij. */
+static double or_plan_mass(const or_cost *k, const double *alpha, const double *beta, double eps,
+                           const double *f, const double *g) {
+  const int n = k->n, m = k->m;
+  double tot = 0.0;
+#pragma omp parallel for reduction(+ : tot) schedule(static)
+  for (int i = 0; i < n; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < m; ++j) r += or_pi(k, alpha, beta, eps, f, g, i, j);
+    tot += r;
+  }
+  return tot;
+}
+
+/* Dual functional F_eps of eq. (dual-uot-kl) for rho KL penalties, with
+ * -phi*(-f) = rho (1 - exp(-f/rho)) (the KL conjugate, as written in the proof of Prop. 3):
+ * F = rho1 <alpha, 1 - e^{-f/rho1}> + rho2 <beta, 1 - e^{-g/rho2}> - eps (m(pi) - m(alpha) m(beta)). */
+double or_dual_value(const or_cost *k, const double *alpha, const double *beta, double eps,
+                     double rho1, double rho2, const double *f, const double *g) {
+  const int n = k->n, m = k->m;
+  double a = 0.0, b = 0.0, ma = 0.0, mb = 0.0;
+  for (int i = 0; i < n; ++i) { a += alpha[i] * (1.0 - exp(-f[i] / rho1)); ma += alpha[i]; }
+  for (int j = 0; j < m; ++j) { b += beta[j] * (1.0 - exp(-g[j] / rho2)); mb += beta[j]; }
+  double mpi = or_plan_mass(k, alpha, beta, eps, f, g);
+  return rho1 * a + rho2 * b - eps * (mpi - ma * mb);
+}
+
+/* Generalised KL(mu | nu) = sum mu log(mu/nu) - m(mu) + m(nu) (Sec. 1), with 0 log 0 = 0;
+ * +inf when some nu_i = 0 < mu_i. */
+static double or_kl(int n, const double *mu, const double *nu) {
+  double r = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (mu[k] > 0.0) {
+      if (nu[k] == 0.0) return INFINITY;
+      r += mu[k] * log(mu[k] / nu[k]);
+    }
+    r += nu[k] - mu[k];
+  }
+  return r;
+}
+
+/* Primal objective of eq. (primal-uot-kl) at the plan built from (f, g):
+ * P(pi) = <pi, C> + eps KL(pi | alpha x beta) + rho1 KL(pi_1 | alpha) + rho2 KL(pi_2 | beta). */
+double or_primal_value(const or_cost *k, const double *alpha, const double *beta, double eps,
+                       double rho1, double rho2, const double *f, const double *g) {
+  const int n = k->n, m = k->m;
+  double *p1 = (double *)calloc((size_t)n, sizeof(double));
+  double *p2 = (double *)calloc((size_t)m, sizeof(double));
+  double lin = 0.0, klpi = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j) {
+      double ab = alpha[i] * beta[j];
+      double p = or_pi(k, alpha, beta, eps, f, g, i, j);
+      p1[i] += p;
+      p2[j] += p;
+      lin += p * or_c(k, i, j);
+      if (p > 0.0) klpi += p * log(p / ab);
+      klpi += ab - p;
+    }
+  double r = lin + eps * klpi + rho1 * or_kl(n, p1, alpha) + rho2 * or_kl(m, p2, beta);
+  free(p1); free(p2);
+  return r;
+}
+
+/* Translation-invariant functional H_eps of Prop. 3 (eq. dual-form-hell). */
+double or_h_value(const or_cost *k, const double *alpha, const double *beta, double eps,
+                  double rho1, double rho2, const double *fb, const double *gb) {
+  const int n = k->n, m = k->m;
+  const double tau1 = rho1 / (rho1 + rho2), tau2 = rho2 / (rho1 + rho2);
+  double ma = 0.0, mb = 0.0, A = 0.0, B = 0.0;
+  for (int i = 0; i < n; ++i) { ma += alpha[i]; A += alpha[i] * exp(-fb[i] / rho1); }
+  for (int j = 0; j < m; ++j) { mb += beta[j]; B += beta[j] * exp(-gb[j] / rho2); }
+  double mpi = or_plan_mass(k, alpha, beta, eps, fb, gb);
+  return rho1 * ma + rho2 * mb - eps * (mpi - ma * mb) - (rho1 + rho2) * pow(A, tau1) * pow(B, tau2);
+}
+
+/*
+ * Envelope-theorem gradients of UOT = sup F_eps at optimal (f, g), each scaled by gout:
+ *   dUOT/dalpha_i = rho1 (1 - e^{-f_i/rho1}) - eps (sum_j beta_j e^{(f_i+g_j-C_ij)/eps} - m(beta))
+ *   dUOT/dbeta_j  = rho2 (1 - e^{-g_j/rho2}) - eps (sum_i alpha_i e^{(f_i+g_j-C_ij)/eps} - m(alpha))
+ *   dUOT/dx_i     = sum_j pi_ij grad_x c(x_i, y_j),  dUOT/dy_j = sum_i pi_ij grad_y c(x_i, y_j)
+ * with c = ||x - y||^p, grad_x c = p ||x-y||^{p-2} (x - y) (taken as 0 at x = y).
+ * These are the partial derivatives of eq. (dual-uot-kl) in (alpha, beta, C), as the
+ * envelope argument of Prop. 1 uses them. Any output pointer may be NULL.
+ */
+void or_gradients(const or_cost *k, const double *alpha, const double *beta, double eps, double rho1,
+                  double rho2, const double *f, const double *g, double gout, double *dx, double *dy,
+                  double *dalpha, double *dbeta) {
+  const int n = k->n, m = k->m, d = k->d;
+  double ma = 0.0, mb = 0.0;
+  for (int i = 0; i < n; ++i) ma += alpha[i];
+  for (int j = 0; j < m; ++j) mb += beta[j];
+  if (dalpha) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < m; ++j)
+        if (beta[j] != 0.0) s += beta[j] * exp((f[i] + g[j] - or_c(k, i, j)) / eps);
+      dalpha[i] = gout * (rho1 * (1.0 - exp(-f[i] / rho1)) - eps * (s - mb));
+    }
+  }
+  if (dbeta) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (alpha[i] != 0.0) s += alpha[i] * exp((f[i] + g[j] - or_c(k, i, j)) / eps);
+      dbeta[j] = gout * (rho2 * (1.0 - exp(-g[j] / rho2)) - eps * (s - ma));
+    }
+  }
+  if (k->C) return; /* dense cost: no point gradients */
+  if (dx) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      for (int t = 0; t < d; ++t) dx[(long)i * d + t] = 0.0;
+      for (int j = 0; j < m; ++j) {
+        double p = or_pi(k, alpha, beta, eps, f, g, i, j);
+        double s = 0.0;
+        for (int t = 0; t < d; ++t) {
+          double u = k->x[(long)i * d + t] - k->y[(long)j * d + t];
+          s += u * u;
+        }
+        double w = (k->p == 2.0) ? 2.0 : (s > 0.0 ? k->p * pow(sqrt(s), k->p - 2.0) : 0.0);
+        for (int t = 0; t < d; ++t)
+          dx[(long)i * d + t] += gout * p * w * (k->x[(long)i * d + t] - k->y[(long)j * d + t]);
+      }
+    }
+  }
+  if (dy) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; ++j) {
+      for (int t = 0; t < d; ++t) dy[(long)j * d + t] = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double p = or_pi(k, alpha, beta, eps, f, g, i, j);
+        double s = 0.0;
+        for (int t = 0; t < d; ++t) {
+          double u = k->x[(long)i * d + t] - k->y[(long)j * d + t];
+          s += u * u;
+        }
+        double w = (k->p == 2.0) ? 2.0 : (s > 0.0 ? k->p * pow(sqrt(s), k->p - 2.0) : 0.0);
+        for (int t = 0; t < d; ++t)
+          dy[(long)j * d + t] += gout * p * w * (k->y[(long)j * d + t] - k->x[(long)i * d + t]);
+      }
+    }
+  }
+}

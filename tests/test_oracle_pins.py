@@ -1,0 +1,405 @@
+"""Pins of the FP64 oracle to what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: a closed form, a second
+independent algorithm (dense Newton), an exact identity the paper proves, a limit case
+reducing to a textbook routine, or a finite-difference derivative. Together they are
+chosen so that a dropped term, a wrong sign, a swapped rho or a transposed operand in the
+oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.helpers import oracle_cost, rel_inf
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _solve(cost, a, b, eps, r1, r2, ti=True, tol=1e-14, max_iter=200000, **kw):
+    return oracle.sinkhorn(cost, a, b, eps, r1, r2, ti=ti, max_iter=max_iter, tol=tol,
+                           check_every=1, **kw)
+
+
+# ---------------------------------------------------------------------------------------
+# P9: N = M = 1 closed form. Minimising the primal of eq. (primal-uot-kl) over a scalar
+# pi >= 0 gives (eps + rho1 + rho2) log pi = (eps + rho1) log a + (eps + rho2) log b - c;
+# the optimality condition pi_1 = a e^{-f/rho1} gives f = -rho1 log(pi/a) (and g alike);
+# substituting the first-order condition into the primal gives
+# UOT = rho1 (a - pi) + rho2 (b - pi) + eps (a b - pi).
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("ti", [False, True])
+@pytest.mark.parametrize("a,b,c,eps,r1,r2", [
+    (0.7, 1.9, 0.3, 0.1, 1.0, 2.5),
+    (1.0, 1.5, 2.0, 0.5, 0.2, 0.2),
+    (2.0, 0.3, 0.0, 0.05, 3.0, 0.7),
+])
+def test_p9_one_point_closed_form(ti, a, b, c, eps, r1, r2):
+    pi = math.exp(((eps + r1) * math.log(a) + (eps + r2) * math.log(b) - c) / (eps + r1 + r2))
+    f_cf = -r1 * math.log(pi / a)
+    g_cf = -r2 * math.log(pi / b)
+    val_cf = r1 * (a - pi) + r2 * (b - pi) + eps * (a * b - pi)
+    cost = oracle.Cost(C=np.array([[c]]))
+    r = _solve(cost, [a], [b], eps, r1, r2, ti=ti)
+    assert abs(r.f[0] - f_cf) <= 1e-12 * max(1.0, abs(f_cf))
+    assert abs(r.g[0] - g_cf) <= 1e-12 * max(1.0, abs(g_cf))
+    assert abs(oracle.dual_value(cost, [a], [b], eps, r1, r2, r.f, r.g) - val_cf) <= 1e-12
+    assert abs(oracle.primal_value(cost, [a], [b], eps, r1, r2, r.f, r.g) - val_cf) <= 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# P10: tiny problems, Sinkhorn fixed point == dense Newton maximiser of F_eps.
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m", [(1, 2), (2, 1), (2, 3), (3, 5), (5, 4), (8, 7), (8, 8)])
+@pytest.mark.parametrize("ti", [False, True])
+def test_p10_newton_matches_sinkhorn(n, m, ti):
+    rng = np.random.default_rng(100 * n + m)
+    C = rng.uniform(0.0, 2.0, size=(n, m))  # not symmetric, not square: catches transposes
+    a = rng.uniform(0.2, 1.0, size=n)
+    b = rng.uniform(0.2, 1.5, size=m)
+    eps, r1, r2 = 0.3, 0.7, 2.0  # rho1 != rho2: catches a swapped penalty
+    fN, gN, gradn, _ = oracle.newton_dual(C, a, b, eps, r1, r2)
+    assert gradn < 1e-13
+    r = _solve(oracle.Cost(C=C), a, b, eps, r1, r2, ti=ti)
+    assert np.max(np.abs(r.f - fN)) < 1e-11
+    assert np.max(np.abs(r.g - gN)) < 1e-11
+
+
+# ---------------------------------------------------------------------------------------
+# P1 (same fixed point, Thm. of App. B), P2 (marginals at optimum), P3 (zero duality gap).
+# ---------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def medium():
+    pr = workloads.random_small(37, 29, d=2, seed=7, eps=0.05, rho1=0.4, rho2=1.7,
+                                mass_a=1.0, mass_b=1.6)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    plain = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=False)
+    ti = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True)
+    return pr, cost, a, b, plain, ti
+
+
+def test_p1_plain_and_ti_same_fixed_point(medium):
+    pr, cost, a, b, plain, ti = medium
+    assert plain.last_delta < 1e-14 and ti.last_delta < 1e-14
+    assert np.max(np.abs(plain.f - ti.f)) < 1e-12
+    assert np.max(np.abs(plain.g - ti.g)) < 1e-12
+    assert ti.iters < plain.iters  # TI is faster (Thm. 1)
+
+
+def test_p2_marginals_at_optimum(medium):
+    pr, cost, a, b, plain, ti = medium
+    p1, p2 = oracle.marginals(cost, a, b, pr.eps, ti.f, ti.g)
+    assert np.max(np.abs(p1 - a * np.exp(-ti.f / pr.rho1))) < 1e-13
+    assert np.max(np.abs(p2 - b * np.exp(-ti.g / pr.rho2))) < 1e-13
+
+
+def test_p3_zero_duality_gap(medium):
+    pr, cost, a, b, plain, ti = medium
+    P = oracle.primal_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti.f, ti.g)
+    F = oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti.f, ti.g)
+    assert P - F > -1e-12
+    assert P - F < 1e-12
+    # a non-optimal pair leaves a strictly positive gap
+    F0 = oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti.f + 0.05, ti.g)
+    P0 = oracle.primal_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti.f + 0.05, ti.g)
+    assert P0 - F0 > 1e-6
+
+
+def test_p3_monotone_dual_along_iterates():
+    """Both algorithms are exact block maximisations: F increases along plain iterates, and
+    H = F o Phi increases along TI iterates (Sec. 3)."""
+    pr = workloads.random_small(12, 9, d=2, seed=3, eps=0.05, rho1=1.0, rho2=0.5)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    for ti in (False, True):
+        r = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=ti, max_iter=60,
+                            history_potentials=True)
+        vals = [oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.hist_f[t], r.hist_g[t])
+                for t in range(r.iters)]
+        assert np.all(np.diff(vals) >= -1e-13), (ti, np.min(np.diff(vals)))
+
+
+# ---------------------------------------------------------------------------------------
+# P4: plain Sinkhorn started at f* + tau: f_t = f* + (k1 k2)^t tau exactly (Sec. 1 example).
+# P5: TI started at f* + tau is back at (f*, g*) after one iteration (Psi(f + tau) = Psi(f) - tau).
+# ---------------------------------------------------------------------------------------
+def test_p4_translation_mode_of_plain_sinkhorn(medium):
+    pr, cost, a, b, plain, ti = medium
+    k = pr.rho1 / (pr.eps + pr.rho1) * pr.rho2 / (pr.eps + pr.rho2)
+    tau = 0.37
+    r = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=False, max_iter=25,
+                        f0=ti.f + tau, history_potentials=True)
+    for t in range(1, 26):
+        expect = ti.f + k ** t * tau
+        assert np.max(np.abs(r.hist_f[t - 1] - expect)) < 1e-13
+        # g_t = g* - k2 (k1 k2)^{t-1} tau
+        k2 = pr.rho2 / (pr.eps + pr.rho2)
+        assert np.max(np.abs(r.hist_g[t - 1] - (ti.g - k2 * k ** (t - 1) * tau))) < 1e-13
+
+
+@pytest.mark.parametrize("tau", [-3.0, 0.0, 0.5, 11.0])
+def test_p5_ti_translation_invariance(medium, tau):
+    pr, cost, a, b, plain, ti = medium
+    r = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, max_iter=1, f0=ti.f + tau)
+    assert np.max(np.abs(r.f - ti.f)) < 1e-13
+    assert np.max(np.abs(r.g - ti.g)) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------
+# P6: the empirical rate (median estimator of Sec. 3) of plain Sinkhorn equals
+# (rho/(eps+rho))^2 on the 1-D measures, and TI's rate is strictly smaller.
+# ---------------------------------------------------------------------------------------
+def test_p6_empirical_rates_oned():
+    pr = workloads.oned()
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    star = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True)
+    assert star.last_delta < 1e-14
+    rp = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=False, max_iter=1500,
+                         history_potentials=True)
+    rt = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, max_iter=400,
+                         history_potentials=True)
+    kp = oracle.empirical_rate(rp.hist_f, star.f, floor=1e-11)
+    kt = oracle.empirical_rate(rt.hist_f, star.f, floor=1e-11)
+    expect = (pr.rho1 / (pr.eps + pr.rho1)) ** 2
+    assert abs(kp - expect) < 1e-4, (kp, expect)
+    assert kt < kp - 0.01, (kt, kp)
+
+
+# ---------------------------------------------------------------------------------------
+# P7: Prop. 1/2 (equal tilted masses at lambda*), Prop. 3 (H = F o Phi), H invariance.
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p7_lambda_star_and_h(seed):
+    rng = np.random.default_rng(seed)
+    pr = workloads.random_small(9, 11, d=3, seed=seed, eps=0.2, rho1=0.3 + seed, rho2=1.1)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    fb = rng.normal(size=9)
+    gb = rng.normal(size=11)
+    lam = oracle.lambda_star(a, b, fb, gb, pr.rho1, pr.rho2)
+    ma = np.sum(a * np.exp(-(fb + lam) / pr.rho1))
+    mb = np.sum(b * np.exp(-(gb - lam) / pr.rho2))
+    assert abs(ma - mb) < 1e-13 * max(ma, mb)
+    H = oracle.h_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, fb, gb)
+    F = oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, fb + lam, gb - lam)
+    assert abs(H - F) < 1e-13 * max(1.0, abs(F))
+    H2 = oracle.h_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, fb + 1.7, gb - 1.7)
+    assert abs(H2 - H) < 1e-13 * max(1.0, abs(H))
+    # lambda* maximises G(lambda) = F(fb + lambda, gb - lambda)
+    for dl in (-1e-3, 1e-3):
+        assert oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, fb + lam + dl, gb - lam - dl) < F
+
+
+# ---------------------------------------------------------------------------------------
+# P8: one TI iteration is non-expansive: by the chain of App. B (Phi 1-Lipschitz into the
+# (**)-norm, Upsilon 2-Lipschitz from the Hilbert norm, Psi contracting by rho/(eps+rho)),
+# ||f_1 - f_1'||_inf + ||g_1 - g_1'||_inf <= 2 (rho/(eps+rho)) ||fb_0 - fb_0'||_star.
+# ---------------------------------------------------------------------------------------
+def test_p8_ti_iteration_lipschitz():
+    pr = workloads.random_small(14, 10, d=2, seed=11, eps=0.1, rho1=0.8, rho2=0.8)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    rng = np.random.default_rng(5)
+    kfac = pr.rho1 / (pr.eps + pr.rho1)
+    for _ in range(20):
+        f0 = rng.normal(size=14)
+        f1 = f0 + rng.normal(scale=rng.uniform(0.01, 1.0), size=14)
+        r0 = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, max_iter=1, f0=f0)
+        r1 = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, max_iter=1, f0=f1)
+        lhs = np.max(np.abs(r0.f - r1.f)) + np.max(np.abs(r0.g - r1.g))
+        assert lhs <= 2 * kfac * oracle.hilbert_norm(f0 - f1) + 1e-14
+
+
+# ---------------------------------------------------------------------------------------
+# P11: rho -> infinity recovers balanced entropic OT (Sec. 1), solved here by the textbook
+# scaling iteration u = a / (K v), v = b / (K^T u) with Gibbs kernel K = exp(-C/eps).
+# ---------------------------------------------------------------------------------------
+def test_p11_large_rho_is_balanced():
+    pr = workloads.random_small(15, 12, d=2, seed=21, eps=0.1, rho1=1e6, rho2=1e6,
+                                mass_a=1.0, mass_b=1.0)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    b = b * (a.sum() / b.sum())  # equal masses exactly in float64
+    C = cost.dense()
+    K = np.exp(-C / pr.eps)
+    v = np.ones(len(b))
+    for _ in range(20000):
+        u = a / (K @ v)
+        v = b / (K.T @ u)
+    pi_bal = u[:, None] * K * v[None, :]
+    r = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, tol=1e-13)
+    pi = a[:, None] * b[None, :] * np.exp((r.f[:, None] + r.g[None, :] - C) / pr.eps)
+    assert np.sum(np.abs(pi - pi_bal)) < 1e-5
+
+
+# ---------------------------------------------------------------------------------------
+# P12: envelope gradients equal central finite differences of the converged value.
+# ---------------------------------------------------------------------------------------
+def _uot_value(x, y, a, b, eps, r1, r2):
+    cost = oracle.Cost(x=x, y=y, p=2.0)
+    r = _solve(cost, a, b, eps, r1, r2, ti=True, tol=1e-15, max_iter=100000)
+    return oracle.dual_value(cost, a, b, eps, r1, r2, r.f, r.g)
+
+
+def test_p12_envelope_gradients_match_finite_differences():
+    pr = workloads.random_small(6, 5, d=2, seed=4, eps=0.2, rho1=0.9, rho2=1.4)
+    x, y = pr.x.astype(np.float64), pr.y.astype(np.float64)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    cost = oracle.Cost(x=x, y=y, p=2.0)
+    r = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, tol=1e-15)
+    gout = 1.7
+    dx, dy, da, db = oracle.gradients(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.f, r.g, gout)
+    h = 1e-5
+    args = (pr.eps, pr.rho1, pr.rho2)
+    for i in range(6):
+        e = np.zeros(6); e[i] = h
+        fd = (_uot_value(x, y, a + e, b, *args) - _uot_value(x, y, a - e, b, *args)) / (2 * h)
+        assert abs(gout * fd - da[i]) < 1e-7 * max(1.0, abs(da[i]))
+        for t in range(2):
+            ex = np.zeros_like(x); ex[i, t] = h
+            fd = (_uot_value(x + ex, y, a, b, *args) - _uot_value(x - ex, y, a, b, *args)) / (2 * h)
+            assert abs(gout * fd - dx[i, t]) < 1e-7 * max(1.0, abs(dx[i, t]))
+    for j in range(5):
+        e = np.zeros(5); e[j] = h
+        fd = (_uot_value(x, y, a, b + e, *args) - _uot_value(x, y, a, b - e, *args)) / (2 * h)
+        assert abs(gout * fd - db[j]) < 1e-7 * max(1.0, abs(db[j]))
+        for t in range(2):
+            ey = np.zeros_like(y); ey[j, t] = h
+            fd = (_uot_value(x, y + ey, a, b, *args) - _uot_value(x, y - ey, a, b, *args)) / (2 * h)
+            assert abs(gout * fd - dy[j, t]) < 1e-7 * max(1.0, abs(dy[j, t]))
+
+
+def test_p12_dense_alpha_gradient_general_p():
+    """Dense cost with p = 1.5 (the stored-cost workload's exponent): dalpha, dbeta by FD."""
+    pr = workloads.random_small(5, 4, d=3, seed=8, eps=0.15, rho1=0.5, rho2=0.5, p=1.5, dense=True)
+    C = pr.C.astype(np.float64)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+
+    def val(a_, b_):
+        cost = oracle.Cost(C=C)
+        r = _solve(cost, a_, b_, pr.eps, pr.rho1, pr.rho2, ti=True, tol=1e-15)
+        return oracle.dual_value(cost, a_, b_, pr.eps, pr.rho1, pr.rho2, r.f, r.g)
+
+    cost = oracle.Cost(C=C)
+    r = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, tol=1e-15)
+    _, _, da, db = oracle.gradients(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.f, r.g)
+    h = 1e-5
+    for i in range(5):
+        e = np.zeros(5); e[i] = h
+        assert abs((val(a + e, b) - val(a - e, b)) / (2 * h) - da[i]) < 1e-7
+    for j in range(4):
+        e = np.zeros(4); e[j] = h
+        assert abs((val(a, b + e) - val(a, b - e)) / (2 * h) - db[j]) < 1e-7
+
+
+def test_p12_point_gradient_general_p():
+    """Points with p = 1.5: dx by FD (checks the p ||x-y||^{p-2} (x-y) factor)."""
+    pr = workloads.random_small(4, 5, d=2, seed=9, eps=0.2, rho1=1.0, rho2=1.0, p=1.5)
+    x, y = pr.x.astype(np.float64), pr.y.astype(np.float64)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+
+    def val(x_):
+        cost = oracle.Cost(x=x_, y=y, p=1.5)
+        r = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, tol=1e-15)
+        return oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.f, r.g)
+
+    cost = oracle.Cost(x=x, y=y, p=1.5)
+    r = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True, tol=1e-15)
+    dx, _, _, _ = oracle.gradients(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.f, r.g)
+    h = 1e-6
+    for i in range(4):
+        for t in range(2):
+            e = np.zeros_like(x); e[i, t] = h
+            assert abs((val(x + e) - val(x - e)) / (2 * h) - dx[i, t]) < 1e-7
+
+
+# ---------------------------------------------------------------------------------------
+# P13: Hilbert-metric contraction of the softmin (Birkhoff): for K = exp(-C/eps),
+# ||Smin(C - f) - Smin(C - f')||_star <= tanh(Delta/4) ||f - f'||_star,
+# Delta = max_{i,k,j,l} (C_il + C_kj - C_ij - C_kl)/eps  (the (1-eta)/(1+eta) reading).
+# ---------------------------------------------------------------------------------------
+def test_p13_birkhoff_contraction():
+    pr = workloads.random_small(7, 6, d=2, seed=13, eps=0.5)
+    cost = oracle_cost(pr)
+    a = pr.alpha.astype(np.float64)
+    C = cost.dense()
+    D4 = C[:, None, None, :] + C[None, :, :, None] - C[:, None, :, None] - C[None, :, None, :]
+    # D4[i, k, j, l] = C_il + C_kj - C_ij - C_kl
+    Delta = np.max(D4) / pr.eps
+    bound = math.tanh(Delta / 4)
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for _ in range(50):
+        f = rng.normal(size=7)
+        f2 = f + rng.normal(scale=0.3, size=7)
+        s1 = oracle.smin_cols(cost, a, f, pr.eps)
+        s2 = oracle.smin_cols(cost, a, f2, pr.eps)
+        ratio = oracle.hilbert_norm(s1 - s2) / oracle.hilbert_norm(f - f2)
+        worst = max(worst, ratio)
+    assert worst <= bound + 1e-12
+    assert worst > 0.1 * bound  # the bound is not vacuous on this problem
+
+
+# ---------------------------------------------------------------------------------------
+# Softmin special cases and plan-apply adjoint identity.
+# ---------------------------------------------------------------------------------------
+def test_softmin_special_cases():
+    # one point: Smin_w^s(h) = h - s log w
+    assert abs(oracle.smin_vec([0.3], [1.2], 0.7) - (1.2 - 0.7 * math.log(0.3))) < 1e-15
+    # constant h: Smin_w^s(c) = c - s log m(w)
+    w = np.array([0.1, 0.5, 0.7])
+    assert abs(oracle.smin_vec(w, [2.0, 2.0, 2.0], 0.3) - (2.0 - 0.3 * math.log(w.sum()))) < 1e-14
+    # small s tends to the min; a zero weight drops its entry
+    assert abs(oracle.smin_vec([1.0, 1.0], [0.5, 3.0], 1e-3) - 0.5) < 1e-12
+    assert abs(oracle.smin_vec([0.0, 1.0], [-5.0, 3.0], 0.2) - 3.0) < 1e-15
+    # column/row softmins on a dense matrix against the vector softmin per column/row
+    rng = np.random.default_rng(1)
+    C = rng.uniform(size=(4, 3))
+    a, b = rng.uniform(0.1, 1, 4), rng.uniform(0.1, 1, 3)
+    h, k = rng.normal(size=4), rng.normal(size=3)
+    cols = oracle.smin_cols(oracle.Cost(C=C), a, h, 0.2)
+    rows = oracle.smin_rows(oracle.Cost(C=C), b, k, 0.2)
+    for j in range(3):
+        assert abs(cols[j] - oracle.smin_vec(a, C[:, j] - h, 0.2)) < 1e-14
+    for i in range(4):
+        assert abs(rows[i] - oracle.smin_vec(b, C[i, :] - k, 0.2)) < 1e-14
+
+
+def test_plan_apply_adjoint_and_points_vs_dense():
+    pr = workloads.random_small(9, 7, d=3, seed=2, eps=0.3)
+    cost = oracle_cost(pr)
+    dense = oracle.Cost(C=cost.dense())
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    rng = np.random.default_rng(0)
+    f, g = rng.normal(size=9) * 0.1, rng.normal(size=7) * 0.1
+    V = rng.normal(size=(7, 2))
+    U = rng.normal(size=(9, 2))
+    PV = oracle.plan_apply(cost, a, b, pr.eps, f, g, V)
+    PtU = oracle.plan_apply(cost, a, b, pr.eps, f, g, U, transpose=True)
+    assert abs(np.sum(U * PV) - np.sum(PtU * V)) < 1e-13
+    assert rel_inf(oracle.plan_apply(dense, a, b, pr.eps, f, g, V), PV) < 1e-13
+    # pi_ij from basis vectors matches the one-point closed form structure a_i b_j e^{...}
+    e = np.zeros(7); e[3] = 1.0
+    col = oracle.plan_apply(cost, a, b, pr.eps, f, g, e)
+    C = cost.dense()
+    assert abs(col[5] - a[5] * b[3] * math.exp((f[5] + g[3] - C[5, 3]) / pr.eps)) < 1e-15
+
+
+def test_zero_weight_convention():
+    """A zero weight drops its point from every sum (nu_i = 0 convention, Sec. 1): the
+    solution on the other points equals the solution of the problem without it."""
+    pr = workloads.random_small(6, 5, d=2, seed=17, eps=0.1, rho1=0.6, rho2=0.9)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64).copy(), pr.beta.astype(np.float64)
+    a[2] = 0.0
+    r = _solve(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=True)
+    keep = [0, 1, 3, 4, 5]
+    cost2 = oracle.Cost(x=pr.x.astype(np.float64)[keep], y=pr.y.astype(np.float64), p=2.0)
+    r2 = _solve(cost2, a[keep], b, pr.eps, pr.rho1, pr.rho2, ti=True)
+    assert np.max(np.abs(r.f[keep] - r2.f)) < 1e-12
+    assert np.max(np.abs(r.g - r2.g)) < 1e-12
+    assert np.isfinite(r.f[2])
