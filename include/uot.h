@@ -1,0 +1,215 @@
+/*
+ * uot.h - C ABI of libuot.so: entropic KL-unbalanced optimal transport on AMD Instinct
+ * MI355X (gfx950), plain Sinkhorn and translation-invariant (TI) Sinkhorn.
+ *
+ * Method: Sejourne, Vialard, Peyre, "Faster Unbalanced Optimal Transport: Translation
+ * invariant Sinkhorn and 1-D Frank-Wolfe", AISTATS 2022.
+ *
+ * Problem (Sec. 1, eq. primal-uot-kl, with D_phi = rho KL):
+ *   UOT(alpha, beta) = inf_{pi >= 0} <pi, C> + eps KL(pi | alpha x beta)
+ *                      + rho1 KL(pi 1 | alpha) + rho2 KL(pi^T 1 | beta)
+ * and its dual (eq. dual-uot-kl), UOT = sup_{f,g} F_eps(f, g) with
+ *   F_eps(f, g) = rho1 <alpha, 1 - e^{-f/rho1}> + rho2 <beta, 1 - e^{-g/rho2}>
+ *                 - eps <alpha x beta, e^{(f + g - C)/eps} - 1>.
+ * The optimal plan is pi_ij = alpha_i beta_j exp((f_i + g_j - C_ij)/eps).
+ *
+ * Conventions shared by every entry point
+ *  - All array pointers are DEVICE pointers (memory returned by hipMalloc or a PyTorch
+ *    CUDA/HIP tensor) unless the comment says (host). The caller owns all memory; the
+ *    library never frees or retains a caller pointer after the call returns.
+ *  - Arrays are float32, dense and row-major unless stated; sizes are element counts.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Work is ordered on it.
+ *  - Scalars eps, rho1, rho2, p are double in the ABI and are rounded once to the
+ *    working precision on the device; masses, lambda*, convergence tests and the dual
+ *    value are accumulated in double precision.
+ *  - Errors are reported by return code only (no exceptions, no abort). Arguments that
+ *    can be checked on the host are validated before any launch; then outputs are left
+ *    untouched. Weight arrays are checked on the device by the first kernel of a call
+ *    (negative, NaN or infinite weights, or a zero total mass, give UOT_ERR_INVALID and
+ *    leave the caller's outputs untouched).
+ *  - Workspace: every call that needs scratch memory takes `workspace` and its size
+ *    `workspace_bytes`. Query the size with uot_workspace_bytes(). A NULL workspace makes
+ *    the call allocate (and free) its own with hipMalloc; a non-NULL workspace smaller
+ *    than required gives UOT_ERR_WORKSPACE. The workspace must not be shared by calls
+ *    that may run concurrently.
+ *  - Calls that return a host value (info, value) synchronise `stream` before returning.
+ *  - Two calls on different streams with different workspaces may run concurrently; the
+ *    library keeps no global mutable state besides a per-device kernel-shape cache that
+ *    is guarded by a mutex.
+ */
+#ifndef UOT_H_
+#define UOT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  UOT_OK = 0,
+  UOT_ERR_INVALID = 1,   /* bad argument (sizes, pointers, eps/rho/p, weights)             */
+  UOT_ERR_HIP = 2,       /* a HIP runtime call failed (message in uot_last_error())        */
+  UOT_ERR_NUMERIC = 3,   /* non-finite potentials or value were produced                   */
+  UOT_ERR_WORKSPACE = 4  /* workspace too small                                             */
+} uot_status;
+
+typedef enum {
+  UOT_COST_DENSE = 0,    /* C given as a stored matrix                                      */
+  UOT_COST_POINTS = 1    /* C_ij = ||x_i - y_j||_2^p evaluated on the fly                   */
+} uot_cost_kind;
+
+/*
+ * Cost description (Sec. 1: C in R^{n x m}, or C_ij = d(x_i, y_j)^p built from points).
+ *  kind = UOT_COST_DENSE:  C points to n rows of ldc floats (row-major, ldc >= m); only
+ *                          the first m entries of each row are read. x, y, d, p unused.
+ *  kind = UOT_COST_POINTS: x is [n, d], y is [m, d] (row-major float32), 1 <= d <= 64,
+ *                          p >= 1 (p = 2 is the squared Euclidean cost and takes the
+ *                          fastest path). C and ldc unused.
+ * n (size of alpha, the "source" side) and m (size of beta) are >= 1.
+ */
+typedef struct {
+  int32_t kind;
+  int32_t n, m, d;
+  const float *C;
+  int64_t ldc;
+  const float *x;
+  const float *y;
+  double p;
+} uot_cost;
+
+/*
+ * Solver parameters.
+ *  eps > 0         entropic regularisation (Sec. 1)
+ *  rho1, rho2 > 0  KL penalty weights on the first and second marginal (finite)
+ *  max_iter >= 1   iteration cap; one iteration = one g-update then one f-update (Sec. 3)
+ *  tol >= 0        stop at the first iteration t with t % check_every == 0 and
+ *                  max(||f_t - f_{t-1}||_inf, ||g_t - g_{t-1}||_inf) < tol, measured on
+ *                  the reported (translated) potentials; tol = 0 runs exactly max_iter
+ *  check_every>=1  period of the convergence test
+ *  warm_start      0: start from f_0 = 0; 1: read the starting f_0 from the f argument
+ *                  (for TI the start is the translation-invariant potential fb_0; passing
+ *                  the f returned by an earlier TI call resumes that run)
+ */
+typedef struct {
+  double eps, rho1, rho2;
+  int32_t max_iter;
+  double tol;
+  int32_t check_every;
+  int32_t warm_start;
+} uot_params;
+
+/* Per-call report (host). */
+typedef struct {
+  int32_t iters;        /* iterations run                                                  */
+  int32_t converged;    /* 1 if the tol test passed, else 0 (max_iter reached or tol = 0)  */
+  double last_change;   /* the change measured at the last iteration (inf after one)       */
+  double lambda;        /* TI: lambda*(fb, gb) of Prop. 2 at the last iterate; plain: 0    */
+} uot_info;
+
+enum {
+  UOT_WS_SOLVE = 0,     /* uot_sinkhorn, uot_ti_sinkhorn                                   */
+  UOT_WS_DUAL = 1,      /* uot_dual_value                                                  */
+  UOT_WS_PLAN = 2,      /* uot_plan_apply (size independent of k up to k = 64)             */
+  UOT_WS_BACKWARD = 3   /* uot_backward                                                    */
+};
+
+/* Workspace bytes needed by the entry point `which` for this cost (0 on invalid input). */
+size_t uot_workspace_bytes(const uot_cost *cost, int32_t which);
+
+/*
+ * Plain (F-) Sinkhorn of Sec. 3 for rho KL penalties: alternate exact maximisation of
+ * F_eps, in the log domain:
+ *   g_j <- rho2/(eps+rho2) * Smin_alpha^eps(C_{:,j} - f)
+ *   f_i <- rho1/(eps+rho1) * Smin_beta^eps(C_{i,:} - g)
+ * with Smin_w^eps(h) = -eps log sum_k w_k exp(-h_k/eps) (the softmin of Sec. 3) and the
+ * KL anisotropic prox x -> rho/(eps+rho) x.
+ *  alpha [n], beta [m]: nonnegative weights (zero weights allowed; a zero weight removes
+ *                       its point from every sum), any total masses > 0.
+ *  f [n]: in (if warm_start) / out; g [m]: out. The dual potentials of the last iterate.
+ *  info (host, may be NULL): iterations, convergence flag, last change.
+ */
+uot_status uot_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,
+                        const uot_params *params, float *f, float *g, void *workspace,
+                        size_t workspace_bytes, uot_info *info, void *stream);
+
+/*
+ * Translation-invariant (H-) Sinkhorn of Sec. 3 (Prop. 4) for general rho1, rho2 (App. B,
+ * eq. general-iter-h-sink): alternate maximisation of H_eps(fb, gb) = sup_lambda
+ * F_eps(fb + lambda, gb - lambda), each half-step a softmin followed by the KL prox and a
+ * scalar translation computed from the tilted mass <alpha, e^{-fb/rho1}> (resp. beta).
+ * Same arguments and conventions as uot_sinkhorn. The returned f, g are the translated
+ * potentials Phi(fb, gb) = (fb + lambda*, gb - lambda*) with lambda* of Prop. 2, i.e. the
+ * F-potentials, which converge to the same unique optimum as plain Sinkhorn.
+ */
+uot_status uot_ti_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,
+                           const uot_params *params, float *f, float *g, void *workspace,
+                           size_t workspace_bytes, uot_info *info, void *stream);
+
+/*
+ * Dual value F_eps(f, g) of eq. (dual-uot-kl), which equals UOT(alpha, beta) at the
+ * optimal potentials. m(pi) is obtained from one row-softmin pass over C:
+ * m(pi) = sum_i alpha_i exp((f_i - Smin_beta^eps(C_{i,:} - g))/eps).
+ *  f [n], g [m]: potentials; value (host): result. Synchronises the stream.
+ */
+uot_status uot_dual_value(const uot_cost *cost, const float *alpha, const float *beta, double eps,
+                          double rho1, double rho2, const float *f, const float *g, void *workspace,
+                          size_t workspace_bytes, double *value, void *stream);
+
+/*
+ * Plan application with pi_ij = alpha_i beta_j exp((f_i + g_j - C_ij)/eps), pi never stored:
+ *  transpose = 0: out[i, c] = sum_j pi_ij V[j, c],  V is [m, k] (leading dim ldv >= k),
+ *                 out is [n, k] (leading dim ldout >= k)
+ *  transpose = 1: out[j, c] = sum_i pi_ij V[i, c],  V is [n, k], out is [m, k]
+ * 1 <= k <= 64. V = NULL means a column of ones (k must be 1): the marginals pi 1 and
+ * pi^T 1 of Sec. 1. Each output row is computed with its own running max of the exponent,
+ * so pi V is exact up to rounding even where individual entries of e^{f+g-C} overflow.
+ */
+uot_status uot_plan_apply(const uot_cost *cost, const float *alpha, const float *beta, double eps,
+                          const float *f, const float *g, int32_t transpose, const float *V,
+                          int32_t k, int64_t ldv, float *out, int64_t ldout, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/*
+ * Envelope-theorem gradients of UOT = sup F_eps at the given (converged) potentials,
+ * each multiplied by grad_out (the partial derivatives of eq. dual-uot-kl, pi recomputed
+ * tile by tile and never stored):
+ *   dalpha_i = rho1 (1 - e^{-f_i/rho1}) - eps (sum_j beta_j e^{(f_i+g_j-C_ij)/eps} - m(beta))
+ *   dbeta_j  = rho2 (1 - e^{-g_j/rho2}) - eps (sum_i alpha_i e^{(f_i+g_j-C_ij)/eps} - m(alpha))
+ *   dx_i     = sum_j pi_ij p ||x_i - y_j||^{p-2} (x_i - y_j)     (points cost only)
+ *   dy_j     = sum_i pi_ij p ||x_i - y_j||^{p-2} (y_j - x_i)     (points cost only)
+ * (the gradient of ||x - y||^p is taken as 0 at x = y).
+ * dx [n, d], dy [m, d], dalpha [n], dbeta [m]: outputs; any may be NULL (dx, dy must be
+ * NULL for a dense cost).
+ */
+uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *beta, double eps,
+                        double rho1, double rho2, const float *f, const float *g, double grad_out,
+                        float *dx, float *dy, float *dalpha, float *dbeta, void *workspace,
+                        size_t workspace_bytes, void *stream);
+
+/*
+ * Kernel timing, for benchmarks (off by default). While enabled, every softmin launch of
+ * uot_sinkhorn / uot_ti_sinkhorn is bracketed by two HIP events recorded on the call's
+ * stream, and its duration is accumulated, with the number of cost entries it processed,
+ * per kernel kind: 0 = points-cost softmin, 1 = stored-cost column softmin, 2 = stored-cost
+ * row softmin. Thread-safe (a mutex guards the counters); enabling it adds two event
+ * records per launch.
+ *  uot_profile_read returns the number of timed launches of `kind` (-1 for a bad kind) and
+ *  writes the summed milliseconds and summed entries (host pointers, may be NULL).
+ */
+void uot_profile_enable(int32_t on);
+void uot_profile_reset(void);
+int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries);
+
+/* Static description of a status code. */
+const char *uot_status_string(uot_status s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *uot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UOT_H_ */

@@ -1,0 +1,352 @@
+"""Entropic KL-unbalanced optimal transport on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libuot.so`` (C ABI in ``include/uot.h``): plain Sinkhorn and
+translation-invariant Sinkhorn (Sejourne, Vialard, Peyre, AISTATS 2022, Sec. 3), the dual
+value, plan application and the envelope-theorem backward. Every step of the computation
+runs in the library's HIP kernels; this module only marshals tensors (``data_ptr()``) and
+the current HIP stream. PyTorch provides device memory and streams.
+
+There is no CPU fallback: importing works without a GPU, but every compute call raises if
+the library is missing or no GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_apply", "marginals",
+           "backward", "workspace_bytes", "UOTLoss", "uot_loss", "library_path", "load_library",
+           "profile_enable", "profile_reset", "profile_read"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libuot.so")
+_lib = None
+
+UOT_OK, UOT_ERR_INVALID, UOT_ERR_HIP, UOT_ERR_NUMERIC, UOT_ERR_WORKSPACE = range(5)
+UOT_COST_DENSE, UOT_COST_POINTS = 0, 1
+UOT_WS_SOLVE, UOT_WS_DUAL, UOT_WS_PLAN, UOT_WS_BACKWARD = range(4)
+
+
+class UOTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("uot status %d: %s" % (status, message))
+        self.status = status
+
+
+class _Cost(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("p", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("last_change", ctypes.c_double), ("lambda_", ctypes.c_double)]
+
+
+@dataclass
+class Info:
+    iters: int
+    converged: bool
+    last_change: float
+    lam: float
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libuot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libuot.so is not built; run `python -m paper_2201_00730_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, S, I32, I64, D = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    CP = ctypes.POINTER(_Cost)
+    lib.uot_workspace_bytes.argtypes = [CP, I32]
+    lib.uot_workspace_bytes.restype = S
+    for name in ("uot_sinkhorn", "uot_ti_sinkhorn"):
+        fn = getattr(lib, name)
+        fn.argtypes = [CP, P, P, ctypes.POINTER(_Params), P, P, P, S, ctypes.POINTER(_Info), P]
+        fn.restype = ctypes.c_int
+    lib.uot_dual_value.argtypes = [CP, P, P, D, D, D, P, P, P, S, ctypes.POINTER(D), P]
+    lib.uot_dual_value.restype = ctypes.c_int
+    lib.uot_plan_apply.argtypes = [CP, P, P, D, P, P, I32, P, I32, I64, P, I64, P, S, P]
+    lib.uot_plan_apply.restype = ctypes.c_int
+    lib.uot_backward.argtypes = [CP, P, P, D, D, D, P, P, D, P, P, P, P, P, S, P]
+    lib.uot_backward.restype = ctypes.c_int
+    lib.uot_status_string.argtypes = [ctypes.c_int]
+    lib.uot_status_string.restype = ctypes.c_char_p
+    lib.uot_last_error.argtypes = []
+    lib.uot_last_error.restype = ctypes.c_char_p
+    lib.uot_profile_enable.argtypes = [I32]
+    lib.uot_profile_enable.restype = None
+    lib.uot_profile_reset.argtypes = []
+    lib.uot_profile_reset.restype = None
+    lib.uot_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.uot_profile_read.restype = I64
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != UOT_OK:
+        lib = load_library()
+        raise UOTError(status, (lib.uot_last_error() or b"").decode() or
+                       lib.uot_status_string(status).decode())
+
+
+def _require_gpu():
+    load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the UOT kernels only run on the GPU")
+
+
+def _f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _CostRef:
+    """A uot_cost struct plus the tensors it points into (kept alive)."""
+
+    def __init__(self, C=None, x=None, y=None, p: float = 2.0):
+        s = _Cost()
+        self.keep = []
+        if C is not None:
+            if x is not None or y is not None:
+                raise ValueError("give either C or (x, y)")
+            C = C if C.stride(-1) == 1 else C.contiguous()
+            if C.dim() != 2 or C.dtype != torch.float32 or not C.is_cuda:
+                raise ValueError("C must be a 2-D float32 device tensor")
+            s.kind, s.n, s.m, s.d = UOT_COST_DENSE, C.shape[0], C.shape[1], 0
+            s.C, s.ldc = C.data_ptr(), C.stride(0)
+            s.x = s.y = None
+            s.p = 1.0
+            self.keep.append(C)
+        else:
+            x, y = _f32(x, "x"), _f32(y, "y")
+            if x.dim() == 1:
+                x = x[:, None].contiguous()
+            if y.dim() == 1:
+                y = y[:, None].contiguous()
+            if x.shape[1] != y.shape[1]:
+                raise ValueError("x and y dimensions differ")
+            s.kind, s.n, s.m, s.d = UOT_COST_POINTS, x.shape[0], y.shape[0], x.shape[1]
+            s.C, s.ldc = None, 0
+            s.x, s.y, s.p = x.data_ptr(), y.data_ptr(), float(p)
+            self.keep += [x, y]
+        self.s = s
+
+    @property
+    def n(self):
+        return self.s.n
+
+    @property
+    def m(self):
+        return self.s.m
+
+    @property
+    def device(self):
+        return self.keep[0].device
+
+
+PROFILE_POINTS, PROFILE_DENSE_COLS, PROFILE_DENSE_ROWS = 0, 1, 2
+
+
+def profile_enable(on: bool = True):
+    """Time every softmin launch of the solvers with HIP events on the call's stream."""
+    load_library().uot_profile_enable(int(bool(on)))
+
+
+def profile_reset():
+    load_library().uot_profile_reset()
+
+
+def profile_read(kind: int):
+    """(launches, total_ms, total_entries) accumulated for a softmin kernel kind."""
+    ms, ent = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    n = load_library().uot_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(ent))
+    return int(n), ms.value, ent.value
+
+
+def workspace_bytes(which: int = UOT_WS_SOLVE, *, C=None, x=None, y=None, p: float = 2.0) -> int:
+    lib = load_library()
+    cr = _CostRef(C, x, y, p)
+    return int(lib.uot_workspace_bytes(ctypes.byref(cr.s), int(which)))
+
+
+def _workspace(lib, cr: _CostRef, which: int):
+    nb = int(lib.uot_workspace_bytes(ctypes.byref(cr.s), int(which)))
+    if nb == 0:
+        _check(UOT_ERR_INVALID)
+    return torch.empty(nb, dtype=torch.uint8, device=cr.device)
+
+
+def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, eps: float,
+           rho1: float, rho2: float | None = None, max_iter: int = 1000, tol: float = 0.0,
+           check_every: int = 10, f0=None, workspace=None):
+    _require_gpu()
+    lib = load_library()
+    cr = _CostRef(C, x, y, p)
+    alpha, beta = _f32(alpha, "alpha"), _f32(beta, "beta")
+    if alpha.numel() != cr.n or beta.numel() != cr.m:
+        raise ValueError("alpha/beta sizes do not match the cost")
+    rho2 = rho1 if rho2 is None else rho2
+    f = torch.empty(cr.n, dtype=torch.float32, device=alpha.device)
+    g = torch.empty(cr.m, dtype=torch.float32, device=alpha.device)
+    if f0 is not None:
+        f.copy_(_f32(f0, "f0").reshape(-1))
+    prm = _Params(float(eps), float(rho1), float(rho2), int(max_iter), float(tol), int(check_every),
+                  int(f0 is not None))
+    ws = workspace if workspace is not None else _workspace(lib, cr, UOT_WS_SOLVE)
+    info = _Info()
+    st = getattr(lib, name)(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), ctypes.byref(prm), _ptr(f),
+                            _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(info), _stream())
+    _check(st)
+    return f, g, Info(info.iters, bool(info.converged), info.last_change, info.lambda_)
+
+
+def sinkhorn(alpha, beta, **kw):
+    """Plain (F-) Sinkhorn (Sec. 3). Keyword args: C | (x, y, p), eps, rho1, rho2,
+    max_iter, tol, check_every, f0. Returns (f, g, Info)."""
+    return _solve("uot_sinkhorn", alpha, beta, **kw)
+
+
+def ti_sinkhorn(alpha, beta, **kw):
+    """Translation-invariant (H-) Sinkhorn (Sec. 3, Prop. 4; App. B for rho1 != rho2).
+    Returns the translated potentials Phi(fb, gb) = (f, g) and Info."""
+    return _solve("uot_ti_sinkhorn", alpha, beta, **kw)
+
+
+def dual_value(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: float,
+               rho1: float, rho2: float | None = None) -> float:
+    """F_eps(f, g) of the dual problem (eq. dual-uot-kl)."""
+    _require_gpu()
+    lib = load_library()
+    cr = _CostRef(C, x, y, p)
+    rho2 = rho1 if rho2 is None else rho2
+    alpha, beta, f, g = (_f32(alpha, "alpha"), _f32(beta, "beta"), _f32(f, "f"), _f32(g, "g"))
+    ws = _workspace(lib, cr, UOT_WS_DUAL)
+    out = ctypes.c_double(0.0)
+    _check(lib.uot_dual_value(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), float(eps), float(rho1),
+                              float(rho2), _ptr(f), _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(out),
+                              _stream()))
+    return out.value
+
+
+def plan_apply(alpha, beta, f, g, V=None, *, transpose: bool = False, C=None, x=None, y=None,
+               p: float = 2.0, eps: float):
+    """pi V (or pi^T V) with pi_ij = alpha_i beta_j exp((f_i + g_j - C_ij)/eps); V = None
+    applies to a column of ones (the marginals). Returns [rows, k] (or [rows] for V = None
+    or a 1-D V)."""
+    _require_gpu()
+    lib = load_library()
+    cr = _CostRef(C, x, y, p)
+    alpha, beta, f, g = (_f32(alpha, "alpha"), _f32(beta, "beta"), _f32(f, "f"), _f32(g, "g"))
+    rows = cr.m if transpose else cr.n
+    squeeze = V is None or V.dim() == 1
+    if V is not None:
+        V = _f32(V, "V")
+        if V.dim() == 1:
+            V = V[:, None].contiguous()
+        k, ldv = V.shape[1], V.stride(0)
+    else:
+        k, ldv = 1, 1
+    out = torch.empty((rows, k), dtype=torch.float32, device=alpha.device)
+    ws = _workspace(lib, cr, UOT_WS_PLAN)
+    _check(lib.uot_plan_apply(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), float(eps), _ptr(f), _ptr(g),
+                              int(bool(transpose)), _ptr(V), int(k), int(ldv), _ptr(out), int(k),
+                              _ptr(ws), ws.numel(), _stream()))
+    return out[:, 0] if squeeze else out
+
+
+def marginals(alpha, beta, f, g, **kw):
+    """(pi 1, pi^T 1)."""
+    return (plan_apply(alpha, beta, f, g, None, transpose=False, **kw),
+            plan_apply(alpha, beta, f, g, None, transpose=True, **kw))
+
+
+def backward(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: float, rho1: float,
+             rho2: float | None = None, grad_out: float = 1.0, need_dx: bool = True,
+             need_dy: bool = True, need_dalpha: bool = True, need_dbeta: bool = True):
+    """Envelope gradients of UOT at (f, g): returns (dx, dy, dalpha, dbeta), None where not
+    requested (dx, dy are None for a dense cost)."""
+    _require_gpu()
+    lib = load_library()
+    cr = _CostRef(C, x, y, p)
+    rho2 = rho1 if rho2 is None else rho2
+    alpha, beta, f, g = (_f32(alpha, "alpha"), _f32(beta, "beta"), _f32(f, "f"), _f32(g, "g"))
+    dev = alpha.device
+    pts = cr.s.kind == UOT_COST_POINTS
+    dx = torch.empty((cr.n, cr.s.d), dtype=torch.float32, device=dev) if pts and need_dx else None
+    dy = torch.empty((cr.m, cr.s.d), dtype=torch.float32, device=dev) if pts and need_dy else None
+    da = torch.empty(cr.n, dtype=torch.float32, device=dev) if need_dalpha else None
+    db = torch.empty(cr.m, dtype=torch.float32, device=dev) if need_dbeta else None
+    ws = _workspace(lib, cr, UOT_WS_BACKWARD)
+    _check(lib.uot_backward(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), float(eps), float(rho1),
+                            float(rho2), _ptr(f), _ptr(g), float(grad_out), _ptr(dx), _ptr(dy), _ptr(da),
+                            _ptr(db), _ptr(ws), ws.numel(), _stream()))
+    return dx, dy, da, db
+
+
+class UOTLoss(torch.autograd.Function):
+    """UOT(alpha, beta; x, y) as a differentiable scalar: the forward runs TI Sinkhorn and
+    evaluates the dual value; the backward applies the envelope theorem (gradients of
+    F_eps at the optimal potentials), with the plan recomputed by the backward kernel."""
+
+    @staticmethod
+    def forward(ctx, x, y, alpha, beta, eps, rho1, rho2, p, max_iter, tol, check_every):
+        f, g, info = ti_sinkhorn(alpha.detach(), beta.detach(), x=x.detach(), y=y.detach(), p=p,
+                                 eps=eps, rho1=rho1, rho2=rho2, max_iter=max_iter, tol=tol,
+                                 check_every=check_every)
+        val = dual_value(alpha.detach(), beta.detach(), f, g, x=x.detach(), y=y.detach(), p=p,
+                         eps=eps, rho1=rho1, rho2=rho2)
+        ctx.save_for_backward(x, y, alpha, beta, f, g)
+        ctx.cfg = (eps, rho1, rho2, p)
+        return torch.tensor(val, dtype=torch.float32, device=x.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, y, alpha, beta, f, g = ctx.saved_tensors
+        eps, rho1, rho2, p = ctx.cfg
+        go = float(gout.item())
+        dx, dy, da, db = backward(alpha.detach(), beta.detach(), f, g, x=x.detach(), y=y.detach(), p=p,
+                                  eps=eps, rho1=rho1, rho2=rho2, grad_out=go,
+                                  need_dx=ctx.needs_input_grad[0], need_dy=ctx.needs_input_grad[1],
+                                  need_dalpha=ctx.needs_input_grad[2],
+                                  need_dbeta=ctx.needs_input_grad[3])
+        return dx, dy, da, db, None, None, None, None, None, None, None
+
+
+def uot_loss(x, y, alpha, beta, *, eps: float, rho1: float, rho2: float | None = None, p: float = 2.0,
+             max_iter: int = 10000, tol: float = 1e-6, check_every: int = 10):
+    """Differentiable UOT value between point clouds (see UOTLoss)."""
+    rho2 = rho1 if rho2 is None else rho2
+    return UOTLoss.apply(x, y, alpha, beta, eps, rho1, rho2, p, max_iter, tol, check_every)

@@ -1,0 +1,416 @@
+// O(N + M) kernels around the softmin passes: combine of split partials with the half-step
+// epilogue (KL prox and TI translation), the single-block scalar reductions (tilted masses,
+// lambda*, convergence test), source-record construction, input validation, centring of the
+// point clouds, the final translation of the potentials and the dual-value / weight-gradient
+// terms. Everything scalar is double precision.
+#include <cfloat>
+
+#include "uot_internal.h"
+
+namespace uot {
+namespace {
+
+// Log-sum-exp pair (max, sum of exp(v - max)) merge; (-inf, 0) is the neutral element.
+__device__ __forceinline__ void lse_merge(double &m, double &s, double mo, double so) {
+  const double mn = fmax(m, mo);
+  if (mn == -INFINITY) { m = mn; s = 0.0; return; }
+  s = s * exp(m - mn) + so * exp(mo - mn);
+  m = mn;
+}
+
+// Block-wide reduction of (lse max, lse sum, max, min) over 256 threads.
+__device__ void block_reduce_part(double &mm, double &ms, double &dmx, double &dmn) {
+  __shared__ double s0[kBlock], s1[kBlock], s2[kBlock], s3[kBlock];
+  const int t = threadIdx.x;
+  s0[t] = mm; s1[t] = ms; s2[t] = dmx; s3[t] = dmn;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      double a = s0[t], b = s1[t];
+      lse_merge(a, b, s0[t + off], s1[t + off]);
+      s0[t] = a; s1[t] = b;
+      s2[t] = fmax(s2[t], s2[t + off]);
+      s3[t] = fmin(s3[t], s3[t + off]);
+    }
+    __syncthreads();
+  }
+  mm = s0[0]; ms = s1[0]; dmx = s2[0]; dmn = s3[0];
+  __syncthreads();
+}
+
+__device__ double block_sum(double v) {
+  __shared__ double s[kBlock];
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (t < off) s[t] += s[t + off];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// Log2-sum over the split partials of one target: M + log2(sum_p l_p 2^{m_p - M}).
+__device__ __forceinline__ double combine_lse2(const float2 *part, int nsplit, int nt, int t) {
+  float M = -FLT_MAX;
+  for (int p = 0; p < nsplit; ++p) M = fmaxf(M, part[(size_t)p * nt + t].x);
+  double L = 0.0;
+  for (int p = 0; p < nsplit; ++p) {
+    const float2 q = part[(size_t)p * nt + t];
+    L += (double)q.y * exp2((double)q.x - (double)M);
+  }
+  return (double)M + log2(L);
+}
+
+// Centred coordinates of one target (as the softmin kernels form them) and their squared norm.
+template <int D>
+__device__ __forceinline__ double centred(const float *pts, int d, int t, const double *mu,
+                                          float *yc) {
+  double n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    yc[k] = k < d ? pts[(size_t)t * d + k] - (float)mu[k] : 0.0f;
+    n2 += (double)yc[k] * (double)yc[k];
+  }
+  return n2;
+}
+
+// Writes the source record of point t with stored potential hf (see rec_stride).
+template <int D, int MODE>
+__device__ __forceinline__ void write_record(float *rec, int t, const float *yc, double yn2,
+                                             float hf, float w, double sc) {
+  const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
+  float *rp = rec + (size_t)t * rec_stride(MODE, D);
+  if constexpr (MODE == kSqEuc) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
+    rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
+  } else if constexpr (MODE == kPower) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) rp[k] = yc[k];
+    rp[D] = (float)(sc * (double)hf + lw2);
+  } else {
+    rp[0] = (float)(sc * (double)hf + lw2);
+  }
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
+  if (a.st->done) return;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+  if (t < a.nt) {
+    double lse2 = combine_lse2(a.part, a.nsplit, a.nt, t);
+    float yc[D > 0 ? D : 1];
+    double yn2 = 0.0;
+    if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, t, a.st->mu, yc);
+    if constexpr (MODE == kSqEuc) lse2 -= a.sc * yn2;
+    const double S = -lse2 / a.sc;  // softmin over the stored source potential
+    const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
+    const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
+    const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
+    const float hf = (float)hnew;
+    const float old = a.pot[t];
+    a.pot[t] = hf;
+    dmx = dmn = (double)hf - (double)old;
+    const float w = a.w[t];
+    write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
+    if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
+    if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);
+  }
+  block_reduce_part(mm, ms, dmx, dmn);
+  if (threadIdx.x == 0) a.bparts[blockIdx.x] = BlockPart{mm, ms, dmx, dmn};
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_build_records(RecordArgs a) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  double mm = -INFINITY, ms = 0.0, dmx = 0.0, dmn = 0.0;
+  if (t < a.n) {
+    const double h = (a.pot ? (double)a.pot[t] : 0.0) + a.pot_off;
+    const float hf = (float)h;
+    if (a.pot_copy) a.pot_copy[t] = hf;
+    float yc[D > 0 ? D : 1];
+    double yn2 = 0.0;
+    if constexpr (MODE != kDense) yn2 = centred<D>(a.pts, a.d, t, a.st->mu, yc);
+    const float w = a.w[t];
+    write_record<D, MODE>(a.rec, t, yc, yn2, hf, w, a.sc);
+    if (w > 0.0f) { mm = log((double)w) - (double)hf / a.rho; ms = 1.0; }
+  }
+  if (a.bparts) {
+    block_reduce_part(mm, ms, dmx, dmn);
+    if (threadIdx.x == 0) a.bparts[blockIdx.x] = BlockPart{mm, ms, dmx, dmn};
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
+  SolveState *st = a.st;
+  if (a.kind != kReduceInit && st->done) return;
+  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+  for (int b = threadIdx.x; b < a.nb; b += kBlock) {
+    const BlockPart q = a.bparts[b];
+    lse_merge(mm, ms, q.mass_max, q.mass_sum);
+    dmx = fmax(dmx, q.dmax);
+    dmn = fmin(dmn, q.dmin);
+  }
+  block_reduce_part(mm, ms, dmx, dmn);
+  if (threadIdx.x != 0) return;
+  const double L = (mm == -INFINITY) ? -INFINITY : mm + log(ms);  // log of the tilted mass
+  if (a.kind == kReduceInit) {
+    st->iter = 0;
+    st->tau_f = st->tau_g = st->lambda = 0.0;
+    st->off_f_prev = st->off_g_prev = 0.0;
+    st->gdiff_max = st->gdiff_min = 0.0;
+    st->delta = INFINITY;
+    st->sA = -a.rho1 * L;  // Smin_alpha^rho1(f_0)
+    st->sB = 0.0;
+    if (!st->pos_a || !st->pos_b) st->error |= kErrWeights;
+    st->done = st->error ? 1 : 0;
+  } else if (a.kind == kReduceG) {
+    const double sBhat = -a.rho2 * L;  // Smin_beta^rho2(ghat)
+    const double tg = a.ti ? a.kappa_t / (1.0 - a.kappa_t) * sBhat : 0.0;
+    st->tau_g = tg;
+    st->sB = sBhat + tg;
+    st->gdiff_max = dmx;
+    st->gdiff_min = dmn;
+  } else {
+    const double sAhat = -a.rho1 * L;  // Smin_alpha^rho1(fhat)
+    double tf = 0.0, lam = 0.0;
+    if (a.ti) {
+      tf = a.kappa_t / (1.0 - a.kappa_t) * sAhat;
+      st->sA = sAhat + tf;
+      lam = a.tau1 * st->sB - a.tau2 * st->sA;  // Prop. 2 through softmins
+    } else {
+      st->sA = sAhat;
+    }
+    st->tau_f = tf;
+    st->lambda = lam;
+    const double off_f = tf + lam, off_g = st->tau_g - lam;
+    const int it = st->iter + 1;
+    st->iter = it;
+    double delta = INFINITY;
+    if (it > 1) {
+      const double cf = off_f - st->off_f_prev, cg = off_g - st->off_g_prev;
+      const double df = fmax(dmx + cf, -(dmn + cf));
+      const double dg = fmax(st->gdiff_max + cg, -(st->gdiff_min + cg));
+      delta = fmax(df, dg);
+    }
+    st->delta = delta;
+    st->off_f_prev = off_f;
+    st->off_g_prev = off_g;
+    if (!isfinite(off_f) || !isfinite(off_g) || isnan(delta)) st->error |= kErrNumeric;
+    if (st->error)
+      st->done = 1;
+    else if (a.tol > 0.0 && a.check_every > 0 && it % a.check_every == 0 && delta < a.tol)
+      st->done = 1;
+  }
+}
+
+// Zeroes the flags of the state and computes the common mean of x and y (points costs).
+__global__ __launch_bounds__(kBlock) void k_center(const float *x, int n, const float *y, int m,
+                                                   int d, SolveState *st) {
+  for (int k = 0; k < d; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += (double)x[(size_t)i * d + k];
+    for (int j = threadIdx.x; j < m; j += kBlock) s += (double)y[(size_t)j * d + k];
+    s = block_sum(s);
+    if (threadIdx.x == 0) st->mu[k] = s / (double)(n + m);
+  }
+  if (threadIdx.x == 0) {
+    for (int k = d; k < kMaxDim; ++k) st->mu[k] = 0.0;
+    st->error = 0;
+    st->done = 0;
+    st->pos_a = 0;
+    st->pos_b = 0;
+    st->iter = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate(const float *a, int n, const float *b, int m,
+                                                     SolveState *st) {
+  const int stride = gridDim.x * kBlock;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + m; i += stride) {
+    const float w = i < n ? a[i] : b[i - n];
+    if (!(w >= 0.0f) || isinf(w)) atomicOr(&st->error, kErrWeights);
+    if (w > 0.0f) {
+      if (i < n) st->pos_a = 1; else st->pos_b = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const float *pot, int n, int which,
+                                                     const SolveState *st, float *out) {
+  const double off = which == 0 ? st->tau_f + st->lambda : st->tau_g - st->lambda;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) out[t] = (float)((double)pot[t] + off);
+}
+
+// Dual value terms. Threads i < n (targets of the row softmin over beta with g):
+//   m(pi) partial: log alpha_i + (f_i - S_i)/eps,  S_i = Smin_beta^eps(C_{i,:} - g);
+//   rho1 alpha_i (1 - e^{-f_i/rho1}) and alpha_i. Threads j < m: rho2 beta_j (1 - e^{-g_j/rho2}), beta_j.
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_dual_terms(DualArgs a) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  double mm = -INFINITY, ms = 0.0, A = 0.0, B = 0.0, ma = 0.0, mb = 0.0;
+  if (t < a.n) {
+    double lse2 = combine_lse2(a.part, a.nsplit, a.n, t);
+    float yc[D > 0 ? D : 1];
+    if constexpr (MODE == kSqEuc) lse2 -= a.sc * centred<D>(a.x, a.d, t, a.st->mu, yc);
+    const double S = -lse2 / a.sc;
+    const double w = a.alpha[t], f = a.f[t];
+    if (w > 0.0) { mm = log(w) + (f - S) / a.eps; ms = 1.0; }
+    A = w * (-expm1(-f / a.rho1));
+    ma = w;
+  }
+  if (t < a.m) {
+    const double w = a.beta[t], g = a.g[t];
+    B = w * (-expm1(-g / a.rho2));
+    mb = w;
+  }
+  double dummy0 = 0.0, dummy1 = 0.0;
+  block_reduce_part(mm, ms, dummy0, dummy1);
+  A = block_sum(A);
+  B = block_sum(B);
+  ma = block_sum(ma);
+  mb = block_sum(mb);
+  if (threadIdx.x == 0) {
+    double *o = a.acc + (size_t)blockIdx.x * 6;
+    o[0] = mm; o[1] = ms; o[2] = A; o[3] = B; o[4] = ma; o[5] = mb;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual_reduce(DualArgs a, int nb) {
+  double mm = -INFINITY, ms = 0.0, A = 0.0, B = 0.0, ma = 0.0, mb = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const double *o = a.acc + (size_t)b * 6;
+    lse_merge(mm, ms, o[0], o[1]);
+    A += o[2]; B += o[3]; ma += o[4]; mb += o[5];
+  }
+  double dummy0 = 0.0, dummy1 = 0.0;
+  block_reduce_part(mm, ms, dummy0, dummy1);
+  A = block_sum(A);
+  B = block_sum(B);
+  ma = block_sum(ma);
+  mb = block_sum(mb);
+  if (threadIdx.x == 0) {
+    const double mpi = (mm == -INFINITY) ? 0.0 : exp(mm) * ms;
+    const double v = a.rho1 * A + a.rho2 * B - a.eps * (mpi - ma * mb);
+    a.st->value = v;
+    if (!isfinite(v)) a.st->error |= kErrNumeric;
+  }
+}
+
+template <int D, int MODE>
+hipError_t combine_for(const CombineArgs &a, hipStream_t s) {
+  const int nb = (a.nt + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_combine<D, MODE>), dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int D, int MODE>
+hipError_t records_for(const RecordArgs &a, hipStream_t s) {
+  const int nb = (a.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_build_records<D, MODE>), dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int D, int MODE>
+hipError_t dual_for(const DualArgs &a, int nb, hipStream_t s) {
+  hipLaunchKernelGGL((k_dual_terms<D, MODE>), dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// Dispatch on (mode, bucketed dimension).
+#define UOT_DISPATCH(FN, MODE_, D_, ...)                                         \
+  do {                                                                           \
+    if ((MODE_) == kDense) return FN<0, kDense>(__VA_ARGS__);                    \
+    const int b_ = dim_bucket(D_);                                               \
+    if ((MODE_) == kSqEuc) {                                                     \
+      switch (b_) {                                                              \
+        case 1: return FN<1, kSqEuc>(__VA_ARGS__);                               \
+        case 2: return FN<2, kSqEuc>(__VA_ARGS__);                               \
+        case 3: return FN<3, kSqEuc>(__VA_ARGS__);                               \
+        case 4: return FN<4, kSqEuc>(__VA_ARGS__);                               \
+        case 5: return FN<5, kSqEuc>(__VA_ARGS__);                               \
+        case 6: return FN<6, kSqEuc>(__VA_ARGS__);                               \
+        case 7: return FN<7, kSqEuc>(__VA_ARGS__);                               \
+        case 8: return FN<8, kSqEuc>(__VA_ARGS__);                               \
+        case 12: return FN<12, kSqEuc>(__VA_ARGS__);                             \
+        case 16: return FN<16, kSqEuc>(__VA_ARGS__);                             \
+        case 24: return FN<24, kSqEuc>(__VA_ARGS__);                             \
+        case 32: return FN<32, kSqEuc>(__VA_ARGS__);                             \
+        case 48: return FN<48, kSqEuc>(__VA_ARGS__);                             \
+        case 64: return FN<64, kSqEuc>(__VA_ARGS__);                             \
+      }                                                                          \
+    } else if ((MODE_) == kPower) {                                              \
+      switch (b_) {                                                              \
+        case 1: return FN<1, kPower>(__VA_ARGS__);                               \
+        case 2: return FN<2, kPower>(__VA_ARGS__);                               \
+        case 3: return FN<3, kPower>(__VA_ARGS__);                               \
+        case 4: return FN<4, kPower>(__VA_ARGS__);                               \
+        case 5: return FN<5, kPower>(__VA_ARGS__);                               \
+        case 6: return FN<6, kPower>(__VA_ARGS__);                               \
+        case 7: return FN<7, kPower>(__VA_ARGS__);                               \
+        case 8: return FN<8, kPower>(__VA_ARGS__);                               \
+        case 12: return FN<12, kPower>(__VA_ARGS__);                             \
+        case 16: return FN<16, kPower>(__VA_ARGS__);                             \
+        case 24: return FN<24, kPower>(__VA_ARGS__);                             \
+        case 32: return FN<32, kPower>(__VA_ARGS__);                             \
+        case 48: return FN<48, kPower>(__VA_ARGS__);                             \
+        case 64: return FN<64, kPower>(__VA_ARGS__);                             \
+      }                                                                          \
+    }                                                                            \
+    return hipErrorInvalidValue;                                                 \
+  } while (0)
+
+}  // namespace
+
+hipError_t launch_combine(const CombineArgs &a, hipStream_t s) {
+  UOT_DISPATCH(combine_for, a.mode, a.d, a, s);
+}
+
+hipError_t launch_build_records(const RecordArgs &a, hipStream_t s) {
+  UOT_DISPATCH(records_for, a.mode, a.d, a, s);
+}
+
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_center, dim3(1), dim3(kBlock), 0, s, x, n, y, m, d, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const float *a, int n, const float *b, int m, SolveState *st,
+                           hipStream_t s) {
+  int nb = (n + m + kBlock - 1) / kBlock;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_validate, dim3(nb), dim3(kBlock), 0, s, a, n, b, m, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const float *pot, int n, double off_sel, int which, SolveState *st,
+                           float *out, hipStream_t s) {
+  (void)off_sel;
+  hipLaunchKernelGGL(k_finalize, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pot, n,
+                     which, st, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual_terms(const DualArgs &a, int *nblocks, hipStream_t s) {
+  const int nb = ((a.n > a.m ? a.n : a.m) + kBlock - 1) / kBlock;
+  *nblocks = nb;
+  UOT_DISPATCH(dual_for, a.mode, a.d, a, nb, s);
+}
+
+hipError_t launch_dual_reduce(const DualArgs &a, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_dual_reduce, dim3(1), dim3(kBlock), 0, s, a, nblocks);
+  return hipGetLastError();
+}
+
+}  // namespace uot

@@ -1,0 +1,851 @@
+// Host side of libuot.so: argument validation, workspace layout, and the launch sequence of
+// the plain and translation-invariant Sinkhorn solvers, the dual value, plan application
+// and the envelope backward. Every entry point is extern "C" and declared in uot.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/uot.h"
+#include "uot_internal.h"
+
+namespace uot {
+namespace {
+
+thread_local std::string g_last_error;
+
+uot_status fail(uot_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define UOT_HIP(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(UOT_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int mode_of(const uot_cost *c) {
+  if (c->kind == UOT_COST_DENSE) return kDense;
+  return c->p == 2.0 ? kSqEuc : kPower;
+}
+
+uot_status check_cost(const uot_cost *c) {
+  if (c == nullptr) return fail(UOT_ERR_INVALID, "cost is NULL");
+  if (c->n < 1 || c->m < 1) return fail(UOT_ERR_INVALID, "n and m must be >= 1 (got %d, %d)", c->n, c->m);
+  if (c->kind == UOT_COST_DENSE) {
+    if (c->C == nullptr) return fail(UOT_ERR_INVALID, "dense cost with C = NULL");
+    if (c->ldc < c->m) return fail(UOT_ERR_INVALID, "ldc (%lld) < m (%d)", (long long)c->ldc, c->m);
+  } else if (c->kind == UOT_COST_POINTS) {
+    if (c->x == nullptr || c->y == nullptr) return fail(UOT_ERR_INVALID, "points cost with NULL x or y");
+    if (c->d < 1 || c->d > kMaxDim) return fail(UOT_ERR_INVALID, "point dimension d=%d not in [1, %d]", c->d, kMaxDim);
+    if (!std::isfinite(c->p) || c->p < 1.0) return fail(UOT_ERR_INVALID, "exponent p=%g must be finite and >= 1", c->p);
+  } else {
+    return fail(UOT_ERR_INVALID, "unknown cost kind %d", c->kind);
+  }
+  return UOT_OK;
+}
+
+// A pointer the GPU can read: device or managed memory, or host memory mapped to the device.
+uot_status check_device_ptr(const void *p, const char *name) {
+  if (p == nullptr) return fail(UOT_ERR_INVALID, "%s is NULL", name);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(UOT_ERR_INVALID, "%s is not a HIP device pointer", name);
+  }
+  if (attr.type == hipMemoryTypeHost && attr.devicePointer == nullptr)
+    return fail(UOT_ERR_INVALID, "%s is host memory not mapped to the device", name);
+  if (attr.type == hipMemoryTypeUnregistered)
+    return fail(UOT_ERR_INVALID, "%s is not a HIP device pointer", name);
+  return UOT_OK;
+}
+
+uot_status check_cost_ptrs(const uot_cost *c) {
+  uot_status s;
+  if (c->kind == UOT_COST_DENSE) return check_device_ptr(c->C, "C");
+  if ((s = check_device_ptr(c->x, "x")) != UOT_OK) return s;
+  return check_device_ptr(c->y, "y");
+}
+
+// ---------------------------------------------------------------------------------------
+// Launch shapes and workspace layout
+// ---------------------------------------------------------------------------------------
+constexpr int kTargetBlocks = 2048;  // blocks wanted per softmin launch (256 CUs x 8)
+
+struct Split {
+  int len = 1, n = 1;
+};
+
+// Splits of `ns` sources so that tiles * nsplit ~ kTargetBlocks, split lengths multiple of 8.
+Split make_split(int ns, int tiles, int min_len) {
+  Split s;
+  int want = (kTargetBlocks + tiles - 1) / tiles;
+  int maxn = (ns + min_len - 1) / min_len;
+  if (want > maxn) want = maxn;
+  if (want < 1) want = 1;
+  int len = (ns + want - 1) / want;
+  len = (len + 7) / 8 * 8;
+  s.len = len;
+  s.n = (ns + len - 1) / len;
+  return s;
+}
+
+// Softmin launch shape for a half-step with `nt` targets and `ns` sources.
+struct HalfShape {
+  Split split;
+  bool rows_kernel = false;  // dense, targets are rows (single split)
+  int nb_combine = 1;
+};
+
+HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
+  HalfShape h;
+  if (mode == kDense) {
+    if (targets_are_rows) {
+      h.rows_kernel = true;
+      h.split.len = ns;
+      h.split.n = 1;
+    } else {
+      const int tiles = (nt + dense_cols_per_block() - 1) / dense_cols_per_block();
+      h.split = make_split(ns, tiles, 64);
+    }
+  } else {
+    const int tpb = points_targets_per_block(mode, d);
+    const int tiles = (nt + tpb - 1) / tpb;
+    h.split = make_split(ns, tiles, 64);
+  }
+  h.nb_combine = (nt + kBlock - 1) / kBlock;
+  return h;
+}
+
+struct Layout {
+  size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0;
+  size_t dual = 0, rowsum_x = 0, rowsum_y = 0, tmp_x = 0, tmp_y = 0, scratch = 0, total = 0;
+  HalfShape g, f;  // g-step: targets y (columns), sources x; f-step: targets x (rows), sources y
+};
+
+Layout make_layout(const uot_cost *c, int which) {
+  Layout L;
+  const int mode = mode_of(c);
+  const int d = c->kind == UOT_COST_POINTS ? c->d : 0;
+  const int n = c->n, m = c->m;
+  const int stride = rec_stride_for(mode, d);
+  L.g = half_shape(mode, d, m, n, false);
+  L.f = half_shape(mode, d, n, m, true);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.state = take(sizeof(SolveState));
+  L.pot_x = take((size_t)n * sizeof(float));
+  L.pot_y = take((size_t)m * sizeof(float));
+  L.rec_x = take((size_t)n * stride * sizeof(float));
+  L.rec_y = take((size_t)m * stride * sizeof(float));
+  const size_t part_g = (size_t)L.g.split.n * m * sizeof(float2);
+  const size_t part_f = (size_t)L.f.split.n * n * sizeof(float2);
+  L.part = take(part_g > part_f ? part_g : part_f);
+  const int nb = (n > m ? n : m) + kBlock - 1;
+  L.bparts = take((size_t)(nb / kBlock + 1) * sizeof(BlockPart));
+  L.dual = take((size_t)(nb / kBlock + 1) * 6 * sizeof(double));
+  if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
+    L.rowsum_x = take((size_t)n * sizeof(float));
+    L.rowsum_y = take((size_t)m * sizeof(float));
+    L.tmp_x = take((size_t)n * sizeof(float));
+    L.tmp_y = take((size_t)m * sizeof(float));
+    const size_t a = apply_partial_bytes(n, m), b = apply_partial_bytes(m, n);
+    L.scratch = take(a > b ? a : b);
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T *at(void *base, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+// Workspace supplied by the caller, or allocated for the duration of the call.
+struct Workspace {
+  void *ptr = nullptr;
+  bool owned = false;
+  ~Workspace() {
+    if (owned && ptr) (void)hipFree(ptr);
+  }
+};
+
+uot_status acquire(Workspace &w, void *user, size_t user_bytes, size_t need) {
+  if (user != nullptr) {
+    if (user_bytes < need)
+      return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", user_bytes, need);
+    if (reinterpret_cast<uintptr_t>(user) % kAlign != 0)
+      return fail(UOT_ERR_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    w.ptr = user;
+    return UOT_OK;
+  }
+  hipError_t e = hipMalloc(&w.ptr, need);
+  if (e != hipSuccess) return fail(UOT_ERR_HIP, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+  w.owned = true;
+  return UOT_OK;
+}
+
+struct PinnedState {
+  SolveState *h = nullptr;
+  ~PinnedState() {
+    if (h) (void)hipHostFree(h);
+  }
+};
+
+// Common start of every call: flags, centring (points), weight validation.
+uot_status prepare(const uot_cost *c, const float *alpha, const float *beta, SolveState *st,
+                   hipStream_t s) {
+  const bool pts = c->kind == UOT_COST_POINTS;
+  UOT_HIP(launch_center(pts ? c->x : nullptr, pts ? c->n : 0, pts ? c->y : nullptr,
+                        pts ? c->m : 0, pts ? c->d : 0, st, s));
+  UOT_HIP(launch_validate(alpha, c->n, beta, c->m, st, s));
+  return UOT_OK;
+}
+
+uot_status read_state(SolveState *dev, SolveState &host, hipStream_t s) {
+  UOT_HIP(hipMemcpyAsync(&host, dev, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  UOT_HIP(hipStreamSynchronize(s));
+  return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Optional kernel timing: when enabled, each softmin launch is bracketed by two HIP events
+// on the launch stream; durations are accumulated per kernel kind under a mutex.
+// ---------------------------------------------------------------------------------------
+enum ProfKind : int { kProfPoints = 0, kProfDenseCols = 1, kProfDenseRows = 2, kProfKinds = 3 };
+struct ProfAcc {
+  int64_t launches = 0;
+  double ms = 0.0, entries = 0.0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+ProfAcc g_prof[kProfKinds];
+
+// Event pairs of one call, drained into g_prof when the ring wraps and at the end.
+class Timer {
+ public:
+  explicit Timer(bool on) : on_(on) {}
+  ~Timer() { drain(); for (auto &p : ring_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); } }
+  bool on() const { return on_; }
+  hipError_t begin(hipStream_t s) {
+    if (!on_) return hipSuccess;
+    if (used_ == kRing) {
+      hipError_t e = settle(head_);
+      if (e != hipSuccess) return e;
+    } else if (ring_.size() < kRing) {
+      Pair p;
+      hipError_t e = hipEventCreate(&p.a);
+      if (e == hipSuccess) e = hipEventCreate(&p.b);
+      if (e != hipSuccess) return e;
+      ring_.push_back(p);
+      ++used_;
+    }
+    cur_ = head_;
+    head_ = (head_ + 1) % kRing;
+    return hipEventRecord(ring_[cur_].a, s);
+  }
+  hipError_t end(hipStream_t s, int kind, double entries) {
+    if (!on_) return hipSuccess;
+    ring_[cur_].kind = kind;
+    ring_[cur_].entries = entries;
+    ring_[cur_].live = true;
+    return hipEventRecord(ring_[cur_].b, s);
+  }
+  void drain() {
+    for (size_t i = 0; i < ring_.size(); ++i) (void)settle(i);
+  }
+
+ private:
+  static constexpr size_t kRing = 512;
+  struct Pair {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;
+    double entries = 0.0;
+    bool live = false;
+  };
+  hipError_t settle(size_t i) {
+    Pair &p = ring_[i];
+    if (!p.live) return hipSuccess;
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e != hipSuccess) return e;
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, p.a, p.b);
+    p.live = false;
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[p.kind].launches += 1;
+    g_prof[p.kind].ms += ms;
+    g_prof[p.kind].entries += p.entries;
+    return hipSuccess;
+  }
+  bool on_;
+  std::vector<Pair> ring_;
+  size_t used_ = 0, head_ = 0, cur_ = 0;
+};
+
+bool profiling_enabled() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
+// Everything one solve needs to launch its kernels.
+struct Ctx {
+  const uot_cost *c;
+  int mode, d, n, m;
+  const float *alpha, *beta;
+  double eps, rho1, rho2;
+  double sc;  // log2(e)/eps
+  bool ti;
+  Layout L;
+  void *ws;
+  hipStream_t s;
+  Timer *timer = nullptr;
+  SolveState *st() const { return at<SolveState>(ws, L.state); }
+};
+
+// Softmin partials of one half-step into the part buffer.
+//   g_step: targets are the y side (columns of C), sources the x side with records rec_x;
+//   otherwise targets are the x side (rows of C), sources the y side with records rec_y.
+uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
+  const HalfShape &h = g_step ? k.L.g : k.L.f;
+  float2 *part = at<float2>(k.ws, k.L.part);
+  const float *rec_src = at<float>(k.ws, g_step ? k.L.rec_x : k.L.rec_y);
+  if (k.mode == kDense) {
+    DenseArgs a;
+    a.C = k.c->C;
+    a.ldc = k.c->ldc;
+    a.n = k.n;
+    a.m = k.m;
+    a.rec = rec_src;
+    a.split_len = h.split.len;
+    a.nsplit = h.split.n;
+    a.sc = (float)k.sc;
+    a.part = part;
+    a.done = done;
+    if (k.timer) UOT_HIP(k.timer->begin(k.s));
+    UOT_HIP(g_step ? launch_dense_cols_partial(a, k.s) : launch_dense_rows(a, k.s));
+    if (k.timer)
+      UOT_HIP(k.timer->end(k.s, g_step ? kProfDenseCols : kProfDenseRows, (double)k.n * (double)k.m));
+  } else {
+    PointsArgs a;
+    a.rec = rec_src;
+    a.ns = g_step ? k.n : k.m;
+    a.split_len = h.split.len;
+    a.nsplit = h.split.n;
+    a.tgt = g_step ? k.c->y : k.c->x;
+    a.nt = g_step ? k.m : k.n;
+    a.d = k.d;
+    a.mu = k.st()->mu;
+    a.sc = (float)k.sc;
+    a.half_p = (float)(0.5 * k.c->p);
+    a.part = part;
+    a.done = done;
+    if (k.timer) UOT_HIP(k.timer->begin(k.s));
+    UOT_HIP(launch_points_partial(k.mode, a, k.s));
+    if (k.timer) UOT_HIP(k.timer->end(k.s, kProfPoints, (double)k.n * (double)k.m));
+  }
+  return UOT_OK;
+}
+
+Epilogue epilogue_for(const Ctx &k, bool g_step) {
+  const double e = k.eps, r1 = k.rho1, r2 = k.rho2;
+  Epilogue ep;
+  ep.ti = k.ti;
+  if (g_step) {  // targets y: g = k2 (S - tau_f) - c_g sA, kappa_g = e r1 / ((e + r2)(r1 + r2))
+    ep.k_t = r2 / (e + r2);
+    ep.c_t = k.ti ? e * r2 / ((e + r2) * (r1 + r2)) : 0.0;
+    ep.rho_t = r2;
+    ep.kappa_t = k.ti ? e * r1 / ((e + r2) * (r1 + r2)) : 0.0;
+    ep.src_is_x = 1;
+  } else {       // targets x: f = k1 (S - tau_g) - c_f sB, kappa_f = e r2 / ((e + r1)(r1 + r2))
+    ep.k_t = r1 / (e + r1);
+    ep.c_t = k.ti ? e * r1 / ((e + r1) * (r1 + r2)) : 0.0;
+    ep.rho_t = r1;
+    ep.kappa_t = k.ti ? e * r2 / ((e + r1) * (r1 + r2)) : 0.0;
+    ep.src_is_x = 0;
+  }
+  return ep;
+}
+
+uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
+  SolveState *st = k.st();
+  uot_status r = softmin_partials(k, g_step, &st->done);
+  if (r != UOT_OK) return r;
+  const HalfShape &h = g_step ? k.L.g : k.L.f;
+  CombineArgs ca;
+  ca.part = at<float2>(k.ws, k.L.part);
+  ca.nsplit = h.split.n;
+  ca.nt = g_step ? k.m : k.n;
+  ca.mode = k.mode;
+  ca.d = k.d;
+  ca.tgt = k.mode == kDense ? nullptr : (g_step ? k.c->y : k.c->x);
+  ca.w = g_step ? k.beta : k.alpha;
+  ca.pot = at<float>(k.ws, g_step ? k.L.pot_y : k.L.pot_x);
+  ca.rec_out = at<float>(k.ws, g_step ? k.L.rec_y : k.L.rec_x);
+  ca.bparts = at<BlockPart>(k.ws, k.L.bparts);
+  ca.st = st;
+  ca.ep = epilogue_for(k, g_step);
+  ca.sc = k.sc;
+  ca.eps = k.eps;
+  UOT_HIP(launch_combine(ca, k.s));
+  ReduceArgs ra;
+  ra.bparts = ca.bparts;
+  ra.nb = h.nb_combine;
+  ra.st = st;
+  ra.kind = g_step ? kReduceG : kReduceF;
+  ra.ti = k.ti;
+  ra.rho1 = k.rho1;
+  ra.rho2 = k.rho2;
+  ra.kappa_t = ca.ep.kappa_t;
+  ra.tau1 = k.rho1 / (k.rho1 + k.rho2);
+  ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
+  ra.tol = tol;
+  ra.check_every = check_every;
+  UOT_HIP(launch_reduce(ra, k.s));
+  return UOT_OK;
+}
+
+// Records of one side from a potential (or zeros), optionally with its tilted-mass partials.
+uot_status build_records(const Ctx &k, bool x_side, const float *pot, bool copy_pot,
+                         bool with_mass, int *nblocks) {
+  RecordArgs a;
+  a.pts = k.mode == kDense ? nullptr : (x_side ? k.c->x : k.c->y);
+  a.w = x_side ? k.alpha : k.beta;
+  a.pot = pot;
+  a.pot_copy = copy_pot ? at<float>(k.ws, x_side ? k.L.pot_x : k.L.pot_y) : nullptr;
+  a.pot_off = 0.0;
+  a.n = x_side ? k.n : k.m;
+  a.mode = k.mode;
+  a.d = k.d;
+  a.rec = at<float>(k.ws, x_side ? k.L.rec_x : k.L.rec_y);
+  a.bparts = with_mass ? at<BlockPart>(k.ws, k.L.bparts) : nullptr;
+  a.rho = x_side ? k.rho1 : k.rho2;
+  a.sc = k.sc;
+  a.st = k.st();
+  if (nblocks) *nblocks = (a.n + kBlock - 1) / kBlock;
+  UOT_HIP(launch_build_records(a, k.s));
+  return UOT_OK;
+}
+
+uot_status check_params(const uot_params *p) {
+  if (p == nullptr) return fail(UOT_ERR_INVALID, "params is NULL");
+  if (!finite_pos(p->eps)) return fail(UOT_ERR_INVALID, "eps=%g must be finite and > 0", p->eps);
+  if (!finite_pos(p->rho1) || !finite_pos(p->rho2))
+    return fail(UOT_ERR_INVALID, "rho1=%g, rho2=%g must be finite and > 0", p->rho1, p->rho2);
+  if (p->max_iter < 1) return fail(UOT_ERR_INVALID, "max_iter=%d must be >= 1", p->max_iter);
+  if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return fail(UOT_ERR_INVALID, "tol=%g must be finite and >= 0", p->tol);
+  if (p->check_every < 1) return fail(UOT_ERR_INVALID, "check_every=%d must be >= 1", p->check_every);
+  return UOT_OK;
+}
+
+uot_status check_scalars(double eps, double rho1, double rho2) {
+  if (!finite_pos(eps)) return fail(UOT_ERR_INVALID, "eps=%g must be finite and > 0", eps);
+  if (!finite_pos(rho1) || !finite_pos(rho2))
+    return fail(UOT_ERR_INVALID, "rho1=%g, rho2=%g must be finite and > 0", rho1, rho2);
+  return UOT_OK;
+}
+
+#define UOT_TRY(expr)                    \
+  do {                                   \
+    uot_status r_ = (expr);              \
+    if (r_ != UOT_OK) return r_;         \
+  } while (0)
+
+uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const uot_params *P,
+                 float *f, float *g, void *workspace, size_t workspace_bytes, uot_info *info,
+                 void *stream, bool ti) {
+  UOT_TRY(check_cost(c));
+  UOT_TRY(check_params(P));
+  UOT_TRY(check_cost_ptrs(c));
+  UOT_TRY(check_device_ptr(alpha, "alpha"));
+  UOT_TRY(check_device_ptr(beta, "beta"));
+  UOT_TRY(check_device_ptr(f, "f"));
+  UOT_TRY(check_device_ptr(g, "g"));
+  Ctx k;
+  k.c = c;
+  k.mode = mode_of(c);
+  k.d = c->kind == UOT_COST_POINTS ? c->d : 0;
+  k.n = c->n;
+  k.m = c->m;
+  k.alpha = alpha;
+  k.beta = beta;
+  k.eps = P->eps;
+  k.rho1 = P->rho1;
+  k.rho2 = P->rho2;
+  k.sc = kLog2e / P->eps;
+  k.ti = ti;
+  k.L = make_layout(c, UOT_WS_SOLVE);
+  k.s = static_cast<hipStream_t>(stream);
+  Workspace w;
+  UOT_TRY(acquire(w, workspace, workspace_bytes, k.L.total));
+  k.ws = w.ptr;
+  SolveState *st = k.st();
+  Timer timer(profiling_enabled());
+  k.timer = timer.on() ? &timer : nullptr;
+
+  PinnedState pin;
+  UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
+
+  // start: flags, centring, weights, records of x from f_0 (with Smin_alpha^rho1(f_0)), g = 0
+  UOT_TRY(prepare(c, alpha, beta, st, k.s));
+  int nbx = 0;
+  UOT_TRY(build_records(k, true, P->warm_start ? f : nullptr, true, true, &nbx));
+  ReduceArgs ri;
+  ri.bparts = at<BlockPart>(k.ws, k.L.bparts);
+  ri.nb = nbx;
+  ri.st = st;
+  ri.kind = kReduceInit;
+  ri.ti = ti;
+  ri.rho1 = k.rho1;
+  ri.rho2 = k.rho2;
+  ri.kappa_t = 0.0;
+  ri.tau1 = ri.tau2 = 0.0;
+  ri.tol = 0.0;
+  ri.check_every = 1;
+  UOT_HIP(launch_reduce(ri, k.s));
+  UOT_TRY(build_records(k, false, nullptr, true, false, nullptr));
+  UOT_TRY(read_state(st, pin.h[0], k.s));
+  if (pin.h[0].error & kErrWeights)
+    return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
+
+  // iterations, in chunks of check_every; the host reads the convergence flag one chunk late
+  // so the GPU always has queued work (solver kernels return at once after convergence)
+  const bool checking = P->tol > 0.0;
+  const int chunk = checking ? P->check_every : P->max_iter;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  UOT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  UOT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evg{ev};
+  int issued = 0, c_idx = 0;
+  bool stop = false;
+  while (issued < P->max_iter && !stop) {
+    const int todo = (P->max_iter - issued) < chunk ? (P->max_iter - issued) : chunk;
+    for (int t = 0; t < todo; ++t) {
+      UOT_TRY(half_step(k, true, P->tol, P->check_every));
+      UOT_TRY(half_step(k, false, P->tol, P->check_every));
+    }
+    issued += todo;
+    if (checking) {
+      SolveState *slot = &pin.h[c_idx & 1];
+      UOT_HIP(hipMemcpyAsync(slot, st, sizeof(SolveState), hipMemcpyDeviceToHost, k.s));
+      UOT_HIP(hipEventRecord(ev[c_idx & 1], k.s));
+      if (c_idx >= 1) {
+        UOT_HIP(hipEventSynchronize(ev[(c_idx - 1) & 1]));
+        if (pin.h[(c_idx - 1) & 1].done) stop = true;
+      }
+      ++c_idx;
+    }
+  }
+  UOT_HIP(launch_finalize(at<float>(k.ws, k.L.pot_x), k.n, 0.0, 0, st, f, k.s));
+  UOT_HIP(launch_finalize(at<float>(k.ws, k.L.pot_y), k.m, 0.0, 1, st, g, k.s));
+  SolveState fin;
+  UOT_TRY(read_state(st, fin, k.s));
+  if (info) {
+    info->iters = fin.iter;
+    info->converged = (checking && fin.done && !fin.error) ? 1 : 0;
+    info->last_change = fin.delta;
+    info->lambda = fin.lambda;
+  }
+  if (fin.error & kErrNumeric) return fail(UOT_ERR_NUMERIC, "non-finite potentials after %d iterations", fin.iter);
+  return UOT_OK;
+}
+
+uot_status dual_value(const uot_cost *c, const float *alpha, const float *beta, double eps,
+                      double rho1, double rho2, const float *f, const float *g, void *workspace,
+                      size_t workspace_bytes, double *value, void *stream) {
+  UOT_TRY(check_cost(c));
+  UOT_TRY(check_scalars(eps, rho1, rho2));
+  if (value == nullptr) return fail(UOT_ERR_INVALID, "value is NULL");
+  UOT_TRY(check_cost_ptrs(c));
+  UOT_TRY(check_device_ptr(alpha, "alpha"));
+  UOT_TRY(check_device_ptr(beta, "beta"));
+  UOT_TRY(check_device_ptr(f, "f"));
+  UOT_TRY(check_device_ptr(g, "g"));
+  Ctx k;
+  k.c = c;
+  k.mode = mode_of(c);
+  k.d = c->kind == UOT_COST_POINTS ? c->d : 0;
+  k.n = c->n;
+  k.m = c->m;
+  k.alpha = alpha;
+  k.beta = beta;
+  k.eps = eps;
+  k.rho1 = rho1;
+  k.rho2 = rho2;
+  k.sc = kLog2e / eps;
+  k.ti = false;
+  k.L = make_layout(c, UOT_WS_DUAL);
+  k.s = static_cast<hipStream_t>(stream);
+  Workspace w;
+  UOT_TRY(acquire(w, workspace, workspace_bytes, k.L.total));
+  k.ws = w.ptr;
+  SolveState *st = k.st();
+  UOT_TRY(prepare(c, alpha, beta, st, k.s));
+  UOT_TRY(build_records(k, false, g, false, false, nullptr));
+  UOT_TRY(softmin_partials(k, false, nullptr));
+  DualArgs da;
+  da.part = at<float2>(k.ws, k.L.part);
+  da.nsplit = k.L.f.split.n;
+  da.n = k.n;
+  da.m = k.m;
+  da.mode = k.mode;
+  da.d = k.d;
+  da.x = k.mode == kDense ? nullptr : c->x;
+  da.alpha = alpha;
+  da.beta = beta;
+  da.f = f;
+  da.g = g;
+  da.st = st;
+  da.sc = k.sc;
+  da.eps = eps;
+  da.rho1 = rho1;
+  da.rho2 = rho2;
+  da.acc = at<double>(k.ws, k.L.dual);
+  int nb = 0;
+  UOT_HIP(launch_dual_terms(da, &nb, k.s));
+  UOT_HIP(launch_dual_reduce(da, nb, k.s));
+  SolveState fin;
+  UOT_TRY(read_state(st, fin, k.s));
+  if (fin.error & kErrWeights) return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
+  if (!fin.pos_a || !fin.pos_b) return fail(UOT_ERR_INVALID, "weights must have positive total mass");
+  *value = fin.value;
+  if (fin.error & kErrNumeric) return fail(UOT_ERR_NUMERIC, "non-finite dual value");
+  return UOT_OK;
+}
+
+// Fills the ApplyArgs common to plan application and the backward.
+ApplyArgs apply_args(const uot_cost *c, int mode, bool targets_x, const float *alpha,
+                     const float *beta, const float *f, const float *g, double eps, SolveState *st) {
+  ApplyArgs a;
+  memset(&a, 0, sizeof a);
+  a.mode = mode;
+  a.d = c->kind == UOT_COST_POINTS ? c->d : 0;
+  a.C = c->C;
+  a.ldc = c->ldc;
+  a.transpose = targets_x ? 0 : 1;
+  a.tgt = c->kind == UOT_COST_POINTS ? (targets_x ? c->x : c->y) : nullptr;
+  a.src = c->kind == UOT_COST_POINTS ? (targets_x ? c->y : c->x) : nullptr;
+  a.mu = st->mu;
+  a.p = c->kind == UOT_COST_POINTS ? c->p : 1.0;
+  a.nt = targets_x ? c->n : c->m;
+  a.ns = targets_x ? c->m : c->n;
+  a.w_t = targets_x ? alpha : beta;
+  a.w_s = targets_x ? beta : alpha;
+  a.h_t = targets_x ? f : g;
+  a.h_s = targets_x ? g : f;
+  a.sc = (float)(kLog2e / eps);
+  a.gscale = 1.0;
+  return a;
+}
+
+uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, double eps,
+                      const float *f, const float *g, int32_t transpose, const float *V, int32_t kc,
+                      int64_t ldv, float *out, int64_t ldout, void *workspace, size_t workspace_bytes,
+                      void *stream) {
+  UOT_TRY(check_cost(c));
+  if (!finite_pos(eps)) return fail(UOT_ERR_INVALID, "eps=%g must be finite and > 0", eps);
+  if (kc < 1 || kc > 64) return fail(UOT_ERR_INVALID, "k=%d not in [1, 64]", kc);
+  if (V == nullptr && kc != 1) return fail(UOT_ERR_INVALID, "V = NULL (ones) needs k = 1");
+  if (V != nullptr && ldv < kc) return fail(UOT_ERR_INVALID, "ldv < k");
+  if (ldout < kc) return fail(UOT_ERR_INVALID, "ldout < k");
+  if (transpose != 0 && transpose != 1) return fail(UOT_ERR_INVALID, "transpose must be 0 or 1");
+  UOT_TRY(check_cost_ptrs(c));
+  UOT_TRY(check_device_ptr(alpha, "alpha"));
+  UOT_TRY(check_device_ptr(beta, "beta"));
+  UOT_TRY(check_device_ptr(f, "f"));
+  UOT_TRY(check_device_ptr(g, "g"));
+  UOT_TRY(check_device_ptr(out, "out"));
+  if (V != nullptr) UOT_TRY(check_device_ptr(V, "V"));
+  const Layout L = make_layout(c, UOT_WS_PLAN);
+  Workspace w;
+  UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SolveState *st = at<SolveState>(w.ptr, L.state);
+  UOT_TRY(prepare(c, alpha, beta, st, s));
+  ApplyArgs a = apply_args(c, mode_of(c), transpose == 0, alpha, beta, f, g, eps, st);
+  a.V = V;
+  a.k = kc;
+  a.ldv = ldv;
+  a.out = out;
+  a.ldout = ldout;
+  UOT_HIP(launch_apply_with_scratch(a, at<void>(w.ptr, L.scratch), s));
+  SolveState fin;
+  UOT_TRY(read_state(st, fin, s));
+  if ((fin.error & kErrWeights) || !fin.pos_a || !fin.pos_b)
+    return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
+  return UOT_OK;
+}
+
+uot_status backward(const uot_cost *c, const float *alpha, const float *beta, double eps,
+                    double rho1, double rho2, const float *f, const float *g, double grad_out,
+                    float *dx, float *dy, float *dalpha, float *dbeta, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+  UOT_TRY(check_cost(c));
+  UOT_TRY(check_scalars(eps, rho1, rho2));
+  if (!std::isfinite(grad_out)) return fail(UOT_ERR_INVALID, "grad_out must be finite");
+  if (c->kind == UOT_COST_DENSE && (dx != nullptr || dy != nullptr))
+    return fail(UOT_ERR_INVALID, "dx/dy need a points cost");
+  UOT_TRY(check_cost_ptrs(c));
+  UOT_TRY(check_device_ptr(alpha, "alpha"));
+  UOT_TRY(check_device_ptr(beta, "beta"));
+  UOT_TRY(check_device_ptr(f, "f"));
+  UOT_TRY(check_device_ptr(g, "g"));
+  if (dx) UOT_TRY(check_device_ptr(dx, "dx"));
+  if (dy) UOT_TRY(check_device_ptr(dy, "dy"));
+  if (dalpha) UOT_TRY(check_device_ptr(dalpha, "dalpha"));
+  if (dbeta) UOT_TRY(check_device_ptr(dbeta, "dbeta"));
+  const Layout L = make_layout(c, UOT_WS_BACKWARD);
+  Workspace w;
+  UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SolveState *st = at<SolveState>(w.ptr, L.state);
+  UOT_TRY(prepare(c, alpha, beta, st, s));
+  const int mode = mode_of(c);
+  void *scratch = at<void>(w.ptr, L.scratch);
+  double *masses = at<double>(w.ptr, L.dual);  // [0] = m(alpha), [1] = m(beta)
+  for (int side = 0; side < 2; ++side) {
+    const bool tx = side == 0;  // targets are the x side
+    float *dpts = tx ? dx : dy;
+    float *dw = tx ? dalpha : dbeta;
+    if (dpts == nullptr && dw == nullptr) continue;
+    ApplyArgs a = apply_args(c, mode, tx, alpha, beta, f, g, eps, st);
+    float *rowsum = at<float>(w.ptr, tx ? L.rowsum_x : L.rowsum_y);
+    a.rowsum = dw ? rowsum : nullptr;
+    if (dpts) {
+      a.grad = 1;
+      a.gscale = grad_out;
+      a.out = dpts;
+      a.ldout = c->d;
+    } else {
+      a.V = nullptr;
+      a.k = 1;
+      a.out = at<float>(w.ptr, tx ? L.tmp_x : L.tmp_y);
+      a.ldout = 1;
+    }
+    UOT_HIP(launch_apply_with_scratch(a, scratch, s));
+    if (dw) {
+      UOT_HIP(launch_sum(tx ? beta : alpha, tx ? c->m : c->n, masses + side, s));
+      WeightGradArgs wa;
+      wa.rowsum = rowsum;
+      wa.h = tx ? f : g;
+      wa.n = tx ? c->n : c->m;
+      wa.rho = tx ? rho1 : rho2;
+      wa.eps = eps;
+      wa.gout = grad_out;
+      wa.out = dw;
+      UOT_HIP(launch_weight_grad_from_rowsum(wa, masses + side, s));
+    }
+  }
+  SolveState fin;
+  UOT_TRY(read_state(st, fin, s));
+  if ((fin.error & kErrWeights) || !fin.pos_a || !fin.pos_b)
+    return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
+  return UOT_OK;
+}
+
+}  // namespace
+}  // namespace uot
+
+extern "C" {
+
+size_t uot_workspace_bytes(const uot_cost *cost, int32_t which) {
+  if (uot::check_cost(cost) != UOT_OK) return 0;
+  if (which < UOT_WS_SOLVE || which > UOT_WS_BACKWARD) return 0;
+  return uot::make_layout(cost, which).total;
+}
+
+uot_status uot_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,
+                        const uot_params *params, float *f, float *g, void *workspace,
+                        size_t workspace_bytes, uot_info *info, void *stream) {
+  uot::g_last_error.clear();
+  return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream, false);
+}
+
+uot_status uot_ti_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,
+                           const uot_params *params, float *f, float *g, void *workspace,
+                           size_t workspace_bytes, uot_info *info, void *stream) {
+  uot::g_last_error.clear();
+  return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream, true);
+}
+
+uot_status uot_dual_value(const uot_cost *cost, const float *alpha, const float *beta, double eps,
+                          double rho1, double rho2, const float *f, const float *g, void *workspace,
+                          size_t workspace_bytes, double *value, void *stream) {
+  uot::g_last_error.clear();
+  return uot::dual_value(cost, alpha, beta, eps, rho1, rho2, f, g, workspace, workspace_bytes, value,
+                         stream);
+}
+
+uot_status uot_plan_apply(const uot_cost *cost, const float *alpha, const float *beta, double eps,
+                          const float *f, const float *g, int32_t transpose, const float *V,
+                          int32_t k, int64_t ldv, float *out, int64_t ldout, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+  uot::g_last_error.clear();
+  return uot::plan_apply(cost, alpha, beta, eps, f, g, transpose, V, k, ldv, out, ldout, workspace,
+                         workspace_bytes, stream);
+}
+
+uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *beta, double eps,
+                        double rho1, double rho2, const float *f, const float *g, double grad_out,
+                        float *dx, float *dy, float *dalpha, float *dbeta, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+  uot::g_last_error.clear();
+  return uot::backward(cost, alpha, beta, eps, rho1, rho2, f, g, grad_out, dx, dy, dalpha, dbeta,
+                       workspace, workspace_bytes, stream);
+}
+
+void uot_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(uot::g_prof_mu);
+  uot::g_prof_on = on != 0;
+}
+
+void uot_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(uot::g_prof_mu);
+  for (auto &p : uot::g_prof) p = uot::ProfAcc();
+}
+
+int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries) {
+  if (kind < 0 || kind >= uot::kProfKinds) return -1;
+  std::lock_guard<std::mutex> lk(uot::g_prof_mu);
+  if (total_ms) *total_ms = uot::g_prof[kind].ms;
+  if (total_entries) *total_entries = uot::g_prof[kind].entries;
+  return uot::g_prof[kind].launches;
+}
+
+const char *uot_status_string(uot_status s) {
+  switch (s) {
+    case UOT_OK: return "ok";
+    case UOT_ERR_INVALID: return "invalid argument";
+    case UOT_ERR_HIP: return "HIP runtime error";
+    case UOT_ERR_NUMERIC: return "non-finite result";
+    case UOT_ERR_WORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+const char *uot_last_error(void) { return uot::g_last_error.c_str(); }
+
+}  // extern "C"

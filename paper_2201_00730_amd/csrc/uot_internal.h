@@ -1,0 +1,233 @@
+// Internal definitions shared by the HIP kernels and the host orchestration of libuot.so.
+// Not part of the public ABI (that is include/uot.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace uot {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.6931471805599453094;
+constexpr int kMaxDim = 64;
+constexpr int kBlock = 256;  // threads per block of the O(N) kernels
+
+// How C is formed inside a kernel.
+enum CostMode : int {
+  kDense = 0,   // stored C (row-major, leading dimension ldc)
+  kSqEuc = 1,   // points, p = 2: expanded form |x|^2 + |y|^2 - 2<x,y> on centred points
+  kPower = 2,   // points, general p: direct differences, ||x - y||^p
+};
+
+// Point dimensions are padded (with zero coordinates) up to one of the compiled buckets.
+__host__ __device__ constexpr int dim_bucket(int d) {
+  return d <= 8 ? d : d <= 12 ? 12 : d <= 16 ? 16 : d <= 24 ? 24 : d <= 32 ? 32 : d <= 48 ? 48 : 64;
+}
+
+// Source-record stride in floats for a cost mode and a (bucketed) dimension D. A source
+// record holds what a softmin needs of one source point: D coordinates (scaled for kSqEuc,
+// zero beyond the true dimension) then the log2-domain offset b; dense records hold b only.
+__host__ __device__ constexpr int rec_stride(int mode, int D) {
+  return mode == kDense ? 1 : ((D + 1 + 3) / 4) * 4;
+}
+__host__ __device__ constexpr int rec_stride_for(int mode, int d) {
+  return rec_stride(mode, dim_bucket(d));
+}
+
+// Device-resident scalar state of one solve, all double precision.
+// Potentials are stored untranslated ("hat" values); the reported TI potentials are
+//   f = fhat + off_f,  g = ghat + off_g,  off_f = tau_f + lambda,  off_g = tau_g - lambda.
+struct SolveState {
+  double sA;          // Smin_alpha^rho1(fb) of the current fb = fhat + tau_f
+  double sB;          // Smin_beta^rho2(gb) of the current gb = ghat + tau_g
+  double tau_f;       // pending scalar translation of the stored f
+  double tau_g;       // pending scalar translation of the stored g
+  double lambda;      // lambda*(fb, gb)
+  double off_f_prev;  // off_f after the previous iteration
+  double off_g_prev;  // off_g after the previous iteration
+  double gdiff_max;   // max_j (ghat_new - ghat_old) of the latest g-step
+  double gdiff_min;   // min_j (ghat_new - ghat_old)
+  double delta;       // change of the reported potentials at the last iteration
+  double value;       // scratch for single-value reductions (dual value)
+  int32_t iter;       // completed iterations
+  int32_t done;       // 1 once converged or failed: solver kernels return at once
+  int32_t error;      // bit 1: invalid weights, bit 2: non-finite result
+  int32_t pos_a;      // some alpha_i > 0
+  int32_t pos_b;      // some beta_j > 0
+  int32_t pad_;
+  double mu[kMaxDim]; // common centring of x and y (points costs)
+};
+
+enum : int32_t { kErrWeights = 1, kErrNumeric = 2 };
+
+// One block's partial reductions in a combine kernel.
+struct BlockPart {
+  double mass_max;  // log-sum-exp of the tilted mass: running max
+  double mass_sum;  //   and sum of exp(v - max)
+  double dmax;      // max of (new - old) potential differences
+  double dmin;      // min of the same
+};
+
+// Epilogue of a half-step (all double): given the softmin S_t over the current sources,
+//   hnew_t = k_t * (S_t - tau_src) - c_t * s_src
+// (KL prox, and for TI the translation term of App. B; c_t = 0 for plain Sinkhorn).
+struct Epilogue {
+  double k_t;       // rho_t / (eps + rho_t)
+  double c_t;       // TI: eps rho_t / ((eps + rho_t)(rho1 + rho2)); plain: 0
+  double rho_t;     // penalty of the target side (for its tilted mass)
+  double kappa_t;   // TI: kappa of the target side; plain: 0 (used by the reduction)
+  int32_t src_is_x; // 1: sources are the x/alpha side (g-step)
+  int32_t ti;
+};
+
+// ---------------------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files). All return hipError_t of the launch.
+// ---------------------------------------------------------------------------------------
+struct PointsArgs {
+  const float *rec;    // source records [ns, rec_stride]
+  int ns;
+  int split_len;       // sources per split (multiple of 8)
+  int nsplit;
+  const float *tgt;    // raw target coordinates [nt, d]
+  int nt;
+  int d;
+  const double *mu;    // centring (device, inside SolveState)
+  float sc;            // log2(e)/eps
+  float half_p;        // p/2 (kPower)
+  float2 *part;        // [nsplit, nt] (running max, sum) in log2 domain
+  const int32_t *done; // early-exit flag (may be NULL)
+};
+
+hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st);
+int points_targets_per_block(int mode, int d);
+
+struct DenseArgs {
+  const float *C;
+  int64_t ldc;
+  int n, m;            // C is n x m
+  const float *rec;    // source records (1 float each): rows (cols kernel) or columns (rows kernel)
+  int split_len;       // rows per split (cols kernel)
+  int nsplit;
+  float sc;
+  float2 *part;        // cols: [nsplit, m]; rows: [1, n]
+  const int32_t *done;
+};
+
+hipError_t launch_dense_cols_partial(const DenseArgs &a, hipStream_t st);
+hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st);
+int dense_cols_per_block();
+int dense_rows_per_block();
+
+// Epilogue kernels (kernels_epilogue.hip).
+struct CombineArgs {
+  const float2 *part;  // [nsplit, nt]
+  int nsplit;
+  int nt;
+  int mode, d;
+  const float *tgt;    // raw target coordinates (points) or NULL
+  const float *w;      // target weights [nt]
+  float *pot;          // stored target potential [nt] (in: old, out: new)
+  float *rec_out;      // target records for the next half-step [nt, stride]
+  BlockPart *bparts;   // [gridDim]
+  SolveState *st;
+  Epilogue ep;
+  double sc;           // log2(e)/eps (double)
+  double eps;
+};
+
+hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
+
+enum ReduceKind : int { kReduceInit = 0, kReduceG = 1, kReduceF = 2 };
+struct ReduceArgs {
+  const BlockPart *bparts;
+  int nb;
+  SolveState *st;
+  int kind;
+  int ti;
+  double rho1, rho2, kappa_t, tau1, tau2;
+  double tol;
+  int check_every;
+};
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
+
+// Build source records from a potential (solve start, dual value, plan, backward).
+struct RecordArgs {
+  const float *pts;    // raw coordinates [n, d] (points) or NULL
+  const float *w;      // weights [n]
+  const float *pot;    // potential [n] or NULL (zeros)
+  float *pot_copy;     // if non-NULL, receives the potential (stored copy)
+  double pot_off;      // constant added to the potential
+  int n, mode, d;
+  float *rec;          // [n, stride]
+  BlockPart *bparts;   // tilted mass partials for rho (or NULL)
+  double rho;
+  double sc;
+  SolveState *st;
+};
+hipError_t launch_build_records(const RecordArgs &a, hipStream_t st);
+
+hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
+                         hipStream_t s);
+hipError_t launch_validate(const float *a, int n, const float *b, int m, SolveState *st,
+                           hipStream_t s);
+hipError_t launch_finalize(const float *pot, int n, double off_sel, int which, SolveState *st,
+                           float *out, hipStream_t s);
+
+// Dual value pieces.
+struct DualArgs {
+  const float2 *part;  // row softmin partials over the m sources [nsplit, n]
+  int nsplit;
+  int n, m, mode, d;
+  const float *x;      // raw x for the kSqEuc target constant
+  const float *alpha, *beta, *f, *g;
+  SolveState *st;
+  double sc, eps, rho1, rho2;
+  double *acc;         // [gridDim, 4] block partials
+};
+hipError_t launch_dual_terms(const DualArgs &a, int *nblocks, hipStream_t s);
+hipError_t launch_dual_reduce(const DualArgs &a, int nblocks, hipStream_t s);
+
+// Plan application / gradient accumulation over sources (kernels_apply.hip).
+struct ApplyArgs {
+  int mode, d;
+  // dense: C, ldc; transpose = 0 means targets are rows of C, 1 means columns
+  const float *C;
+  int64_t ldc;
+  int transpose;
+  // points
+  const float *tgt;    // raw target coords [nt, d]
+  const float *src;    // raw source coords [ns, d]
+  const double *mu;    // centring (SolveState::mu)
+  double p;
+  int nt, ns;
+  const float *w_t, *w_s;    // target / source weights
+  const float *h_t, *h_s;    // target / source potentials
+  float sc;
+  // V: [ns, k] with leading dim ldv; NULL => ones (k = 1)
+  const float *V;
+  int k;
+  int64_t ldv;
+  // grad mode: accumulate sum_s pi_ts * p ||t-s||^{p-2} (t - s) into out [nt, d]
+  int grad;
+  double gscale;       // multiplies the output
+  float *out;
+  int64_t ldout;
+  float *rowsum;       // optional [nt]: sum_s w_s e^{(h_t + h_s - C_ts)/eps}
+};
+size_t apply_partial_bytes(int nt, int ns);
+hipError_t launch_apply_with_scratch(const ApplyArgs &a, void *scratch, hipStream_t s);
+
+struct WeightGradArgs {
+  const float *rowsum; // [n]: sum_j w_j e^{(h_i + h_j - C_ij)/eps}
+  const float *h;      // potential [n]
+  int n;
+  double rho, eps, gout;
+  float *out;
+};
+hipError_t launch_weight_grad_from_rowsum(const WeightGradArgs &a, const double *mass_other,
+                                          hipStream_t s);
+hipError_t launch_sum(const float *w, int n, double *out, hipStream_t s);
+
+}  // namespace uot

@@ -1,0 +1,129 @@
+"""C ABI of libuot.so: loads, exports every function declared in include/*.h, and rejects
+invalid arguments on the host before any launch (CPU only; no compute calls)."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2201_00730_amd as uot
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for mt in re.finditer(r"\b(uot_[a-z0-9_]+)\s*\(", text):
+            names.add(mt.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(uot.library_path()):
+        pytest.fail("libuot.so is not built (run __graft_entry__.build())")
+    return uot.load_library()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ("uot_sinkhorn", "uot_ti_sinkhorn", "uot_dual_value", "uot_plan_apply",
+                     "uot_backward", "uot_workspace_bytes", "uot_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", uot.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for name in _declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def _cost(kind=1, n=10, m=12, d=3, p=2.0, ldc=0):
+    c = uot._Cost()
+    c.kind, c.n, c.m, c.d = kind, n, m, d
+    c.C = ctypes.c_void_p(0x1000) if kind == 0 else None
+    c.ldc = ldc if ldc else m
+    c.x = ctypes.c_void_p(0x1000) if kind == 1 else None
+    c.y = ctypes.c_void_p(0x2000) if kind == 1 else None
+    c.p = p
+    return c
+
+
+def test_workspace_bytes_host_only(lib):
+    c = _cost()
+    assert lib.uot_workspace_bytes(ctypes.byref(c), 0) > 0
+    big = _cost(n=20000, m=20000)
+    assert lib.uot_workspace_bytes(ctypes.byref(big), 0) > lib.uot_workspace_bytes(ctypes.byref(c), 0)
+    dense = _cost(kind=0, n=64, m=100, d=0)
+    assert lib.uot_workspace_bytes(ctypes.byref(dense), 0) > 0
+    for bad in (_cost(n=0), _cost(m=0), _cost(d=0), _cost(d=65), _cost(p=0.5),
+                _cost(p=float("nan")), _cost(kind=0, ldc=5), _cost(kind=7)):
+        assert lib.uot_workspace_bytes(ctypes.byref(bad), 0) == 0
+    assert lib.uot_workspace_bytes(ctypes.byref(c), 9) == 0
+    assert lib.uot_workspace_bytes(None, 0) == 0
+
+
+@pytest.mark.parametrize("field,value", [("eps", 0.0), ("eps", -1.0), ("eps", float("inf")),
+                                         ("rho1", 0.0), ("rho2", float("nan")), ("max_iter", 0),
+                                         ("tol", -1.0), ("check_every", 0)])
+def test_solver_rejects_bad_params_before_any_launch(lib, field, value):
+    c = _cost()
+    prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
+    setattr(prm, field, value)
+    for fn in (lib.uot_sinkhorn, lib.uot_ti_sinkhorn):
+        st = fn(ctypes.byref(c), None, None, ctypes.byref(prm), None, None, None, 0, None, None)
+        assert st == uot.UOT_ERR_INVALID
+        assert lib.uot_last_error()
+
+
+def test_solver_rejects_bad_cost(lib):
+    prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
+    for bad in (_cost(n=0), _cost(d=100), _cost(p=0.0), _cost(kind=0, ldc=3)):
+        assert lib.uot_ti_sinkhorn(ctypes.byref(bad), None, None, ctypes.byref(prm), None, None, None,
+                                   0, None, None) == uot.UOT_ERR_INVALID
+    assert lib.uot_ti_sinkhorn(None, None, None, ctypes.byref(prm), None, None, None, 0, None,
+                               None) == uot.UOT_ERR_INVALID
+
+
+def test_other_entry_points_reject_bad_scalars(lib):
+    c = _cost()
+    v = ctypes.c_double(0)
+    assert lib.uot_dual_value(ctypes.byref(c), None, None, -1.0, 1.0, 1.0, None, None, None, 0,
+                              ctypes.byref(v), None) == uot.UOT_ERR_INVALID
+    assert lib.uot_dual_value(ctypes.byref(c), None, None, 0.1, 1.0, 1.0, None, None, None, 0,
+                              None, None) == uot.UOT_ERR_INVALID
+    assert lib.uot_plan_apply(ctypes.byref(c), None, None, 0.1, None, None, 0, None, 0, 1, None, 1,
+                              None, 0, None) == uot.UOT_ERR_INVALID  # k = 0
+    assert lib.uot_plan_apply(ctypes.byref(c), None, None, 0.1, None, None, 0, None, 2, 2, None, 2,
+                              None, 0, None) == uot.UOT_ERR_INVALID  # V = NULL with k = 2
+    assert lib.uot_plan_apply(ctypes.byref(c), None, None, 0.1, None, None, 2, None, 1, 1, None, 1,
+                              None, 0, None) == uot.UOT_ERR_INVALID  # transpose = 2
+    dense = _cost(kind=0, d=0)
+    assert lib.uot_backward(ctypes.byref(dense), None, None, 0.1, 1.0, 1.0, None, None, 1.0,
+                            ctypes.c_void_p(0x1000), None, None, None, None, 0,
+                            None) == uot.UOT_ERR_INVALID  # dx with a dense cost
+    assert lib.uot_backward(ctypes.byref(c), None, None, 0.1, 1.0, 1.0, None, None,
+                            float("nan"), None, None, None, None, None, 0, None) == uot.UOT_ERR_INVALID
+
+
+def test_status_strings(lib):
+    for s in range(5):
+        assert lib.uot_status_string(s)
+    assert lib.uot_status_string(99) == b"unknown status"
+
+
+def test_python_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(RuntimeError):
+        uot.ti_sinkhorn(torch.ones(3), torch.ones(3), x=torch.zeros(3, 1), y=torch.zeros(3, 1),
+                        eps=0.1, rho1=1.0)

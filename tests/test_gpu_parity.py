@@ -1,0 +1,346 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element,
+on identical float32 inputs.
+
+Tolerance: relative 1e-5 (vectors: ||a - b||_inf / ||b||_inf; scalars: |a - b| / |b|), the
+bar the float32 path is held to. Iteration parity runs both sides the same number of
+iterations from f_0 = 0; converged parity runs both to tolerance.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_00730_amd as uot
+import workloads
+from tests.helpers import oracle_cost, rel_inf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def cost_kw(pr, cache=None):
+    if pr.C is not None:
+        return dict(C=dev(pr.C))
+    return dict(x=dev(pr.x), y=dev(pr.y), p=pr.p)
+
+
+def run_gpu(pr, ti, iters, tol=0.0, ce=1, f0=None, kw=None):
+    fn = uot.ti_sinkhorn if ti else uot.sinkhorn
+    kw = kw if kw is not None else cost_kw(pr)
+    f, g, info = fn(dev(pr.alpha), dev(pr.beta), eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2,
+                    max_iter=iters, tol=tol, check_every=ce,
+                    f0=None if f0 is None else dev(np.asarray(f0, np.float32)), **kw)
+    torch.cuda.synchronize()
+    return f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), info
+
+
+def run_oracle(pr, ti, iters, tol=0.0, ce=1, f0=None):
+    return oracle.sinkhorn(oracle_cost(pr), pr.alpha.astype(np.float64), pr.beta.astype(np.float64),
+                           pr.eps, pr.rho1, pr.rho2, ti=ti, max_iter=iters, tol=tol, check_every=ce,
+                           f0=f0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    uot.load_library()
+
+
+# ---------------------------------------------------------------------------------------
+# Iteration parity on the 1-D measures (N = M = 200, eps = 1e-2, rho = 1)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("ti", [True, False])
+@pytest.mark.parametrize("iters", [1, 7, 200, 2000])
+def test_oned_iteration_parity(ti, iters):
+    pr = workloads.oned()
+    _say("oned ti=%s iters=%d" % (ti, iters))
+    f, g, info = run_gpu(pr, ti, iters)
+    r = run_oracle(pr, ti, iters)
+    assert info.iters == iters
+    assert rel_inf(f, r.f) < TOL, rel_inf(f, r.f)
+    assert rel_inf(g, r.g) < TOL, rel_inf(g, r.g)
+    if ti:
+        assert abs(info.lam - r.lam) <= TOL * max(1.0, abs(r.lam))
+
+
+@pytest.mark.parametrize("ti", [True, False])
+def test_oned_converged_parity(ti):
+    """Run to max change < 1e-6 (checked every 10 iterations). The oracle with the same rule
+    stops within a check or two of the GPU (the change is a difference of nearby iterates, so
+    rounding can move the crossing); at the GPU's stopping iteration both sides agree to 1e-5,
+    and both are as close to the optimum f* as the stopping rule allows."""
+    pr = workloads.oned()
+    _say("oned converged ti=%s" % ti)
+    star = run_oracle(pr, True, 100000, tol=1e-13)
+    f, g, info = run_gpu(pr, ti, 20000, tol=1e-6, ce=10)
+    assert info.converged and info.last_change < 1e-6
+    r_rule = run_oracle(pr, ti, 20000, tol=1e-6, ce=10)
+    assert abs(info.iters - r_rule.iters) <= 20, (info.iters, r_rule.iters)
+    r = run_oracle(pr, ti, info.iters)
+    assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL, (rel_inf(f, r.f), rel_inf(g, r.g))
+    err_gpu = np.max(np.abs(f - star.f))
+    err_orc = np.max(np.abs(r.f - star.f))
+    assert err_gpu <= 1.5 * err_orc + 1e-6, (err_gpu, err_orc)
+
+
+# ---------------------------------------------------------------------------------------
+# Ragged sizes, every cost mode, rho1 != rho2
+# ---------------------------------------------------------------------------------------
+CASES = [
+    # (n, m, d, p, dense)
+    (1, 1, 1, 2.0, False),
+    (2, 3, 2, 2.0, False),
+    (7, 64, 3, 2.0, False),
+    (200, 137, 3, 2.0, False),
+    (1000, 1337, 2, 2.0, False),
+    (333, 517, 5, 2.0, False),
+    (129, 255, 8, 2.0, False),
+    (300, 211, 16, 2.0, False),
+    (97, 150, 20, 2.0, False),
+    (211, 300, 3, 1.5, False),
+    (150, 97, 2, 1.0, False),
+    (1, 5, 3, 1.5, True),
+    (64, 100, 3, 1.5, True),
+    (1000, 1337, 8, 1.5, True),
+    (513, 257, 4, 2.0, True),
+]
+
+
+@pytest.mark.parametrize("ti", [True, False])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d_m%d_d%d_p%g_%s" % (c[0], c[1], c[2], c[3], "dense" if c[4] else "pts"))
+def test_ragged_iteration_parity(case, ti):
+    n, m, d, p, dense = case
+    pr = workloads.random_small(n, m, d=d, seed=n * 31 + m, eps=0.05, rho1=0.7, rho2=2.0, p=p,
+                                dense=dense)
+    if dense:
+        pr.x = pr.y = None
+    _say("ragged %s ti=%s" % (case, ti))
+    f, g, info = run_gpu(pr, ti, 25)
+    r = run_oracle(pr, ti, 25)
+    assert rel_inf(f, r.f) < TOL, rel_inf(f, r.f)
+    assert rel_inf(g, r.g) < TOL, rel_inf(g, r.g)
+
+
+def test_dense_matches_points():
+    """The stored-cost and on-the-fly paths agree on the same problem."""
+    pr = workloads.random_small(300, 400, d=3, seed=5, eps=0.05, rho1=1.0, rho2=1.0, p=2.0, dense=True)
+    f1, g1, _ = run_gpu(pr, True, 50, kw=dict(C=dev(pr.C)))
+    f2, g2, _ = run_gpu(pr, True, 50, kw=dict(x=dev(pr.x), y=dev(pr.y), p=2.0))
+    assert rel_inf(f1, f2) < TOL and rel_inf(g1, g2) < TOL
+
+
+def test_dense_leading_dimension():
+    """ldc > m (a column slice of a wider matrix) and an unaligned ldc."""
+    pr = workloads.random_small(77, 90, d=3, seed=6, eps=0.1, rho1=1.0, rho2=0.5, p=1.5, dense=True)
+    r = run_oracle(pr, True, 30)
+    for extra in (6, 7):
+        wide = np.zeros((77, 90 + extra), np.float32)
+        wide[:, 3:93] = pr.C
+        Ct = dev(wide)[:, 3:93]
+        f, g, _ = run_gpu(pr, True, 30, kw=dict(C=Ct))
+        assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL
+
+
+def test_zero_weights():
+    pr = workloads.random_small(50, 40, d=2, seed=8, eps=0.05, rho1=1.0, rho2=1.3)
+    pr.alpha[[0, 7, 49]] = 0.0
+    pr.beta[[3, 39]] = 0.0
+    for ti in (True, False):
+        f, g, _ = run_gpu(pr, ti, 40)
+        r = run_oracle(pr, ti, 40)
+        assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
+        assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL
+
+
+def test_warm_start_resume():
+    """T + T iterations with a warm start equal 2T iterations (TI resumes from its output)."""
+    pr = workloads.random_small(120, 90, d=3, seed=9, eps=0.05, rho1=0.5, rho2=2.0)
+    f2, g2, _ = run_gpu(pr, True, 60)
+    fa, _, _ = run_gpu(pr, True, 30)
+    fb, gb, _ = run_gpu(pr, True, 30, f0=fa)
+    assert rel_inf(fb, f2) < TOL and rel_inf(gb, g2) < TOL
+    # plain Sinkhorn resumes exactly too
+    p2, q2, _ = run_gpu(pr, False, 60)
+    pa, _, _ = run_gpu(pr, False, 30)
+    pb, qb, _ = run_gpu(pr, False, 30, f0=pa)
+    assert rel_inf(pb, p2) < TOL and rel_inf(qb, q2) < TOL
+
+
+def test_invalid_weights_rejected():
+    pr = workloads.random_small(10, 10, d=2, seed=1)
+    a = pr.alpha.copy()
+    a[3] = -1.0
+    with pytest.raises(uot.UOTError) as e:
+        uot.ti_sinkhorn(dev(a), dev(pr.beta), x=dev(pr.x), y=dev(pr.y), eps=0.1, rho1=1.0, max_iter=3)
+    assert e.value.status == uot.UOT_ERR_INVALID
+    a[3] = float("nan")
+    with pytest.raises(uot.UOTError):
+        uot.sinkhorn(dev(a), dev(pr.beta), x=dev(pr.x), y=dev(pr.y), eps=0.1, rho1=1.0, max_iter=3)
+    with pytest.raises(uot.UOTError):
+        uot.sinkhorn(dev(np.zeros(10, np.float32)), dev(pr.beta), x=dev(pr.x), y=dev(pr.y), eps=0.1,
+                     rho1=1.0, max_iter=3)
+
+
+# ---------------------------------------------------------------------------------------
+# Dual value, plan application, marginals, backward
+# ---------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def solved():
+    pr = workloads.random_small(400, 333, d=3, seed=12, eps=0.05, rho1=0.8, rho2=1.6)
+    r = run_oracle(pr, True, 100000, tol=1e-12)
+    return pr, r
+
+
+@pytest.mark.parametrize("mode", ["points", "dense", "power"])
+def test_dual_value(solved, mode):
+    pr, r = solved
+    prc = workloads.random_small(400, 333, d=3, seed=12, eps=0.05, rho1=0.8, rho2=1.6,
+                                 p=1.5 if mode == "power" else 2.0, dense=(mode == "dense"))
+    cost = oracle_cost(prc) if mode != "dense" else oracle.Cost(C=prc.C.astype(np.float64))
+    a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
+    f32, g32 = r.f.astype(np.float32), r.g.astype(np.float32)
+    ref = oracle.dual_value(cost, a, b, prc.eps, prc.rho1, prc.rho2, f32.astype(np.float64),
+                            g32.astype(np.float64))
+    kw = dict(C=dev(prc.C)) if mode == "dense" else dict(x=dev(prc.x), y=dev(prc.y), p=prc.p)
+    v = uot.dual_value(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), eps=prc.eps,
+                       rho1=prc.rho1, rho2=prc.rho2, **kw)
+    assert abs(v - ref) <= TOL * abs(ref), (v, ref)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_marginals_and_plan_apply(solved, dense):
+    pr, r = solved
+    prc = workloads.random_small(400, 333, d=3, seed=12, eps=0.05, rho1=0.8, rho2=1.6, dense=dense)
+    cost = oracle_cost(prc)
+    a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
+    f32, g32 = r.f.astype(np.float32), r.g.astype(np.float32)
+    kw = dict(C=dev(prc.C)) if dense else dict(x=dev(prc.x), y=dev(prc.y), p=2.0)
+    p1, p2 = uot.marginals(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), eps=prc.eps, **kw)
+    o1, o2 = oracle.marginals(cost, a, b, prc.eps, f32.astype(np.float64), g32.astype(np.float64))
+    assert rel_inf(p1.cpu().numpy(), o1) < TOL and rel_inf(p2.cpu().numpy(), o2) < TOL
+    rng = np.random.default_rng(0)
+    for transpose, rows_src in ((False, 333), (True, 400)):
+        V = rng.normal(size=(rows_src, 7)).astype(np.float32)
+        out = uot.plan_apply(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), dev(V),
+                             transpose=transpose, eps=prc.eps, **kw).cpu().numpy()
+        ref = oracle.plan_apply(cost, a, b, prc.eps, f32.astype(np.float64), g32.astype(np.float64),
+                                V.astype(np.float64), transpose=transpose)
+        # signed sums: compare against the scale of |pi| |V|
+        scale = oracle.plan_apply(cost, a, b, prc.eps, f32.astype(np.float64), g32.astype(np.float64),
+                                  np.abs(V).astype(np.float64), transpose=transpose)
+        assert np.max(np.abs(out - ref)) <= TOL * np.max(scale)
+
+
+@pytest.mark.parametrize("p", [2.0, 1.5])
+def test_backward_matches_oracle_gradients(solved, p):
+    pr, r = solved
+    prc = workloads.random_small(400, 333, d=3, seed=12, eps=0.05, rho1=0.8, rho2=1.6, p=p)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    cost = oracle_cost(prc)
+    a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
+    f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
+    dx, dy, da, db = oracle.gradients(cost, a, b, prc.eps, prc.rho1, prc.rho2, f32.astype(np.float64),
+                                      g32.astype(np.float64), gout=0.7)
+    gx, gy, ga, gb = uot.backward(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), x=dev(prc.x),
+                                  y=dev(prc.y), p=p, eps=prc.eps, rho1=prc.rho1, rho2=prc.rho2,
+                                  grad_out=0.7)
+    assert rel_inf(gx.cpu().numpy(), dx) < TOL
+    assert rel_inf(gy.cpu().numpy(), dy) < TOL
+    # dalpha_i = rho1(1 - e^{-f/rho1}) - eps(rowsum - m(beta)): compare on the scale of its terms
+    sa = prc.rho1 + prc.eps * (np.max(np.abs(da)) + b.sum())
+    sb = prc.rho2 + prc.eps * (np.max(np.abs(db)) + a.sum())
+    assert np.max(np.abs(ga.cpu().numpy() - da)) < TOL * sa
+    assert np.max(np.abs(gb.cpu().numpy() - db)) < TOL * sb
+
+
+def test_autograd_loss_matches_oracle(solved):
+    pr, r = solved
+    x = dev(pr.x).requires_grad_(True)
+    y = dev(pr.y).requires_grad_(True)
+    al = dev(pr.alpha).requires_grad_(True)
+    be = dev(pr.beta).requires_grad_(True)
+    loss = uot.uot_loss(x, y, al, be, eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2, tol=1e-6, check_every=5)
+    loss.backward()
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    val = oracle.dual_value(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.f, r.g)
+    assert abs(loss.item() - val) <= 1e-5 * abs(val)
+    dx, dy, da, db = oracle.gradients(cost, a, b, pr.eps, pr.rho1, pr.rho2, r.f, r.g)
+    assert rel_inf(x.grad.cpu().numpy(), dx) < 1e-4
+    assert rel_inf(y.grad.cpu().numpy(), dy) < 1e-4
+
+
+# ---------------------------------------------------------------------------------------
+# Full-size sampled parity. At any iteration count, the reported potentials satisfy the
+# f-update of plain Sinkhorn with respect to their own g: f_i = k1 Smin_beta^eps(C_i - g)
+# (for TI this is the implicit equation of the H-update, App. B, with Phi's translation);
+# TI outputs also have equal tilted masses tau1 Smin_beta^rho2(g) = tau2 Smin_alpha^rho1(f)
+# (Prop. 1-2). One plain iteration from a warm start f_0 gives g = k2 Smin_alpha^eps(C - f_0).
+# The oracle evaluates these row by row / column by column in FP64 on sampled indices.
+# ---------------------------------------------------------------------------------------
+def _sample_rows_softmin(pr, g, rows):
+    """Smin_beta^eps(C_i - g) for the sampled rows i (FP64)."""
+    if pr.C is not None:
+        sub = oracle.Cost(C=pr.C[rows].astype(np.float64))
+    else:
+        sub = oracle.Cost(x=pr.x[rows].astype(np.float64), y=pr.y.astype(np.float64), p=pr.p)
+    return oracle.smin_rows(sub, pr.beta.astype(np.float64), g, pr.eps)
+
+
+def _sample_cols_softmin(pr, f, cols):
+    if pr.C is not None:
+        sub = oracle.Cost(C=np.ascontiguousarray(pr.C[:, cols]).astype(np.float64))
+    else:
+        sub = oracle.Cost(x=pr.x.astype(np.float64), y=pr.y[cols].astype(np.float64), p=pr.p)
+    return oracle.smin_cols(sub, pr.alpha.astype(np.float64), f, pr.eps)
+
+
+def _full_size_check(pr, kw, iters):
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(pr.n, size=min(256, pr.n), replace=False))
+    cols = np.sort(rng.choice(pr.m, size=min(256, pr.m), replace=False))
+    k1 = pr.rho1 / (pr.eps + pr.rho1)
+    k2 = pr.rho2 / (pr.eps + pr.rho2)
+    f, g, info = run_gpu(pr, True, iters, kw=kw)
+    assert info.iters == iters
+    ref_f = k1 * _sample_rows_softmin(pr, g, rows)
+    assert rel_inf(f[rows], ref_f) < TOL, rel_inf(f[rows], ref_f)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    tau1 = pr.rho1 / (pr.rho1 + pr.rho2)
+    lhs = tau1 * oracle.smin_vec(b, g, pr.rho2)
+    rhs = (1 - tau1) * oracle.smin_vec(a, f, pr.rho1)
+    assert abs(lhs - rhs) <= TOL * max(abs(lhs), np.max(np.abs(f))), (lhs, rhs)
+    f1, g1, _ = run_gpu(pr, False, 1, f0=f, kw=kw)
+    ref_g = k2 * _sample_cols_softmin(pr, f.astype(np.float32).astype(np.float64), cols)
+    assert rel_inf(g1[cols], ref_g) < TOL, rel_inf(g1[cols], ref_g)
+
+
+@pytest.mark.parametrize("eps,rho", [(1e-2, 1.0), (1e-1, 10.0), (1e-2, 0.1)])
+def test_cloud3d_full_size_sampled(eps, rho):
+    pr = workloads.cloud3d(eps=eps, rho=rho)
+    _say("cloud3d full size eps=%g rho=%g" % (eps, rho))
+    _full_size_check(pr, dict(x=dev(pr.x), y=dev(pr.y), p=2.0), 20)
+
+
+def test_stored8d_full_size_sampled():
+    pr = workloads.stored8d()
+    _say("stored8d full size")
+    _full_size_check(pr, dict(C=dev(pr.C)), 20)
+
+
+def test_highdim16_full_size_sampled():
+    pr = workloads.highdim16()
+    _say("highdim16 full size")
+    _full_size_check(pr, dict(x=dev(pr.x), y=dev(pr.y), p=2.0), 10)
