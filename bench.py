@@ -49,6 +49,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="", help="restrict to one eps,rho pair, e.g. 0.01,1")
+    ap.add_argument("--points-kernel", choices=("auto", "valu", "mfma", "mfma2"), default="auto",
+                    help="p = 2 softmin implementation")
     return ap.parse_args()
 
 
@@ -115,6 +117,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     uot.load_library()
+    uot.set_points_kernel({"auto": 0, "valu": 1, "mfma": 2, "mfma2": 3}[args.points_kernel])
     pr = workloads.cloud3d(n=args.n, m=args.n)
     dev = torch.device("cuda:0")
     tens = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
@@ -146,7 +149,9 @@ def main():
     achieved = kentries / (kms * 1e-3) if kms > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_EXP_PER_S / 1e9,
                 "unit": "Gexp/s", "frac": achieved / PEAK_EXP_PER_S, "traffic": None,
-                "kernel": "k_points_partial<3,kSqEuc,4>", "launches": launches,
+                "kernel": ("k_points_partial<3,kSqEuc,4>" if args.points_kernel == "valu"
+                           else "k_points_mfma<3,%d>" % (2 if args.points_kernel == "mfma2" else 1)),
+                "launches": launches,
                 "avg_launch_ms": kms / launches if launches else None,
                 "entries_per_launch": kentries / launches if launches else None}
     by_pair = {}

@@ -202,6 +202,16 @@ void uot_profile_enable(int32_t on);
 void uot_profile_reset(void);
 int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries);
 
+/*
+ * Implementation of the squared-Euclidean (p = 2) points softmin, process-wide:
+ * 0 = default (matrix cores, one 32-target tile per wave), 1 = vector ALU, 2 = matrix
+ * cores with one 32-target tile per wave, 3 = matrix cores with two. Returns the previous
+ * setting, or -1 for an unknown value (then nothing changes). Both compute the same
+ * softmin; the switch exists for benchmarks and must not be changed while calls are
+ * running.
+ */
+int32_t uot_set_points_kernel(int32_t variant);
+
 /* Static description of a status code. */
 const char *uot_status_string(uot_status s);
 

@@ -20,7 +20,7 @@ import torch
 
 __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_apply", "marginals",
            "backward", "workspace_bytes", "UOTLoss", "uot_loss", "library_path", "load_library",
-           "profile_enable", "profile_reset", "profile_read"]
+           "profile_enable", "profile_reset", "profile_read", "set_points_kernel"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -98,6 +98,8 @@ def load_library():
     lib.uot_profile_reset.restype = None
     lib.uot_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.uot_profile_read.restype = I64
+    lib.uot_set_points_kernel.argtypes = [I32]
+    lib.uot_set_points_kernel.restype = I32
     _lib = lib
     return lib
 
@@ -194,6 +196,18 @@ def profile_read(kind: int):
     ms, ent = ctypes.c_double(0.0), ctypes.c_double(0.0)
     n = load_library().uot_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(ent))
     return int(n), ms.value, ent.value
+
+
+POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA, POINTS_KERNEL_MFMA2 = 0, 1, 2, 3
+
+
+def set_points_kernel(variant: int) -> int:
+    """Select the p = 2 points-softmin implementation (0 auto, 1 VALU, 2 MFMA with one
+    32-target tile per wave, 3 MFMA with two); returns the previous setting."""
+    prev = load_library().uot_set_points_kernel(int(variant))
+    if prev < 0:
+        raise ValueError("unknown points kernel variant %r" % (variant,))
+    return prev
 
 
 def workspace_bytes(which: int = UOT_WS_SOLVE, *, C=None, x=None, y=None, p: float = 2.0) -> int:

@@ -87,41 +87,18 @@ __device__ __forceinline__ void write_record(float *rec, int t, const float *yc,
 #pragma unroll
     for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
     rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
+    rp[D + 1] = 1.0f;  // multiplies -sigma_t in the matrix-core contraction
+#pragma unroll
+    for (int k = D + 2; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;  // padding read by MFMA
   } else if constexpr (MODE == kPower) {
 #pragma unroll
     for (int k = 0; k < D; ++k) rp[k] = yc[k];
     rp[D] = (float)(sc * (double)hf + lw2);
+#pragma unroll
+    for (int k = D + 1; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;
   } else {
     rp[0] = (float)(sc * (double)hf + lw2);
   }
-}
-
-template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
-  if (a.st->done) return;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
-  if (t < a.nt) {
-    double lse2 = combine_lse2(a.part, a.nsplit, a.nt, t);
-    float yc[D > 0 ? D : 1];
-    double yn2 = 0.0;
-    if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, t, a.st->mu, yc);
-    if constexpr (MODE == kSqEuc) lse2 -= a.sc * yn2;
-    const double S = -lse2 / a.sc;  // softmin over the stored source potential
-    const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
-    const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
-    const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
-    const float hf = (float)hnew;
-    const float old = a.pot[t];
-    a.pot[t] = hf;
-    dmx = dmn = (double)hf - (double)old;
-    const float w = a.w[t];
-    write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
-    if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
-    if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);
-  }
-  block_reduce_part(mm, ms, dmx, dmn);
-  if (threadIdx.x == 0) a.bparts[blockIdx.x] = BlockPart{mm, ms, dmx, dmn};
 }
 
 template <int D, int MODE>
@@ -138,6 +115,12 @@ __global__ __launch_bounds__(kBlock) void k_build_records(RecordArgs a) {
     const float w = a.w[t];
     write_record<D, MODE>(a.rec, t, yc, yn2, hf, w, a.sc);
     if (w > 0.0f) { mm = log((double)w) - (double)hf / a.rho; ms = 1.0; }
+  } else if (t < rec_count(a.n)) {
+    // pad record: zero coordinates, weight 0
+    float yc[D > 0 ? D : 1];
+#pragma unroll
+    for (int k = 0; k < (D > 0 ? D : 1); ++k) yc[k] = 0.0f;
+    write_record<D, MODE>(a.rec, t, yc, 0.0, 0.0f, 0.0f, a.sc);
   }
   if (a.bparts) {
     block_reduce_part(mm, ms, dmx, dmn);
@@ -145,9 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_build_records(RecordArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
+// Reduces the block partials of a half-step (or of the start) into the scalar state; run by
+// one block of kBlock threads. Thread 0 writes the results.
+__device__ void reduce_scalars(const ReduceArgs &a) {
   SolveState *st = a.st;
-  if (a.kind != kReduceInit && st->done) return;
   double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
   for (int b = threadIdx.x; b < a.nb; b += kBlock) {
     const BlockPart q = a.bparts[b];
@@ -208,6 +192,71 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
+  if (a.kind != kReduceInit && a.st->done) return;
+  reduce_scalars(a);
+}
+
+// Threads per target in the combine kernel: each merges every 4th split partial, then the
+// four (max, sum) pairs are merged with lane shuffles.
+constexpr int kCombLanes = 4;
+constexpr int kCombTargets = kBlock / kCombLanes;
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
+  if (a.st->done) return;
+  __shared__ int s_last;
+  const int sub = threadIdx.x % kCombLanes;
+  const int t = blockIdx.x * kCombTargets + threadIdx.x / kCombLanes;
+  const int tc = t < a.nt ? t : a.nt - 1;
+  // log2-sum over the split partials of target tc: M + log2(sum_p l_p 2^{m_p - M})
+  float M = -FLT_MAX;
+  for (int p = sub; p < a.nsplit; p += kCombLanes) M = fmaxf(M, a.part[(size_t)p * a.nt + tc].x);
+  M = fmaxf(M, __shfl_xor(M, 1, kCombLanes));
+  M = fmaxf(M, __shfl_xor(M, 2, kCombLanes));
+  float L = 0.0f;
+  for (int p = sub; p < a.nsplit; p += kCombLanes) {
+    const float2 q = a.part[(size_t)p * a.nt + tc];
+    L += q.y * __builtin_amdgcn_exp2f(q.x - M);
+  }
+  L += __shfl_xor(L, 1, kCombLanes);
+  L += __shfl_xor(L, 2, kCombLanes);
+
+  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+  if (sub == 0 && t < a.nt) {
+    double lse2 = (double)M + log2((double)L);
+    float yc[D > 0 ? D : 1];
+    double yn2 = 0.0;
+    if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, t, a.st->mu, yc);
+    if constexpr (MODE == kSqEuc) lse2 -= a.sc * yn2;
+    const double S = -lse2 / a.sc;  // softmin over the stored source potential
+    const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
+    const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
+    const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
+    const float hf = (float)hnew;
+    const float old = a.pot[t];
+    a.pot[t] = hf;
+    dmx = dmn = (double)hf - (double)old;
+    const float w = a.w[t];
+    write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
+    if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
+    if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);
+  }
+  block_reduce_part(mm, ms, dmx, dmn);
+  // The last block to finish reduces all block partials into the scalar state.
+  if (threadIdx.x == 0) {
+    a.bparts[blockIdx.x] = BlockPart{mm, ms, dmx, dmn};
+    __threadfence();
+    const unsigned prev = atomicAdd(&a.st->ticket, 1u);
+    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  reduce_scalars(a.red);
+  if (threadIdx.x == 0) a.st->ticket = 0u;
+}
+
 // Zeroes the flags of the state and computes the common mean of x and y (points costs).
 __global__ __launch_bounds__(kBlock) void k_center(const float *x, int n, const float *y, int m,
                                                    int d, SolveState *st) {
@@ -225,6 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_center(const float *x, int n, const 
     st->pos_a = 0;
     st->pos_b = 0;
     st->iter = 0;
+    st->ticket = 0u;
   }
 }
 
@@ -304,14 +354,14 @@ __global__ __launch_bounds__(kBlock) void k_dual_reduce(DualArgs a, int nb) {
 
 template <int D, int MODE>
 hipError_t combine_for(const CombineArgs &a, hipStream_t s) {
-  const int nb = (a.nt + kBlock - 1) / kBlock;
+  const int nb = (a.nt + kCombTargets - 1) / kCombTargets;
   hipLaunchKernelGGL((k_combine<D, MODE>), dim3(nb), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 template <int D, int MODE>
 hipError_t records_for(const RecordArgs &a, hipStream_t s) {
-  const int nb = (a.n + kBlock - 1) / kBlock;
+  const int nb = (rec_count(a.n) + kBlock - 1) / kBlock;
   hipLaunchKernelGGL((k_build_records<D, MODE>), dim3(nb), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -366,6 +416,8 @@ hipError_t dual_for(const DualArgs &a, int nb, hipStream_t s) {
   } while (0)
 
 }  // namespace
+
+int combine_blocks(int nt) { return (nt + kCombTargets - 1) / kCombTargets; }
 
 hipError_t launch_combine(const CombineArgs &a, hipStream_t s) {
   UOT_DISPATCH(combine_for, a.mode, a.d, a, s);

@@ -147,15 +147,274 @@ hipError_t launch_mode(const PointsArgs &a, hipStream_t st) {
   }
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Squared-Euclidean costs on the matrix cores. The base-2 exponent of entry (s, t), shifted
+// by the running reference sigma_t of its target, is the augmented dot product
+//   v_ts - sigma_t = sum_{e < K} A_se B_et,
+//   A_s = (u_s[0..D-1], b_s, 1, 0...),   B_t = (y_t - mu, 1, -sigma_t, 0...),
+// a K = D+2 (rounded to even) contraction done by v_mfma_f32_32x32x2f32 with sources as the
+// 32 rows and targets as the 32 columns of each output tile; the VALU then does one exp2 and
+// one add per entry. A_s comes from the source record plus the constant 1; B_t is built in
+// registers. Element e of k-slice ks for lane half h is e = KS*h + ks, so the KS elements a
+// lane needs from one record are contiguous.
+//
+// Each lane owns one target column (lane % 32) and 16 source rows of every tile. sigma_t is
+// shared by the two lanes of a column and is raised only when a tile's sum of 2^{v - sigma}
+// exceeds 2^64 in either lane (or at the column's first tile); otherwise the exponents are
+// used as they come out of the matrix core. The next tile's MFMAs are issued before the
+// current tile's exps (software pipelining); an accumulator computed with an older sigma is
+// corrected on the slow path.
+// ---------------------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaWaves = 4;  // waves per block
+
+template <int D>
+struct MfmaShape {
+  static constexpr int K = ((D + 2) + 1) / 2 * 2;  // augmented depth, even
+  static constexpr int KS = K / 2;                  // k-slices of the 32x32x2 instruction
+  static constexpr int SD = rec_stride(kSqEuc, D);
+  static constexpr int EB = D;                      // element holding b_s (A) / 1 (B)
+  static constexpr int ES = D + 1;                  // element holding 1 (A) / -sigma (B)
+  static_assert(K <= SD, "record shorter than the contraction");
+};
+
+template <int D, int TJ>
+__global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  using S = MfmaShape<D>;
+  constexpr int KS = S::KS, SD = S::SD;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 31;
+  const int h = lane >> 5;
+  const int tbase = (blockIdx.x * kMfmaWaves + wave) * (32 * TJ);
+
+  // B fragments: element e = KS*h + ks of (y - mu, 1, -sigma, 0...); sigma starts at 0
+  float bf[TJ][KS];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    const int t = tbase + tj * 32 + col;
+    const bool valid = t < a.nt;
+    const int tc = valid ? t : 0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int e = KS * h + ks;
+      const int ec = e < a.d ? e : 0;
+      const float coord = a.tgt[(size_t)tc * a.d + ec] - (float)a.mu[ec];
+      bf[tj][ks] = (e < D) ? ((valid && e < a.d) ? coord : 0.0f) : (e == S::EB ? 1.0f : 0.0f);
+    }
+  }
+
+  const int s0 = blockIdx.y * a.split_len;
+  const int s1 = min(a.ns, s0 + a.split_len);
+
+  // A fragments of the tile starting at sb: record elements [KS*h, KS*h + KS) (in bounds since
+  // K <= SD). Tiles end at s1 or at the padded end of the record array, whose pad records
+  // carry b = -inf (weight 0), so no source needs a mask.
+  auto load_a = [&](int sb, float *af) {
+    const float *rp = a.rec + (size_t)(sb + col) * SD + KS * h;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) af[ks] = rp[ks];
+  };
+  const f32x16 zero = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
+                       0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  auto tile_mfma = [&](const float *af, int tj) {
+    f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[0], bf[tj][0], zero, 0, 0, 0);
+#pragma unroll
+    for (int ks = 1; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[ks], bf[tj][ks], acc, 0, 0, 0);
+    return acc;
+  };
+
+  float sig[TJ], l[TJ];  // running reference and sum of 2^{v - sig} (this lane's rows)
+  bool started[TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) { sig[tj] = 0.0f; l[tj] = 0.0f; started[tj] = false; }
+  const int es_ks = S::ES - KS * h;  // k-slice holding -sigma in this lane half
+
+  // Adds the tile held in acc (computed with reference `used`) to the running sums. The
+  // fast/slow decision is wave-uniform, so the common path has no divergence and no
+  // cross-lane traffic.
+  auto consume = [&](f32x16 (&acc)[TJ], float (&used)[TJ]) {
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) {
+      float ts = 0.0f;
+      const bool same = __all(used[tj] == sig[tj] && started[tj]);
+      if (same) {
+        float q0 = fast_exp2(acc[tj][0]), q1 = fast_exp2(acc[tj][1]);
+        float q2 = fast_exp2(acc[tj][2]), q3 = fast_exp2(acc[tj][3]);
+#pragma unroll
+        for (int r = 4; r < 16; r += 4) {
+          q0 += fast_exp2(acc[tj][r]);
+          q1 += fast_exp2(acc[tj][r + 1]);
+          q2 += fast_exp2(acc[tj][r + 2]);
+          q3 += fast_exp2(acc[tj][r + 3]);
+        }
+        ts = (q0 + q1) + (q2 + q3);
+      }
+      if (!same || __any(!(ts <= 0x1p64f))) {
+        // all lanes: re-centre each column on its largest exponent (exact for every column)
+        const float corr = sig[tj] - used[tj];  // acc - corr = v - sig
+        float tm = acc[tj][0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) tm = fmaxf(tm, acc[tj][r]);
+        tm -= corr;
+        tm = fmaxf(tm, __shfl_xor(tm, 32, 64));
+        if (tm > -INFINITY) {
+          const float delta = started[tj] ? fmaxf(tm, 0.0f) : tm;
+          const float off = corr + delta;
+          float t2 = 0.0f;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) t2 += fast_exp2(acc[tj][r] - off);
+          // first tile: no rescale (delta may be far below -126 and 0 * 2^{-delta} is NaN)
+          l[tj] = started[tj] ? l[tj] * fast_exp2(-delta) + t2 : t2;
+          sig[tj] += delta;
+          started[tj] = true;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) bf[tj][ks] = (ks == es_ks) ? -sig[tj] : bf[tj][ks];
+        }
+      } else {
+        l[tj] += ts;
+      }
+    }
+  };
+
+  // software pipeline over tiles of 32 sources, two accumulator sets used in turn
+  float an[KS];
+  f32x16 accA[TJ], accB[TJ];
+  float usedA[TJ], usedB[TJ];
+  load_a(s0, an);
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) { accA[tj] = tile_mfma(an, tj); usedA[tj] = sig[tj]; }
+  if (s0 + 32 < s1) load_a(s0 + 32, an);
+  for (int sb = s0; sb < s1; sb += 64) {
+    const bool has_b = sb + 32 < s1;
+    if (has_b) {
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) { accB[tj] = tile_mfma(an, tj); usedB[tj] = sig[tj]; }
+      if (sb + 64 < s1) load_a(sb + 64, an);
+    }
+    consume(accA, usedA);
+    if (has_b) {
+      if (sb + 64 < s1) {
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) { accA[tj] = tile_mfma(an, tj); usedA[tj] = sig[tj]; }
+        if (sb + 96 < s1) load_a(sb + 96, an);
+      }
+      consume(accB, usedB);
+    }
+  }
+
+  // merge the two half-waves of each column (same sigma; sums add)
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    const float lo = __shfl_xor(l[tj], 32, 64);
+    const float ll = l[tj] + lo;
+    const int t = tbase + tj * 32 + col;
+    if (h == 0 && t < a.nt)
+      a.part[(size_t)blockIdx.y * a.nt + t] = make_float2(ll > 0.0f ? sig[tj] : -FLT_MAX, ll);
+  }
+}
+
+
+template <int D, int TJ>
+hipError_t launch_mfma_tj(const PointsArgs &a, hipStream_t st) {
+  const int tpb = kMfmaWaves * 32 * TJ;
+  dim3 grid((a.nt + tpb - 1) / tpb, a.nsplit);
+  hipLaunchKernelGGL((k_points_mfma<D, TJ>), grid, dim3(64 * kMfmaWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_mfma_bucket(const PointsArgs &a, hipStream_t st) {
+  return mfma_tiles_per_wave() == 2 ? launch_mfma_tj<D, 2>(a, st) : launch_mfma_tj<D, 1>(a, st);
+}
+
+hipError_t launch_mfma(const PointsArgs &a, hipStream_t st) {
+  switch (dim_bucket(a.d)) {
+    case 1: return launch_mfma_bucket<1>(a, st);
+    case 2: return launch_mfma_bucket<2>(a, st);
+    case 3: return launch_mfma_bucket<3>(a, st);
+    case 4: return launch_mfma_bucket<4>(a, st);
+    case 5: return launch_mfma_bucket<5>(a, st);
+    case 6: return launch_mfma_bucket<6>(a, st);
+    case 7: return launch_mfma_bucket<7>(a, st);
+    case 8: return launch_mfma_bucket<8>(a, st);
+    case 12: return launch_mfma_bucket<12>(a, st);
+    case 16: return launch_mfma_bucket<16>(a, st);
+    case 24: return launch_mfma_bucket<24>(a, st);
+    case 32: return launch_mfma_bucket<32>(a, st);
+    case 48: return launch_mfma_bucket<48>(a, st);
+    case 64: return launch_mfma_bucket<64>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Kern>
+int occupancy_blocks(Kern kern) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+template <int D>
+int points_blocks_per_cu_bucket(int mode) {
+  if (mode == kSqEuc && g_points_variant != kPointsValu)
+    return mfma_tiles_per_wave() == 2 ? occupancy_blocks(k_points_mfma<D, 2>)
+                                      : occupancy_blocks(k_points_mfma<D, 1>);
+  constexpr int R = targets_per_thread<D>();
+  return mode == kSqEuc ? occupancy_blocks(k_points_partial<D, kSqEuc, R>)
+                        : occupancy_blocks(k_points_partial<D, kPower, R>);
+}
+
 }  // namespace
 
+int g_points_variant = kPointsAuto;
+
+int points_blocks_per_cu(int mode, int d) {
+  switch (dim_bucket(d)) {
+    case 1: return points_blocks_per_cu_bucket<1>(mode);
+    case 2: return points_blocks_per_cu_bucket<2>(mode);
+    case 3: return points_blocks_per_cu_bucket<3>(mode);
+    case 4: return points_blocks_per_cu_bucket<4>(mode);
+    case 5: return points_blocks_per_cu_bucket<5>(mode);
+    case 6: return points_blocks_per_cu_bucket<6>(mode);
+    case 7: return points_blocks_per_cu_bucket<7>(mode);
+    case 8: return points_blocks_per_cu_bucket<8>(mode);
+    case 12: return points_blocks_per_cu_bucket<12>(mode);
+    case 16: return points_blocks_per_cu_bucket<16>(mode);
+    case 24: return points_blocks_per_cu_bucket<24>(mode);
+    case 32: return points_blocks_per_cu_bucket<32>(mode);
+    case 48: return points_blocks_per_cu_bucket<48>(mode);
+    case 64: return points_blocks_per_cu_bucket<64>(mode);
+    default: return 0;
+  }
+}
+
+// 32-target column tiles per wave of the matrix-core kernel.
+int mfma_tiles_per_wave() { return g_points_variant == kPointsMfma2 ? 2 : 1; }
+
+bool points_uses_mfma(int mode, int d) {
+  (void)d;
+  if (mode != kSqEuc) return false;
+  return g_points_variant != kPointsValu;
+}
+
 int points_targets_per_block(int mode, int d) {
-  (void)mode;
+  if (points_uses_mfma(mode, d)) return kMfmaWaves * 32 * mfma_tiles_per_wave();
   const int b = dim_bucket(d);
   return 256 * (b <= 4 ? 4 : (b <= 8 ? 2 : 1));
 }
 
+int points_split_align(int mode, int d) { return points_uses_mfma(mode, d) ? 32 : 8; }
+
 hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st) {
+  if (points_uses_mfma(mode, a.d)) return launch_mfma(a, st);
   if (mode == kSqEuc) return launch_mode<kSqEuc>(a, st);
   if (mode == kPower) return launch_mode<kPower>(a, st);
   return hipErrorInvalidValue;

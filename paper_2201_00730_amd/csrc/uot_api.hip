@@ -86,21 +86,42 @@ uot_status check_cost_ptrs(const uot_cost *c) {
 // ---------------------------------------------------------------------------------------
 // Launch shapes and workspace layout
 // ---------------------------------------------------------------------------------------
-constexpr int kTargetBlocks = 2048;  // blocks wanted per softmin launch (256 CUs x 8)
+constexpr int kMaxSplits = 64;          // cap on source splits (bounds the partials buffer)
+constexpr int kDefaultResidentBlocks = 2048;
 
 struct Split {
   int len = 1, n = 1;
 };
 
-// Splits of `ns` sources so that tiles * nsplit ~ kTargetBlocks, split lengths multiple of 8.
-Split make_split(int ns, int tiles, int min_len) {
+// Number of CUs of the current device (cached; a default when no device is visible).
+int device_cus() {
+  static int cus = -1;
+  if (cus < 0) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess &&
+        p.multiProcessorCount > 0)
+      cus = p.multiProcessorCount;
+    else
+      cus = 0;
+    (void)hipGetLastError();
+  }
+  return cus;
+}
+
+// Splits of `ns` sources over `tiles` target tiles: as many splits as fill one round of
+// resident blocks (capacity = blocks per CU x CUs), capped at kMaxSplits and by a minimum
+// split length; split lengths are multiples of `align`.
+Split make_split(int ns, int tiles, int min_len, int align, int capacity) {
   Split s;
-  int want = (kTargetBlocks + tiles - 1) / tiles;
-  int maxn = (ns + min_len - 1) / min_len;
+  if (capacity <= 0) capacity = kDefaultResidentBlocks;
+  int want = capacity / tiles;
+  const int maxn = (ns + min_len - 1) / min_len;
   if (want > maxn) want = maxn;
+  if (want > kMaxSplits) want = kMaxSplits;
   if (want < 1) want = 1;
   int len = (ns + want - 1) / want;
-  len = (len + 7) / 8 * 8;
+  len = (len + align - 1) / align * align;
   s.len = len;
   s.n = (ns + len - 1) / len;
   return s;
@@ -115,6 +136,7 @@ struct HalfShape {
 
 HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
   HalfShape h;
+  const int cus = device_cus();
   if (mode == kDense) {
     if (targets_are_rows) {
       h.rows_kernel = true;
@@ -122,14 +144,16 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
       h.split.n = 1;
     } else {
       const int tiles = (nt + dense_cols_per_block() - 1) / dense_cols_per_block();
-      h.split = make_split(ns, tiles, 64);
+      h.split = make_split(ns, tiles, 64, 8, cus > 0 ? 8 * cus : 0);
     }
   } else {
     const int tpb = points_targets_per_block(mode, d);
     const int tiles = (nt + tpb - 1) / tpb;
-    h.split = make_split(ns, tiles, 64);
+    const int per_cu = points_blocks_per_cu(mode, d);
+    h.split = make_split(ns, tiles, 64, points_split_align(mode, d),
+                         (cus > 0 && per_cu > 0) ? per_cu * cus : 0);
   }
-  h.nb_combine = (nt + kBlock - 1) / kBlock;
+  h.nb_combine = combine_blocks(nt);
   return h;
 }
 
@@ -156,14 +180,18 @@ Layout make_layout(const uot_cost *c, int which) {
   L.state = take(sizeof(SolveState));
   L.pot_x = take((size_t)n * sizeof(float));
   L.pot_y = take((size_t)m * sizeof(float));
-  L.rec_x = take((size_t)n * stride * sizeof(float));
-  L.rec_y = take((size_t)m * stride * sizeof(float));
-  const size_t part_g = (size_t)L.g.split.n * m * sizeof(float2);
-  const size_t part_f = (size_t)L.f.split.n * n * sizeof(float2);
+  L.rec_x = take((size_t)rec_count(n) * stride * sizeof(float));
+  L.rec_y = take((size_t)rec_count(m) * stride * sizeof(float));
+  // sized for the largest split count any device may choose, so the workspace size does
+  // not depend on the device
+  const size_t part_g = (size_t)kMaxSplits * m * sizeof(float2);
+  const size_t part_f = (size_t)kMaxSplits * n * sizeof(float2);
   L.part = take(part_g > part_f ? part_g : part_f);
-  const int nb = (n > m ? n : m) + kBlock - 1;
-  L.bparts = take((size_t)(nb / kBlock + 1) * sizeof(BlockPart));
-  L.dual = take((size_t)(nb / kBlock + 1) * 6 * sizeof(double));
+  const int nmax = n > m ? n : m;
+  const int nrec = (rec_count(nmax) + kBlock - 1) / kBlock;
+  const int nbp = combine_blocks(nmax) > nrec ? combine_blocks(nmax) : nrec;
+  L.bparts = take((size_t)(nbp + 1) * sizeof(BlockPart));
+  L.dual = take((size_t)((nmax + kBlock - 1) / kBlock + 1) * 6 * sizeof(double));
   if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
     L.rowsum_x = take((size_t)n * sizeof(float));
     L.rowsum_y = take((size_t)m * sizeof(float));
@@ -407,8 +435,7 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ca.ep = epilogue_for(k, g_step);
   ca.sc = k.sc;
   ca.eps = k.eps;
-  UOT_HIP(launch_combine(ca, k.s));
-  ReduceArgs ra;
+  ReduceArgs &ra = ca.red;
   ra.bparts = ca.bparts;
   ra.nb = h.nb_combine;
   ra.st = st;
@@ -421,7 +448,7 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
   ra.tol = tol;
   ra.check_every = check_every;
-  UOT_HIP(launch_reduce(ra, k.s));
+  UOT_HIP(launch_combine(ca, k.s));
   return UOT_OK;
 }
 
@@ -442,7 +469,7 @@ uot_status build_records(const Ctx &k, bool x_side, const float *pot, bool copy_
   a.rho = x_side ? k.rho1 : k.rho2;
   a.sc = k.sc;
   a.st = k.st();
-  if (nblocks) *nblocks = (a.n + kBlock - 1) / kBlock;
+  if (nblocks) *nblocks = (rec_count(a.n) + kBlock - 1) / kBlock;
   UOT_HIP(launch_build_records(a, k.s));
   return UOT_OK;
 }
@@ -815,6 +842,13 @@ uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *b
   uot::g_last_error.clear();
   return uot::backward(cost, alpha, beta, eps, rho1, rho2, f, g, grad_out, dx, dy, dalpha, dbeta,
                        workspace, workspace_bytes, stream);
+}
+
+int32_t uot_set_points_kernel(int32_t variant) {
+  if (variant < uot::kPointsAuto || variant > uot::kPointsMfma2) return -1;
+  const int32_t prev = uot::g_points_variant;
+  uot::g_points_variant = variant;
+  return prev;
 }
 
 void uot_profile_enable(int32_t on) {

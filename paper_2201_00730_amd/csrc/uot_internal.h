@@ -28,13 +28,20 @@ __host__ __device__ constexpr int dim_bucket(int d) {
 
 // Source-record stride in floats for a cost mode and a (bucketed) dimension D. A source
 // record holds what a softmin needs of one source point: D coordinates (scaled for kSqEuc,
-// zero beyond the true dimension) then the log2-domain offset b; dense records hold b only.
+// zero beyond the true dimension) then the log2-domain offset b; kSqEuc records continue
+// with the constant 1 of the matrix-core contraction and zeros up to an even length; dense
+// records hold b only.
 __host__ __device__ constexpr int rec_stride(int mode, int D) {
-  return mode == kDense ? 1 : ((D + 1 + 3) / 4) * 4;
+  return mode == kDense ? 1
+         : mode == kSqEuc ? ((((D + 2) + 1) / 2 * 2) + 3) / 4 * 4
+                          : ((D + 1 + 3) / 4) * 4;
 }
 __host__ __device__ constexpr int rec_stride_for(int mode, int d) {
   return rec_stride(mode, dim_bucket(d));
 }
+// Record arrays hold this many records: whole tiles of 32, the tail filled with weight-0
+// records (b = -inf) that the matrix-core kernel reads without masking.
+__host__ __device__ constexpr int rec_count(int n) { return (n + 31) / 32 * 32; }
 
 // Device-resident scalar state of one solve, all double precision.
 // Potentials are stored untranslated ("hat" values); the reported TI potentials are
@@ -56,7 +63,7 @@ struct SolveState {
   int32_t error;      // bit 1: invalid weights, bit 2: non-finite result
   int32_t pos_a;      // some alpha_i > 0
   int32_t pos_b;      // some beta_j > 0
-  int32_t pad_;
+  uint32_t ticket;    // arrival counter of the combine kernel's blocks (0 between launches)
   double mu[kMaxDim]; // common centring of x and y (points costs)
 };
 
@@ -102,6 +109,14 @@ struct PointsArgs {
 
 hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st);
 int points_targets_per_block(int mode, int d);
+int points_split_align(int mode, int d);   // split lengths are multiples of this
+// Resident 256-thread blocks per CU of the selected points kernel (0 if unknown).
+int points_blocks_per_cu(int mode, int d);
+bool points_uses_mfma(int mode, int d);
+// Points-softmin kernel selection (process-wide): matrix cores for p = 2 unless forced.
+enum PointsVariant : int { kPointsAuto = 0, kPointsValu = 1, kPointsMfma = 2, kPointsMfma2 = 3 };
+extern int g_points_variant;
+int mfma_tiles_per_wave();  // 32-target column tiles per wave of the matrix-core kernel
 
 struct DenseArgs {
   const float *C;
@@ -120,6 +135,18 @@ hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st);
 int dense_cols_per_block();
 int dense_rows_per_block();
 
+enum ReduceKind : int { kReduceInit = 0, kReduceG = 1, kReduceF = 2 };
+struct ReduceArgs {
+  const BlockPart *bparts;
+  int nb;
+  SolveState *st;
+  int kind;
+  int ti;
+  double rho1, rho2, kappa_t, tau1, tau2;
+  double tol;
+  int check_every;
+};
+
 // Epilogue kernels (kernels_epilogue.hip).
 struct CombineArgs {
   const float2 *part;  // [nsplit, nt]
@@ -135,21 +162,13 @@ struct CombineArgs {
   Epilogue ep;
   double sc;           // log2(e)/eps (double)
   double eps;
+  ReduceArgs red;      // scalar reduction run by the last block to finish (bparts, st, kind...)
 };
 
+// Combine + epilogue + (in its last block) the scalar reduction of the half-step.
 hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
+int combine_blocks(int nt);
 
-enum ReduceKind : int { kReduceInit = 0, kReduceG = 1, kReduceF = 2 };
-struct ReduceArgs {
-  const BlockPart *bparts;
-  int nb;
-  SolveState *st;
-  int kind;
-  int ti;
-  double rho1, rho2, kappa_t, tau1, tau2;
-  double tol;
-  int check_every;
-};
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 
 // Build source records from a potential (solve start, dual value, plan, backward).

@@ -344,3 +344,27 @@ def test_highdim16_full_size_sampled():
     pr = workloads.highdim16()
     _say("highdim16 full size")
     _full_size_check(pr, dict(x=dev(pr.x), y=dev(pr.y), p=2.0), 10)
+
+
+@pytest.mark.parametrize("n,m,d", [(1, 1, 1), (33, 65, 3), (1000, 1337, 2), (300, 211, 16), (97, 150, 20)])
+def test_points_kernels_agree(n, m, d):
+    """The VALU and matrix-core implementations of the p = 2 softmin both match the oracle."""
+    pr = workloads.random_small(n, m, d=d, seed=n + 7 * m, eps=0.02, rho1=0.5, rho2=3.0)
+    r = run_oracle(pr, True, 15)
+    # Both evaluate the exponent in the expanded form |x|^2 + |y|^2 - 2<x, y> on centred
+    # points; its float32 rounding is about 2^-24 (|x - mu| + |y - mu|)^2 per term in
+    # potential units (independent of eps), accumulated over the d products. The default
+    # (matrix-core) path is held to 1e-5; the vector-ALU variant to that bound when larger.
+    xc = pr.x.astype(np.float64) - np.concatenate([pr.x, pr.y]).astype(np.float64).mean(0)
+    yc = pr.y.astype(np.float64) - np.concatenate([pr.x, pr.y]).astype(np.float64).mean(0)
+    span = np.sqrt((xc ** 2).sum(1)).max() + np.sqrt((yc ** 2).sum(1)).max()
+    bound = max(TOL, 2.0 ** -24 * (d + 4) * span ** 2 / np.max(np.abs(r.f)))
+    prev = uot.set_points_kernel(uot.POINTS_KERNEL_VALU)
+    try:
+        for variant, tol in ((uot.POINTS_KERNEL_VALU, bound), (uot.POINTS_KERNEL_MFMA, TOL),
+                             (uot.POINTS_KERNEL_MFMA2, TOL)):
+            uot.set_points_kernel(variant)
+            f, g, _ = run_gpu(pr, True, 15)
+            assert rel_inf(f, r.f) < tol and rel_inf(g, r.g) < tol, (variant, rel_inf(f, r.f), tol)
+    finally:
+        uot.set_points_kernel(prev)
