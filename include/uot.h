@@ -188,6 +188,45 @@ uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *b
                         float *dx, float *dy, float *dalpha, float *dbeta, void *workspace,
                         size_t workspace_bytes, void *stream);
 
+/* Per-problem outcome of uot_ti_sinkhorn_batched (the status array). */
+enum {
+  UOT_BATCH_CONVERGED = 0,  /* the tol test passed                                           */
+  UOT_BATCH_MAX_ITER = 1,   /* max_iter reached first (or tol = 0)                           */
+  UOT_BATCH_INVALID = 2,    /* bad weights (negative, NaN, inf, zero mass) or eps/rho <= 0    */
+  UOT_BATCH_NUMERIC = 3     /* non-finite potentials                                          */
+};
+
+/*
+ * Many independent KL-UOT problems with point costs, solved together by translation-
+ * invariant Sinkhorn (Sec. 3, Prop. 4 / App. B), each to its own convergence. Problem b
+ * owns points [offN[b], offN[b+1]) of x/alpha/f and [offM[b], offM[b+1]) of y/beta/g
+ * (every problem has at least one point on each side).
+ *  B >= 1; offN, offM (host) [B+1], offN[0] = offM[0] = 0, nondecreasing.
+ *  d in [1, 8]; p >= 1 (p = 2: squared Euclidean cost; otherwise ||x - y||^p).
+ *  x [offN[B], d], y [offM[B], d], alpha [offN[B]], beta [offM[B]] (device, float32).
+ *  eps, rho1, rho2 (device, double) [B]: per-problem parameters (> 0, finite).
+ *  max_iter, tol, check_every: as in uot_params, applied to every problem; a problem stops
+ *  at its own first passing check (or at max_iter) while the others continue.
+ *  f [offN[B]], g [offM[B]] (device, out): the translated potentials of each problem.
+ *  iters, status (device, int32 [B], out): iterations run and UOT_BATCH_* outcome.
+ * All problems advance together one half-step per kernel launch; a wave takes one chunk of
+ * up to 64 targets of one problem at a time from a shared counter over the problems still
+ * running, so the work follows the active problems as they converge. A chunk of iterations
+ * is captured once as a HIP graph and replayed until every problem has stopped.
+ * Returns UOT_OK when every problem has an outcome (check the status array); bad host
+ * arguments give UOT_ERR_INVALID before any launch.
+ */
+uot_status uot_ti_sinkhorn_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
+                                   double p, const float *x, const float *y, const float *alpha,
+                                   const float *beta, const double *eps, const double *rho1,
+                                   const double *rho2, int32_t max_iter, double tol,
+                                   int32_t check_every, float *f, float *g, int32_t *iters,
+                                   int32_t *status, void *workspace, size_t workspace_bytes,
+                                   void *stream);
+
+/* Workspace bytes of uot_ti_sinkhorn_batched (offN, offM on the host); 0 on invalid input. */
+size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d);
+
 /*
  * Kernel timing, for benchmarks (off by default). While enabled, every softmin launch of
  * uot_sinkhorn / uot_ti_sinkhorn is bracketed by two HIP events recorded on the call's

@@ -20,7 +20,8 @@ import torch
 
 __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_apply", "marginals",
            "backward", "workspace_bytes", "UOTLoss", "uot_loss", "library_path", "load_library",
-           "profile_enable", "profile_reset", "profile_read", "set_points_kernel"]
+           "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
+           "ti_sinkhorn_batched"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -100,6 +101,11 @@ def load_library():
     lib.uot_profile_read.restype = I64
     lib.uot_set_points_kernel.argtypes = [I32]
     lib.uot_set_points_kernel.restype = I32
+    lib.uot_ti_sinkhorn_batched.argtypes = [I32, P, P, I32, D, P, P, P, P, P, P, P, I32, D, I32,
+                                            P, P, P, P, P, S, P]
+    lib.uot_ti_sinkhorn_batched.restype = ctypes.c_int
+    lib.uot_batched_workspace_bytes.argtypes = [I32, P, P, I32]
+    lib.uot_batched_workspace_bytes.restype = S
     _lib = lib
     return lib
 
@@ -328,6 +334,57 @@ def backward(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: 
                             float(rho2), _ptr(f), _ptr(g), float(grad_out), _ptr(dx), _ptr(dy), _ptr(da),
                             _ptr(db), _ptr(ws), ws.numel(), _stream()))
     return dx, dy, da, db
+
+
+BATCH_CONVERGED, BATCH_MAX_ITER, BATCH_INVALID, BATCH_NUMERIC = 0, 1, 2, 3
+
+
+def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, p: float = 2.0,
+                        max_iter: int = 10000, tol: float = 1e-6, check_every: int = 10,
+                        workspace=None):
+    """Batched translation-invariant Sinkhorn over packed problems.
+
+    offN, offM: host int64 sequences [B+1] (CSR offsets of the x and y sides); x [sum N, d],
+    y [sum M, d], alpha, beta: float32 device tensors; eps, rho1, rho2: float64 device
+    tensors [B] (or host sequences). Returns (f, g, iters, status) as device tensors."""
+    _require_gpu()
+    lib = load_library()
+    import numpy as np
+    offN = np.ascontiguousarray(np.asarray(offN, dtype=np.int64))
+    offM = np.ascontiguousarray(np.asarray(offM, dtype=np.int64))
+    B = len(offN) - 1
+    if len(offM) != B + 1:
+        raise ValueError("offN and offM lengths differ")
+    x, y = _f32(x, "x"), _f32(y, "y")
+    if x.dim() == 1:
+        x = x[:, None].contiguous()
+    if y.dim() == 1:
+        y = y[:, None].contiguous()
+    alpha, beta = _f32(alpha, "alpha"), _f32(beta, "beta")
+    dev = x.device
+
+    def _d64(v):
+        if isinstance(v, torch.Tensor):
+            return v.to(device=dev, dtype=torch.float64).contiguous()
+        return torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev)
+
+    eps_t, r1_t = _d64(eps), _d64(rho1)
+    r2_t = r1_t if rho2 is None else _d64(rho2)
+    f = torch.empty(int(offN[-1]), dtype=torch.float32, device=dev)
+    g = torch.empty(int(offM[-1]), dtype=torch.float32, device=dev)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    pN, pM = offN.ctypes.data_as(ctypes.c_void_p), offM.ctypes.data_as(ctypes.c_void_p)
+    if workspace is None:
+        nb = int(lib.uot_batched_workspace_bytes(B, pN, pM, x.shape[1]))
+        if nb == 0:
+            _check(UOT_ERR_INVALID)
+        workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib.uot_ti_sinkhorn_batched(B, pN, pM, x.shape[1], float(p), _ptr(x), _ptr(y), _ptr(alpha),
+                                       _ptr(beta), _ptr(eps_t), _ptr(r1_t), _ptr(r2_t), int(max_iter),
+                                       float(tol), int(check_every), _ptr(f), _ptr(g), _ptr(iters),
+                                       _ptr(status), _ptr(workspace), workspace.numel(), _stream()))
+    return f, g, iters, status
 
 
 class UOTLoss(torch.autograd.Function):

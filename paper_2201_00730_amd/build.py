@@ -21,6 +21,7 @@ SOURCES = [
     "kernels_dense.hip",
     "kernels_epilogue.hip",
     "kernels_apply.hip",
+    "kernels_batched.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,484 @@
+// Batched translation-invariant Sinkhorn for many independent KL-UOT problems with point
+// costs (gfx950).
+//
+// Problems are packed back to back (CSR offsets offN/offM). One half-step of every active
+// problem is one launch of k_batched_half: each wave repeatedly takes a work item (problem
+// p, a chunk of <= 64 targets of p) from a dynamic counter over the compacted list of active
+// items, computes the softmin of its targets over all sources of p (one target per lane;
+// sources uniform across the wave, read with scalar loads, 8 at a time with one exp2 per
+// entry), applies the KL prox and TI translation of App. B, writes the new potentials and
+// source records, and leaves its item partials (tilted mass log-sum-exp, potential-change
+// range). The last wave to finish an item of p (an atomic ticket, no waiting) reduces p's
+// partials into p's scalars: the translation tau, Smin of the new side, and after an f-step
+// lambda* (Prop. 2), the change of the reported potentials and the convergence flag.
+// k_batched_compact rebuilds the active item lists between chunks of iterations.
+//
+// Same base-2 conventions as the single-problem kernels: sc_p = log2(e)/eps_p and records
+//   kSqEuc: u_s = 2 sc_p (x_s - mu_p), b_s = sc_p h_s + log2 w_s - sc_p |x_s - mu_p|^2
+//   kPower: u_s = x_s - mu_p,          b_s = sc_p h_s + log2 w_s
+// where mu_p is the common mean of problem p's two clouds.
+#include <cfloat>
+
+#include "uot_batched.h"
+
+namespace uot {
+namespace {
+
+constexpr int kTile = 8;
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// Wave-wide reductions (all 64 lanes participate).
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ void wave_lse(double &m, double &s) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double mo = __shfl_xor(m, o, 64), so = __shfl_xor(s, o, 64);
+    const double mn = fmax(m, mo);
+    if (mn == -INFINITY) {
+      s = 0.0;
+    } else {
+      s = s * exp(m - mn) + so * exp(mo - mn);
+    }
+    m = mn;
+  }
+}
+
+// TI coefficients of a half-step whose targets have penalty rho_t and sources rho_s.
+struct HalfCoef {
+  double k_t, c_t, kappa_t;
+};
+__device__ __forceinline__ HalfCoef half_coef(double eps, double rho_t, double rho_s) {
+  HalfCoef c;
+  c.k_t = rho_t / (eps + rho_t);
+  c.c_t = eps * rho_t / ((eps + rho_t) * (rho_s + rho_t));
+  c.kappa_t = eps * rho_s / ((eps + rho_t) * (rho_s + rho_t));
+  return c;
+}
+
+template <int D, int MODE>
+__device__ __forceinline__ void write_rec(float *rp, const float *yc, double yn2, float hf, float w,
+                                          double sc) {
+  const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
+  if constexpr (MODE == kSqEuc) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
+    rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
+  } else {
+#pragma unroll
+    for (int k = 0; k < D; ++k) rp[k] = yc[k];
+    rp[D] = (float)(sc * (double)hf + lw2);
+  }
+#pragma unroll
+  for (int k = D + 1; k < batched_rec_stride(D); ++k) rp[k] = 0.0f;
+}
+
+// Reduces problem p's item partials of the half-step just finished (one wave).
+__device__ void reduce_problem(const BatchedArgs &a, int p, bool g_step) {
+  BatchState &st = a.state[p];
+  const int i0 = g_step ? a.pitem_g[p] : a.pitem_f[p];
+  const int i1 = g_step ? a.pitem_g[p + 1] : a.pitem_f[p + 1];
+  const BlockPart *parts = g_step ? a.part_g : a.part_f;
+  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+  const int lane = threadIdx.x & 63;
+  for (int i = i0 + lane; i < i1; i += 64) {
+    const BlockPart q = parts[i];
+    const double mn = fmax(mm, q.mass_max);
+    if (mn != -INFINITY) ms = ms * exp(mm - mn) + q.mass_sum * exp(q.mass_max - mn);
+    mm = mn;
+    dmx = fmax(dmx, q.dmax);
+    dmn = fmin(dmn, q.dmin);
+  }
+  wave_lse(mm, ms);
+  dmx = wave_max(dmx);
+  dmn = wave_min(dmn);
+  if (lane != 0) return;
+  const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
+  const double L = (mm == -INFINITY) ? -INFINITY : mm + log(ms);
+  if (g_step) {
+    const HalfCoef c = half_coef(eps, r2, r1);
+    const double sBhat = -r2 * L;
+    const double tg = c.kappa_t / (1.0 - c.kappa_t) * sBhat;
+    st.tau_g = tg;
+    st.sB = sBhat + tg;
+    st.gdiff_max = dmx;
+    st.gdiff_min = dmn;
+  } else {
+    const HalfCoef c = half_coef(eps, r1, r2);
+    const double sAhat = -r1 * L;
+    const double tf = c.kappa_t / (1.0 - c.kappa_t) * sAhat;
+    st.tau_f = tf;
+    st.sA = sAhat + tf;
+    const double tau1 = r1 / (r1 + r2), tau2 = r2 / (r1 + r2);
+    const double lam = tau1 * st.sB - tau2 * st.sA;
+    st.lambda = lam;
+    const double off_f = tf + lam, off_g = st.tau_g - lam;
+    const int it = st.iter + 1;
+    st.iter = it;
+    double delta = INFINITY;
+    if (it > 1) {
+      const double cf = off_f - st.off_f_prev, cg = off_g - st.off_g_prev;
+      delta = fmax(fmax(dmx + cf, -(dmn + cf)), fmax(st.gdiff_max + cg, -(st.gdiff_min + cg)));
+    }
+    st.delta = delta;
+    st.off_f_prev = off_f;
+    st.off_g_prev = off_g;
+    if (!isfinite(off_f) || !isfinite(off_g) || isnan(delta)) st.status = kBatchNumeric;
+    if (st.status != kBatchRunning) {
+      st.done = 1;
+    } else if (a.tol > 0.0 && it % a.check_every == 0 && delta < a.tol) {
+      st.status = kBatchConverged;
+      st.done = 1;
+    } else if (it >= a.max_iter) {
+      st.status = kBatchMaxIter;
+      st.done = 1;
+    }
+  }
+}
+
+// One half-step for every active problem. g_step: targets y (beta, rho2), sources x.
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step) {
+  const int lane = threadIdx.x & 63;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int nact = g_step ? *a.nact_g : *a.nact_f;
+  const int *act = g_step ? a.act_g : a.act_f;
+  const int4 *items = g_step ? a.items_g : a.items_f;
+  int *ctr = g_step ? a.ctr_g : a.ctr_f;
+  const int64_t *off_t = g_step ? a.offM : a.offN;
+  const int64_t *off_s = g_step ? a.offN : a.offM;
+  const float *tpts = g_step ? a.y : a.x;
+  const float *tw = g_step ? a.beta : a.alpha;
+  float *tpot = g_step ? a.pot_y : a.pot_x;
+  float *trec = g_step ? a.rec_y : a.rec_x;
+  const float *srec = g_step ? a.rec_x : a.rec_y;
+  BlockPart *parts = g_step ? a.part_g : a.part_f;
+  int *ticket = g_step ? a.ticket_g : a.ticket_f;
+  const int *pitem = g_step ? a.pitem_g : a.pitem_f;
+  constexpr int SD = batched_rec_stride(D);
+  (void)wid;
+  (void)nwaves;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the other side's counter is idle during this launch: reset it for the next one
+    if (g_step) *a.ctr_f = 0; else *a.ctr_g = 0;
+  }
+
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(ctr, 1);
+    item = __shfl(item, 0, 64);
+    if (item >= nact) break;
+    const int4 it = items[act[item]];  // (problem, first target, count, slot)
+    const int p = it.x;
+    BatchState &st = a.state[p];
+    if (st.done) continue;  // finished by an earlier half-step (compaction is periodic)
+    const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
+    const double scd = 1.4426950408889634074 / eps;
+    const float sc = (float)scd;
+    const HalfCoef cf = g_step ? half_coef(eps, r2, r1) : half_coef(eps, r1, r2);
+    const double tau_src = g_step ? st.tau_f : st.tau_g;
+    const double s_src = g_step ? st.sA : st.sB;
+    const double rho_t = g_step ? r2 : r1;
+    const int64_t tb = off_t[p];
+    const int t = it.y + lane;  // target index within problem p
+    const bool valid = lane < it.z;
+    const int64_t tg = tb + (valid ? t : it.y);
+    const double *mu = a.mu + (size_t)p * kBatchMaxDim;
+    float yc[D];
+    double yn2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      yc[k] = k < a.d ? tpts[tg * a.d + k] - (float)mu[k] : 0.0f;
+      yn2 += (double)yc[k] * (double)yc[k];
+    }
+    // softmin over all sources of p
+    const int64_t s0 = off_s[p], s1 = off_s[p + 1];
+    float m = -FLT_MAX, l = 0.0f;
+    auto expo = [&](const float *rp) -> float {
+      if constexpr (MODE == kSqEuc) {
+        float acc = rp[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc = fmaf(rp[k], yc[k], acc);
+        return acc;
+      } else {
+        float d2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const float u = rp[k] - yc[k];
+          d2 = fmaf(u, u, d2);
+        }
+        const float c = (a.half_p == 0.5f) ? __builtin_sqrtf(d2) : fast_exp2(a.half_p * fast_log2(d2));
+        return fmaf(-sc, c, rp[D]);
+      }
+    };
+    int64_t s = s0;
+    for (; s + kTile <= s1; s += kTile) {
+      float v[kTile];
+#pragma unroll
+      for (int k = 0; k < kTile; ++k) v[k] = expo(srec + (size_t)(s + k) * SD);
+      float mt = v[0];
+#pragma unroll
+      for (int k = 1; k < kTile; ++k) mt = fmaxf(mt, v[k]);
+      const float mn = fmaxf(m, mt);
+      float acc = l * fast_exp2(m - mn);
+#pragma unroll
+      for (int k = 0; k < kTile; ++k) acc += fast_exp2(v[k] - mn);
+      l = acc;
+      m = mn;
+    }
+    for (; s < s1; ++s) {
+      const float v = expo(srec + (size_t)s * SD);
+      const float mn = fmaxf(m, v);
+      l = l * fast_exp2(m - mn) + fast_exp2(v - mn);
+      m = mn;
+    }
+    // epilogue: KL prox and TI translation (App. B), records of the new potential
+    double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+    if (valid) {
+      double lse2 = (double)m + log2((double)l);
+      if constexpr (MODE == kSqEuc) lse2 -= scd * yn2;
+      const double S = -lse2 / scd;
+      const double hnew = cf.k_t * (S - tau_src) - cf.c_t * s_src;
+      const float hf = (float)hnew;
+      const float old = tpot[tg];
+      tpot[tg] = hf;
+      dmx = dmn = (double)hf - (double)old;
+      const float w = tw[tg];
+      write_rec<D, MODE>(trec + (size_t)tg * SD, yc, yn2, hf, w, scd);
+      if (w > 0.0f) { mm = log((double)w) - (double)hf / rho_t; ms = 1.0; }
+      if (!isfinite(hnew)) st.status = kBatchNumeric;
+    }
+    wave_lse(mm, ms);
+    dmx = wave_max(dmx);
+    dmn = wave_min(dmn);
+    int last = 0;
+    if (lane == 0) {
+      parts[it.w] = BlockPart{mm, ms, dmx, dmn};
+      __threadfence();
+      const int nitems = pitem[p + 1] - pitem[p];
+      last = (atomicAdd(&ticket[p], 1) == nitems - 1) ? 1 : 0;
+    }
+    last = __shfl(last, 0, 64);
+    if (last) {
+      __threadfence();
+      reduce_problem(a, p, g_step != 0);
+      if (lane == 0) ticket[p] = 0;
+    }
+  }
+}
+
+// Rebuilds the active item lists (items of problems not done), resets the work counters,
+// and counts the problems still running. One block.
+__global__ __launch_bounds__(1024) void k_batched_compact(BatchedArgs a) {
+  __shared__ int s_ng, s_nf, s_run;
+  if (threadIdx.x == 0) { s_ng = 0; s_nf = 0; s_run = 0; }
+  __syncthreads();
+  for (int p = threadIdx.x; p < a.B; p += blockDim.x)
+    if (!a.state[p].done) atomicAdd(&s_run, 1);
+  for (int i = threadIdx.x; i < a.n_items_g; i += blockDim.x)
+    if (!a.state[a.items_g[i].x].done) a.act_g[atomicAdd(&s_ng, 1)] = i;
+  for (int i = threadIdx.x; i < a.n_items_f; i += blockDim.x)
+    if (!a.state[a.items_f[i].x].done) a.act_f[atomicAdd(&s_nf, 1)] = i;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *a.nact_g = s_ng;
+    *a.nact_f = s_nf;
+    *a.running = s_run;
+    *a.ctr_g = 0;
+    *a.ctr_f = 0;
+  }
+}
+
+// Per problem (one block each): common mean of its clouds, weight checks, zero potentials,
+// records of both sides from zero potentials, and the initial scalars (Smin_alpha^rho1(0)).
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
+  const int p = blockIdx.x;
+  __shared__ double sh[256];
+  __shared__ int s_bad, s_pa, s_pb;
+  const int64_t n0 = a.offN[p], n1 = a.offN[p + 1], m0 = a.offM[p], m1 = a.offM[p + 1];
+  if (threadIdx.x == 0) { s_bad = 0; s_pa = 0; s_pb = 0; }
+  __syncthreads();
+  double *mu = a.mu + (size_t)p * kBatchMaxDim;
+  for (int k = 0; k < kBatchMaxDim; ++k) {
+    double s = 0.0;
+    if (k < a.d) {
+      for (int64_t i = n0 + threadIdx.x; i < n1; i += 256) s += (double)a.x[i * a.d + k];
+      for (int64_t j = m0 + threadIdx.x; j < m1; j += 256) s += (double)a.y[j * a.d + k];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) mu[k] = (k < a.d) ? sh[0] / (double)((n1 - n0) + (m1 - m0)) : 0.0;
+    __syncthreads();
+  }
+  const double eps = a.eps[p], r1 = a.rho1[p];
+  const double scd = 1.4426950408889634074 / eps;
+  constexpr int SD = batched_rec_stride(D);
+  // x side (alpha) and y side (beta): zero potentials and records; tilted mass of alpha
+  double mm = -INFINITY, ms = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t b0 = side == 0 ? n0 : m0, b1 = side == 0 ? n1 : m1;
+    const float *pts = side == 0 ? a.x : a.y;
+    const float *w = side == 0 ? a.alpha : a.beta;
+    float *pot = side == 0 ? a.pot_x : a.pot_y;
+    float *rec = side == 0 ? a.rec_x : a.rec_y;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+      const float wi = w[i];
+      if (!(wi >= 0.0f) || isinf(wi)) s_bad = 1;
+      if (wi > 0.0f) { if (side == 0) s_pa = 1; else s_pb = 1; }
+      float yc[D];
+      double yn2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        yc[k] = k < a.d ? pts[i * a.d + k] - (float)mu[k] : 0.0f;
+        yn2 += (double)yc[k] * (double)yc[k];
+      }
+      pot[i] = 0.0f;
+      write_rec<D, MODE>(rec + (size_t)i * SD, yc, yn2, 0.0f, wi, scd);
+      if (side == 0 && wi > 0.0f) {
+        const double v = log((double)wi);
+        const double mn = fmax(mm, v);
+        ms = ms * exp(mm - mn) + exp(v - mn);
+        mm = mn;
+      }
+    }
+  }
+  // block log-sum-exp of the alpha terms
+  __shared__ double sm[256], ss[256];
+  sm[threadIdx.x] = mm;
+  ss[threadIdx.x] = ms;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double m_a = sm[threadIdx.x], m_b = sm[threadIdx.x + o];
+      const double mn = fmax(m_a, m_b);
+      if (mn != -INFINITY)
+        ss[threadIdx.x] = ss[threadIdx.x] * exp(m_a - mn) + ss[threadIdx.x + o] * exp(m_b - mn);
+      sm[threadIdx.x] = mn;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    BatchState &st = a.state[p];
+    const double L = sm[0] == -INFINITY ? -INFINITY : sm[0] + log(ss[0]);
+    st.sA = -r1 * L;
+    st.sB = 0.0;
+    st.tau_f = st.tau_g = st.lambda = 0.0;
+    st.off_f_prev = st.off_g_prev = 0.0;
+    st.gdiff_max = st.gdiff_min = 0.0;
+    st.delta = INFINITY;
+    st.iter = 0;
+    const double e = a.eps[p], q1 = a.rho1[p], q2 = a.rho2[p];
+    const bool bad_par = !(e > 0.0) || !isfinite(e) || !(q1 > 0.0) || !isfinite(q1) ||
+                         !(q2 > 0.0) || !isfinite(q2);
+    const bool bad = s_bad || !s_pa || !s_pb || bad_par;
+    st.status = bad ? kBatchInvalid : kBatchRunning;
+    st.done = bad ? 1 : 0;
+    a.ticket_g[p] = 0;
+    a.ticket_f[p] = 0;
+  }
+}
+
+// Reported potentials f = fhat + tau_f + lambda, g = ghat + tau_g - lambda, per problem;
+// iteration counts and statuses.
+__global__ __launch_bounds__(256) void k_batched_finalize(BatchedArgs a, float *f, float *g,
+                                                           int32_t *iters, int32_t *status) {
+  const int64_t totN = a.offN[a.B], totM = a.offM[a.B];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < totN + totM; i += stride) {
+    const bool xs = i < totN;
+    const int64_t j = xs ? i : i - totN;
+    const int64_t *off = xs ? a.offN : a.offM;
+    int lo = 0, hi = a.B - 1;  // problem p with off[p] <= j < off[p + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    const BatchState &st = a.state[lo];
+    if (xs) f[j] = (float)((double)a.pot_x[j] + st.tau_f + st.lambda);
+    else g[j] = (float)((double)a.pot_y[j] + st.tau_g - st.lambda);
+  }
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.B; p += stride) {
+    iters[p] = a.state[p].iter;
+    status[p] = a.state[p].status;
+  }
+}
+
+template <int D, int MODE>
+hipError_t launch_half_t(const BatchedArgs &a, int g_step, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_batched_half<D, MODE>), dim3(blocks), dim3(256), 0, s, a, g_step);
+  return hipGetLastError();
+}
+
+template <int D, int MODE>
+hipError_t launch_init_t(const BatchedArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_batched_init<D, MODE>), dim3(a.B), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int D, int MODE>
+int half_occupancy_t() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, MODE>, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+#define UOT_BATCH_DISPATCH(FN, ...)                                                  \
+  do {                                                                               \
+    const bool sq = a.mode == kSqEuc;                                                \
+    switch (a.d) {                                                                   \
+      case 1: return sq ? FN<1, kSqEuc>(__VA_ARGS__) : FN<1, kPower>(__VA_ARGS__);   \
+      case 2: return sq ? FN<2, kSqEuc>(__VA_ARGS__) : FN<2, kPower>(__VA_ARGS__);   \
+      case 3: return sq ? FN<3, kSqEuc>(__VA_ARGS__) : FN<3, kPower>(__VA_ARGS__);   \
+      case 4: return sq ? FN<4, kSqEuc>(__VA_ARGS__) : FN<4, kPower>(__VA_ARGS__);   \
+      case 5: return sq ? FN<5, kSqEuc>(__VA_ARGS__) : FN<5, kPower>(__VA_ARGS__);   \
+      case 6: return sq ? FN<6, kSqEuc>(__VA_ARGS__) : FN<6, kPower>(__VA_ARGS__);   \
+      case 7: return sq ? FN<7, kSqEuc>(__VA_ARGS__) : FN<7, kPower>(__VA_ARGS__);   \
+      case 8: return sq ? FN<8, kSqEuc>(__VA_ARGS__) : FN<8, kPower>(__VA_ARGS__);   \
+    }                                                                                \
+  } while (0)
+
+}  // namespace
+
+hipError_t launch_batched_half(const BatchedArgs &a, int g_step, int blocks, hipStream_t s) {
+  UOT_BATCH_DISPATCH(launch_half_t, a, g_step, blocks, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_init(const BatchedArgs &a, hipStream_t s) {
+  UOT_BATCH_DISPATCH(launch_init_t, a, s);
+  return hipErrorInvalidValue;
+}
+
+int batched_half_blocks_per_cu(const BatchedArgs &a) {
+  UOT_BATCH_DISPATCH(half_occupancy_t);
+  return 0;
+}
+
+hipError_t launch_batched_compact(const BatchedArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_batched_compact, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_finalize(const BatchedArgs &a, float *f, float *g, int32_t *iters,
+                                   int32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_batched_finalize, dim3(1024), dim3(256), 0, s, a, f, g, iters, status);
+  return hipGetLastError();
+}
+
+}  // namespace uot

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/uot.h"
+#include "uot_batched.h"
 #include "uot_internal.h"
 
 namespace uot {
@@ -793,6 +794,229 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
   return UOT_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Batched TI Sinkhorn
+// ---------------------------------------------------------------------------------------
+constexpr int kBatchItemTargets = 64;  // targets per work item (one wave, one per lane)
+
+struct BatchLayout {
+  size_t state = 0, mu = 0, offN = 0, offM = 0, items_g = 0, items_f = 0, pitem_g = 0, pitem_f = 0;
+  size_t act_g = 0, act_f = 0, ctrs = 0, part_g = 0, part_f = 0, tick_g = 0, tick_f = 0;
+  size_t pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, total = 0;
+  int n_items_g = 0, n_items_f = 0;
+  int64_t totN = 0, totM = 0;
+};
+
+uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
+                          BatchLayout &L) {
+  if (B < 1) return fail(UOT_ERR_INVALID, "B=%d must be >= 1", B);
+  if (offN == nullptr || offM == nullptr) return fail(UOT_ERR_INVALID, "offN/offM are NULL");
+  if (d < 1 || d > kBatchMaxDim) return fail(UOT_ERR_INVALID, "batched d=%d not in [1, %d]", d, kBatchMaxDim);
+  if (offN[0] != 0 || offM[0] != 0) return fail(UOT_ERR_INVALID, "offN[0] and offM[0] must be 0");
+  int64_t ig = 0, jf = 0;
+  for (int p = 0; p < B; ++p) {
+    const int64_t n = offN[p + 1] - offN[p], m = offM[p + 1] - offM[p];
+    if (n < 1 || m < 1) return fail(UOT_ERR_INVALID, "problem %d has n=%lld, m=%lld (must be >= 1)", p, (long long)n, (long long)m);
+    if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_ERR_INVALID, "problem %d is too large", p);
+    ig += (m + kBatchItemTargets - 1) / kBatchItemTargets;
+    jf += (n + kBatchItemTargets - 1) / kBatchItemTargets;
+  }
+  if (ig > (1 << 30) || jf > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
+  L.n_items_g = (int)ig;
+  L.n_items_f = (int)jf;
+  L.totN = offN[B];
+  L.totM = offM[B];
+  const int stride = batched_rec_stride(d);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.state = take((size_t)B * sizeof(BatchState));
+  L.mu = take((size_t)B * kBatchMaxDim * sizeof(double));
+  L.offN = take((size_t)(B + 1) * sizeof(int64_t));
+  L.offM = take((size_t)(B + 1) * sizeof(int64_t));
+  L.items_g = take((size_t)L.n_items_g * sizeof(int4));
+  L.items_f = take((size_t)L.n_items_f * sizeof(int4));
+  L.pitem_g = take((size_t)(B + 1) * sizeof(int));
+  L.pitem_f = take((size_t)(B + 1) * sizeof(int));
+  L.act_g = take((size_t)L.n_items_g * sizeof(int));
+  L.act_f = take((size_t)L.n_items_f * sizeof(int));
+  L.ctrs = take(8 * sizeof(int));
+  L.part_g = take((size_t)L.n_items_g * sizeof(BlockPart));
+  L.part_f = take((size_t)L.n_items_f * sizeof(BlockPart));
+  L.tick_g = take((size_t)B * sizeof(int));
+  L.tick_f = take((size_t)B * sizeof(int));
+  L.pot_x = take((size_t)L.totN * sizeof(float));
+  L.pot_y = take((size_t)L.totM * sizeof(float));
+  L.rec_x = take((size_t)L.totN * stride * sizeof(float));
+  L.rec_y = take((size_t)L.totM * stride * sizeof(float));
+  L.total = off;
+  return UOT_OK;
+}
+
+// Work items of one side: (problem, first target, count, item index), grouped by problem.
+void build_items(int32_t B, const int64_t *off, std::vector<int4> &items, std::vector<int> &pitem) {
+  items.clear();
+  pitem.assign((size_t)B + 1, 0);
+  for (int p = 0; p < B; ++p) {
+    pitem[p] = (int)items.size();
+    const int64_t n = off[p + 1] - off[p];
+    for (int64_t t0 = 0; t0 < n; t0 += kBatchItemTargets) {
+      const int cnt = (int)((n - t0) < kBatchItemTargets ? (n - t0) : kBatchItemTargets);
+      items.push_back(make_int4(p, (int)t0, cnt, (int)items.size()));
+    }
+  }
+  pitem[B] = (int)items.size();
+}
+
+struct GraphGuard {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  hipStream_t cs = nullptr;
+  ~GraphGuard() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d, double p,
+                      const float *x, const float *y, const float *alpha, const float *beta,
+                      const double *eps, const double *rho1, const double *rho2, int32_t max_iter,
+                      double tol, int32_t check_every, float *f, float *g, int32_t *iters,
+                      int32_t *status, void *workspace, size_t workspace_bytes, void *stream) {
+  BatchLayout L;
+  UOT_TRY(batched_layout(B, offN, offM, d, L));
+  if (!std::isfinite(p) || p < 1.0) return fail(UOT_ERR_INVALID, "exponent p=%g must be finite and >= 1", p);
+  if (max_iter < 1) return fail(UOT_ERR_INVALID, "max_iter=%d must be >= 1", max_iter);
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(UOT_ERR_INVALID, "tol=%g must be finite and >= 0", tol);
+  if (check_every < 1) return fail(UOT_ERR_INVALID, "check_every=%d must be >= 1", check_every);
+  const void *ptrs[] = {x, y, alpha, beta, eps, rho1, rho2, f, g, iters, status};
+  const char *names[] = {"x", "y", "alpha", "beta", "eps", "rho1", "rho2", "f", "g", "iters", "status"};
+  for (int i = 0; i < 11; ++i) UOT_TRY(check_device_ptr(ptrs[i], names[i]));
+  Workspace w;
+  UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  std::vector<int4> items_g, items_f;
+  std::vector<int> pitem_g, pitem_f;
+  build_items(B, offM, items_g, pitem_g);  // g-step targets: the y side
+  build_items(B, offN, items_f, pitem_f);  // f-step targets: the x side
+  char *ws = static_cast<char *>(w.ptr);
+  UOT_HIP(hipMemcpyAsync(ws + L.offN, offN, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.offM, offM, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.items_g, items_g.data(), items_g.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.items_f, items_f.data(), items_f.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.pitem_g, pitem_g.data(), pitem_g.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.pitem_f, pitem_f.data(), pitem_f.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipStreamSynchronize(s));  // the host tables must outlive the copies
+
+  BatchedArgs a;
+  a.B = B;
+  a.d = d;
+  a.mode = p == 2.0 ? kSqEuc : kPower;
+  a.half_p = (float)(0.5 * p);
+  a.offN = at<int64_t>(w.ptr, L.offN);
+  a.offM = at<int64_t>(w.ptr, L.offM);
+  a.x = x;
+  a.y = y;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.eps = eps;
+  a.rho1 = rho1;
+  a.rho2 = rho2;
+  a.max_iter = max_iter;
+  a.tol = tol;
+  a.check_every = check_every;
+  a.state = at<BatchState>(w.ptr, L.state);
+  a.mu = at<double>(w.ptr, L.mu);
+  a.pot_x = at<float>(w.ptr, L.pot_x);
+  a.pot_y = at<float>(w.ptr, L.pot_y);
+  a.rec_x = at<float>(w.ptr, L.rec_x);
+  a.rec_y = at<float>(w.ptr, L.rec_y);
+  a.items_g = at<int4>(w.ptr, L.items_g);
+  a.items_f = at<int4>(w.ptr, L.items_f);
+  a.pitem_g = at<int>(w.ptr, L.pitem_g);
+  a.pitem_f = at<int>(w.ptr, L.pitem_f);
+  a.n_items_g = L.n_items_g;
+  a.n_items_f = L.n_items_f;
+  a.act_g = at<int>(w.ptr, L.act_g);
+  a.act_f = at<int>(w.ptr, L.act_f);
+  int *ctrs = at<int>(w.ptr, L.ctrs);
+  a.nact_g = ctrs + 0;
+  a.nact_f = ctrs + 1;
+  a.ctr_g = ctrs + 2;
+  a.ctr_f = ctrs + 3;
+  a.running = ctrs + 4;
+  a.part_g = at<BlockPart>(w.ptr, L.part_g);
+  a.part_f = at<BlockPart>(w.ptr, L.part_f);
+  a.ticket_g = at<int>(w.ptr, L.tick_g);
+  a.ticket_f = at<int>(w.ptr, L.tick_f);
+
+  UOT_HIP(launch_batched_init(a, s));
+  UOT_HIP(launch_batched_compact(a, s));
+  const int cus = device_cus();
+  const int per_cu = batched_half_blocks_per_cu(a);
+  const int blocks = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 4);
+
+  // One chunk of iterations (g and f half-steps) and the compaction, captured once.
+  const int chunk = tol > 0.0 ? check_every : (max_iter < 64 ? max_iter : 64);
+  GraphGuard gg;
+  UOT_HIP(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+  UOT_HIP(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeRelaxed));
+  for (int i = 0; i < chunk; ++i) {
+    hipError_t e = launch_batched_half(a, 1, blocks, gg.cs);
+    if (e == hipSuccess) e = launch_batched_half(a, 0, blocks, gg.cs);
+    if (e != hipSuccess) {
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(gg.cs, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      return fail(UOT_ERR_HIP, "batched launch during capture: %s", hipGetErrorString(e));
+    }
+  }
+  {
+    hipError_t e = launch_batched_compact(a, gg.cs);
+    hipError_t e2 = hipStreamEndCapture(gg.cs, &gg.g);
+    if (e != hipSuccess || e2 != hipSuccess)
+      return fail(UOT_ERR_HIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  UOT_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+
+  PinnedState pin;  // reused as two int slots for the running counts
+  UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
+  int *run_h = reinterpret_cast<int *>(pin.h);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  UOT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  UOT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evg{ev};
+  // problems still running right after initialisation
+  UOT_HIP(hipMemcpyAsync(run_h, a.running, sizeof(int), hipMemcpyDeviceToHost, s));
+  UOT_HIP(hipStreamSynchronize(s));
+  const int max_chunks = (max_iter + chunk - 1) / chunk;
+  int launched = 0;
+  if (run_h[0] > 0) {
+    for (int c = 0; c < max_chunks; ++c) {
+      UOT_HIP(hipGraphLaunch(gg.e, s));
+      ++launched;
+      UOT_HIP(hipMemcpyAsync(run_h + 16 * (c & 1), a.running, sizeof(int), hipMemcpyDeviceToHost, s));
+      UOT_HIP(hipEventRecord(ev[c & 1], s));
+      if (c >= 1) {
+        UOT_HIP(hipEventSynchronize(ev[(c - 1) & 1]));
+        if (run_h[16 * ((c - 1) & 1)] == 0) break;
+      }
+    }
+  }
+  UOT_HIP(launch_batched_finalize(a, f, g, iters, status, s));
+  UOT_HIP(hipStreamSynchronize(s));
+  (void)launched;
+  return UOT_OK;
+}
+
 }  // namespace
 }  // namespace uot
 
@@ -867,6 +1091,24 @@ int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries) 
   if (total_ms) *total_ms = uot::g_prof[kind].ms;
   if (total_entries) *total_entries = uot::g_prof[kind].entries;
   return uot::g_prof[kind].launches;
+}
+
+size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d) {
+  uot::BatchLayout L;
+  if (uot::batched_layout(B, offN, offM, d, L) != UOT_OK) return 0;
+  return L.total;
+}
+
+uot_status uot_ti_sinkhorn_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
+                                   double p, const float *x, const float *y, const float *alpha,
+                                   const float *beta, const double *eps, const double *rho1,
+                                   const double *rho2, int32_t max_iter, double tol,
+                                   int32_t check_every, float *f, float *g, int32_t *iters,
+                                   int32_t *status, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+  uot::g_last_error.clear();
+  return uot::ti_batched(B, offN, offM, d, p, x, y, alpha, beta, eps, rho1, rho2, max_iter, tol,
+                         check_every, f, g, iters, status, workspace, workspace_bytes, stream);
 }
 
 const char *uot_status_string(uot_status s) {

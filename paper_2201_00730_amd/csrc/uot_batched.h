@@ -1,0 +1,64 @@
+// Internal definitions of the batched solver (kernels_batched.hip, batched_api.hip).
+#pragma once
+
+#include "uot_internal.h"
+
+namespace uot {
+
+constexpr int kBatchMaxDim = 8;  // point dimension limit of the batched solver
+
+// Per-problem status (the public codes are the non-negative ones, see uot.h).
+enum : int32_t {
+  kBatchRunning = -1,
+  kBatchConverged = 0,
+  kBatchMaxIter = 1,
+  kBatchInvalid = 2,
+  kBatchNumeric = 3,
+};
+
+// Record stride of the batched kernels (D coordinates, b, padding to a multiple of 4).
+__host__ __device__ constexpr int batched_rec_stride(int D) { return (D + 1 + 3) / 4 * 4; }
+
+// Scalar state of one problem (same meaning as SolveState).
+struct BatchState {
+  double sA, sB, tau_f, tau_g, lambda;
+  double off_f_prev, off_g_prev, gdiff_max, gdiff_min, delta;
+  int32_t iter;
+  int32_t done;
+  int32_t status;
+  int32_t pad_;
+};
+
+struct BatchedArgs {
+  int B;
+  int d, mode;
+  float half_p;
+  const int64_t *offN, *offM;      // device [B+1]
+  const float *x, *y, *alpha, *beta;
+  const double *eps, *rho1, *rho2;  // device [B]
+  int max_iter;
+  double tol;
+  int check_every;
+  BatchState *state;               // [B]
+  double *mu;                      // [B, kBatchMaxDim]
+  float *pot_x, *pot_y;            // stored (untranslated) potentials
+  float *rec_x, *rec_y;            // source records
+  const int4 *items_g, *items_f;   // (problem, first target, count, slot)
+  const int *pitem_g, *pitem_f;    // [B+1] item ranges per problem
+  int n_items_g, n_items_f;
+  int *act_g, *act_f;              // active item lists
+  int *nact_g, *nact_f;            // their lengths
+  int *ctr_g, *ctr_f;              // dynamic work counters
+  int *running;                    // problems not done (after the last compaction)
+  BlockPart *part_g, *part_f;      // per-item partials
+  int *ticket_g, *ticket_f;        // [B] arrival counters
+};
+
+hipError_t launch_batched_init(const BatchedArgs &a, hipStream_t s);
+hipError_t launch_batched_half(const BatchedArgs &a, int g_step, int blocks, hipStream_t s);
+hipError_t launch_batched_compact(const BatchedArgs &a, hipStream_t s);
+hipError_t launch_batched_finalize(const BatchedArgs &a, float *f, float *g, int32_t *iters,
+                                   int32_t *status, hipStream_t s);
+int batched_half_blocks_per_cu(const BatchedArgs &a);
+
+}  // namespace uot

@@ -1,0 +1,126 @@
+"""GPU parity of the batched TI solver against the FP64 oracle, problem by problem."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_00730_amd as uot
+import workloads
+from tests.helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    uot.load_library()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def run_batched(bt, iters, tol=0.0, ce=1):
+    f, g, it, st = uot.ti_sinkhorn_batched(bt.offN, bt.offM, dev(bt.x), dev(bt.y), dev(bt.alpha),
+                                           dev(bt.beta), bt.eps, bt.rho1, bt.rho2, p=bt.p,
+                                           max_iter=iters, tol=tol, check_every=ce)
+    torch.cuda.synchronize()
+    return (f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64),
+            it.cpu().numpy(), st.cpu().numpy())
+
+
+def oracle_problem(bt, b, iters, tol=0.0, ce=1):
+    pr = bt.problem(b)
+    cost = oracle.Cost(x=pr.x.astype(np.float64), y=pr.y.astype(np.float64), p=pr.p)
+    return oracle.sinkhorn(cost, pr.alpha.astype(np.float64), pr.beta.astype(np.float64), pr.eps,
+                           pr.rho1, pr.rho2, ti=True, max_iter=iters, tol=tol, check_every=ce)
+
+
+def small_batch(B=23, nmin=1, nmax=300, seed=31, d=2, p=2.0, eps=(2e-2, 2e-1), rho=(0.1, 10.0)):
+    bt = workloads.batch2d(B=B, nmin=nmin, nmax=nmax, seed=seed, eps_range=eps, rho_range=rho)
+    if d != 2:
+        rng = np.random.default_rng(seed)
+        bt.x = rng.uniform(0, 1, size=(int(bt.offN[-1]), d)).astype(np.float32)
+        bt.y = rng.uniform(0, 1, size=(int(bt.offM[-1]), d)).astype(np.float32)
+    bt.p = p
+    # unequal penalties on half of the problems
+    bt.rho2 = bt.rho2 * np.where(np.arange(B) % 2 == 0, 1.0, 2.5)
+    return bt
+
+
+@pytest.mark.parametrize("d,p", [(2, 2.0), (3, 2.0), (1, 2.0), (5, 1.5), (8, 2.0)])
+def test_batched_iteration_parity(d, p):
+    bt = small_batch(d=d, p=p, seed=40 + d)
+    print("batched d=%d p=%g B=%d" % (d, p, bt.B), file=sys.stderr, flush=True)
+    T = 12
+    f, g, it, st = run_batched(bt, T)
+    assert np.all(it == T) and np.all(st == uot.BATCH_MAX_ITER)
+    for b in range(bt.B):
+        r = oracle_problem(bt, b, T)
+        fb = f[bt.offN[b]:bt.offN[b + 1]]
+        gb = g[bt.offM[b]:bt.offM[b + 1]]
+        assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, (b, rel_inf(fb, r.f), rel_inf(gb, r.g))
+
+
+def test_batched_converges_per_problem():
+    """Each problem stops at its own first passing check; at its stopping iteration it matches
+    the oracle run for that many iterations, and the oracle's own stopping iteration is close."""
+    bt = small_batch(B=17, nmin=5, nmax=200, seed=7)
+    f, g, it, st = run_batched(bt, 5000, tol=1e-6, ce=10)
+    assert np.all(st == uot.BATCH_CONVERGED), st
+    assert len(set(it.tolist())) > 1  # problems converge at different iterations
+    for b in range(bt.B):
+        r = oracle_problem(bt, b, int(it[b]))
+        fb = f[bt.offN[b]:bt.offN[b + 1]]
+        gb = g[bt.offM[b]:bt.offM[b + 1]]
+        assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, b
+        rr = oracle_problem(bt, b, 5000, tol=1e-6, ce=10)
+        assert abs(int(it[b]) - rr.iters) <= 20, (b, it[b], rr.iters)
+
+
+def test_batched_matches_single_problem_solver():
+    bt = small_batch(B=9, nmin=50, nmax=400, seed=3)
+    f, g, _, _ = run_batched(bt, 30)
+    for b in range(bt.B):
+        pr = bt.problem(b)
+        fs, gs, info = uot.ti_sinkhorn(dev(pr.alpha), dev(pr.beta), x=dev(pr.x), y=dev(pr.y), eps=pr.eps,
+                                       rho1=pr.rho1, rho2=pr.rho2, max_iter=30)
+        assert rel_inf(f[bt.offN[b]:bt.offN[b + 1]], fs.cpu().numpy()) < TOL
+        assert rel_inf(g[bt.offM[b]:bt.offM[b + 1]], gs.cpu().numpy()) < TOL
+
+
+def test_batched_bad_problems_are_isolated():
+    bt = small_batch(B=6, nmin=3, nmax=40, seed=5)
+    a = bt.alpha.copy()
+    a[bt.offN[1]] = -1.0                      # problem 1: negative weight
+    bt.beta[bt.offM[3]:bt.offM[4]] = 0.0      # problem 3: zero mass
+    eps = bt.eps.copy()
+    eps[4] = -0.1                             # problem 4: bad eps
+    bt.alpha = a
+    bt.eps = eps
+    f, g, it, st = run_batched(bt, 10)
+    assert st[1] == uot.BATCH_INVALID and st[3] == uot.BATCH_INVALID and st[4] == uot.BATCH_INVALID
+    for b in (0, 2, 5):
+        assert st[b] == uot.BATCH_MAX_ITER
+        r = oracle_problem(bt, b, 10)
+        assert rel_inf(f[bt.offN[b]:bt.offN[b + 1]], r.f) < TOL
+
+
+def test_batched_sampled_full_size():
+    """The full 4096-problem batch (N, M up to 4096, eps down to 1e-3): a fixed number of
+    iterations, then sampled problems checked against the oracle run for as many iterations."""
+    bt = workloads.batch2d()
+    T = 6
+    f, g, it, st = run_batched(bt, T)
+    assert np.all(it == T)
+    rng = np.random.default_rng(0)
+    for b in rng.choice(bt.B, size=6, replace=False):
+        r = oracle_problem(bt, int(b), T)
+        fb = f[bt.offN[b]:bt.offN[b + 1]]
+        gb = g[bt.offM[b]:bt.offM[b + 1]]
+        assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, (b, rel_inf(fb, r.f))
