@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--only", default="", help="restrict to one eps,rho pair, e.g. 0.01,1")
     ap.add_argument("--points-kernel", choices=("auto", "valu", "mfma", "mfma2"), default="auto",
                     help="p = 2 softmin implementation")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -79,6 +81,25 @@ def one_step(uot, torch, tens, pairs, record):
         uot.backward(a, b, fti, gti, x=x, y=y, eps=eps, rho1=rho, rho2=rho)
     torch.cuda.synchronize()
     return updates
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the points softmin from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    summary = os.path.join(ROOT, "profiles", "points_softmin_cloud3d_hbm_bytes.md")
+    src = os.path.join(ROOT, "paper_2201_00730_amd", "csrc", "kernels_points.hip")
+    try:
+        text = open(summary).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    m_tr = re.search(r"traffic_bytes_per_launch: ([0-9.]+)", text)
+    if not m_sha or not m_tr or m_sha.group(1) != sha:
+        return None
+    return float(m_tr.group(1))
 
 
 def cpu_baseline(pr, seconds):
@@ -127,6 +148,14 @@ def main():
         e, r = (float(v) for v in args.only.split(","))
         pairs = [(e, r)]
 
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for w in range(args.warmup):
         one_step(uot, torch, tens, pairs, None)
         print("warmup step %d done" % w, file=sys.stderr, flush=True)
@@ -148,7 +177,7 @@ def main():
     value = updates / wall
     achieved = kentries / (kms * 1e-3) if kms > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_EXP_PER_S / 1e9,
-                "unit": "Gexp/s", "frac": achieved / PEAK_EXP_PER_S, "traffic": None,
+                "unit": "Gexp/s", "frac": achieved / PEAK_EXP_PER_S, "traffic": profiled_traffic(),
                 "kernel": ("k_points_partial<3,kSqEuc,4>" if args.points_kernel == "valu"
                            else "k_points_mfma<3,%d>" % (2 if args.points_kernel == "mfma2" else 1)),
                 "launches": launches,
