@@ -5,101 +5,10 @@
 // terms. Everything scalar is double precision.
 #include <cfloat>
 
-#include "uot_internal.h"
+#include "uot_epilogue.cuh"
 
 namespace uot {
 namespace {
-
-// Log-sum-exp pair (max, sum of exp(v - max)) merge; (-inf, 0) is the neutral element.
-__device__ __forceinline__ void lse_merge(double &m, double &s, double mo, double so) {
-  const double mn = fmax(m, mo);
-  if (mn == -INFINITY) { m = mn; s = 0.0; return; }
-  s = s * exp(m - mn) + so * exp(mo - mn);
-  m = mn;
-}
-
-// Block-wide reduction of (lse max, lse sum, max, min) over 256 threads.
-__device__ void block_reduce_part(double &mm, double &ms, double &dmx, double &dmn) {
-  __shared__ double s0[kBlock], s1[kBlock], s2[kBlock], s3[kBlock];
-  const int t = threadIdx.x;
-  s0[t] = mm; s1[t] = ms; s2[t] = dmx; s3[t] = dmn;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      double a = s0[t], b = s1[t];
-      lse_merge(a, b, s0[t + off], s1[t + off]);
-      s0[t] = a; s1[t] = b;
-      s2[t] = fmax(s2[t], s2[t + off]);
-      s3[t] = fmin(s3[t], s3[t + off]);
-    }
-    __syncthreads();
-  }
-  mm = s0[0]; ms = s1[0]; dmx = s2[0]; dmn = s3[0];
-  __syncthreads();
-}
-
-__device__ double block_sum(double v) {
-  __shared__ double s[kBlock];
-  const int t = threadIdx.x;
-  s[t] = v;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (t < off) s[t] += s[t + off];
-    __syncthreads();
-  }
-  const double r = s[0];
-  __syncthreads();
-  return r;
-}
-
-// Log2-sum over the split partials of one target: M + log2(sum_p l_p 2^{m_p - M}).
-__device__ __forceinline__ double combine_lse2(const float2 *part, int nsplit, int nt, int t) {
-  float M = -FLT_MAX;
-  for (int p = 0; p < nsplit; ++p) M = fmaxf(M, part[(size_t)p * nt + t].x);
-  double L = 0.0;
-  for (int p = 0; p < nsplit; ++p) {
-    const float2 q = part[(size_t)p * nt + t];
-    L += (double)q.y * exp2((double)q.x - (double)M);
-  }
-  return (double)M + log2(L);
-}
-
-// Centred coordinates of one target (as the softmin kernels form them) and their squared norm.
-template <int D>
-__device__ __forceinline__ double centred(const float *pts, int d, int t, const double *mu,
-                                          float *yc) {
-  double n2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    yc[k] = k < d ? pts[(size_t)t * d + k] - (float)mu[k] : 0.0f;
-    n2 += (double)yc[k] * (double)yc[k];
-  }
-  return n2;
-}
-
-// Writes the source record of point t with stored potential hf (see rec_stride).
-template <int D, int MODE>
-__device__ __forceinline__ void write_record(float *rec, int t, const float *yc, double yn2,
-                                             float hf, float w, double sc) {
-  const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
-  float *rp = rec + (size_t)t * rec_stride(MODE, D);
-  if constexpr (MODE == kSqEuc) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
-    rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
-    rp[D + 1] = 1.0f;  // multiplies -sigma_t in the matrix-core contraction
-#pragma unroll
-    for (int k = D + 2; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;  // padding read by MFMA
-  } else if constexpr (MODE == kPower) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) rp[k] = yc[k];
-    rp[D] = (float)(sc * (double)hf + lw2);
-#pragma unroll
-    for (int k = D + 1; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;
-  } else {
-    rp[0] = (float)(sc * (double)hf + lw2);
-  }
-}
 
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_build_records(RecordArgs a) {
@@ -128,133 +37,19 @@ __global__ __launch_bounds__(kBlock) void k_build_records(RecordArgs a) {
   }
 }
 
-// Reduces the block partials of a half-step (or of the start) into the scalar state; run by
-// one block of kBlock threads. Thread 0 writes the results.
-__device__ void reduce_scalars(const ReduceArgs &a) {
-  SolveState *st = a.st;
-  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
-  for (int b = threadIdx.x; b < a.nb; b += kBlock) {
-    const BlockPart q = a.bparts[b];
-    lse_merge(mm, ms, q.mass_max, q.mass_sum);
-    dmx = fmax(dmx, q.dmax);
-    dmn = fmin(dmn, q.dmin);
-  }
-  block_reduce_part(mm, ms, dmx, dmn);
-  if (threadIdx.x != 0) return;
-  const double L = (mm == -INFINITY) ? -INFINITY : mm + log(ms);  // log of the tilted mass
-  if (a.kind == kReduceInit) {
-    st->iter = 0;
-    st->tau_f = st->tau_g = st->lambda = 0.0;
-    st->off_f_prev = st->off_g_prev = 0.0;
-    st->gdiff_max = st->gdiff_min = 0.0;
-    st->delta = INFINITY;
-    st->sA = -a.rho1 * L;  // Smin_alpha^rho1(f_0)
-    st->sB = 0.0;
-    if (!st->pos_a || !st->pos_b) st->error |= kErrWeights;
-    st->done = st->error ? 1 : 0;
-  } else if (a.kind == kReduceG) {
-    const double sBhat = -a.rho2 * L;  // Smin_beta^rho2(ghat)
-    const double tg = a.ti ? a.kappa_t / (1.0 - a.kappa_t) * sBhat : 0.0;
-    st->tau_g = tg;
-    st->sB = sBhat + tg;
-    st->gdiff_max = dmx;
-    st->gdiff_min = dmn;
-  } else {
-    const double sAhat = -a.rho1 * L;  // Smin_alpha^rho1(fhat)
-    double tf = 0.0, lam = 0.0;
-    if (a.ti) {
-      tf = a.kappa_t / (1.0 - a.kappa_t) * sAhat;
-      st->sA = sAhat + tf;
-      lam = a.tau1 * st->sB - a.tau2 * st->sA;  // Prop. 2 through softmins
-    } else {
-      st->sA = sAhat;
-    }
-    st->tau_f = tf;
-    st->lambda = lam;
-    const double off_f = tf + lam, off_g = st->tau_g - lam;
-    const int it = st->iter + 1;
-    st->iter = it;
-    double delta = INFINITY;
-    if (it > 1) {
-      const double cf = off_f - st->off_f_prev, cg = off_g - st->off_g_prev;
-      const double df = fmax(dmx + cf, -(dmn + cf));
-      const double dg = fmax(st->gdiff_max + cg, -(st->gdiff_min + cg));
-      delta = fmax(df, dg);
-    }
-    st->delta = delta;
-    st->off_f_prev = off_f;
-    st->off_g_prev = off_g;
-    if (!isfinite(off_f) || !isfinite(off_g) || isnan(delta)) st->error |= kErrNumeric;
-    if (st->error)
-      st->done = 1;
-    else if (a.tol > 0.0 && a.check_every > 0 && it % a.check_every == 0 && delta < a.tol)
-      st->done = 1;
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
   if (a.kind != kReduceInit && a.st->done) return;
   reduce_scalars(a);
 }
 
-// Threads per target in the combine kernel: each merges every 4th split partial, then the
-// four (max, sum) pairs are merged with lane shuffles.
+// Threads per target in the combine kernel.
 constexpr int kCombLanes = 4;
 constexpr int kCombTargets = kBlock / kCombLanes;
 
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
   if (a.st->done) return;
-  __shared__ int s_last;
-  const int sub = threadIdx.x % kCombLanes;
-  const int t = blockIdx.x * kCombTargets + threadIdx.x / kCombLanes;
-  const int tc = t < a.nt ? t : a.nt - 1;
-  // log2-sum over the split partials of target tc: M + log2(sum_p l_p 2^{m_p - M})
-  float M = -FLT_MAX;
-  for (int p = sub; p < a.nsplit; p += kCombLanes) M = fmaxf(M, a.part[(size_t)p * a.nt + tc].x);
-  M = fmaxf(M, __shfl_xor(M, 1, kCombLanes));
-  M = fmaxf(M, __shfl_xor(M, 2, kCombLanes));
-  float L = 0.0f;
-  for (int p = sub; p < a.nsplit; p += kCombLanes) {
-    const float2 q = a.part[(size_t)p * a.nt + tc];
-    L += q.y * __builtin_amdgcn_exp2f(q.x - M);
-  }
-  L += __shfl_xor(L, 1, kCombLanes);
-  L += __shfl_xor(L, 2, kCombLanes);
-
-  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
-  if (sub == 0 && t < a.nt) {
-    double lse2 = (double)M + log2((double)L);
-    float yc[D > 0 ? D : 1];
-    double yn2 = 0.0;
-    if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, t, a.st->mu, yc);
-    if constexpr (MODE == kSqEuc) lse2 -= a.sc * yn2;
-    const double S = -lse2 / a.sc;  // softmin over the stored source potential
-    const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
-    const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
-    const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
-    const float hf = (float)hnew;
-    const float old = a.pot[t];
-    a.pot[t] = hf;
-    dmx = dmn = (double)hf - (double)old;
-    const float w = a.w[t];
-    write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
-    if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
-    if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);
-  }
-  block_reduce_part(mm, ms, dmx, dmn);
-  // The last block to finish reduces all block partials into the scalar state.
-  if (threadIdx.x == 0) {
-    a.bparts[blockIdx.x] = BlockPart{mm, ms, dmx, dmn};
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.st->ticket, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  reduce_scalars(a.red);
-  if (threadIdx.x == 0) a.st->ticket = 0u;
+  combine_and_reduce<D, MODE, kCombLanes>(a, blockIdx.x * kCombTargets, blockIdx.x, gridDim.x);
 }
 
 // Zeroes the flags of the state and computes the common mean of x and y (points costs).
@@ -435,6 +230,17 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
 hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_center, dim3(1), dim3(kBlock), 0, s, x, n, y, m, d, st);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned *p, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 // tile, and each entry then costs one exp2.
 #include <cfloat>
 
+#include "uot_epilogue.cuh"
 #include "uot_internal.h"
 
 namespace uot {
@@ -150,14 +151,17 @@ hipError_t launch_mode(const PointsArgs &a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------------------
 // Squared-Euclidean costs on the matrix cores. The base-2 exponent of entry (s, t), shifted
-// by the running reference sigma_t of its target, is the augmented dot product
-//   v_ts - sigma_t = sum_{e < K} A_se B_et,
-//   A_s = (u_s[0..D-1], b_s, 1, 0...),   B_t = (y_t - mu, 1, -sigma_t, 0...),
-// a K = D+2 (rounded to even) contraction done by v_mfma_f32_32x32x2f32 with sources as the
-// 32 rows and targets as the 32 columns of each output tile; the VALU then does one exp2 and
-// one add per entry. A_s comes from the source record plus the constant 1; B_t is built in
-// registers. Element e of k-slice ks for lane half h is e = KS*h + ks, so the KS elements a
-// lane needs from one record are contiguous.
+// by the running reference sigma_t of its target, is an augmented dot product plus a
+// per-column constant,
+//   v_ts - sigma_t = sum_{e < K} A_se B_et - sigma_t,
+//   A_s = (u_s[0..D-1], b_s, 0...),   B_t = (y_t - mu, 1, 0...),
+// a K = D+1 (rounded to even) contraction done by v_mfma_f32_32x32x2f32 with sources as the
+// 32 rows and targets as the 32 columns of each output tile; -sigma_t enters as the
+// accumulator input of the first k-slice (a register tile holding -sigma of each lane's
+// column), so it costs no contraction depth. The VALU then does one exp2 and one add per
+// entry. A_s comes from the source record; B_t is built in registers. Element e of k-slice ks
+// for lane half h is e = KS*h + ks, so the KS elements a lane needs from one record are
+// contiguous.
 //
 // Each lane owns one target column (lane % 32) and 16 source rows of every tile. sigma_t is
 // shared by the two lanes of a column and is raised only when a tile's sum of 2^{v - sigma}
@@ -172,16 +176,15 @@ constexpr int kMfmaWaves = 4;  // waves per block
 
 template <int D>
 struct MfmaShape {
-  static constexpr int K = ((D + 2) + 1) / 2 * 2;  // augmented depth, even
+  static constexpr int K = ((D + 1) + 1) / 2 * 2;  // augmented depth, even
   static constexpr int KS = K / 2;                  // k-slices of the 32x32x2 instruction
   static constexpr int SD = rec_stride(kSqEuc, D);
   static constexpr int EB = D;                      // element holding b_s (A) / 1 (B)
-  static constexpr int ES = D + 1;                  // element holding 1 (A) / -sigma (B)
   static_assert(K <= SD, "record shorter than the contraction");
 };
 
-template <int D, int TJ>
-__global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
+template <int D, int TJ, bool FUSE>
+__global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a, FusedTail fz) {
   if (a.done != nullptr && *a.done) return;
   using S = MfmaShape<D>;
   constexpr int KS = S::KS, SD = S::SD;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
   const int h = lane >> 5;
   const int tbase = (blockIdx.x * kMfmaWaves + wave) * (32 * TJ);
 
-  // B fragments: element e = KS*h + ks of (y - mu, 1, -sigma, 0...); sigma starts at 0
+  // B fragments: element e = KS*h + ks of (y - mu, 1, 0...)
   float bf[TJ][KS];
 #pragma unroll
   for (int tj = 0; tj < TJ; ++tj) {
@@ -218,31 +221,64 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) af[ks] = rp[ks];
   };
-  const f32x16 zero = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
-                       0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  auto tile_mfma = [&](const float *af, int tj) {
-    f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[0], bf[tj][0], zero, 0, 0, 0);
-#pragma unroll
-    for (int ks = 1; ks < KS; ++ks)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[ks], bf[tj][ks], acc, 0, 0, 0);
-    return acc;
-  };
-
   float sig[TJ], l[TJ];  // running reference and sum of 2^{v - sig} (this lane's rows)
   bool started[TJ];
 #pragma unroll
   for (int tj = 0; tj < TJ; ++tj) { sig[tj] = 0.0f; l[tj] = 0.0f; started[tj] = false; }
-  const int es_ks = S::ES - KS * h;  // k-slice holding -sigma in this lane half
 
-  // Adds the tile held in acc (computed with reference `used`) to the running sums. The
-  // fast/slow decision is wave-uniform, so the common path has no divergence and no
-  // cross-lane traffic.
-  auto consume = [&](f32x16 (&acc)[TJ], float (&used)[TJ]) {
+  // Re-centres column tile tj on its largest exponent and adds it (all lanes; exact for any
+  // column). acc was computed with the current sig.
+  auto recentre = [&](const f32x16 &acc, int tj) {
+    float tm = acc[0];
 #pragma unroll
-    for (int tj = 0; tj < TJ; ++tj) {
-      float ts = 0.0f;
-      const bool same = __all(used[tj] == sig[tj] && started[tj]);
-      if (same) {
+    for (int r = 1; r < 16; ++r) tm = fmaxf(tm, acc[r]);
+    tm = fmaxf(tm, __shfl_xor(tm, 32, 64));
+    if (tm > -INFINITY) {
+      const float delta = started[tj] ? fmaxf(tm, 0.0f) : tm;
+      float t2 = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) t2 += fast_exp2(acc[r] - delta);
+      // first tile: no rescale (delta may be far below -126 and 0 * 2^{-delta} is NaN)
+      l[tj] = started[tj] ? l[tj] * fast_exp2(-delta) + t2 : t2;
+      sig[tj] += delta;
+      started[tj] = true;
+    }
+  };
+
+  // Tiles of 32 sources; the next tile's records are prefetched while this tile's exps run,
+  // and the waves resident on the SIMD cover each other's matrix-core latency. The inner
+  // loop is the fast path, where -sig (the accumulator input) is loop-invariant; a tile that
+  // would overflow the sums, or a column not yet started, leaves it for recentre().
+  float an[KS], ac[KS];
+  load_a(s0, an);
+  int sb = s0;
+  while (sb < s1) {
+    f32x16 nsig[TJ];
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) nsig[tj][r] = -sig[tj];
+    bool all_started = true;
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) all_started = all_started && __all(started[tj]);
+    f32x16 acc[TJ];
+    bool slow = false;
+    for (; sb < s1; sb += 32) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) ac[ks] = an[ks];
+      if (sb + 32 < s1) load_a(sb + 32, an);
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) {
+        acc[tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[0], bf[tj][0], nsig[tj], 0, 0, 0);
+#pragma unroll
+        for (int ks = 1; ks < KS; ++ks)
+          acc[tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[ks], bf[tj][ks], acc[tj], 0, 0, 0);
+      }
+      if (!all_started) { slow = true; break; }
+      float ts[TJ];
+      bool ok = true;
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) {
         float q0 = fast_exp2(acc[tj][0]), q1 = fast_exp2(acc[tj][1]);
         float q2 = fast_exp2(acc[tj][2]), q3 = fast_exp2(acc[tj][3]);
 #pragma unroll
@@ -252,59 +288,17 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
           q2 += fast_exp2(acc[tj][r + 2]);
           q3 += fast_exp2(acc[tj][r + 3]);
         }
-        ts = (q0 + q1) + (q2 + q3);
+        ts[tj] = (q0 + q1) + (q2 + q3);
+        ok = ok && !__any(!(ts[tj] <= 0x1p64f));
       }
-      if (!same || __any(!(ts <= 0x1p64f))) {
-        // all lanes: re-centre each column on its largest exponent (exact for every column)
-        const float corr = sig[tj] - used[tj];  // acc - corr = v - sig
-        float tm = acc[tj][0];
+      if (!ok) { slow = true; break; }
 #pragma unroll
-        for (int r = 1; r < 16; ++r) tm = fmaxf(tm, acc[tj][r]);
-        tm -= corr;
-        tm = fmaxf(tm, __shfl_xor(tm, 32, 64));
-        if (tm > -INFINITY) {
-          const float delta = started[tj] ? fmaxf(tm, 0.0f) : tm;
-          const float off = corr + delta;
-          float t2 = 0.0f;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) t2 += fast_exp2(acc[tj][r] - off);
-          // first tile: no rescale (delta may be far below -126 and 0 * 2^{-delta} is NaN)
-          l[tj] = started[tj] ? l[tj] * fast_exp2(-delta) + t2 : t2;
-          sig[tj] += delta;
-          started[tj] = true;
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) bf[tj][ks] = (ks == es_ks) ? -sig[tj] : bf[tj][ks];
-        }
-      } else {
-        l[tj] += ts;
-      }
+      for (int tj = 0; tj < TJ; ++tj) l[tj] += ts[tj];
     }
-  };
-
-  // software pipeline over tiles of 32 sources, two accumulator sets used in turn
-  float an[KS];
-  f32x16 accA[TJ], accB[TJ];
-  float usedA[TJ], usedB[TJ];
-  load_a(s0, an);
+    if (!slow) break;
 #pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) { accA[tj] = tile_mfma(an, tj); usedA[tj] = sig[tj]; }
-  if (s0 + 32 < s1) load_a(s0 + 32, an);
-  for (int sb = s0; sb < s1; sb += 64) {
-    const bool has_b = sb + 32 < s1;
-    if (has_b) {
-#pragma unroll
-      for (int tj = 0; tj < TJ; ++tj) { accB[tj] = tile_mfma(an, tj); usedB[tj] = sig[tj]; }
-      if (sb + 64 < s1) load_a(sb + 64, an);
-    }
-    consume(accA, usedA);
-    if (has_b) {
-      if (sb + 64 < s1) {
-#pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) { accA[tj] = tile_mfma(an, tj); usedA[tj] = sig[tj]; }
-        if (sb + 96 < s1) load_a(sb + 96, an);
-      }
-      consume(accB, usedB);
-    }
+    for (int tj = 0; tj < TJ; ++tj) recentre(acc[tj], tj);
+    sb += 32;
   }
 
   // merge the two half-waves of each column (same sigma; sums add)
@@ -316,38 +310,67 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
     if (h == 0 && t < a.nt)
       a.part[(size_t)blockIdx.y * a.nt + t] = make_float2(ll > 0.0f ? sig[tj] : -FLT_MAX, ll);
   }
+
+  if constexpr (FUSE) {
+    // The last of the gridDim.y split blocks of this tile to arrive merges the tile; no block
+    // waits for another.
+    // Every wave waits for its own partial stores to complete before the barrier (the
+    // barrier alone does not wait for them), so thread 0's release (L2 write-back) covers
+    // the whole block. Only the last block acquires (L2 invalidate): an invalidate in every
+    // block would evict the source records that the blocks still running stream.
+    __shared__ int s_last;
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned prev = atomicAdd(&fz.tile_ticket[blockIdx.x], 1u);
+      s_last = (prev == gridDim.y - 1u) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) fz.tile_ticket[blockIdx.x] = 0u;
+    constexpr int kTileTargets = kMfmaWaves * 32 * TJ;
+    combine_and_reduce<D, kSqEuc, 256 / kTileTargets>(fz.c, blockIdx.x * kTileTargets,
+                                                      blockIdx.x, gridDim.x);
+  }
 }
 
 
 template <int D, int TJ>
-hipError_t launch_mfma_tj(const PointsArgs &a, hipStream_t st) {
+hipError_t launch_mfma_tj(const PointsArgs &a, const FusedTail *fz, hipStream_t st) {
   const int tpb = kMfmaWaves * 32 * TJ;
   dim3 grid((a.nt + tpb - 1) / tpb, a.nsplit);
-  hipLaunchKernelGGL((k_points_mfma<D, TJ>), grid, dim3(64 * kMfmaWaves), 0, st, a);
+  if (fz != nullptr)
+    hipLaunchKernelGGL((k_points_mfma<D, TJ, true>), grid, dim3(64 * kMfmaWaves), 0, st, a, *fz);
+  else
+    hipLaunchKernelGGL((k_points_mfma<D, TJ, false>), grid, dim3(64 * kMfmaWaves), 0, st, a,
+                       FusedTail{});
   return hipGetLastError();
 }
 
 template <int D>
-hipError_t launch_mfma_bucket(const PointsArgs &a, hipStream_t st) {
-  return mfma_tiles_per_wave() == 2 ? launch_mfma_tj<D, 2>(a, st) : launch_mfma_tj<D, 1>(a, st);
+hipError_t launch_mfma_bucket(const PointsArgs &a, const FusedTail *fz, hipStream_t st) {
+  return mfma_tiles_per_wave() == 2 ? launch_mfma_tj<D, 2>(a, fz, st)
+                                    : launch_mfma_tj<D, 1>(a, fz, st);
 }
 
-hipError_t launch_mfma(const PointsArgs &a, hipStream_t st) {
+hipError_t launch_mfma(const PointsArgs &a, const FusedTail *fz, hipStream_t st) {
   switch (dim_bucket(a.d)) {
-    case 1: return launch_mfma_bucket<1>(a, st);
-    case 2: return launch_mfma_bucket<2>(a, st);
-    case 3: return launch_mfma_bucket<3>(a, st);
-    case 4: return launch_mfma_bucket<4>(a, st);
-    case 5: return launch_mfma_bucket<5>(a, st);
-    case 6: return launch_mfma_bucket<6>(a, st);
-    case 7: return launch_mfma_bucket<7>(a, st);
-    case 8: return launch_mfma_bucket<8>(a, st);
-    case 12: return launch_mfma_bucket<12>(a, st);
-    case 16: return launch_mfma_bucket<16>(a, st);
-    case 24: return launch_mfma_bucket<24>(a, st);
-    case 32: return launch_mfma_bucket<32>(a, st);
-    case 48: return launch_mfma_bucket<48>(a, st);
-    case 64: return launch_mfma_bucket<64>(a, st);
+    case 1: return launch_mfma_bucket<1>(a, fz, st);
+    case 2: return launch_mfma_bucket<2>(a, fz, st);
+    case 3: return launch_mfma_bucket<3>(a, fz, st);
+    case 4: return launch_mfma_bucket<4>(a, fz, st);
+    case 5: return launch_mfma_bucket<5>(a, fz, st);
+    case 6: return launch_mfma_bucket<6>(a, fz, st);
+    case 7: return launch_mfma_bucket<7>(a, fz, st);
+    case 8: return launch_mfma_bucket<8>(a, fz, st);
+    case 12: return launch_mfma_bucket<12>(a, fz, st);
+    case 16: return launch_mfma_bucket<16>(a, fz, st);
+    case 24: return launch_mfma_bucket<24>(a, fz, st);
+    case 32: return launch_mfma_bucket<32>(a, fz, st);
+    case 48: return launch_mfma_bucket<48>(a, fz, st);
+    case 64: return launch_mfma_bucket<64>(a, fz, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -365,8 +388,8 @@ int occupancy_blocks(Kern kern) {
 template <int D>
 int points_blocks_per_cu_bucket(int mode) {
   if (mode == kSqEuc && g_points_variant != kPointsValu)
-    return mfma_tiles_per_wave() == 2 ? occupancy_blocks(k_points_mfma<D, 2>)
-                                      : occupancy_blocks(k_points_mfma<D, 1>);
+    return mfma_tiles_per_wave() == 2 ? occupancy_blocks(k_points_mfma<D, 2, true>)
+                                      : occupancy_blocks(k_points_mfma<D, 1, true>);
   constexpr int R = targets_per_thread<D>();
   return mode == kSqEuc ? occupancy_blocks(k_points_partial<D, kSqEuc, R>)
                         : occupancy_blocks(k_points_partial<D, kPower, R>);
@@ -411,10 +434,20 @@ int points_targets_per_block(int mode, int d) {
   return 256 * (b <= 4 ? 4 : (b <= 8 ? 2 : 1));
 }
 
+int points_fused_tiles(int nt) {
+  const int tpb = kMfmaWaves * 32 * mfma_tiles_per_wave();
+  return (nt + tpb - 1) / tpb;
+}
+
+hipError_t launch_points_fused(const PointsArgs &a, const FusedTail &f, hipStream_t st) {
+  if (!points_uses_mfma(kSqEuc, a.d)) return hipErrorInvalidValue;
+  return launch_mfma(a, &f, st);
+}
+
 int points_split_align(int mode, int d) { return points_uses_mfma(mode, d) ? 32 : 8; }
 
 hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st) {
-  if (points_uses_mfma(mode, a.d)) return launch_mfma(a, st);
+  if (points_uses_mfma(mode, a.d)) return launch_mfma(a, nullptr, st);
   if (mode == kSqEuc) return launch_mode<kSqEuc>(a, st);
   if (mode == kPower) return launch_mode<kPower>(a, st);
   return hipErrorInvalidValue;

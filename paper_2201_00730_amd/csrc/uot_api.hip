@@ -36,6 +36,12 @@ uot_status fail(uot_status s, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(UOT_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+#define UOT_TRY(expr)                    \
+  do {                                   \
+    uot_status r_ = (expr);              \
+    if (r_ != UOT_OK) return r_;         \
+  } while (0)
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -159,7 +165,8 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
 }
 
 struct Layout {
-  size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0;
+  size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0, tickets = 0;
+  int ntickets = 0;
   size_t dual = 0, rowsum_x = 0, rowsum_y = 0, tmp_x = 0, tmp_y = 0, scratch = 0, total = 0;
   HalfShape g, f;  // g-step: targets y (columns), sources x; f-step: targets x (rows), sources y
 };
@@ -192,6 +199,9 @@ Layout make_layout(const uot_cost *c, int which) {
   const int nrec = (rec_count(nmax) + kBlock - 1) / kBlock;
   const int nbp = combine_blocks(nmax) > nrec ? combine_blocks(nmax) : nrec;
   L.bparts = take((size_t)(nbp + 1) * sizeof(BlockPart));
+  // one counter per target tile of the fused softmin (tiles of at least 32 targets)
+  L.ntickets = (nmax + 31) / 32;
+  L.tickets = take((size_t)L.ntickets * sizeof(unsigned));
   L.dual = take((size_t)((nmax + kBlock - 1) / kBlock + 1) * 6 * sizeof(double));
   if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
     L.rowsum_x = take((size_t)n * sizeof(float));
@@ -355,7 +365,9 @@ struct Ctx {
 // Softmin partials of one half-step into the part buffer.
 //   g_step: targets are the y side (columns of C), sources the x side with records rec_x;
 //   otherwise targets are the x side (rows of C), sources the y side with records rec_y.
-uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
+//   fused: the combine runs in the tail of the softmin kernel (matrix-core path only).
+uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done,
+                            const FusedTail *fused = nullptr) {
   const HalfShape &h = g_step ? k.L.g : k.L.f;
   float2 *part = at<float2>(k.ws, k.L.part);
   const float *rec_src = at<float>(k.ws, g_step ? k.L.rec_x : k.L.rec_y);
@@ -390,11 +402,14 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     a.part = part;
     a.done = done;
     if (k.timer) UOT_HIP(k.timer->begin(k.s));
-    UOT_HIP(launch_points_partial(k.mode, a, k.s));
+    UOT_HIP(fused ? launch_points_fused(a, *fused, k.s) : launch_points_partial(k.mode, a, k.s));
     if (k.timer) UOT_HIP(k.timer->end(k.s, kProfPoints, (double)k.n * (double)k.m));
   }
   return UOT_OK;
 }
+
+// Solver half-steps on the matrix-core path run the combine inside the softmin kernel.
+bool fused_softmin(const Ctx &k) { return k.mode != kDense && points_uses_mfma(k.mode, k.d); }
 
 Epilogue epilogue_for(const Ctx &k, bool g_step) {
   const double e = k.eps, r1 = k.rho1, r2 = k.rho2;
@@ -418,8 +433,6 @@ Epilogue epilogue_for(const Ctx &k, bool g_step) {
 
 uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   SolveState *st = k.st();
-  uot_status r = softmin_partials(k, g_step, &st->done);
-  if (r != UOT_OK) return r;
   const HalfShape &h = g_step ? k.L.g : k.L.f;
   CombineArgs ca;
   ca.part = at<float2>(k.ws, k.L.part);
@@ -449,6 +462,14 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
   ra.tol = tol;
   ra.check_every = check_every;
+  if (fused_softmin(k)) {
+    FusedTail fz;
+    fz.c = ca;
+    fz.c.red.nb = points_fused_tiles(ca.nt);
+    fz.tile_ticket = at<unsigned>(k.ws, k.L.tickets);
+    return softmin_partials(k, g_step, &st->done, &fz);
+  }
+  UOT_TRY(softmin_partials(k, g_step, &st->done));
   UOT_HIP(launch_combine(ca, k.s));
   return UOT_OK;
 }
@@ -493,12 +514,6 @@ uot_status check_scalars(double eps, double rho1, double rho2) {
   return UOT_OK;
 }
 
-#define UOT_TRY(expr)                    \
-  do {                                   \
-    uot_status r_ = (expr);              \
-    if (r_ != UOT_OK) return r_;         \
-  } while (0)
-
 uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const uot_params *P,
                  float *f, float *g, void *workspace, size_t workspace_bytes, uot_info *info,
                  void *stream, bool ti) {
@@ -536,6 +551,8 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
 
   // start: flags, centring, weights, records of x from f_0 (with Smin_alpha^rho1(f_0)), g = 0
   UOT_TRY(prepare(c, alpha, beta, st, k.s));
+  if (fused_softmin(k))
+    UOT_HIP(launch_zero_u32(at<unsigned>(k.ws, k.L.tickets), k.L.ntickets, k.s));
   int nbx = 0;
   UOT_TRY(build_records(k, true, P->warm_start ? f : nullptr, true, true, &nbx));
   ReduceArgs ri;

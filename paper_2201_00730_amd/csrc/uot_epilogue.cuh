@@ -1,0 +1,254 @@
+// Device helpers shared by the epilogue kernels and the fused softmin kernels: log-sum-exp
+// merges, block reductions, centred coordinates, source records and the scalar reduction of
+// a half-step (tilted masses, TI translations, lambda*, change, convergence test).
+#pragma once
+
+#include <cfloat>
+
+#include "uot_internal.h"
+
+namespace uot {
+
+// Log-sum-exp pair (max, sum of exp(v - max)) merge; (-inf, 0) is the neutral element.
+static __device__ __forceinline__ void lse_merge(double &m, double &s, double mo, double so) {
+  const double mn = fmax(m, mo);
+  if (mn == -INFINITY) { m = mn; s = 0.0; return; }
+  s = s * exp(m - mn) + so * exp(mo - mn);
+  m = mn;
+}
+
+// Block-wide reduction of (lse max, lse sum, max, min) over 256 threads: lane shuffles within
+// each wave, then the four wave results through LDS.
+static __device__ void block_reduce_part(double &mm, double &ms, double &dmx, double &dmn) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ double s[4][kWaves];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lse_merge(mm, ms, __shfl_xor(mm, o, 64), __shfl_xor(ms, o, 64));
+    dmx = fmax(dmx, __shfl_xor(dmx, o, 64));
+    dmn = fmin(dmn, __shfl_xor(dmn, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { s[0][w] = mm; s[1][w] = ms; s[2][w] = dmx; s[3][w] = dmn; }
+  __syncthreads();
+  mm = s[0][0]; ms = s[1][0]; dmx = s[2][0]; dmn = s[3][0];
+  for (int k = 1; k < kWaves; ++k) {
+    lse_merge(mm, ms, s[0][k], s[1][k]);
+    dmx = fmax(dmx, s[2][k]);
+    dmn = fmin(dmn, s[3][k]);
+  }
+  __syncthreads();
+}
+
+static __device__ double block_sum(double v) {
+  __shared__ double s[kBlock];
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (t < off) s[t] += s[t + off];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// Log2-sum over the split partials of one target: M + log2(sum_p l_p 2^{m_p - M}).
+static __device__ __forceinline__ double combine_lse2(const float2 *part, int nsplit, int nt, int t) {
+  float M = -FLT_MAX;
+  for (int p = 0; p < nsplit; ++p) M = fmaxf(M, part[(size_t)p * nt + t].x);
+  double L = 0.0;
+  for (int p = 0; p < nsplit; ++p) {
+    const float2 q = part[(size_t)p * nt + t];
+    L += (double)q.y * exp2((double)q.x - (double)M);
+  }
+  return (double)M + log2(L);
+}
+
+// Centred coordinates of one target (as the softmin kernels form them) and their squared norm.
+template <int D>
+static __device__ __forceinline__ double centred(const float *pts, int d, int t, const double *mu,
+                                          float *yc) {
+  double n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    yc[k] = k < d ? pts[(size_t)t * d + k] - (float)mu[k] : 0.0f;
+    n2 += (double)yc[k] * (double)yc[k];
+  }
+  return n2;
+}
+
+// Writes the source record of point t with stored potential hf (see rec_stride).
+template <int D, int MODE>
+static __device__ __forceinline__ void write_record(float *rec, int t, const float *yc, double yn2,
+                                             float hf, float w, double sc) {
+  const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
+  float *rp = rec + (size_t)t * rec_stride(MODE, D);
+  if constexpr (MODE == kSqEuc) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
+    rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
+    rp[D + 1] = 1.0f;  // multiplies -sigma_t in the matrix-core contraction
+#pragma unroll
+    for (int k = D + 2; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;  // padding read by MFMA
+  } else if constexpr (MODE == kPower) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) rp[k] = yc[k];
+    rp[D] = (float)(sc * (double)hf + lw2);
+#pragma unroll
+    for (int k = D + 1; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;
+  } else {
+    rp[0] = (float)(sc * (double)hf + lw2);
+  }
+}
+
+// Reduces the block partials of a half-step (or of the start) into the scalar state; run by
+// one block of kBlock threads. Thread 0 writes the results.
+static __device__ void reduce_scalars(const ReduceArgs &a) {
+  SolveState *st = a.st;
+  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+  for (int b = threadIdx.x; b < a.nb; b += kBlock) {
+    const BlockPart q = a.bparts[b];
+    lse_merge(mm, ms, q.mass_max, q.mass_sum);
+    dmx = fmax(dmx, q.dmax);
+    dmn = fmin(dmn, q.dmin);
+  }
+  block_reduce_part(mm, ms, dmx, dmn);
+  if (threadIdx.x != 0) return;
+  const double L = (mm == -INFINITY) ? -INFINITY : mm + log(ms);  // log of the tilted mass
+  if (a.kind == kReduceInit) {
+    st->iter = 0;
+    st->tau_f = st->tau_g = st->lambda = 0.0;
+    st->off_f_prev = st->off_g_prev = 0.0;
+    st->gdiff_max = st->gdiff_min = 0.0;
+    st->delta = INFINITY;
+    st->sA = -a.rho1 * L;  // Smin_alpha^rho1(f_0)
+    st->sB = 0.0;
+    if (!st->pos_a || !st->pos_b) st->error |= kErrWeights;
+    st->done = st->error ? 1 : 0;
+  } else if (a.kind == kReduceG) {
+    const double sBhat = -a.rho2 * L;  // Smin_beta^rho2(ghat)
+    const double tg = a.ti ? a.kappa_t / (1.0 - a.kappa_t) * sBhat : 0.0;
+    st->tau_g = tg;
+    st->sB = sBhat + tg;
+    st->gdiff_max = dmx;
+    st->gdiff_min = dmn;
+  } else {
+    const double sAhat = -a.rho1 * L;  // Smin_alpha^rho1(fhat)
+    double tf = 0.0, lam = 0.0;
+    if (a.ti) {
+      tf = a.kappa_t / (1.0 - a.kappa_t) * sAhat;
+      st->sA = sAhat + tf;
+      lam = a.tau1 * st->sB - a.tau2 * st->sA;  // Prop. 2 through softmins
+    } else {
+      st->sA = sAhat;
+    }
+    st->tau_f = tf;
+    st->lambda = lam;
+    const double off_f = tf + lam, off_g = st->tau_g - lam;
+    const int it = st->iter + 1;
+    st->iter = it;
+    double delta = INFINITY;
+    if (it > 1) {
+      const double cf = off_f - st->off_f_prev, cg = off_g - st->off_g_prev;
+      const double df = fmax(dmx + cf, -(dmn + cf));
+      const double dg = fmax(st->gdiff_max + cg, -(st->gdiff_min + cg));
+      delta = fmax(df, dg);
+    }
+    st->delta = delta;
+    st->off_f_prev = off_f;
+    st->off_g_prev = off_g;
+    if (!isfinite(off_f) || !isfinite(off_g) || isnan(delta)) st->error |= kErrNumeric;
+    if (st->error)
+      st->done = 1;
+    else if (a.tol > 0.0 && a.check_every > 0 && it % a.check_every == 0 && delta < a.tol)
+      st->done = 1;
+  }
+}
+
+// Merges the split partials of targets [t_begin, t_begin + kBlock / LANES) (LANES threads per
+// target), applies the half-step epilogue (KL prox and TI translation, App. B) and writes the
+// new potentials and source records; returns this thread's contribution to the block's
+// (tilted-mass log-sum-exp, potential-change range) partial.
+template <int D, int MODE, int LANES>
+static __device__ void combine_range(const CombineArgs &a, int t_begin, double &mm, double &ms,
+                                     double &dmx, double &dmn) {
+  const int sub = threadIdx.x % LANES;
+  const int t = t_begin + threadIdx.x / LANES;
+  const int tc = t < a.nt ? t : a.nt - 1;
+  // log2-sum over the split partials: M + log2(sum_p l_p 2^{m_p - M}), one pass, the loads of
+  // a batch of 8 partials issued together (this merge is latency bound)
+  constexpr int kBatch = 8;
+  float M = -FLT_MAX, L = 0.0f;
+  for (int p0 = sub; p0 < a.nsplit; p0 += kBatch * LANES) {
+    float2 q[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int p = p0 + u * LANES;
+      q[u] = p < a.nsplit ? a.part[(size_t)p * a.nt + tc] : make_float2(-FLT_MAX, 0.0f);
+    }
+    float nm = M;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) nm = fmaxf(nm, q[u].x);
+    float acc = L * __builtin_amdgcn_exp2f(M - nm);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) acc += q[u].y * __builtin_amdgcn_exp2f(q[u].x - nm);
+    M = nm;
+    L = acc;
+  }
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) {
+    const float Mo = __shfl_xor(M, o, LANES), Lo = __shfl_xor(L, o, LANES);
+    const float nm = fmaxf(M, Mo);
+    L = L * __builtin_amdgcn_exp2f(M - nm) + Lo * __builtin_amdgcn_exp2f(Mo - nm);
+    M = nm;
+  }
+  mm = -INFINITY;
+  ms = 0.0;
+  dmx = -INFINITY;
+  dmn = INFINITY;
+  if (sub == 0 && t < a.nt) {
+    double lse2 = (double)M + log2((double)L);
+    float yc[D > 0 ? D : 1];
+    double yn2 = 0.0;
+    if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, t, a.st->mu, yc);
+    if constexpr (MODE == kSqEuc) lse2 -= a.sc * yn2;
+    const double S = -lse2 / a.sc;  // softmin over the stored source potential
+    const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
+    const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
+    const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
+    const float hf = (float)hnew;
+    const float old = a.pot[t];
+    a.pot[t] = hf;
+    dmx = dmn = (double)hf - (double)old;
+    const float w = a.w[t];
+    write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
+    if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
+    if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);
+  }
+}
+
+// combine_range over one block's targets, then the block partial into bparts[tile]; the last
+// of `ntiles` blocks to arrive (atomic ticket, no waiting) reduces all partials into the
+// scalar state and re-arms the ticket.
+template <int D, int MODE, int LANES>
+static __device__ void combine_and_reduce(const CombineArgs &a, int t_begin, int tile, int ntiles) {
+  __shared__ int s_last;
+  double mm, ms, dmx, dmn;
+  combine_range<D, MODE, LANES>(a, t_begin, mm, ms, dmx, dmn);
+  block_reduce_part(mm, ms, dmx, dmn);
+  if (threadIdx.x == 0) {
+    a.bparts[tile] = BlockPart{mm, ms, dmx, dmn};
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned prev = atomicAdd(&a.st->ticket, 1u);
+    s_last = (prev == (unsigned)ntiles - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  reduce_scalars(a.red);
+  if (threadIdx.x == 0) a.st->ticket = 0u;
+}
+
+}  // namespace uot

@@ -12,6 +12,9 @@ namespace uot {
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2 = 0.6931471805599453094;
 constexpr int kMaxDim = 64;
+// s_waitcnt immediate that waits for every outstanding vector memory operation of the wave
+// (vmcnt 0; expcnt and lgkmcnt at their no-wait maxima), gfx9 encoding.
+constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr int kBlock = 256;  // threads per block of the O(N) kernels
 
 // How C is formed inside a kernel.
@@ -170,6 +173,18 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
 int combine_blocks(int nt);
 
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
+
+// Matrix-core softmin with the combine fused into its tail: the last split block of each
+// target tile (per-tile ticket) merges that tile's partials and runs the epilogue, the last
+// tile reduces the scalars (c.red.nb = number of tiles). tile_ticket holds one zeroed counter
+// per tile; every launch leaves them zeroed again.
+struct FusedTail {
+  CombineArgs c;
+  unsigned *tile_ticket;
+};
+hipError_t launch_points_fused(const PointsArgs &a, const FusedTail &f, hipStream_t st);
+int points_fused_tiles(int nt);   // target tiles of the fused kernel (blocks along x)
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t st);
 
 // Build source records from a potential (solve start, dual value, plan, backward).
 struct RecordArgs {
