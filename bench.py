@@ -49,7 +49,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="", help="restrict to one eps,rho pair, e.g. 0.01,1")
-    ap.add_argument("--points-kernel", choices=("auto", "valu", "mfma", "mfma2"), default="auto",
+    ap.add_argument("--points-kernel", choices=("auto", "valu", "mfma-f32", "mfma-bf16"),
+                    default="auto",
                     help="p = 2 softmin implementation")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -122,6 +123,16 @@ def cpu_baseline(pr, seconds):
                       "eps=1e-2 rho=1, %d iterations from f=0, %.1f s" % (pr.n, iters, dt)}
 
 
+PROFILE_PERIOD = 15
+
+
+def kernel_name(variant: str) -> str:
+    """Name of the timed softmin kernel of the 3-D workload."""
+    if variant == "valu":
+        return "k_points_partial<3,kSqEuc,4>"
+    return "k_points_mfma<3,%s<3>>" % ("F32Form" if variant == "mfma-f32" else "Bf16Form")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -138,7 +149,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     uot.load_library()
-    uot.set_points_kernel({"auto": 0, "valu": 1, "mfma": 2, "mfma2": 3}[args.points_kernel])
+    uot.set_points_kernel({"auto": 0, "valu": 1, "mfma-f32": 2, "mfma-bf16": 3}[args.points_kernel])
     pr = workloads.cloud3d(n=args.n, m=args.n)
     dev = torch.device("cuda:0")
     tens = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
@@ -161,7 +172,10 @@ def main():
         print("warmup step %d done" % w, file=sys.stderr, flush=True)
 
     uot.profile_reset()
-    uot.profile_enable(True)
+    # every 15th softmin launch is bracketed by events (an odd period samples both half-steps;
+    # each event record idles the GPU for microseconds, so timing every launch would slow
+    # the timed run itself)
+    uot.profile_enable(True, period=PROFILE_PERIOD)
     record = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -178,8 +192,7 @@ def main():
     achieved = kentries / (kms * 1e-3) if kms > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_EXP_PER_S / 1e9,
                 "unit": "Gexp/s", "frac": achieved / PEAK_EXP_PER_S, "traffic": profiled_traffic(),
-                "kernel": ("k_points_partial<3,kSqEuc,4>" if args.points_kernel == "valu"
-                           else "k_points_mfma<3,%d>" % (2 if args.points_kernel == "mfma2" else 1)),
+                "kernel": kernel_name(args.points_kernel),
                 "launches": launches,
                 "avg_launch_ms": kms / launches if launches else None,
                 "entries_per_launch": kentries / launches if launches else None}

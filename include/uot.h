@@ -228,25 +228,28 @@ uot_status uot_ti_sinkhorn_batched(int32_t B, const int64_t *offN, const int64_t
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d);
 
 /*
- * Kernel timing, for benchmarks (off by default). While enabled, every softmin launch of
- * uot_sinkhorn / uot_ti_sinkhorn is bracketed by two HIP events recorded on the call's
- * stream, and its duration is accumulated, with the number of cost entries it processed,
- * per kernel kind: 0 = points-cost softmin, 1 = stored-cost column softmin, 2 = stored-cost
- * row softmin. Thread-safe (a mutex guards the counters); enabling it adds two event
- * records per launch.
+ * Kernel timing, for benchmarks (off by default). uot_profile_enable(period): 0 disables;
+ * period >= 1 brackets every period-th softmin launch of uot_sinkhorn / uot_ti_sinkhorn
+ * (counted process-wide) with two HIP events recorded on the call's stream, and accumulates
+ * its duration, with the number of cost entries it processed, per kernel kind:
+ * 0 = points-cost softmin, 1 = stored-cost column softmin, 2 = stored-cost row softmin.
+ * Each event record idles the GPU for a few microseconds, so a period above 1 keeps the
+ * timed launches a sample of an otherwise undisturbed run (an odd period samples both
+ * half-steps). Thread-safe (a mutex guards the counters).
  *  uot_profile_read returns the number of timed launches of `kind` (-1 for a bad kind) and
  *  writes the summed milliseconds and summed entries (host pointers, may be NULL).
  */
-void uot_profile_enable(int32_t on);
+void uot_profile_enable(int32_t period);
 void uot_profile_reset(void);
 int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries);
 
 /*
  * Implementation of the squared-Euclidean (p = 2) points softmin, process-wide:
- * 0 = default (matrix cores, one 32-target tile per wave), 1 = vector ALU, 2 = matrix
- * cores with one 32-target tile per wave, 3 = matrix cores with two. Returns the previous
- * setting, or -1 for an unknown value (then nothing changes). Both compute the same
- * softmin; the switch exists for benchmarks and must not be changed while calls are
+ * 0 = default (3 up to dimension 16, 2 above), 1 = vector ALU, 2 = matrix cores on the
+ * float32 exponent, 3 = matrix cores on the exponent split into bf16 pieces (three per
+ * float32 value, float32 accuracy; dimensions up to 16, 2 above). Returns the previous
+ * setting, or -1 for an unknown value (then nothing changes). All compute the same softmin;
+ * the switch exists for tests and benchmarks and must not be changed while calls are
  * running.
  */
 int32_t uot_set_points_kernel(int32_t variant);

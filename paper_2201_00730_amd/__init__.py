@@ -188,9 +188,10 @@ class _CostRef:
 PROFILE_POINTS, PROFILE_DENSE_COLS, PROFILE_DENSE_ROWS = 0, 1, 2
 
 
-def profile_enable(on: bool = True):
-    """Time every softmin launch of the solvers with HIP events on the call's stream."""
-    load_library().uot_profile_enable(int(bool(on)))
+def profile_enable(on=True, period: int = 1):
+    """Time every `period`-th softmin launch of the solvers with HIP events on the call's
+    stream (on=False disables)."""
+    load_library().uot_profile_enable(int(period) if on else 0)
 
 
 def profile_reset():
@@ -204,7 +205,7 @@ def profile_read(kind: int):
     return int(n), ms.value, ent.value
 
 
-POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA, POINTS_KERNEL_MFMA2 = 0, 1, 2, 3
+POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA_F32, POINTS_KERNEL_MFMA_BF16 = 0, 1, 2, 3
 
 
 def set_points_kernel(variant: int) -> int:

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_terms(DualArgs a) {
   if (t < a.n) {
     double lse2 = combine_lse2(a.part, a.nsplit, a.n, t);
     float yc[D > 0 ? D : 1];
-    if constexpr (MODE == kSqEuc) lse2 -= a.sc * centred<D>(a.x, a.d, t, a.st->mu, yc);
+    if constexpr (is_sq(MODE)) lse2 -= a.sc * centred<D>(a.x, a.d, t, a.st->mu, yc);
     const double S = -lse2 / a.sc;
     const double w = a.alpha[t], f = a.f[t];
     if (w > 0.0) { mm = log(w) + (f - S) / a.eps; ms = 1.0; }
@@ -206,6 +206,19 @@ hipError_t dual_for(const DualArgs &a, int nb, hipStream_t s) {
         case 48: return FN<48, kPower>(__VA_ARGS__);                             \
         case 64: return FN<64, kPower>(__VA_ARGS__);                             \
       }                                                                          \
+    } else if ((MODE_) == kSqEucMx) {                                            \
+      switch (b_) {                                                              \
+        case 1: return FN<1, kSqEucMx>(__VA_ARGS__);                             \
+        case 2: return FN<2, kSqEucMx>(__VA_ARGS__);                             \
+        case 3: return FN<3, kSqEucMx>(__VA_ARGS__);                             \
+        case 4: return FN<4, kSqEucMx>(__VA_ARGS__);                             \
+        case 5: return FN<5, kSqEucMx>(__VA_ARGS__);                             \
+        case 6: return FN<6, kSqEucMx>(__VA_ARGS__);                             \
+        case 7: return FN<7, kSqEucMx>(__VA_ARGS__);                             \
+        case 8: return FN<8, kSqEucMx>(__VA_ARGS__);                             \
+        case 12: return FN<12, kSqEucMx>(__VA_ARGS__);                           \
+        case 16: return FN<16, kSqEucMx>(__VA_ARGS__);                           \
+      }                                                                          \
     }                                                                            \
     return hipErrorInvalidValue;                                                 \
   } while (0)
@@ -230,17 +243,6 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
 hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_center, dim3(1), dim3(kBlock), 0, s, x, n, y, m, d, st);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned *p, int n) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
-hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, n);
   return hipGetLastError();
 }
 

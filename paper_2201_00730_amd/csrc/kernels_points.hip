@@ -1,4 +1,5 @@
-// Points-cost softmin partials on the VALU (gfx950).
+// Points-cost softmin partials (gfx950): vector-ALU kernels for any p, matrix-core kernels
+// for p = 2 further below.
 //
 // For every target t and every split of the sources, one pass computes the log2-domain
 // running pair (max m_t, sum l_t) of 2^{v_ts}, where v_ts is the exponent of the softmin
@@ -14,7 +15,6 @@
 // tile, and each entry then costs one exp2.
 #include <cfloat>
 
-#include "uot_epilogue.cuh"
 #include "uot_internal.h"
 
 namespace uot {
@@ -151,228 +151,256 @@ hipError_t launch_mode(const PointsArgs &a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------------------
 // Squared-Euclidean costs on the matrix cores. The base-2 exponent of entry (s, t), shifted
-// by the running reference sigma_t of its target, is an augmented dot product plus a
-// per-column constant,
+// by the running reference sigma_t of its target, is a contraction plus a per-column
+// constant,
 //   v_ts - sigma_t = sum_{e < K} A_se B_et - sigma_t,
-//   A_s = (u_s[0..D-1], b_s, 0...),   B_t = (y_t - mu, 1, 0...),
-// a K = D+1 (rounded to even) contraction done by v_mfma_f32_32x32x2f32 with sources as the
-// 32 rows and targets as the 32 columns of each output tile; -sigma_t enters as the
-// accumulator input of the first k-slice (a register tile holding -sigma of each lane's
-// column), so it costs no contraction depth. The VALU then does one exp2 and one add per
-// entry. A_s comes from the source record; B_t is built in registers. Element e of k-slice ks
-// for lane half h is e = KS*h + ks, so the KS elements a lane needs from one record are
-// contiguous.
+// with sources as the 32 rows and targets as the 32 columns of each output tile; -sigma_t
+// enters as the accumulator input of the first instruction (a register tile holding -sigma
+// of each lane's column), so it costs no contraction depth. The VALU then does one exp2 and
+// one add per entry. A_s comes from the source record, B_t is built in registers. Two forms:
+//
+//  - float32 (F32Form): A_s = (u_s, b_s, 0...), B_t = (y_t - mu, 1, 0...), K = D+1 rounded to
+//    even, v_mfma_f32_32x32x2f32. Element e of k-slice j for lane half h is e = NJ*h + j.
+//  - bf16-split (Bf16Form): the slots of mx_slots() (three bf16 pieces per float32 value, six
+//    piece products per coordinate), v_mfma_f32_32x32x16_bf16, K = 16 per instruction. Lane
+//    half h of instruction j holds slots 16j + 8h .. 16j + 8h + 7. The bf16 matrix cores run
+//    beside the exp/add stream of the other waves, where the float32 ones take VALU cycles;
+//    the split keeps the float32 accuracy of the exponent.
 //
 // Each lane owns one target column (lane % 32) and 16 source rows of every tile. sigma_t is
 // shared by the two lanes of a column and is raised only when a tile's sum of 2^{v - sigma}
 // exceeds 2^64 in either lane (or at the column's first tile); otherwise the exponents are
-// used as they come out of the matrix core. The next tile's MFMAs are issued before the
-// current tile's exps (software pipelining); an accumulator computed with an older sigma is
-// corrected on the slow path.
+// used as they come out of the matrix core.
 // ---------------------------------------------------------------------------------------
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMfmaWaves = 4;  // waves per block
 
+// Centred coordinates of target t (zero beyond the true dimension and for t >= nt).
 template <int D>
-struct MfmaShape {
+__device__ __forceinline__ void target_coords(const PointsArgs &a, int t, float (&yc)[D]) {
+  const bool valid = t < a.nt;
+  const int tc = valid ? t : 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int kc = k < a.d ? k : 0;
+    const float v = a.tgt[(size_t)tc * a.d + kc] - (float)a.mu[kc];
+    yc[k] = (valid && k < a.d) ? v : 0.0f;
+  }
+}
+
+template <int D>
+struct F32Form {
   static constexpr int K = ((D + 1) + 1) / 2 * 2;  // augmented depth, even
-  static constexpr int KS = K / 2;                  // k-slices of the 32x32x2 instruction
-  static constexpr int SD = rec_stride(kSqEuc, D);
-  static constexpr int EB = D;                      // element holding b_s (A) / 1 (B)
-  static_assert(K <= SD, "record shorter than the contraction");
+  static constexpr int NJ = K / 2;                  // instructions per tile
+  static constexpr int RS = rec_stride(kSqEuc, D);  // record stride (floats)
+  static_assert(K <= RS, "record shorter than the contraction");
+  typedef float Frag;
+
+  static __device__ __forceinline__ float elem(const float (&yc)[D], int e) {
+    return e < D ? yc[e] : (e == D ? 1.0f : 0.0f);
+  }
+  static __device__ __forceinline__ void build_b(const float (&yc)[D], int h, Frag (&b)[NJ]) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) b[j] = h ? elem(yc, NJ + j) : elem(yc, j);
+  }
+  // record elements [NJ*h, NJ*h + NJ) of source row `col` of the tile at `tile`
+  static __device__ __forceinline__ void load_a(const float *tile, int col, int h, Frag (&af)[NJ]) {
+    const float *rp = tile + col * RS + NJ * h;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) af[j] = rp[j];
+  }
+  static __device__ __forceinline__ f32x16 mma(const Frag (&af)[NJ], const Frag (&b)[NJ],
+                                               const f32x16 &c) {
+    f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[0], b[0], c, 0, 0, 0);
+#pragma unroll
+    for (int j = 1; j < NJ; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[j], b[j], acc, 0, 0, 0);
+    return acc;
+  }
 };
 
-template <int D, int TJ, bool FUSE>
-__global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a, FusedTail fz) {
+template <int D>
+struct Bf16Form {
+  static constexpr int KP = mx_slots(D);
+  static constexpr int NJ = KP / 16;                  // instructions per tile
+  static constexpr int RS = rec_stride(kSqEucMx, D);  // record stride (floats)
+  typedef bf16x8 Frag;
+
+  static __device__ __forceinline__ __bf16 elem(const __bf16 (&yp)[D][3], int e) {
+    return e < 6 * D ? yp[e / 6][mx_piece_y(e % 6)] : (e < 6 * D + 3 ? (__bf16)1.0f : (__bf16)0.0f);
+  }
+  static __device__ __forceinline__ void build_b(const float (&yc)[D], int h, Frag (&b)[NJ]) {
+    __bf16 yp[D][3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) split3(yc[k], yp[k][0], yp[k][1], yp[k][2]);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) b[j][i] = h ? elem(yp, 16 * j + 8 + i) : elem(yp, 16 * j + i);
+  }
+  // slots [16j + 8h, 16j + 8h + 8) of source row `col` for every instruction j
+  static __device__ __forceinline__ void load_a(const float *tile, int col, int h, Frag (&af)[NJ]) {
+    const Frag *rp = reinterpret_cast<const Frag *>(tile + col * RS) + h;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) af[j] = rp[2 * j];
+  }
+  static __device__ __forceinline__ f32x16 mma(const Frag (&af)[NJ], const Frag (&b)[NJ],
+                                               const f32x16 &c) {
+    f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], b[0], c, 0, 0, 0);
+#pragma unroll
+    for (int j = 1; j < NJ; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[j], b[j], acc, 0, 0, 0);
+    return acc;
+  }
+};
+
+template <int D, typename Form>
+__global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
   if (a.done != nullptr && *a.done) return;
-  using S = MfmaShape<D>;
-  constexpr int KS = S::KS, SD = S::SD;
+  constexpr int NJ = Form::NJ, RS = Form::RS;
+  typedef typename Form::Frag Frag;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = lane & 31;
   const int h = lane >> 5;
-  const int tbase = (blockIdx.x * kMfmaWaves + wave) * (32 * TJ);
+  const int t = (blockIdx.x * kMfmaWaves + wave) * 32 + col;
 
-  // B fragments: element e = KS*h + ks of (y - mu, 1, 0...)
-  float bf[TJ][KS];
-#pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) {
-    const int t = tbase + tj * 32 + col;
-    const bool valid = t < a.nt;
-    const int tc = valid ? t : 0;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int e = KS * h + ks;
-      const int ec = e < a.d ? e : 0;
-      const float coord = a.tgt[(size_t)tc * a.d + ec] - (float)a.mu[ec];
-      bf[tj][ks] = (e < D) ? ((valid && e < a.d) ? coord : 0.0f) : (e == S::EB ? 1.0f : 0.0f);
-    }
+  Frag bf[NJ];
+  {
+    float yc[D];
+    target_coords<D>(a, t, yc);
+    Form::build_b(yc, h, bf);
   }
 
   const int s0 = blockIdx.y * a.split_len;
   const int s1 = min(a.ns, s0 + a.split_len);
+  // Tiles end at s1 or at the padded end of the record array, whose pad records carry
+  // b = -inf (weight 0), so no source needs a mask.
+  auto load_a = [&](int sb, Frag (&af)[NJ]) { Form::load_a(a.rec + (size_t)sb * RS, col, h, af); };
 
-  // A fragments of the tile starting at sb: record elements [KS*h, KS*h + KS) (in bounds since
-  // K <= SD). Tiles end at s1 or at the padded end of the record array, whose pad records
-  // carry b = -inf (weight 0), so no source needs a mask.
-  auto load_a = [&](int sb, float *af) {
-    const float *rp = a.rec + (size_t)(sb + col) * SD + KS * h;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) af[ks] = rp[ks];
-  };
-  float sig[TJ], l[TJ];  // running reference and sum of 2^{v - sig} (this lane's rows)
-  bool started[TJ];
-#pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) { sig[tj] = 0.0f; l[tj] = 0.0f; started[tj] = false; }
+  float sig = 0.0f, l = 0.0f;  // running reference and sum of 2^{v - sig} (this lane's rows)
+  bool started = false;
 
-  // Re-centres column tile tj on its largest exponent and adds it (all lanes; exact for any
-  // column). acc was computed with the current sig.
-  auto recentre = [&](const f32x16 &acc, int tj) {
+  // Re-centres the tile on its column maximum and adds it (all lanes; exact for any column).
+  // acc was computed with the current sig.
+  auto recentre = [&](const f32x16 &acc) {
     float tm = acc[0];
 #pragma unroll
     for (int r = 1; r < 16; ++r) tm = fmaxf(tm, acc[r]);
     tm = fmaxf(tm, __shfl_xor(tm, 32, 64));
     if (tm > -INFINITY) {
-      const float delta = started[tj] ? fmaxf(tm, 0.0f) : tm;
+      const float delta = started ? fmaxf(tm, 0.0f) : tm;
       float t2 = 0.0f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) t2 += fast_exp2(acc[r] - delta);
       // first tile: no rescale (delta may be far below -126 and 0 * 2^{-delta} is NaN)
-      l[tj] = started[tj] ? l[tj] * fast_exp2(-delta) + t2 : t2;
-      sig[tj] += delta;
-      started[tj] = true;
+      l = started ? l * fast_exp2(-delta) + t2 : t2;
+      sig += delta;
+      started = true;
     }
   };
 
-  // Tiles of 32 sources; the next tile's records are prefetched while this tile's exps run,
-  // and the waves resident on the SIMD cover each other's matrix-core latency. The inner
-  // loop is the fast path, where -sig (the accumulator input) is loop-invariant; a tile that
-  // would overflow the sums, or a column not yet started, leaves it for recentre().
-  float an[KS], ac[KS];
-  load_a(s0, an);
+  // Adds the tile in acc to l unless it would overflow the sum (wave-uniform answer).
+  auto fast_add = [&](const f32x16 &acc) {
+    float q0 = fast_exp2(acc[0]), q1 = fast_exp2(acc[1]);
+    float q2 = fast_exp2(acc[2]), q3 = fast_exp2(acc[3]);
+#pragma unroll
+    for (int r = 4; r < 16; r += 4) {
+      q0 += fast_exp2(acc[r]);
+      q1 += fast_exp2(acc[r + 1]);
+      q2 += fast_exp2(acc[r + 2]);
+      q3 += fast_exp2(acc[r + 3]);
+    }
+    const float ts = (q0 + q1) + (q2 + q3);
+    if (__any(!(ts <= 0x1p64f))) return false;
+    l += ts;
+    return true;
+  };
+
+  // The next tile's records are prefetched while this tile's exps run (two fragment buffers
+  // used in turn), and the waves resident on the SIMD cover each other's matrix-core
+  // latency. The inner loop is the fast path, where -sig (the accumulator input) is
+  // loop-invariant; a tile that would overflow the sum, or a column not yet started, leaves
+  // it for recentre().
+  Frag fa[NJ], fb[NJ];
+  load_a(s0, fa);
   int sb = s0;
   while (sb < s1) {
-    f32x16 nsig[TJ];
+    f32x16 nsig;
 #pragma unroll
-    for (int tj = 0; tj < TJ; ++tj)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) nsig[tj][r] = -sig[tj];
-    bool all_started = true;
-#pragma unroll
-    for (int tj = 0; tj < TJ; ++tj) all_started = all_started && __all(started[tj]);
-    f32x16 acc[TJ];
-    bool slow = false;
-    for (; sb < s1; sb += 32) {
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) ac[ks] = an[ks];
-      if (sb + 32 < s1) load_a(sb + 32, an);
-#pragma unroll
-      for (int tj = 0; tj < TJ; ++tj) {
-        acc[tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[0], bf[tj][0], nsig[tj], 0, 0, 0);
-#pragma unroll
-        for (int ks = 1; ks < KS; ++ks)
-          acc[tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[ks], bf[tj][ks], acc[tj], 0, 0, 0);
-      }
-      if (!all_started) { slow = true; break; }
-      float ts[TJ];
-      bool ok = true;
-#pragma unroll
-      for (int tj = 0; tj < TJ; ++tj) {
-        float q0 = fast_exp2(acc[tj][0]), q1 = fast_exp2(acc[tj][1]);
-        float q2 = fast_exp2(acc[tj][2]), q3 = fast_exp2(acc[tj][3]);
-#pragma unroll
-        for (int r = 4; r < 16; r += 4) {
-          q0 += fast_exp2(acc[tj][r]);
-          q1 += fast_exp2(acc[tj][r + 1]);
-          q2 += fast_exp2(acc[tj][r + 2]);
-          q3 += fast_exp2(acc[tj][r + 3]);
-        }
-        ts[tj] = (q0 + q1) + (q2 + q3);
-        ok = ok && !__any(!(ts[tj] <= 0x1p64f));
-      }
-      if (!ok) { slow = true; break; }
-#pragma unroll
-      for (int tj = 0; tj < TJ; ++tj) l[tj] += ts[tj];
+    for (int r = 0; r < 16; ++r) nsig[r] = -sig;
+    const bool all_started = __all(started);
+    f32x16 acc;
+    bool slow = false, next_in_b = false;
+    for (;;) {
+      // tile sb in fa
+      if (sb + 32 < s1) load_a(sb + 32, fb);
+      acc = Form::mma(fa, bf, nsig);
+      if (!all_started || !fast_add(acc)) { slow = true; next_in_b = true; break; }
+      sb += 32;
+      if (sb >= s1) break;
+      // tile sb in fb
+      if (sb + 32 < s1) load_a(sb + 32, fa);
+      acc = Form::mma(fb, bf, nsig);
+      if (!fast_add(acc)) { slow = true; break; }
+      sb += 32;
+      if (sb >= s1) break;
     }
     if (!slow) break;
-#pragma unroll
-    for (int tj = 0; tj < TJ; ++tj) recentre(acc[tj], tj);
+    recentre(acc);
     sb += 32;
+    if (next_in_b) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) fa[j] = fb[j];
+    }
   }
 
   // merge the two half-waves of each column (same sigma; sums add)
-#pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) {
-    const float lo = __shfl_xor(l[tj], 32, 64);
-    const float ll = l[tj] + lo;
-    const int t = tbase + tj * 32 + col;
-    if (h == 0 && t < a.nt)
-      a.part[(size_t)blockIdx.y * a.nt + t] = make_float2(ll > 0.0f ? sig[tj] : -FLT_MAX, ll);
-  }
-
-  if constexpr (FUSE) {
-    // The last of the gridDim.y split blocks of this tile to arrive merges the tile; no block
-    // waits for another.
-    // Every wave waits for its own partial stores to complete before the barrier (the
-    // barrier alone does not wait for them), so thread 0's release (L2 write-back) covers
-    // the whole block. Only the last block acquires (L2 invalidate): an invalidate in every
-    // block would evict the source records that the blocks still running stream.
-    __shared__ int s_last;
-    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const unsigned prev = atomicAdd(&fz.tile_ticket[blockIdx.x], 1u);
-      s_last = (prev == gridDim.y - 1u) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x == 0) fz.tile_ticket[blockIdx.x] = 0u;
-    constexpr int kTileTargets = kMfmaWaves * 32 * TJ;
-    combine_and_reduce<D, kSqEuc, 256 / kTileTargets>(fz.c, blockIdx.x * kTileTargets,
-                                                      blockIdx.x, gridDim.x);
-  }
+  const float ll = l + __shfl_xor(l, 32, 64);
+  if (h == 0 && t < a.nt)
+    a.part[(size_t)blockIdx.y * a.nt + t] = make_float2(ll > 0.0f ? sig : -FLT_MAX, ll);
 }
 
-
-template <int D, int TJ>
-hipError_t launch_mfma_tj(const PointsArgs &a, const FusedTail *fz, hipStream_t st) {
-  const int tpb = kMfmaWaves * 32 * TJ;
+template <int D, typename Form>
+hipError_t launch_mfma_form(const PointsArgs &a, hipStream_t st) {
+  constexpr int tpb = kMfmaWaves * 32;
   dim3 grid((a.nt + tpb - 1) / tpb, a.nsplit);
-  if (fz != nullptr)
-    hipLaunchKernelGGL((k_points_mfma<D, TJ, true>), grid, dim3(64 * kMfmaWaves), 0, st, a, *fz);
-  else
-    hipLaunchKernelGGL((k_points_mfma<D, TJ, false>), grid, dim3(64 * kMfmaWaves), 0, st, a,
-                       FusedTail{});
+  hipLaunchKernelGGL((k_points_mfma<D, Form>), grid, dim3(64 * kMfmaWaves), 0, st, a);
   return hipGetLastError();
 }
 
-template <int D>
-hipError_t launch_mfma_bucket(const PointsArgs &a, const FusedTail *fz, hipStream_t st) {
-  return mfma_tiles_per_wave() == 2 ? launch_mfma_tj<D, 2>(a, fz, st)
-                                    : launch_mfma_tj<D, 1>(a, fz, st);
+#define UOT_MFMA_BUCKETS_LO(FN, FORM, ...)         \
+  switch (dim_bucket(a.d)) {                        \
+    case 1: return FN<1, FORM<1>>(__VA_ARGS__);     \
+    case 2: return FN<2, FORM<2>>(__VA_ARGS__);     \
+    case 3: return FN<3, FORM<3>>(__VA_ARGS__);     \
+    case 4: return FN<4, FORM<4>>(__VA_ARGS__);     \
+    case 5: return FN<5, FORM<5>>(__VA_ARGS__);     \
+    case 6: return FN<6, FORM<6>>(__VA_ARGS__);     \
+    case 7: return FN<7, FORM<7>>(__VA_ARGS__);     \
+    case 8: return FN<8, FORM<8>>(__VA_ARGS__);     \
+    case 12: return FN<12, FORM<12>>(__VA_ARGS__);  \
+    case 16: return FN<16, FORM<16>>(__VA_ARGS__);  \
+    default: break;                                 \
+  }
+#define UOT_MFMA_BUCKETS_HI(FN, FORM, ...)         \
+  switch (dim_bucket(a.d)) {                        \
+    case 24: return FN<24, FORM<24>>(__VA_ARGS__);  \
+    case 32: return FN<32, FORM<32>>(__VA_ARGS__);  \
+    case 48: return FN<48, FORM<48>>(__VA_ARGS__);  \
+    case 64: return FN<64, FORM<64>>(__VA_ARGS__);  \
+    default: break;                                 \
+  }
+
+hipError_t launch_mfma_f32(const PointsArgs &a, hipStream_t st) {
+  UOT_MFMA_BUCKETS_LO(launch_mfma_form, F32Form, a, st)
+  UOT_MFMA_BUCKETS_HI(launch_mfma_form, F32Form, a, st)
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma(const PointsArgs &a, const FusedTail *fz, hipStream_t st) {
-  switch (dim_bucket(a.d)) {
-    case 1: return launch_mfma_bucket<1>(a, fz, st);
-    case 2: return launch_mfma_bucket<2>(a, fz, st);
-    case 3: return launch_mfma_bucket<3>(a, fz, st);
-    case 4: return launch_mfma_bucket<4>(a, fz, st);
-    case 5: return launch_mfma_bucket<5>(a, fz, st);
-    case 6: return launch_mfma_bucket<6>(a, fz, st);
-    case 7: return launch_mfma_bucket<7>(a, fz, st);
-    case 8: return launch_mfma_bucket<8>(a, fz, st);
-    case 12: return launch_mfma_bucket<12>(a, fz, st);
-    case 16: return launch_mfma_bucket<16>(a, fz, st);
-    case 24: return launch_mfma_bucket<24>(a, fz, st);
-    case 32: return launch_mfma_bucket<32>(a, fz, st);
-    case 48: return launch_mfma_bucket<48>(a, fz, st);
-    case 64: return launch_mfma_bucket<64>(a, fz, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_mfma_bf16(const PointsArgs &a, hipStream_t st) {
+  UOT_MFMA_BUCKETS_LO(launch_mfma_form, Bf16Form, a, st)
+  return hipErrorInvalidValue;
 }
 
 template <typename Kern>
@@ -385,11 +413,14 @@ int occupancy_blocks(Kern kern) {
   return nb;
 }
 
+template <int D, typename Form>
+int mfma_occupancy(const PointsArgs &a) {
+  (void)a;
+  return occupancy_blocks(k_points_mfma<D, Form>);
+}
+
 template <int D>
-int points_blocks_per_cu_bucket(int mode) {
-  if (mode == kSqEuc && g_points_variant != kPointsValu)
-    return mfma_tiles_per_wave() == 2 ? occupancy_blocks(k_points_mfma<D, 2, true>)
-                                      : occupancy_blocks(k_points_mfma<D, 1, true>);
+int valu_occupancy(int mode) {
   constexpr int R = targets_per_thread<D>();
   return mode == kSqEuc ? occupancy_blocks(k_points_partial<D, kSqEuc, R>)
                         : occupancy_blocks(k_points_partial<D, kPower, R>);
@@ -399,55 +430,59 @@ int points_blocks_per_cu_bucket(int mode) {
 
 int g_points_variant = kPointsAuto;
 
+int points_record_mode(int mode, int d) {
+  if (mode != kSqEuc) return mode;
+  const bool bf16 = g_points_variant == kPointsAuto || g_points_variant == kPointsMfmaBf16;
+  return (bf16 && dim_bucket(d) <= kMxMaxDim) ? kSqEucMx : kSqEuc;
+}
+
+bool points_uses_mfma(int mode, int d) {
+  (void)d;
+  return mode == kSqEucMx || (mode == kSqEuc && g_points_variant != kPointsValu);
+}
+
 int points_blocks_per_cu(int mode, int d) {
+  PointsArgs a{};
+  a.d = d;
+  if (mode == kSqEucMx) {
+    UOT_MFMA_BUCKETS_LO(mfma_occupancy, Bf16Form, a)
+    return 0;
+  }
+  if (points_uses_mfma(mode, d)) {
+    UOT_MFMA_BUCKETS_LO(mfma_occupancy, F32Form, a)
+    UOT_MFMA_BUCKETS_HI(mfma_occupancy, F32Form, a)
+    return 0;
+  }
   switch (dim_bucket(d)) {
-    case 1: return points_blocks_per_cu_bucket<1>(mode);
-    case 2: return points_blocks_per_cu_bucket<2>(mode);
-    case 3: return points_blocks_per_cu_bucket<3>(mode);
-    case 4: return points_blocks_per_cu_bucket<4>(mode);
-    case 5: return points_blocks_per_cu_bucket<5>(mode);
-    case 6: return points_blocks_per_cu_bucket<6>(mode);
-    case 7: return points_blocks_per_cu_bucket<7>(mode);
-    case 8: return points_blocks_per_cu_bucket<8>(mode);
-    case 12: return points_blocks_per_cu_bucket<12>(mode);
-    case 16: return points_blocks_per_cu_bucket<16>(mode);
-    case 24: return points_blocks_per_cu_bucket<24>(mode);
-    case 32: return points_blocks_per_cu_bucket<32>(mode);
-    case 48: return points_blocks_per_cu_bucket<48>(mode);
-    case 64: return points_blocks_per_cu_bucket<64>(mode);
+    case 1: return valu_occupancy<1>(mode);
+    case 2: return valu_occupancy<2>(mode);
+    case 3: return valu_occupancy<3>(mode);
+    case 4: return valu_occupancy<4>(mode);
+    case 5: return valu_occupancy<5>(mode);
+    case 6: return valu_occupancy<6>(mode);
+    case 7: return valu_occupancy<7>(mode);
+    case 8: return valu_occupancy<8>(mode);
+    case 12: return valu_occupancy<12>(mode);
+    case 16: return valu_occupancy<16>(mode);
+    case 24: return valu_occupancy<24>(mode);
+    case 32: return valu_occupancy<32>(mode);
+    case 48: return valu_occupancy<48>(mode);
+    case 64: return valu_occupancy<64>(mode);
     default: return 0;
   }
 }
 
-// 32-target column tiles per wave of the matrix-core kernel.
-int mfma_tiles_per_wave() { return g_points_variant == kPointsMfma2 ? 2 : 1; }
-
-bool points_uses_mfma(int mode, int d) {
-  (void)d;
-  if (mode != kSqEuc) return false;
-  return g_points_variant != kPointsValu;
-}
-
 int points_targets_per_block(int mode, int d) {
-  if (points_uses_mfma(mode, d)) return kMfmaWaves * 32 * mfma_tiles_per_wave();
+  if (points_uses_mfma(mode, d)) return kMfmaWaves * 32;
   const int b = dim_bucket(d);
   return 256 * (b <= 4 ? 4 : (b <= 8 ? 2 : 1));
-}
-
-int points_fused_tiles(int nt) {
-  const int tpb = kMfmaWaves * 32 * mfma_tiles_per_wave();
-  return (nt + tpb - 1) / tpb;
-}
-
-hipError_t launch_points_fused(const PointsArgs &a, const FusedTail &f, hipStream_t st) {
-  if (!points_uses_mfma(kSqEuc, a.d)) return hipErrorInvalidValue;
-  return launch_mfma(a, &f, st);
 }
 
 int points_split_align(int mode, int d) { return points_uses_mfma(mode, d) ? 32 : 8; }
 
 hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st) {
-  if (points_uses_mfma(mode, a.d)) return launch_mfma(a, nullptr, st);
+  if (mode == kSqEucMx) return launch_mfma_bf16(a, st);
+  if (points_uses_mfma(mode, a.d)) return launch_mfma_f32(a, st);
   if (mode == kSqEuc) return launch_mode<kSqEuc>(a, st);
   if (mode == kPower) return launch_mode<kPower>(a, st);
   return hipErrorInvalidValue;

@@ -3,6 +3,7 @@
 // and the envelope backward. Every entry point is extern "C" and declared in uot.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -47,9 +48,15 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// How kernels form C: the cost mode of the apply kernels.
 int mode_of(const uot_cost *c) {
   if (c->kind == UOT_COST_DENSE) return kDense;
   return c->p == 2.0 ? kSqEuc : kPower;
+}
+
+// Mode of the source records and softmin kernels of the solver and the dual value.
+int rec_mode_of(const uot_cost *c) {
+  return points_record_mode(mode_of(c), c->kind == UOT_COST_POINTS ? c->d : 0);
 }
 
 uot_status check_cost(const uot_cost *c) {
@@ -165,18 +172,23 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
 }
 
 struct Layout {
-  size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0, tickets = 0;
-  int ntickets = 0;
+  size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0;
   size_t dual = 0, rowsum_x = 0, rowsum_y = 0, tmp_x = 0, tmp_y = 0, scratch = 0, total = 0;
   HalfShape g, f;  // g-step: targets y (columns), sources x; f-step: targets x (rows), sources y
 };
 
 Layout make_layout(const uot_cost *c, int which) {
   Layout L;
-  const int mode = mode_of(c);
+  const int mode = rec_mode_of(c);
   const int d = c->kind == UOT_COST_POINTS ? c->d : 0;
   const int n = c->n, m = c->m;
-  const int stride = rec_stride_for(mode, d);
+  // records sized for either p = 2 record form, so the size does not depend on the
+  // points-kernel setting
+  int stride = rec_stride_for(mode, d);
+  if (is_sq(mode) && dim_bucket(d) <= kMxMaxDim) {
+    const int a = rec_stride_for(kSqEuc, d), b = rec_stride_for(kSqEucMx, d);
+    stride = a > b ? a : b;
+  }
   L.g = half_shape(mode, d, m, n, false);
   L.f = half_shape(mode, d, n, m, true);
   size_t off = 0;
@@ -199,9 +211,6 @@ Layout make_layout(const uot_cost *c, int which) {
   const int nrec = (rec_count(nmax) + kBlock - 1) / kBlock;
   const int nbp = combine_blocks(nmax) > nrec ? combine_blocks(nmax) : nrec;
   L.bparts = take((size_t)(nbp + 1) * sizeof(BlockPart));
-  // one counter per target tile of the fused softmin (tiles of at least 32 targets)
-  L.ntickets = (nmax + 31) / 32;
-  L.tickets = take((size_t)L.ntickets * sizeof(unsigned));
   L.dual = take((size_t)((nmax + kBlock - 1) / kBlock + 1) * 6 * sizeof(double));
   if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
     L.rowsum_x = take((size_t)n * sizeof(float));
@@ -278,16 +287,24 @@ struct ProfAcc {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_prof_period = 1;          // time every g_prof_period-th softmin launch
+std::atomic<int64_t> g_prof_count{0};
 ProfAcc g_prof[kProfKinds];
 
 // Event pairs of one call, drained into g_prof when the ring wraps and at the end.
 class Timer {
  public:
-  explicit Timer(bool on) : on_(on) {}
+  explicit Timer(bool on) : on_(on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    period_ = g_prof_period;
+  }
   ~Timer() { drain(); for (auto &p : ring_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); } }
   bool on() const { return on_; }
   hipError_t begin(hipStream_t s) {
+    sampled_ = false;
     if (!on_) return hipSuccess;
+    if (g_prof_count.fetch_add(1) % period_ != 0) return hipSuccess;
+    sampled_ = true;
     if (used_ == kRing) {
       hipError_t e = settle(head_);
       if (e != hipSuccess) return e;
@@ -304,7 +321,7 @@ class Timer {
     return hipEventRecord(ring_[cur_].a, s);
   }
   hipError_t end(hipStream_t s, int kind, double entries) {
-    if (!on_) return hipSuccess;
+    if (!on_ || !sampled_) return hipSuccess;
     ring_[cur_].kind = kind;
     ring_[cur_].entries = entries;
     ring_[cur_].live = true;
@@ -338,6 +355,8 @@ class Timer {
     return hipSuccess;
   }
   bool on_;
+  bool sampled_ = false;
+  int64_t period_ = 1;
   std::vector<Pair> ring_;
   size_t used_ = 0, head_ = 0, cur_ = 0;
 };
@@ -365,9 +384,7 @@ struct Ctx {
 // Softmin partials of one half-step into the part buffer.
 //   g_step: targets are the y side (columns of C), sources the x side with records rec_x;
 //   otherwise targets are the x side (rows of C), sources the y side with records rec_y.
-//   fused: the combine runs in the tail of the softmin kernel (matrix-core path only).
-uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done,
-                            const FusedTail *fused = nullptr) {
+uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
   const HalfShape &h = g_step ? k.L.g : k.L.f;
   float2 *part = at<float2>(k.ws, k.L.part);
   const float *rec_src = at<float>(k.ws, g_step ? k.L.rec_x : k.L.rec_y);
@@ -402,14 +419,11 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done,
     a.part = part;
     a.done = done;
     if (k.timer) UOT_HIP(k.timer->begin(k.s));
-    UOT_HIP(fused ? launch_points_fused(a, *fused, k.s) : launch_points_partial(k.mode, a, k.s));
+    UOT_HIP(launch_points_partial(k.mode, a, k.s));
     if (k.timer) UOT_HIP(k.timer->end(k.s, kProfPoints, (double)k.n * (double)k.m));
   }
   return UOT_OK;
 }
-
-// Solver half-steps on the matrix-core path run the combine inside the softmin kernel.
-bool fused_softmin(const Ctx &k) { return k.mode != kDense && points_uses_mfma(k.mode, k.d); }
 
 Epilogue epilogue_for(const Ctx &k, bool g_step) {
   const double e = k.eps, r1 = k.rho1, r2 = k.rho2;
@@ -433,6 +447,7 @@ Epilogue epilogue_for(const Ctx &k, bool g_step) {
 
 uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   SolveState *st = k.st();
+  UOT_TRY(softmin_partials(k, g_step, &st->done));
   const HalfShape &h = g_step ? k.L.g : k.L.f;
   CombineArgs ca;
   ca.part = at<float2>(k.ws, k.L.part);
@@ -462,14 +477,6 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
   ra.tol = tol;
   ra.check_every = check_every;
-  if (fused_softmin(k)) {
-    FusedTail fz;
-    fz.c = ca;
-    fz.c.red.nb = points_fused_tiles(ca.nt);
-    fz.tile_ticket = at<unsigned>(k.ws, k.L.tickets);
-    return softmin_partials(k, g_step, &st->done, &fz);
-  }
-  UOT_TRY(softmin_partials(k, g_step, &st->done));
   UOT_HIP(launch_combine(ca, k.s));
   return UOT_OK;
 }
@@ -526,7 +533,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   UOT_TRY(check_device_ptr(g, "g"));
   Ctx k;
   k.c = c;
-  k.mode = mode_of(c);
+  k.mode = rec_mode_of(c);
   k.d = c->kind == UOT_COST_POINTS ? c->d : 0;
   k.n = c->n;
   k.m = c->m;
@@ -551,8 +558,6 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
 
   // start: flags, centring, weights, records of x from f_0 (with Smin_alpha^rho1(f_0)), g = 0
   UOT_TRY(prepare(c, alpha, beta, st, k.s));
-  if (fused_softmin(k))
-    UOT_HIP(launch_zero_u32(at<unsigned>(k.ws, k.L.tickets), k.L.ntickets, k.s));
   int nbx = 0;
   UOT_TRY(build_records(k, true, P->warm_start ? f : nullptr, true, true, &nbx));
   ReduceArgs ri;
@@ -631,7 +636,7 @@ uot_status dual_value(const uot_cost *c, const float *alpha, const float *beta, 
   UOT_TRY(check_device_ptr(g, "g"));
   Ctx k;
   k.c = c;
-  k.mode = mode_of(c);
+  k.mode = rec_mode_of(c);
   k.d = c->kind == UOT_COST_POINTS ? c->d : 0;
   k.n = c->n;
   k.m = c->m;
@@ -1086,15 +1091,16 @@ uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *b
 }
 
 int32_t uot_set_points_kernel(int32_t variant) {
-  if (variant < uot::kPointsAuto || variant > uot::kPointsMfma2) return -1;
+  if (variant < uot::kPointsAuto || variant > uot::kPointsMfmaBf16) return -1;
   const int32_t prev = uot::g_points_variant;
   uot::g_points_variant = variant;
   return prev;
 }
 
-void uot_profile_enable(int32_t on) {
+void uot_profile_enable(int32_t period) {
   std::lock_guard<std::mutex> lk(uot::g_prof_mu);
-  uot::g_prof_on = on != 0;
+  uot::g_prof_on = period > 0;
+  uot::g_prof_period = period > 0 ? period : 1;
 }
 
 void uot_profile_reset(void) {

@@ -17,27 +17,44 @@ static __device__ __forceinline__ void lse_merge(double &m, double &s, double mo
   m = mn;
 }
 
-// Block-wide reduction of (lse max, lse sum, max, min) over 256 threads: lane shuffles within
-// each wave, then the four wave results through LDS.
+// Block-wide reduction over 256 threads of a log-sum-exp pair (mm, ms), meaning ms e^mm with
+// (-inf, 0) neutral, and of a (max, min) range. Maxima and minima go first (lane shuffles,
+// then the four wave results through LDS); the sums are then rescaled to the block maximum,
+// so the pair costs one exp per thread rather than one per merge level.
 static __device__ void block_reduce_part(double &mm, double &ms, double &dmx, double &dmn) {
   constexpr int kWaves = kBlock / 64;
   __shared__ double s[4][kWaves];
+  double m = mm, x = dmx, n = dmn;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    lse_merge(mm, ms, __shfl_xor(mm, o, 64), __shfl_xor(ms, o, 64));
-    dmx = fmax(dmx, __shfl_xor(dmx, o, 64));
-    dmn = fmin(dmn, __shfl_xor(dmn, o, 64));
+    m = fmax(m, __shfl_xor(m, o, 64));
+    x = fmax(x, __shfl_xor(x, o, 64));
+    n = fmin(n, __shfl_xor(n, o, 64));
   }
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { s[0][w] = mm; s[1][w] = ms; s[2][w] = dmx; s[3][w] = dmn; }
+  const bool lead = (threadIdx.x & 63) == 0;
+  if (lead) { s[0][w] = m; s[1][w] = x; s[2][w] = n; }
   __syncthreads();
-  mm = s[0][0]; ms = s[1][0]; dmx = s[2][0]; dmn = s[3][0];
+  m = s[0][0]; x = s[1][0]; n = s[2][0];
+#pragma unroll
   for (int k = 1; k < kWaves; ++k) {
-    lse_merge(mm, ms, s[0][k], s[1][k]);
-    dmx = fmax(dmx, s[2][k]);
-    dmn = fmin(dmn, s[3][k]);
+    m = fmax(m, s[0][k]);
+    x = fmax(x, s[1][k]);
+    n = fmin(n, s[2][k]);
   }
+  double v = (mm == -INFINITY) ? 0.0 : ms * exp(mm - m);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lead) s[3][w] = v;
   __syncthreads();
+  double sum = s[3][0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) sum += s[3][k];
+  __syncthreads();
+  mm = m;
+  ms = sum;
+  dmx = x;
+  dmn = n;
 }
 
 static __device__ double block_sum(double v) {
@@ -89,9 +106,22 @@ static __device__ __forceinline__ void write_record(float *rec, int t, const flo
 #pragma unroll
     for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
     rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
-    rp[D + 1] = 1.0f;  // multiplies -sigma_t in the matrix-core contraction
 #pragma unroll
-    for (int k = D + 2; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;  // padding read by MFMA
+    for (int k = D + 1; k < rec_stride(MODE, D); ++k) rp[k] = 0.0f;  // padding read by MFMA
+  } else if constexpr (MODE == kSqEucMx) {
+    constexpr int KP = mx_slots(D);
+    __bf16 up[D][3], bp[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) split3((float)(2.0 * sc * (double)yc[k]), up[k][0], up[k][1], up[k][2]);
+    split3((float)(sc * (double)hf + lw2 - sc * yn2), bp[0], bp[1], bp[2]);
+    auto slot = [&](int e) -> unsigned {
+      const __bf16 v = e < 6 * D ? up[e / 6][mx_piece_u(e % 6)]
+                       : e < 6 * D + 3 ? bp[e - 6 * D] : (__bf16)0.0f;
+      return (unsigned)__builtin_bit_cast(unsigned short, v);
+    };
+    unsigned *wp = reinterpret_cast<unsigned *>(rp);
+#pragma unroll
+    for (int e = 0; e < KP; e += 2) wp[e / 2] = slot(e) | (slot(e + 1) << 16);
   } else if constexpr (MODE == kPower) {
 #pragma unroll
     for (int k = 0; k < D; ++k) rp[k] = yc[k];
@@ -177,6 +207,14 @@ static __device__ void combine_range(const CombineArgs &a, int t_begin, double &
   const int sub = threadIdx.x % LANES;
   const int t = t_begin + threadIdx.x / LANES;
   const int tc = t < a.nt ? t : a.nt - 1;
+  // Everything the epilogue reads is loaded first, so that its latency overlaps the merge.
+  const float w = a.w[tc];
+  const float old = a.pot[tc];
+  const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
+  const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
+  float yc[D > 0 ? D : 1];
+  double yn2 = 0.0;
+  if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, tc, a.st->mu, yc);
   // log2-sum over the split partials: M + log2(sum_p l_p 2^{m_p - M}), one pass, the loads of
   // a batch of 8 partials issued together (this merge is latency bound)
   constexpr int kBatch = 8;
@@ -210,19 +248,12 @@ static __device__ void combine_range(const CombineArgs &a, int t_begin, double &
   dmn = INFINITY;
   if (sub == 0 && t < a.nt) {
     double lse2 = (double)M + log2((double)L);
-    float yc[D > 0 ? D : 1];
-    double yn2 = 0.0;
-    if constexpr (MODE != kDense) yn2 = centred<D>(a.tgt, a.d, t, a.st->mu, yc);
-    if constexpr (MODE == kSqEuc) lse2 -= a.sc * yn2;
+    if constexpr (is_sq(MODE)) lse2 -= a.sc * yn2;
     const double S = -lse2 / a.sc;  // softmin over the stored source potential
-    const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
-    const double s_src = a.ep.src_is_x ? a.st->sA : a.st->sB;
     const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
     const float hf = (float)hnew;
-    const float old = a.pot[t];
     a.pot[t] = hf;
     dmx = dmn = (double)hf - (double)old;
-    const float w = a.w[t];
     write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
     if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
     if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);

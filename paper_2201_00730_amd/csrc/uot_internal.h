@@ -12,17 +12,44 @@ namespace uot {
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2 = 0.6931471805599453094;
 constexpr int kMaxDim = 64;
-// s_waitcnt immediate that waits for every outstanding vector memory operation of the wave
-// (vmcnt 0; expcnt and lgkmcnt at their no-wait maxima), gfx9 encoding.
-constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr int kBlock = 256;  // threads per block of the O(N) kernels
 
 // How C is formed inside a kernel.
 enum CostMode : int {
-  kDense = 0,   // stored C (row-major, leading dimension ldc)
-  kSqEuc = 1,   // points, p = 2: expanded form |x|^2 + |y|^2 - 2<x,y> on centred points
-  kPower = 2,   // points, general p: direct differences, ||x - y||^p
+  kDense = 0,    // stored C (row-major, leading dimension ldc)
+  kSqEuc = 1,    // points, p = 2: expanded form |x|^2 + |y|^2 - 2<x,y> on centred points
+  kPower = 2,    // points, general p: direct differences, ||x - y||^p
+  kSqEucMx = 3,  // as kSqEuc, source records split into bf16 pieces for the matrix cores
 };
+__host__ __device__ constexpr bool is_sq(int mode) { return mode == kSqEuc || mode == kSqEucMx; }
+
+// bf16-split form of the squared-Euclidean exponent. Each float32 value v is carried by three
+// bf16 pieces v = v0 + v1 + v2 (split3); the product u*y of a coordinate is carried by the six
+// piece products (0,0) (0,1) (1,0) (0,2) (2,0) (1,1), which leave out only terms of relative
+// size 2^-24 and below; b takes three slots against the constant 1. Slot 6k + r holds piece
+// mx_piece_u(r) of u_k (source side) and piece mx_piece_y(r) of y_k (target side); slots 6D,
+// 6D + 1, 6D + 2 hold b0, b1, b2 (target side: 1); the rest, up to a multiple of 16, are 0.
+__host__ __device__ constexpr int mx_slots(int D) { return (6 * D + 3 + 15) / 16 * 16; }
+__host__ __device__ constexpr int mx_piece_u(int r) {
+  return r == 2 ? 1 : r == 4 ? 2 : r == 5 ? 1 : 0;
+}
+__host__ __device__ constexpr int mx_piece_y(int r) {
+  return r == 1 ? 1 : r == 3 ? 2 : r == 5 ? 1 : 0;
+}
+constexpr int kMxMaxDim = 16;  // largest dimension bucket with bf16-split records
+
+// Splits v into bf16 pieces (round to nearest even) with v0 + v1 + v2 = v up to less than
+// 2^-24 |v|; each residual is exact in float32. A non-finite v gives (v, 0, 0).
+static __device__ inline void split3(float v, __bf16 &v0, __bf16 &v1, __bf16 &v2) {
+  v0 = (__bf16)v;
+  if (!__builtin_isfinite(v)) {
+    v1 = v2 = (__bf16)0.0f;
+    return;
+  }
+  const float r1 = v - (float)v0;
+  v1 = (__bf16)r1;
+  v2 = (__bf16)(r1 - (float)v1);
+}
 
 // Point dimensions are padded (with zero coordinates) up to one of the compiled buckets.
 __host__ __device__ constexpr int dim_bucket(int d) {
@@ -31,13 +58,12 @@ __host__ __device__ constexpr int dim_bucket(int d) {
 
 // Source-record stride in floats for a cost mode and a (bucketed) dimension D. A source
 // record holds what a softmin needs of one source point: D coordinates (scaled for kSqEuc,
-// zero beyond the true dimension) then the log2-domain offset b; kSqEuc records continue
-// with the constant 1 of the matrix-core contraction and zeros up to an even length; dense
-// records hold b only.
+// zero beyond the true dimension) then the log2-domain offset b, zero-padded to a multiple
+// of 4 floats (16-byte aligned records; the matrix-core contraction reads the zeros);
+// kSqEucMx records hold the mx_slots(D) bf16 source-side slots instead (two per float);
+// dense records hold b only.
 __host__ __device__ constexpr int rec_stride(int mode, int D) {
-  return mode == kDense ? 1
-         : mode == kSqEuc ? ((((D + 2) + 1) / 2 * 2) + 3) / 4 * 4
-                          : ((D + 1 + 3) / 4) * 4;
+  return mode == kDense ? 1 : mode == kSqEucMx ? mx_slots(D) / 2 : ((D + 1 + 3) / 4) * 4;
 }
 __host__ __device__ constexpr int rec_stride_for(int mode, int d) {
   return rec_stride(mode, dim_bucket(d));
@@ -117,9 +143,15 @@ int points_split_align(int mode, int d);   // split lengths are multiples of thi
 int points_blocks_per_cu(int mode, int d);
 bool points_uses_mfma(int mode, int d);
 // Points-softmin kernel selection (process-wide): matrix cores for p = 2 unless forced.
-enum PointsVariant : int { kPointsAuto = 0, kPointsValu = 1, kPointsMfma = 2, kPointsMfma2 = 3 };
+// Auto: bf16-split matrix-core form up to dimension bucket kMxMaxDim, float32 matrix-core
+// form above it.
+enum PointsVariant : int {
+  kPointsAuto = 0, kPointsValu = 1, kPointsMfmaF32 = 2, kPointsMfmaBf16 = 3
+};
 extern int g_points_variant;
-int mfma_tiles_per_wave();  // 32-target column tiles per wave of the matrix-core kernel
+// Record mode of a points cost of mode kSqEuc / kPower and dimension d under the current
+// points-kernel setting (kSqEucMx when the bf16-split matrix-core kernel runs).
+int points_record_mode(int mode, int d);
 
 struct DenseArgs {
   const float *C;
@@ -173,18 +205,6 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
 int combine_blocks(int nt);
 
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
-
-// Matrix-core softmin with the combine fused into its tail: the last split block of each
-// target tile (per-tile ticket) merges that tile's partials and runs the epilogue, the last
-// tile reduces the scalars (c.red.nb = number of tiles). tile_ticket holds one zeroed counter
-// per tile; every launch leaves them zeroed again.
-struct FusedTail {
-  CombineArgs c;
-  unsigned *tile_ticket;
-};
-hipError_t launch_points_fused(const PointsArgs &a, const FusedTail &f, hipStream_t st);
-int points_fused_tiles(int nt);   // target tiles of the fused kernel (blocks along x)
-hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t st);
 
 // Build source records from a potential (solve start, dual value, plan, backward).
 struct RecordArgs {

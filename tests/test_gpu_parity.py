@@ -361,8 +361,8 @@ def test_points_kernels_agree(n, m, d):
     bound = max(TOL, 2.0 ** -24 * (d + 4) * span ** 2 / np.max(np.abs(r.f)))
     prev = uot.set_points_kernel(uot.POINTS_KERNEL_VALU)
     try:
-        for variant, tol in ((uot.POINTS_KERNEL_VALU, bound), (uot.POINTS_KERNEL_MFMA, TOL),
-                             (uot.POINTS_KERNEL_MFMA2, TOL)):
+        for variant, tol in ((uot.POINTS_KERNEL_VALU, bound), (uot.POINTS_KERNEL_MFMA_F32, TOL),
+                             (uot.POINTS_KERNEL_MFMA_BF16, TOL)):
             uot.set_points_kernel(variant)
             f, g, _ = run_gpu(pr, True, 15)
             assert rel_inf(f, r.f) < tol and rel_inf(g, r.g) < tol, (variant, rel_inf(f, r.f), tol)
