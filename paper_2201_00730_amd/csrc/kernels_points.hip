@@ -154,15 +154,17 @@ hipError_t launch_mode(const PointsArgs &a, hipStream_t st) {
 // by the running reference sigma_t of its target, is a contraction plus a per-column
 // constant,
 //   v_ts - sigma_t = sum_{e < K} A_se B_et - sigma_t,
-// with sources as the 32 rows and targets as the 32 columns of each output tile; -sigma_t
-// enters as the accumulator input of the first instruction (a register tile holding -sigma
-// of each lane's column), so it costs no contraction depth. The VALU then does one exp2 and
-// one add per entry. A_s comes from the source record, B_t is built in registers. Two forms:
+// with sources as the 32 rows and targets as the 32 columns of each output tile. The VALU
+// then does one exp2 and one add per entry. A_s comes from the source record, B_t is built in
+// registers. Two forms:
 //
 //  - float32 (F32Form): A_s = (u_s, b_s, 0...), B_t = (y_t - mu, 1, 0...), K = D+1 rounded to
-//    even, v_mfma_f32_32x32x2f32. Element e of k-slice j for lane half h is e = NJ*h + j.
+//    even, v_mfma_f32_32x32x2f32; -sigma_t enters as the accumulator input of the first
+//    instruction (a register tile holding -sigma of each lane's column), so it costs no
+//    contraction depth. Element e of k-slice j for lane half h is e = NJ*h + j.
 //  - bf16-split (Bf16Form): the slots of mx_slots() (three bf16 pieces per float32 value, six
-//    piece products per coordinate), v_mfma_f32_32x32x16_bf16, K = 16 per instruction. Lane
+//    piece products per coordinate; -sigma_t in two slots of the contraction, so the
+//    accumulator input is zero), v_mfma_f32_32x32x16_bf16, K = 16 per instruction. Lane
 //    half h of instruction j holds slots 16j + 8h .. 16j + 8h + 7. The bf16 matrix cores run
 //    beside the exp/add stream of the other waves, where the float32 ones take VALU cycles;
 //    the split keeps the float32 accuracy of the exponent.
@@ -195,6 +197,7 @@ struct F32Form {
   static constexpr int K = ((D + 1) + 1) / 2 * 2;  // augmented depth, even
   static constexpr int NJ = K / 2;                  // instructions per tile
   static constexpr int RS = rec_stride(kSqEuc, D);  // record stride (floats)
+  static constexpr bool kSigmaInB = false;          // -sigma enters as accumulator input
   static_assert(K <= RS, "record shorter than the contraction");
   typedef float Frag;
 
@@ -205,6 +208,8 @@ struct F32Form {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) b[j] = h ? elem(yc, NJ + j) : elem(yc, j);
   }
+  static __device__ __forceinline__ float representable(float sig) { return sig; }
+  static __device__ __forceinline__ void set_sigma(Frag (&)[NJ], float, int) {}
   // record elements [NJ*h, NJ*h + NJ) of source row `col` of the tile at `tile`
   static __device__ __forceinline__ void load_a(const float *tile, int col, int h, Frag (&af)[NJ]) {
     const float *rp = tile + col * RS + NJ * h;
@@ -225,6 +230,8 @@ struct Bf16Form {
   static constexpr int KP = mx_slots(D);
   static constexpr int NJ = KP / 16;                  // instructions per tile
   static constexpr int RS = rec_stride(kSqEucMx, D);  // record stride (floats)
+  static constexpr bool kSigmaInB = true;             // -sigma in slots ES0, ES1
+  static constexpr int ES0 = 6 * D + 3, ES1 = 6 * D + 4;
   typedef bf16x8 Frag;
 
   static __device__ __forceinline__ __bf16 elem(const __bf16 (&yp)[D][3], int e) {
@@ -238,6 +245,28 @@ struct Bf16Form {
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int i = 0; i < 8; ++i) b[j][i] = h ? elem(yp, 16 * j + 8 + i) : elem(yp, 16 * j + i);
+  }
+  // Nearest value at or below sig's two-piece rounding that the slots carry exactly:
+  // -(s0 + s1) with s0 = bf16(-sig), s1 = bf16(-sig - s0) (the sum is exact in float32).
+  static __device__ __forceinline__ float representable(float sig) {
+    const __bf16 s0 = (__bf16)(-sig);
+    const __bf16 s1 = (__bf16)(-sig - (float)s0);
+    return -((float)s0 + (float)s1);
+  }
+  // Writes the pieces of -sig (sig representable) into the slots this lane half holds.
+  static __device__ __forceinline__ void set_sigma(Frag (&b)[NJ], float sig, int h) {
+    const __bf16 s0 = (__bf16)(-sig);
+    const __bf16 s1 = (__bf16)(-sig - (float)s0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e0 = 16 * j + i, e1 = e0 + 8;
+        if (e0 == ES0 || e0 == ES1 || e1 == ES0 || e1 == ES1) {
+          const int e = h ? e1 : e0;
+          b[j][i] = e == ES0 ? s0 : (e == ES1 ? s1 : b[j][i]);
+        }
+      }
   }
   // slots [16j + 8h, 16j + 8h + 8) of source row `col` for every instruction j
   static __device__ __forceinline__ void load_a(const float *tile, int col, int h, Frag (&af)[NJ]) {
@@ -289,14 +318,16 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
     for (int r = 1; r < 16; ++r) tm = fmaxf(tm, acc[r]);
     tm = fmaxf(tm, __shfl_xor(tm, 32, 64));
     if (tm > -INFINITY) {
-      const float delta = started ? fmaxf(tm, 0.0f) : tm;
+      const float ns = Form::representable(sig + (started ? fmaxf(tm, 0.0f) : tm));
+      const float delta = ns - sig;
       float t2 = 0.0f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) t2 += fast_exp2(acc[r] - delta);
       // first tile: no rescale (delta may be far below -126 and 0 * 2^{-delta} is NaN)
       l = started ? l * fast_exp2(-delta) + t2 : t2;
-      sig += delta;
+      sig = ns;
       started = true;
+      Form::set_sigma(bf, sig, h);
     }
   };
 
@@ -317,42 +348,31 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
     return true;
   };
 
-  // The next tile's records are prefetched while this tile's exps run (two fragment buffers
-  // used in turn), and the waves resident on the SIMD cover each other's matrix-core
-  // latency. The inner loop is the fast path, where -sig (the accumulator input) is
-  // loop-invariant; a tile that would overflow the sum, or a column not yet started, leaves
-  // it for recentre().
-  Frag fa[NJ], fb[NJ];
-  load_a(s0, fa);
+  // The next tile's records are prefetched while this tile's exps run, and the waves
+  // resident on the SIMD (eight at this register count) cover each other's matrix-core
+  // latency. The inner loop is the fast path, where the accumulator input (-sig, F32Form)
+  // and the B fragments (Bf16Form) are loop-invariant; a tile that would overflow the sum,
+  // or a column not yet started, leaves it for recentre(), which may move sig.
+  Frag an[NJ], ac[NJ];
+  load_a(s0, an);
   int sb = s0;
   while (sb < s1) {
-    f32x16 nsig;
+    f32x16 cin;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) nsig[r] = -sig;
+    for (int r = 0; r < 16; ++r) cin[r] = Form::kSigmaInB ? 0.0f : -sig;
     const bool all_started = __all(started);
     f32x16 acc;
-    bool slow = false, next_in_b = false;
-    for (;;) {
-      // tile sb in fa
-      if (sb + 32 < s1) load_a(sb + 32, fb);
-      acc = Form::mma(fa, bf, nsig);
-      if (!all_started || !fast_add(acc)) { slow = true; next_in_b = true; break; }
-      sb += 32;
-      if (sb >= s1) break;
-      // tile sb in fb
-      if (sb + 32 < s1) load_a(sb + 32, fa);
-      acc = Form::mma(fb, bf, nsig);
-      if (!fast_add(acc)) { slow = true; break; }
-      sb += 32;
-      if (sb >= s1) break;
+    bool slow = false;
+    for (; sb < s1; sb += 32) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) ac[j] = an[j];
+      if (sb + 32 < s1) load_a(sb + 32, an);
+      acc = Form::mma(ac, bf, cin);
+      if (!all_started || !fast_add(acc)) { slow = true; break; }
     }
     if (!slow) break;
     recentre(acc);
     sb += 32;
-    if (next_in_b) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) fa[j] = fb[j];
-    }
   }
 
   // merge the two half-waves of each column (same sigma; sums add)

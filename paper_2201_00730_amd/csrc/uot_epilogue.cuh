@@ -116,7 +116,8 @@ static __device__ __forceinline__ void write_record(float *rec, int t, const flo
     split3((float)(sc * (double)hf + lw2 - sc * yn2), bp[0], bp[1], bp[2]);
     auto slot = [&](int e) -> unsigned {
       const __bf16 v = e < 6 * D ? up[e / 6][mx_piece_u(e % 6)]
-                       : e < 6 * D + 3 ? bp[e - 6 * D] : (__bf16)0.0f;
+                       : e < 6 * D + 3 ? bp[e - 6 * D]
+                       : e < 6 * D + 5 ? (__bf16)1.0f : (__bf16)0.0f;
       return (unsigned)__builtin_bit_cast(unsigned short, v);
     };
     unsigned *wp = reinterpret_cast<unsigned *>(rp);

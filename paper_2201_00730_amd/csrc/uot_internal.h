@@ -26,10 +26,13 @@ __host__ __device__ constexpr bool is_sq(int mode) { return mode == kSqEuc || mo
 // bf16-split form of the squared-Euclidean exponent. Each float32 value v is carried by three
 // bf16 pieces v = v0 + v1 + v2 (split3); the product u*y of a coordinate is carried by the six
 // piece products (0,0) (0,1) (1,0) (0,2) (2,0) (1,1), which leave out only terms of relative
-// size 2^-24 and below; b takes three slots against the constant 1. Slot 6k + r holds piece
-// mx_piece_u(r) of u_k (source side) and piece mx_piece_y(r) of y_k (target side); slots 6D,
-// 6D + 1, 6D + 2 hold b0, b1, b2 (target side: 1); the rest, up to a multiple of 16, are 0.
-__host__ __device__ constexpr int mx_slots(int D) { return (6 * D + 3 + 15) / 16 * 16; }
+// size 2^-24 and below; b takes three slots against the constant 1, and the running reference
+// -sigma of a target two slots (two pieces; sigma is kept exactly representable by them)
+// against the constant 1 of the source side. Slot 6k + r holds piece mx_piece_u(r) of u_k
+// (source side) and piece mx_piece_y(r) of y_k (target side); slots 6D .. 6D + 2 hold
+// b0, b1, b2 (target side: 1); slots 6D + 3, 6D + 4 hold 1 (target side: the pieces of
+// -sigma); the rest, up to a multiple of 16 (the depth of one instruction), are 0.
+__host__ __device__ constexpr int mx_slots(int D) { return (6 * D + 5 + 15) / 16 * 16; }
 __host__ __device__ constexpr int mx_piece_u(int r) {
   return r == 2 ? 1 : r == 4 ? 2 : r == 5 ? 1 : 0;
 }
