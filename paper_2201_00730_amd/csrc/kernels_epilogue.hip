@@ -49,7 +49,7 @@ constexpr int kCombTargets = kBlock / kCombLanes;
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
   if (a.st->done) return;
-  combine_and_reduce<D, MODE, kCombLanes>(a, blockIdx.x * kCombTargets, blockIdx.x, gridDim.x);
+  combine_block<D, MODE, kCombLanes>(a, blockIdx.x * kCombTargets, blockIdx.x);
 }
 
 // Zeroes the flags of the state and computes the common mean of x and y (points costs).

@@ -464,7 +464,8 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ca.ep = epilogue_for(k, g_step);
   ca.sc = k.sc;
   ca.eps = k.eps;
-  ReduceArgs &ra = ca.red;
+  UOT_HIP(launch_combine(ca, k.s));
+  ReduceArgs ra;
   ra.bparts = ca.bparts;
   ra.nb = h.nb_combine;
   ra.st = st;
@@ -477,7 +478,7 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
   ra.tol = tol;
   ra.check_every = check_every;
-  UOT_HIP(launch_combine(ca, k.s));
+  UOT_HIP(launch_reduce(ra, k.s));
   return UOT_OK;
 }
 

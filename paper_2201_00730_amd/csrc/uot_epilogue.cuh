@@ -138,13 +138,19 @@ static __device__ __forceinline__ void write_record(float *rec, int t, const flo
 // one block of kBlock threads. Thread 0 writes the results.
 static __device__ void reduce_scalars(const ReduceArgs &a) {
   SolveState *st = a.st;
+  // this thread's partials: maxima first, then the mass sums rescaled to their maximum
   double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
   for (int b = threadIdx.x; b < a.nb; b += kBlock) {
     const BlockPart q = a.bparts[b];
-    lse_merge(mm, ms, q.mass_max, q.mass_sum);
+    mm = fmax(mm, q.mass_max);
     dmx = fmax(dmx, q.dmax);
     dmn = fmin(dmn, q.dmin);
   }
+  if (mm > -INFINITY)
+    for (int b = threadIdx.x; b < a.nb; b += kBlock) {
+      const BlockPart q = a.bparts[b];
+      if (q.mass_max > -INFINITY) ms += q.mass_sum * exp(q.mass_max - mm);
+    }
   block_reduce_part(mm, ms, dmx, dmn);
   if (threadIdx.x != 0) return;
   const double L = (mm == -INFINITY) ? -INFINITY : mm + log(ms);  // log of the tilted mass
@@ -261,26 +267,13 @@ static __device__ void combine_range(const CombineArgs &a, int t_begin, double &
   }
 }
 
-// combine_range over one block's targets, then the block partial into bparts[tile]; the last
-// of `ntiles` blocks to arrive (atomic ticket, no waiting) reduces all partials into the
-// scalar state and re-arms the ticket.
+// combine_range over one block's targets, then the block partial into bparts[tile].
 template <int D, int MODE, int LANES>
-static __device__ void combine_and_reduce(const CombineArgs &a, int t_begin, int tile, int ntiles) {
-  __shared__ int s_last;
+static __device__ void combine_block(const CombineArgs &a, int t_begin, int tile) {
   double mm, ms, dmx, dmn;
   combine_range<D, MODE, LANES>(a, t_begin, mm, ms, dmx, dmn);
   block_reduce_part(mm, ms, dmx, dmn);
-  if (threadIdx.x == 0) {
-    a.bparts[tile] = BlockPart{mm, ms, dmx, dmn};
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned prev = atomicAdd(&a.st->ticket, 1u);
-    s_last = (prev == (unsigned)ntiles - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  reduce_scalars(a.red);
-  if (threadIdx.x == 0) a.st->ticket = 0u;
+  if (threadIdx.x == 0) a.bparts[tile] = BlockPart{mm, ms, dmx, dmn};
 }
 
 }  // namespace uot

@@ -124,6 +124,19 @@ struct Epilogue {
 // ---------------------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files). All return hipError_t of the launch.
 // ---------------------------------------------------------------------------------------
+// Scalar reduction of a half-step (tilted masses, TI translations, lambda*, change,
+// convergence test) from its per-block partials.
+struct ReduceArgs {
+  const BlockPart *bparts;
+  int nb;
+  SolveState *st;
+  int kind;
+  int ti;
+  double rho1, rho2, kappa_t, tau1, tau2;
+  double tol;
+  int check_every;
+};
+
 struct PointsArgs {
   const float *rec;    // source records [ns, rec_stride]
   int ns;
@@ -174,16 +187,6 @@ int dense_cols_per_block();
 int dense_rows_per_block();
 
 enum ReduceKind : int { kReduceInit = 0, kReduceG = 1, kReduceF = 2 };
-struct ReduceArgs {
-  const BlockPart *bparts;
-  int nb;
-  SolveState *st;
-  int kind;
-  int ti;
-  double rho1, rho2, kappa_t, tau1, tau2;
-  double tol;
-  int check_every;
-};
 
 // Epilogue kernels (kernels_epilogue.hip).
 struct CombineArgs {
@@ -200,10 +203,11 @@ struct CombineArgs {
   Epilogue ep;
   double sc;           // log2(e)/eps (double)
   double eps;
-  ReduceArgs red;      // scalar reduction run by the last block to finish (bparts, st, kind...)
 };
 
-// Combine + epilogue + (in its last block) the scalar reduction of the half-step.
+// Combine + epilogue; each block writes its (tilted mass, change range) partial to bparts,
+// which launch_reduce then reduces into the scalar state (a one-block launch: cheaper than
+// an atomic ticket and a last-block reduction inside the combine).
 hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
 int combine_blocks(int nt);
 
