@@ -172,9 +172,8 @@ def main():
         print("warmup step %d done" % w, file=sys.stderr, flush=True)
 
     uot.profile_reset()
-    # every 15th softmin launch is bracketed by events (an odd period samples both half-steps;
-    # each event record idles the GPU for microseconds, so timing every launch would slow
-    # the timed run itself)
+    # every 15th softmin launch carries start/stop events on its dispatch (an odd period
+    # samples both half-steps; reading the events back synchronises when the ring wraps)
     uot.profile_enable(True, period=PROFILE_PERIOD)
     record = []
     torch.cuda.synchronize()

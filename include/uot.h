@@ -229,13 +229,14 @@ size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t
 
 /*
  * Kernel timing, for benchmarks (off by default). uot_profile_enable(period): 0 disables;
- * period >= 1 brackets every period-th softmin launch of uot_sinkhorn / uot_ti_sinkhorn
- * (counted process-wide) with two HIP events recorded on the call's stream, and accumulates
- * its duration, with the number of cost entries it processed, per kernel kind:
- * 0 = points-cost softmin, 1 = stored-cost column softmin, 2 = stored-cost row softmin.
- * Each event record idles the GPU for a few microseconds, so a period above 1 keeps the
- * timed launches a sample of an otherwise undisturbed run (an odd period samples both
- * half-steps). Thread-safe (a mutex guards the counters).
+ * period >= 1 times every period-th softmin launch of uot_sinkhorn / uot_ti_sinkhorn
+ * (counted process-wide) with start/stop HIP events attached to the kernel dispatch itself
+ * (hipExtLaunchKernel: no extra commands in the stream), and accumulates its duration, with
+ * the number of cost entries it processed, per kernel kind: 0 = points-cost softmin,
+ * 1 = stored-cost column softmin, 2 = stored-cost row softmin. Reading the events back
+ * synchronises with the timed launches when the event ring (512 pairs) wraps, so a period
+ * above 1 keeps a long solve asynchronous (an odd period samples both half-steps).
+ * Thread-safe (a mutex guards the counters).
  *  uot_profile_read returns the number of timed launches of `kind` (-1 for a bad kind) and
  *  writes the summed milliseconds and summed entries (host pointers, may be NULL).
  */

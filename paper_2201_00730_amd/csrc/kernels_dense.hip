@@ -166,25 +166,19 @@ __global__ __launch_bounds__(256) void k_dense_rows(DenseArgs a) {
 int dense_cols_per_block() { return 256 * kColsPerThread; }
 int dense_rows_per_block() { return 4 * kRowsPerWave; }
 
-hipError_t launch_dense_cols_partial(const DenseArgs &a, hipStream_t st) {
+hipError_t launch_dense_cols_partial(const DenseArgs &a, hipStream_t st, const LaunchTiming *t) {
   const bool vec = (reinterpret_cast<uintptr_t>(a.C) % 16 == 0) && (a.ldc % 4 == 0);
   dim3 grid((a.m + dense_cols_per_block() - 1) / dense_cols_per_block(), a.nsplit);
-  if (vec)
-    hipLaunchKernelGGL(k_dense_cols_partial<true>, grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_dense_cols_partial<false>, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
+  return vec ? launch_timed(k_dense_cols_partial<true>, grid, dim3(256), st, t, a)
+             : launch_timed(k_dense_cols_partial<false>, grid, dim3(256), st, t, a);
 }
 
-hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st) {
+hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st, const LaunchTiming *t) {
   const bool vec = (reinterpret_cast<uintptr_t>(a.C) % 16 == 0) && (a.ldc % 4 == 0) &&
                    (reinterpret_cast<uintptr_t>(a.rec) % 16 == 0);
   dim3 grid((a.n + dense_rows_per_block() - 1) / dense_rows_per_block());
-  if (vec)
-    hipLaunchKernelGGL(k_dense_rows<true>, grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_dense_rows<false>, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
+  return vec ? launch_timed(k_dense_rows<true>, grid, dim3(256), st, t, a)
+             : launch_timed(k_dense_rows<false>, grid, dim3(256), st, t, a);
 }
 
 }  // namespace uot

@@ -120,30 +120,29 @@ constexpr int targets_per_thread() {
 }
 
 template <int D, int MODE>
-hipError_t launch_bucket(const PointsArgs &a, hipStream_t st) {
+hipError_t launch_bucket(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
   constexpr int R = targets_per_thread<D>();
   dim3 grid((a.nt + 256 * R - 1) / (256 * R), a.nsplit);
-  hipLaunchKernelGGL((k_points_partial<D, MODE, R>), grid, dim3(256), 0, st, a);
-  return hipGetLastError();
+  return launch_timed(k_points_partial<D, MODE, R>, grid, dim3(256), st, t, a);
 }
 
 template <int MODE>
-hipError_t launch_mode(const PointsArgs &a, hipStream_t st) {
+hipError_t launch_mode(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
   switch (dim_bucket(a.d)) {
-    case 1: return launch_bucket<1, MODE>(a, st);
-    case 2: return launch_bucket<2, MODE>(a, st);
-    case 3: return launch_bucket<3, MODE>(a, st);
-    case 4: return launch_bucket<4, MODE>(a, st);
-    case 5: return launch_bucket<5, MODE>(a, st);
-    case 6: return launch_bucket<6, MODE>(a, st);
-    case 7: return launch_bucket<7, MODE>(a, st);
-    case 8: return launch_bucket<8, MODE>(a, st);
-    case 12: return launch_bucket<12, MODE>(a, st);
-    case 16: return launch_bucket<16, MODE>(a, st);
-    case 24: return launch_bucket<24, MODE>(a, st);
-    case 32: return launch_bucket<32, MODE>(a, st);
-    case 48: return launch_bucket<48, MODE>(a, st);
-    case 64: return launch_bucket<64, MODE>(a, st);
+    case 1: return launch_bucket<1, MODE>(a, st, t);
+    case 2: return launch_bucket<2, MODE>(a, st, t);
+    case 3: return launch_bucket<3, MODE>(a, st, t);
+    case 4: return launch_bucket<4, MODE>(a, st, t);
+    case 5: return launch_bucket<5, MODE>(a, st, t);
+    case 6: return launch_bucket<6, MODE>(a, st, t);
+    case 7: return launch_bucket<7, MODE>(a, st, t);
+    case 8: return launch_bucket<8, MODE>(a, st, t);
+    case 12: return launch_bucket<12, MODE>(a, st, t);
+    case 16: return launch_bucket<16, MODE>(a, st, t);
+    case 24: return launch_bucket<24, MODE>(a, st, t);
+    case 32: return launch_bucket<32, MODE>(a, st, t);
+    case 48: return launch_bucket<48, MODE>(a, st, t);
+    case 64: return launch_bucket<64, MODE>(a, st, t);
     default: return hipErrorInvalidValue;
   }
 }
@@ -382,11 +381,10 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
 }
 
 template <int D, typename Form>
-hipError_t launch_mfma_form(const PointsArgs &a, hipStream_t st) {
+hipError_t launch_mfma_form(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
   constexpr int tpb = kMfmaWaves * 32;
   dim3 grid((a.nt + tpb - 1) / tpb, a.nsplit);
-  hipLaunchKernelGGL((k_points_mfma<D, Form>), grid, dim3(64 * kMfmaWaves), 0, st, a);
-  return hipGetLastError();
+  return launch_timed(k_points_mfma<D, Form>, grid, dim3(64 * kMfmaWaves), st, t, a);
 }
 
 #define UOT_MFMA_BUCKETS_LO(FN, FORM, ...)         \
@@ -412,14 +410,14 @@ hipError_t launch_mfma_form(const PointsArgs &a, hipStream_t st) {
     default: break;                                 \
   }
 
-hipError_t launch_mfma_f32(const PointsArgs &a, hipStream_t st) {
-  UOT_MFMA_BUCKETS_LO(launch_mfma_form, F32Form, a, st)
-  UOT_MFMA_BUCKETS_HI(launch_mfma_form, F32Form, a, st)
+hipError_t launch_mfma_f32(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
+  UOT_MFMA_BUCKETS_LO(launch_mfma_form, F32Form, a, st, t)
+  UOT_MFMA_BUCKETS_HI(launch_mfma_form, F32Form, a, st, t)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_bf16(const PointsArgs &a, hipStream_t st) {
-  UOT_MFMA_BUCKETS_LO(launch_mfma_form, Bf16Form, a, st)
+hipError_t launch_mfma_bf16(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
+  UOT_MFMA_BUCKETS_LO(launch_mfma_form, Bf16Form, a, st, t)
   return hipErrorInvalidValue;
 }
 
@@ -500,11 +498,12 @@ int points_targets_per_block(int mode, int d) {
 
 int points_split_align(int mode, int d) { return points_uses_mfma(mode, d) ? 32 : 8; }
 
-hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st) {
-  if (mode == kSqEucMx) return launch_mfma_bf16(a, st);
-  if (points_uses_mfma(mode, a.d)) return launch_mfma_f32(a, st);
-  if (mode == kSqEuc) return launch_mode<kSqEuc>(a, st);
-  if (mode == kPower) return launch_mode<kPower>(a, st);
+hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st,
+                                 const LaunchTiming *t) {
+  if (mode == kSqEucMx) return launch_mfma_bf16(a, st, t);
+  if (points_uses_mfma(mode, a.d)) return launch_mfma_f32(a, st, t);
+  if (mode == kSqEuc) return launch_mode<kSqEuc>(a, st, t);
+  if (mode == kPower) return launch_mode<kPower>(a, st, t);
   return hipErrorInvalidValue;
 }
 

@@ -291,41 +291,50 @@ int g_prof_period = 1;          // time every g_prof_period-th softmin launch
 std::atomic<int64_t> g_prof_count{0};
 ProfAcc g_prof[kProfKinds];
 
-// Event pairs of one call, drained into g_prof when the ring wraps and at the end.
+// Event pairs of one call, drained into g_prof when the ring wraps and at the end. A sampled
+// softmin launch gets its start/stop events attached to the dispatch (hipExtLaunchKernel),
+// so they time the kernel itself and add no commands between kernels.
 class Timer {
  public:
   explicit Timer(bool on) : on_(on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     period_ = g_prof_period;
   }
-  ~Timer() { drain(); for (auto &p : ring_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); } }
-  bool on() const { return on_; }
-  hipError_t begin(hipStream_t s) {
-    sampled_ = false;
-    if (!on_) return hipSuccess;
-    if (g_prof_count.fetch_add(1) % period_ != 0) return hipSuccess;
-    sampled_ = true;
-    if (used_ == kRing) {
-      hipError_t e = settle(head_);
-      if (e != hipSuccess) return e;
-    } else if (ring_.size() < kRing) {
-      Pair p;
-      hipError_t e = hipEventCreate(&p.a);
-      if (e == hipSuccess) e = hipEventCreate(&p.b);
-      if (e != hipSuccess) return e;
-      ring_.push_back(p);
-      ++used_;
+  ~Timer() {
+    drain();
+    for (auto &p : ring_) {
+      (void)hipEventDestroy(p.t.start);
+      (void)hipEventDestroy(p.t.stop);
     }
-    cur_ = head_;
-    head_ = (head_ + 1) % kRing;
-    return hipEventRecord(ring_[cur_].a, s);
   }
-  hipError_t end(hipStream_t s, int kind, double entries) {
-    if (!on_ || !sampled_) return hipSuccess;
-    ring_[cur_].kind = kind;
-    ring_[cur_].entries = entries;
-    ring_[cur_].live = true;
-    return hipEventRecord(ring_[cur_].b, s);
+  bool on() const { return on_; }
+  // Events for the next softmin launch if it is sampled, else nullptr (*err set on failure).
+  const LaunchTiming *next(hipError_t *err) {
+    *err = hipSuccess;
+    cur_ = -1;
+    if (!on_ || g_prof_count.fetch_add(1) % period_ != 0) return nullptr;
+    if (ring_.size() < kRing) {
+      Pair p;
+      *err = hipEventCreate(&p.t.start);
+      if (*err == hipSuccess) *err = hipEventCreate(&p.t.stop);
+      if (*err != hipSuccess) return nullptr;
+      ring_.push_back(p);
+    } else {
+      *err = settle(head_);
+      if (*err != hipSuccess) return nullptr;
+    }
+    cur_ = (long)head_;
+    head_ = (head_ + 1) % kRing;
+    return &ring_[cur_].t;
+  }
+  // Marks the launch that used next()'s events (if any) for accounting.
+  void launched(int kind, double entries) {
+    if (cur_ < 0) return;
+    Pair &p = ring_[cur_];
+    p.kind = kind;
+    p.entries = entries;
+    p.live = true;
+    cur_ = -1;
   }
   void drain() {
     for (size_t i = 0; i < ring_.size(); ++i) (void)settle(i);
@@ -334,7 +343,7 @@ class Timer {
  private:
   static constexpr size_t kRing = 512;
   struct Pair {
-    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTiming t{nullptr, nullptr};
     int kind = 0;
     double entries = 0.0;
     bool live = false;
@@ -342,10 +351,10 @@ class Timer {
   hipError_t settle(size_t i) {
     Pair &p = ring_[i];
     if (!p.live) return hipSuccess;
-    hipError_t e = hipEventSynchronize(p.b);
+    hipError_t e = hipEventSynchronize(p.t.stop);
     if (e != hipSuccess) return e;
     float ms = 0.0f;
-    e = hipEventElapsedTime(&ms, p.a, p.b);
+    e = hipEventElapsedTime(&ms, p.t.start, p.t.stop);
     p.live = false;
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -355,10 +364,10 @@ class Timer {
     return hipSuccess;
   }
   bool on_;
-  bool sampled_ = false;
   int64_t period_ = 1;
   std::vector<Pair> ring_;
-  size_t used_ = 0, head_ = 0, cur_ = 0;
+  size_t head_ = 0;
+  long cur_ = -1;
 };
 
 bool profiling_enabled() {
@@ -400,10 +409,11 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     a.sc = (float)k.sc;
     a.part = part;
     a.done = done;
-    if (k.timer) UOT_HIP(k.timer->begin(k.s));
-    UOT_HIP(g_step ? launch_dense_cols_partial(a, k.s) : launch_dense_rows(a, k.s));
-    if (k.timer)
-      UOT_HIP(k.timer->end(k.s, g_step ? kProfDenseCols : kProfDenseRows, (double)k.n * (double)k.m));
+    hipError_t te = hipSuccess;
+    const LaunchTiming *t = k.timer ? k.timer->next(&te) : nullptr;
+    UOT_HIP(te);
+    UOT_HIP(g_step ? launch_dense_cols_partial(a, k.s, t) : launch_dense_rows(a, k.s, t));
+    if (k.timer) k.timer->launched(g_step ? kProfDenseCols : kProfDenseRows, (double)k.n * (double)k.m);
   } else {
     PointsArgs a;
     a.rec = rec_src;
@@ -418,9 +428,11 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     a.half_p = (float)(0.5 * k.c->p);
     a.part = part;
     a.done = done;
-    if (k.timer) UOT_HIP(k.timer->begin(k.s));
-    UOT_HIP(launch_points_partial(k.mode, a, k.s));
-    if (k.timer) UOT_HIP(k.timer->end(k.s, kProfPoints, (double)k.n * (double)k.m));
+    hipError_t te = hipSuccess;
+    const LaunchTiming *t = k.timer ? k.timer->next(&te) : nullptr;
+    UOT_HIP(te);
+    UOT_HIP(launch_points_partial(k.mode, a, k.s, t));
+    if (k.timer) k.timer->launched(kProfPoints, (double)k.n * (double)k.m);
   }
   return UOT_OK;
 }

@@ -2,6 +2,7 @@
 // Not part of the public ABI (that is include/uot.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -121,6 +122,23 @@ struct Epilogue {
   int32_t ti;
 };
 
+// Start/stop events attached to one kernel dispatch (timestamps of the dispatch itself, no
+// separate event commands in the stream).
+struct LaunchTiming {
+  hipEvent_t start, stop;
+};
+
+// Launches kern, through hipExtLaunchKernelGGL with the events of t when t is non-null.
+template <typename F, typename... Args>
+hipError_t launch_timed(F kern, dim3 grid, dim3 block, hipStream_t st, const LaunchTiming *t,
+                        Args... args) {
+  if (t)
+    hipExtLaunchKernelGGL(kern, grid, block, 0, st, t->start, t->stop, 0, args...);
+  else
+    hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files). All return hipError_t of the launch.
 // ---------------------------------------------------------------------------------------
@@ -152,7 +170,8 @@ struct PointsArgs {
   const int32_t *done; // early-exit flag (may be NULL)
 };
 
-hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st);
+hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st,
+                                 const LaunchTiming *t = nullptr);
 int points_targets_per_block(int mode, int d);
 int points_split_align(int mode, int d);   // split lengths are multiples of this
 // Resident 256-thread blocks per CU of the selected points kernel (0 if unknown).
@@ -181,8 +200,9 @@ struct DenseArgs {
   const int32_t *done;
 };
 
-hipError_t launch_dense_cols_partial(const DenseArgs &a, hipStream_t st);
-hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st);
+hipError_t launch_dense_cols_partial(const DenseArgs &a, hipStream_t st,
+                                     const LaunchTiming *t = nullptr);
+hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st, const LaunchTiming *t = nullptr);
 int dense_cols_per_block();
 int dense_rows_per_block();
 
