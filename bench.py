@@ -54,6 +54,10 @@ def parse():
                     help="p = 2 softmin implementation")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="cloud3d",
+                    choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16"),
+                    help="cloud3d (default) is the benchmark step above; the others print one "
+                         "JSON line of their own measurement (see extra_workload)")
     return ap.parse_args()
 
 
@@ -103,6 +107,132 @@ def profiled_traffic():
     return float(m_tr.group(1))
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def _profiled(uot, kinds):
+    """(launches, total ms, total entries) summed over the given profile kinds."""
+    n, ms, ent = 0, 0.0, 0.0
+    for k in kinds:
+        a, b, c = uot.profile_read(k)
+        n, ms, ent = n + a, ms + b, ent + c
+    return n, ms, ent
+
+
+def extra_workload(args, uot, torch, np, workloads):
+    """One JSON line for a workload other than the benchmark step:
+    oned      N=M=200 1-D measures: latency per iteration (2000 iterations from 0, TI and
+              plain) and time to change < 1e-6; the FP64 oracle runs the same 2000 iterations.
+    stored8d  stored 16384^2 float32 cost (||x-y||^1.5, D=8): TI, exactly 500 iterations;
+              HBM roofline of the stored-cost softmin kernels (4 bytes of C per entry).
+    batch2d   4096 problems, N_p, M_p ~ U{64..4096}, D=2: batched TI to change < 1e-6;
+              updates/s = sum_p 2 N_p M_p iters_p / wall.
+    highdim16 N=M=50,000, D=16: TI forward to change < 1e-6, then the envelope backward."""
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "higher_is_better": True, "scaling": "weak"}
+    if args.workload == "oned":
+        pr = workloads.oned()
+        a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)
+        kw = dict(x=x, y=y, p=2.0, eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2)
+        res = {}
+        for name, fn in (("ti", uot.ti_sinkhorn), ("plain", uot.sinkhorn)):
+            fn(a, b, max_iter=10, **kw)  # warm
+            _, dt = _timed(torch, lambda: fn(a, b, max_iter=2000, tol=0.0, **kw))
+            (_, _, info), dt_tol = _timed(torch, lambda: fn(a, b, max_iter=MAX_ITER, tol=TOL,
+                                                           check_every=1, **kw))
+            res[name] = {"us_per_iteration": dt / 2000 * 1e6, "iters_to_tol": info.iters,
+                         "seconds_to_tol": dt_tol}
+        import oracle
+        cost = oracle.Cost(x=pr.x.astype(np.float64), y=pr.y.astype(np.float64), p=2.0)
+        t0 = time.perf_counter()
+        for ti in (True, False):
+            oracle.sinkhorn(cost, pr.alpha.astype(np.float64), pr.beta.astype(np.float64),
+                            pr.eps, pr.rho1, pr.rho2, ti=ti, max_iter=2000)
+        cpu = (time.perf_counter() - t0) / 4000 * 1e6
+        out.update({"metric": "microseconds per Sinkhorn iteration (latency bound)",
+                    "value": res["ti"]["us_per_iteration"], "unit": "us/iteration",
+                    "higher_is_better": False,
+                    "config": {"workload": "1-D measures N=M=200, eps=1e-2, rho=1"},
+                    "solvers": res, "roofline": None,
+                    "cpu_baseline": {"value": cpu, "unit": "us/iteration", "kind": "oracle",
+                                     "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                                     "sample": "FP64 C oracle, 2000 iterations each of TI and plain"}})
+    elif args.workload == "stored8d":
+        pr = workloads.stored8d()
+        a, b, C = t(pr.alpha), t(pr.beta), t(pr.C)
+        kw = dict(C=C, eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2)
+        uot.ti_sinkhorn(a, b, max_iter=5, **kw)
+        uot.profile_reset()
+        uot.profile_enable(True, period=PROFILE_PERIOD)
+        (_, _, info), dt = _timed(torch, lambda: uot.ti_sinkhorn(a, b, max_iter=500, tol=0.0, **kw))
+        uot.profile_enable(False)
+        n, ms, ent = _profiled(uot, (uot.PROFILE_DENSE_COLS, uot.PROFILE_DENSE_ROWS))
+        gbs = 4.0 * ent / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out.update({"metric": "C-entry softmin updates/s", "unit": "C-entry softmin updates/s",
+                    "value": 2.0 * pr.n * pr.m * info.iters / dt, "ms_per_500_iterations": dt * 1e3,
+                    "config": {"workload": "stored cost 16384^2 float32 (||x-y||^1.5, D=8), "
+                                           "eps=5e-3, rho=0.5, TI 500 iterations"},
+                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                                 "frac": gbs / 8000.0, "traffic": None,
+                                 "kernel": "k_dense_cols_partial + k_dense_rows (4 B of C per entry)",
+                                 "launches": n, "avg_launch_ms": ms / n if n else None}})
+    elif args.workload == "batch2d":
+        bt = workloads.batch2d()
+        x, y, a, b = t(bt.x), t(bt.y), t(bt.alpha), t(bt.beta)
+        run = lambda: uot.ti_sinkhorn_batched(bt.offN, bt.offM, x, y, a, b, bt.eps, bt.rho1,
+                                              bt.rho2, max_iter=MAX_ITER, tol=TOL,
+                                              check_every=CHECK_EVERY)
+        run()
+        (f, g, iters, status), dt = _timed(torch, run)
+        it = iters.cpu().numpy().astype(np.float64)
+        N = np.diff(bt.offN).astype(np.float64)
+        M = np.diff(bt.offM).astype(np.float64)
+        ups = float((2.0 * N * M * it).sum())
+        hist = np.percentile(it, [0, 50, 90, 99, 100]).tolist()
+        out.update({"metric": "C-entry softmin updates/s", "unit": "C-entry softmin updates/s",
+                    "value": ups / dt, "seconds": dt,
+                    "config": {"workload": "4096 problems, N_p,M_p ~ U{64..4096}, D=2, "
+                                           "eps log-U[1e-3,1e-1], rho log-U[0.1,10], TI to 1e-6"},
+                    "iterations_percentiles_0_50_90_99_100": hist,
+                    "status_counts": {str(k): int(v) for k, v in
+                                      zip(*np.unique(status.cpu().numpy(), return_counts=True))},
+                    "roofline": {"bound": "alu", "achieved": ups / dt / 1e9,
+                                 "peak": PEAK_EXP_PER_S / 1e9, "unit": "Gexp/s",
+                                 "frac": ups / dt / PEAK_EXP_PER_S, "traffic": None,
+                                 "kernel": "k_batched_half (whole solve wall time, not per launch)"}})
+    else:  # highdim16
+        pr = workloads.highdim16()
+        a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)
+        kw = dict(x=x, y=y, p=2.0, eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2)
+        uot.ti_sinkhorn(a, b, max_iter=3, **kw)
+        uot.profile_reset()
+        uot.profile_enable(True, period=PROFILE_PERIOD)
+        (f, g, info), dt = _timed(torch, lambda: uot.ti_sinkhorn(
+            a, b, max_iter=MAX_ITER, tol=TOL, check_every=CHECK_EVERY, **kw))
+        uot.profile_enable(False)
+        n, ms, ent = _profiled(uot, (uot.PROFILE_POINTS,))
+        _, dtb = _timed(torch, lambda: uot.backward(a, b, f, g, **kw))
+        ach = ent / (ms * 1e-3) if ms > 0 else 0.0
+        out.update({"metric": "C-entry softmin updates/s", "unit": "C-entry softmin updates/s",
+                    "value": 2.0 * pr.n * pr.m * info.iters / dt,
+                    "config": {"workload": "D=16 clouds N=M=50,000, eps=0.05, rho=1, TI to 1e-6 "
+                                           "then the envelope backward"},
+                    "iters": info.iters, "converged": info.converged, "forward_seconds": dt,
+                    "backward_seconds": dtb,
+                    "roofline": {"bound": "alu", "achieved": ach / 1e9, "peak": PEAK_EXP_PER_S / 1e9,
+                                 "unit": "Gexp/s", "frac": ach / PEAK_EXP_PER_S, "traffic": None,
+                                 "kernel": "k_points_mfma<16,Bf16Form<16>>", "launches": n,
+                                 "avg_launch_ms": ms / n if n else None}})
+    print(json.dumps(out))
+
+
 def cpu_baseline(pr, seconds):
     """FP64 oracle TI Sinkhorn on the same inputs for a bounded number of iterations."""
     import numpy as np
@@ -150,6 +280,9 @@ def main():
         sys.exit(1)
     uot.load_library()
     uot.set_points_kernel({"auto": 0, "valu": 1, "mfma-f32": 2, "mfma-bf16": 3}[args.points_kernel])
+    if args.workload != "cloud3d":
+        extra_workload(args, uot, torch, np, workloads)
+        return
     pr = workloads.cloud3d(n=args.n, m=args.n)
     dev = torch.device("cuda:0")
     tens = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
