@@ -154,6 +154,7 @@ hipError_t launch_mode(const PointsArgs &a, hipStream_t st, const LaunchTiming *
 // uot_mx.cuh; this kernel gives each wave one 32-target column tile of one source split.
 // ---------------------------------------------------------------------------------------
 constexpr int kMfmaWaves = 4;  // waves per block
+constexpr int kXcds = 8;       // accelerator complex dies of the MI355X (L2 per die)
 
 // Centred coordinates of target t (zero beyond the true dimension and for t >= nt).
 template <int D>
@@ -177,7 +178,15 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
   const int wave = threadIdx.x >> 6;
   const int col = lane & 31;
   const int h = lane >> 5;
-  const int t = (blockIdx.x * kMfmaWaves + wave) * 32 + col;
+  // XCD-aware order: workgroups go to the 8 XCDs round-robin by id, so id b runs on XCD
+  // b % 8; give XCD x the contiguous range x * per .. of the split-major (split, tile) pairs,
+  // so each XCD's L2 holds the source records of about nsplit / 8 splits, not of all.
+  const int ntiles = (a.nt + kMfmaWaves * 32 - 1) / (kMfmaWaves * 32);
+  const int per = (int)(gridDim.x / kXcds);
+  const int q = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (q >= ntiles * a.nsplit) return;
+  const int split = q / ntiles, tile = q - split * ntiles;
+  const int t = (tile * kMfmaWaves + wave) * 32 + col;
 
   Frag bf[NJ];
   {
@@ -186,7 +195,7 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
     Form::build_b(yc, h, bf);
   }
 
-  const int s0 = blockIdx.y * a.split_len;
+  const int s0 = split * a.split_len;
   const int s1 = min(a.ns, s0 + a.split_len);
   float sig, l;
   column_softmin<Form>(a.rec, s0, s1, col, h, bf, sig, l);
@@ -194,13 +203,14 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
   // merge the two half-waves of each column (same sigma; sums add)
   const float ll = l + __shfl_xor(l, 32, 64);
   if (h == 0 && t < a.nt)
-    a.part[(size_t)blockIdx.y * a.nt + t] = make_float2(ll > 0.0f ? sig : -FLT_MAX, ll);
+    a.part[(size_t)split * a.nt + t] = make_float2(ll > 0.0f ? sig : -FLT_MAX, ll);
 }
 
 template <int D, typename Form>
 hipError_t launch_mfma_form(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
   constexpr int tpb = kMfmaWaves * 32;
-  dim3 grid((a.nt + tpb - 1) / tpb, a.nsplit);
+  const int pairs = (a.nt + tpb - 1) / tpb * a.nsplit;  // (split, tile) pairs, one block each
+  dim3 grid((pairs + kXcds - 1) / kXcds * kXcds);        // whole rounds over the XCDs
   return launch_timed(k_points_mfma<D, Form>, grid, dim3(64 * kMfmaWaves), st, t, a);
 }
 
