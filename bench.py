@@ -94,13 +94,16 @@ def profiled_traffic():
     import hashlib
     import re
     summary = os.path.join(ROOT, "profiles", "points_softmin_cloud3d_hbm_bytes.md")
-    src = os.path.join(ROOT, "paper_2201_00730_amd", "csrc", "kernels_points.hip")
+    csrc = os.path.join(ROOT, "paper_2201_00730_amd", "csrc")
     try:
         text = open(summary).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for name in ("kernels_points.hip", "uot_mx.cuh"):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+        sha = h.hexdigest()
     except OSError:
         return None
-    m_sha = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    m_sha = re.search(r"source_sha256 \(kernels_points.hip \+ uot_mx.cuh\): ([0-9a-f]{64})", text)
     m_tr = re.search(r"traffic_bytes_per_launch: ([0-9.]+)", text)
     if not m_sha or not m_tr or m_sha.group(1) != sha:
         return None

@@ -182,13 +182,14 @@ __device__ __forceinline__ void column_softmin(const float *rec, int s0, int s1,
     return true;
   };
 
-  // The next tile's records are prefetched while this tile's exps run, and the waves
-  // resident on the SIMD (eight at this register count) cover each other's matrix-core
-  // latency. The inner loop is the fast path, where the accumulator input (-sig, F32Form)
-  // and the B fragments (Bf16Form) are loop-invariant; a tile that would overflow the sum,
-  // or a column not yet started, leaves it for recentre(), which may move sig.
-  Frag an[NJ], ac[NJ];
-  load_a(s0, an);
+  // The next tile's records are loaded into the fragments as soon as this tile's MFMAs have
+  // read them, so the load overlaps this tile's exps (one buffer, no copies), and the waves
+  // resident on the SIMD (eight at this register count) cover each other's latencies.
+  // The inner loop is the fast path, where the accumulator input (-sig, F32Form) and the
+  // B fragments (Bf16Form) are loop-invariant; a tile that would overflow the sum, or a
+  // column not yet started, leaves it for recentre(), which may move sig.
+  Frag fa[NJ];
+  load_a(s0, fa);
   int sb = s0;
   while (sb < s1) {
     f32x16 cin;
@@ -198,10 +199,8 @@ __device__ __forceinline__ void column_softmin(const float *rec, int s0, int s1,
     f32x16 acc;
     bool slow = false;
     for (; sb < s1; sb += 32) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) ac[j] = an[j];
-      if (sb + 32 < s1) load_a(sb + 32, an);
-      acc = Form::mma(ac, bf, cin);
+      acc = Form::mma(fa, bf, cin);
+      if (sb + 32 < s1) load_a(sb + 32, fa);
       if (!all_started || !fast_add(acc)) { slow = true; break; }
     }
     if (!slow) break;
