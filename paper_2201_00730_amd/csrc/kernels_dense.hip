@@ -11,6 +11,7 @@
 // offsets between the 4 rows; the (max, sum) pairs are merged across lanes with shuffles.
 #include <cfloat>
 
+#include "uot_epilogue.cuh"
 #include "uot_internal.h"
 
 namespace uot {
@@ -33,7 +34,7 @@ __device__ __forceinline__ float4 load4_stream(const float *p) {
 // VEC4: C and ldc allow aligned float4 loads.
 template <bool VEC4>
 __global__ __launch_bounds__(256) void k_dense_cols_partial(DenseArgs a) {
-  if (a.done != nullptr && *a.done) return;
+  if (a.done != nullptr && get_done(a.done)) return;
   const int j0 = (blockIdx.x * 256 + threadIdx.x) * kColsPerThread;
   if (j0 >= a.m) return;
   const bool full = VEC4 && (j0 + kColsPerThread <= a.m);
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_dense_cols_partial(DenseArgs a) {
 
 template <bool VEC4>
 __global__ __launch_bounds__(256) void k_dense_rows(DenseArgs a) {
-  if (a.done != nullptr && *a.done) return;
+  if (a.done != nullptr && get_done(a.done)) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int row0 = (blockIdx.x * 4 + wave) * kRowsPerWave;

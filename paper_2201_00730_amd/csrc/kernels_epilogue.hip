@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_build_records(RecordArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
-  if (a.kind != kReduceInit && a.st->done) return;
+  if (a.kind != kReduceInit && get_done(&a.st->done)) return;
   reduce_scalars(a);
 }
 
@@ -48,7 +48,6 @@ constexpr int kCombTargets = kBlock / kCombLanes;
 
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
-  if (a.st->done) return;
   combine_block<D, MODE, kCombLanes>(a, blockIdx.x * kCombTargets, blockIdx.x);
 }
 

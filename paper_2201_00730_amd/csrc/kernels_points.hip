@@ -15,6 +15,7 @@
 // tile, and each entry then costs one exp2.
 #include <cfloat>
 
+#include "uot_epilogue.cuh"
 #include "uot_internal.h"
 #include "uot_mx.cuh"
 
@@ -36,7 +37,7 @@ __device__ __forceinline__ float cost_pow(float d2, float half_p) {
 
 template <int D, int MODE, int R>
 __global__ __launch_bounds__(256) void k_points_partial(PointsArgs a) {
-  if (a.done != nullptr && *a.done) return;
+  if (a.done != nullptr && get_done(a.done)) return;
   constexpr int SD = rec_stride(MODE, D);
   const int t0 = blockIdx.x * (256 * R) + threadIdx.x;
 
@@ -171,7 +172,7 @@ __device__ __forceinline__ void target_coords(const PointsArgs &a, int t, float 
 
 template <int D, typename Form>
 __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
-  if (a.done != nullptr && *a.done) return;
+  static_assert(kMfmaWaves * 64 == kBlock, "the side reduction runs on one whole block");
   constexpr int NJ = Form::NJ;
   typedef typename Form::Frag Frag;
   const int lane = threadIdx.x & 63;
@@ -184,21 +185,28 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
   const int ntiles = (a.nt + kMfmaWaves * 32 - 1) / (kMfmaWaves * 32);
   const int per = (int)(gridDim.x / kXcds);
   const int q = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-  if (q >= ntiles * a.nsplit) return;
+  const int pairs = ntiles * a.nsplit;
+  if (q >= pairs) {
+    // the first block past the pairs reduces the previous half-step (block-uniform branch)
+    if (q == pairs && a.red_on && !get_done(&a.red.st->done)) reduce_scalars(a.red);
+    return;
+  }
   const int split = q / ntiles, tile = q - split * ntiles;
   const int t = (tile * kMfmaWaves + wave) * 32 + col;
-
-  Frag bf[NJ];
-  {
-    float yc[D];
-    target_coords<D>(a, t, yc);
-    Form::build_b(yc, h, bf);
-  }
-
   const int s0 = split * a.split_len;
   const int s1 = min(a.ns, s0 + a.split_len);
+
+  // The first tile's records, the target coordinates and the early-exit flag are loaded
+  // together, so the start costs one memory latency.
+  Frag fa[NJ], bf[NJ];
+  Form::load_a(a.rec + (size_t)s0 * Form::RS, col, h, fa);
+  float yc[D];
+  target_coords<D>(a, t, yc);
+  const bool stop = a.done != nullptr && get_done(a.done);
+  Form::build_b(yc, h, bf);
+  if (stop) return;
   float sig, l;
-  column_softmin<Form>(a.rec, s0, s1, col, h, bf, sig, l);
+  column_softmin<Form>(a.rec, s0, s1, col, h, bf, fa, sig, l);
 
   // merge the two half-waves of each column (same sigma; sums add)
   const float ll = l + __shfl_xor(l, 32, 64);
@@ -209,8 +217,9 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
 template <int D, typename Form>
 hipError_t launch_mfma_form(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
   constexpr int tpb = kMfmaWaves * 32;
-  const int pairs = (a.nt + tpb - 1) / tpb * a.nsplit;  // (split, tile) pairs, one block each
-  dim3 grid((pairs + kXcds - 1) / kXcds * kXcds);        // whole rounds over the XCDs
+  // (split, tile) pairs, one block each, plus the side-reduction block
+  const int blocks = (a.nt + tpb - 1) / tpb * a.nsplit + (a.red_on ? 1 : 0);
+  dim3 grid((blocks + kXcds - 1) / kXcds * kXcds);  // whole rounds over the XCDs
   return launch_timed(k_points_mfma<D, Form>, grid, dim3(64 * kMfmaWaves), st, t, a);
 }
 

@@ -387,8 +387,19 @@ struct Ctx {
   void *ws;
   hipStream_t s;
   Timer *timer = nullptr;
+  // The scalar reduction of the last half-step, not launched yet: the next matrix-core
+  // softmin runs it in a block of its own, or flush_reduce() launches it alone.
+  mutable ReduceArgs pending{};
+  mutable bool has_pending = false;
   SolveState *st() const { return at<SolveState>(ws, L.state); }
 };
+
+uot_status flush_reduce(const Ctx &k) {
+  if (!k.has_pending) return UOT_OK;
+  k.has_pending = false;
+  UOT_HIP(launch_reduce(k.pending, k.s));
+  return UOT_OK;
+}
 
 // Softmin partials of one half-step into the part buffer.
 //   g_step: targets are the y side (columns of C), sources the x side with records rec_x;
@@ -397,6 +408,7 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
   const HalfShape &h = g_step ? k.L.g : k.L.f;
   float2 *part = at<float2>(k.ws, k.L.part);
   const float *rec_src = at<float>(k.ws, g_step ? k.L.rec_x : k.L.rec_y);
+  if (k.mode == kDense || !points_uses_mfma(k.mode, k.d)) UOT_TRY(flush_reduce(k));
   if (k.mode == kDense) {
     DenseArgs a;
     a.C = k.c->C;
@@ -428,6 +440,9 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     a.half_p = (float)(0.5 * k.c->p);
     a.part = part;
     a.done = done;
+    a.red = k.pending;
+    a.red_on = k.has_pending ? 1 : 0;
+    k.has_pending = false;
     hipError_t te = hipSuccess;
     const LaunchTiming *t = k.timer ? k.timer->next(&te) : nullptr;
     UOT_HIP(te);
@@ -490,7 +505,8 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
   ra.tol = tol;
   ra.check_every = check_every;
-  UOT_HIP(launch_reduce(ra, k.s));
+  k.pending = ra;  // run beside the next softmin, or by flush_reduce()
+  k.has_pending = true;
   return UOT_OK;
 }
 
@@ -611,6 +627,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
       UOT_TRY(half_step(k, false, P->tol, P->check_every));
     }
     issued += todo;
+    UOT_TRY(flush_reduce(k));
     if (checking) {
       SolveState *slot = &pin.h[c_idx & 1];
       UOT_HIP(hipMemcpyAsync(slot, st, sizeof(SolveState), hipMemcpyDeviceToHost, k.s));

@@ -134,6 +134,15 @@ static __device__ __forceinline__ void write_record(float *rec, int t, const flo
   }
 }
 
+// The early-exit flag is read by softmin blocks while the side reduction may write it, so
+// both sides access it atomically (relaxed: a stale read only costs the reader's work).
+static __device__ __forceinline__ int32_t get_done(const int32_t *done) {
+  return __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+static __device__ __forceinline__ void set_done(SolveState *st, int32_t v) {
+  __hip_atomic_store(&st->done, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Reduces the block partials of a half-step (or of the start) into the scalar state; run by
 // one block of kBlock threads. Thread 0 writes the results.
 static __device__ void reduce_scalars(const ReduceArgs &a) {
@@ -163,7 +172,7 @@ static __device__ void reduce_scalars(const ReduceArgs &a) {
     st->sA = -a.rho1 * L;  // Smin_alpha^rho1(f_0)
     st->sB = 0.0;
     if (!st->pos_a || !st->pos_b) st->error |= kErrWeights;
-    st->done = st->error ? 1 : 0;
+    set_done(st, st->error ? 1 : 0);
   } else if (a.kind == kReduceG) {
     const double sBhat = -a.rho2 * L;  // Smin_beta^rho2(ghat)
     const double tg = a.ti ? a.kappa_t / (1.0 - a.kappa_t) * sBhat : 0.0;
@@ -198,23 +207,26 @@ static __device__ void reduce_scalars(const ReduceArgs &a) {
     st->off_g_prev = off_g;
     if (!isfinite(off_f) || !isfinite(off_g) || isnan(delta)) st->error |= kErrNumeric;
     if (st->error)
-      st->done = 1;
+      set_done(st, 1);
     else if (a.tol > 0.0 && a.check_every > 0 && it % a.check_every == 0 && delta < a.tol)
-      st->done = 1;
+      set_done(st, 1);
   }
 }
 
 // Merges the split partials of targets [t_begin, t_begin + kBlock / LANES) (LANES threads per
 // target), applies the half-step epilogue (KL prox and TI translation, App. B) and writes the
-// new potentials and source records; returns this thread's contribution to the block's
-// (tilted-mass log-sum-exp, potential-change range) partial.
+// new potentials and source records; sets this thread's contribution to the block's
+// (tilted-mass log-sum-exp, potential-change range) partial. Returns false, having written
+// nothing, once the solve is done.
 template <int D, int MODE, int LANES>
-static __device__ void combine_range(const CombineArgs &a, int t_begin, double &mm, double &ms,
+static __device__ bool combine_range(const CombineArgs &a, int t_begin, double &mm, double &ms,
                                      double &dmx, double &dmn) {
   const int sub = threadIdx.x % LANES;
   const int t = t_begin + threadIdx.x / LANES;
   const int tc = t < a.nt ? t : a.nt - 1;
-  // Everything the epilogue reads is loaded first, so that its latency overlaps the merge.
+  // Everything the epilogue reads, the early-exit flag included, is loaded first, so that
+  // its latency overlaps the merge.
+  const int32_t done = get_done(&a.st->done);
   const float w = a.w[tc];
   const float old = a.pot[tc];
   const double tau_src = a.ep.src_is_x ? a.st->tau_f : a.st->tau_g;
@@ -249,6 +261,7 @@ static __device__ void combine_range(const CombineArgs &a, int t_begin, double &
     L = L * __builtin_amdgcn_exp2f(M - nm) + Lo * __builtin_amdgcn_exp2f(Mo - nm);
     M = nm;
   }
+  if (done) return false;  // the same flag for the whole block
   mm = -INFINITY;
   ms = 0.0;
   dmx = -INFINITY;
@@ -265,13 +278,14 @@ static __device__ void combine_range(const CombineArgs &a, int t_begin, double &
     if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }
     if (!isfinite(hnew)) atomicOr(&a.st->error, kErrNumeric);
   }
+  return true;
 }
 
 // combine_range over one block's targets, then the block partial into bparts[tile].
 template <int D, int MODE, int LANES>
 static __device__ void combine_block(const CombineArgs &a, int t_begin, int tile) {
   double mm, ms, dmx, dmn;
-  combine_range<D, MODE, LANES>(a, t_begin, mm, ms, dmx, dmn);
+  if (!combine_range<D, MODE, LANES>(a, t_begin, mm, ms, dmx, dmn)) return;
   block_reduce_part(mm, ms, dmx, dmn);
   if (threadIdx.x == 0) a.bparts[tile] = BlockPart{mm, ms, dmx, dmn};
 }

@@ -168,6 +168,11 @@ struct PointsArgs {
   float half_p;        // p/2 (kPower)
   float2 *part;        // [nsplit, nt] (running max, sum) in log2 domain
   const int32_t *done; // early-exit flag (may be NULL)
+  // Matrix-core kernels only: when red_on is set, one extra block of the launch reduces the
+  // previous half-step's block partials (red) beside the softmin blocks, which read none of
+  // the scalars it writes.
+  ReduceArgs red;
+  int red_on;
 };
 
 hipError_t launch_points_partial(int mode, const PointsArgs &a, hipStream_t st,

@@ -1,5 +1,5 @@
-// Matrix-core column softmin of the squared-Euclidean cost, shared by the single-problem
-// and the batched solvers (gfx950).
+// Matrix-core column softmin of the squared-Euclidean cost (gfx950), used by the points
+// softmin kernel.
 //
 // The base-2 exponent of entry (s, t), shifted
 // by the running reference sigma_t of its target, is a contraction plus a per-column
@@ -133,10 +133,13 @@ struct Bf16Form {
 // up to a whole tile). Lane (col, h) owns
 // target column col and returns the running reference sig and this lane's sum l of
 // 2^{v - sig} over its 16 rows of every tile (the two lanes of a column share sig; their
-// sums add). bf is the column's B fragment set (its sigma slots are rewritten).
+// sums add). bf is the column's B fragment set (its sigma slots are rewritten); fa holds
+// the records of the tile at s0 on entry (Form::load_a), so that the caller can issue that
+// load together with its own.
 template <typename Form>
 __device__ __forceinline__ void column_softmin(const float *rec, int s0, int s1, int col, int h,
-                                               typename Form::Frag (&bf)[Form::NJ], float &sig,
+                                               typename Form::Frag (&bf)[Form::NJ],
+                                               typename Form::Frag (&fa)[Form::NJ], float &sig,
                                                float &l) {
   constexpr int NJ = Form::NJ, RS = Form::RS;
   typedef typename Form::Frag Frag;
@@ -188,8 +191,6 @@ __device__ __forceinline__ void column_softmin(const float *rec, int s0, int s1,
   // The inner loop is the fast path, where the accumulator input (-sig, F32Form) and the
   // B fragments (Bf16Form) are loop-invariant; a tile that would overflow the sum, or a
   // column not yet started, leaves it for recentre(), which may move sig.
-  Frag fa[NJ];
-  load_a(s0, fa);
   int sb = s0;
   while (sb < s1) {
     f32x16 cin;
