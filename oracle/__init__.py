@@ -65,6 +65,10 @@ def _load():
             lib.or_lambda_star.restype = D
             lib.or_sinkhorn.argtypes = [CP, P, P, D, D, D, I, I, D, I, I, P, P, P, P, P, P, P]
             lib.or_sinkhorn.restype = I
+            lib.or_anderson_mix.argtypes = [I, I, P, D, P, P]
+            lib.or_anderson_mix.restype = I
+            lib.or_sinkhorn_anderson.argtypes = [CP, P, P, D, D, D, I, I, D, I, D, I, I, P, P, P, P, P]
+            lib.or_sinkhorn_anderson.restype = I
             lib.or_plan_apply.argtypes = [CP, P, P, D, P, P, I, P, I, P]
             lib.or_dual_value.argtypes = [CP, P, P, D, D, D, P, P]
             lib.or_dual_value.restype = D
@@ -224,6 +228,46 @@ def sinkhorn(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: float, *, t
                           hist_delta=None if hd is None else hd[:it].copy(),
                           hist_f=None if hf is None else hf[:it].copy(),
                           hist_g=None if hg is None else hg[:it].copy())
+
+
+def anderson_mix(X, r: float):
+    """Anderson extrapolation of the appendix on accelerating Sinkhorn: rows of X are the
+    iterates x_0 .. x_K of a map (x_{k+1} = T(x_k)); the residuals x_{k+1} - x_k form U;
+    c = (G + rI)^{-1} 1 / (1^T (G + rI)^{-1} 1) with G = U^T U over its Frobenius norm;
+    returns (c, sum_k c_k x_{k+1})."""
+    X = np.ascontiguousarray(_f64(X))
+    K = X.shape[0] - 1
+    c = np.empty(K)
+    out = np.empty(X.shape[1])
+    if _load().or_anderson_mix(X.shape[1], K, _ptr(X), float(r), _ptr(c), _ptr(out)) != 0:
+        raise ValueError("singular Anderson system")
+    return c, out
+
+
+def sinkhorn_anderson(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: float, *, ti: bool,
+                      K: int, r: float, max_iter: int, tol: float = 0.0, check_every: int = 1,
+                      f0=None, history: bool = False) -> SinkhornResult:
+    """``sinkhorn`` with Anderson extrapolation of f (plain) or fb (TI) every K iterations
+    (see ``anderson_mix``); the change is +inf at the first iteration after an extrapolation."""
+    alpha, beta = _f64(alpha), _f64(beta)
+    n, m = cost.n, cost.m
+    if alpha.shape != (n,) or beta.shape != (m,):
+        raise ValueError("alpha/beta shape mismatch")
+    f = _f64(f0).copy() if f0 is not None else np.zeros(n)
+    g = np.zeros(m)
+    lam = ctypes.c_double(0.0)
+    last = ctypes.c_double(0.0)
+    hd = np.empty(max_iter) if history else None
+    cs = cost._struct()
+    it = _load().or_sinkhorn_anderson(ctypes.byref(cs), _ptr(alpha), _ptr(beta), float(eps),
+                                      float(rho1), float(rho2), int(bool(ti)), int(K), float(r),
+                                      int(max_iter), float(tol), int(check_every),
+                                      int(f0 is not None), _ptr(f), _ptr(g), ctypes.byref(lam),
+                                      ctypes.byref(last), _ptr(hd))
+    if it < 0:
+        raise ValueError("K must be in 1..16")
+    return SinkhornResult(f=f, g=g, iters=it, last_delta=last.value, lam=lam.value,
+                          hist_delta=None if hd is None else hd[:it].copy())
 
 
 def plan_apply(cost: Cost, alpha, beta, eps: float, f, g, V, transpose: bool = False) -> np.ndarray:

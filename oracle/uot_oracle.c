@@ -135,6 +135,54 @@ double or_lambda_star(int n, int m, const double *loga, const double *logb, cons
  * Optional histories (NULL to skip): hist_delta[max_iter], hist_f[max_iter*n], hist_g[max_iter*m].
  * Returns the number of iterations run; writes f, g, *lambda_out (0 for ti = 0), *last_delta.
  */
+/* Working state of one solve: log-weights, parameters and the potentials being iterated. */
+typedef struct {
+  const or_cost *k;
+  const double *loga, *logb;
+  double eps, rho1, rho2;
+  int ti;
+  double *fb, *gb, *S;  /* f, g (plain) or fb, gb (TI); S: softmin scratch of max(n, m) */
+} or_state;
+
+/* One iteration, g-step then f-step, from s->fb (see the formulas above). Leaves the new
+ * fb, gb in s and writes the reported potentials: fr, gr = (f, g) for plain Sinkhorn and
+ * Phi(fb, gb) = (fb + lambda*, gb - lambda*) for TI. Returns lambda* (0 for plain). */
+static double or_iterate(or_state *s, double *fr, double *gr) {
+  const or_cost *k = s->k;
+  const int n = k->n, m = k->m;
+  const double eps = s->eps, rho1 = s->rho1, rho2 = s->rho2;
+  const double k1 = rho1 / (eps + rho1), k2 = rho2 / (eps + rho2);
+  double *fb = s->fb, *gb = s->gb, *S = s->S;
+  double lam = 0.0;
+  if (!s->ti) {
+    or_smin_cols(k, s->loga, fb, eps, S);
+    for (int j = 0; j < m; ++j) gb[j] = k2 * S[j];
+    or_smin_rows(k, s->logb, gb, eps, S);
+    for (int i = 0; i < n; ++i) fb[i] = k1 * S[i];
+    memcpy(fr, fb, sizeof(double) * (size_t)n);
+    memcpy(gr, gb, sizeof(double) * (size_t)m);
+  } else {
+    const double cg = eps * rho2 / ((eps + rho2) * (rho1 + rho2));
+    const double kg = eps * rho1 / ((eps + rho2) * (rho1 + rho2));
+    const double cf = eps * rho1 / ((eps + rho1) * (rho1 + rho2));
+    const double kf = eps * rho2 / ((eps + rho1) * (rho1 + rho2));
+    double sA = or_smin_vec(n, s->loga, fb, rho1);
+    or_smin_cols(k, s->loga, fb, eps, S);
+    for (int j = 0; j < m; ++j) gb[j] = k2 * S[j] - cg * sA;          /* gh */
+    double tg = kg / (1.0 - kg) * or_smin_vec(m, s->logb, gb, rho2);
+    for (int j = 0; j < m; ++j) gb[j] += tg;                          /* gb */
+    double sB = or_smin_vec(m, s->logb, gb, rho2);
+    or_smin_rows(k, s->logb, gb, eps, S);
+    for (int i = 0; i < n; ++i) fb[i] = k1 * S[i] - cf * sB;          /* fh */
+    double tf = kf / (1.0 - kf) * or_smin_vec(n, s->loga, fb, rho1);
+    for (int i = 0; i < n; ++i) fb[i] += tf;                          /* fb */
+    lam = or_lambda_star(n, m, s->loga, s->logb, fb, gb, rho1, rho2);
+    for (int i = 0; i < n; ++i) fr[i] = fb[i] + lam;
+    for (int j = 0; j < m; ++j) gr[j] = gb[j] - lam;
+  }
+  return lam;
+}
+
 int or_sinkhorn(const or_cost *k, const double *alpha, const double *beta, double eps, double rho1,
                 double rho2, int ti, int max_iter, double tol, int check_every, int warm_start,
                 double *f, double *g, double *lambda_out, double *last_delta, double *hist_delta,
@@ -144,7 +192,6 @@ int or_sinkhorn(const or_cost *k, const double *alpha, const double *beta, doubl
   double *logb = (double *)malloc(sizeof(double) * (size_t)m);
   for (int i = 0; i < n; ++i) loga[i] = log(alpha[i]);
   for (int j = 0; j < m; ++j) logb[j] = log(beta[j]);
-  const double k1 = rho1 / (eps + rho1), k2 = rho2 / (eps + rho2);
   double *fb = (double *)malloc(sizeof(double) * (size_t)n);  /* f (plain) or fb (TI) */
   double *gb = (double *)malloc(sizeof(double) * (size_t)m);
   double *S = (double *)malloc(sizeof(double) * (size_t)(n > m ? n : m));
@@ -154,35 +201,11 @@ int or_sinkhorn(const or_cost *k, const double *alpha, const double *beta, doubl
   double *gr = (double *)malloc(sizeof(double) * (size_t)m);
   for (int i = 0; i < n; ++i) fb[i] = warm_start ? f[i] : 0.0;
   for (int j = 0; j < m; ++j) gb[j] = 0.0;
+  or_state st = {k, loga, logb, eps, rho1, rho2, ti, fb, gb, S};
   double lam = 0.0, delta = INFINITY;
   int t = 0;
   for (t = 1; t <= max_iter; ++t) {
-    if (!ti) {
-      or_smin_cols(k, loga, fb, eps, S);
-      for (int j = 0; j < m; ++j) gb[j] = k2 * S[j];
-      or_smin_rows(k, logb, gb, eps, S);
-      for (int i = 0; i < n; ++i) fb[i] = k1 * S[i];
-      memcpy(fr, fb, sizeof(double) * (size_t)n);
-      memcpy(gr, gb, sizeof(double) * (size_t)m);
-    } else {
-      const double cg = eps * rho2 / ((eps + rho2) * (rho1 + rho2));
-      const double kg = eps * rho1 / ((eps + rho2) * (rho1 + rho2));
-      const double cf = eps * rho1 / ((eps + rho1) * (rho1 + rho2));
-      const double kf = eps * rho2 / ((eps + rho1) * (rho1 + rho2));
-      double sA = or_smin_vec(n, loga, fb, rho1);
-      or_smin_cols(k, loga, fb, eps, S);
-      for (int j = 0; j < m; ++j) gb[j] = k2 * S[j] - cg * sA;          /* gh */
-      double tg = kg / (1.0 - kg) * or_smin_vec(m, logb, gb, rho2);
-      for (int j = 0; j < m; ++j) gb[j] += tg;                          /* gb */
-      double sB = or_smin_vec(m, logb, gb, rho2);
-      or_smin_rows(k, logb, gb, eps, S);
-      for (int i = 0; i < n; ++i) fb[i] = k1 * S[i] - cf * sB;          /* fh */
-      double tf = kf / (1.0 - kf) * or_smin_vec(n, loga, fb, rho1);
-      for (int i = 0; i < n; ++i) fb[i] += tf;                          /* fb */
-      lam = or_lambda_star(n, m, loga, logb, fb, gb, rho1, rho2);
-      for (int i = 0; i < n; ++i) fr[i] = fb[i] + lam;
-      for (int j = 0; j < m; ++j) gr[j] = gb[j] - lam;
-    }
+    lam = or_iterate(&st, fr, gr);
     if (t == 1) {
       delta = INFINITY;
     } else {
@@ -202,6 +225,139 @@ int or_sinkhorn(const or_cost *k, const double *alpha, const double *beta, doubl
   if (lambda_out) *lambda_out = ti ? lam : 0.0;
   if (last_delta) *last_delta = delta;
   free(loga); free(logb); free(fb); free(gb); free(S); free(fo); free(go); free(fr); free(gr);
+  return t;
+}
+
+/*
+ * Anderson extrapolation (appendix "Combining Sinkhorn with Anderson acceleration").
+ * X holds K + 1 iterates of a map T, row k = x_k (length n), with x_{k+1} = T(x_k). The
+ * residuals u_k = x_{k+1} - x_k (k < K) form U = [u_0 .. u_{K-1}]. With G = U^T U divided by
+ * its Frobenius norm (left as is when that norm is 0),
+ *   c = (G + r I)^{-1} 1 / (1^T (G + r I)^{-1} 1),
+ * and the extrapolated point is out = sum_k c_k x_{k+1}, the combination of the images
+ * T(x_k). Writes c[K] and out[n]; returns 0, or -1 (c, out untouched) if G + r I is singular.
+ */
+int or_anderson_mix(int n, int K, const double *X, double r, double *c, double *out) {
+  double G[16][16], z[16];
+  if (K < 1 || K > 16) return -1;
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b) {
+      double sum = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double ua = X[(size_t)(a + 1) * n + i] - X[(size_t)a * n + i];
+        const double ub = X[(size_t)(b + 1) * n + i] - X[(size_t)b * n + i];
+        sum += ua * ub;
+      }
+      G[a][b] = sum;
+    }
+  double fro = 0.0;
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b) fro += G[a][b] * G[a][b];
+  fro = sqrt(fro);
+  for (int a = 0; a < K; ++a) {
+    for (int b = 0; b < K; ++b) G[a][b] = fro > 0.0 ? G[a][b] / fro : G[a][b];
+    G[a][a] += r;
+    z[a] = 1.0;
+  }
+  /* (G + r I) z = 1 by Gaussian elimination with partial pivoting */
+  for (int p = 0; p < K; ++p) {
+    int piv = p;
+    for (int a = p + 1; a < K; ++a)
+      if (fabs(G[a][p]) > fabs(G[piv][p])) piv = a;
+    if (G[piv][p] == 0.0) return -1;
+    if (piv != p) {
+      for (int b = 0; b < K; ++b) { const double t = G[p][b]; G[p][b] = G[piv][b]; G[piv][b] = t; }
+      const double t = z[p]; z[p] = z[piv]; z[piv] = t;
+    }
+    for (int a = p + 1; a < K; ++a) {
+      const double l = G[a][p] / G[p][p];
+      for (int b = p; b < K; ++b) G[a][b] -= l * G[p][b];
+      z[a] -= l * z[p];
+    }
+  }
+  for (int p = K - 1; p >= 0; --p) {
+    double v = z[p];
+    for (int b = p + 1; b < K; ++b) v -= G[p][b] * z[b];
+    z[p] = v / G[p][p];
+  }
+  double zs = 0.0;
+  for (int a = 0; a < K; ++a) zs += z[a];
+  if (zs == 0.0 || !isfinite(zs)) return -1;
+  for (int a = 0; a < K; ++a) c[a] = z[a] / zs;
+  for (int i = 0; i < n; ++i) {
+    double v = 0.0;
+    for (int a = 0; a < K; ++a) v += c[a] * X[(size_t)(a + 1) * n + i];
+    out[i] = v;
+  }
+  return 0;
+}
+
+/*
+ * Anderson-accelerated Sinkhorn: the solver above (plain for ti = 0, TI for ti = 1) whose
+ * iterated variable x = f (plain) or fb (TI) is extrapolated every K iterations. From x_0,
+ * K iterations give x_1 .. x_K; after iteration t with t % K == 0 (and t < max_iter, and
+ * the stopping test not met) x is replaced by or_anderson_mix(x_0 .. x_K) and the next cycle
+ * starts from it (its g-step recomputes g). The change delta_t is measured as in
+ * or_sinkhorn, except that it is +inf at the first iteration after an extrapolation. K = 1
+ * extrapolates to x_1 itself, i.e. reproduces or_sinkhorn's iterates. If the mix fails
+ * (singular system) the cycle ends without extrapolation. Returns the iterations run.
+ */
+int or_sinkhorn_anderson(const or_cost *k, const double *alpha, const double *beta, double eps,
+                         double rho1, double rho2, int ti, int K, double r, int max_iter,
+                         double tol, int check_every, int warm_start, double *f, double *g,
+                         double *lambda_out, double *last_delta, double *hist_delta) {
+  const int n = k->n, m = k->m;
+  if (K < 1 || K > 16) return -1;
+  double *loga = (double *)malloc(sizeof(double) * (size_t)n);
+  double *logb = (double *)malloc(sizeof(double) * (size_t)m);
+  for (int i = 0; i < n; ++i) loga[i] = log(alpha[i]);
+  for (int j = 0; j < m; ++j) logb[j] = log(beta[j]);
+  double *fb = (double *)malloc(sizeof(double) * (size_t)n);
+  double *gb = (double *)malloc(sizeof(double) * (size_t)m);
+  double *S = (double *)malloc(sizeof(double) * (size_t)(n > m ? n : m));
+  double *fo = (double *)malloc(sizeof(double) * (size_t)n);
+  double *go = (double *)malloc(sizeof(double) * (size_t)m);
+  double *fr = (double *)malloc(sizeof(double) * (size_t)n);
+  double *gr = (double *)malloc(sizeof(double) * (size_t)m);
+  double *X = (double *)malloc(sizeof(double) * (size_t)(K + 1) * n);  /* x_0 .. x_K */
+  double *xe = (double *)malloc(sizeof(double) * (size_t)n);
+  double c[16];
+  for (int i = 0; i < n; ++i) fb[i] = warm_start ? f[i] : 0.0;
+  for (int j = 0; j < m; ++j) gb[j] = 0.0;
+  memcpy(X, fb, sizeof(double) * (size_t)n);
+  or_state st = {k, loga, logb, eps, rho1, rho2, ti, fb, gb, S};
+  double lam = 0.0, delta = INFINITY;
+  int fresh = 0, t = 0;
+  for (t = 1; t <= max_iter; ++t) {
+    lam = or_iterate(&st, fr, gr);
+    const int kc = (t - 1) % K + 1;
+    memcpy(X + (size_t)kc * n, fb, sizeof(double) * (size_t)n);
+    if (t == 1 || fresh) {
+      delta = INFINITY;
+    } else {
+      double a = sup_diff(n, fr, fo), b = sup_diff(m, gr, go);
+      delta = a > b ? a : b;
+    }
+    fresh = 0;
+    if (hist_delta) hist_delta[t - 1] = delta;
+    memcpy(fo, fr, sizeof(double) * (size_t)n);
+    memcpy(go, gr, sizeof(double) * (size_t)m);
+    if (tol > 0 && check_every > 0 && t % check_every == 0 && delta < tol) break;
+    if (kc == K && t < max_iter) {
+      if (or_anderson_mix(n, K, X, r, c, xe) == 0) {
+        memcpy(fb, xe, sizeof(double) * (size_t)n);
+        fresh = 1;
+      }
+      memcpy(X, fb, sizeof(double) * (size_t)n);
+    }
+  }
+  if (t > max_iter) t = max_iter;
+  memcpy(f, fo, sizeof(double) * (size_t)n);
+  memcpy(g, go, sizeof(double) * (size_t)m);
+  if (lambda_out) *lambda_out = ti ? lam : 0.0;
+  if (last_delta) *last_delta = delta;
+  free(loga); free(logb); free(fb); free(gb); free(S); free(fo); free(go); free(fr); free(gr);
+  free(X); free(xe);
   return t;
 }
 

@@ -403,3 +403,91 @@ def test_zero_weight_convention():
     assert np.max(np.abs(r.f[keep] - r2.f)) < 1e-12
     assert np.max(np.abs(r.g - r2.g)) < 1e-12
     assert np.isfinite(r.f[2])
+
+
+# ---------------------------------------------------------------------------------------
+# Anderson extrapolation (appendix on combining Sinkhorn with Anderson acceleration).
+# ---------------------------------------------------------------------------------------
+def _linear_iterates(A, b, x0, K):
+    X = [x0]
+    for _ in range(K):
+        X.append(A @ X[-1] + b)
+    return np.array(X)
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_anderson_mix_is_exact_on_linear_maps(symmetric):
+    # For T(x) = A x + b with I - A invertible, the residuals are u_k = (A - I) A^k e_0
+    # (e_0 = x_0 - x*). With K = n + 1 of them in R^n some c with sum 1 has U c = 0, and then
+    # sum_k c_k x_{k+1} = x* + A sum_k c_k A^k e_0 = x*: the unregularised (r = 0) mix returns
+    # the fixed point exactly. A wrong residual index, a combination of x_k instead of
+    # x_{k+1}, or a transposed Gram fails this.
+    rng = np.random.default_rng(7 if symmetric else 8)
+    n = 5
+    if symmetric:
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        A = Q @ np.diag(rng.uniform(-0.9, 0.9, n)) @ Q.T
+    else:
+        A = rng.standard_normal((n, n))
+        A *= 0.8 / np.max(np.abs(np.linalg.eigvals(A)))
+    b = rng.standard_normal(n)
+    xs = np.linalg.solve(np.eye(n) - A, b)
+    X = _linear_iterates(A, b, rng.standard_normal(n), n + 1)
+    c, out = oracle.anderson_mix(X, 0.0)
+    assert abs(c.sum() - 1.0) < 1e-12
+    assert np.max(np.abs(out - xs)) < 1e-7 * max(1.0, np.max(np.abs(xs)))
+
+
+def test_anderson_mix_two_step_closed_form():
+    # K = 1: one residual, c = [1], the mix is T(x_0). K = 2 with r = 0: minimising
+    # |c0 u0 + c1 u1|^2 on c0 + c1 = 1 gives c0 = (u1.u1 - u0.u1) / |u0 - u1|^2.
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((2, 6))
+    c, out = oracle.anderson_mix(X, 1e-7)
+    assert np.array_equal(c, [1.0]) and np.array_equal(out, X[1])
+    X = rng.standard_normal((3, 6))
+    u0, u1 = X[1] - X[0], X[2] - X[1]
+    c0 = (u1 @ u1 - u0 @ u1) / ((u0 - u1) @ (u0 - u1))
+    c, out = oracle.anderson_mix(X, 0.0)
+    assert np.allclose(c, [c0, 1.0 - c0], rtol=0, atol=1e-12)
+    assert np.allclose(out, c0 * X[1] + (1.0 - c0) * X[2], rtol=0, atol=1e-12)
+
+
+def test_anderson_mix_is_scale_invariant():
+    # The Gram matrix is normalised before r is added, so the weights do not depend on the
+    # scale of the residuals (an affine map of the iterates maps the mix alike). Without the
+    # normalisation a fixed r = 1e-3 would turn the mix into an average as the residuals
+    # shrink.
+    rng = np.random.default_rng(10)
+    X = rng.standard_normal((5, 40))
+    a = rng.standard_normal(40)
+    c1, o1 = oracle.anderson_mix(X, 1e-3)
+    c2, o2 = oracle.anderson_mix(a + 1e-5 * (X - a), 1e-3)
+    assert np.max(np.abs(c1 - c2)) < 1e-8
+    assert np.max(np.abs(a + 1e-5 * (o1 - a) - o2)) < 1e-12
+
+
+@pytest.mark.parametrize("ti", [False, True])
+def test_anderson_k1_reproduces_sinkhorn(ti):
+    pr = workloads.oned()
+    cost = oracle_cost(pr)
+    base = oracle.sinkhorn(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, ti=ti, max_iter=50)
+    k1 = oracle.sinkhorn_anderson(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, ti=ti, K=1,
+                                  r=1e-7, max_iter=50)
+    assert np.array_equal(base.f, k1.f) and np.array_equal(base.g, k1.g)
+
+
+@pytest.mark.parametrize("ti", [False, True])
+def test_anderson_reaches_the_fixed_point_faster(ti):
+    # The F-potentials are unique, so the accelerated iteration must converge to the same
+    # (f*, g*); the appendix reports faster convergence for each Sinkhorn variant with
+    # K = 4, r = 1e-7.
+    pr = workloads.oned()
+    cost = oracle_cost(pr)
+    star = _solve(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, ti=True)
+    kw = dict(ti=ti, max_iter=20000, tol=1e-12, check_every=10)
+    acc = oracle.sinkhorn_anderson(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, K=4,
+                                   r=1e-7, **kw)
+    std = oracle.sinkhorn(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, **kw)
+    assert rel_inf(acc.f, star.f) < 1e-8 and rel_inf(acc.g, star.g) < 1e-8
+    assert acc.iters < std.iters / 2
