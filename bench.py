@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="cloud3d",
-                    choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16"),
+                    choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16", "anderson"),
                     help="cloud3d (default) is the benchmark step above; the others print one "
                          "JSON line of their own measurement (see extra_workload)")
     return ap.parse_args()
@@ -135,7 +135,10 @@ def extra_workload(args, uot, torch, np, workloads):
               HBM roofline of the stored-cost softmin kernels (4 bytes of C per entry).
     batch2d   4096 problems, N_p, M_p ~ U{64..4096}, D=2: batched TI to change < 1e-6;
               updates/s = sum_p 2 N_p M_p iters_p / wall.
-    highdim16 N=M=50,000, D=16: TI forward to change < 1e-6, then the envelope backward."""
+    highdim16 N=M=50,000, D=16: TI forward to change < 1e-6, then the envelope backward.
+    anderson  the benchmark's 3-D clouds and six (eps, rho): time and iterations to change
+              < 1e-6 of TI and plain Sinkhorn with and without Anderson extrapolation
+              (K = 4, r = 1e-7)."""
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
@@ -210,6 +213,38 @@ def extra_workload(args, uot, torch, np, workloads):
                                  "peak": PEAK_EXP_PER_S / 1e9, "unit": "Gexp/s",
                                  "frac": ups / dt / PEAK_EXP_PER_S, "traffic": None,
                                  "kernel": "k_batched_half (whole solve wall time, not per launch)"}})
+    elif args.workload == "anderson":
+        res = {}
+        total = {"ti": 0.0, "ti_anderson": 0.0, "plain": 0.0, "plain_anderson": 0.0}
+        for eps in (1e-1, 1e-2):
+            for rho in (0.1, 1.0, 10.0):
+                pr = workloads.cloud3d(n=args.n, m=args.n, eps=eps, rho=rho)
+                a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)
+                kw = dict(x=x, y=y, p=2.0, eps=eps, rho1=rho, rho2=rho, max_iter=MAX_ITER, tol=TOL,
+                          check_every=CHECK_EVERY)
+                row = {}
+                if not res:  # first launches of each entry point, untimed
+                    for fn in (uot.ti_sinkhorn, uot.sinkhorn):
+                        fn(a, b, **dict(kw, max_iter=5))
+                    for fn in (uot.ti_sinkhorn_anderson, uot.sinkhorn_anderson):
+                        fn(a, b, K=4, r=1e-7, **dict(kw, max_iter=5))
+                for name, fn, extra in (("ti", uot.ti_sinkhorn, {}),
+                                        ("ti_anderson", uot.ti_sinkhorn_anderson, dict(K=4, r=1e-7)),
+                                        ("plain", uot.sinkhorn, {}),
+                                        ("plain_anderson", uot.sinkhorn_anderson, dict(K=4, r=1e-7))):
+                    (_, _, info), dt = _timed(torch, lambda: fn(a, b, **kw, **extra))
+                    row[name] = {"iters": info.iters, "seconds": round(dt, 5),
+                                 "converged": info.converged}
+                    total[name] += dt
+                res["eps=%g,rho=%g" % (eps, rho)] = row
+                print("anderson eps=%g rho=%g %s" % (eps, rho, row), file=sys.stderr, flush=True)
+        out.update({"metric": "seconds to change < 1e-6, TI with Anderson extrapolation, summed "
+                              "over six (eps, rho)", "unit": "s", "higher_is_better": False,
+                    "value": total["ti_anderson"], "totals_seconds": total,
+                    "config": {"workload": "3-D clouds N=M=%d, eps in {0.1,0.01} x rho in "
+                                           "{0.1,1,10}, K=4, r=1e-7, change checked every %d"
+                                           % (args.n, CHECK_EVERY)},
+                    "time_to_tol": res, "roofline": None})
     else:  # highdim16
         pr = workloads.highdim16()
         a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)

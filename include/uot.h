@@ -112,7 +112,8 @@ enum {
   UOT_WS_SOLVE = 0,     /* uot_sinkhorn, uot_ti_sinkhorn                                   */
   UOT_WS_DUAL = 1,      /* uot_dual_value                                                  */
   UOT_WS_PLAN = 2,      /* uot_plan_apply (size independent of k up to k = 64)             */
-  UOT_WS_BACKWARD = 3   /* uot_backward                                                    */
+  UOT_WS_BACKWARD = 3,  /* uot_backward                                                    */
+  UOT_WS_ANDERSON = 4   /* uot_sinkhorn_anderson, uot_ti_sinkhorn_anderson (any k <= 8)    */
 };
 
 /* Workspace bytes needed by the entry point `which` for this cost (0 on invalid input). */
@@ -146,6 +147,38 @@ uot_status uot_sinkhorn(const uot_cost *cost, const float *alpha, const float *b
 uot_status uot_ti_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,
                            const uot_params *params, float *f, float *g, void *workspace,
                            size_t workspace_bytes, uot_info *info, void *stream);
+
+/* Anderson extrapolation settings (see uot_sinkhorn_anderson). */
+typedef struct {
+  int32_t k;  /* iterations per extrapolation = residuals in the mix, 2 <= k <= 8              */
+  double r;   /* regularisation added to the normalised Gram matrix, finite and > 0           */
+} uot_anderson;
+
+/*
+ * Plain or translation-invariant Sinkhorn with Anderson extrapolation (appendix on
+ * combining Sinkhorn with Anderson acceleration). The iterated variable x is f for plain
+ * Sinkhorn and fb for TI; one iteration T maps x to the next x through a g-step and an
+ * f-step as in uot_sinkhorn / uot_ti_sinkhorn. From x_0, k iterations give x_1 .. x_k, the
+ * residuals u_i = x_{i+1} - x_i form U, and, with G = U^T U divided by its Frobenius norm,
+ *   c = (G + r I)^{-1} 1 / (1^T (G + r I)^{-1} 1),   x <- sum_i c_i x_{i+1},
+ * after which the next k iterations start from the extrapolated x. No extrapolation
+ * follows the last iteration (max_iter), and the change of the first iteration after an
+ * extrapolation is +inf, so the stopping test always compares two plain iterates. The
+ * paper's experiment uses k = 4, r = 1e-7.
+ * Arguments and conventions as uot_sinkhorn (params.warm_start gives x_0 = f for plain
+ * Sinkhorn and fb = f for TI); acc (host) holds k and r, and k outside 2..8 or r not finite
+ * and > 0 give UOT_ERR_INVALID. The workspace is UOT_WS_ANDERSON's (the iterates of one
+ * cycle, k + 1 vectors of n floats, beside the solver's own). A Gram system that cannot be
+ * solved (non-finite entries) ends the solve with UOT_ERR_NUMERIC.
+ */
+uot_status uot_sinkhorn_anderson(const uot_cost *cost, const float *alpha, const float *beta,
+                                 const uot_params *params, const uot_anderson *acc, float *f,
+                                 float *g, void *workspace, size_t workspace_bytes,
+                                 uot_info *info, void *stream);
+uot_status uot_ti_sinkhorn_anderson(const uot_cost *cost, const float *alpha, const float *beta,
+                                    const uot_params *params, const uot_anderson *acc, float *f,
+                                    float *g, void *workspace, size_t workspace_bytes,
+                                    uot_info *info, void *stream);
 
 /*
  * Dual value F_eps(f, g) of eq. (dual-uot-kl), which equals UOT(alpha, beta) at the

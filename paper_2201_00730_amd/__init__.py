@@ -29,7 +29,7 @@ _lib = None
 
 UOT_OK, UOT_ERR_INVALID, UOT_ERR_HIP, UOT_ERR_NUMERIC, UOT_ERR_WORKSPACE = range(5)
 UOT_COST_DENSE, UOT_COST_POINTS = 0, 1
-UOT_WS_SOLVE, UOT_WS_DUAL, UOT_WS_PLAN, UOT_WS_BACKWARD = range(4)
+UOT_WS_SOLVE, UOT_WS_DUAL, UOT_WS_PLAN, UOT_WS_BACKWARD, UOT_WS_ANDERSON = range(5)
 
 
 class UOTError(RuntimeError):
@@ -48,6 +48,10 @@ class _Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+
+
+class _Anderson(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("r", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -82,6 +86,11 @@ def load_library():
     for name in ("uot_sinkhorn", "uot_ti_sinkhorn"):
         fn = getattr(lib, name)
         fn.argtypes = [CP, P, P, ctypes.POINTER(_Params), P, P, P, S, ctypes.POINTER(_Info), P]
+        fn.restype = ctypes.c_int
+    for name in ("uot_sinkhorn_anderson", "uot_ti_sinkhorn_anderson"):
+        fn = getattr(lib, name)
+        fn.argtypes = [CP, P, P, ctypes.POINTER(_Params), ctypes.POINTER(_Anderson), P, P, P, S,
+                       ctypes.POINTER(_Info), P]
         fn.restype = ctypes.c_int
     lib.uot_dual_value.argtypes = [CP, P, P, D, D, D, P, P, P, S, ctypes.POINTER(D), P]
     lib.uot_dual_value.restype = ctypes.c_int
@@ -232,7 +241,7 @@ def _workspace(lib, cr: _CostRef, which: int):
 
 def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, eps: float,
            rho1: float, rho2: float | None = None, max_iter: int = 1000, tol: float = 0.0,
-           check_every: int = 10, f0=None, workspace=None):
+           check_every: int = 10, f0=None, workspace=None, anderson=None):
     _require_gpu()
     lib = load_library()
     cr = _CostRef(C, x, y, p)
@@ -246,10 +255,14 @@ def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, ep
         f.copy_(_f32(f0, "f0").reshape(-1))
     prm = _Params(float(eps), float(rho1), float(rho2), int(max_iter), float(tol), int(check_every),
                   int(f0 is not None))
-    ws = workspace if workspace is not None else _workspace(lib, cr, UOT_WS_SOLVE)
+    which = UOT_WS_SOLVE if anderson is None else UOT_WS_ANDERSON
+    ws = workspace if workspace is not None else _workspace(lib, cr, which)
     info = _Info()
-    st = getattr(lib, name)(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), ctypes.byref(prm), _ptr(f),
-                            _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(info), _stream())
+    args = [ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), ctypes.byref(prm)]
+    if anderson is not None:
+        args.append(ctypes.byref(_Anderson(int(anderson[0]), float(anderson[1]))))
+    st = getattr(lib, name)(*args, _ptr(f), _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(info),
+                            _stream())
     _check(st)
     return f, g, Info(info.iters, bool(info.converged), info.last_change, info.lambda_)
 
@@ -264,6 +277,19 @@ def ti_sinkhorn(alpha, beta, **kw):
     """Translation-invariant (H-) Sinkhorn (Sec. 3, Prop. 4; App. B for rho1 != rho2).
     Returns the translated potentials Phi(fb, gb) = (f, g) and Info."""
     return _solve("uot_ti_sinkhorn", alpha, beta, **kw)
+
+
+def sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, **kw):
+    """Plain Sinkhorn with Anderson extrapolation of f every K iterations (appendix on
+    Anderson acceleration; the paper's experiment uses K = 4, r = 1e-7). Other keyword
+    args as ``sinkhorn``. Returns (f, g, Info)."""
+    return _solve("uot_sinkhorn_anderson", alpha, beta, anderson=(K, r), **kw)
+
+
+def ti_sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, **kw):
+    """Translation-invariant Sinkhorn with Anderson extrapolation of fb every K iterations.
+    Other keyword args as ``ti_sinkhorn``. Returns the translated (f, g, Info)."""
+    return _solve("uot_ti_sinkhorn_anderson", alpha, beta, anderson=(K, r), **kw)
 
 
 def dual_value(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: float,

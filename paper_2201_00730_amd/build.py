@@ -22,6 +22,7 @@ SOURCES = [
     "kernels_epilogue.hip",
     "kernels_apply.hip",
     "kernels_batched.hip",
+    "kernels_anderson.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_center(const float *x, int n, const 
     st->pos_a = 0;
     st->pos_b = 0;
     st->iter = 0;
-    st->ticket = 0u;
+    st->fresh = 0;
   }
 }
 

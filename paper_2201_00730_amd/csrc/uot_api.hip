@@ -174,6 +174,8 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
 struct Layout {
   size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0;
   size_t dual = 0, rowsum_x = 0, rowsum_y = 0, tmp_x = 0, tmp_y = 0, scratch = 0, total = 0;
+  size_t hist = 0, taus = 0, gram = 0, acc_c = 0;  // Anderson
+  int64_t ldh = 0;
   HalfShape g, f;  // g-step: targets y (columns), sources x; f-step: targets x (rows), sources y
 };
 
@@ -219,6 +221,13 @@ Layout make_layout(const uot_cost *c, int which) {
     L.tmp_y = take((size_t)m * sizeof(float));
     const size_t a = apply_partial_bytes(n, m), b = apply_partial_bytes(m, n);
     L.scratch = take(a > b ? a : b);
+  }
+  if (which == UOT_WS_ANDERSON) {
+    L.ldh = ((int64_t)n + 63) / 64 * 64;
+    L.hist = take((size_t)(kAndersonMaxK + 1) * L.ldh * sizeof(float));
+    L.taus = take((size_t)(kAndersonMaxK + 1) * sizeof(double));
+    L.gram = take(anderson_gram_bytes(n));
+    L.acc_c = take((size_t)kAndersonMaxK * sizeof(double));
   }
   L.total = off;
   return L;
@@ -472,7 +481,10 @@ Epilogue epilogue_for(const Ctx &k, bool g_step) {
   return ep;
 }
 
-uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
+// snap, tau_out (f-steps of an Anderson solve, else NULL): receive the new stored f and
+// its translation tau_f.
+uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every, float *snap = nullptr,
+                     double *tau_out = nullptr) {
   SolveState *st = k.st();
   UOT_TRY(softmin_partials(k, g_step, &st->done));
   const HalfShape &h = g_step ? k.L.g : k.L.f;
@@ -491,6 +503,7 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ca.ep = epilogue_for(k, g_step);
   ca.sc = k.sc;
   ca.eps = k.eps;
+  ca.snap = snap;
   UOT_HIP(launch_combine(ca, k.s));
   ReduceArgs ra;
   ra.bparts = ca.bparts;
@@ -505,6 +518,7 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every) {
   ra.tau2 = k.rho2 / (k.rho1 + k.rho2);
   ra.tol = tol;
   ra.check_every = check_every;
+  ra.tau_out = tau_out;
   k.pending = ra;  // run beside the next softmin, or by flush_reduce()
   k.has_pending = true;
   return UOT_OK;
@@ -550,9 +564,54 @@ uot_status check_scalars(double eps, double rho1, double rho2) {
   return UOT_OK;
 }
 
+// Anderson cycle end: extrapolate x from the stored iterates, rebuild the x records with
+// their tilted-mass partials, and leave the restart reduction pending.
+uot_status anderson_step(const Ctx &k, const uot_anderson *acc) {
+  UOT_TRY(flush_reduce(k));  // tau_f of the last iterate
+  AndersonArgs aa;
+  aa.H = at<float>(k.ws, k.L.hist);
+  aa.ldh = k.L.ldh;
+  aa.taus = at<double>(k.ws, k.L.taus);
+  aa.n = k.n;
+  aa.K = acc->k;
+  aa.r = acc->r;
+  aa.gram = at<double>(k.ws, k.L.gram);
+  aa.c = at<double>(k.ws, k.L.acc_c);
+  aa.pot = at<float>(k.ws, k.L.pot_x);
+  aa.H0 = at<float>(k.ws, k.L.hist);
+  aa.tau0 = aa.taus;
+  aa.st = k.st();
+  UOT_HIP(launch_anderson(aa, k.s));
+  int nbx = 0;
+  UOT_TRY(build_records(k, true, at<float>(k.ws, k.L.pot_x), false, true, &nbx));
+  ReduceArgs rr;
+  rr.bparts = at<BlockPart>(k.ws, k.L.bparts);
+  rr.nb = nbx;
+  rr.st = k.st();
+  rr.kind = kReduceRestart;
+  rr.ti = k.ti;
+  rr.rho1 = k.rho1;
+  rr.rho2 = k.rho2;
+  rr.kappa_t = 0.0;
+  rr.tau1 = rr.tau2 = 0.0;
+  rr.tol = 0.0;
+  rr.check_every = 1;
+  k.pending = rr;
+  k.has_pending = true;
+  return UOT_OK;
+}
+
+uot_status check_anderson(const uot_anderson *acc) {
+  if (acc == nullptr) return fail(UOT_ERR_INVALID, "anderson settings are NULL");
+  if (acc->k < 2 || acc->k > kAndersonMaxK)
+    return fail(UOT_ERR_INVALID, "anderson k=%d must be in 2..%d", acc->k, kAndersonMaxK);
+  if (!finite_pos(acc->r)) return fail(UOT_ERR_INVALID, "anderson r=%g must be finite and > 0", acc->r);
+  return UOT_OK;
+}
+
 uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const uot_params *P,
                  float *f, float *g, void *workspace, size_t workspace_bytes, uot_info *info,
-                 void *stream, bool ti) {
+                 void *stream, bool ti, const uot_anderson *acc = nullptr) {
   UOT_TRY(check_cost(c));
   UOT_TRY(check_params(P));
   UOT_TRY(check_cost_ptrs(c));
@@ -573,7 +632,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   k.rho2 = P->rho2;
   k.sc = kLog2e / P->eps;
   k.ti = ti;
-  k.L = make_layout(c, UOT_WS_SOLVE);
+  k.L = make_layout(c, acc ? UOT_WS_ANDERSON : UOT_WS_SOLVE);
   k.s = static_cast<hipStream_t>(stream);
   Workspace w;
   UOT_TRY(acquire(w, workspace, workspace_bytes, k.L.total));
@@ -603,6 +662,11 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   ri.check_every = 1;
   UOT_HIP(launch_reduce(ri, k.s));
   UOT_TRY(build_records(k, false, nullptr, true, false, nullptr));
+  if (acc) {  // x_0 of the first cycle: the starting f (untranslated), tau 0
+    UOT_HIP(hipMemcpyAsync(at<float>(k.ws, k.L.hist), at<float>(k.ws, k.L.pot_x),
+                           (size_t)k.n * sizeof(float), hipMemcpyDeviceToDevice, k.s));
+    UOT_HIP(hipMemsetAsync(at<double>(k.ws, k.L.taus), 0, (kAndersonMaxK + 1) * sizeof(double), k.s));
+  }
   UOT_TRY(read_state(st, pin.h[0], k.s));
   if (pin.h[0].error & kErrWeights)
     return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
@@ -623,8 +687,17 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   while (issued < P->max_iter && !stop) {
     const int todo = (P->max_iter - issued) < chunk ? (P->max_iter - issued) : chunk;
     for (int t = 0; t < todo; ++t) {
+      const int it = issued + t + 1;  // 1-based iteration number
       UOT_TRY(half_step(k, true, P->tol, P->check_every));
-      UOT_TRY(half_step(k, false, P->tol, P->check_every));
+      if (acc) {
+        const int kc = (it - 1) % acc->k + 1;  // position of this iterate in its cycle
+        UOT_TRY(half_step(k, false, P->tol, P->check_every,
+                          at<float>(k.ws, k.L.hist) + (size_t)kc * k.L.ldh,
+                          at<double>(k.ws, k.L.taus) + kc));
+        if (kc == acc->k && it < P->max_iter) UOT_TRY(anderson_step(k, acc));
+      } else {
+        UOT_TRY(half_step(k, false, P->tol, P->check_every));
+      }
     }
     issued += todo;
     UOT_TRY(flush_reduce(k));
@@ -1076,7 +1149,7 @@ extern "C" {
 
 size_t uot_workspace_bytes(const uot_cost *cost, int32_t which) {
   if (uot::check_cost(cost) != UOT_OK) return 0;
-  if (which < UOT_WS_SOLVE || which > UOT_WS_BACKWARD) return 0;
+  if (which < UOT_WS_SOLVE || which > UOT_WS_ANDERSON) return 0;
   return uot::make_layout(cost, which).total;
 }
 
@@ -1085,6 +1158,28 @@ uot_status uot_sinkhorn(const uot_cost *cost, const float *alpha, const float *b
                         size_t workspace_bytes, uot_info *info, void *stream) {
   uot::g_last_error.clear();
   return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream, false);
+}
+
+uot_status uot_sinkhorn_anderson(const uot_cost *cost, const float *alpha, const float *beta,
+                                 const uot_params *params, const uot_anderson *acc, float *f,
+                                 float *g, void *workspace, size_t workspace_bytes,
+                                 uot_info *info, void *stream) {
+  uot::g_last_error.clear();
+  const uot_status s = uot::check_anderson(acc);
+  if (s != UOT_OK) return s;
+  return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream,
+                    false, acc);
+}
+
+uot_status uot_ti_sinkhorn_anderson(const uot_cost *cost, const float *alpha, const float *beta,
+                                    const uot_params *params, const uot_anderson *acc, float *f,
+                                    float *g, void *workspace, size_t workspace_bytes,
+                                    uot_info *info, void *stream) {
+  uot::g_last_error.clear();
+  const uot_status s = uot::check_anderson(acc);
+  if (s != UOT_OK) return s;
+  return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream,
+                    true, acc);
 }
 
 uot_status uot_ti_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,

@@ -173,6 +173,9 @@ static __device__ void reduce_scalars(const ReduceArgs &a) {
     st->sB = 0.0;
     if (!st->pos_a || !st->pos_b) st->error |= kErrWeights;
     set_done(st, st->error ? 1 : 0);
+  } else if (a.kind == kReduceRestart) {
+    st->sA = -a.rho1 * L;  // Smin_alpha^rho1 of the extrapolated x, stored untranslated
+    st->tau_f = 0.0;
   } else if (a.kind == kReduceG) {
     const double sBhat = -a.rho2 * L;  // Smin_beta^rho2(ghat)
     const double tg = a.ti ? a.kappa_t / (1.0 - a.kappa_t) * sBhat : 0.0;
@@ -191,18 +194,20 @@ static __device__ void reduce_scalars(const ReduceArgs &a) {
       st->sA = sAhat;
     }
     st->tau_f = tf;
+    if (a.tau_out) *a.tau_out = tf;
     st->lambda = lam;
     const double off_f = tf + lam, off_g = st->tau_g - lam;
     const int it = st->iter + 1;
     st->iter = it;
     double delta = INFINITY;
-    if (it > 1) {
+    if (it > 1 && !st->fresh) {
       const double cf = off_f - st->off_f_prev, cg = off_g - st->off_g_prev;
       const double df = fmax(dmx + cf, -(dmn + cf));
       const double dg = fmax(st->gdiff_max + cg, -(st->gdiff_min + cg));
       delta = fmax(df, dg);
     }
     st->delta = delta;
+    st->fresh = 0;
     st->off_f_prev = off_f;
     st->off_g_prev = off_g;
     if (!isfinite(off_f) || !isfinite(off_g) || isnan(delta)) st->error |= kErrNumeric;
@@ -273,6 +278,7 @@ static __device__ bool combine_range(const CombineArgs &a, int t_begin, double &
     const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
     const float hf = (float)hnew;
     a.pot[t] = hf;
+    if (a.snap) a.snap[t] = hf;
     dmx = dmn = (double)hf - (double)old;
     write_record<D, MODE>(a.rec_out, t, yc, yn2, hf, w, a.sc);
     if (w > 0.0f) { mm = log((double)w) - (double)hf / a.ep.rho_t; ms = 1.0; }

@@ -96,7 +96,7 @@ struct SolveState {
   int32_t error;      // bit 1: invalid weights, bit 2: non-finite result
   int32_t pos_a;      // some alpha_i > 0
   int32_t pos_b;      // some beta_j > 0
-  uint32_t ticket;    // arrival counter of the combine kernel's blocks (0 between launches)
+  int32_t fresh;      // 1 after an Anderson extrapolation: the next change is +inf
   double mu[kMaxDim]; // common centring of x and y (points costs)
 };
 
@@ -153,6 +153,7 @@ struct ReduceArgs {
   double rho1, rho2, kappa_t, tau1, tau2;
   double tol;
   int check_every;
+  double *tau_out = nullptr;  // kReduceF with Anderson: receives tau_f
 };
 
 struct PointsArgs {
@@ -211,7 +212,9 @@ hipError_t launch_dense_rows(const DenseArgs &a, hipStream_t st, const LaunchTim
 int dense_cols_per_block();
 int dense_rows_per_block();
 
-enum ReduceKind : int { kReduceInit = 0, kReduceG = 1, kReduceF = 2 };
+// kReduceRestart: the x side was replaced by an Anderson extrapolation written without
+// translation: Smin_alpha^rho1 of it from the block partials, tau_f = 0.
+enum ReduceKind : int { kReduceInit = 0, kReduceG = 1, kReduceF = 2, kReduceRestart = 3 };
 
 // Epilogue kernels (kernels_epilogue.hip).
 struct CombineArgs {
@@ -228,11 +231,13 @@ struct CombineArgs {
   Epilogue ep;
   double sc;           // log2(e)/eps (double)
   double eps;
+  float *snap = nullptr;  // Anderson: receives a copy of the new stored potential
 };
 
 // Combine + epilogue; each block writes its (tilted mass, change range) partial to bparts,
 // which launch_reduce then reduces into the scalar state (a one-block launch: cheaper than
-// an atomic ticket and a last-block reduction inside the combine).
+// an atomic ticket and a last-block reduction inside the combine), or runs as a spare
+// block of the next matrix-core softmin launch.
 hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
 int combine_blocks(int nt);
 
@@ -315,5 +320,25 @@ struct WeightGradArgs {
 hipError_t launch_weight_grad_from_rowsum(const WeightGradArgs &a, const double *mass_other,
                                           hipStream_t s);
 hipError_t launch_sum(const float *w, int n, double *out, hipStream_t s);
+
+// Anderson extrapolation (kernels_anderson.hip): from the stored iterates of one cycle,
+// x_k = H[k] + taus[k] (k = 0..K), computes c and writes x = sum_k c_k x_{k+1} to pot and
+// H[0], taus[0] = 0, fresh = 1. gram: anderson_gram_bytes(n); c: kAndersonMaxK doubles.
+constexpr int kAndersonMaxK = 8;
+struct AndersonArgs {
+  const float *H;      // [K + 1, ldh]
+  int64_t ldh;
+  double *taus;        // [K + 1]
+  int n, K;
+  double r;
+  double *gram;
+  double *c;
+  float *pot;          // stored potential of the x side (out)
+  float *H0;           // H[0] (out)
+  double *tau0;        // taus[0] (out)
+  SolveState *st;
+};
+hipError_t launch_anderson(const AndersonArgs &a, hipStream_t s);
+size_t anderson_gram_bytes(int n);
 
 }  // namespace uot

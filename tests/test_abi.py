@@ -84,6 +84,28 @@ def test_solver_rejects_bad_params_before_any_launch(lib, field, value):
         assert lib.uot_last_error()
 
 
+@pytest.mark.parametrize("k,r", [(1, 1e-7), (9, 1e-7), (0, 1e-7), (4, 0.0), (4, -1e-7),
+                                 (4, float("nan")), (4, float("inf"))])
+def test_anderson_rejects_bad_settings_before_any_launch(lib, k, r):
+    c = _cost()
+    prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
+    acc = uot._Anderson(k, r)
+    for fn in (lib.uot_sinkhorn_anderson, lib.uot_ti_sinkhorn_anderson):
+        st = fn(ctypes.byref(c), None, None, ctypes.byref(prm), ctypes.byref(acc), None, None, None,
+                0, None, None)
+        assert st == uot.UOT_ERR_INVALID
+        assert b"anderson" in lib.uot_last_error()
+        assert fn(ctypes.byref(c), None, None, ctypes.byref(prm), None, None, None, None, 0, None,
+                  None) == uot.UOT_ERR_INVALID
+
+
+def test_anderson_workspace_is_larger(lib):
+    c = _cost(n=1000, m=900)
+    solve = lib.uot_workspace_bytes(ctypes.byref(c), uot.UOT_WS_SOLVE)
+    acc = lib.uot_workspace_bytes(ctypes.byref(c), uot.UOT_WS_ANDERSON)
+    assert acc >= solve + 9 * 1000 * 4
+
+
 def test_solver_rejects_bad_cost(lib):
     prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
     for bad in (_cost(n=0), _cost(d=100), _cost(p=0.0), _cost(kind=0, ldc=3)):

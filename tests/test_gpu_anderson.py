@@ -1,0 +1,165 @@
+"""GPU parity of the Anderson-extrapolated solvers (appendix on combining Sinkhorn with
+Anderson acceleration) against the oracle's ``sinkhorn_anderson`` on identical float32
+inputs, through the C ABI.
+
+Tolerance: relative 1e-5 (||a - b||_inf / ||b||_inf), as for the other solvers. Iteration
+parity runs both sides the same number of iterations from f_0 = 0 (the extrapolations fall
+after iterations K, 2K, ...); converged parity runs both to tolerance; the full-size check
+tests properties that hold at any iteration count.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_00730_amd as uot
+import workloads
+from tests.helpers import oracle_cost, rel_inf
+from tests.test_gpu_parity import _sample_cols_softmin, _sample_rows_softmin, cost_kw, dev, run_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+R = 1e-7  # the paper's regularisation
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu_acc(pr, ti, iters, K, r=R, tol=0.0, ce=1, f0=None, kw=None):
+    fn = uot.ti_sinkhorn_anderson if ti else uot.sinkhorn_anderson
+    kw = kw if kw is not None else cost_kw(pr)
+    f, g, info = fn(dev(pr.alpha), dev(pr.beta), K=K, r=r, eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2,
+                    max_iter=iters, tol=tol, check_every=ce,
+                    f0=None if f0 is None else dev(np.asarray(f0, np.float32)), **kw)
+    torch.cuda.synchronize()
+    return f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), info
+
+
+def run_oracle_acc(pr, ti, iters, K, r=R, tol=0.0, ce=1, f0=None):
+    return oracle.sinkhorn_anderson(oracle_cost(pr), pr.alpha.astype(np.float64),
+                                    pr.beta.astype(np.float64), pr.eps, pr.rho1, pr.rho2, ti=ti,
+                                    K=K, r=r, max_iter=iters, tol=tol, check_every=ce, f0=f0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    uot.load_library()
+
+
+# Plain Sinkhorn's slow mode is the translation f + c, g - c (contraction k1 k2, Sec. 3);
+# the extrapolation steps along it with weights of order 1 / (1 - k1 k2) (50 here), so it
+# magnifies the float32 rounding of the iterates cycle after cycle. Plain trajectories are
+# therefore compared over the first cycles only; past them both sides still converge to the
+# same optimum (test_anderson_converged). TI has no such mode and is compared throughout.
+ITERATION_CASES = [(True, K, it) for K in (2, 4, 8) for it in (3, 8, 9, 30)] + \
+                  [(False, K, it) for K in (2, 4, 8) for it in (3, 8, 9)]
+
+
+@pytest.mark.parametrize("ti,K,iters", ITERATION_CASES)
+def test_anderson_iteration_parity(ti, K, iters):
+    pr = workloads.oned()
+    _say("anderson oned ti=%s K=%d iters=%d" % (ti, K, iters))
+    f, g, info = run_gpu_acc(pr, ti, iters, K)
+    r = run_oracle_acc(pr, ti, iters, K)
+    _say("  rel f %.3g g %.3g" % (rel_inf(f, r.f), rel_inf(g, r.g)))
+    assert info.iters == iters
+    assert rel_inf(f, r.f) < TOL, rel_inf(f, r.f)
+    assert rel_inf(g, r.g) < TOL, rel_inf(g, r.g)
+
+
+CASES = [
+    # (n, m, d, p, dense)
+    (7, 64, 3, 2.0, False),
+    (200, 137, 3, 2.0, False),
+    (1000, 1337, 2, 2.0, False),
+    (333, 517, 5, 2.0, False),
+    (211, 300, 3, 1.5, False),
+    (513, 257, 4, 2.0, True),
+]
+
+
+@pytest.mark.parametrize("ti", [True, False])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d_m%d_d%d_p%g_%s" % (c[0], c[1], c[2], c[3], "dense" if c[4] else "pts"))
+def test_anderson_ragged_parity(case, ti):
+    n, m, d, p, dense = case
+    pr = workloads.random_small(n, m, d=d, seed=n * 31 + m, eps=0.05, rho1=0.7, rho2=2.0, p=p,
+                                dense=dense)
+    if dense:
+        pr.x = pr.y = None
+    _say("anderson ragged %s ti=%s" % (case, ti))
+    f, g, _ = run_gpu_acc(pr, ti, 13, 4)
+    r = run_oracle_acc(pr, ti, 13, 4)
+    _say("  rel f %.3g g %.3g" % (rel_inf(f, r.f), rel_inf(g, r.g)))
+    assert rel_inf(f, r.f) < TOL, rel_inf(f, r.f)
+    assert rel_inf(g, r.g) < TOL, rel_inf(g, r.g)
+
+
+@pytest.mark.parametrize("ti", [True, False])
+def test_anderson_converged(ti):
+    """To change < 1e-6 (checked every 10 iterations): the GPU stops within a check or two of
+    the oracle under the same rule, in fewer than half the iterations of the solver without
+    extrapolation, as close to the optimum as the oracle's accelerated run."""
+    pr = workloads.oned()
+    _say("anderson oned converged ti=%s" % ti)
+    star = oracle.sinkhorn(oracle_cost(pr), pr.alpha.astype(np.float64), pr.beta.astype(np.float64),
+                           pr.eps, pr.rho1, pr.rho2, ti=True, max_iter=100000, tol=1e-13,
+                           check_every=1)
+    f, g, info = run_gpu_acc(pr, ti, 20000, 4, tol=1e-6, ce=10)
+    r = run_oracle_acc(pr, ti, 20000, 4, tol=1e-6, ce=10)
+    _, _, plain = run_gpu(pr, ti, 20000, tol=1e-6, ce=10)
+    err_gpu = np.max(np.abs(f - star.f))
+    err_orc = np.max(np.abs(r.f - star.f))
+    _say("  iters gpu %d oracle %d without %d; err gpu %.3g oracle %.3g"
+         % (info.iters, r.iters, plain.iters, err_gpu, err_orc))
+    assert info.converged and info.last_change < 1e-6
+    assert abs(info.iters - r.iters) <= 20, (info.iters, r.iters)
+    assert info.iters < plain.iters / 2, (info.iters, plain.iters)
+    assert err_gpu <= 1.5 * err_orc + 1e-6, (err_gpu, err_orc)
+
+
+def test_anderson_warm_start():
+    """A warm start gives x_0 = f for the first cycle on both sides."""
+    pr = workloads.random_small(120, 90, d=3, seed=9, eps=0.05, rho1=0.5, rho2=2.0)
+    f0 = np.linspace(-0.3, 0.2, 120).astype(np.float32)
+    for ti in (True, False):
+        f, g, _ = run_gpu_acc(pr, ti, 10, 3, f0=f0)
+        r = run_oracle_acc(pr, ti, 10, 3, f0=f0.astype(np.float64))
+        assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL, (rel_inf(f, r.f), rel_inf(g, r.g))
+
+
+@pytest.mark.parametrize("eps,rho", [(1e-2, 1.0), (1e-1, 10.0)])
+def test_anderson_cloud3d_full_size_sampled(eps, rho):
+    """N = M = 20,000 in the launch configuration of the benchmark: after 21 iterations (five
+    extrapolations) the reported potentials satisfy the f-update with respect to their own g
+    on sampled rows, the tilted masses balance (Prop. 1-2), and one plain iteration from f
+    gives the sampled column softmins."""
+    pr = workloads.cloud3d(eps=eps, rho=rho)
+    _say("anderson cloud3d full size eps=%g rho=%g" % (eps, rho))
+    kw = dict(x=dev(pr.x), y=dev(pr.y), p=2.0)
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(pr.n, size=256, replace=False))
+    cols = np.sort(rng.choice(pr.m, size=256, replace=False))
+    k1 = pr.rho1 / (pr.eps + pr.rho1)
+    k2 = pr.rho2 / (pr.eps + pr.rho2)
+    f, g, info = run_gpu_acc(pr, True, 21, 4, kw=kw)
+    assert info.iters == 21
+    ref_f = k1 * _sample_rows_softmin(pr, g, rows)
+    assert rel_inf(f[rows], ref_f) < TOL, rel_inf(f[rows], ref_f)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    tau1 = pr.rho1 / (pr.rho1 + pr.rho2)
+    lhs = tau1 * oracle.smin_vec(b, g, pr.rho2)
+    rhs = (1 - tau1) * oracle.smin_vec(a, f, pr.rho1)
+    assert abs(lhs - rhs) <= TOL * max(abs(lhs), np.max(np.abs(f))), (lhs, rhs)
+    _, g1, _ = run_gpu(pr, False, 1, f0=f, kw=kw)
+    ref_g = k2 * _sample_cols_softmin(pr, f.astype(np.float32).astype(np.float64), cols)
+    assert rel_inf(g1[cols], ref_g) < TOL, rel_inf(g1[cols], ref_g)
+    # and it is closer to convergence than 21 iterations without extrapolation
+    fp, gp, _ = run_gpu(pr, True, 21, kw=kw)
+    f2, g2, _ = run_gpu(pr, True, 22, kw=kw)
+    fa, ga, _ = run_gpu_acc(pr, True, 22, 4, kw=kw)
+    assert np.max(np.abs(fa - f)) <= np.max(np.abs(f2 - fp)), (np.max(np.abs(fa - f)), np.max(np.abs(f2 - fp)))
