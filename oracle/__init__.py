@@ -65,6 +65,18 @@ def _load():
             lib.or_lambda_star.restype = D
             lib.or_sinkhorn.argtypes = [CP, P, P, D, D, D, I, I, D, I, I, P, P, P, P, P, P, P]
             lib.or_sinkhorn.restype = I
+            lib.or_phistar.argtypes = [I, D, D]
+            lib.or_phistar.restype = D
+            lib.or_phistar_prime.argtypes = [I, D, D]
+            lib.or_phistar_prime.restype = D
+            lib.or_dual_update.argtypes = [I, D, D, D]
+            lib.or_dual_update.restype = D
+            lib.or_lambda_star_div.argtypes = [I, I, I, P, P, P, P, D, D]
+            lib.or_lambda_star_div.restype = D
+            lib.or_dual_value_div.argtypes = [CP, P, P, D, D, D, I, P, P]
+            lib.or_dual_value_div.restype = D
+            lib.or_sinkhorn_div.argtypes = [CP, P, P, D, D, D, I, I, I, D, I, P, P, P, P]
+            lib.or_sinkhorn_div.restype = I
             lib.or_anderson_mix.argtypes = [I, I, P, D, P, P]
             lib.or_anderson_mix.restype = I
             lib.or_sinkhorn_anderson.argtypes = [CP, P, P, D, D, D, I, I, D, I, D, I, I, P, P, P, P, P]
@@ -268,6 +280,62 @@ def sinkhorn_anderson(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: fl
         raise ValueError("K must be in 1..16")
     return SinkhornResult(f=f, g=g, iters=it, last_delta=last.value, lam=lam.value,
                           hist_delta=None if hd is None else hd[:it].copy())
+
+
+DIVERGENCES = {"kl": 0, "berg": 1}
+
+
+def _div(div) -> int:
+    if div not in DIVERGENCES:
+        raise ValueError("divergence must be one of %s" % sorted(DIVERGENCES))
+    return DIVERGENCES[div]
+
+
+def phistar(div: str, rho: float, x: float) -> float:
+    """phi*(x): KL rho (e^{x/rho} - 1); Berg -rho log(1 - x/rho) (x < rho)."""
+    return _load().or_phistar(_div(div), float(rho), float(x))
+
+
+def phistar_prime(div: str, rho: float, x: float) -> float:
+    return _load().or_phistar_prime(_div(div), float(rho), float(x))
+
+
+def dual_update(div: str, rho: float, eps: float, S: float) -> float:
+    """g = -aprox_{phi*}(-S): the root of e^{(g - S)/eps} = phi*'(-g) (Sec. 3)."""
+    return _load().or_dual_update(_div(div), float(rho), float(eps), float(S))
+
+
+def lambda_star_div(div: str, alpha, beta, fb, gb, rho1: float, rho2: float) -> float:
+    """lambda*(fb, gb): root of <alpha, phi1*'(-fb - l)> = <beta, phi2*'(-gb + l)>."""
+    a, b, fb, gb = _f64(alpha), _f64(beta), _f64(fb), _f64(gb)
+    return _load().or_lambda_star_div(_div(div), len(a), len(b), _ptr(a), _ptr(b), _ptr(fb),
+                                      _ptr(gb), float(rho1), float(rho2))
+
+
+def dual_value_div(cost: Cost, alpha, beta, eps, rho1, rho2, div: str, f, g) -> float:
+    """F_eps(f, g) with the entropy's phi*."""
+    a, b, f, g = _f64(alpha), _f64(beta), _f64(f), _f64(g)
+    cs = cost._struct()
+    return _load().or_dual_value_div(ctypes.byref(cs), _ptr(a), _ptr(b), float(eps), float(rho1),
+                                     float(rho2), _div(div), _ptr(f), _ptr(g))
+
+
+def sinkhorn_div(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: float, *, div: str,
+                 variant: str, max_iter: int, tol: float = 0.0,
+                 check_every: int = 1) -> SinkhornResult:
+    """F-Sinkhorn (``variant="F"``) or G-Sinkhorn (``"G"``) of Sec. 3 for the entropy ``div``
+    ("kl" or "berg"), from zero potentials; G reports (fb + lambda, gb - lambda)."""
+    if variant not in ("F", "G"):
+        raise ValueError("variant must be F or G")
+    alpha, beta = _f64(alpha), _f64(beta)
+    f, g = np.empty(cost.n), np.empty(cost.m)
+    lam, last = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    cs = cost._struct()
+    it = _load().or_sinkhorn_div(ctypes.byref(cs), _ptr(alpha), _ptr(beta), float(eps), float(rho1),
+                                 float(rho2), _div(div), int(variant == "G"), int(max_iter),
+                                 float(tol), int(check_every), _ptr(f), _ptr(g), ctypes.byref(lam),
+                                 ctypes.byref(last))
+    return SinkhornResult(f=f, g=g, iters=it, last_delta=last.value, lam=lam.value)
 
 
 def plan_apply(cost: Cost, alpha, beta, eps: float, f, g, V, transpose: bool = False) -> np.ndarray:

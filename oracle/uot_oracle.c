@@ -361,6 +361,153 @@ int or_sinkhorn_anderson(const or_cost *k, const double *alpha, const double *be
   return t;
 }
 
+/*
+ * Generic entropies (Sec. 3, the phi* of the dual; the Berg entropy of the experiments of
+ * Sec. 3): div = 0 is rho KL, phi*(x) = rho (e^{x/rho} - 1); div = 1 is the Berg entropy
+ * phi(x) = rho (x - 1 - log x), phi*(x) = -rho log(1 - x/rho) for x < rho.
+ * phi*'(x): KL e^{x/rho}; Berg rho / (rho - x) (+inf for x >= rho).
+ */
+double or_phistar_prime(int div, double rho, double x) {
+  if (div == 0) return exp(x / rho);
+  return x < rho ? rho / (rho - x) : INFINITY;
+}
+
+double or_phistar(int div, double rho, double x) {
+  if (div == 0) return rho * (exp(x / rho) - 1.0);
+  return x < rho ? -rho * log(1.0 - x / rho) : INFINITY;
+}
+
+/*
+ * The dual update of one potential from its softmin S (Sec. 3): g = -aprox_{phi*}(-S), the
+ * minimiser y of eps e^{(-S - y)/eps} + phi*(y) negated; its optimality condition reads
+ *   e^{(g - S)/eps} = phi*'(-g).
+ * KL: g = rho/(eps + rho) S. Berg: (g - S)/eps = log rho - log(rho + g) on g > -rho, whose
+ * left minus right side increases from -inf to +inf; solved by bisection on (-rho, max(S, 0)]
+ * until the bracket stops shrinking.
+ */
+double or_dual_update(int div, double rho, double eps, double S) {
+  if (div == 0) return rho / (eps + rho) * S;
+  double lo = -rho, hi = S > 0.0 ? S : 0.0;
+  for (int it = 0; it < 2000; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double h = (mid - S) / eps + log(rho + mid) - log(rho);
+    if (h > 0.0) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/*
+ * Optimal translation lambda*(fb, gb) for a generic entropy (Prop. on the existence of
+ * lambda*): the root of <alpha, phi1*'(-fb - lambda)> = <beta, phi2*'(-gb + lambda)>.
+ * KL: the closed form of Prop. 2. Berg: the left side decreases from +inf to 0 and the right
+ * side increases from 0 to +inf on (-rho1 - min fb, rho2 + min gb) (minima over positive
+ * weights): bisection until the bracket stops shrinking.
+ */
+double or_lambda_star_div(int div, int n, int m, const double *alpha, const double *beta,
+                          const double *fb, const double *gb, double rho1, double rho2) {
+  if (div == 0) {
+    double *la = (double *)malloc(sizeof(double) * (size_t)n);
+    double *lb = (double *)malloc(sizeof(double) * (size_t)m);
+    for (int i = 0; i < n; ++i) la[i] = log(alpha[i]);
+    for (int j = 0; j < m; ++j) lb[j] = log(beta[j]);
+    const double r = or_lambda_star(n, m, la, lb, fb, gb, rho1, rho2);
+    free(la); free(lb);
+    return r;
+  }
+  double fmin = INFINITY, gmin = INFINITY;
+  for (int i = 0; i < n; ++i) if (alpha[i] > 0.0 && fb[i] < fmin) fmin = fb[i];
+  for (int j = 0; j < m; ++j) if (beta[j] > 0.0 && gb[j] < gmin) gmin = gb[j];
+  double lo = -rho1 - fmin, hi = rho2 + gmin;
+  for (int it = 0; it < 2000; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (alpha[i] > 0.0) a += alpha[i] * or_phistar_prime(1, rho1, -fb[i] - mid);
+    for (int j = 0; j < m; ++j)
+      if (beta[j] > 0.0) b += beta[j] * or_phistar_prime(1, rho2, -gb[j] + mid);
+    if (a > b) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/*
+ * Dual value F_eps(f, g) = -<alpha, phi1*(-f)> - <beta, phi2*(-g)> - eps (m(pi) - m(alpha) m(beta))
+ * for a generic entropy (eq. dual-uot with its phi*; for KL it equals or_dual_value).
+ */
+double or_dual_value_div(const or_cost *k, const double *alpha, const double *beta, double eps,
+                         double rho1, double rho2, int div, const double *f, const double *g) {
+  const int n = k->n, m = k->m;
+  double a = 0.0, b = 0.0, ma = 0.0, mb = 0.0;
+  for (int i = 0; i < n; ++i) { if (alpha[i] > 0.0) a += alpha[i] * or_phistar(div, rho1, -f[i]); ma += alpha[i]; }
+  for (int j = 0; j < m; ++j) { if (beta[j] > 0.0) b += beta[j] * or_phistar(div, rho2, -g[j]); mb += beta[j]; }
+  double mpi = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j) mpi += alpha[i] * beta[j] * exp((f[i] + g[j] - or_c(k, i, j)) / eps);
+  return -a - b - eps * (mpi - ma * mb);
+}
+
+/*
+ * F-Sinkhorn (variant 0) or G-Sinkhorn (variant 1) of Sec. 3 for a generic entropy div:
+ *   F: g_{t+1} = U2(Smin_alpha^eps(C - f_t)),  f_{t+1} = U1(Smin_beta^eps(C - g_{t+1}))
+ *   G: gb_{t+1} = U2(Smin_alpha^eps(C - fb_t - lambda_t)) + lambda_t,
+ *      fb_{t+1} = U1(Smin_beta^eps(C - gb_{t+1} + lambda_t)) - lambda_t,
+ *      lambda_{t+1} = lambda*(fb_{t+1}, gb_{t+1}),
+ *      reported (f, g) = (fb + lambda, gb - lambda)
+ * with U_i(S) = or_dual_update(div, rho_i, eps, S) (the g-update uses rho2, the f-update
+ * rho1) and, for G, the +-lambda_t outside the prox (maximising G_eps(fb, gb, lambda) =
+ * F_eps(fb + lambda, gb - lambda) in gb at fixed fb + lambda). From f = fb = 0, lambda = 0;
+ * change and stopping rule as or_sinkhorn. Returns the iterations run.
+ */
+int or_sinkhorn_div(const or_cost *k, const double *alpha, const double *beta, double eps,
+                    double rho1, double rho2, int div, int variant, int max_iter, double tol,
+                    int check_every, double *f, double *g, double *lambda_out, double *last_delta) {
+  const int n = k->n, m = k->m;
+  double *loga = (double *)malloc(sizeof(double) * (size_t)n);
+  double *logb = (double *)malloc(sizeof(double) * (size_t)m);
+  for (int i = 0; i < n; ++i) loga[i] = log(alpha[i]);
+  for (int j = 0; j < m; ++j) logb[j] = log(beta[j]);
+  double *fb = (double *)calloc((size_t)n, sizeof(double));
+  double *gb = (double *)calloc((size_t)m, sizeof(double));
+  double *S = (double *)malloc(sizeof(double) * (size_t)(n > m ? n : m));
+  double *h = (double *)malloc(sizeof(double) * (size_t)(n > m ? n : m));
+  double *fo = (double *)malloc(sizeof(double) * (size_t)n);
+  double *go = (double *)malloc(sizeof(double) * (size_t)m);
+  double lam = 0.0, delta = INFINITY;
+  int t;
+  for (t = 1; t <= max_iter; ++t) {
+    const double l = variant ? lam : 0.0;
+    for (int i = 0; i < n; ++i) h[i] = fb[i] + l;
+    or_smin_cols(k, loga, h, eps, S);
+    for (int j = 0; j < m; ++j) gb[j] = or_dual_update(div, rho2, eps, S[j]) + l;
+    for (int j = 0; j < m; ++j) h[j] = gb[j] - l;
+    or_smin_rows(k, logb, h, eps, S);
+    for (int i = 0; i < n; ++i) fb[i] = or_dual_update(div, rho1, eps, S[i]) - l;
+    if (variant) lam = or_lambda_star_div(div, n, m, alpha, beta, fb, gb, rho1, rho2);
+    double d = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = fb[i] + lam;
+      if (t > 1 && fabs(v - fo[i]) > d) d = fabs(v - fo[i]);
+      fo[i] = v;
+    }
+    for (int j = 0; j < m; ++j) {
+      const double v = gb[j] - lam;
+      if (t > 1 && fabs(v - go[j]) > d) d = fabs(v - go[j]);
+      go[j] = v;
+    }
+    delta = t > 1 ? d : INFINITY;
+    if (tol > 0 && check_every > 0 && t % check_every == 0 && delta < tol) break;
+  }
+  if (t > max_iter) t = max_iter;
+  memcpy(f, fo, sizeof(double) * (size_t)n);
+  memcpy(g, go, sizeof(double) * (size_t)m);
+  if (lambda_out) *lambda_out = lam;
+  if (last_delta) *last_delta = delta;
+  free(loga); free(logb); free(fb); free(gb); free(S); free(h); free(fo); free(go);
+  return t;
+}
+
 /* Plan entry pi_ij = alpha_i beta_j exp((f_i + g_j - C_ij)/eps) (primal-dual link of the dual problem). */
 static double or_pi(const or_cost *k, const double *alpha, const double *beta, double eps,
                     const double *f, const double *g, int i, int j) {

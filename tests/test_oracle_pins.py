@@ -491,3 +491,97 @@ def test_anderson_reaches_the_fixed_point_faster(ti):
     std = oracle.sinkhorn(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, **kw)
     assert rel_inf(acc.f, star.f) < 1e-8 and rel_inf(acc.g, star.g) < 1e-8
     assert acc.iters < std.iters / 2
+
+
+# ---------------------------------------------------------------------------------------
+# Generic entropies (Sec. 3: F- and G-Sinkhorn for smooth phi*; the Berg entropy of the
+# experiments of Sec. 3).
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("div", ["kl", "berg"])
+@pytest.mark.parametrize("eps,rho,S", [(0.01, 1.0, 0.3), (0.1, 0.5, -2.0), (0.05, 2.0, 5.0),
+                                       (1.0, 0.1, 0.7), (0.02, 10.0, -0.4)])
+def test_dual_update_minimises_the_aprox_objective(div, eps, rho, S):
+    # aprox_{phi*}(x) = argmin_y eps e^{(x - y)/eps} + phi*(y), and the update is
+    # g = -aprox(-S): a direct bounded minimisation of the objective (no optimality
+    # condition involved) must land on -g.
+    from scipy.optimize import minimize_scalar
+    g = oracle.dual_update(div, rho, eps, S)
+    obj = lambda y: eps * math.exp(min((-S - y) / eps, 700.0)) + oracle.phistar(div, rho, y)
+    hi = min(rho - 1e-12, abs(S) + 1.0) if div == "berg" else abs(S) + 1.0
+    res = minimize_scalar(obj, bounds=(-abs(S) - 1.0, hi), method="bounded",
+                          options={"xatol": 1e-13})
+    assert abs(g + res.x) < 1e-6 * max(1.0, abs(g))
+    if div == "kl":
+        assert g == rho / (eps + rho) * S
+
+
+def test_berg_update_tends_to_kl_for_small_potentials():
+    # phi*'(0) = 1 and phi*''(0) = 1/rho for both entropies, so the updates agree to second
+    # order in S/rho: |U_berg(S) - U_kl(S)| = O(S^2 / rho).
+    eps, rho = 0.05, 2.0
+    for S in (1e-2, 1e-3, 1e-4):
+        d = abs(oracle.dual_update("berg", rho, eps, S) - oracle.dual_update("kl", rho, eps, S))
+        assert d < 2.0 * S * S / rho
+
+
+@pytest.mark.parametrize("div", ["kl", "berg"])
+def test_lambda_star_div_maximises_g(div):
+    # lambda* = argmax_l G_eps(fb, gb, l) = F_eps(fb + l, gb - l); the entropic term is
+    # invariant under the translation, so a direct maximisation of
+    # -<alpha, phi1*(-fb - l)> - <beta, phi2*(-gb + l)> must give the same l.
+    from scipy.optimize import minimize_scalar
+    rng = np.random.default_rng(21)
+    a, b = rng.uniform(0.1, 1.0, 7), rng.uniform(0.1, 1.0, 5)
+    fb, gb = rng.uniform(-0.3, 0.5, 7), rng.uniform(-0.2, 0.6, 5)
+    r1, r2 = 0.8, 1.7
+    lam = oracle.lambda_star_div(div, a, b, fb, gb, r1, r2)
+    obj = lambda l: sum(ai * oracle.phistar(div, r1, -fi - l) for ai, fi in zip(a, fb)) + \
+        sum(bj * oracle.phistar(div, r2, -gj + l) for bj, gj in zip(b, gb))
+    lo, hi = (-r1 - fb.min() + 1e-9, r2 + gb.min() - 1e-9) if div == "berg" else (-5.0, 5.0)
+    res = minimize_scalar(obj, bounds=(lo, hi), method="bounded", options={"xatol": 1e-13})
+    assert abs(lam - res.x) < 1e-6
+    c = 0.37
+    assert abs(oracle.lambda_star_div(div, a, b, fb + c, gb - c, r1, r2) - (lam - c)) < 1e-12
+
+
+def test_kl_f_variant_is_plain_sinkhorn():
+    pr = workloads.oned()
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    base = oracle.sinkhorn(cost, a, b, pr.eps, pr.rho1, pr.rho2, ti=False, max_iter=40)
+    r = oracle.sinkhorn_div(cost, a, b, pr.eps, pr.rho1, pr.rho2, div="kl", variant="F", max_iter=40)
+    assert np.array_equal(base.f, r.f) and np.array_equal(base.g, r.g)
+
+
+def test_berg_fixed_point_maximises_the_dual():
+    # Tiny problem: a direct numerical maximisation of the concave Berg dual F_eps over
+    # (f, g) (L-BFGS-B inside the domain f > -rho1, g > -rho2) must reach the potentials
+    # of the Sinkhorn fixed point; F- and G-Sinkhorn share that fixed point.
+    from scipy.optimize import minimize
+    pr = workloads.random_small(3, 4, d=2, seed=5, eps=0.2, rho1=0.7, rho2=1.3)
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    kw = dict(div="berg", max_iter=100000, tol=1e-14, check_every=1)
+    F = oracle.sinkhorn_div(cost, a, b, pr.eps, pr.rho1, pr.rho2, variant="F", **kw)
+    G = oracle.sinkhorn_div(cost, a, b, pr.eps, pr.rho1, pr.rho2, variant="G", **kw)
+    neg = lambda z: -oracle.dual_value_div(cost, a, b, pr.eps, pr.rho1, pr.rho2, "berg", z[:3], z[3:])
+    bounds = [(-pr.rho1 + 1e-6, None)] * 3 + [(-pr.rho2 + 1e-6, None)] * 4
+    res = minimize(neg, np.zeros(7), method="L-BFGS-B", bounds=bounds,
+                   options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 10000})
+    assert np.max(np.abs(res.x[:3] - F.f)) < 1e-5 and np.max(np.abs(res.x[3:] - F.g)) < 1e-5
+    assert np.max(np.abs(G.f - F.f)) < 1e-11 and np.max(np.abs(G.g - F.g)) < 1e-11
+
+
+@pytest.mark.parametrize("div", ["kl", "berg"])
+def test_g_sinkhorn_is_faster_when_eps_below_rho(div):
+    # Sec. 3 reports G-Sinkhorn faster than F-Sinkhorn in the regime eps <= rho, for KL and
+    # the Berg entropy, towards the same optimum.
+    pr = workloads.oned()
+    cost = oracle_cost(pr)
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    for rho in (1.0, 10.0):
+        kw = dict(div=div, max_iter=100000, tol=1e-10, check_every=10)
+        F = oracle.sinkhorn_div(cost, a, b, pr.eps, rho, rho, variant="F", **kw)
+        G = oracle.sinkhorn_div(cost, a, b, pr.eps, rho, rho, variant="G", **kw)
+        assert G.iters < F.iters / 3, (rho, F.iters, G.iters)
+        assert rel_inf(G.f, F.f) < 1e-7
