@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="cloud3d",
-                    choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16", "anderson"),
+                    choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16", "anderson",
+                             "phi"),
                     help="cloud3d (default) is the benchmark step above; the others print one "
                          "JSON line of their own measurement (see extra_workload)")
     return ap.parse_args()
@@ -138,7 +139,9 @@ def extra_workload(args, uot, torch, np, workloads):
     highdim16 N=M=50,000, D=16: TI forward to change < 1e-6, then the envelope backward.
     anderson  the benchmark's 3-D clouds and six (eps, rho): time and iterations to change
               < 1e-6 of TI and plain Sinkhorn with and without Anderson extrapolation
-              (K = 4, r = 1e-7)."""
+              (K = 4, r = 1e-7).
+    phi       the same clouds at eps = 0.01, rho in {0.1, 1, 10}: time and iterations to change
+              < 1e-6 of F- and G-Sinkhorn with the KL and the Berg entropy."""
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
@@ -244,6 +247,36 @@ def extra_workload(args, uot, torch, np, workloads):
                     "config": {"workload": "3-D clouds N=M=%d, eps in {0.1,0.01} x rho in "
                                            "{0.1,1,10}, K=4, r=1e-7, change checked every %d"
                                            % (args.n, CHECK_EVERY)},
+                    "time_to_tol": res, "roofline": None})
+    elif args.workload == "phi":
+        res = {}
+        total = {}
+        for rho in (0.1, 1.0, 10.0):
+            pr = workloads.cloud3d(n=args.n, m=args.n, eps=1e-2, rho=rho)
+            a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)
+            kw = dict(x=x, y=y, p=2.0, eps=1e-2, rho1=rho, rho2=rho, max_iter=MAX_ITER, tol=TOL,
+                      check_every=CHECK_EVERY)
+            if not res:  # first launches, untimed
+                for ent in ("kl", "berg"):
+                    for var in ("F", "G"):
+                        uot.sinkhorn_phi(a, b, entropy=ent, variant=var, **dict(kw, max_iter=5))
+            row = {}
+            for ent in ("kl", "berg"):
+                for var in ("F", "G"):
+                    (_, _, info), dt = _timed(torch, lambda: uot.sinkhorn_phi(
+                        a, b, entropy=ent, variant=var, **kw))
+                    name = "%s_%s" % (ent, var)
+                    row[name] = {"iters": info.iters, "seconds": round(dt, 5),
+                                 "converged": info.converged}
+                    total[name] = total.get(name, 0.0) + dt
+            res["eps=0.01,rho=%g" % rho] = row
+            print("phi rho=%g %s" % (rho, row), file=sys.stderr, flush=True)
+        out.update({"metric": "seconds to change < 1e-6, G-Sinkhorn with the Berg entropy, summed "
+                              "over rho in {0.1, 1, 10}", "unit": "s", "higher_is_better": False,
+                    "value": total["berg_G"], "totals_seconds": total,
+                    "config": {"workload": "3-D clouds N=M=%d, eps=0.01, rho in {0.1,1,10}, KL "
+                                           "and Berg entropies, F- and G-Sinkhorn, change "
+                                           "checked every %d" % (args.n, CHECK_EVERY)},
                     "time_to_tol": res, "roofline": None})
     else:  # highdim16
         pr = workloads.highdim16()

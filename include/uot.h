@@ -180,6 +180,42 @@ uot_status uot_ti_sinkhorn_anderson(const uot_cost *cost, const float *alpha, co
                                     float *g, void *workspace, size_t workspace_bytes,
                                     uot_info *info, void *stream);
 
+/* Marginal penalties and Sinkhorn variant of uot_sinkhorn_phi. */
+enum {
+  UOT_ENTROPY_KL = 0,    /* rho KL: phi*(x) = rho (e^{x/rho} - 1)                              */
+  UOT_ENTROPY_BERG = 1   /* Berg: phi(x) = rho (x - 1 - log x), phi*(x) = -rho log(1 - x/rho)  */
+};
+enum {
+  UOT_SINKHORN_F = 0,    /* alternate maximisation of F_eps (plain Sinkhorn)                  */
+  UOT_SINKHORN_G = 1     /* alternate maximisation of G_eps(fb, gb, lambda) (G-Sinkhorn)       */
+};
+typedef struct {
+  int32_t entropy;  /* UOT_ENTROPY_*, the same for both marginals (rho1, rho2 may differ)       */
+  int32_t variant;  /* UOT_SINKHORN_*                                                          */
+} uot_phi;
+
+/*
+ * Sinkhorn for a smooth entropy phi* (Sec. 3): the F-Sinkhorn updates with the dual update
+ * U_i(S) = -aprox_{phi_i*}(-S), the root h of e^{(h - S)/eps} = phi_i*'(-h), i.e.
+ *   g <- U_2(Smin_alpha^eps(C - f)),   f <- U_1(Smin_beta^eps(C - g))
+ * (KL: U(S) = rho/(eps + rho) S, which is uot_sinkhorn; Berg: h > -rho solving
+ * e^{(h - S)/eps} = rho / (rho + h), by Newton's method in log(rho + h), per point). The
+ * G-Sinkhorn variant alternates maximisation of G_eps(fb, gb, lambda) = F_eps(fb + lambda,
+ * gb - lambda) over gb, fb and lambda; equivalently, each iteration is the F-iteration above
+ * from f = fb + lambda followed by the translation (f, g) -> (f + l*, g - l*) with
+ * l* = lambda*(f, g), the root of <alpha, phi1*'(-f - l)> = <beta, phi2*'(-g + l)> (closed
+ * form of Prop. 2 for KL; a bracketed Newton iteration over the potentials for Berg). The
+ * reported f, g are the F-potentials (fb + lambda, gb - lambda); info->lambda is G's
+ * lambda_t = lambda*(fb_t, gb_t), the sum of those steps (0 for F). Arguments and
+ * conventions as uot_sinkhorn (warm_start gives f_0 = fb_0, lambda_0 = 0);
+ * phi (host): entropy and variant, anything else gives UOT_ERR_INVALID. Workspace
+ * UOT_WS_SOLVE.
+ */
+uot_status uot_sinkhorn_phi(const uot_cost *cost, const float *alpha, const float *beta,
+                            const uot_params *params, const uot_phi *phi, float *f, float *g,
+                            void *workspace, size_t workspace_bytes, uot_info *info,
+                            void *stream);
+
 /*
  * Dual value F_eps(f, g) of eq. (dual-uot-kl), which equals UOT(alpha, beta) at the
  * optimal potentials. m(pi) is obtained from one row-softmin pass over C:

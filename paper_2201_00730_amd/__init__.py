@@ -54,6 +54,10 @@ class _Anderson(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("r", ctypes.c_double)]
 
 
+class _Phi(ctypes.Structure):
+    _fields_ = [("entropy", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("last_change", ctypes.c_double), ("lambda_", ctypes.c_double)]
@@ -92,6 +96,9 @@ def load_library():
         fn.argtypes = [CP, P, P, ctypes.POINTER(_Params), ctypes.POINTER(_Anderson), P, P, P, S,
                        ctypes.POINTER(_Info), P]
         fn.restype = ctypes.c_int
+    lib.uot_sinkhorn_phi.argtypes = [CP, P, P, ctypes.POINTER(_Params), ctypes.POINTER(_Phi), P, P,
+                                     P, S, ctypes.POINTER(_Info), P]
+    lib.uot_sinkhorn_phi.restype = ctypes.c_int
     lib.uot_dual_value.argtypes = [CP, P, P, D, D, D, P, P, P, S, ctypes.POINTER(D), P]
     lib.uot_dual_value.restype = ctypes.c_int
     lib.uot_plan_apply.argtypes = [CP, P, P, D, P, P, I32, P, I32, I64, P, I64, P, S, P]
@@ -241,7 +248,7 @@ def _workspace(lib, cr: _CostRef, which: int):
 
 def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, eps: float,
            rho1: float, rho2: float | None = None, max_iter: int = 1000, tol: float = 0.0,
-           check_every: int = 10, f0=None, workspace=None, anderson=None):
+           check_every: int = 10, f0=None, workspace=None, anderson=None, phi=None):
     _require_gpu()
     lib = load_library()
     cr = _CostRef(C, x, y, p)
@@ -261,6 +268,8 @@ def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, ep
     args = [ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), ctypes.byref(prm)]
     if anderson is not None:
         args.append(ctypes.byref(_Anderson(int(anderson[0]), float(anderson[1]))))
+    if phi is not None:
+        args.append(ctypes.byref(_Phi(int(phi[0]), int(phi[1]))))
     st = getattr(lib, name)(*args, _ptr(f), _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(info),
                             _stream())
     _check(st)
@@ -277,6 +286,20 @@ def ti_sinkhorn(alpha, beta, **kw):
     """Translation-invariant (H-) Sinkhorn (Sec. 3, Prop. 4; App. B for rho1 != rho2).
     Returns the translated potentials Phi(fb, gb) = (f, g) and Info."""
     return _solve("uot_ti_sinkhorn", alpha, beta, **kw)
+
+
+ENTROPIES = {"kl": 0, "berg": 1}
+VARIANTS = {"F": 0, "G": 1}
+
+
+def sinkhorn_phi(alpha, beta, *, entropy: str = "kl", variant: str = "F", **kw):
+    """F- or G-Sinkhorn (Sec. 3) with the KL or the Berg entropy for both marginal penalties
+    (rho1, rho2 may differ). Other keyword args as ``sinkhorn``. Returns the F-potentials
+    (f, g, Info); Info.lam is the last lambda* for G-Sinkhorn."""
+    if entropy not in ENTROPIES or variant not in VARIANTS:
+        raise ValueError("entropy must be one of %s and variant one of %s"
+                         % (sorted(ENTROPIES), sorted(VARIANTS)))
+    return _solve("uot_sinkhorn_phi", alpha, beta, phi=(ENTROPIES[entropy], VARIANTS[variant]), **kw)
 
 
 def sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, **kw):

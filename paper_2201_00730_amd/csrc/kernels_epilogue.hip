@@ -42,6 +42,16 @@ __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) {
   reduce_scalars(a);
 }
 
+// G-Sinkhorn with the Berg entropy: lambda*(stored f, stored g) into st->lam_step, by one
+// block of kBergThreads (Newton over all potentials), between the f-step's combine and its
+// reduction. The previous step (tau_f) is the start.
+constexpr int kBergThreads = 1024;
+__global__ __launch_bounds__(kBergThreads) void k_berg_lambda(ReduceArgs a) {
+  if (get_done(&a.st->done)) return;
+  const double l = berg_lambda<kBergThreads>(a, a.st->tau_f);
+  if (threadIdx.x == 0) a.st->lam_step = l;
+}
+
 // Threads per target in the combine kernel.
 constexpr int kCombLanes = 4;
 constexpr int kCombTargets = kBlock / kCombLanes;
@@ -86,7 +96,9 @@ __global__ __launch_bounds__(kBlock) void k_validate(const float *a, int n, cons
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const float *pot, int n, int which,
                                                      const SolveState *st, float *out) {
-  const double off = which == 0 ? st->tau_f + st->lambda : st->tau_g - st->lambda;
+  // the offsets of the reported potentials recorded by the last f-step reduction: TI
+  // tau_f + lambda and tau_g - lambda, G-Sinkhorn lambda and -lambda, plain Sinkhorn 0
+  const double off = which == 0 ? st->off_f_prev : st->off_g_prev;
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t < n) out[t] = (float)((double)pot[t] + off);
 }
@@ -232,6 +244,11 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t s) {
 
 hipError_t launch_build_records(const RecordArgs &a, hipStream_t s) {
   UOT_DISPATCH(records_for, a.mode, a.d, a, s);
+}
+
+hipError_t launch_berg_lambda(const ReduceArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_berg_lambda, dim3(1), dim3(kBergThreads), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {

@@ -392,6 +392,8 @@ struct Ctx {
   double eps, rho1, rho2;
   double sc;  // log2(e)/eps
   bool ti;
+  int entropy = kEntropyKL;  // marginal penalties (plain and G-Sinkhorn)
+  bool gvar = false;         // G-Sinkhorn: translate by lambda* after every iteration
   Layout L;
   void *ws;
   hipStream_t s;
@@ -465,6 +467,7 @@ Epilogue epilogue_for(const Ctx &k, bool g_step) {
   const double e = k.eps, r1 = k.rho1, r2 = k.rho2;
   Epilogue ep;
   ep.ti = k.ti;
+  ep.entropy = k.entropy;
   if (g_step) {  // targets y: g = k2 (S - tau_f) - c_g sA, kappa_g = e r1 / ((e + r2)(r1 + r2))
     ep.k_t = r2 / (e + r2);
     ep.c_t = k.ti ? e * r2 / ((e + r2) * (r1 + r2)) : 0.0;
@@ -519,6 +522,15 @@ uot_status half_step(const Ctx &k, bool g_step, double tol, int check_every, flo
   ra.tol = tol;
   ra.check_every = check_every;
   ra.tau_out = tau_out;
+  ra.gvar = k.gvar ? 1 : 0;
+  ra.entropy = k.entropy;
+  ra.pot_f = at<float>(k.ws, k.L.pot_x);
+  ra.pot_g = at<float>(k.ws, k.L.pot_y);
+  ra.w_f = k.alpha;
+  ra.w_g = k.beta;
+  ra.nf = k.n;
+  ra.ng = k.m;
+  if (!g_step && k.gvar && k.entropy == kEntropyBerg) UOT_HIP(launch_berg_lambda(ra, k.s));
   k.pending = ra;  // run beside the next softmin, or by flush_reduce()
   k.has_pending = true;
   return UOT_OK;
@@ -609,9 +621,19 @@ uot_status check_anderson(const uot_anderson *acc) {
   return UOT_OK;
 }
 
+uot_status check_phi(const uot_phi *phi) {
+  if (phi == nullptr) return fail(UOT_ERR_INVALID, "phi settings are NULL");
+  if (phi->entropy != UOT_ENTROPY_KL && phi->entropy != UOT_ENTROPY_BERG)
+    return fail(UOT_ERR_INVALID, "phi entropy=%d must be UOT_ENTROPY_KL or UOT_ENTROPY_BERG", phi->entropy);
+  if (phi->variant != UOT_SINKHORN_F && phi->variant != UOT_SINKHORN_G)
+    return fail(UOT_ERR_INVALID, "phi variant=%d must be UOT_SINKHORN_F or UOT_SINKHORN_G", phi->variant);
+  return UOT_OK;
+}
+
 uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const uot_params *P,
                  float *f, float *g, void *workspace, size_t workspace_bytes, uot_info *info,
-                 void *stream, bool ti, const uot_anderson *acc = nullptr) {
+                 void *stream, bool ti, const uot_anderson *acc = nullptr,
+                 const uot_phi *phi = nullptr) {
   UOT_TRY(check_cost(c));
   UOT_TRY(check_params(P));
   UOT_TRY(check_cost_ptrs(c));
@@ -632,6 +654,10 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   k.rho2 = P->rho2;
   k.sc = kLog2e / P->eps;
   k.ti = ti;
+  if (phi) {
+    k.entropy = phi->entropy == UOT_ENTROPY_BERG ? kEntropyBerg : kEntropyKL;
+    k.gvar = phi->variant == UOT_SINKHORN_G;
+  }
   k.L = make_layout(c, acc ? UOT_WS_ANDERSON : UOT_WS_SOLVE);
   k.s = static_cast<hipStream_t>(stream);
   Workspace w;
@@ -1180,6 +1206,17 @@ uot_status uot_ti_sinkhorn_anderson(const uot_cost *cost, const float *alpha, co
   if (s != UOT_OK) return s;
   return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream,
                     true, acc);
+}
+
+uot_status uot_sinkhorn_phi(const uot_cost *cost, const float *alpha, const float *beta,
+                            const uot_params *params, const uot_phi *phi, float *f, float *g,
+                            void *workspace, size_t workspace_bytes, uot_info *info,
+                            void *stream) {
+  uot::g_last_error.clear();
+  const uot_status s = uot::check_phi(phi);
+  if (s != UOT_OK) return s;
+  return uot::solve(cost, alpha, beta, params, f, g, workspace, workspace_bytes, info, stream,
+                    false, nullptr, phi);
 }
 
 uot_status uot_ti_sinkhorn(const uot_cost *cost, const float *alpha, const float *beta,

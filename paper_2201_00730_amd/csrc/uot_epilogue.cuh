@@ -143,6 +143,123 @@ static __device__ __forceinline__ void set_done(SolveState *st, int32_t v) {
   __hip_atomic_store(&st->done, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The dual update of one potential with the Berg entropy (Sec. 3, g = -aprox_{phi*}(-S)):
+// h > -rho solving e^{(h - S)/eps} = rho / (rho + h). In w = log(rho + h) the equation is
+// q(w) = (e^w - rho - S)/eps + w - log rho = 0 with q convex, increasing and q' >= 1, so
+// Newton's method converges from any start (past the first step, from above and
+// monotonically); the KL update rho/(eps + rho) S, kept inside the domain, is the start.
+static __device__ double berg_update(double S, double rho, double eps) {
+  const double lr = log(rho);
+  double w = log(fmax(rho + rho / (eps + rho) * S, 0.5 * rho));
+  for (int it = 0; it < 100; ++it) {
+    const double e = exp(w);
+    const double step = ((e - rho - S) / eps + w - lr) / (e / eps + 1.0);
+    w -= step;
+    if (!(fabs(step) > 1e-15 * fmax(1.0, fabs(w)))) break;
+  }
+  return exp(w) - rho;
+}
+
+// Block-wide sums (s0, s1) and minima (m0, m1) over NT threads, broadcast to every thread.
+template <int NT>
+static __device__ void block_sum2(double &s0, double &s1) {
+  constexpr int kWaves = NT / 64;
+  __shared__ double sh[2][kWaves];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sh[0][w] = s0; sh[1][w] = s1; }
+  __syncthreads();
+  s0 = sh[0][0];
+  s1 = sh[1][0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) { s0 += sh[0][k]; s1 += sh[1][k]; }
+  __syncthreads();
+}
+template <int NT>
+static __device__ void block_min2(double &m0, double &m1) {
+  constexpr int kWaves = NT / 64;
+  __shared__ double sh[2][kWaves];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m0 = fmin(m0, __shfl_xor(m0, o, 64));
+    m1 = fmin(m1, __shfl_xor(m1, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sh[0][w] = m0; sh[1][w] = m1; }
+  __syncthreads();
+  m0 = sh[0][0];
+  m1 = sh[1][0];
+#pragma unroll
+  for (int k = 1; k < kWaves; ++k) { m0 = fmin(m0, sh[0][k]); m1 = fmin(m1, sh[1][k]); }
+  __syncthreads();
+}
+
+// Adds w rho / (rho + p + s l) and its derivative in l to (D, dD) for the entries of one side
+// (s = +1 for f, -1 for g, which enters D with a minus sign); four independent entries per
+// step keep several divisions in flight.
+template <int NT>
+static __device__ void berg_terms(const float *pot, const float *w, int n, double rho, double l,
+                                  double sgn, double &D, double &dD) {
+  int i = threadIdx.x;
+  for (; i + 3 * NT < n; i += 4 * NT) {
+    double q[4], ww[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ww[u] = w[i + u * NT];
+      q[u] = rho / (rho + (double)pot[i + u * NT] + sgn * l);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ww[u] > 0.0) {
+        D += sgn * ww[u] * q[u];
+        dD -= ww[u] * q[u] * q[u] / rho;
+      }
+  }
+  for (; i < n; i += NT) {
+    const double ww = w[i];
+    if (ww > 0.0) {
+      const double q = rho / (rho + (double)pot[i] + sgn * l);
+      D += sgn * ww * q;
+      dD -= ww * q * q / rho;
+    }
+  }
+}
+
+// lambda*(f, g) with the Berg entropy (the maximiser of G_eps in lambda, whose first-order
+// condition equates the tilted masses): the root of
+//   D(l) = sum_i a_i rho1 / (rho1 + f_i + l) - sum_j b_j rho2 / (rho2 + g_j - l),
+// which decreases on (-rho1 - min f, rho2 + min g) (minima over positive weights). Newton
+// steps from `start`, inside a bracket that every evaluation shrinks (a step leaving it is
+// replaced by bisection). Run by a whole block of NT threads; every thread gets the result.
+template <int NT>
+static __device__ double berg_lambda(const ReduceArgs &a, double start) {
+  double fmn = INFINITY, gmn = INFINITY;
+  for (int i = threadIdx.x; i < a.nf; i += NT)
+    if (a.w_f[i] > 0.0f) fmn = fmin(fmn, (double)a.pot_f[i]);
+  for (int j = threadIdx.x; j < a.ng; j += NT)
+    if (a.w_g[j] > 0.0f) gmn = fmin(gmn, (double)a.pot_g[j]);
+  block_min2<NT>(fmn, gmn);
+  double lo = -a.rho1 - fmn, hi = a.rho2 + gmn;
+  double lam = (start > lo && start < hi) ? start : 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    double D = 0.0, dD = 0.0;
+    berg_terms<NT>(a.pot_f, a.w_f, a.nf, a.rho1, lam, 1.0, D, dD);
+    berg_terms<NT>(a.pot_g, a.w_g, a.ng, a.rho2, lam, -1.0, D, dD);
+    block_sum2<NT>(D, dD);
+    if (D > 0.0) lo = lam; else hi = lam;
+    double nl = lam - D / dD;
+    if (!(nl > lo && nl < hi)) nl = 0.5 * (lo + hi);
+    const bool stop = D == 0.0 || !(fabs(nl - lam) > 1e-15 * fmax(1.0, fabs(lam)));
+    lam = nl;
+    if (stop) break;
+  }
+  return lam;
+}
+
 // Reduces the block partials of a half-step (or of the start) into the scalar state; run by
 // one block of kBlock threads. Thread 0 writes the results.
 static __device__ void reduce_scalars(const ReduceArgs &a) {
@@ -192,10 +309,16 @@ static __device__ void reduce_scalars(const ReduceArgs &a) {
       lam = a.tau1 * st->sB - a.tau2 * st->sA;  // Prop. 2 through softmins
     } else {
       st->sA = sAhat;
+      // G-Sinkhorn: the stored pair is the F-update from the last reported f; its optimal
+      // translation lambda*(stored f, stored g) (Prop. 2 for KL) moves the reported pair, and
+      // G's own lambda_t = lambda*(fb_t, gb_t) advances by the same amount
+      // (Berg: computed by k_berg_lambda after the f-step's combine)
+      if (a.gvar) lam = a.entropy == kEntropyBerg ? st->lam_step : a.tau1 * st->sB - a.tau2 * sAhat;
     }
-    st->tau_f = tf;
+    // the next g-step reads the stored f translated by tau_f: TI's translation, or G's step
+    st->tau_f = a.gvar ? lam : tf;
     if (a.tau_out) *a.tau_out = tf;
-    st->lambda = lam;
+    st->lambda = a.gvar ? st->lambda + lam : lam;
     const double off_f = tf + lam, off_g = st->tau_g - lam;
     const int it = st->iter + 1;
     st->iter = it;
@@ -275,7 +398,9 @@ static __device__ bool combine_range(const CombineArgs &a, int t_begin, double &
     double lse2 = (double)M + log2((double)L);
     if constexpr (is_sq(MODE)) lse2 -= a.sc * yn2;
     const double S = -lse2 / a.sc;  // softmin over the stored source potential
-    const double hnew = a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
+    const double hnew = a.ep.entropy == kEntropyBerg
+                            ? berg_update(S - tau_src, a.ep.rho_t, a.eps)
+                            : a.ep.k_t * (S - tau_src) - a.ep.c_t * s_src;
     const float hf = (float)hnew;
     a.pot[t] = hf;
     if (a.snap) a.snap[t] = hf;

@@ -97,6 +97,7 @@ struct SolveState {
   int32_t pos_a;      // some alpha_i > 0
   int32_t pos_b;      // some beta_j > 0
   int32_t fresh;      // 1 after an Anderson extrapolation: the next change is +inf
+  double lam_step;    // G-Sinkhorn, Berg entropy: lambda*(stored f, stored g) of this step
   double mu[kMaxDim]; // common centring of x and y (points costs)
 };
 
@@ -113,6 +114,10 @@ struct BlockPart {
 // Epilogue of a half-step (all double): given the softmin S_t over the current sources,
 //   hnew_t = k_t * (S_t - tau_src) - c_t * s_src
 // (KL prox, and for TI the translation term of App. B; c_t = 0 for plain Sinkhorn).
+// Entropy of the marginal penalties (Sec. 3): rho KL, or the Berg entropy
+// phi(x) = rho (x - 1 - log x), phi*(x) = -rho log(1 - x/rho).
+enum Entropy : int32_t { kEntropyKL = 0, kEntropyBerg = 1 };
+
 struct Epilogue {
   double k_t;       // rho_t / (eps + rho_t)
   double c_t;       // TI: eps rho_t / ((eps + rho_t)(rho1 + rho2)); plain: 0
@@ -120,6 +125,7 @@ struct Epilogue {
   double kappa_t;   // TI: kappa of the target side; plain: 0 (used by the reduction)
   int32_t src_is_x; // 1: sources are the x/alpha side (g-step)
   int32_t ti;
+  int32_t entropy = kEntropyKL;  // kEntropyBerg: hnew solves e^{(h - S')/eps} = rho/(rho + h)
 };
 
 // Start/stop events attached to one kernel dispatch (timestamps of the dispatch itself, no
@@ -154,6 +160,13 @@ struct ReduceArgs {
   double tol;
   int check_every;
   double *tau_out = nullptr;  // kReduceF with Anderson: receives tau_f
+  // G-Sinkhorn (gvar): kReduceF sets lambda = lambda*(stored f, stored g) and carries it as
+  // the translation of the stored f; with the Berg entropy lambda* is found by a bracketed
+  // Newton iteration over the stored potentials (pot_f [nf], pot_g [ng], weights w_f, w_g).
+  int gvar = 0;
+  int entropy = kEntropyKL;
+  const float *pot_f = nullptr, *pot_g = nullptr, *w_f = nullptr, *w_g = nullptr;
+  int nf = 0, ng = 0;
 };
 
 struct PointsArgs {
@@ -242,6 +255,7 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t st);
 int combine_blocks(int nt);
 
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
+hipError_t launch_berg_lambda(const ReduceArgs &a, hipStream_t st);
 
 // Build source records from a potential (solve start, dual value, plan, backward).
 struct RecordArgs {

@@ -149,3 +149,15 @@ def test_python_binding_fails_loudly_without_gpu():
     with pytest.raises(RuntimeError):
         uot.ti_sinkhorn(torch.ones(3), torch.ones(3), x=torch.zeros(3, 1), y=torch.zeros(3, 1),
                         eps=0.1, rho1=1.0)
+
+
+@pytest.mark.parametrize("entropy,variant", [(2, 0), (-1, 0), (0, 2), (1, -1)])
+def test_phi_rejects_bad_settings_before_any_launch(lib, entropy, variant):
+    c = _cost()
+    prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
+    phi = uot._Phi(entropy, variant)
+    assert lib.uot_sinkhorn_phi(ctypes.byref(c), None, None, ctypes.byref(prm), ctypes.byref(phi),
+                                None, None, None, 0, None, None) == uot.UOT_ERR_INVALID
+    assert b"phi" in lib.uot_last_error()
+    assert lib.uot_sinkhorn_phi(ctypes.byref(c), None, None, ctypes.byref(prm), None, None, None,
+                                None, 0, None, None) == uot.UOT_ERR_INVALID
