@@ -77,6 +77,12 @@ def _load():
             lib.or_dual_value_div.restype = D
             lib.or_sinkhorn_div.argtypes = [CP, P, P, D, D, D, I, I, I, D, I, P, P, P, P]
             lib.or_sinkhorn_div.restype = I
+            lib.or_solve_ot_1d.argtypes = [I, I, P, P, P, P, D, P, P, P, P]
+            lib.or_solve_ot_1d.restype = D
+            lib.or_h0.argtypes = [I, I, P, P, P, P, D, D, P]
+            lib.or_h0.restype = D
+            lib.or_fw_1d.argtypes = [I, I, P, P, P, P, D, D, D, I, I, D, P, P, P, P]
+            lib.or_fw_1d.restype = I
             lib.or_anderson_mix.argtypes = [I, I, P, D, P, P]
             lib.or_anderson_mix.restype = I
             lib.or_sinkhorn_anderson.argtypes = [CP, P, P, D, D, D, I, I, D, I, D, I, I, P, P, P, P, P]
@@ -336,6 +342,54 @@ def sinkhorn_div(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: float, 
                                  float(tol), int(check_every), _ptr(f), _ptr(g), ctypes.byref(lam),
                                  ctypes.byref(last))
     return SinkhornResult(f=f, g=g, iters=it, last_delta=last.value, lam=lam.value)
+
+
+def solve_ot_1d(x, y, a, b, p: float):
+    """Balanced 1-D OT between sorted supports (Sec. 4, the linear oracle of Frank-Wolfe):
+    monotone coupling and its complementary-slackness dual. Returns (cost, r, s, cells, mass)."""
+    x, y, a, b = _f64(x), _f64(y), _f64(a), _f64(b)
+    n, m = len(x), len(y)
+    r, s = np.empty(n), np.empty(m)
+    cells = np.empty(2 * (n + m - 1), dtype=np.int32)
+    mass = np.empty(n + m - 1)
+    cost = _load().or_solve_ot_1d(n, m, _ptr(x), _ptr(y), _ptr(a), _ptr(b), float(p), _ptr(r),
+                                  _ptr(s), cells.ctypes.data_as(ctypes.c_void_p), _ptr(mass))
+    return cost, r, s, cells.reshape(-1, 2), mass
+
+
+def h0(alpha, beta, fb, gb, rho1: float, rho2: float):
+    """H_0(fb, gb) = F_0(fb + lambda*, gb - lambda*) for KL; returns (value, lambda*)."""
+    a, b, fb, gb = _f64(alpha), _f64(beta), _f64(fb), _f64(gb)
+    lam = ctypes.c_double(0.0)
+    v = _load().or_h0(len(a), len(b), _ptr(a), _ptr(b), _ptr(fb), _ptr(gb), float(rho1),
+                      float(rho2), ctypes.byref(lam))
+    return v, lam.value
+
+
+@dataclass
+class FWResult:
+    f: np.ndarray
+    g: np.ndarray
+    iters: int
+    gap: float
+    hist_gap: np.ndarray | None = None
+
+
+def fw_1d(x, y, alpha, beta, rho1: float, rho2: float, *, p: float = 2.0,
+          line_search: bool = False, max_iter: int = 1000, tol: float = 0.0,
+          history: bool = False) -> FWResult:
+    """Frank-Wolfe on H_0 for 1-D KL-UOT with eps = 0 (Sec. 4) on sorted supports; step
+    2/(2+t) or line search. Returns the reported potentials (fb + lambda*, gb - lambda*)."""
+    x, y, a, b = _f64(x), _f64(y), _f64(alpha), _f64(beta)
+    n, m = len(x), len(y)
+    f, g = np.empty(n), np.empty(m)
+    gap = ctypes.c_double(0.0)
+    hg = np.empty(max_iter) if history else None
+    it = _load().or_fw_1d(n, m, _ptr(x), _ptr(y), _ptr(a), _ptr(b), float(rho1), float(rho2),
+                          float(p), int(bool(line_search)), int(max_iter), float(tol), _ptr(f),
+                          _ptr(g), ctypes.byref(gap), _ptr(hg))
+    return FWResult(f=f, g=g, iters=it, gap=gap.value,
+                    hist_gap=None if hg is None else hg[:it].copy())
 
 
 def plan_apply(cost: Cost, alpha, beta, eps: float, f, g, V, transpose: bool = False) -> np.ndarray:

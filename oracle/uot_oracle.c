@@ -508,6 +508,155 @@ int or_sinkhorn_div(const or_cost *k, const double *alpha, const double *beta, d
   return t;
 }
 
+/*
+ * ---------------------------------------------------------------------------------------
+ * 1-D Frank-Wolfe for unregularised KL-UOT (eps = 0), Sec. 4.
+ * ---------------------------------------------------------------------------------------
+ * Balanced 1-D OT between sorted supports x[0..n) and y[0..m) (ascending) with weights a, b
+ * of equal total mass and cost C_ij = |x_i - y_j|^p, p >= 1: the monotone (north-west
+ * corner) coupling walks the cells of the n x m grid from (0, 0), at each cell moving mass
+ * min(remaining of row i, remaining of column j); a row that runs out first (or ties) moves
+ * the walk down, otherwise right; the last row or column absorbs what is left. Dual
+ * potentials from complementary slackness along the walk: r_0 = 0, s_0 = C_00, and each
+ * cell (i, j) entered is tight, r_i + s_j = C_ij (entering row i at column j sets r_i,
+ * entering column j at row i sets s_j). For costs with the Monge property (|x - y|^p, p >= 1)
+ * this pair is dual feasible, r_i + s_j <= C_ij everywhere.
+ * Writes r[n], s[m]; if cells != NULL also the walk: cells[2k], cells[2k+1] = (i, j) and
+ * mass[k] for its n + m - 1 cells. Returns the transport cost sum_k mass_k C(cell_k).
+ */
+static double or_c1d(double x, double y, double p) { return pow(fabs(x - y), p); }
+
+double or_solve_ot_1d(int n, int m, const double *x, const double *y, const double *a,
+                      const double *b, double p, double *r, double *s, int *cells, double *mass) {
+  int i = 0, j = 0, k = 0;
+  double ra = a[0], rb = b[0], cost = 0.0;
+  r[0] = 0.0;
+  s[0] = or_c1d(x[0], y[0], p);
+  while (1) {
+    const int last_i = i == n - 1, last_j = j == m - 1;
+    double moved;
+    int down;
+    if (last_i && last_j) { moved = ra > rb ? ra : rb; down = -1; }
+    else if (last_j) { moved = ra; down = 1; }           /* the last column takes the row   */
+    else if (last_i) { moved = rb; down = 0; }           /* the last row takes the column   */
+    else if (ra <= rb) { moved = ra; down = 1; }
+    else { moved = rb; down = 0; }
+    if (moved < 0.0) moved = 0.0;
+    if (cells) { cells[2 * k] = i; cells[2 * k + 1] = j; mass[k] = moved; }
+    cost += moved * or_c1d(x[i], y[j], p);
+    ++k;
+    if (down < 0) break;
+    if (down) {
+      rb -= moved;
+      ++i;
+      ra = a[i];
+      r[i] = or_c1d(x[i], y[j], p) - s[j];
+    } else {
+      ra -= moved;
+      ++j;
+      rb = b[j];
+      s[j] = or_c1d(x[i], y[j], p) - r[i];
+    }
+  }
+  return cost;
+}
+
+/*
+ * H_0 for KL (Sec. 4 applies F-W to H_0 = sup_lambda F_0(fb + lambda, gb - lambda)): with
+ * A = <alpha, e^{-fb/rho1}>, B = <beta, e^{-gb/rho2}>, the maximising lambda is
+ * rho1 rho2/(rho1 + rho2) log(A/B) (Prop. 2), and
+ *   H_0 = rho1 m(alpha) + rho2 m(beta) - (rho1 + rho2) A^{tau1} B^{tau2}.
+ * Computed here as F_0 at (fb + lambda*, gb - lambda*), its definition.
+ */
+double or_h0(int n, int m, const double *alpha, const double *beta, const double *fb,
+             const double *gb, double rho1, double rho2, double *lambda_out) {
+  double A = 0.0, B = 0.0;
+  for (int i = 0; i < n; ++i) A += alpha[i] * exp(-fb[i] / rho1);
+  for (int j = 0; j < m; ++j) B += beta[j] * exp(-gb[j] / rho2);
+  const double lam = rho1 * rho2 / (rho1 + rho2) * (log(A) - log(B));
+  double v = 0.0;
+  for (int i = 0; i < n; ++i) v += rho1 * alpha[i] * (1.0 - exp(-(fb[i] + lam) / rho1));
+  for (int j = 0; j < m; ++j) v += rho2 * beta[j] * (1.0 - exp(-(gb[j] - lam) / rho2));
+  if (lambda_out) *lambda_out = lam;
+  return v;
+}
+
+/*
+ * Frank-Wolfe on H_0 over {fb (+) gb <= C} (Sec. 4, KL): from (fb, gb) = (0, 0), each
+ * iteration t = 0, 1, ... forms the tilted histograms (the gradient of H_0, Prop. on
+ * lambda*) at = alpha e^{-(fb + l)/rho1}, bt = beta e^{-(gb - l)/rho2}, l = lambda*(fb, gb),
+ * which have equal masses; takes the linear maximisation oracle (r, s) = the dual solution
+ * of balanced 1-D OT between (x, at) and (y, bt) (or_solve_ot_1d, after scaling both to mass
+ * 1); the Frank-Wolfe gap <at, r - fb> + <bt, s - gb> (>= H_0* - H_0(fb, gb)); and steps
+ * (fb, gb) <- (1 - gamma)(fb, gb) + gamma (r, s) with gamma = 2/(2 + t) (line_search = 0) or
+ * the maximiser of H_0 on the segment, gamma in [0, 1] (line_search = 1; H_0 along the
+ * segment is concave, found by bisection on the sign of its derivative to the last bit).
+ * An iteration is one oracle call and, unless its gap is <= tol (tol > 0), one step; the
+ * loop ends at such an iteration or after max_iter iterations. Writes the reported
+ * potentials (fb + lambda*, gb - lambda*) and returns the iterations run; *gap_out is the
+ * last gap. hist_gap[max_iter] (optional) receives every gap.
+ */
+int or_fw_1d(int n, int m, const double *x, const double *y, const double *alpha,
+             const double *beta, double rho1, double rho2, double p, int line_search,
+             int max_iter, double tol, double *f, double *g, double *gap_out, double *hist_gap) {
+  double *fb = (double *)calloc((size_t)n, sizeof(double));
+  double *gb = (double *)calloc((size_t)m, sizeof(double));
+  double *at = (double *)malloc(sizeof(double) * (size_t)n);
+  double *bt = (double *)malloc(sizeof(double) * (size_t)m);
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  double *s = (double *)malloc(sizeof(double) * (size_t)m);
+  double *ft = (double *)malloc(sizeof(double) * (size_t)n);
+  double *gt = (double *)malloc(sizeof(double) * (size_t)m);
+  double gap = INFINITY, lam = 0.0;
+  int t;
+  for (t = 0; t < max_iter; ++t) {
+    or_h0(n, m, alpha, beta, fb, gb, rho1, rho2, &lam);
+    double ma = 0.0, mb = 0.0;
+    for (int i = 0; i < n; ++i) { at[i] = alpha[i] * exp(-(fb[i] + lam) / rho1); ma += at[i]; }
+    for (int j = 0; j < m; ++j) { bt[j] = beta[j] * exp(-(gb[j] - lam) / rho2); mb += bt[j]; }
+    gap = 0.0;
+    {
+      double *an = ft, *bn = gt;  /* scratch: histograms scaled to mass 1 */
+      for (int i = 0; i < n; ++i) an[i] = at[i] / ma;
+      for (int j = 0; j < m; ++j) bn[j] = bt[j] / mb;
+      or_solve_ot_1d(n, m, x, y, an, bn, p, r, s, NULL, NULL);
+    }
+    for (int i = 0; i < n; ++i) gap += at[i] * (r[i] - fb[i]);
+    for (int j = 0; j < m; ++j) gap += bt[j] * (s[j] - gb[j]);
+    if (hist_gap) hist_gap[t] = gap;
+    if (tol > 0.0 && gap <= tol) break;
+    double gamma;
+    if (!line_search) {
+      gamma = 2.0 / (2.0 + t);
+    } else {
+      /* derivative of H_0 along the segment at gamma: with l* at the point,
+       * dH/dgamma = <at(gamma), r - fb> + <bt(gamma), s - gb> (envelope theorem) */
+      double lo = 0.0, hi = 1.0;
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        for (int i = 0; i < n; ++i) ft[i] = (1.0 - mid) * fb[i] + mid * r[i];
+        for (int j = 0; j < m; ++j) gt[j] = (1.0 - mid) * gb[j] + mid * s[j];
+        double l2;
+        or_h0(n, m, alpha, beta, ft, gt, rho1, rho2, &l2);
+        double d = 0.0;
+        for (int i = 0; i < n; ++i) d += alpha[i] * exp(-(ft[i] + l2) / rho1) * (r[i] - fb[i]);
+        for (int j = 0; j < m; ++j) d += beta[j] * exp(-(gt[j] - l2) / rho2) * (s[j] - gb[j]);
+        if (d > 0.0) lo = mid; else hi = mid;
+      }
+      gamma = 0.5 * (lo + hi);
+    }
+    for (int i = 0; i < n; ++i) fb[i] = (1.0 - gamma) * fb[i] + gamma * r[i];
+    for (int j = 0; j < m; ++j) gb[j] = (1.0 - gamma) * gb[j] + gamma * s[j];
+  }
+  or_h0(n, m, alpha, beta, fb, gb, rho1, rho2, &lam);
+  for (int i = 0; i < n; ++i) f[i] = fb[i] + lam;
+  for (int j = 0; j < m; ++j) g[j] = gb[j] - lam;
+  if (gap_out) *gap_out = gap;
+  free(fb); free(gb); free(at); free(bt); free(r); free(s); free(ft); free(gt);
+  return t < max_iter ? t + 1 : max_iter;
+}
+
 /* Plan entry pi_ij = alpha_i beta_j exp((f_i + g_j - C_ij)/eps) (primal-dual link of the dual problem). */
 static double or_pi(const or_cost *k, const double *alpha, const double *beta, double eps,
                     const double *f, const double *g, int i, int j) {

@@ -585,3 +585,78 @@ def test_g_sinkhorn_is_faster_when_eps_below_rho(div):
         G = oracle.sinkhorn_div(cost, a, b, pr.eps, rho, rho, variant="G", **kw)
         assert G.iters < F.iters / 3, (rho, F.iters, G.iters)
         assert rel_inf(G.f, F.f) < 1e-7
+
+
+# ---------------------------------------------------------------------------------------
+# 1-D Frank-Wolfe for unregularised KL-UOT (Sec. 4).
+# ---------------------------------------------------------------------------------------
+def _sorted_problem(n, m, seed):
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(0.0, 1.0, n))
+    y = np.sort(rng.uniform(0.0, 1.0, m))
+    return x, y, rng.uniform(0.2, 1.0, n), rng.uniform(0.2, 1.0, m)
+
+
+@pytest.mark.parametrize("n,m,p", [(1, 1, 2.0), (1, 6, 1.0), (5, 1, 1.5), (4, 5, 2.0),
+                                   (9, 7, 1.0), (12, 17, 1.5)])
+def test_solve_ot_1d_is_an_optimal_primal_dual_pair(n, m, p):
+    # Against a linear program (scipy's HiGHS) on the full n x m cost: same optimal cost;
+    # the walk's plan has the prescribed marginals; the potentials are dual feasible and
+    # their dual value equals the cost (strong duality), so both are optimal.
+    from scipy.optimize import linprog
+    x, y, a, b = _sorted_problem(n, m, 100 + n * m)
+    a, b = a / a.sum(), b / b.sum()
+    C = np.abs(x[:, None] - y[None, :]) ** p
+    cost, r, s, cells, mass = oracle.solve_ot_1d(x, y, a, b, p)
+    A = np.zeros((n + m, n * m))
+    for i in range(n):
+        A[i, i * m:(i + 1) * m] = 1.0
+    for j in range(m):
+        A[n + j, j::m] = 1.0
+    lp = linprog(C.reshape(-1), A_eq=A, b_eq=np.concatenate([a, b]), bounds=(0, None),
+                 method="highs")
+    assert abs(cost - lp.fun) <= 1e-12 * max(1.0, abs(lp.fun))
+    pi = np.zeros((n, m))
+    for (i, j), w in zip(cells, mass):
+        pi[i, j] += w
+    assert np.allclose(pi.sum(1), a, rtol=0, atol=1e-14) and np.allclose(pi.sum(0), b, rtol=0, atol=1e-14)
+    assert np.max(r[:, None] + s[None, :] - C) <= 1e-14
+    assert abs(r @ a + s @ b - cost) <= 1e-13
+
+
+def test_fw_reaches_the_unregularised_optimum():
+    # A direct constrained maximisation of F_0(f, g) = rho1 <alpha, 1 - e^{-f/rho1}> +
+    # rho2 <beta, 1 - e^{-g/rho2}> over f_i + g_j <= C_ij (SLSQP on a 4 x 5 problem) and
+    # Frank-Wolfe on H_0 (both step rules) give the same potentials.
+    from scipy.optimize import minimize
+    x, y, a, b = _sorted_problem(4, 5, 3)
+    r1, r2, p = 0.3, 0.7, 2.0
+    n, m = 4, 5
+    C = np.abs(x[:, None] - y[None, :]) ** p
+    neg = lambda z: -(r1 * np.sum(a * (1 - np.exp(-z[:n] / r1))) + r2 * np.sum(b * (1 - np.exp(-z[n:] / r2))))
+    cons = [{"type": "ineq", "fun": (lambda z, i=i, j=j: C[i, j] - z[i] - z[n + j])}
+            for i in range(n) for j in range(m)]
+    res = minimize(neg, np.zeros(n + m), method="SLSQP", constraints=cons,
+                   options={"ftol": 1e-15, "maxiter": 1000})
+    assert res.success
+    for ls, tol in ((True, 1e-13), (False, 1e-10)):
+        fw = oracle.fw_1d(x, y, a, b, r1, r2, p=p, line_search=ls, max_iter=200000, tol=tol)
+        assert fw.gap <= tol
+        assert np.max(np.abs(fw.f - res.x[:n])) < 1e-6 and np.max(np.abs(fw.g - res.x[n:])) < 1e-6
+
+
+def test_fw_gap_bounds_the_suboptimality():
+    # The Frank-Wolfe gap at an iterate bounds H_0* - H_0(iterate) (concavity of H_0); and
+    # H_0 of the reported pair equals F_0 there (lambda* folded in).
+    pr = workloads.oned()
+    x, y = np.sort(pr.x.reshape(-1).astype(np.float64)), np.sort(pr.y.reshape(-1).astype(np.float64))
+    a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
+    rho = 0.5
+    star = oracle.fw_1d(x, y, a, b, rho, rho, line_search=True, max_iter=3000, tol=1e-14)
+    h_star, _ = oracle.h0(a, b, star.f, star.g, rho, rho)
+    for K in (1, 3, 10, 40):
+        it = oracle.fw_1d(x, y, a, b, rho, rho, max_iter=K)  # iterate K (K steps)
+        gap = oracle.fw_1d(x, y, a, b, rho, rho, max_iter=K + 1, history=True).hist_gap[K]
+        h, lam = oracle.h0(a, b, it.f, it.g, rho, rho)
+        assert abs(lam) < 1e-12  # the reported pair is already optimally translated
+        assert 0.0 <= h_star - h <= gap + 1e-12, (K, h_star - h, gap)
