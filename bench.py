@@ -56,7 +56,7 @@ def parse():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="cloud3d",
                     choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16", "anderson",
-                             "phi"),
+                             "phi", "fw1d"),
                     help="cloud3d (default) is the benchmark step above; the others print one "
                          "JSON line of their own measurement (see extra_workload)")
     return ap.parse_args()
@@ -141,7 +141,11 @@ def extra_workload(args, uot, torch, np, workloads):
               < 1e-6 of TI and plain Sinkhorn with and without Anderson extrapolation
               (K = 4, r = 1e-7).
     phi       the same clouds at eps = 0.01, rho in {0.1, 1, 10}: time and iterations to change
-              < 1e-6 of F- and G-Sinkhorn with the KL and the Berg entropy."""
+              < 1e-6 of F- and G-Sinkhorn with the KL and the Berg entropy.
+    fw1d      1-D Frank-Wolfe for unregularised UOT: the sorted 1-D measures N=M=200, rho=1,
+              5000 iterations with step 2/(2+t) (microseconds per iteration, FP64 oracle on the
+              same iterations); and 4096 problems, N_p, M_p ~ U{64..4096}, line search to gap
+              1e-9 (point-iterations/s = sum_p (N_p + M_p) iters_p / wall)."""
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
@@ -278,6 +282,40 @@ def extra_workload(args, uot, torch, np, workloads):
                                            "and Berg entropies, F- and G-Sinkhorn, change "
                                            "checked every %d" % (args.n, CHECK_EVERY)},
                     "time_to_tol": res, "roofline": None})
+    elif args.workload == "fw1d":
+        import oracle
+        pr = workloads.oned()
+        xs = np.sort(pr.x.reshape(-1)).astype(np.float32)
+        ys = np.sort(pr.y.reshape(-1)).astype(np.float32)
+        a, b, x, y = t(pr.alpha), t(pr.beta), t(xs), t(ys)
+        uot.fw1d(x, y, a, b, 1.0, 1.0, max_iter=10)  # warm
+        _, dt = _timed(torch, lambda: uot.fw1d(x, y, a, b, 1.0, 1.0, max_iter=5000))
+        t0 = time.perf_counter()
+        oracle.fw_1d(xs.astype(np.float64), ys.astype(np.float64), pr.alpha.astype(np.float64),
+                     pr.beta.astype(np.float64), 1.0, 1.0, max_iter=5000)
+        cpu = (time.perf_counter() - t0) / 5000 * 1e6
+        bt = workloads.fw1d_batch()
+        args_b = (bt.offN, bt.offM, t(bt.x), t(bt.y), t(bt.alpha), t(bt.beta),
+                  torch.from_numpy(bt.rho1).to(dev), torch.from_numpy(bt.rho2).to(dev))
+        uot.fw1d_batched(*args_b, line_search=True, max_iter=2)  # warm
+        (f, g, iters, gap, status), dtb = _timed(torch, lambda: uot.fw1d_batched(
+            *args_b, line_search=True, max_iter=2000, tol=1e-9))
+        it = iters.cpu().numpy().astype(np.float64)
+        pts = np.diff(bt.offN) + np.diff(bt.offM)
+        out["dtype"] = "f64"
+        out.update({"metric": "microseconds per Frank-Wolfe iteration, 1-D N=M=200 (latency bound)",
+                    "value": dt / 5000 * 1e6, "unit": "us/iteration", "higher_is_better": False,
+                    "config": {"workload": "sorted 1-D measures N=M=200, rho=1, eps=0, 5000 "
+                                           "iterations, step 2/(2+t); and 4096 problems "
+                                           "N_p,M_p ~ U{64..4096}, line search to gap 1e-9"},
+                    "batched": {"seconds": dtb, "point_iterations_per_s": float((pts * it).sum()) / dtb,
+                                "iterations_percentiles_0_50_90_99_100":
+                                    np.percentile(it, [0, 50, 90, 99, 100]).tolist(),
+                                "status_counts": {str(k): int(v) for k, v in
+                                                  zip(*np.unique(status.cpu().numpy(), return_counts=True))}},
+                    "roofline": None,
+                    "cpu_baseline": {"value": cpu, "unit": "us/iteration", "kind": "oracle", "cores": 1,
+                                     "sample": "FP64 C oracle, the same 5000 iterations"}})
     else:  # highdim16
         pr = workloads.highdim16()
         a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)

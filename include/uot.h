@@ -293,6 +293,39 @@ uot_status uot_ti_sinkhorn_batched(int32_t B, const int64_t *offN, const int64_t
                                    int32_t *status, void *workspace, size_t workspace_bytes,
                                    void *stream);
 
+/*
+ * Frank-Wolfe for unregularised (eps = 0) KL-UOT between 1-D measures (Sec. 4), for B
+ * independent problems at once. Problem b owns the points [offN[b], offN[b+1]) of x/alpha/f
+ * and [offM[b], offM[b+1]) of y/beta/g; its supports must be sorted ascending. The method
+ * is Frank-Wolfe on H_0(fb, gb) = sup_lambda F_0(fb + lambda, gb - lambda) over fb (+) gb <= C,
+ * C_ij = |x_i - y_j|^p, from (0, 0): each iteration forms the gradient of H_0, the tilted
+ * histograms alpha e^{-(fb + l)/rho1} and beta e^{-(gb - l)/rho2} with l = lambda*(fb, gb)
+ * (Prop. 2; equal masses), takes the linear oracle (r, s) = the dual solution of balanced
+ * 1-D OT between them (the monotone coupling; its walk's cells are tight), and steps
+ * (fb, gb) <- (1 - gamma)(fb, gb) + gamma (r, s) with gamma = 2/(2 + t) (line_search = 0) or
+ * the maximiser of H_0 on the segment (line_search = 1). The Frank-Wolfe gap
+ * <grad H_0, (r, s) - (fb, gb)> bounds H_0* - H_0(fb, gb); an iteration whose gap is <= tol
+ * (tol > 0) ends that problem before its step, otherwise it runs max_iter iterations.
+ *  B >= 1; offN, offM (host) [B+1] as in uot_ti_sinkhorn_batched.
+ *  x [offN[B]], y [offM[B]], alpha [offN[B]], beta [offM[B]] (device, float32).
+ *  rho1, rho2 (device, double) [B]; p >= 1 (host).
+ *  f [offN[B]], g [offM[B]] (device, out): the reported potentials (fb + l*, gb - l*).
+ *  iters (device, int32 [B], out): iterations run (linear-oracle calls); gap (device,
+ *  double [B], out): the last gap; status (device, int32 [B], out): UOT_BATCH_* (INVALID:
+ *  unsorted support, bad weights or penalties; its f, g are NaN).
+ * Everything runs in double precision; one workgroup owns one problem at a time and runs all
+ * of its iterations in one launch. Workspace: uot_fw1d_workspace_bytes.
+ */
+uot_status uot_fw1d_batched(int32_t B, const int64_t *offN, const int64_t *offM, const float *x,
+                            const float *y, const float *alpha, const float *beta,
+                            const double *rho1, const double *rho2, double p, int32_t line_search,
+                            int32_t max_iter, double tol, float *f, float *g, int32_t *iters,
+                            double *gap, int32_t *status, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* Workspace bytes of uot_fw1d_batched (offN, offM on the host); 0 on invalid input. */
+size_t uot_fw1d_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM);
+
 /* Workspace bytes of uot_ti_sinkhorn_batched (offN, offM on the host); 0 on invalid input. */
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d);
 

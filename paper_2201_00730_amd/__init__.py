@@ -16,12 +16,14 @@ import math
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_apply", "marginals",
            "backward", "workspace_bytes", "UOTLoss", "uot_loss", "library_path", "load_library",
            "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
-           "ti_sinkhorn_batched"]
+           "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
+           "fw1d_batched", "fw1d"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -120,6 +122,11 @@ def load_library():
     lib.uot_ti_sinkhorn_batched.argtypes = [I32, P, P, I32, D, P, P, P, P, P, P, P, I32, D, I32,
                                             P, P, P, P, P, S, P]
     lib.uot_ti_sinkhorn_batched.restype = ctypes.c_int
+    lib.uot_fw1d_batched.argtypes = [I32, P, P, P, P, P, P, P, P, D, I32, I32, D, P, P, P, P, P,
+                                     P, S, P]
+    lib.uot_fw1d_batched.restype = ctypes.c_int
+    lib.uot_fw1d_workspace_bytes.argtypes = [I32, P, P]
+    lib.uot_fw1d_workspace_bytes.restype = S
     lib.uot_batched_workspace_bytes.argtypes = [I32, P, P, I32]
     lib.uot_batched_workspace_bytes.restype = S
     _lib = lib
@@ -399,7 +406,6 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
     tensors [B] (or host sequences). Returns (f, g, iters, status) as device tensors."""
     _require_gpu()
     lib = load_library()
-    import numpy as np
     offN = np.ascontiguousarray(np.asarray(offN, dtype=np.int64))
     offM = np.ascontiguousarray(np.asarray(offM, dtype=np.int64))
     B = len(offN) - 1
@@ -435,6 +441,50 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
                                        float(tol), int(check_every), _ptr(f), _ptr(g), _ptr(iters),
                                        _ptr(status), _ptr(workspace), workspace.numel(), _stream()))
     return f, g, iters, status
+
+
+def fw1d_batched(offN, offM, x, y, alpha, beta, rho1, rho2=None, *, p: float = 2.0,
+                 line_search: bool = False, max_iter: int = 1000, tol: float = 0.0):
+    """Frank-Wolfe for unregularised 1-D KL-UOT (Sec. 4) on B problems with sorted supports
+    (see uot_fw1d_batched). offN, offM: host int64 [B+1]; x, y, alpha, beta: float32 device
+    [total]; rho1, rho2: float64 device [B] (or scalars). Returns (f, g, iters, gap, status)."""
+    _require_gpu()
+    lib = load_library()
+    offN = np.ascontiguousarray(np.asarray(offN, dtype=np.int64))
+    offM = np.ascontiguousarray(np.asarray(offM, dtype=np.int64))
+    B = len(offN) - 1
+    x, y = _f32(x, "x").reshape(-1), _f32(y, "y").reshape(-1)
+    alpha, beta = _f32(alpha, "alpha"), _f32(beta, "beta")
+    dev = alpha.device
+
+    def per_problem(v, name):
+        if isinstance(v, torch.Tensor):
+            return v.to(device=dev, dtype=torch.float64).contiguous().reshape(-1)
+        return torch.full((B,), float(v), dtype=torch.float64, device=dev)
+    r1 = per_problem(rho1, "rho1")
+    r2 = per_problem(rho1 if rho2 is None else rho2, "rho2")
+    f = torch.empty(int(offN[-1]), dtype=torch.float32, device=dev)
+    g = torch.empty(int(offM[-1]), dtype=torch.float32, device=dev)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    gap = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    nb = int(lib.uot_fw1d_workspace_bytes(B, offN.ctypes.data, offM.ctypes.data))
+    if nb == 0:
+        _check(UOT_ERR_INVALID)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    st = lib.uot_fw1d_batched(B, offN.ctypes.data, offM.ctypes.data, _ptr(x), _ptr(y), _ptr(alpha),
+                              _ptr(beta), _ptr(r1), _ptr(r2), float(p), int(bool(line_search)),
+                              int(max_iter), float(tol), _ptr(f), _ptr(g), _ptr(iters), _ptr(gap),
+                              _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _check(st)
+    return f, g, iters, gap, status
+
+
+def fw1d(x, y, alpha, beta, rho1: float, rho2: float | None = None, **kw):
+    """One 1-D problem (sorted supports) by fw1d_batched; returns (f, g, iters, gap, status)."""
+    n, m = int(np.prod(tuple(x.shape))), int(np.prod(tuple(y.shape)))
+    f, g, it, gap, st = fw1d_batched([0, n], [0, m], x, y, alpha, beta, rho1, rho2, **kw)
+    return f, g, int(it[0].item()), float(gap[0].item()), int(st[0].item())
 
 
 class UOTLoss(torch.autograd.Function):

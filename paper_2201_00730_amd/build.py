@@ -23,6 +23,7 @@ SOURCES = [
     "kernels_apply.hip",
     "kernels_batched.hip",
     "kernels_anderson.hip",
+    "kernels_fw.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

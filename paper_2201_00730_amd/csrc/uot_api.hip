@@ -958,6 +958,108 @@ struct BatchLayout {
   int64_t totN = 0, totM = 0;
 };
 
+// Workspace of uot_fw1d_batched: device offsets and the per-point scratch of the solver.
+struct FwLayout {
+  size_t offN = 0, offM = 0, fb = 0, gb = 0, Ac = 0, Bc = 0, r = 0, s = 0, jst = 0, ist = 0;
+  size_t total = 0;
+  int64_t totN = 0, totM = 0;
+};
+
+uot_status fw_layout(int32_t B, const int64_t *offN, const int64_t *offM, FwLayout &L) {
+  if (B < 1) return fail(UOT_ERR_INVALID, "B=%d must be >= 1", B);
+  if (offN == nullptr || offM == nullptr) return fail(UOT_ERR_INVALID, "offN/offM are NULL");
+  if (offN[0] != 0 || offM[0] != 0) return fail(UOT_ERR_INVALID, "offN[0] and offM[0] must be 0");
+  for (int p = 0; p < B; ++p) {
+    const int64_t n = offN[p + 1] - offN[p], m = offM[p + 1] - offM[p];
+    if (n < 1 || m < 1) return fail(UOT_ERR_INVALID, "problem %d has n=%lld, m=%lld (must be >= 1)", p, (long long)n, (long long)m);
+    if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_ERR_INVALID, "problem %d is too large", p);
+  }
+  L.totN = offN[B];
+  L.totM = offM[B];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.offN = take((size_t)(B + 1) * sizeof(int64_t));
+  L.offM = take((size_t)(B + 1) * sizeof(int64_t));
+  L.fb = take((size_t)L.totN * sizeof(double));
+  L.Ac = take((size_t)L.totN * sizeof(double));
+  L.r = take((size_t)L.totN * sizeof(double));
+  L.jst = take((size_t)L.totN * sizeof(int));
+  L.gb = take((size_t)L.totM * sizeof(double));
+  L.Bc = take((size_t)L.totM * sizeof(double));
+  L.s = take((size_t)L.totM * sizeof(double));
+  L.ist = take((size_t)L.totM * sizeof(int));
+  L.total = off;
+  return UOT_OK;
+}
+
+uot_status fw1d(int32_t B, const int64_t *offN, const int64_t *offM, const float *x, const float *y,
+                const float *alpha, const float *beta, const double *rho1, const double *rho2,
+                double p, int32_t line_search, int32_t max_iter, double tol, float *f, float *g,
+                int32_t *iters, double *gap, int32_t *status, void *workspace,
+                size_t workspace_bytes, void *stream) {
+  FwLayout L;
+  UOT_TRY(fw_layout(B, offN, offM, L));
+  if (!(p >= 1.0) || !std::isfinite(p)) return fail(UOT_ERR_INVALID, "p=%g must be finite and >= 1", p);
+  if (line_search != 0 && line_search != 1) return fail(UOT_ERR_INVALID, "line_search=%d must be 0 or 1", line_search);
+  if (max_iter < 1) return fail(UOT_ERR_INVALID, "max_iter=%d must be >= 1", max_iter);
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(UOT_ERR_INVALID, "tol=%g must be finite and >= 0", tol);
+  UOT_TRY(check_device_ptr(x, "x"));
+  UOT_TRY(check_device_ptr(y, "y"));
+  UOT_TRY(check_device_ptr(alpha, "alpha"));
+  UOT_TRY(check_device_ptr(beta, "beta"));
+  UOT_TRY(check_device_ptr(rho1, "rho1"));
+  UOT_TRY(check_device_ptr(rho2, "rho2"));
+  UOT_TRY(check_device_ptr(f, "f"));
+  UOT_TRY(check_device_ptr(g, "g"));
+  UOT_TRY(check_device_ptr(iters, "iters"));
+  UOT_TRY(check_device_ptr(gap, "gap"));
+  UOT_TRY(check_device_ptr(status, "status"));
+  Workspace w;
+  UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  UOT_HIP(hipMemcpyAsync(at<int64_t>(w.ptr, L.offN), offN, (size_t)(B + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(at<int64_t>(w.ptr, L.offM), offM, (size_t)(B + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  UOT_HIP(hipStreamSynchronize(s));  // the host tables must outlive the copies
+  FwLaunch l;
+  l.B = B;
+  l.offN = at<int64_t>(w.ptr, L.offN);
+  l.offM = at<int64_t>(w.ptr, L.offM);
+  l.x = x;
+  l.y = y;
+  l.alpha = alpha;
+  l.beta = beta;
+  l.rho1 = rho1;
+  l.rho2 = rho2;
+  l.p = p;
+  l.line_search = line_search;
+  l.max_iter = max_iter;
+  l.tol = tol;
+  l.fb = at<double>(w.ptr, L.fb);
+  l.gb = at<double>(w.ptr, L.gb);
+  l.Ac = at<double>(w.ptr, L.Ac);
+  l.Bc = at<double>(w.ptr, L.Bc);
+  l.r = at<double>(w.ptr, L.r);
+  l.s = at<double>(w.ptr, L.s);
+  l.jst = at<int>(w.ptr, L.jst);
+  l.ist = at<int>(w.ptr, L.ist);
+  l.f = f;
+  l.g = g;
+  l.iters = iters;
+  l.gap = gap;
+  l.status = status;
+  const int cus = device_cus();
+  l.max_blocks = cus > 0 ? 2 * cus : 512;
+  UOT_HIP(launch_fw1d(l, s));
+  if (w.owned) UOT_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
+  return UOT_OK;
+}
+
 uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
                           BatchLayout &L) {
   if (B < 1) return fail(UOT_ERR_INVALID, "B=%d must be >= 1", B);
@@ -1276,6 +1378,23 @@ int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries) 
   if (total_ms) *total_ms = uot::g_prof[kind].ms;
   if (total_entries) *total_entries = uot::g_prof[kind].entries;
   return uot::g_prof[kind].launches;
+}
+
+size_t uot_fw1d_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM) {
+  uot::FwLayout L;
+  if (uot::fw_layout(B, offN, offM, L) != UOT_OK) return 0;
+  return L.total;
+}
+
+uot_status uot_fw1d_batched(int32_t B, const int64_t *offN, const int64_t *offM, const float *x,
+                            const float *y, const float *alpha, const float *beta,
+                            const double *rho1, const double *rho2, double p, int32_t line_search,
+                            int32_t max_iter, double tol, float *f, float *g, int32_t *iters,
+                            double *gap, int32_t *status, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+  uot::g_last_error.clear();
+  return uot::fw1d(B, offN, offM, x, y, alpha, beta, rho1, rho2, p, line_search, max_iter, tol,
+                   f, g, iters, gap, status, workspace, workspace_bytes, stream);
 }
 
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d) {

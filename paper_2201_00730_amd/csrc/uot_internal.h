@@ -355,4 +355,24 @@ struct AndersonArgs {
 hipError_t launch_anderson(const AndersonArgs &a, hipStream_t s);
 size_t anderson_gram_bytes(int n);
 
+// 1-D Frank-Wolfe (kernels_fw.hip): problem b owns [offN[b], offN[b+1]) of x, alpha, f and
+// the double scratch fb, Ac, r, jst, and [offM[b], offM[b+1]) of y, beta, g, gb, Bc, s, ist.
+struct FwLaunch {
+  int B;
+  const int64_t *offN, *offM;  // device [B + 1]
+  const float *x, *y, *alpha, *beta;
+  const double *rho1, *rho2;
+  double p;
+  int line_search, max_iter;
+  double tol;
+  double *fb, *gb, *Ac, *Bc, *r, *s;
+  int *jst, *ist;
+  float *f, *g;
+  int32_t *iters;
+  double *gap;
+  int32_t *status;
+  int max_blocks;
+};
+hipError_t launch_fw1d(const FwLaunch &l, hipStream_t s);
+
 }  // namespace uot

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_2201_00730_amd as uot
@@ -161,3 +162,19 @@ def test_phi_rejects_bad_settings_before_any_launch(lib, entropy, variant):
     assert b"phi" in lib.uot_last_error()
     assert lib.uot_sinkhorn_phi(ctypes.byref(c), None, None, ctypes.byref(prm), None, None, None,
                                 None, 0, None, None) == uot.UOT_ERR_INVALID
+
+
+def test_fw1d_rejects_bad_arguments_before_any_launch(lib):
+    offN = np.array([0, 3, 5], dtype=np.int64)
+    offM = np.array([0, 2, 6], dtype=np.int64)
+    assert lib.uot_fw1d_workspace_bytes(2, offN.ctypes.data, offM.ctypes.data) > 0
+    bad = np.array([0, 3, 3], dtype=np.int64)  # an empty problem
+    assert lib.uot_fw1d_workspace_bytes(2, bad.ctypes.data, offM.ctypes.data) == 0
+    assert lib.uot_fw1d_workspace_bytes(0, offN.ctypes.data, offM.ctypes.data) == 0
+    for p, ls, it, tol in ((0.5, 0, 10, 0.0), (2.0, 2, 10, 0.0), (2.0, 0, 0, 0.0),
+                           (2.0, 0, 10, -1.0), (float("nan"), 0, 10, 0.0)):
+        st = lib.uot_fw1d_batched(2, offN.ctypes.data, offM.ctypes.data, None, None, None, None,
+                                  None, None, p, ls, it, tol, None, None, None, None, None, None,
+                                  0, None)
+        assert st == uot.UOT_ERR_INVALID
+        assert lib.uot_last_error()

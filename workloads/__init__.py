@@ -165,6 +165,36 @@ def batch2d(B: int = 4096, nmin: int = 64, nmax: int = 4096, seed: int = 4,
                  eps=eps.astype(np.float64), rho1=rho.astype(np.float64), rho2=rho.astype(np.float64))
 
 
+def fw1d_batch(B: int = 4096, nmin: int = 64, nmax: int = 4096, seed: int = 6,
+               rho_range=(0.1, 10.0)) -> Batch:
+    """B 1-D problems for the unregularised Frank-Wolfe solver: N_p, M_p integer-uniform in
+    [nmin, nmax]; x ~ U[0,1], y ~ N(0.5, 0.2^2), each sorted ascending within its problem;
+    positive random weights (U[0.2, 1] / size) with masses ~ U[0.5, 2]; rho log-uniform,
+    rho1 = rho2; eps unused (0)."""
+    rng = np.random.default_rng(seed)
+    N = rng.integers(nmin, nmax + 1, size=B)
+    M = rng.integers(nmin, nmax + 1, size=B)
+    ma = rng.uniform(0.5, 2.0, size=B)
+    mb = rng.uniform(0.5, 2.0, size=B)
+    rho = np.exp(rng.uniform(np.log(rho_range[0]), np.log(rho_range[1]), size=B))
+    offN = np.concatenate([[0], np.cumsum(N)]).astype(np.int64)
+    offM = np.concatenate([[0], np.cumsum(M)]).astype(np.int64)
+    x = np.empty(int(offN[-1]))
+    y = np.empty(int(offM[-1]))
+    alpha = np.empty(int(offN[-1]))
+    beta = np.empty(int(offM[-1]))
+    for b in range(B):
+        n0, n1, m0, m1 = offN[b], offN[b + 1], offM[b], offM[b + 1]
+        x[n0:n1] = np.sort(rng.uniform(0.0, 1.0, size=n1 - n0))
+        y[m0:m1] = np.sort(rng.normal(0.5, 0.2, size=m1 - m0))
+        wa = rng.uniform(0.2, 1.0, size=n1 - n0)
+        wb = rng.uniform(0.2, 1.0, size=m1 - m0)
+        alpha[n0:n1] = wa * ma[b] / wa.sum()
+        beta[m0:m1] = wb * mb[b] / wb.sum()
+    return Batch(offN=offN, offM=offM, x=_f32(x), y=_f32(y), alpha=_f32(alpha), beta=_f32(beta),
+                 eps=np.zeros(B), rho1=rho.astype(np.float64), rho2=rho.astype(np.float64))
+
+
 def random_small(n: int, m: int, d: int = 2, seed: int = 0, eps: float = 0.1, rho1: float = 1.0,
                  rho2: float = 1.0, mass_a: float = 1.0, mass_b: float = 1.5, dense: bool = False,
                  p: float = 2.0, weight_jitter: bool = True) -> Problem:
