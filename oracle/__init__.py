@@ -83,6 +83,13 @@ def _load():
             lib.or_h0.restype = D
             lib.or_fw_1d.argtypes = [I, I, P, P, P, P, D, D, D, I, I, D, P, P, P, P]
             lib.or_fw_1d.restype = I
+            lib.or_solve_mot_1d.argtypes = [I, P, P, P, P, P, P, P]
+            lib.or_solve_mot_1d.restype = D
+            lib.or_mm_lambda.argtypes = [I, P, P, P, P, D, P]
+            lib.or_mm_dual.argtypes = [I, P, P, P, P, D]
+            lib.or_mm_dual.restype = D
+            lib.or_fw_barycenter.argtypes = [I, P, P, P, P, D, I, D, P, P, P, P]
+            lib.or_fw_barycenter.restype = I
             lib.or_anderson_mix.argtypes = [I, I, P, D, P, P]
             lib.or_anderson_mix.restype = I
             lib.or_sinkhorn_anderson.argtypes = [CP, P, P, D, D, D, I, I, D, I, D, I, I, P, P, P, P, P]
@@ -390,6 +397,62 @@ def fw_1d(x, y, alpha, beta, rho1: float, rho2: float, *, p: float = 2.0,
                           _ptr(g), ctypes.byref(gap), _ptr(hg))
     return FWResult(f=f, g=g, iters=it, gap=gap.value,
                     hist_gap=None if hg is None else hg[:it].copy())
+
+
+def _off(off):
+    return np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+
+
+def solve_mot_1d(off, x, a, w):
+    """Balanced 1-D multi-marginal OT (Sec. 5), squared distance, measures k on
+    [off[k], off[k+1]) with sorted supports and equal masses: returns (cost, f, bary_x, bary_m)."""
+    off, x, a, w = _off(off), _f64(x), _f64(a), _f64(w)
+    K = len(off) - 1
+    f = np.empty(int(off[-1]))
+    nb = int(off[-1]) - K + 1
+    bx, bm = np.empty(nb), np.empty(nb)
+    cost = _load().or_solve_mot_1d(K, off.ctypes.data_as(ctypes.c_void_p), _ptr(x), _ptr(a), _ptr(w),
+                                   _ptr(f), _ptr(bx), _ptr(bm))
+    return cost, f, bx, bm
+
+
+def mm_lambda(off, a, fb, w, rho: float) -> np.ndarray:
+    """Closed-form optimal translation of the multi-marginal dual (KL, Sec. 5)."""
+    off, a, fb, w = _off(off), _f64(a), _f64(fb), _f64(w)
+    lam = np.empty(len(off) - 1)
+    _load().or_mm_lambda(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), _ptr(a), _ptr(fb),
+                         _ptr(w), float(rho), _ptr(lam))
+    return lam
+
+
+def mm_dual(off, a, f, w, rho: float) -> float:
+    off, a, f, w = _off(off), _f64(a), _f64(f), _f64(w)
+    return _load().or_mm_dual(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), _ptr(a), _ptr(f),
+                              _ptr(w), float(rho))
+
+
+@dataclass
+class BarycenterResult:
+    f: np.ndarray
+    bary_x: np.ndarray
+    bary_m: np.ndarray
+    iters: int
+    gap: float
+
+
+def fw_barycenter(off, x, a, w, rho: float, *, max_iter: int = 1000, tol: float = 0.0) -> BarycenterResult:
+    """Frank-Wolfe on the translation-invariant multi-marginal dual (Sec. 5): unbalanced 1-D
+    barycenter of K measures (sorted supports), KL penalty rho, weights w; step 2/(2+t)."""
+    off, x, a, w = _off(off), _f64(x), _f64(a), _f64(w)
+    K = len(off) - 1
+    f = np.empty(int(off[-1]))
+    nb = int(off[-1]) - K + 1
+    bx, bm = np.empty(nb), np.empty(nb)
+    gap = ctypes.c_double(0.0)
+    it = _load().or_fw_barycenter(K, off.ctypes.data_as(ctypes.c_void_p), _ptr(x), _ptr(a), _ptr(w),
+                                  float(rho), int(max_iter), float(tol), _ptr(f), _ptr(bx), _ptr(bm),
+                                  ctypes.byref(gap))
+    return BarycenterResult(f=f, bary_x=bx, bary_m=bm, iters=it, gap=gap.value)
 
 
 def plan_apply(cost: Cost, alpha, beta, eps: float, f, g, V, transpose: bool = False) -> np.ndarray:

@@ -20,6 +20,7 @@
  * every sum (the nu_i = 0 convention of the Csiszar divergence, Sec. 1).
  */
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -654,6 +655,167 @@ int or_fw_1d(int n, int m, const double *x, const double *y, const double *alpha
   for (int j = 0; j < m; ++j) g[j] = gb[j] - lam;
   if (gap_out) *gap_out = gap;
   free(fb); free(gb); free(at); free(bt); free(r); free(s); free(ft); free(gt);
+  return t < max_iter ? t + 1 : max_iter;
+}
+
+/*
+ * ---------------------------------------------------------------------------------------
+ * 1-D unbalanced barycenters by Frank-Wolfe on the translation-invariant multi-marginal
+ * dual (Sec. 5), squared distance ground cost.
+ * ---------------------------------------------------------------------------------------
+ * Multi-marginal cost of one tuple (z_0 .. z_{K-1}): min_b sum_k w_k (z_k - b)^2, attained
+ * at the barycentric map b = sum_k w_k z_k / sum_k w_k.
+ */
+static double or_mm_cost(int K, const double *w, const double *z, double *bary) {
+  double sw = 0.0, sz = 0.0;
+  for (int k = 0; k < K; ++k) { sw += w[k]; sz += w[k] * z[k]; }
+  const double b = sz / sw;
+  double c = 0.0;
+  for (int k = 0; k < K; ++k) c += w[k] * (z[k] - b) * (z[k] - b);
+  if (bary) *bary = b;
+  return c;
+}
+
+/*
+ * Balanced multi-marginal OT in 1-D between K measures with sorted supports x_k (offsets
+ * off[0..K]) and weights a of equal masses: the walk starts at the first point of every
+ * measure; at each step the measure with the least remaining mass among those not at their
+ * last point (the first such k on ties) advances, the current tuple receiving that mass and
+ * every measure's remainder dropping by it; when all are at their last point the final
+ * tuple takes what is left. Every visited tuple is tight: f_{0,0} = C(first tuple), the
+ * other f_{k,0} = 0, and a measure entering point i sets f_{k,i} = C(tuple) minus the other
+ * potentials of the tuple. Writes f[off[K]] and, optionally, the support and mass of each
+ * visited tuple (off[K] - K + 1 of them: its barycentric point and mass). Returns the total
+ * transport cost.
+ */
+double or_solve_mot_1d(int K, const int64_t *off, const double *x, const double *a,
+                       const double *w, double *f, double *bary_x, double *bary_m) {
+  int idx[64];
+  double rem[64], z[64];
+  if (K < 1 || K > 64) return NAN;
+  for (int k = 0; k < K; ++k) {
+    idx[k] = 0;
+    rem[k] = a[off[k]];
+    z[k] = x[off[k]];
+    f[off[k]] = 0.0;
+  }
+  double b;
+  f[off[0]] = or_mm_cost(K, w, z, &b);
+  double cost = 0.0;
+  int t = 0;
+  while (1) {
+    int p = -1;
+    for (int k = 0; k < K; ++k)
+      if (idx[k] < off[k + 1] - off[k] - 1 && (p < 0 || rem[k] < rem[p])) p = k;
+    const double c = or_mm_cost(K, w, z, &b);
+    if (p < 0) {  /* every measure at its last point: the final tuple takes the rest */
+      double mv = 0.0;
+      for (int k = 0; k < K; ++k) if (rem[k] > mv) mv = rem[k];
+      cost += mv * c;
+      if (bary_x) { bary_x[t] = b; bary_m[t] = mv; }
+      break;
+    }
+    const double mv = rem[p] > 0.0 ? rem[p] : 0.0;
+    cost += mv * c;
+    if (bary_x) { bary_x[t] = b; bary_m[t] = mv; }
+    ++t;
+    for (int k = 0; k < K; ++k) rem[k] -= mv;
+    idx[p] += 1;
+    const int64_t e = off[p] + idx[p];
+    z[p] = x[e];
+    rem[p] = a[e];
+    double others = 0.0;
+    for (int k = 0; k < K; ++k) if (k != p) others += f[off[k] + idx[k]];
+    f[e] = or_mm_cost(K, w, z, NULL) - others;
+  }
+  return cost;
+}
+
+/*
+ * Optimal translation of the multi-marginal dual (Prop. for the KL setting in Sec. 5): with
+ * q_k = log <a_k, e^{-fb_k / (w_k rho)}>, lambda_k = w_k rho q_k - w_k / sum_j w_j *
+ * sum_j w_j rho q_j (so sum_k lambda_k = 0).
+ */
+void or_mm_lambda(int K, const int64_t *off, const double *a, const double *fb, const double *w,
+                  double rho, double *lam) {
+  double sw = 0.0, sq = 0.0, q[64];
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int64_t i = off[k]; i < off[k + 1]; ++i) s += a[i] * exp(-fb[i] / (w[k] * rho));
+    q[k] = log(s);
+    sw += w[k];
+    sq += w[k] * rho * q[k];
+  }
+  for (int k = 0; k < K; ++k) lam[k] = w[k] * rho * q[k] - w[k] / sw * sq;
+}
+
+/* The multi-marginal dual F(f) = sum_k <a_k, w_k rho (1 - e^{-f_k / (w_k rho)})> (KL). */
+double or_mm_dual(int K, const int64_t *off, const double *a, const double *f, const double *w,
+                  double rho) {
+  double v = 0.0;
+  for (int k = 0; k < K; ++k)
+    for (int64_t i = off[k]; i < off[k + 1]; ++i)
+      v += a[i] * w[k] * rho * (1.0 - exp(-f[i] / (w[k] * rho)));
+  return v;
+}
+
+/*
+ * Frank-Wolfe on H(fb) = sup_{sum lambda = 0} F(fb + lambda) over fb_0 (+) ... (+) fb_{K-1} <= C
+ * (Sec. 5), from fb = 0: each iteration takes lambda* (or_mm_lambda), the gradient of H =
+ * the tilted histograms a_k e^{-(fb_k + lambda_k)/(w_k rho)} (equal masses), the linear
+ * oracle = the balanced multi-marginal dual between them (or_solve_mot_1d after scaling to
+ * mass 1), the gap sum_k <at_k, r_k - fb_k>, and the step 2/(2 + t). An iteration whose
+ * gap is <= tol (tol > 0) ends the loop before its step. Writes the reported potentials
+ * fb_k + lambda_k, and the barycenter: the support and masses of the balanced plan between
+ * the final tilted marginals (off[K] - K + 1 entries; masses in the units of the inputs).
+ * Returns the iterations run.
+ */
+int or_fw_barycenter(int K, const int64_t *off, const double *x, const double *a,
+                     const double *w, double rho, int max_iter, double tol, double *f,
+                     double *bary_x, double *bary_m, double *gap_out) {
+  const int64_t tot = off[K];
+  double *fb = (double *)calloc((size_t)tot, sizeof(double));
+  double *at = (double *)malloc(sizeof(double) * (size_t)tot);
+  double *an = (double *)malloc(sizeof(double) * (size_t)tot);
+  double *r = (double *)malloc(sizeof(double) * (size_t)tot);
+  double lam[64], mass[64];
+  double gap = INFINITY;
+  int t;
+  for (t = 0; t < max_iter; ++t) {
+    or_mm_lambda(K, off, a, fb, w, rho, lam);
+    for (int k = 0; k < K; ++k) {
+      mass[k] = 0.0;
+      for (int64_t i = off[k]; i < off[k + 1]; ++i) {
+        at[i] = a[i] * exp(-(fb[i] + lam[k]) / (w[k] * rho));
+        mass[k] += at[i];
+      }
+      for (int64_t i = off[k]; i < off[k + 1]; ++i) an[i] = at[i] / mass[k];
+    }
+    or_solve_mot_1d(K, off, x, an, w, r, NULL, NULL);
+    gap = 0.0;
+    for (int64_t i = 0; i < tot; ++i) gap += at[i] * (r[i] - fb[i]);
+    if (tol > 0.0 && gap <= tol) break;
+    const double gamma = 2.0 / (2.0 + t);
+    for (int64_t i = 0; i < tot; ++i) fb[i] = (1.0 - gamma) * fb[i] + gamma * r[i];
+  }
+  or_mm_lambda(K, off, a, fb, w, rho, lam);
+  double m0 = 0.0;
+  for (int k = 0; k < K; ++k) {
+    mass[k] = 0.0;
+    for (int64_t i = off[k]; i < off[k + 1]; ++i) {
+      f[i] = fb[i] + lam[k];
+      at[i] = a[i] * exp(-f[i] / (w[k] * rho));
+      mass[k] += at[i];
+    }
+    for (int64_t i = off[k]; i < off[k + 1]; ++i) an[i] = at[i] / mass[k];
+  }
+  m0 = mass[0];
+  if (bary_x) {
+    or_solve_mot_1d(K, off, x, an, w, r, bary_x, bary_m);
+    for (int64_t e = 0; e < tot - K + 1; ++e) bary_m[e] *= m0;
+  }
+  if (gap_out) *gap_out = gap;
+  free(fb); free(at); free(an); free(r);
   return t < max_iter ? t + 1 : max_iter;
 }
 

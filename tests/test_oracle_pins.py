@@ -660,3 +660,92 @@ def test_fw_gap_bounds_the_suboptimality():
         h, lam = oracle.h0(a, b, it.f, it.g, rho, rho)
         assert abs(lam) < 1e-12  # the reported pair is already optimally translated
         assert 0.0 <= h_star - h <= gap + 1e-12, (K, h_star - h, gap)
+
+
+# ---------------------------------------------------------------------------------------
+# Unbalanced 1-D barycenters by Frank-Wolfe on the multi-marginal dual (Sec. 5).
+# ---------------------------------------------------------------------------------------
+def test_mot_two_marginals_is_pairwise_ot():
+    # K = 2, w = (1/2, 1/2): min_b (x - b)^2/2 + (y - b)^2/2 = |x/2 - y/2|^2, so the
+    # multi-marginal walk is the pairwise coupling on the halved supports: same cost, same
+    # potentials up to the translation (f_0 + c, f_1 - c).
+    rng = np.random.default_rng(5)
+    n, m = 7, 9
+    x, y = np.sort(rng.uniform(0, 1, n)), np.sort(rng.uniform(0, 1, m))
+    a, b = rng.uniform(0.2, 1, n), rng.uniform(0.2, 1, m)
+    a, b = a / a.sum(), b / b.sum()
+    cost, f, bx, bm = oracle.solve_mot_1d([0, n, n + m], np.concatenate([x, y]),
+                                          np.concatenate([a, b]), [0.5, 0.5])
+    c2, r, s, _, _ = oracle.solve_ot_1d(x / 2, y / 2, a, b, 2.0)
+    assert abs(cost - c2) <= 1e-15
+    assert np.ptp(f[:n] - r) < 1e-14 and np.ptp(f[n:] - s) < 1e-14
+    assert abs((f[:n] - r)[0] + (f[n:] - s)[0]) < 1e-14
+    assert abs(bm.sum() - 1.0) < 1e-14 and np.all(bm >= 0)
+
+
+def test_mot_three_marginals_is_an_optimal_primal_dual_pair():
+    # Against a linear program on the full tensor of tuples (HiGHS): same cost, dual
+    # feasibility on every tuple, strong duality; the barycenter points are the barycentric
+    # maps of the visited tuples.
+    import itertools
+    from scipy.optimize import linprog
+    rng = np.random.default_rng(6)
+    Ns = [3, 4, 3]
+    xs = [np.sort(rng.uniform(0, 1, k)) for k in Ns]
+    ws = [rng.uniform(0.2, 1, k) for k in Ns]
+    ws = [v / v.sum() for v in ws]
+    w = np.array([0.2, 0.5, 0.3])
+    off = np.concatenate([[0], np.cumsum(Ns)])
+    X, A = np.concatenate(xs), np.concatenate(ws)
+    cost, f, bx, bm = oracle.solve_mot_1d(off, X, A, w)
+    tuples = list(itertools.product(*[range(k) for k in Ns]))
+    bar = lambda t: sum(w[k] * xs[k][t[k]] for k in range(3)) / w.sum()
+    Cc = np.array([sum(w[k] * (xs[k][t[k]] - bar(t)) ** 2 for k in range(3)) for t in tuples])
+    Aeq = np.zeros((sum(Ns), len(tuples)))
+    for col, t in enumerate(tuples):
+        for k in range(3):
+            Aeq[off[k] + t[k], col] = 1.0
+    lp = linprog(Cc, A_eq=Aeq, b_eq=A, bounds=(0, None), method="highs")
+    assert abs(cost - lp.fun) <= 1e-12
+    viol = max(sum(f[off[k] + t[k]] for k in range(3)) - Cc[c] for c, t in enumerate(tuples))
+    assert viol <= 1e-14
+    assert abs(f @ A - cost) <= 1e-13
+    assert len(bx) == sum(Ns) - 3 + 1 and abs(bm.sum() - 1.0) < 1e-14
+    assert np.all(np.diff(bx) >= -1e-15)  # the monotone walk visits tuples in order
+
+
+def test_mm_lambda_maximises_the_translated_dual():
+    # lambda* maximises F(fb + lambda) over sum lambda = 0 (Prop. on the multi-marginal
+    # translation); checked by a direct unconstrained maximisation over K - 1 free values.
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(7)
+    Ns = [3, 4, 3]
+    off = np.concatenate([[0], np.cumsum(Ns)])
+    A = rng.uniform(0.2, 1.0, off[-1])
+    fb = rng.uniform(-0.3, 0.3, off[-1])
+    w, rho = np.array([0.2, 0.5, 0.3]), 0.7
+    lam = oracle.mm_lambda(off, A, fb, w, rho)
+
+    def neg(l2):
+        lv = np.array([l2[0], l2[1], -l2[0] - l2[1]])
+        return -oracle.mm_dual(off, A, fb + np.repeat(lv, Ns), w, rho)
+    res = minimize(neg, [0.0, 0.0], method="BFGS", options={"gtol": 1e-12})
+    assert abs(lam.sum()) < 1e-15
+    assert np.max(np.abs(lam[:2] - res.x)) < 1e-7
+
+
+def test_barycenter_fw_two_marginals_is_pairwise_fw():
+    # K = 2, w = (1/2, 1/2), penalty rho: the multi-marginal dual is the pairwise F_0 with
+    # rho1 = rho2 = rho/2 on the halved supports, and lambda* coincides with Prop. 2, so the
+    # reported potentials of both Frank-Wolfe solvers agree iterate by iterate.
+    rng = np.random.default_rng(8)
+    n, m = 7, 9
+    x, y = np.sort(rng.uniform(0, 1, n)), np.sort(rng.uniform(0, 1, m))
+    a, b = rng.uniform(0.2, 1, n) / n, rng.uniform(0.2, 1, m) * 1.4 / m
+    rho = 0.8
+    for iters in (1, 5, 50):
+        fb = oracle.fw_barycenter([0, n, n + m], np.concatenate([x, y]), np.concatenate([a, b]),
+                                  [0.5, 0.5], rho, max_iter=iters)
+        fw = oracle.fw_1d(x / 2, y / 2, a, b, rho / 2, rho / 2, max_iter=iters)
+        assert np.max(np.abs(fb.f[:n] - fw.f)) < 1e-13 and np.max(np.abs(fb.f[n:] - fw.g)) < 1e-13
+        assert abs(fb.gap - fw.gap) < 1e-13
