@@ -56,7 +56,7 @@ def parse():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="cloud3d",
                     choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16", "anderson",
-                             "phi", "fw1d"),
+                             "phi", "fw1d", "bary"),
                     help="cloud3d (default) is the benchmark step above; the others print one "
                          "JSON line of their own measurement (see extra_workload)")
     return ap.parse_args()
@@ -145,7 +145,10 @@ def extra_workload(args, uot, torch, np, workloads):
     fw1d      1-D Frank-Wolfe for unregularised UOT: the sorted 1-D measures N=M=200, rho=1,
               5000 iterations with step 2/(2+t) (microseconds per iteration, FP64 oracle on the
               same iterations); and 4096 problems, N_p, M_p ~ U{64..4096}, line search to gap
-              1e-9 (point-iterations/s = sum_p (N_p + M_p) iters_p / wall)."""
+              1e-9 (point-iterations/s = sum_p (N_p + M_p) iters_p / wall).
+    bary      unbalanced 1-D barycenter of K = 8 random mixtures of 2000 points (rho = 0.1),
+              1000 Frank-Wolfe iterations (microseconds per iteration, FP64 oracle on 50 of
+              them); and 512 such problems with 64..512 points per measure, 500 iterations."""
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
@@ -316,6 +319,35 @@ def extra_workload(args, uot, torch, np, workloads):
                     "roofline": None,
                     "cpu_baseline": {"value": cpu, "unit": "us/iteration", "kind": "oracle", "cores": 1,
                                      "sample": "FP64 C oracle, the same 5000 iterations"}})
+    elif args.workload == "bary":
+        import oracle
+        off, x, a, w, rho = workloads.bary_mixtures()
+        K = 8
+        xd, ad, wd, rd = t(x), t(a), torch.from_numpy(w).to(dev), torch.from_numpy(rho).to(dev)
+        uot.fw1d_barycenter(off, K, xd, ad, wd, rd, max_iter=5)  # warm
+        (f, bx, bw, it, gap, st), dt = _timed(torch, lambda: uot.fw1d_barycenter(
+            off, K, xd, ad, wd, rd, max_iter=1000))
+        t0 = time.perf_counter()
+        oracle.fw_barycenter(off, x.astype(np.float64), a.astype(np.float64), w, float(rho[0]),
+                             max_iter=50)
+        cpu = (time.perf_counter() - t0) / 50 * 1e6
+        offb, xb, ab, wb, rb = workloads.bary_mixtures(B=512, nmin=64, nmax=512, seed=8)
+        argsb = (offb, K, t(xb), t(ab), torch.from_numpy(wb).to(dev), torch.from_numpy(rb).to(dev))
+        uot.fw1d_barycenter(*argsb, max_iter=2)
+        (_, _, _, itb, gapb, stb), dtb = _timed(torch, lambda: uot.fw1d_barycenter(*argsb, max_iter=500))
+        out["dtype"] = "f64"
+        out.update({"metric": "microseconds per Frank-Wolfe barycenter iteration, K=8 x 2000 points",
+                    "value": dt / 1000 * 1e6, "unit": "us/iteration", "higher_is_better": False,
+                    "config": {"workload": "unbalanced 1-D barycenter of 8 random mixtures x 2000 "
+                                           "points, rho=0.1, 1000 iterations; and 512 problems of "
+                                           "8 measures x 64..512 points, 500 iterations"},
+                    "gap_after_1000": float(gap[0].item()), "status": int(st[0].item()),
+                    "batched": {"seconds": dtb, "point_iterations_per_s":
+                                float(int(offb[-1]) * 500) / dtb,
+                                "gap_median": float(gapb.median().item())},
+                    "roofline": None,
+                    "cpu_baseline": {"value": cpu, "unit": "us/iteration", "kind": "oracle", "cores": 1,
+                                     "sample": "FP64 C oracle, 50 iterations of the same problem"}})
     else:  # highdim16
         pr = workloads.highdim16()
         a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)

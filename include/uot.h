@@ -326,6 +326,37 @@ uot_status uot_fw1d_batched(int32_t B, const int64_t *offN, const int64_t *offM,
 /* Workspace bytes of uot_fw1d_batched (offN, offM on the host); 0 on invalid input. */
 size_t uot_fw1d_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM);
 
+/*
+ * Unregularised 1-D unbalanced barycenters (Sec. 5) of K measures, for B independent problems:
+ * Frank-Wolfe on the translation-invariant multi-marginal dual
+ *   H(fb) = sup_{sum_k lambda_k = 0} sum_k <alpha_k, w_k rho (1 - e^{-(fb_k + lambda_k)/(w_k rho)})>
+ * over fb_0 (+) ... (+) fb_{K-1} <= C, C(z) = min_b sum_k w_k (z_k - b)^2 (squared distance;
+ * b = sum w_k z_k / sum w_k, the barycentric map), with the closed-form lambda* of the KL
+ * setting (q_k = log <alpha_k, e^{-fb_k/(w_k rho)}>, lambda_k = w_k rho q_k - w_k/sum_j w_j *
+ * sum_j w_j rho q_j), from fb = 0 with step 2/(2 + t). The linear oracle is the balanced
+ * multi-marginal walk between the tilted histograms (the measure with the least remaining
+ * mass advances; the first on ties), whose visited tuples are tight.
+ *  B >= 1, 2 <= K <= 16; off (host) [B*K + 1]: measure k of problem b is the point range
+ *  [off[b*K + k], off[b*K + k + 1]) (at least one point), supports sorted ascending.
+ *  x, alpha [off[B*K]] (device, float32); w [B*K] (device, double, > 0); rho [B] (device,
+ *  double, > 0).
+ *  f [off[B*K]] (device, out): the reported potentials fb_k + lambda_k.
+ *  bary_x, bary_w (device, out): problem b's barycenter, the barycentric points and masses of
+ *  the tuples of the balanced plan between its final tilted marginals (those marginals are
+ *  the plan's marginals at the optimum), off[(b+1)K] - off[bK] - K + 1 entries starting at
+ *  off[bK] - bK + b.
+ *  iters, gap, status (device, [B], out): as in uot_fw1d_batched.
+ * Double precision; one workgroup per problem, all iterations in one launch.
+ */
+uot_status uot_fw1d_barycenter(int32_t B, int32_t K, const int64_t *off, const float *x,
+                               const float *alpha, const double *w, const double *rho,
+                               int32_t max_iter, double tol, float *f, float *bary_x,
+                               float *bary_w, int32_t *iters, double *gap, int32_t *status,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes of uot_fw1d_barycenter (off on the host); 0 on invalid input. */
+size_t uot_fw1d_barycenter_workspace_bytes(int32_t B, int32_t K, const int64_t *off);
+
 /* Workspace bytes of uot_ti_sinkhorn_batched (offN, offM on the host); 0 on invalid input. */
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d);
 

@@ -23,7 +23,7 @@ __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_ap
            "backward", "workspace_bytes", "UOTLoss", "uot_loss", "library_path", "load_library",
            "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
            "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
-           "fw1d_batched", "fw1d"]
+           "fw1d_batched", "fw1d", "fw1d_barycenter"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -125,6 +125,10 @@ def load_library():
     lib.uot_fw1d_batched.argtypes = [I32, P, P, P, P, P, P, P, P, D, I32, I32, D, P, P, P, P, P,
                                      P, S, P]
     lib.uot_fw1d_batched.restype = ctypes.c_int
+    lib.uot_fw1d_barycenter.argtypes = [I32, I32, P, P, P, P, P, I32, D, P, P, P, P, P, P, P, S, P]
+    lib.uot_fw1d_barycenter.restype = ctypes.c_int
+    lib.uot_fw1d_barycenter_workspace_bytes.argtypes = [I32, I32, P]
+    lib.uot_fw1d_barycenter_workspace_bytes.restype = S
     lib.uot_fw1d_workspace_bytes.argtypes = [I32, P, P]
     lib.uot_fw1d_workspace_bytes.restype = S
     lib.uot_batched_workspace_bytes.argtypes = [I32, P, P, I32]
@@ -478,6 +482,38 @@ def fw1d_batched(offN, offM, x, y, alpha, beta, rho1, rho2=None, *, p: float = 2
                               _ptr(status), _ptr(ws), ws.numel(), _stream())
     _check(st)
     return f, g, iters, gap, status
+
+
+def fw1d_barycenter(off, K: int, x, alpha, w, rho, *, max_iter: int = 1000, tol: float = 0.0):
+    """Unregularised 1-D unbalanced barycenters (Sec. 5) of K measures for B problems (see
+    uot_fw1d_barycenter). off: host int64 [B*K+1]; x, alpha: float32 device; w: float64
+    device [B*K]; rho: float64 device [B] (or a scalar). Returns (f, bary_x, bary_w, iters,
+    gap, status); problem b's barycenter starts at off[b*K] - b*K + b."""
+    _require_gpu()
+    lib = load_library()
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    B = (len(off) - 1) // K
+    x, alpha = _f32(x, "x").reshape(-1), _f32(alpha, "alpha")
+    dev = alpha.device
+    w = w.to(device=dev, dtype=torch.float64).contiguous().reshape(-1)
+    rho = (rho.to(device=dev, dtype=torch.float64).contiguous().reshape(-1)
+           if isinstance(rho, torch.Tensor) else torch.full((B,), float(rho), dtype=torch.float64, device=dev))
+    tot = int(off[-1])
+    f = torch.empty(tot, dtype=torch.float32, device=dev)
+    bx = torch.empty(tot - B * K + B, dtype=torch.float32, device=dev)
+    bw = torch.empty(tot - B * K + B, dtype=torch.float32, device=dev)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    gap = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    nb = int(lib.uot_fw1d_barycenter_workspace_bytes(B, K, off.ctypes.data))
+    if nb == 0:
+        _check(UOT_ERR_INVALID)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    st = lib.uot_fw1d_barycenter(B, K, off.ctypes.data, _ptr(x), _ptr(alpha), _ptr(w), _ptr(rho),
+                                 int(max_iter), float(tol), _ptr(f), _ptr(bx), _ptr(bw), _ptr(iters),
+                                 _ptr(gap), _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _check(st)
+    return f, bx, bw, iters, gap, status
 
 
 def fw1d(x, y, alpha, beta, rho1: float, rho2: float | None = None, **kw):

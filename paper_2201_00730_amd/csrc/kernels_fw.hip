@@ -360,7 +360,284 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Unbalanced 1-D barycenters (Sec. 5): Frank-Wolfe on the translation-invariant
+// multi-marginal dual, squared distance ground cost, one workgroup per problem of K measures.
+// The linear oracle is the balanced multi-marginal walk: at each step the measure with the
+// least remaining mass (the first on ties) advances, i.e. measure k leaves its point i at
+// the level Ac_k[i] of its normalised CDF, and the events happen in the order of these levels
+// (ties: smaller k first). At the event (k, i) the other measures stand at their co-ranks:
+// #{i' : Ac_j[i'] <= level} for j < k and #{i' : Ac_j[i'] < level} for j > k. Every visited
+// tuple is tight, so f_{k,i+1} - f_{k,i} = C(tuple after) - C(tuple before): prefix sums per
+// measure from f_{0,0} = C(first tuple), f_{k,0} = 0.
+// ---------------------------------------------------------------------------------------
+constexpr int kBaryMaxK = kBaryMaxMeasures;
+
+struct BaryArgs {
+  int B, K;
+  const int64_t *off;   // device [B*K + 1]: measure m = b*K + k owns [off[m], off[m+1])
+  const float *x, *alpha;
+  const double *w;      // [B*K]
+  const double *rho;    // [B]
+  int max_iter;
+  double tol;
+  double *fb, *Ac, *r;  // per point
+  float *f;             // per point (out)
+  float *bx, *bw;       // per problem [off[(b+1)K] - off[bK] - K + 1] at offset off[bK] - bK + b
+  int32_t *iters;
+  double *gap;
+  int32_t *status;
+};
+
+// Number of entries of the sorted a[0..n) that are < v (strict) or <= v.
+__device__ __forceinline__ int count_below(const double *a, int n, double v, bool inclusive) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (inclusive ? a[mid] <= v : a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+struct BaryTuple {
+  int K;
+  const double *w;
+  double sw;
+  __device__ double cost(const double *z, double *bary) const {
+    double sz = 0.0;
+    for (int k = 0; k < K; ++k) sz += w[k] * z[k];
+    const double b = sz / sw;
+    double c = 0.0;
+    for (int k = 0; k < K; ++k) c += w[k] * (z[k] - b) * (z[k] - b);
+    if (bary) *bary = b;
+    return c;
+  }
+};
+
+__global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
+  __shared__ double q[kBaryMaxK], lam[kBaryMaxK], wsh[kBaryMaxK];
+  __shared__ int64_t o[kBaryMaxK + 1];
+  const int K = a.K;
+  for (int prob = blockIdx.x; prob < a.B; prob += gridDim.x) {
+    const int m0 = prob * K;
+    if (threadIdx.x <= K) o[threadIdx.x] = a.off[m0 + threadIdx.x];
+    if (threadIdx.x < K) wsh[threadIdx.x] = a.w[m0 + threadIdx.x];
+    __syncthreads();
+    const double rho = a.rho[prob];
+    double sw = 0.0;
+    for (int k = 0; k < K; ++k) sw += wsh[k];
+    const BaryTuple tup{K, wsh, sw};
+    const int64_t base = o[0];
+    const int64_t tot = o[K] - base;
+    float *bx = a.bx + (base - m0 + prob), *bw = a.bw + (base - m0 + prob);
+    const int T = (int)(tot - K);  // events; T + 1 visited tuples
+    // validation: sorted supports, finite nonnegative weights, positive masses and penalties
+    int bad = !(rho > 0.0) || !isfinite(rho);
+    for (int k = 0; k < K; ++k) bad |= !(wsh[k] > 0.0) || !isfinite(wsh[k]);
+    for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) {
+      const int64_t g = base + e;
+      const float v = a.alpha[g];
+      if (!(v >= 0.0f) || !isfinite(v)) bad = 1;
+      int k = 0;
+      while (g >= o[k + 1]) ++k;
+      if (g + 1 < o[k + 1] && !(a.x[g] <= a.x[g + 1])) bad = 1;
+    }
+    for (int k = 0; k < K; ++k) {
+      double mk = 0.0;
+      for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += kFwThreads) mk += a.alpha[g];
+      mk = fw_sum(mk);
+      bad |= !(mk > 0.0);
+    }
+    bad = -fw_min_int(-bad);
+    if (bad) {
+      for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) a.f[base + e] = NAN;
+      if (threadIdx.x == 0) { a.status[prob] = kBatchInvalid; a.iters[prob] = 0; a.gap[prob] = NAN; }
+      __syncthreads();
+      continue;
+    }
+    double *fb = a.fb + base, *Ac = a.Ac + base, *r = a.r + base;
+    for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) fb[e] = 0.0;
+    __syncthreads();
+
+    // q_k = log <alpha_k, e^{-fb_k/(w_k rho)}> and lambda* (closed form); then Ac = the
+    // normalised tilted CDFs. Returns log of the common tilted mass.
+    auto tilt = [&]() -> double {
+      for (int k = 0; k < K; ++k) {
+        Lse3 l;
+        const double sc = 1.0 / (wsh[k] * rho);
+        for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += kFwThreads) {
+          const double v = a.alpha[g];
+          l.add(v > 0.0 ? log(v) - fb[g - base] * sc : -INFINITY, 0.0);
+        }
+        double lq, u1, u2;
+        l.reduce(lq, u1, u2);
+        if (threadIdx.x == 0) q[k] = lq;
+      }
+      __syncthreads();
+      double sq = 0.0;
+      for (int k = 0; k < K; ++k) sq += wsh[k] * rho * q[k];
+      if (threadIdx.x < K) lam[threadIdx.x] = wsh[threadIdx.x] * rho * q[threadIdx.x] - wsh[threadIdx.x] / sw * sq;
+      for (int k = 0; k < K; ++k) {
+        const double sc = 1.0 / (wsh[k] * rho);
+        for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += kFwThreads) {
+          const double v = a.alpha[g];
+          Ac[g - base] = v > 0.0 ? exp(log(v) - fb[g - base] * sc - q[k]) : 0.0;
+        }
+      }
+      __syncthreads();
+      for (int k = 0; k < K; ++k) fw_scan(Ac + (o[k] - base), (int)(o[k + 1] - o[k]));
+      return q[0] - lam[0] / (wsh[0] * rho);
+    };
+
+    // the walk: potentials into r (oracle mode) or the barycenter (plan mode). Each thread
+    // takes a contiguous run of points; along a run within one measure the levels do not
+    // decrease, so the co-ranks in the other measures are found by one binary search at the
+    // run's first event and then by forward steps.
+    auto walk = [&](bool plan) {
+      const int64_t chunk = (tot + kFwThreads - 1) / kFwThreads;
+      const int64_t e0 = min(tot, (int64_t)threadIdx.x * chunk), e1 = min(tot, e0 + chunk);
+      int cur[kBaryMaxK];
+      int curk = -1, k = 0;
+      for (int64_t e = e0; e < e1; ++e) {
+        const int64_t g = base + e;
+        while (g >= o[k + 1]) ++k;
+        const int i = (int)(g - o[k]);
+        const int nk = (int)(o[k + 1] - o[k]);
+        if (i == 0 && !plan) {
+          if (k == 0) {
+            double z[kBaryMaxK];
+            for (int jj = 0; jj < K; ++jj) z[jj] = a.x[o[jj]];
+            r[e] = tup.cost(z, nullptr);
+          } else {
+            r[e] = 0.0;
+          }
+        }
+        if (i + 1 >= nk) continue;  // the last point never leaves
+        const double lev = Ac[e];
+        double z[kBaryMaxK];
+        int pos = i;
+#pragma unroll
+        for (int jj = 0; jj < kBaryMaxK; ++jj) {
+          if (jj >= K) break;
+          if (jj == k) { z[jj] = a.x[g]; continue; }
+          const int nj = (int)(o[jj + 1] - o[jj]);
+          const double *aj = Ac + (o[jj] - base);
+          int c;
+          if (k != curk) {
+            c = count_below(aj, nj, lev, jj < k);
+          } else {
+            c = cur[jj];
+            if (jj < k) { while (c < nj && aj[c] <= lev) ++c; }
+            else { while (c < nj && aj[c] < lev) ++c; }
+          }
+          cur[jj] = c;
+          // clamped: a level at or past a measure's total (rounding, trailing zero weights)
+          // leaves it at its last point, and keeps pos inside [0, T)
+          const int cc = min(c, nj - 1);
+          pos += cc;
+          z[jj] = a.x[o[jj] + cc];
+        }
+        curk = k;
+        if (!plan) {
+          const double before = tup.cost(z, nullptr);
+          z[k] = a.x[g + 1];
+          r[e + 1] = tup.cost(z, nullptr) - before;
+        } else {
+          z[k] = a.x[g + 1];
+          double b;
+          tup.cost(z, &b);
+          bx[pos + 1] = (float)b;  // the tuple after the event at merged position pos
+          r[pos] = lev;            // the event's level (r is free in plan mode)
+        }
+      }
+      __syncthreads();
+    };
+
+    double gap = INFINITY;
+    int t = 0;
+    for (; t < a.max_iter; ++t) {
+      const double logmt = tilt();
+      walk(false);
+      for (int k = 0; k < K; ++k) fw_scan(r + (o[k] - base), (int)(o[k + 1] - o[k]));
+      double gp = 0.0;
+      for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) {
+        const int64_t g = base + e;
+        int k = 0;
+        while (g >= o[k + 1]) ++k;
+        const double an = Ac[e] - (g > o[k] ? Ac[e - 1] : 0.0);
+        gp += an * (r[e] - fb[e]);
+      }
+      gap = exp(logmt) * fw_sum(gp);
+      if (a.tol > 0.0 && gap <= a.tol) break;
+      const double gamma = 2.0 / (2.0 + t);
+      for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) fb[e] = (1.0 - gamma) * fb[e] + gamma * r[e];
+      __syncthreads();
+    }
+    const int run = t < a.max_iter ? t + 1 : a.max_iter;
+    // reported potentials and the barycenter of the final tilted marginals
+    const double logmt = tilt();
+    const double mt = exp(logmt);
+    bool finite = true;
+    for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) {
+      const int64_t g = base + e;
+      int k = 0;
+      while (g >= o[k + 1]) ++k;
+      const double v = fb[e] + lam[k];
+      finite = finite && isfinite(v);
+      a.f[g] = (float)v;
+    }
+    if (threadIdx.x == 0) {
+      double z[kBaryMaxK], b;
+      for (int j = 0; j < K; ++j) z[j] = a.x[o[j]];
+      tup.cost(z, &b);
+      bx[0] = (float)b;
+    }
+    walk(true);
+    // masses: tuple tt lies between the events tt - 1 and tt (levels 0 and 1 at the ends)
+    for (int tt = threadIdx.x; tt <= T; tt += kFwThreads) {
+      const double hi = tt < T ? fmin(r[tt], 1.0) : 1.0;
+      const double lo = tt > 0 ? fmin(r[tt - 1], 1.0) : 0.0;
+      bw[tt] = (float)(fmax(hi - lo, 0.0) * mt);
+    }
+    __syncthreads();
+    const int allfinite = fw_min_int(finite ? 1 : 0);
+    if (threadIdx.x == 0) {
+      a.iters[prob] = run;
+      a.gap[prob] = gap;
+      a.status[prob] = !allfinite ? kBatchNumeric
+                       : (a.tol > 0.0 && gap <= a.tol) ? kBatchConverged : kBatchMaxIter;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fw_bary(const BaryLaunch &l, hipStream_t s) {
+  if (l.K < 2 || l.K > kBaryMaxK) return hipErrorInvalidValue;
+  BaryArgs a;
+  a.B = l.B;
+  a.K = l.K;
+  a.off = l.off;
+  a.x = l.x;
+  a.alpha = l.alpha;
+  a.w = l.w;
+  a.rho = l.rho;
+  a.max_iter = l.max_iter;
+  a.tol = l.tol;
+  a.fb = l.fb;
+  a.Ac = l.Ac;
+  a.r = l.r;
+  a.f = l.f;
+  a.bx = l.bx;
+  a.bw = l.bw;
+  a.iters = l.iters;
+  a.gap = l.gap;
+  a.status = l.status;
+  const int grid = l.B < l.max_blocks ? l.B : l.max_blocks;
+  hipLaunchKernelGGL(k_fw_bary, dim3(grid > 0 ? grid : 1), dim3(kFwThreads), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_fw1d(const FwLaunch &l, hipStream_t s) {
   FwArgs a;

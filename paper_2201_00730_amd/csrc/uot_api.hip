@@ -1060,6 +1060,88 @@ uot_status fw1d(int32_t B, const int64_t *offN, const int64_t *offM, const float
   return UOT_OK;
 }
 
+// Workspace of uot_fw1d_barycenter: device offsets and per-point scratch.
+struct BaryLayout {
+  size_t off = 0, fb = 0, Ac = 0, r = 0, total = 0;
+  int64_t tot = 0;
+};
+
+uot_status bary_layout(int32_t B, int32_t K, const int64_t *off, BaryLayout &L) {
+  if (B < 1) return fail(UOT_ERR_INVALID, "B=%d must be >= 1", B);
+  if (K < 2 || K > kBaryMaxMeasures) return fail(UOT_ERR_INVALID, "K=%d not in [2, %d]", K, kBaryMaxMeasures);
+  if (off == nullptr) return fail(UOT_ERR_INVALID, "off is NULL");
+  if (off[0] != 0) return fail(UOT_ERR_INVALID, "off[0] must be 0");
+  for (int64_t m = 0; m < (int64_t)B * K; ++m) {
+    const int64_t n = off[m + 1] - off[m];
+    if (n < 1) return fail(UOT_ERR_INVALID, "measure %lld has %lld points (must be >= 1)", (long long)m, (long long)n);
+    if (n > (1 << 30)) return fail(UOT_ERR_INVALID, "measure %lld is too large", (long long)m);
+  }
+  L.tot = off[(int64_t)B * K];
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  L.off = take(((size_t)B * K + 1) * sizeof(int64_t));
+  L.fb = take((size_t)L.tot * sizeof(double));
+  L.Ac = take((size_t)L.tot * sizeof(double));
+  L.r = take((size_t)L.tot * sizeof(double));
+  L.total = o;
+  return UOT_OK;
+}
+
+uot_status fw_barycenter(int32_t B, int32_t K, const int64_t *off, const float *x,
+                         const float *alpha, const double *w, const double *rho, int32_t max_iter,
+                         double tol, float *f, float *bary_x, float *bary_w, int32_t *iters,
+                         double *gap, int32_t *status, void *workspace, size_t workspace_bytes,
+                         void *stream) {
+  BaryLayout L;
+  UOT_TRY(bary_layout(B, K, off, L));
+  if (max_iter < 1) return fail(UOT_ERR_INVALID, "max_iter=%d must be >= 1", max_iter);
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(UOT_ERR_INVALID, "tol=%g must be finite and >= 0", tol);
+  UOT_TRY(check_device_ptr(x, "x"));
+  UOT_TRY(check_device_ptr(alpha, "alpha"));
+  UOT_TRY(check_device_ptr(w, "w"));
+  UOT_TRY(check_device_ptr(rho, "rho"));
+  UOT_TRY(check_device_ptr(f, "f"));
+  UOT_TRY(check_device_ptr(bary_x, "bary_x"));
+  UOT_TRY(check_device_ptr(bary_w, "bary_w"));
+  UOT_TRY(check_device_ptr(iters, "iters"));
+  UOT_TRY(check_device_ptr(gap, "gap"));
+  UOT_TRY(check_device_ptr(status, "status"));
+  Workspace ws;
+  UOT_TRY(acquire(ws, workspace, workspace_bytes, L.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  UOT_HIP(hipMemcpyAsync(at<int64_t>(ws.ptr, L.off), off, ((size_t)B * K + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  UOT_HIP(hipStreamSynchronize(s));  // the host table must outlive the copy
+  BaryLaunch l;
+  l.B = B;
+  l.K = K;
+  l.off = at<int64_t>(ws.ptr, L.off);
+  l.x = x;
+  l.alpha = alpha;
+  l.w = w;
+  l.rho = rho;
+  l.max_iter = max_iter;
+  l.tol = tol;
+  l.fb = at<double>(ws.ptr, L.fb);
+  l.Ac = at<double>(ws.ptr, L.Ac);
+  l.r = at<double>(ws.ptr, L.r);
+  l.f = f;
+  l.bx = bary_x;
+  l.bw = bary_w;
+  l.iters = iters;
+  l.gap = gap;
+  l.status = status;
+  const int cus = device_cus();
+  l.max_blocks = cus > 0 ? 2 * cus : 512;
+  UOT_HIP(launch_fw_bary(l, s));
+  if (ws.owned) UOT_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
+  return UOT_OK;
+}
+
 uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
                           BatchLayout &L) {
   if (B < 1) return fail(UOT_ERR_INVALID, "B=%d must be >= 1", B);
@@ -1378,6 +1460,22 @@ int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries) 
   if (total_ms) *total_ms = uot::g_prof[kind].ms;
   if (total_entries) *total_entries = uot::g_prof[kind].entries;
   return uot::g_prof[kind].launches;
+}
+
+size_t uot_fw1d_barycenter_workspace_bytes(int32_t B, int32_t K, const int64_t *off) {
+  uot::BaryLayout L;
+  if (uot::bary_layout(B, K, off, L) != UOT_OK) return 0;
+  return L.total;
+}
+
+uot_status uot_fw1d_barycenter(int32_t B, int32_t K, const int64_t *off, const float *x,
+                               const float *alpha, const double *w, const double *rho,
+                               int32_t max_iter, double tol, float *f, float *bary_x,
+                               float *bary_w, int32_t *iters, double *gap, int32_t *status,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+  uot::g_last_error.clear();
+  return uot::fw_barycenter(B, K, off, x, alpha, w, rho, max_iter, tol, f, bary_x, bary_w, iters,
+                            gap, status, workspace, workspace_bytes, stream);
 }
 
 size_t uot_fw1d_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM) {

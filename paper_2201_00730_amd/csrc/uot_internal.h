@@ -375,4 +375,24 @@ struct FwLaunch {
 };
 hipError_t launch_fw1d(const FwLaunch &l, hipStream_t s);
 
+// 1-D barycenters (kernels_fw.hip): problem b has K measures m = b*K + k on
+// [off[m], off[m+1]); per-point double scratch fb, Ac, r; barycenter outputs at offset
+// off[b*K] - b*K + b, off[(b+1)K] - off[bK] - K + 1 entries.
+constexpr int kBaryMaxMeasures = 16;
+struct BaryLaunch {
+  int B, K;
+  const int64_t *off;
+  const float *x, *alpha;
+  const double *w, *rho;
+  int max_iter;
+  double tol;
+  double *fb, *Ac, *r;
+  float *f, *bx, *bw;
+  int32_t *iters;
+  double *gap;
+  int32_t *status;
+  int max_blocks;
+};
+hipError_t launch_fw_bary(const BaryLaunch &l, hipStream_t s);
+
 }  // namespace uot

@@ -178,3 +178,17 @@ def test_fw1d_rejects_bad_arguments_before_any_launch(lib):
                                   0, None)
         assert st == uot.UOT_ERR_INVALID
         assert lib.uot_last_error()
+
+
+def test_barycenter_rejects_bad_arguments_before_any_launch(lib):
+    off = np.array([0, 3, 5, 9], dtype=np.int64)
+    assert lib.uot_fw1d_barycenter_workspace_bytes(1, 3, off.ctypes.data) > 0
+    assert lib.uot_fw1d_barycenter_workspace_bytes(1, 1, off.ctypes.data) == 0     # K < 2
+    assert lib.uot_fw1d_barycenter_workspace_bytes(1, 17, off.ctypes.data) == 0    # K > 16
+    bad = np.array([0, 3, 3, 9], dtype=np.int64)  # an empty measure
+    assert lib.uot_fw1d_barycenter_workspace_bytes(1, 3, bad.ctypes.data) == 0
+    for it, tol in ((0, 0.0), (10, -1.0), (10, float("inf"))):
+        st = lib.uot_fw1d_barycenter(1, 3, off.ctypes.data, None, None, None, None, it, tol, None,
+                                     None, None, None, None, None, None, 0, None)
+        assert st == uot.UOT_ERR_INVALID
+        assert lib.uot_last_error()

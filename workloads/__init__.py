@@ -195,6 +195,27 @@ def fw1d_batch(B: int = 4096, nmin: int = 64, nmax: int = 4096, seed: int = 6,
                  eps=np.zeros(B), rho1=rho.astype(np.float64), rho2=rho.astype(np.float64))
 
 
+def bary_mixtures(B: int = 1, K: int = 8, nmin: int = 2000, nmax: int = 2000, seed: int = 7,
+                  rho: float = 0.1):
+    """Barycenter inputs: B problems of K random mixtures on [0, 1] (two Gaussian components
+    with centres ~ U[0.2, 0.8] and std 0.06, clipped), sizes integer-uniform in [nmin, nmax],
+    sorted supports, positive random weights with masses ~ U[0.7, 1.4]; uniform barycenter
+    weights 1/K; KL penalty rho. Returns (off [B*K+1], x, alpha, w [B*K], rho [B])."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, size=B * K)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.empty(int(off[-1]))
+    a = np.empty(int(off[-1]))
+    for m in range(B * K):
+        n = int(sizes[m])
+        c = rng.uniform(0.2, 0.8, 2)
+        comp = rng.integers(0, 2, n)
+        x[off[m]:off[m + 1]] = np.sort(np.clip(rng.normal(c[comp], 0.06), 0.0, 1.0))
+        wv = rng.uniform(0.2, 1.0, n)
+        a[off[m]:off[m + 1]] = wv * rng.uniform(0.7, 1.4) / wv.sum()
+    return off, _f32(x), _f32(a), np.full(B * K, 1.0 / K), np.full(B, float(rho))
+
+
 def random_small(n: int, m: int, d: int = 2, seed: int = 0, eps: float = 0.1, rho1: float = 1.0,
                  rho2: float = 1.0, mass_a: float = 1.0, mass_b: float = 1.5, dense: bool = False,
                  p: float = 2.0, weight_jitter: bool = True) -> Problem:
