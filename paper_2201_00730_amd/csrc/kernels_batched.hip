@@ -3,10 +3,10 @@
 //
 // Problems are packed back to back (CSR offsets offN/offM). One half-step of every active
 // problem is one launch of k_batched_half: each wave repeatedly takes a work item (problem
-// p, a chunk of <= 64 targets of p) from a dynamic counter over the compacted list of active
-// items, computes the softmin of its targets over all sources of p (one target per lane;
-// sources uniform across the wave, read with scalar loads, 8 at a time with one exp2 per
-// entry), applies the KL prox and TI translation of App. B, writes the new potentials and
+// p, a chunk of <= 256 targets of p) from a dynamic counter over the compacted list of active
+// items, computes the softmin of its targets over all sources of p (one target per lane for
+// items of <= 64 targets, four per lane above; sources uniform across the wave, read with
+// scalar loads, 8 at a time with one exp2 per entry), applies the KL prox and TI translation of App. B, writes the new potentials and
 // source records, and leaves its item partials (tilted mass log-sum-exp, potential-change
 // range). The last wave to finish an item of p (an atomic ticket, no waiting) reduces p's
 // partials into p's scalars: the translation tau, Smin of the new side, and after an f-step
@@ -80,8 +80,10 @@ __device__ __forceinline__ void write_rec(float *rp, const float *yc, double yn2
   for (int k = D + 1; k < batched_rec_stride(D); ++k) rp[k] = 0.0f;
 }
 
-// Reduces problem p's item partials of the half-step just finished (one wave).
-__device__ void reduce_problem(const BatchedArgs &a, int p, bool g_step) {
+// Reduces problem p's item partials of the half-step just finished (one wave). Not inlined:
+// it runs once per problem and half-step, and inlined it would raise the register count of
+// the whole softmin kernel.
+__device__ __noinline__ void reduce_problem(const BatchedArgs &a, int p, bool g_step) {
   BatchState &st = a.state[p];
   const int i0 = g_step ? a.pitem_g[p] : a.pitem_f[p];
   const int i1 = g_step ? a.pitem_g[p + 1] : a.pitem_f[p + 1];
@@ -143,16 +145,13 @@ __device__ void reduce_problem(const BatchedArgs &a, int p, bool g_step) {
   }
 }
 
-// One half-step for every active problem. g_step: targets y (beta, rho2), sources x.
-template <int D, int MODE>
-__global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step) {
+// One work item of a half-step: targets it.y .. it.y + it.z - 1 of problem p, lane l taking
+// targets it.y + l + 64 r for r < R (R = 1 for items of at most 64 targets, 4 above), so that
+// each source record read feeds R targets per lane. Softmin over all sources of p, epilogue,
+// item partials, and the problem's reduction by the last wave to finish one of its items.
+template <int D, int MODE, int R>
+__device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, const int4 it) {
   const int lane = threadIdx.x & 63;
-  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const int nact = g_step ? *a.nact_g : *a.nact_f;
-  const int *act = g_step ? a.act_g : a.act_f;
-  const int4 *items = g_step ? a.items_g : a.items_f;
-  int *ctr = g_step ? a.ctr_g : a.ctr_f;
   const int64_t *off_t = g_step ? a.offM : a.offN;
   const int64_t *off_s = g_step ? a.offN : a.offM;
   const float *tpts = g_step ? a.y : a.x;
@@ -164,8 +163,149 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
   int *ticket = g_step ? a.ticket_g : a.ticket_f;
   const int *pitem = g_step ? a.pitem_g : a.pitem_f;
   constexpr int SD = batched_rec_stride(D);
-  (void)wid;
-  (void)nwaves;
+  const int p = it.x;
+  BatchState &st = a.state[p];
+  const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
+  const double scd = 1.4426950408889634074 / eps;
+  const float sc = (float)scd;
+  const HalfCoef cf = g_step ? half_coef(eps, r2, r1) : half_coef(eps, r1, r2);
+  const double tau_src = g_step ? st.tau_f : st.tau_g;
+  const double s_src = g_step ? st.sA : st.sB;
+  const double rho_t = g_step ? r2 : r1;
+  const int64_t tb = off_t[p];
+  const double *mu = a.mu + (size_t)p * kBatchMaxDim;
+  float yc[R][D];
+  double yn2[R];
+  bool valid[R];
+  int64_t tg[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    valid[r] = lane + 64 * r < it.z;
+    tg[r] = tb + it.y + (valid[r] ? lane + 64 * r : 0);
+    yn2[r] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      yc[r][k] = k < a.d ? tpts[tg[r] * a.d + k] - (float)mu[k] : 0.0f;
+      yn2[r] += (double)yc[r][k] * (double)yc[r][k];
+    }
+  }
+  // softmin over all sources of p
+  const int64_t s0 = off_s[p], s1 = off_s[p + 1];
+  float m[R], l[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    m[r] = -FLT_MAX;
+    l[r] = 0.0f;
+  }
+  auto expo = [&](const float *rp, int r) -> float {
+    if constexpr (MODE == kSqEuc) {
+      float acc = rp[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc = fmaf(rp[k], yc[r][k], acc);
+      return acc;
+    } else {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const float u = rp[k] - yc[r][k];
+        d2 = fmaf(u, u, d2);
+      }
+      const float c = (a.half_p == 0.5f) ? __builtin_sqrtf(d2) : fast_exp2(a.half_p * fast_log2(d2));
+      return fmaf(-sc, c, rp[D]);
+    }
+  };
+  int64_t s = s0;
+  for (; s + kTile <= s1; s += kTile) {
+    float v[kTile][R];
+#pragma unroll
+    for (int k = 0; k < kTile; ++k) {
+      const float *rp = srec + (size_t)(s + k) * SD;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = expo(rp, r);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float mt = v[0][r];
+#pragma unroll
+      for (int k = 1; k < kTile; ++k) mt = fmaxf(mt, v[k][r]);
+      const float mn = fmaxf(m[r], mt);
+      float acc = l[r] * fast_exp2(m[r] - mn);
+#pragma unroll
+      for (int k = 0; k < kTile; ++k) acc += fast_exp2(v[k][r] - mn);
+      l[r] = acc;
+      m[r] = mn;
+    }
+  }
+  for (; s < s1; ++s) {
+    const float *rp = srec + (size_t)s * SD;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float v = expo(rp, r);
+      const float mn = fmaxf(m[r], v);
+      l[r] = l[r] * fast_exp2(m[r] - mn) + fast_exp2(v - mn);
+      m[r] = mn;
+    }
+  }
+  // epilogue: KL prox and TI translation (App. B), records of the new potential
+  double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!valid[r]) continue;
+    double lse2 = (double)m[r] + log2((double)l[r]);
+    if constexpr (MODE == kSqEuc) lse2 -= scd * yn2[r];
+    const double S = -lse2 / scd;
+    const double hnew = cf.k_t * (S - tau_src) - cf.c_t * s_src;
+    const float hf = (float)hnew;
+    const float old = tpot[tg[r]];
+    tpot[tg[r]] = hf;
+    const double dh = (double)hf - (double)old;
+    dmx = fmax(dmx, dh);
+    dmn = fmin(dmn, dh);
+    const float w = tw[tg[r]];
+    // the record's coordinates never change (written by k_batched_init): only its offset
+    const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
+    trec[(size_t)tg[r] * SD + D] =
+        (float)(MODE == kSqEuc ? scd * (double)hf + lw2 - scd * yn2[r] : scd * (double)hf + lw2);
+    if (w > 0.0f) {
+      const double v = log((double)w) - (double)hf / rho_t;
+      if (v > mm) {
+        ms = ms * exp(mm - v) + 1.0;
+        mm = v;
+      } else {
+        ms += exp(v - mm);
+      }
+    }
+    if (!isfinite(hnew)) st.status = kBatchNumeric;
+    // one target's FP64 chain at a time: interleaving the R chains would multiply the
+    // registers the whole kernel is allocated
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  wave_lse(mm, ms);
+  dmx = wave_max(dmx);
+  dmn = wave_min(dmn);
+  int last = 0;
+  if (lane == 0) {
+    parts[it.w] = BlockPart{mm, ms, dmx, dmn};
+    __threadfence();
+    const int nitems = pitem[p + 1] - pitem[p];
+    last = (atomicAdd(&ticket[p], 1) == nitems - 1) ? 1 : 0;
+  }
+  last = __shfl(last, 0, 64);
+  if (last) {
+    __threadfence();
+    reduce_problem(a, p, g_step != 0);
+    if (lane == 0) ticket[p] = 0;
+  }
+}
+
+// One half-step for every active problem. g_step: targets y (beta, rho2), sources x.
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step) {
+  const int lane = threadIdx.x & 63;
+  const int nact = g_step ? *a.nact_g : *a.nact_f;
+  const int *act = g_step ? a.act_g : a.act_f;
+  const int4 *items = g_step ? a.items_g : a.items_f;
+  int *ctr = g_step ? a.ctr_g : a.ctr_f;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // the other side's counter is idle during this launch: reset it for the next one
     if (g_step) *a.ctr_f = 0; else *a.ctr_g = 0;
@@ -177,101 +317,11 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
     item = __shfl(item, 0, 64);
     if (item >= nact) break;
     const int4 it = items[act[item]];  // (problem, first target, count, slot)
-    const int p = it.x;
-    BatchState &st = a.state[p];
-    if (st.done) continue;  // finished by an earlier half-step (compaction is periodic)
-    const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
-    const double scd = 1.4426950408889634074 / eps;
-    const float sc = (float)scd;
-    const HalfCoef cf = g_step ? half_coef(eps, r2, r1) : half_coef(eps, r1, r2);
-    const double tau_src = g_step ? st.tau_f : st.tau_g;
-    const double s_src = g_step ? st.sA : st.sB;
-    const double rho_t = g_step ? r2 : r1;
-    const int64_t tb = off_t[p];
-    const int t = it.y + lane;  // target index within problem p
-    const bool valid = lane < it.z;
-    const int64_t tg = tb + (valid ? t : it.y);
-    const double *mu = a.mu + (size_t)p * kBatchMaxDim;
-    float yc[D];
-    double yn2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      yc[k] = k < a.d ? tpts[tg * a.d + k] - (float)mu[k] : 0.0f;
-      yn2 += (double)yc[k] * (double)yc[k];
-    }
-    // softmin over all sources of p
-    const int64_t s0 = off_s[p], s1 = off_s[p + 1];
-    float m = -FLT_MAX, l = 0.0f;
-    auto expo = [&](const float *rp) -> float {
-      if constexpr (MODE == kSqEuc) {
-        float acc = rp[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) acc = fmaf(rp[k], yc[k], acc);
-        return acc;
-      } else {
-        float d2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const float u = rp[k] - yc[k];
-          d2 = fmaf(u, u, d2);
-        }
-        const float c = (a.half_p == 0.5f) ? __builtin_sqrtf(d2) : fast_exp2(a.half_p * fast_log2(d2));
-        return fmaf(-sc, c, rp[D]);
-      }
-    };
-    int64_t s = s0;
-    for (; s + kTile <= s1; s += kTile) {
-      float v[kTile];
-#pragma unroll
-      for (int k = 0; k < kTile; ++k) v[k] = expo(srec + (size_t)(s + k) * SD);
-      float mt = v[0];
-#pragma unroll
-      for (int k = 1; k < kTile; ++k) mt = fmaxf(mt, v[k]);
-      const float mn = fmaxf(m, mt);
-      float acc = l * fast_exp2(m - mn);
-#pragma unroll
-      for (int k = 0; k < kTile; ++k) acc += fast_exp2(v[k] - mn);
-      l = acc;
-      m = mn;
-    }
-    for (; s < s1; ++s) {
-      const float v = expo(srec + (size_t)s * SD);
-      const float mn = fmaxf(m, v);
-      l = l * fast_exp2(m - mn) + fast_exp2(v - mn);
-      m = mn;
-    }
-    // epilogue: KL prox and TI translation (App. B), records of the new potential
-    double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
-    if (valid) {
-      double lse2 = (double)m + log2((double)l);
-      if constexpr (MODE == kSqEuc) lse2 -= scd * yn2;
-      const double S = -lse2 / scd;
-      const double hnew = cf.k_t * (S - tau_src) - cf.c_t * s_src;
-      const float hf = (float)hnew;
-      const float old = tpot[tg];
-      tpot[tg] = hf;
-      dmx = dmn = (double)hf - (double)old;
-      const float w = tw[tg];
-      write_rec<D, MODE>(trec + (size_t)tg * SD, yc, yn2, hf, w, scd);
-      if (w > 0.0f) { mm = log((double)w) - (double)hf / rho_t; ms = 1.0; }
-      if (!isfinite(hnew)) st.status = kBatchNumeric;
-    }
-    wave_lse(mm, ms);
-    dmx = wave_max(dmx);
-    dmn = wave_min(dmn);
-    int last = 0;
-    if (lane == 0) {
-      parts[it.w] = BlockPart{mm, ms, dmx, dmn};
-      __threadfence();
-      const int nitems = pitem[p + 1] - pitem[p];
-      last = (atomicAdd(&ticket[p], 1) == nitems - 1) ? 1 : 0;
-    }
-    last = __shfl(last, 0, 64);
-    if (last) {
-      __threadfence();
-      reduce_problem(a, p, g_step != 0);
-      if (lane == 0) ticket[p] = 0;
-    }
+    if (a.state[it.x].done) continue;  // finished by an earlier half-step (compaction is periodic)
+    if (it.z > 64)
+      batched_item<D, MODE, 4>(a, g_step, it);
+    else
+      batched_item<D, MODE, 1>(a, g_step, it);
   }
 }
 

@@ -948,7 +948,15 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
 // ---------------------------------------------------------------------------------------
 // Batched TI Sinkhorn
 // ---------------------------------------------------------------------------------------
-constexpr int kBatchItemTargets = 64;  // targets per work item (one wave, one per lane)
+// Work items of the batched solver: chunks of 256 targets (one wave, four per lane) while
+// more than 128 targets remain, then chunks of at most 64 (one per lane); a chunk of 129..255
+// runs as one four-per-lane item (it costs no more than the two or three small items).
+int64_t batch_item_len(int64_t rem) { return rem >= 256 ? 256 : rem > 128 ? rem : rem < 64 ? rem : 64; }
+int64_t batch_items(int64_t n) {
+  int64_t k = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += batch_item_len(n - t0)) ++k;
+  return k;
+}
 
 struct BatchLayout {
   size_t state = 0, mu = 0, offN = 0, offM = 0, items_g = 0, items_f = 0, pitem_g = 0, pitem_f = 0;
@@ -1153,8 +1161,8 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
     const int64_t n = offN[p + 1] - offN[p], m = offM[p + 1] - offM[p];
     if (n < 1 || m < 1) return fail(UOT_ERR_INVALID, "problem %d has n=%lld, m=%lld (must be >= 1)", p, (long long)n, (long long)m);
     if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_ERR_INVALID, "problem %d is too large", p);
-    ig += (m + kBatchItemTargets - 1) / kBatchItemTargets;
-    jf += (n + kBatchItemTargets - 1) / kBatchItemTargets;
+    ig += batch_items(m);
+    jf += batch_items(n);
   }
   if (ig > (1 << 30) || jf > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
   L.n_items_g = (int)ig;
@@ -1198,9 +1206,10 @@ void build_items(int32_t B, const int64_t *off, std::vector<int4> &items, std::v
   for (int p = 0; p < B; ++p) {
     pitem[p] = (int)items.size();
     const int64_t n = off[p + 1] - off[p];
-    for (int64_t t0 = 0; t0 < n; t0 += kBatchItemTargets) {
-      const int cnt = (int)((n - t0) < kBatchItemTargets ? (n - t0) : kBatchItemTargets);
+    for (int64_t t0 = 0; t0 < n;) {
+      const int cnt = (int)batch_item_len(n - t0);
       items.push_back(make_int4(p, (int)t0, cnt, (int)items.size()));
+      t0 += cnt;
     }
   }
   pitem[B] = (int)items.size();

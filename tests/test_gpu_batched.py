@@ -53,9 +53,12 @@ def small_batch(B=23, nmin=1, nmax=300, seed=31, d=2, p=2.0, eps=(2e-2, 2e-1), r
     return bt
 
 
-@pytest.mark.parametrize("d,p", [(2, 2.0), (3, 2.0), (1, 2.0), (5, 1.5), (8, 2.0)])
-def test_batched_iteration_parity(d, p):
-    bt = small_batch(d=d, p=p, seed=40 + d)
+@pytest.mark.parametrize("d,p,nmax", [(2, 2.0, 300), (3, 2.0, 300), (1, 2.0, 300), (5, 1.5, 300),
+                                       (8, 2.0, 300), (2, 2.0, 1100), (3, 1.5, 700)])
+def test_batched_iteration_parity(d, p, nmax):
+    """Sizes 1..nmax: work items of <= 64 targets (one per lane), of 129..256 targets (four
+    per lane), and problems split into several items of both kinds."""
+    bt = small_batch(B=23 if nmax <= 300 else 9, nmax=nmax, d=d, p=p, seed=40 + d + nmax)
     print("batched d=%d p=%g B=%d" % (d, p, bt.B), file=sys.stderr, flush=True)
     T = 12
     f, g, it, st = run_batched(bt, T)
