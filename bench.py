@@ -89,6 +89,11 @@ def one_step(uot, torch, tens, pairs, record):
     return updates
 
 
+# Sources compiled into the points softmin kernel (its code, the side reduction it runs, and
+# the argument and state layouts): the committed counters hold while these are unchanged.
+KERNEL_SOURCES = ("kernels_points.hip", "uot_mx.cuh", "uot_epilogue.cuh", "uot_internal.h")
+
+
 def profiled_traffic():
     """HBM bytes per launch of the points softmin from the committed counter summary, or None
     when the kernel source has changed since the counters were taken."""
@@ -99,12 +104,12 @@ def profiled_traffic():
     try:
         text = open(summary).read()
         h = hashlib.sha256()
-        for name in ("kernels_points.hip", "uot_mx.cuh"):
+        for name in KERNEL_SOURCES:
             h.update(open(os.path.join(csrc, name), "rb").read())
         sha = h.hexdigest()
     except OSError:
         return None
-    m_sha = re.search(r"source_sha256 \(kernels_points.hip \+ uot_mx.cuh\): ([0-9a-f]{64})", text)
+    m_sha = re.search(r"source_sha256 \(%s\): ([0-9a-f]{64})" % re.escape(" + ".join(KERNEL_SOURCES)), text)
     m_tr = re.search(r"traffic_bytes_per_launch: ([0-9.]+)", text)
     if not m_sha or not m_tr or m_sha.group(1) != sha:
         return None

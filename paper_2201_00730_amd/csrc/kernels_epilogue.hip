@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBergThreads) void k_berg_lambda(ReduceArgs a) {
 }
 
 // Threads per target in the combine kernel.
-constexpr int kCombLanes = 4;
+constexpr int kCombLanes = 2;
 constexpr int kCombTargets = kBlock / kCombLanes;
 
 template <int D, int MODE>

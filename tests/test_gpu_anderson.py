@@ -52,18 +52,28 @@ def _gpu():
 
 
 # Plain Sinkhorn's slow mode is the translation f + c, g - c (contraction k1 k2, Sec. 3);
-# the extrapolation steps along it with weights of order 1 / (1 - k1 k2) (50 here), so it
-# magnifies the float32 rounding of the iterates cycle after cycle. Plain trajectories are
-# therefore compared over the first cycles only; past them both sides still converge to the
-# same optimum (test_anderson_converged). TI has no such mode and is compared throughout.
+# the extrapolation steps along it with weights of order 1 / (1 - k1 k2) (50 here), so each
+# extrapolation can magnify the float32 rounding already in the iterates by up to that
+# factor: a few 1e-7 before the first, up to ~1e-5 after it, up to ~1e-3 after the second.
+# Plain trajectories are therefore compared through their first extrapolation only (the
+# iteration counts below give at most one); past it both sides still converge to the same
+# optimum (test_anderson_converged). TI has no such mode and is compared throughout.
 ITERATION_CASES = [(True, K, it) for K in (2, 4, 8) for it in (3, 8, 9, 30)] + \
-                  [(False, K, it) for K in (2, 4, 8) for it in (3, 8, 9)]
+                  [(False, 2, it) for it in (2, 3, 4)] + \
+                  [(False, 4, it) for it in (3, 5, 8)] + \
+                  [(False, 8, it) for it in (3, 8, 9, 16)]
+
+
+def extrapolations(K, iters):
+    """Extrapolations in a run of `iters` iterations: after every K-th iteration but the last."""
+    return (iters - 1) // K
 
 
 @pytest.mark.parametrize("ti,K,iters", ITERATION_CASES)
 def test_anderson_iteration_parity(ti, K, iters):
     pr = workloads.oned()
     _say("anderson oned ti=%s K=%d iters=%d" % (ti, K, iters))
+    assert ti or extrapolations(K, iters) <= 1
     f, g, info = run_gpu_acc(pr, ti, iters, K)
     r = run_oracle_acc(pr, ti, iters, K)
     _say("  rel f %.3g g %.3g" % (rel_inf(f, r.f), rel_inf(g, r.g)))
