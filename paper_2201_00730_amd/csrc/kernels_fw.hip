@@ -29,15 +29,16 @@ namespace uot {
 namespace {
 
 constexpr int kFwThreads = 256;
-constexpr int kFwWaves = kFwThreads / 64;
 
 __device__ __forceinline__ double cost1d(double x, double y, double p) {
   const double d = fabs(x - y);
   return p == 2.0 ? d * d : (p == 1.0 ? d : pow(d, p));
 }
 
-// Block-wide reductions (broadcast to every thread).
+// Block-wide reductions over NT threads (broadcast to every thread).
+template <int NT = kFwThreads>
 __device__ double fw_sum(double v) {
+  constexpr int kFwWaves = NT / 64;
   __shared__ double sh[kFwWaves];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -49,7 +50,9 @@ __device__ double fw_sum(double v) {
   __syncthreads();
   return s;
 }
+template <int NT = kFwThreads>
 __device__ double fw_max(double v) {
+  constexpr int kFwWaves = NT / 64;
   __shared__ double sh[kFwWaves];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -61,7 +64,9 @@ __device__ double fw_max(double v) {
   __syncthreads();
   return s;
 }
+template <int NT = kFwThreads>
 __device__ int fw_min_int(int v) {
+  constexpr int kFwWaves = NT / 64;
   __shared__ int sh[kFwWaves];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
@@ -88,10 +93,11 @@ struct Lse3 {
     const double e = exp(v - m);
     s0 += e; s1 += e * u; s2 += e * u * u;
   }
+  template <int NT = kFwThreads>
   __device__ void reduce(double &logs0, double &r1, double &r2) {
-    const double M = fw_max(m);
+    const double M = fw_max<NT>(m);
     const double c = (m == -INFINITY) ? 0.0 : exp(m - M);
-    const double t0 = fw_sum(s0 * c), t1 = fw_sum(s1 * c), t2 = fw_sum(s2 * c);
+    const double t0 = fw_sum<NT>(s0 * c), t1 = fw_sum<NT>(s1 * c), t2 = fw_sum<NT>(s2 * c);
     logs0 = M + log(t0);
     r1 = t1 / t0;
     r2 = t2 / t0;
@@ -101,9 +107,11 @@ struct Lse3 {
 // In-place inclusive prefix sum of v[0..n) by the block: each thread owns a contiguous
 // chunk; the chunk totals are scanned within each wave by lane shuffles and across the
 // waves through LDS.
+template <int NT = kFwThreads>
 __device__ void fw_scan(double *v, int n) {
+  constexpr int kFwWaves = NT / 64;
   __shared__ double sh[kFwWaves];
-  const int chunk = (n + kFwThreads - 1) / kFwThreads;
+  const int chunk = (n + NT - 1) / NT;
   const int i0 = min(n, (int)threadIdx.x * chunk), i1 = min(n, i0 + chunk);
   double s = 0.0;
   for (int i = i0; i < i1; ++i) s += v[i];
@@ -399,23 +407,18 @@ __device__ __forceinline__ int count_below(const double *a, int n, double v, boo
   return lo;
 }
 
-struct BaryTuple {
-  int K;
-  const double *w;
-  double sw;
-  __device__ double cost(const double *z, double *bary) const {
-    double sz = 0.0;
-    for (int k = 0; k < K; ++k) sz += w[k] * z[k];
-    const double b = sz / sw;
-    double c = 0.0;
-    for (int k = 0; k < K; ++k) c += w[k] * (z[k] - b) * (z[k] - b);
-    if (bary) *bary = b;
-    return c;
-  }
-};
+// Tuple costs for the squared distance: C(z) = sum_k w_k (z_k - b)^2 with the barycentric
+// point b = sum_k w_k z_k / sw, i.e. C = sum_k w_k z_k^2 - (sum_k w_k z_k)^2 / sw. Moving one
+// entry z_k by d changes it by w_k d (2 z_k + d - (2 S1 + w_k d) / sw), S1 = sum_k w_k z_k
+// before the move; the walk needs only S1 per event, no per-tuple arrays.
+__device__ __forceinline__ double move_cost(double wk, double zk, double d, double s1, double sw) {
+  return wk * d * (2.0 * zk + d - (2.0 * s1 + wk * d) / sw);
+}
 
-__global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fw_bary(BaryArgs a) {
   __shared__ double q[kBaryMaxK], lam[kBaryMaxK], wsh[kBaryMaxK];
+  __shared__ int cur_sh[kBaryMaxK * NT];
   __shared__ int64_t o[kBaryMaxK + 1];
   const int K = a.K;
   for (int prob = blockIdx.x; prob < a.B; prob += gridDim.x) {
@@ -426,7 +429,14 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
     const double rho = a.rho[prob];
     double sw = 0.0;
     for (int k = 0; k < K; ++k) sw += wsh[k];
-    const BaryTuple tup{K, wsh, sw};
+    // the first tuple (every measure at its first point): its cost and barycentric point
+    double first_cost = 0.0, first_b = 0.0;
+    for (int k = 0; k < K; ++k) first_b += wsh[k] * (double)a.x[o[k]];
+    first_b /= sw;
+    for (int k = 0; k < K; ++k) {
+      const double u = (double)a.x[o[k]] - first_b;
+      first_cost += wsh[k] * u * u;
+    }
     const int64_t base = o[0];
     const int64_t tot = o[K] - base;
     float *bx = a.bx + (base - m0 + prob), *bw = a.bw + (base - m0 + prob);
@@ -434,7 +444,7 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
     // validation: sorted supports, finite nonnegative weights, positive masses and penalties
     int bad = !(rho > 0.0) || !isfinite(rho);
     for (int k = 0; k < K; ++k) bad |= !(wsh[k] > 0.0) || !isfinite(wsh[k]);
-    for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) {
+    for (int64_t e = threadIdx.x; e < tot; e += NT) {
       const int64_t g = base + e;
       const float v = a.alpha[g];
       if (!(v >= 0.0f) || !isfinite(v)) bad = 1;
@@ -444,19 +454,19 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
     }
     for (int k = 0; k < K; ++k) {
       double mk = 0.0;
-      for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += kFwThreads) mk += a.alpha[g];
-      mk = fw_sum(mk);
+      for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += NT) mk += a.alpha[g];
+      mk = fw_sum<NT>(mk);
       bad |= !(mk > 0.0);
     }
-    bad = -fw_min_int(-bad);
+    bad = -fw_min_int<NT>(-bad);
     if (bad) {
-      for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) a.f[base + e] = NAN;
+      for (int64_t e = threadIdx.x; e < tot; e += NT) a.f[base + e] = NAN;
       if (threadIdx.x == 0) { a.status[prob] = kBatchInvalid; a.iters[prob] = 0; a.gap[prob] = NAN; }
       __syncthreads();
       continue;
     }
     double *fb = a.fb + base, *Ac = a.Ac + base, *r = a.r + base;
-    for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) fb[e] = 0.0;
+    for (int64_t e = threadIdx.x; e < tot; e += NT) fb[e] = 0.0;
     __syncthreads();
 
     // q_k = log <alpha_k, e^{-fb_k/(w_k rho)}> and lambda* (closed form); then Ac = the
@@ -465,12 +475,12 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
       for (int k = 0; k < K; ++k) {
         Lse3 l;
         const double sc = 1.0 / (wsh[k] * rho);
-        for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += kFwThreads) {
+        for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += NT) {
           const double v = a.alpha[g];
           l.add(v > 0.0 ? log(v) - fb[g - base] * sc : -INFINITY, 0.0);
         }
         double lq, u1, u2;
-        l.reduce(lq, u1, u2);
+        l.reduce<NT>(lq, u1, u2);
         if (threadIdx.x == 0) q[k] = lq;
       }
       __syncthreads();
@@ -479,13 +489,13 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
       if (threadIdx.x < K) lam[threadIdx.x] = wsh[threadIdx.x] * rho * q[threadIdx.x] - wsh[threadIdx.x] / sw * sq;
       for (int k = 0; k < K; ++k) {
         const double sc = 1.0 / (wsh[k] * rho);
-        for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += kFwThreads) {
+        for (int64_t g = o[k] + threadIdx.x; g < o[k + 1]; g += NT) {
           const double v = a.alpha[g];
           Ac[g - base] = v > 0.0 ? exp(log(v) - fb[g - base] * sc - q[k]) : 0.0;
         }
       }
       __syncthreads();
-      for (int k = 0; k < K; ++k) fw_scan(Ac + (o[k] - base), (int)(o[k + 1] - o[k]));
+      for (int k = 0; k < K; ++k) fw_scan<NT>(Ac + (o[k] - base), (int)(o[k + 1] - o[k]));
       return q[0] - lam[0] / (wsh[0] * rho);
     };
 
@@ -494,60 +504,49 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
     // decrease, so the co-ranks in the other measures are found by one binary search at the
     // run's first event and then by forward steps.
     auto walk = [&](bool plan) {
-      const int64_t chunk = (tot + kFwThreads - 1) / kFwThreads;
+      const int64_t chunk = (tot + NT - 1) / NT;
       const int64_t e0 = min(tot, (int64_t)threadIdx.x * chunk), e1 = min(tot, e0 + chunk);
-      int cur[kBaryMaxK];
+      // forward cursors of this thread's run, one per measure, in LDS (column per thread)
+      int *cur = cur_sh + threadIdx.x;
       int curk = -1, k = 0;
       for (int64_t e = e0; e < e1; ++e) {
         const int64_t g = base + e;
         while (g >= o[k + 1]) ++k;
         const int i = (int)(g - o[k]);
         const int nk = (int)(o[k + 1] - o[k]);
-        if (i == 0 && !plan) {
-          if (k == 0) {
-            double z[kBaryMaxK];
-            for (int jj = 0; jj < K; ++jj) z[jj] = a.x[o[jj]];
-            r[e] = tup.cost(z, nullptr);
-          } else {
-            r[e] = 0.0;
-          }
-        }
+        if (i == 0 && !plan) r[e] = k == 0 ? first_cost : 0.0;
         if (i + 1 >= nk) continue;  // the last point never leaves
         const double lev = Ac[e];
-        double z[kBaryMaxK];
+        const double xk = a.x[g];
+        double s1 = wsh[k] * xk;  // sum_j w_j z_j of the tuple before the event
         int pos = i;
-#pragma unroll
-        for (int jj = 0; jj < kBaryMaxK; ++jj) {
-          if (jj >= K) break;
-          if (jj == k) { z[jj] = a.x[g]; continue; }
+        for (int jj = 0; jj < K; ++jj) {
+          if (jj == k) continue;
           const int nj = (int)(o[jj + 1] - o[jj]);
           const double *aj = Ac + (o[jj] - base);
           int c;
           if (k != curk) {
             c = count_below(aj, nj, lev, jj < k);
           } else {
-            c = cur[jj];
+            c = cur[jj * NT];
             if (jj < k) { while (c < nj && aj[c] <= lev) ++c; }
             else { while (c < nj && aj[c] < lev) ++c; }
           }
-          cur[jj] = c;
+          cur[jj * NT] = c;
           // clamped: a level at or past a measure's total (rounding, trailing zero weights)
           // leaves it at its last point, and keeps pos inside [0, T)
           const int cc = min(c, nj - 1);
           pos += cc;
-          z[jj] = a.x[o[jj] + cc];
+          s1 += wsh[jj] * (double)a.x[o[jj] + cc];
         }
         curk = k;
+        const double d = (double)a.x[g + 1] - xk;
         if (!plan) {
-          const double before = tup.cost(z, nullptr);
-          z[k] = a.x[g + 1];
-          r[e + 1] = tup.cost(z, nullptr) - before;
+          r[e + 1] = move_cost(wsh[k], xk, d, s1, sw);
         } else {
-          z[k] = a.x[g + 1];
-          double b;
-          tup.cost(z, &b);
-          bx[pos + 1] = (float)b;  // the tuple after the event at merged position pos
-          r[pos] = lev;            // the event's level (r is free in plan mode)
+          // the barycentric point of the tuple after the event at merged position pos
+          bx[pos + 1] = (float)((s1 + wsh[k] * d) / sw);
+          r[pos] = lev;  // the event's level (r is free in plan mode)
         }
       }
       __syncthreads();
@@ -558,19 +557,19 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
     for (; t < a.max_iter; ++t) {
       const double logmt = tilt();
       walk(false);
-      for (int k = 0; k < K; ++k) fw_scan(r + (o[k] - base), (int)(o[k + 1] - o[k]));
+      for (int k = 0; k < K; ++k) fw_scan<NT>(r + (o[k] - base), (int)(o[k + 1] - o[k]));
       double gp = 0.0;
-      for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) {
+      for (int64_t e = threadIdx.x; e < tot; e += NT) {
         const int64_t g = base + e;
         int k = 0;
         while (g >= o[k + 1]) ++k;
         const double an = Ac[e] - (g > o[k] ? Ac[e - 1] : 0.0);
         gp += an * (r[e] - fb[e]);
       }
-      gap = exp(logmt) * fw_sum(gp);
+      gap = exp(logmt) * fw_sum<NT>(gp);
       if (a.tol > 0.0 && gap <= a.tol) break;
       const double gamma = 2.0 / (2.0 + t);
-      for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) fb[e] = (1.0 - gamma) * fb[e] + gamma * r[e];
+      for (int64_t e = threadIdx.x; e < tot; e += NT) fb[e] = (1.0 - gamma) * fb[e] + gamma * r[e];
       __syncthreads();
     }
     const int run = t < a.max_iter ? t + 1 : a.max_iter;
@@ -578,7 +577,7 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
     const double logmt = tilt();
     const double mt = exp(logmt);
     bool finite = true;
-    for (int64_t e = threadIdx.x; e < tot; e += kFwThreads) {
+    for (int64_t e = threadIdx.x; e < tot; e += NT) {
       const int64_t g = base + e;
       int k = 0;
       while (g >= o[k + 1]) ++k;
@@ -586,21 +585,16 @@ __global__ __launch_bounds__(kFwThreads) void k_fw_bary(BaryArgs a) {
       finite = finite && isfinite(v);
       a.f[g] = (float)v;
     }
-    if (threadIdx.x == 0) {
-      double z[kBaryMaxK], b;
-      for (int j = 0; j < K; ++j) z[j] = a.x[o[j]];
-      tup.cost(z, &b);
-      bx[0] = (float)b;
-    }
+    if (threadIdx.x == 0) bx[0] = (float)first_b;
     walk(true);
     // masses: tuple tt lies between the events tt - 1 and tt (levels 0 and 1 at the ends)
-    for (int tt = threadIdx.x; tt <= T; tt += kFwThreads) {
+    for (int tt = threadIdx.x; tt <= T; tt += NT) {
       const double hi = tt < T ? fmin(r[tt], 1.0) : 1.0;
       const double lo = tt > 0 ? fmin(r[tt - 1], 1.0) : 0.0;
       bw[tt] = (float)(fmax(hi - lo, 0.0) * mt);
     }
     __syncthreads();
-    const int allfinite = fw_min_int(finite ? 1 : 0);
+    const int allfinite = fw_min_int<NT>(finite ? 1 : 0);
     if (threadIdx.x == 0) {
       a.iters[prob] = run;
       a.gap[prob] = gap;
@@ -635,7 +629,13 @@ hipError_t launch_fw_bary(const BaryLaunch &l, hipStream_t s) {
   a.gap = l.gap;
   a.status = l.status;
   const int grid = l.B < l.max_blocks ? l.B : l.max_blocks;
-  hipLaunchKernelGGL(k_fw_bary, dim3(grid > 0 ? grid : 1), dim3(kFwThreads), 0, s, a);
+  // Two blocks' worth of threads per problem when there are no more problems than CUs
+  // (max_blocks is twice the CU count): the walk's runs and the per-thread shares of the
+  // scans are half as long.
+  if (l.B <= l.max_blocks / 2)
+    hipLaunchKernelGGL(k_fw_bary<512>, dim3(grid > 0 ? grid : 1), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_fw_bary<kFwThreads>, dim3(grid > 0 ? grid : 1), dim3(kFwThreads), 0, s, a);
   return hipGetLastError();
 }
 

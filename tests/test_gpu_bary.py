@@ -117,3 +117,34 @@ def test_barycenter_batched_ragged_and_invalid():
             continue
         assert st[b] == 1
         _check_problem(f[lo:hi], bx[blo:bhi], bw[blo:bhi], xs, ws, W[b], rho[b], 20, "b=%d" % b)
+
+
+def test_barycenter_more_problems_than_cus():
+    """300 problems of K = 3 small measures: more problems than CUs, so each workgroup of the
+    narrower launch shape takes several problems in turn."""
+    K, B = 3, 300
+    rng = np.random.default_rng(77)
+    all_x, all_w, per = [], [], []
+    for b in range(B):
+        sizes = [int(v) for v in rng.integers(1, 40, K)]
+        xs, ws = mixtures(K, sizes, seed=1000 + b)
+        per.append((xs, ws))
+        all_x += xs
+        all_w += ws
+    off = np.concatenate([[0], np.cumsum([len(x) for x in all_x])]).astype(np.int64)
+    W = rng.uniform(0.5, 1.5, (B, K))
+    W /= W.sum(1, keepdims=True)
+    rho = rng.uniform(0.2, 2.0, B)
+    _say("barycenter 300 problems")
+    f, bx, bw, it, gap, st = uot.fw1d_barycenter(off, K, dev(np.concatenate(all_x)),
+                                                 dev(np.concatenate(all_w)),
+                                                 dev(W.reshape(-1), np.float64),
+                                                 dev(rho, np.float64), max_iter=15)
+    f, bx, bw = (v.cpu().numpy().astype(np.float64) for v in (f, bx, bw))
+    assert np.all(st.cpu().numpy() == 1)
+    for b in range(0, B, 7):
+        xs, ws = per[b]
+        lo, hi = off[b * K], off[(b + 1) * K]
+        blo = lo - b * K + b
+        bhi = blo + (hi - lo) - K + 1
+        _check_problem(f[lo:hi], bx[blo:bhi], bw[blo:bhi], xs, ws, W[b], rho[b], 15, "b=%d" % b)
