@@ -134,3 +134,33 @@ def test_fw_batched_ragged_and_invalid():
             worst = max(worst, rel_inf(fk, r.f), rel_inf(gk, r.g))
         _say("  worst rel %.3g" % worst)
         assert worst < TOL
+
+
+def test_fw_batched_large_problems():
+    """6 problems with 700..3000 points a side (each thread of the workgroup owns several
+    points in every loop, scan and merge share), against the oracle."""
+    rng = np.random.default_rng(78)
+    sizes = [(int(rng.integers(700, 3000)), int(rng.integers(700, 3000))) for _ in range(6)]
+    xs, ys, As, Bs = [], [], [], []
+    for k, (n, m) in enumerate(sizes):
+        x, y, a, b = random_problem(n, m, seed=2000 + k)
+        xs.append(x); ys.append(y); As.append(a); Bs.append(b)
+    offN = np.concatenate([[0], np.cumsum([n for n, _ in sizes])]).astype(np.int64)
+    offM = np.concatenate([[0], np.cumsum([m for _, m in sizes])]).astype(np.int64)
+    rho1 = rng.uniform(0.1, 2.0, 6)
+    rho2 = rng.uniform(0.1, 2.0, 6)
+    for ls in (False, True):
+        _say("fw batched large ls=%s" % ls)
+        f, g, it, gap, st = uot.fw1d_batched(offN, offM, dev(np.concatenate(xs)), dev(np.concatenate(ys)),
+                                             dev(np.concatenate(As)), dev(np.concatenate(Bs)),
+                                             dev(rho1, np.float64), dev(rho2, np.float64),
+                                             line_search=ls, max_iter=30)
+        f, g = f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+        it, st = it.cpu().numpy(), st.cpu().numpy()
+        worst = 0.0
+        for k in range(6):
+            r = oracle_fw(xs[k], ys[k], As[k], Bs[k], rho1[k], rho2[k], line_search=ls, max_iter=30)
+            assert st[k] == 1 and it[k] == 30
+            worst = max(worst, rel_inf(f[offN[k]:offN[k + 1]], r.f), rel_inf(g[offM[k]:offM[k + 1]], r.g))
+        _say("  worst rel %.3g" % worst)
+        assert worst < TOL
