@@ -133,10 +133,55 @@ def _profiled(uot, kinds):
     return n, ms, ent
 
 
+RATE_RHOS = (0.01, 0.1, 1.0, 10.0)
+RATE_T = 100        # iterations whose errors enter the rate estimate
+RATE_FLOOR = 1e-5   # errors below this (float32 potentials) are left out
+
+
+def kappa(errs, floor=RATE_FLOOR):
+    """Contraction rate as the paper's empirical study estimates it (Sec. 3): exp of the
+    median over t of log e_{t+1} - log e_t, e_t = ||f_t - f*||_inf, over the pairs above the
+    floor."""
+    import numpy as np
+    d = [np.log(errs[i + 1]) - np.log(errs[i]) for i in range(len(errs) - 1)
+         if errs[i] > floor and errs[i + 1] > floor]
+    return float(np.exp(np.median(d))) if d else None
+
+
+def contraction_rates(uot, np, pr, kw, a, b):
+    """F- (plain), H- (TI) and G-Sinkhorn (KL and Berg entropies) on the 1-D measures at
+    eps = 1e-2 as rho varies: the rate kappa, the iterations to ||f_t - f*|| < 1e-6 and, at
+    rho = 1, the error curve. f* is each solver's own limit (run to change < 1e-8), f_t the
+    potentials after t iterations from zero."""
+    solvers = {
+        "F": lambda **k: uot.sinkhorn(a, b, **k),
+        "H": lambda **k: uot.ti_sinkhorn(a, b, **k),
+        "G_kl": lambda **k: uot.sinkhorn_phi(a, b, entropy="kl", variant="G", **k),
+        "G_berg": lambda **k: uot.sinkhorn_phi(a, b, entropy="berg", variant="G", **k),
+    }
+    out = {}
+    for rho in RATE_RHOS:
+        kk = dict(kw, rho1=rho, rho2=rho)
+        for name, fn in solvers.items():
+            fstar = fn(max_iter=MAX_ITER, tol=1e-8, check_every=10, **kk)[0].cpu().numpy().astype(np.float64)
+            errs = [float(np.max(np.abs(fn(max_iter=t, tol=0.0, **kk)[0].cpu().numpy().astype(np.float64) - fstar)))
+                    for t in range(1, RATE_T + 1)]
+            row = {"kappa": kappa(errs),
+                   "iters_to_err_1e-6": next((t + 1 for t, e in enumerate(errs) if e < 1e-6), None)}
+            if rho == 1.0:
+                row["err_t"] = {str(t): errs[t - 1] for t in (1, 2, 5, 10, 20, 50, 100)}
+            out.setdefault(name, {})[str(rho)] = row
+        print("rates rho=%g %s" % (rho, {n: out[n][str(rho)]["kappa"] for n in solvers}),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def extra_workload(args, uot, torch, np, workloads):
     """One JSON line for a workload other than the benchmark step:
     oned      N=M=200 1-D measures: latency per iteration (2000 iterations from 0, TI and
-              plain) and time to change < 1e-6; the FP64 oracle runs the same 2000 iterations.
+              plain) and time to change < 1e-6; the empirical contraction rates of F-, H- and
+              G-Sinkhorn as rho varies (see contraction_rates); the FP64 oracle runs the same
+              2000 iterations.
     stored8d  stored 16384^2 float32 cost (||x-y||^1.5, D=8): TI, exactly 500 iterations;
               HBM roofline of the stored-cost softmin kernels (4 bytes of C per entry).
     batch2d   4096 problems, N_p, M_p ~ U{64..4096}, D=2: batched TI to change < 1e-6;
@@ -170,6 +215,7 @@ def extra_workload(args, uot, torch, np, workloads):
                                                            check_every=1, **kw))
             res[name] = {"us_per_iteration": dt / 2000 * 1e6, "iters_to_tol": info.iters,
                          "seconds_to_tol": dt_tol}
+        rates = contraction_rates(uot, np, pr, kw, a, b)
         import oracle
         cost = oracle.Cost(x=pr.x.astype(np.float64), y=pr.y.astype(np.float64), p=2.0)
         t0 = time.perf_counter()
@@ -181,7 +227,7 @@ def extra_workload(args, uot, torch, np, workloads):
                     "value": res["ti"]["us_per_iteration"], "unit": "us/iteration",
                     "higher_is_better": False,
                     "config": {"workload": "1-D measures N=M=200, eps=1e-2, rho=1"},
-                    "solvers": res, "roofline": None,
+                    "solvers": res, "contraction_rates": rates, "roofline": None,
                     "cpu_baseline": {"value": cpu, "unit": "us/iteration", "kind": "oracle",
                                      "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                                      "sample": "FP64 C oracle, 2000 iterations each of TI and plain"}})

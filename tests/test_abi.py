@@ -192,3 +192,12 @@ def test_barycenter_rejects_bad_arguments_before_any_launch(lib):
                                      None, None, None, None, None, None, 0, None)
         assert st == uot.UOT_ERR_INVALID
         assert lib.uot_last_error()
+
+
+def test_rate_estimate_of_a_geometric_sequence():
+    """The bench's rate estimate (median log ratio of consecutive errors) returns the ratio of
+    a geometric sequence exactly, ignores errors under the floor, and is None without pairs."""
+    import bench
+    assert abs(bench.kappa([0.8 ** t for t in range(30)]) - 0.8) < 1e-12
+    assert abs(bench.kappa([0.5 ** t for t in range(10)] + [1e-7, 1e-7]) - 0.5) < 1e-12
+    assert bench.kappa([1e-6, 1e-7]) is None
