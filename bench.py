@@ -92,24 +92,25 @@ def one_step(uot, torch, tens, pairs, record):
 # Sources compiled into the points softmin kernel (its code, the side reduction it runs, and
 # the argument and state layouts): the committed counters hold while these are unchanged.
 KERNEL_SOURCES = ("kernels_points.hip", "uot_mx.cuh", "uot_epilogue.cuh", "uot_internal.h")
+DENSE_SOURCES = ("kernels_dense.hip", "uot_internal.h")
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the points softmin from the committed counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+def profiled_traffic(summary_name="points_softmin_cloud3d_hbm_bytes.md", sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a softmin kernel from its committed counter summary, or None
+    when the kernel sources have changed since the counters were taken."""
     import hashlib
     import re
-    summary = os.path.join(ROOT, "profiles", "points_softmin_cloud3d_hbm_bytes.md")
+    summary = os.path.join(ROOT, "profiles", summary_name)
     csrc = os.path.join(ROOT, "paper_2201_00730_amd", "csrc")
     try:
         text = open(summary).read()
         h = hashlib.sha256()
-        for name in KERNEL_SOURCES:
+        for name in sources:
             h.update(open(os.path.join(csrc, name), "rb").read())
         sha = h.hexdigest()
     except OSError:
         return None
-    m_sha = re.search(r"source_sha256 \(%s\): ([0-9a-f]{64})" % re.escape(" + ".join(KERNEL_SOURCES)), text)
+    m_sha = re.search(r"source_sha256 \(%s\): ([0-9a-f]{64})" % re.escape(" + ".join(sources)), text)
     m_tr = re.search(r"traffic_bytes_per_launch: ([0-9.]+)", text)
     if not m_sha or not m_tr or m_sha.group(1) != sha:
         return None
@@ -201,6 +202,13 @@ def extra_workload(args, uot, torch, np, workloads):
               them); and 512 such problems with 64..512 points per measure, 500 iterations."""
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    if args.calibrate_copy:  # a plain 256 MiB device copy, the yardstick of the byte counters
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
            "higher_is_better": True, "scaling": "weak"}
     if args.workload == "oned":
@@ -247,7 +255,9 @@ def extra_workload(args, uot, torch, np, workloads):
                     "config": {"workload": "stored cost 16384^2 float32 (||x-y||^1.5, D=8), "
                                            "eps=5e-3, rho=0.5, TI 500 iterations"},
                     "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                                 "frac": gbs / 8000.0, "traffic": None,
+                                 "frac": gbs / 8000.0,
+                                 "traffic": profiled_traffic("dense_softmin_stored8d_hbm_bytes.md",
+                                                             DENSE_SOURCES),
                                  "kernel": "k_dense_cols_partial + k_dense_rows (4 B of C per entry)",
                                  "launches": n, "avg_launch_ms": ms / n if n else None}})
     elif args.workload == "batch2d":
