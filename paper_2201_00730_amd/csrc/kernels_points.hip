@@ -206,7 +206,10 @@ __global__ __launch_bounds__(256) void k_points_mfma(PointsArgs a) {
   Form::build_b(yc, h, bf);
   if (stop) return;
   float sig, l;
-  column_softmin<Form>(a.rec, s0, s1, col, h, bf, fa, sig, l);
+  if constexpr (Form::kSigmaInB && Form::NJ >= 4)
+    column_softmin_ahead2<Form>(a.rec, s0, s1, col, h, bf, fa, sig, l);
+  else
+    column_softmin<Form>(a.rec, s0, s1, col, h, bf, fa, sig, l);
 
   // merge the two half-waves of each column (same sigma; sums add)
   const float ll = l + __shfl_xor(l, 32, 64);

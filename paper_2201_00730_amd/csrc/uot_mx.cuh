@@ -210,4 +210,72 @@ __device__ __forceinline__ void column_softmin(const float *rec, int s0, int s1,
   }
 }
 
+// column_softmin with the records prefetched two tiles ahead, in two fragment sets that take
+// the tiles in turn (no copies). For the bf16-split forms of larger D (four or more
+// instructions per tile, 16 bytes per instruction and lane): their register count leaves
+// two or three waves per SIMD, too few to cover a one-tile-ahead load with the other waves'
+// work. Same arithmetic and tile order as column_softmin; the slow path (recentre) is
+// taken tile by tile.
+template <typename Form>
+__device__ __forceinline__ void column_softmin_ahead2(const float *rec, int s0, int s1, int col,
+                                                      int h, typename Form::Frag (&bf)[Form::NJ],
+                                                      typename Form::Frag (&fa)[Form::NJ],
+                                                      float &sig, float &l) {
+  static_assert(Form::kSigmaInB, "the accumulator input is zero: sigma rides in B");
+  constexpr int NJ = Form::NJ, RS = Form::RS;
+  typedef typename Form::Frag Frag;
+  auto load_a = [&](int sb, Frag (&af)[NJ]) { Form::load_a(rec + (size_t)sb * RS, col, h, af); };
+  Frag fb[NJ];
+  if (s0 + 32 < s1) load_a(s0 + 32, fb);
+  sig = 0.0f;
+  l = 0.0f;
+  bool started = false;
+  f32x16 zero;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) zero[r] = 0.0f;
+  auto recentre = [&](const f32x16 &acc) {
+    float tm = acc[0];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) tm = fmaxf(tm, acc[r]);
+    tm = fmaxf(tm, __shfl_xor(tm, 32, 64));
+    if (tm > -INFINITY) {
+      const float ns = Form::representable(sig + (started ? fmaxf(tm, 0.0f) : tm));
+      const float delta = ns - sig;
+      float t2 = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) t2 += mx_exp2(acc[r] - delta);
+      l = started ? l * mx_exp2(-delta) + t2 : t2;
+      sig = ns;
+      started = true;
+      Form::set_sigma(bf, sig, h);
+    }
+  };
+  auto fast_add = [&](const f32x16 &acc) {
+    float q0 = mx_exp2(acc[0]), q1 = mx_exp2(acc[1]);
+    float q2 = mx_exp2(acc[2]), q3 = mx_exp2(acc[3]);
+#pragma unroll
+    for (int r = 4; r < 16; r += 4) {
+      q0 += mx_exp2(acc[r]);
+      q1 += mx_exp2(acc[r + 1]);
+      q2 += mx_exp2(acc[r + 2]);
+      q3 += mx_exp2(acc[r + 3]);
+    }
+    const float ts = (q0 + q1) + (q2 + q3);
+    if (__any(!(ts <= 0x1p64f))) return false;
+    l += ts;
+    return true;
+  };
+  // one tile from the fragment set `cur`, which then receives the tile two ahead
+  auto step = [&](Frag (&cur)[NJ], int sb) {
+    const f32x16 acc = Form::mma(cur, bf, zero);
+    if (sb + 64 < s1) load_a(sb + 64, cur);
+    if (!__all(started) || !fast_add(acc)) recentre(acc);
+  };
+  for (int sb = s0; sb < s1; sb += 64) {
+    step(fa, sb);
+    if (sb + 32 >= s1) break;
+    step(fb, sb + 32);
+  }
+}
+
 }  // namespace uot
