@@ -468,7 +468,7 @@ def kernel_name(variant: str) -> str:
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
+        print("bench.py runs on one GPU only (there is no multi-GPU path); got --gpus %d"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
