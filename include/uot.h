@@ -67,6 +67,13 @@ typedef enum {
  *  kind = UOT_COST_POINTS: x is [n, d], y is [m, d] (row-major float32), 1 <= d <= 64,
  *                          p >= 1 (p = 2 is the squared Euclidean cost and takes the
  *                          fastest path). C and ldc unused.
+ *                          Accuracy of p = 2: the exponent is evaluated in the expanded
+ *                          form |x|^2 + |y|^2 - 2<x, y> on points centred on their common
+ *                          mean, whose float32 rounding is about
+ *                          2^-24 (d + 4) (max|x - mu| + max|y - mu|)^2 per softmin in
+ *                          potential units, whatever eps. Where the potentials are not
+ *                          well above that (tiny eps with clouds of large spread), a stored
+ *                          cost or p != 2 (direct differences) is more accurate.
  * n (size of alpha, the "source" side) and m (size of beta) are >= 1.
  */
 typedef struct {

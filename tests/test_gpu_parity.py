@@ -368,3 +368,53 @@ def test_points_kernels_agree(n, m, d):
             assert rel_inf(f, r.f) < tol and rel_inf(g, r.g) < tol, (variant, rel_inf(f, r.f), tol)
     finally:
         uot.set_points_kernel(prev)
+
+
+# ---------------------------------------------------------------------------------------
+# Extreme regularisation and penalties
+# ---------------------------------------------------------------------------------------
+EXTREME = [
+    # (eps, rho1, rho2): tiny eps (exponents up to ~1e4 in log2 units), nearly balanced
+    # (rho / eps = 1e4), strongly unbalanced (rho << eps), eps far above the cost range
+    (1e-4, 1.0, 1.0),
+    (1e-3, 0.05, 2.0),
+    (1.0, 1e4, 1e4),
+    (0.05, 1e-3, 1e-3),
+    (10.0, 1.0, 0.3),
+]
+
+
+def expanded_form_bound(pr, d, iters):
+    """Absolute error bound of the p = 2 points path after `iters` iterations. One softmin
+    evaluates the exponent in the expanded form |x|^2 + |y|^2 - 2<x, y> on centred points, with
+    a float32 rounding of about E = 2^-24 (d + 4) (max|x - mu| + max|y - mu|)^2 in potential
+    units, whatever eps. Each half-step adds at most E to every potential, and the errors
+    already there contract at least as fast as plain Sinkhorn's slowest mode, the translation
+    with k1 k2 = rho1 rho2 / ((eps + rho1)(eps + rho2)) (Sec. 3): at most
+    2 E min(iters, 1 / (1 - k1 k2)) after `iters` iterations."""
+    xy = np.concatenate([pr.x, pr.y]).astype(np.float64)
+    mu = xy.mean(0)
+    span = (np.sqrt(((pr.x - mu) ** 2).sum(1)).max() + np.sqrt(((pr.y - mu) ** 2).sum(1)).max())
+    k1k2 = pr.rho1 / (pr.eps + pr.rho1) * pr.rho2 / (pr.eps + pr.rho2)
+    return 2.0 * 2.0 ** -24 * (d + 4) * span ** 2 * min(iters, 1.0 / (1.0 - k1k2))
+
+
+@pytest.mark.parametrize("dense", [False, True])
+@pytest.mark.parametrize("ti", [True, False])
+@pytest.mark.parametrize("eps,rho1,rho2", EXTREME)
+def test_extreme_parameters(eps, rho1, rho2, ti, dense):
+    """Stored costs meet 1e-5. The points path meets 1e-5 or, where the potentials are small
+    against the squared spread of the clouds (eps = 1e-4 and 1e-3 here, |f| ~ 0.05-0.2),
+    the derived bound of its expanded-form exponent (expanded_form_bound)."""
+    pr = workloads.random_small(150, 97, d=2, seed=17, eps=eps, rho1=rho1, rho2=rho2, p=2.0,
+                                dense=dense)
+    bound = 0.0 if dense else expanded_form_bound(pr, 2, 30)
+    if dense:
+        pr.x = pr.y = None
+    _say("extreme eps=%g rho=(%g, %g) ti=%s dense=%s" % (eps, rho1, rho2, ti, dense))
+    f, g, info = run_gpu(pr, ti, 30)
+    r = run_oracle(pr, ti, 30)
+    _say("  rel f %.3g g %.3g (bound %.3g)" % (rel_inf(f, r.f), rel_inf(g, r.g), bound))
+    assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
+    for u, v in ((f, r.f), (g, r.g)):
+        assert np.max(np.abs(u - v)) <= max(TOL * np.max(np.abs(v)), bound), (rel_inf(u, v), bound)
