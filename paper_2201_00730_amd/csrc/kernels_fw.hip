@@ -133,6 +133,109 @@ __device__ void fw_scan(double *v, int n) {
   __syncthreads();
 }
 
+// K values reduced together (one LDS exchange and two barriers for all of them; each value
+// is summed, or maximised, in the same order as fw_sum / fw_max would).
+template <int K, int NT = kFwThreads>
+__device__ void fw_sum_k(double (&v)[K]) {
+  constexpr int kW = NT / 64;
+  __shared__ double sh[K][kW];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], o, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = sh[k][0];
+#pragma unroll
+    for (int w = 1; w < kW; ++w) t += sh[k][w];
+    v[k] = t;
+  }
+  __syncthreads();
+}
+template <int K, int NT = kFwThreads>
+__device__ void fw_max_k(double (&v)[K]) {
+  constexpr int kW = NT / 64;
+  __shared__ double sh[K][kW];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], o, 64));
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = sh[k][0];
+#pragma unroll
+    for (int w = 1; w < kW; ++w) t = fmax(t, sh[k][w]);
+    v[k] = t;
+  }
+  __syncthreads();
+}
+
+// Lse3::reduce of two sides at once (same arithmetic, four barriers instead of sixteen).
+__device__ void lse3_reduce2(const Lse3 &a, const Lse3 &b, double &la, double &a1, double &a2,
+                             double &lb, double &b1, double &b2) {
+  double M[2] = {a.m, b.m};
+  fw_max_k<2>(M);
+  const double ca = (a.m == -INFINITY) ? 0.0 : exp(a.m - M[0]);
+  const double cb = (b.m == -INFINITY) ? 0.0 : exp(b.m - M[1]);
+  double S[6] = {a.s0 * ca, a.s1 * ca, a.s2 * ca, b.s0 * cb, b.s1 * cb, b.s2 * cb};
+  fw_sum_k<6>(S);
+  la = M[0] + log(S[0]);
+  a1 = S[1] / S[0];
+  a2 = S[2] / S[0];
+  lb = M[1] + log(S[3]);
+  b1 = S[4] / S[3];
+  b2 = S[5] / S[3];
+}
+
+// fw_scan of two arrays at once (one LDS exchange).
+__device__ void fw_scan2(double *v, int n, double *u, int m) {
+  constexpr int kW = kFwThreads / 64;
+  __shared__ double sh[2][kW];
+  const int cv = (n + kFwThreads - 1) / kFwThreads, cu = (m + kFwThreads - 1) / kFwThreads;
+  const int i0 = min(n, (int)threadIdx.x * cv), i1 = min(n, i0 + cv);
+  const int j0 = min(m, (int)threadIdx.x * cu), j1 = min(m, j0 + cu);
+  double sv = 0.0, su = 0.0;
+  for (int i = i0; i < i1; ++i) sv += v[i];
+  for (int j = j0; j < j1; ++j) su += u[j];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double iv = sv, iu = su;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double pv = __shfl_up(iv, o, 64), pu = __shfl_up(iu, o, 64);
+    if (lane >= o) {
+      iv += pv;
+      iu += pu;
+    }
+  }
+  if (lane == 63) {
+    sh[0][wave] = iv;
+    sh[1][wave] = iu;
+  }
+  __syncthreads();
+  double rv = iv - sv, ru = iu - su;  // exclusive prefixes within the wave
+  for (int w = 0; w < wave; ++w) {
+    rv += sh[0][w];
+    ru += sh[1][w];
+  }
+  for (int i = i0; i < i1; ++i) {
+    rv += v[i];
+    v[i] = rv;
+  }
+  for (int j = j0; j < j1; ++j) {
+    ru += u[j];
+    u[j] = ru;
+  }
+  __syncthreads();
+}
+
 // Number of Ac elements among the first k merged elements (rows first on ties).
 __device__ int fw_corank(int k, const double *Ac, int n, const double *Bc, int m) {
   int lo = max(0, k - m), hi = min(k, n);
@@ -152,7 +255,6 @@ struct FwArgs {
   int line_search, max_iter;
   double tol;
   double *fb, *gb, *Ac, *Bc, *r, *s;  // [N] / [M] per problem at the problem's offsets
-  int *jst, *ist;                      // row start columns [N], column start rows [M]
   float *f, *g;
   int32_t *iters;
   double *gap;
@@ -193,7 +295,6 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
     const float *x = a.x + o1, *y = a.y + o2, *al = a.alpha + o1, *be = a.beta + o2;
     double *fb = a.fb + o1, *gb = a.gb + o2, *Ac = a.Ac + o1, *Bc = a.Bc + o2;
     double *r = a.r + o1, *s = a.s + o2;
-    int *jst = a.jst + o1, *ist = a.ist + o2;
     if (!fw_valid(a, o1, n, o2, m, r1, r2)) {
       for (int i = threadIdx.x; i < n; i += kFwThreads) a.f[o1 + i] = NAN;
       for (int j = threadIdx.x; j < m; j += kFwThreads) a.g[o2 + j] = NAN;
@@ -221,9 +322,8 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
         const double w = be[j];
         lb.add(w > 0.0 ? log(w) - gb[j] / r2 : -INFINITY, 0.0);
       }
-      double LA, LB, dummy1, dummy2;
-      la.reduce(LA, dummy1, dummy2);
-      lb.reduce(LB, dummy1, dummy2);
+      double LA, LB, dummy1, dummy2, dummy3, dummy4;
+      lse3_reduce2(la, lb, LA, dummy1, dummy2, LB, dummy3, dummy4);
       const double lam = r1 * r2 / (r1 + r2) * (LA - LB);
       const double logmt = LA - lam / r1;  // log of the common tilted mass
       // normalised tilted histograms, then their CDFs
@@ -236,9 +336,11 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
         Bc[j] = w > 0.0 ? exp(log(w) - gb[j] / r2 - LB) : 0.0;
       }
       __syncthreads();
-      fw_scan(Ac, n);
-      fw_scan(Bc, m);
-      // co-ranks of the merge: start column of each row, start row of each column
+      fw_scan2(Ac, n, Bc, m);
+      // the walk of the monotone coupling by merge path (co-ranks of the merge: each thread
+      // takes a share of the diagonals); where row i + 1 starts at column j it writes the
+      // oracle's potential step r_{i+1} - r_i = C(i+1, j) - C(i, j), where column j + 1
+      // starts at row i, s_{j+1} - s_j = C(i, j+1) - C(i, j)
       {
         const int total = n + m;
         const int per = (total + kFwThreads - 1) / kFwThreads;
@@ -246,29 +348,26 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
         int ai = fw_corank(d0, Ac, n, Bc, m), bi = d0 - ai;
         for (int d = d0; d < d1; ++d) {
           if (ai < n && (bi >= m || Ac[ai] <= Bc[bi])) {
-            if (ai + 1 < n) jst[ai + 1] = min(bi, m - 1);
+            if (ai + 1 < n) {
+              const int j = min(bi, m - 1);
+              r[ai + 1] = cost1d(x[ai + 1], y[j], p) - cost1d(x[ai], y[j], p);
+            }
             ++ai;
           } else {
-            if (bi + 1 < m) ist[bi + 1] = min(ai, n - 1);
+            if (bi + 1 < m) {
+              const int i = min(ai, n - 1);
+              s[bi + 1] = cost1d(x[i], y[bi + 1], p) - cost1d(x[i], y[bi], p);
+            }
             ++bi;
           }
         }
+        if (threadIdx.x == 0) {
+          r[0] = 0.0;
+          s[0] = cost1d(x[0], y[0], p);
+        }
       }
       __syncthreads();
-      // potentials of the oracle: prefix sums of cost differences along the walk
-      for (int i = threadIdx.x; i < n; i += kFwThreads) {
-        if (i == 0) { r[0] = 0.0; continue; }
-        const int j = jst[i];
-        r[i] = cost1d(x[i], y[j], p) - cost1d(x[i - 1], y[j], p);
-      }
-      for (int j = threadIdx.x; j < m; j += kFwThreads) {
-        if (j == 0) { s[0] = cost1d(x[0], y[0], p); continue; }
-        const int i = ist[j];
-        s[j] = cost1d(x[i], y[j], p) - cost1d(x[i], y[j - 1], p);
-      }
-      __syncthreads();
-      fw_scan(r, n);
-      fw_scan(s, m);
+      fw_scan2(r, n, s, m);
       // Frank-Wolfe gap with the gradient pair (normalised histograms times the mass)
       double gp = 0.0;
       for (int i = threadIdx.x; i < n; i += kFwThreads)
@@ -295,8 +394,7 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
             pb.add(w > 0.0 ? log(w) - (gb[j] + gm * dl) / r2 : -INFINITY, -dl / r2);
           }
           double l0, a1, a2, m0, b1, b2;
-          pa.reduce(l0, a1, a2);
-          pb.reduce(m0, b1, b2);
+          lse3_reduce2(pa, pb, l0, a1, a2, m0, b1, b2);
           d1 = tau1 * a1 + tau2 * b1;
           d2 = tau1 * (a2 - a1 * a1) + tau2 * (b2 - b1 * b1);
         };
@@ -341,9 +439,8 @@ __global__ __launch_bounds__(kFwThreads) void k_fw1d(FwArgs a) {
       const double w = be[j];
       lb.add(w > 0.0 ? log(w) - gb[j] / r2 : -INFINITY, 0.0);
     }
-    double LA, LB, u1, u2;
-    la.reduce(LA, u1, u2);
-    lb.reduce(LB, u1, u2);
+    double LA, LB, u1, u2, u3, u4;
+    lse3_reduce2(la, lb, LA, u1, u2, LB, u3, u4);
     const double lam = r1 * r2 / (r1 + r2) * (LA - LB);
     bool finite = true;
     for (int i = threadIdx.x; i < n; i += kFwThreads) {
@@ -660,8 +757,6 @@ hipError_t launch_fw1d(const FwLaunch &l, hipStream_t s) {
   a.Bc = l.Bc;
   a.r = l.r;
   a.s = l.s;
-  a.jst = l.jst;
-  a.ist = l.ist;
   a.f = l.f;
   a.g = l.g;
   a.iters = l.iters;

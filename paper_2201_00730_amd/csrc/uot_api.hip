@@ -968,7 +968,7 @@ struct BatchLayout {
 
 // Workspace of uot_fw1d_batched: device offsets and the per-point scratch of the solver.
 struct FwLayout {
-  size_t offN = 0, offM = 0, fb = 0, gb = 0, Ac = 0, Bc = 0, r = 0, s = 0, jst = 0, ist = 0;
+  size_t offN = 0, offM = 0, fb = 0, gb = 0, Ac = 0, Bc = 0, r = 0, s = 0;
   size_t total = 0;
   int64_t totN = 0, totM = 0;
 };
@@ -995,11 +995,9 @@ uot_status fw_layout(int32_t B, const int64_t *offN, const int64_t *offM, FwLayo
   L.fb = take((size_t)L.totN * sizeof(double));
   L.Ac = take((size_t)L.totN * sizeof(double));
   L.r = take((size_t)L.totN * sizeof(double));
-  L.jst = take((size_t)L.totN * sizeof(int));
   L.gb = take((size_t)L.totM * sizeof(double));
   L.Bc = take((size_t)L.totM * sizeof(double));
   L.s = take((size_t)L.totM * sizeof(double));
-  L.ist = take((size_t)L.totM * sizeof(int));
   L.total = off;
   return UOT_OK;
 }
@@ -1054,8 +1052,6 @@ uot_status fw1d(int32_t B, const int64_t *offN, const int64_t *offM, const float
   l.Bc = at<double>(w.ptr, L.Bc);
   l.r = at<double>(w.ptr, L.r);
   l.s = at<double>(w.ptr, L.s);
-  l.jst = at<int>(w.ptr, L.jst);
-  l.ist = at<int>(w.ptr, L.ist);
   l.f = f;
   l.g = g;
   l.iters = iters;

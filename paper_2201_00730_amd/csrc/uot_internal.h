@@ -356,7 +356,7 @@ hipError_t launch_anderson(const AndersonArgs &a, hipStream_t s);
 size_t anderson_gram_bytes(int n);
 
 // 1-D Frank-Wolfe (kernels_fw.hip): problem b owns [offN[b], offN[b+1]) of x, alpha, f and
-// the double scratch fb, Ac, r, jst, and [offM[b], offM[b+1]) of y, beta, g, gb, Bc, s, ist.
+// the double scratch fb, Ac, r, and [offM[b], offM[b+1]) of y, beta, g, gb, Bc, s.
 struct FwLaunch {
   int B;
   const int64_t *offN, *offM;  // device [B + 1]
@@ -366,7 +366,6 @@ struct FwLaunch {
   int line_search, max_iter;
   double tol;
   double *fb, *gb, *Ac, *Bc, *r, *s;
-  int *jst, *ist;
   float *f, *g;
   int32_t *iters;
   double *gap;
