@@ -148,3 +148,20 @@ def test_barycenter_more_problems_than_cus():
         blo = lo - b * K + b
         bhi = blo + (hi - lo) - K + 1
         _check_problem(f[lo:hi], bx[blo:bhi], bw[blo:bhi], xs, ws, W[b], rho[b], 15, "b=%d" % b)
+
+
+def test_barycenter_sixteen_measures():
+    """K = 16, the largest number of measures per problem."""
+    K = 16
+    sizes = [20 + 3 * k for k in range(K)]
+    xs, ws = mixtures(K, sizes, seed=99)
+    w = np.linspace(1.0, 3.0, K)
+    w /= w.sum()
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    _say("barycenter K=16")
+    f, bx, bw, it, gap, st = uot.fw1d_barycenter(off, K, dev(np.concatenate(xs)),
+                                                 dev(np.concatenate(ws)), dev(w, np.float64), 0.8,
+                                                 max_iter=12)
+    assert int(st[0]) == 1 and int(it[0]) == 12
+    _check_problem(f.cpu().numpy().astype(np.float64), bx.cpu().numpy().astype(np.float64),
+                   bw.cpu().numpy().astype(np.float64), xs, ws, w, 0.8, 12, "K=16")

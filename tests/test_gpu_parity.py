@@ -109,6 +109,8 @@ CASES = [
     (129, 255, 8, 2.0, False),
     (300, 211, 16, 2.0, False),
     (97, 150, 20, 2.0, False),
+    (40, 70, 64, 2.0, False),   # the largest dimension (bucket 64)
+    (33, 45, 48, 1.5, False),
     (211, 300, 3, 1.5, False),
     (150, 97, 2, 1.0, False),
     (1, 5, 3, 1.5, True),
