@@ -726,11 +726,11 @@ hipError_t launch_fw_bary(const BaryLaunch &l, hipStream_t s) {
   a.gap = l.gap;
   a.status = l.status;
   const int grid = l.B < l.max_blocks ? l.B : l.max_blocks;
-  // Two blocks' worth of threads per problem when there are no more problems than CUs
-  // (max_blocks is twice the CU count): the walk's runs and the per-thread shares of the
-  // scans are half as long.
+  // 1024 threads (the whole CU; 66.5 KB of LDS with the cursor columns) per problem when
+  // there are no more problems than CUs (max_blocks is twice the CU count): the walk's runs
+  // are four times shorter and its memory waits spread over 16 waves.
   if (l.B <= l.max_blocks / 2)
-    hipLaunchKernelGGL(k_fw_bary<512>, dim3(grid > 0 ? grid : 1), dim3(512), 0, s, a);
+    hipLaunchKernelGGL(k_fw_bary<1024>, dim3(grid > 0 ? grid : 1), dim3(1024), 0, s, a);
   else
     hipLaunchKernelGGL(k_fw_bary<kFwThreads>, dim3(grid > 0 ? grid : 1), dim3(kFwThreads), 0, s, a);
   return hipGetLastError();
