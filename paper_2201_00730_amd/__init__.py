@@ -236,8 +236,8 @@ POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA_F32, POINTS_KERNEL_MF
 
 
 def set_points_kernel(variant: int) -> int:
-    """Select the p = 2 points-softmin implementation (0 auto, 1 VALU, 2 MFMA with one
-    32-target tile per wave, 3 MFMA with two); returns the previous setting."""
+    """Select the p = 2 points-softmin implementation (0 auto, 1 VALU, 2 matrix cores on
+    the float32 exponent, 3 matrix cores on its bf16 split); returns the previous setting."""
     prev = load_library().uot_set_points_kernel(int(variant))
     if prev < 0:
         raise ValueError("unknown points kernel variant %r" % (variant,))

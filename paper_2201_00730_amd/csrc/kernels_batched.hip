@@ -286,13 +286,15 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
   int last = 0;
   if (lane == 0) {
     parts[it.w] = BlockPart{mm, ms, dmx, dmn};
-    __threadfence();
+    // release only: an acquire here would invalidate this XCD's L2 (and the source records
+    // the other waves on it are reading) after every item
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const int nitems = pitem[p + 1] - pitem[p];
     last = (atomicAdd(&ticket[p], 1) == nitems - 1) ? 1 : 0;
   }
   last = __shfl(last, 0, 64);
   if (last) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other items' partials and records
     reduce_problem(a, p, g_step != 0);
     if (lane == 0) ticket[p] = 0;
   }
