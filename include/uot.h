@@ -72,8 +72,9 @@ typedef enum {
  *                          mean, whose float32 rounding is about
  *                          2^-24 (d + 4) (max|x - mu| + max|y - mu|)^2 per softmin in
  *                          potential units, whatever eps. Where the potentials are not
- *                          well above that (tiny eps with clouds of large spread), a stored
- *                          cost or p != 2 (direct differences) is more accurate.
+ *                          well above that (tiny eps with clouds of large spread), the
+ *                          direct-difference p = 2 softmin (uot_set_points_kernel(4)) or a
+ *                          stored cost is more accurate.
  * n (size of alpha, the "source" side) and m (size of beta) are >= 1.
  */
 typedef struct {
@@ -388,10 +389,12 @@ int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries);
  * Implementation of the squared-Euclidean (p = 2) points softmin, process-wide:
  * 0 = default (3 up to dimension 16, 2 above), 1 = vector ALU, 2 = matrix cores on the
  * float32 exponent, 3 = matrix cores on the exponent split into bf16 pieces (three per
- * float32 value, float32 accuracy; dimensions up to 16, 2 above). Returns the previous
- * setting, or -1 for an unknown value (then nothing changes). All compute the same softmin;
- * the switch exists for tests and benchmarks and must not be changed while calls are
- * running.
+ * float32 value, float32 accuracy; dimensions up to 16, 2 above); these evaluate the
+ * exponent in the expanded form (see the accuracy note at uot_cost). 4 = vector ALU on the
+ * differences x - y, as for p != 2: no expanded-form rounding, at a fraction of the speed
+ * (the solvers and uot_dual_value; plan products and the backward keep the expanded form).
+ * Returns the previous setting, or -1 for an unknown value (then nothing changes). All
+ * compute the same softmin; the switch must not be changed while calls are running.
  */
 int32_t uot_set_points_kernel(int32_t variant);
 

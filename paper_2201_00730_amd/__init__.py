@@ -233,11 +233,13 @@ def profile_read(kind: int):
 
 
 POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA_F32, POINTS_KERNEL_MFMA_BF16 = 0, 1, 2, 3
+POINTS_KERNEL_DIRECT = 4  # p = 2 through the differences x - y (no expanded-form rounding)
 
 
 def set_points_kernel(variant: int) -> int:
     """Select the p = 2 points-softmin implementation (0 auto, 1 VALU, 2 matrix cores on
-    the float32 exponent, 3 matrix cores on its bf16 split); returns the previous setting."""
+    the float32 exponent, 3 matrix cores on its bf16 split, 4 VALU on the differences x - y);
+    returns the previous setting."""
     prev = load_library().uot_set_points_kernel(int(variant))
     if prev < 0:
         raise ValueError("unknown points kernel variant %r" % (variant,))

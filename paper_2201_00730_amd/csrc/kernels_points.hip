@@ -29,8 +29,9 @@ __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_lo
 
 template <int MODE>
 __device__ __forceinline__ float cost_pow(float d2, float half_p) {
-  // ||x - y||^p from the squared distance: p = 1 takes a square root, otherwise
-  // 2^{(p/2) log2 d2} (d2 = 0 gives log2 = -inf and the power 0).
+  // ||x - y||^p from the squared distance: p = 2 is d2 itself, p = 1 takes a square root,
+  // otherwise 2^{(p/2) log2 d2} (d2 = 0 gives log2 = -inf and the power 0).
+  if (half_p == 1.0f) return d2;
   if (half_p == 0.5f) return __builtin_sqrtf(d2);
   return fast_exp2(half_p * fast_log2(d2));
 }
@@ -289,6 +290,7 @@ int g_points_variant = kPointsAuto;
 
 int points_record_mode(int mode, int d) {
   if (mode != kSqEuc) return mode;
+  if (g_points_variant == kPointsDirect) return kPower;
   const bool bf16 = g_points_variant == kPointsAuto || g_points_variant == kPointsMfmaBf16;
   return (bf16 && dim_bucket(d) <= kMxMaxDim) ? kSqEucMx : kSqEuc;
 }

@@ -184,10 +184,10 @@ Layout make_layout(const uot_cost *c, int which) {
   const int mode = rec_mode_of(c);
   const int d = c->kind == UOT_COST_POINTS ? c->d : 0;
   const int n = c->n, m = c->m;
-  // records sized for either p = 2 record form, so the size does not depend on the
+  // records sized for every p = 2 record form, so the size does not depend on the
   // points-kernel setting
   int stride = rec_stride_for(mode, d);
-  if (is_sq(mode) && dim_bucket(d) <= kMxMaxDim) {
+  if (mode_of(c) == kSqEuc && dim_bucket(d) <= kMxMaxDim) {
     const int a = rec_stride_for(kSqEuc, d), b = rec_stride_for(kSqEucMx, d);
     stride = a > b ? a : b;
   }
@@ -1442,7 +1442,7 @@ uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *b
 }
 
 int32_t uot_set_points_kernel(int32_t variant) {
-  if (variant < uot::kPointsAuto || variant > uot::kPointsMfmaBf16) return -1;
+  if (variant < uot::kPointsAuto || variant > uot::kPointsDirect) return -1;
   const int32_t prev = uot::g_points_variant;
   uot::g_points_variant = variant;
   return prev;

@@ -198,9 +198,10 @@ int points_blocks_per_cu(int mode, int d);
 bool points_uses_mfma(int mode, int d);
 // Points-softmin kernel selection (process-wide): matrix cores for p = 2 unless forced.
 // Auto: bf16-split matrix-core form up to dimension bucket kMxMaxDim, float32 matrix-core
-// form above it.
+// form above it. Direct: p = 2 on the vector ALU through the differences x - y (kPower
+// records and kernels with p = 2), free of the rounding of the expanded form.
 enum PointsVariant : int {
-  kPointsAuto = 0, kPointsValu = 1, kPointsMfmaF32 = 2, kPointsMfmaBf16 = 3
+  kPointsAuto = 0, kPointsValu = 1, kPointsMfmaF32 = 2, kPointsMfmaBf16 = 3, kPointsDirect = 4
 };
 extern int g_points_variant;
 // Record mode of a points cost of mode kSqEuc / kPower and dimension d under the current

@@ -107,6 +107,23 @@ def test_anderson_workspace_is_larger(lib):
     assert acc >= solve + 9 * 1000 * 4
 
 
+def test_points_kernel_switch_keeps_workspace_size(lib):
+    """Every p = 2 softmin variant (4: direct differences) fits the same workspace, so a
+    workspace sized under one setting serves the others."""
+    sizes = []
+    prev = uot.set_points_kernel(uot.POINTS_KERNEL_AUTO)
+    try:
+        for v in (0, 1, 2, 3, uot.POINTS_KERNEL_DIRECT):
+            assert uot.set_points_kernel(v) in (0, 1, 2, 3, 4)
+            sizes.append([lib.uot_workspace_bytes(ctypes.byref(_cost(n=1000, m=900, d=d)),
+                                                  uot.UOT_WS_SOLVE) for d in (1, 3, 16, 20)])
+        with pytest.raises(ValueError):
+            uot.set_points_kernel(5)
+    finally:
+        uot.set_points_kernel(prev)
+    assert all(s == sizes[0] for s in sizes), sizes
+
+
 def test_solver_rejects_bad_cost(lib):
     prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
     for bad in (_cost(n=0), _cost(d=100), _cost(p=0.0), _cost(kind=0, ldc=3)):

@@ -205,9 +205,15 @@ def solved():
     return pr, r
 
 
-@pytest.mark.parametrize("mode", ["points", "dense", "power"])
+@pytest.mark.parametrize("mode", ["points", "dense", "power", "direct"])
 def test_dual_value(solved, mode):
     pr, r = solved
+    if mode == "direct":  # p = 2 through the differences x - y
+        prev = uot.set_points_kernel(uot.POINTS_KERNEL_DIRECT)
+        try:
+            return test_dual_value(solved, "points")
+        finally:
+            uot.set_points_kernel(prev)
     prc = workloads.random_small(400, 333, d=3, seed=12, eps=0.05, rho1=0.8, rho2=1.6,
                                  p=1.5 if mode == "power" else 2.0, dense=(mode == "dense"))
     cost = oracle_cost(prc) if mode != "dense" else oracle.Cost(C=prc.C.astype(np.float64))
@@ -364,7 +370,7 @@ def test_points_kernels_agree(n, m, d):
     prev = uot.set_points_kernel(uot.POINTS_KERNEL_VALU)
     try:
         for variant, tol in ((uot.POINTS_KERNEL_VALU, bound), (uot.POINTS_KERNEL_MFMA_F32, TOL),
-                             (uot.POINTS_KERNEL_MFMA_BF16, TOL)):
+                             (uot.POINTS_KERNEL_MFMA_BF16, TOL), (uot.POINTS_KERNEL_DIRECT, TOL)):
             uot.set_points_kernel(variant)
             f, g, _ = run_gpu(pr, True, 15)
             assert rel_inf(f, r.f) < tol and rel_inf(g, r.g) < tol, (variant, rel_inf(f, r.f), tol)
@@ -420,3 +426,22 @@ def test_extreme_parameters(eps, rho1, rho2, ti, dense):
     assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
     for u, v in ((f, r.f), (g, r.g)):
         assert np.max(np.abs(u - v)) <= max(TOL * np.max(np.abs(v)), bound), (rel_inf(u, v), bound)
+
+
+@pytest.mark.parametrize("ti", [True, False])
+@pytest.mark.parametrize("eps,rho1,rho2", EXTREME)
+def test_extreme_parameters_direct(eps, rho1, rho2, ti):
+    """The direct-difference p = 2 softmin (POINTS_KERNEL_DIRECT) has no expanded-form
+    rounding: it meets 1e-5 on the problems where the expanded form needs its derived bound
+    (test_extreme_parameters)."""
+    pr = workloads.random_small(150, 97, d=2, seed=17, eps=eps, rho1=rho1, rho2=rho2, p=2.0)
+    _say("extreme, direct p = 2: eps=%g rho=(%g, %g) ti=%s" % (eps, rho1, rho2, ti))
+    prev = uot.set_points_kernel(uot.POINTS_KERNEL_DIRECT)
+    try:
+        f, g, _ = run_gpu(pr, ti, 30)
+    finally:
+        uot.set_points_kernel(prev)
+    r = run_oracle(pr, ti, 30)
+    _say("  rel f %.3g g %.3g" % (rel_inf(f, r.f), rel_inf(g, r.g)))
+    assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
+    assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL, (rel_inf(f, r.f), rel_inf(g, r.g))
