@@ -951,10 +951,16 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
 // Work items of the batched solver: chunks of 256 targets (one wave, four per lane) while
 // more than 128 targets remain, then chunks of at most 64 (one per lane); a chunk of 129..255
 // runs as one four-per-lane item (it costs no more than the two or three small items).
-int64_t batch_item_len(int64_t rem) { return rem >= 256 ? 256 : rem > 128 ? rem : rem < 64 ? rem : 64; }
-int64_t batch_items(int64_t n) {
+// The fine plan (items of at most 64 targets, one per lane) takes over once the running
+// problems give too few coarse items to fill the chip: more, shorter items then shorten the
+// critical path of each launch.
+int64_t batch_item_len(int64_t rem, bool fine = false) {
+  if (fine) return rem < 64 ? rem : 64;
+  return rem >= 256 ? 256 : rem > 128 ? rem : rem < 64 ? rem : 64;
+}
+int64_t batch_items(int64_t n, bool fine = false) {
   int64_t k = 0;
-  for (int64_t t0 = 0; t0 < n; t0 += batch_item_len(n - t0)) ++k;
+  for (int64_t t0 = 0; t0 < n; t0 += batch_item_len(n - t0, fine)) ++k;
   return k;
 }
 
@@ -962,7 +968,8 @@ struct BatchLayout {
   size_t state = 0, mu = 0, offN = 0, offM = 0, items_g = 0, items_f = 0, pitem_g = 0, pitem_f = 0;
   size_t act_g = 0, act_f = 0, ctrs = 0, part_g = 0, part_f = 0, tick_g = 0, tick_f = 0;
   size_t pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, total = 0;
-  int n_items_g = 0, n_items_f = 0;
+  size_t items_g2 = 0, items_f2 = 0, pitem_g2 = 0, pitem_f2 = 0;  // fine plan
+  int n_items_g = 0, n_items_f = 0, n_items_g2 = 0, n_items_f2 = 0;
   int64_t totN = 0, totM = 0;
 };
 
@@ -1152,17 +1159,21 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   if (offN == nullptr || offM == nullptr) return fail(UOT_ERR_INVALID, "offN/offM are NULL");
   if (d < 1 || d > kBatchMaxDim) return fail(UOT_ERR_INVALID, "batched d=%d not in [1, %d]", d, kBatchMaxDim);
   if (offN[0] != 0 || offM[0] != 0) return fail(UOT_ERR_INVALID, "offN[0] and offM[0] must be 0");
-  int64_t ig = 0, jf = 0;
+  int64_t ig = 0, jf = 0, ig2 = 0, jf2 = 0;
   for (int p = 0; p < B; ++p) {
     const int64_t n = offN[p + 1] - offN[p], m = offM[p + 1] - offM[p];
     if (n < 1 || m < 1) return fail(UOT_ERR_INVALID, "problem %d has n=%lld, m=%lld (must be >= 1)", p, (long long)n, (long long)m);
     if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_ERR_INVALID, "problem %d is too large", p);
     ig += batch_items(m);
     jf += batch_items(n);
+    ig2 += batch_items(m, true);
+    jf2 += batch_items(n, true);
   }
-  if (ig > (1 << 30) || jf > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
+  if (ig2 > (1 << 30) || jf2 > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
   L.n_items_g = (int)ig;
   L.n_items_f = (int)jf;
+  L.n_items_g2 = (int)ig2;  // the fine plan has at least as many items as the coarse one
+  L.n_items_f2 = (int)jf2;
   L.totN = offN[B];
   L.totM = offM[B];
   const int stride = batched_rec_stride(d);
@@ -1180,11 +1191,16 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   L.items_f = take((size_t)L.n_items_f * sizeof(int4));
   L.pitem_g = take((size_t)(B + 1) * sizeof(int));
   L.pitem_f = take((size_t)(B + 1) * sizeof(int));
-  L.act_g = take((size_t)L.n_items_g * sizeof(int));
-  L.act_f = take((size_t)L.n_items_f * sizeof(int));
+  L.items_g2 = take((size_t)L.n_items_g2 * sizeof(int4));
+  L.items_f2 = take((size_t)L.n_items_f2 * sizeof(int4));
+  L.pitem_g2 = take((size_t)(B + 1) * sizeof(int));
+  L.pitem_f2 = take((size_t)(B + 1) * sizeof(int));
+  // active lists and item partials serve either plan
+  L.act_g = take((size_t)L.n_items_g2 * sizeof(int));
+  L.act_f = take((size_t)L.n_items_f2 * sizeof(int));
   L.ctrs = take(8 * sizeof(int));
-  L.part_g = take((size_t)L.n_items_g * sizeof(BlockPart));
-  L.part_f = take((size_t)L.n_items_f * sizeof(BlockPart));
+  L.part_g = take((size_t)L.n_items_g2 * sizeof(BlockPart));
+  L.part_f = take((size_t)L.n_items_f2 * sizeof(BlockPart));
   L.tick_g = take((size_t)B * sizeof(int));
   L.tick_f = take((size_t)B * sizeof(int));
   L.pot_x = take((size_t)L.totN * sizeof(float));
@@ -1196,14 +1212,18 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
 }
 
 // Work items of one side: (problem, first target, count, item index), grouped by problem.
-void build_items(int32_t B, const int64_t *off, std::vector<int4> &items, std::vector<int> &pitem) {
+// Items in problem order (a problem's items are taken by neighbouring waves, which share its
+// source records in L2; ordering the table longest-first was measured slower on batch2d:
+// 2.30e12 against 2.63e12 updates/s); the slots of problem p are [pitem[p], pitem[p+1]).
+void build_items(int32_t B, const int64_t *off, std::vector<int4> &items, std::vector<int> &pitem,
+                 bool fine) {
   items.clear();
   pitem.assign((size_t)B + 1, 0);
   for (int p = 0; p < B; ++p) {
     pitem[p] = (int)items.size();
     const int64_t n = off[p + 1] - off[p];
     for (int64_t t0 = 0; t0 < n;) {
-      const int cnt = (int)batch_item_len(n - t0);
+      const int cnt = (int)batch_item_len(n - t0, fine);
       items.push_back(make_int4(p, (int)t0, cnt, (int)items.size()));
       t0 += cnt;
     }
@@ -1240,10 +1260,12 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  std::vector<int4> items_g, items_f;
-  std::vector<int> pitem_g, pitem_f;
-  build_items(B, offM, items_g, pitem_g);  // g-step targets: the y side
-  build_items(B, offN, items_f, pitem_f);  // f-step targets: the x side
+  std::vector<int4> items_g, items_f, items_g2, items_f2;
+  std::vector<int> pitem_g, pitem_f, pitem_g2, pitem_f2;
+  build_items(B, offM, items_g, pitem_g, false);  // g-step targets: the y side
+  build_items(B, offN, items_f, pitem_f, false);  // f-step targets: the x side
+  build_items(B, offM, items_g2, pitem_g2, true);
+  build_items(B, offN, items_f2, pitem_f2, true);
   char *ws = static_cast<char *>(w.ptr);
   UOT_HIP(hipMemcpyAsync(ws + L.offN, offN, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   UOT_HIP(hipMemcpyAsync(ws + L.offM, offM, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -1251,6 +1273,10 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   UOT_HIP(hipMemcpyAsync(ws + L.items_f, items_f.data(), items_f.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   UOT_HIP(hipMemcpyAsync(ws + L.pitem_g, pitem_g.data(), pitem_g.size() * sizeof(int), hipMemcpyHostToDevice, s));
   UOT_HIP(hipMemcpyAsync(ws + L.pitem_f, pitem_f.data(), pitem_f.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.items_g2, items_g2.data(), items_g2.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.items_f2, items_f2.data(), items_f2.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.pitem_g2, pitem_g2.data(), pitem_g2.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  UOT_HIP(hipMemcpyAsync(ws + L.pitem_f2, pitem_f2.data(), pitem_f2.size() * sizeof(int), hipMemcpyHostToDevice, s));
   UOT_HIP(hipStreamSynchronize(s));  // the host tables must outlive the copies
 
   BatchedArgs a;
@@ -1301,28 +1327,46 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   const int per_cu = batched_half_blocks_per_cu(a);
   const int blocks = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 4);
 
-  // One chunk of iterations (g and f half-steps) and the compaction, captured once.
+  // the fine plan: the same problems and buffers, other item tables
+  BatchedArgs a2 = a;
+  a2.items_g = at<int4>(w.ptr, L.items_g2);
+  a2.items_f = at<int4>(w.ptr, L.items_f2);
+  a2.pitem_g = at<int>(w.ptr, L.pitem_g2);
+  a2.pitem_f = at<int>(w.ptr, L.pitem_f2);
+  a2.n_items_g = L.n_items_g2;
+  a2.n_items_f = L.n_items_f2;
+
+  // One chunk of iterations (g and f half-steps) and the compaction, captured once per plan.
   const int chunk = tol > 0.0 ? check_every : (max_iter < 64 ? max_iter : 64);
-  GraphGuard gg;
-  UOT_HIP(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
-  UOT_HIP(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeRelaxed));
-  for (int i = 0; i < chunk; ++i) {
-    hipError_t e = launch_batched_half(a, 1, blocks, gg.cs);
-    if (e == hipSuccess) e = launch_batched_half(a, 0, blocks, gg.cs);
-    if (e != hipSuccess) {
-      hipGraph_t dead = nullptr;
-      (void)hipStreamEndCapture(gg.cs, &dead);
-      if (dead) (void)hipGraphDestroy(dead);
-      return fail(UOT_ERR_HIP, "batched launch during capture: %s", hipGetErrorString(e));
+  auto capture = [&](const BatchedArgs &pa, GraphGuard &gg) -> uot_status {
+    UOT_HIP(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+    UOT_HIP(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeRelaxed));
+    for (int i = 0; i < chunk; ++i) {
+      hipError_t e = launch_batched_half(pa, 1, blocks, gg.cs);
+      if (e == hipSuccess) e = launch_batched_half(pa, 0, blocks, gg.cs);
+      if (e != hipSuccess) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(gg.cs, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        return fail(UOT_ERR_HIP, "batched launch during capture: %s", hipGetErrorString(e));
+      }
     }
-  }
-  {
-    hipError_t e = launch_batched_compact(a, gg.cs);
+    hipError_t e = launch_batched_compact(pa, gg.cs);
     hipError_t e2 = hipStreamEndCapture(gg.cs, &gg.g);
     if (e != hipSuccess || e2 != hipSuccess)
       return fail(UOT_ERR_HIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
-  }
-  UOT_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+    UOT_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+    return UOT_OK;
+  };
+  GraphGuard gg, gg2;
+  UOT_TRY(capture(a, gg));
+  UOT_TRY(capture(a2, gg2));
+  // Switch to the fine plan (once) when the busier side has at most half as many coarse
+  // items as the launch has resident waves (4 per block): a fine item costs about 1.5x more
+  // per entry (one target per lane), so it pays only on a chip that is mostly idle (batch2d:
+  // 2.52e12 -> 2.63e12 updates/s switching at 1/2 or 1x the waves, 2.24e12 at 4x).
+  const int resident_waves = blocks * 4;
+  auto want_fine = [&](const int *c) { return 2 * (c[0] > c[1] ? c[0] : c[1]) <= resident_waves; };
 
   PinnedState pin;  // reused as two int slots for the running counts
   UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
@@ -1334,26 +1378,34 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     hipEvent_t *e;
     ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
   } evg{ev};
-  // problems still running right after initialisation
-  UOT_HIP(hipMemcpyAsync(run_h, a.running, sizeof(int), hipMemcpyDeviceToHost, s));
+  // counters right after initialisation: active coarse items (g, f) at [0], [1], problems
+  // still running at [4]
+  UOT_HIP(hipMemcpyAsync(run_h, ctrs, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
   UOT_HIP(hipStreamSynchronize(s));
   const int max_chunks = (max_iter + chunk - 1) / chunk;
-  int launched = 0;
-  if (run_h[0] > 0) {
+  bool fine = false;
+  if (run_h[4] > 0) {
+    if (want_fine(run_h)) {
+      UOT_HIP(launch_batched_compact(a2, s));
+      fine = true;
+    }
     for (int c = 0; c < max_chunks; ++c) {
-      UOT_HIP(hipGraphLaunch(gg.e, s));
-      ++launched;
-      UOT_HIP(hipMemcpyAsync(run_h + 16 * (c & 1), a.running, sizeof(int), hipMemcpyDeviceToHost, s));
+      UOT_HIP(hipGraphLaunch(fine ? gg2.e : gg.e, s));
+      UOT_HIP(hipMemcpyAsync(run_h + 16 * (c & 1), ctrs, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
       UOT_HIP(hipEventRecord(ev[c & 1], s));
       if (c >= 1) {
         UOT_HIP(hipEventSynchronize(ev[(c - 1) & 1]));
-        if (run_h[16 * ((c - 1) & 1)] == 0) break;
+        const int *cnt = run_h + 16 * ((c - 1) & 1);
+        if (cnt[4] == 0) break;
+        if (!fine && want_fine(cnt)) {  // after chunk c (queued): rebuild the active lists
+          UOT_HIP(launch_batched_compact(a2, s));
+          fine = true;
+        }
       }
     }
   }
   UOT_HIP(launch_batched_finalize(a, f, g, iters, status, s));
   UOT_HIP(hipStreamSynchronize(s));
-  (void)launched;
   return UOT_OK;
 }
 
