@@ -5,7 +5,7 @@
 // problem is one launch of k_batched_half: each wave repeatedly takes a work item (problem
 // p, a chunk of <= 256 targets of p) from a dynamic counter over the compacted list of active
 // items, computes the softmin of its targets over all sources of p (one target per lane for
-// items of <= 64 targets, four per lane above; sources uniform across the wave, read with
+// items of <= 64 targets, two up to 128, four above; sources uniform across the wave, read with
 // scalar loads, 8 at a time with one exp2 per entry), applies the KL prox and TI translation of App. B, writes the new potentials and
 // source records, and leaves its item partials (tilted mass log-sum-exp, potential-change
 // range). The last wave to finish an item of p (an atomic ticket, no waiting) reduces p's
@@ -146,7 +146,7 @@ __device__ __noinline__ void reduce_problem(const BatchedArgs &a, int p, bool g_
 }
 
 // One work item of a half-step: targets it.y .. it.y + it.z - 1 of problem p, lane l taking
-// targets it.y + l + 64 r for r < R (R = 1 for items of at most 64 targets, 4 above), so that
+// targets it.y + l + 64 r for r < R (R = 1, 2, 4 for items of at most 64, 128, 256 targets), so that
 // each source record read feeds R targets per lane. Softmin over all sources of p, epilogue,
 // item partials, and the problem's reduction by the last wave to finish one of its items.
 template <int D, int MODE, int R>
@@ -320,8 +320,10 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
     if (item >= nact) break;
     const int4 it = items[act[item]];  // (problem, first target, count, slot)
     if (a.state[it.x].done) continue;  // finished by an earlier half-step (compaction is periodic)
-    if (it.z > 64)
+    if (it.z > 128)
       batched_item<D, MODE, 4>(a, g_step, it);
+    else if (it.z > 64)
+      batched_item<D, MODE, 2>(a, g_step, it);
     else
       batched_item<D, MODE, 1>(a, g_step, it);
   }

@@ -951,11 +951,11 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
 // Work items of the batched solver: chunks of 256 targets (one wave, four per lane) while
 // more than 128 targets remain, then chunks of at most 64 (one per lane); a chunk of 129..255
 // runs as one four-per-lane item (it costs no more than the two or three small items).
-// The fine plan (items of at most 64 targets, one per lane) takes over once the running
+// The fine plan (items of at most 128 targets, two per lane) takes over once the running
 // problems give too few coarse items to fill the chip: more, shorter items then shorten the
 // critical path of each launch.
 int64_t batch_item_len(int64_t rem, bool fine = false) {
-  if (fine) return rem < 64 ? rem : 64;
+  if (fine) return rem < 128 ? rem : 128;
   return rem >= 256 ? 256 : rem > 128 ? rem : rem < 64 ? rem : 64;
 }
 int64_t batch_items(int64_t n, bool fine = false) {
@@ -1361,12 +1361,14 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   GraphGuard gg, gg2;
   UOT_TRY(capture(a, gg));
   UOT_TRY(capture(a2, gg2));
-  // Switch to the fine plan (once) when the busier side has at most half as many coarse
-  // items as the launch has resident waves (4 per block): a fine item costs about 1.5x more
-  // per entry (one target per lane), so it pays only on a chip that is mostly idle (batch2d:
-  // 2.52e12 -> 2.63e12 updates/s switching at 1/2 or 1x the waves, 2.24e12 at 4x).
+  // Switch to the fine plan (once) when the busier side has at most twice as many coarse
+  // items as the launch has resident waves (4 per block). A fine item (two targets per lane)
+  // costs more per entry than a coarse one (four), so it pays only once the long items of
+  // big problems, not the total work, bound a launch. batch2d, updates/s: coarse only
+  // 2.52e12; switching at 1/2, 2, 4, 8x the waves 2.63, 2.71, 2.71, 2.59e12 (one target per
+  // lane instead of two: 2.63e12 at 1/2 and 1x, 2.24e12 at 4x).
   const int resident_waves = blocks * 4;
-  auto want_fine = [&](const int *c) { return 2 * (c[0] > c[1] ? c[0] : c[1]) <= resident_waves; };
+  auto want_fine = [&](const int *c) { return (c[0] > c[1] ? c[0] : c[1]) <= 2 * resident_waves; };
 
   PinnedState pin;  // reused as two int slots for the running counts
   UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
