@@ -948,15 +948,15 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
 // ---------------------------------------------------------------------------------------
 // Batched TI Sinkhorn
 // ---------------------------------------------------------------------------------------
-// Work items of the batched solver: chunks of 256 targets (one wave, four per lane) while
-// more than 128 targets remain, then chunks of at most 64 (one per lane); a chunk of 129..255
-// runs as one four-per-lane item (it costs no more than the two or three small items).
+// Work items of the batched solver: chunks of 256 targets (one wave, four per lane), and the
+// remainder of a problem as one item (four, two or one targets per lane above 128, above 64,
+// up to 64; measured as fast as splitting a remainder of 65..128 into 64 + the rest).
 // The fine plan (items of at most 128 targets, two per lane) takes over once the running
 // problems give too few coarse items to fill the chip: more, shorter items then shorten the
 // critical path of each launch.
 int64_t batch_item_len(int64_t rem, bool fine = false) {
   if (fine) return rem < 128 ? rem : 128;
-  return rem >= 256 ? 256 : rem > 128 ? rem : rem < 64 ? rem : 64;
+  return rem >= 256 ? 256 : rem;
 }
 int64_t batch_items(int64_t n, bool fine = false) {
   int64_t k = 0;
