@@ -57,6 +57,10 @@ def _load():
             D = ctypes.c_double
             I = ctypes.c_int
             CP = ctypes.POINTER(_Cost)
+            lib.or_set_threads.argtypes = [I]
+            lib.or_set_threads.restype = None
+            lib.or_max_threads.argtypes = []
+            lib.or_max_threads.restype = I
             lib.or_smin_vec.argtypes = [I, P, P, D]
             lib.or_smin_vec.restype = D
             lib.or_smin_cols.argtypes = [CP, P, P, D, P]
@@ -90,9 +94,10 @@ def _load():
             lib.or_mm_dual.restype = D
             lib.or_fw_barycenter.argtypes = [I, P, P, P, P, D, I, D, P, P, P, P]
             lib.or_fw_barycenter.restype = I
-            lib.or_anderson_mix.argtypes = [I, I, P, D, P, P]
+            lib.or_anderson_mix.argtypes = [I, I, P, D, I, P, P]
             lib.or_anderson_mix.restype = I
-            lib.or_sinkhorn_anderson.argtypes = [CP, P, P, D, D, D, I, I, D, I, D, I, I, P, P, P, P, P]
+            lib.or_sinkhorn_anderson.argtypes = [CP, P, P, D, D, D, I, I, D, I, I, D, I, I, P, P, P,
+                                                 P, P]
             lib.or_sinkhorn_anderson.restype = I
             lib.or_plan_apply.argtypes = [CP, P, P, D, P, P, I, P, I, P]
             lib.or_dual_value.argtypes = [CP, P, P, D, D, D, P, P]
@@ -104,6 +109,14 @@ def _load():
             lib.or_gradients.argtypes = [CP, P, P, D, D, D, P, P, D, P, P, P, P]
             _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Run the oracle's OpenMP loops on n threads; returns the previous maximum."""
+    lib = _load()
+    prev = int(lib.or_max_threads())
+    lib.or_set_threads(int(n))
+    return prev
 
 
 def _f64(a) -> np.ndarray:
@@ -255,25 +268,27 @@ def sinkhorn(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: float, *, t
                           hist_g=None if hg is None else hg[:it].copy())
 
 
-def anderson_mix(X, r: float):
+def anderson_mix(X, r: float, normalize: bool = False):
     """Anderson extrapolation of the appendix on accelerating Sinkhorn: rows of X are the
     iterates x_0 .. x_K of a map (x_{k+1} = T(x_k)); the residuals x_{k+1} - x_k form U;
-    c = (G + rI)^{-1} 1 / (1^T (G + rI)^{-1} 1) with G = U^T U over its Frobenius norm;
-    returns (c, sum_k c_k x_{k+1})."""
+    c = (G + rI)^{-1} 1 / (1^T (G + rI)^{-1} 1) with G = U^T U (normalize=True: G divided
+    by its Frobenius norm first); returns (c, sum_k c_k x_{k+1})."""
     X = np.ascontiguousarray(_f64(X))
     K = X.shape[0] - 1
     c = np.empty(K)
     out = np.empty(X.shape[1])
-    if _load().or_anderson_mix(X.shape[1], K, _ptr(X), float(r), _ptr(c), _ptr(out)) != 0:
+    if _load().or_anderson_mix(X.shape[1], K, _ptr(X), float(r), int(bool(normalize)), _ptr(c),
+                               _ptr(out)) != 0:
         raise ValueError("singular Anderson system")
     return c, out
 
 
 def sinkhorn_anderson(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: float, *, ti: bool,
                       K: int, r: float, max_iter: int, tol: float = 0.0, check_every: int = 1,
-                      f0=None, history: bool = False) -> SinkhornResult:
+                      f0=None, history: bool = False, normalize: bool = False) -> SinkhornResult:
     """``sinkhorn`` with Anderson extrapolation of f (plain) or fb (TI) every K iterations
-    (see ``anderson_mix``); the change is +inf at the first iteration after an extrapolation."""
+    (see ``anderson_mix``, including ``normalize``); the change is +inf at the first
+    iteration after an extrapolation."""
     alpha, beta = _f64(alpha), _f64(beta)
     n, m = cost.n, cost.m
     if alpha.shape != (n,) or beta.shape != (m,):
@@ -286,7 +301,7 @@ def sinkhorn_anderson(cost: Cost, alpha, beta, eps: float, rho1: float, rho2: fl
     cs = cost._struct()
     it = _load().or_sinkhorn_anderson(ctypes.byref(cs), _ptr(alpha), _ptr(beta), float(eps),
                                       float(rho1), float(rho2), int(bool(ti)), int(K), float(r),
-                                      int(max_iter), float(tol), int(check_every),
+                                      int(bool(normalize)), int(max_iter), float(tol), int(check_every),
                                       int(f0 is not None), _ptr(f), _ptr(g), ctypes.byref(lam),
                                       ctypes.byref(last), _ptr(hd))
     if it < 0:

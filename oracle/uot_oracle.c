@@ -20,9 +20,14 @@
  * every sum (the nu_i = 0 convention of the Csiszar divergence, Sec. 1).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the OpenMP loops below (timing the oracle on one or all host cores). */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_max_threads(void) { return omp_get_max_threads(); }
 
 typedef struct {
   int n, m, d;          /* n source points (alpha), m target points (beta), point dimension */
@@ -232,13 +237,17 @@ int or_sinkhorn(const or_cost *k, const double *alpha, const double *beta, doubl
 /*
  * Anderson extrapolation (appendix "Combining Sinkhorn with Anderson acceleration").
  * X holds K + 1 iterates of a map T, row k = x_k (length n), with x_{k+1} = T(x_k). The
- * residuals u_k = x_{k+1} - x_k (k < K) form U = [u_0 .. u_{K-1}]. With G = U^T U divided by
- * its Frobenius norm (left as is when that norm is 0),
+ * residuals u_k = x_{k+1} - x_k (k < K) form U = [u_0 .. u_{K-1}]. With G = U^T U, the
+ * appendix's regularised closed form is
  *   c = (G + r I)^{-1} 1 / (1^T (G + r I)^{-1} 1),
- * and the extrapolated point is out = sum_k c_k x_{k+1}, the combination of the images
- * T(x_k). Writes c[K] and out[n]; returns 0, or -1 (c, out untouched) if G + r I is singular.
+ * the minimiser of c^T (G + r I) c over 1^T c = 1 (normalize = 0). normalize = 1 is a
+ * variant: G is first divided by its Frobenius norm (left as is when that norm is 0), so
+ * that r is relative to the scale of the residuals. The extrapolated point is
+ * out = sum_k c_k x_{k+1}, the combination of the images T(x_k). Writes c[K] and out[n];
+ * returns 0, or -1 (c, out untouched) if G + r I is singular.
  */
-int or_anderson_mix(int n, int K, const double *X, double r, double *c, double *out) {
+int or_anderson_mix(int n, int K, const double *X, double r, int normalize, double *c,
+                    double *out) {
   double G[16][16], z[16];
   if (K < 1 || K > 16) return -1;
   for (int a = 0; a < K; ++a)
@@ -256,7 +265,8 @@ int or_anderson_mix(int n, int K, const double *X, double r, double *c, double *
     for (int b = 0; b < K; ++b) fro += G[a][b] * G[a][b];
   fro = sqrt(fro);
   for (int a = 0; a < K; ++a) {
-    for (int b = 0; b < K; ++b) G[a][b] = fro > 0.0 ? G[a][b] / fro : G[a][b];
+    if (normalize && fro > 0.0)
+      for (int b = 0; b < K; ++b) G[a][b] /= fro;
     G[a][a] += r;
     z[a] = 1.0;
   }
@@ -298,13 +308,15 @@ int or_anderson_mix(int n, int K, const double *X, double r, double *c, double *
  * iterated variable x = f (plain) or fb (TI) is extrapolated every K iterations. From x_0,
  * K iterations give x_1 .. x_K; after iteration t with t % K == 0 (and t < max_iter, and
  * the stopping test not met) x is replaced by or_anderson_mix(x_0 .. x_K) and the next cycle
- * starts from it (its g-step recomputes g). The change delta_t is measured as in
+ * starts from it (its g-step recomputes g); normalize selects the form of the mix (see
+ * or_anderson_mix). The change delta_t is measured as in
  * or_sinkhorn, except that it is +inf at the first iteration after an extrapolation. K = 1
  * extrapolates to x_1 itself, i.e. reproduces or_sinkhorn's iterates. If the mix fails
  * (singular system) the cycle ends without extrapolation. Returns the iterations run.
  */
 int or_sinkhorn_anderson(const or_cost *k, const double *alpha, const double *beta, double eps,
-                         double rho1, double rho2, int ti, int K, double r, int max_iter,
+                         double rho1, double rho2, int ti, int K, double r, int normalize,
+                         int max_iter,
                          double tol, int check_every, int warm_start, double *f, double *g,
                          double *lambda_out, double *last_delta, double *hist_delta) {
   const int n = k->n, m = k->m;
@@ -345,7 +357,7 @@ int or_sinkhorn_anderson(const or_cost *k, const double *alpha, const double *be
     memcpy(go, gr, sizeof(double) * (size_t)m);
     if (tol > 0 && check_every > 0 && t % check_every == 0 && delta < tol) break;
     if (kc == K && t < max_iter) {
-      if (or_anderson_mix(n, K, X, r, c, xe) == 0) {
+      if (or_anderson_mix(n, K, X, r, normalize, c, xe) == 0) {
         memcpy(fb, xe, sizeof(double) * (size_t)n);
         fresh = 1;
       }

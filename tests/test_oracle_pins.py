@@ -453,16 +453,61 @@ def test_anderson_mix_two_step_closed_form():
     assert np.allclose(out, c0 * X[1] + (1.0 - c0) * X[2], rtol=0, atol=1e-12)
 
 
-def test_anderson_mix_is_scale_invariant():
-    # The Gram matrix is normalised before r is added, so the weights do not depend on the
-    # scale of the residuals (an affine map of the iterates maps the mix alike). Without the
-    # normalisation a fixed r = 1e-3 would turn the mix into an average as the residuals
-    # shrink.
+def test_anderson_mix_two_step_closed_form_regularised():
+    # The appendix's regularised weights for K = 2: with a = |u0|^2, b = u0.u1, d = |u1|^2,
+    # (G + rI)^{-1} 1 is proportional to (d + r - b, a + r - b) (2 x 2 inverse by cofactors),
+    # so c0 = (d + r - b) / (a + d + 2r - 2b). r is comparable to the Gram entries here, so a
+    # dropped or misplaced r (or a normalised Gram) moves c far beyond the tolerance.
+    rng = np.random.default_rng(11)
+    X = 0.01 * rng.standard_normal((3, 8))
+    u0, u1 = X[1] - X[0], X[2] - X[1]
+    a, b, d = u0 @ u0, u0 @ u1, u1 @ u1
+    r = 0.5 * (a + d)
+    c0 = (d + r - b) / (a + d + 2 * r - 2 * b)
+    c, out = oracle.anderson_mix(X, r)
+    assert np.allclose(c, [c0, 1.0 - c0], rtol=0, atol=1e-13)
+    assert np.allclose(out, c0 * X[1] + (1.0 - c0) * X[2], rtol=0, atol=1e-13)
+    cn, _ = oracle.anderson_mix(X, r, normalize=True)
+    assert np.max(np.abs(cn - c)) > 1e-3  # the variant is a different mix
+
+
+@pytest.mark.parametrize("normalize", [False, True])
+def test_anderson_weights_minimise_the_regularised_energy(normalize):
+    # c* minimises c^T (G + rI) c over 1^T c = 1 (the appendix's definition; G = U^T U, or
+    # U^T U / ||U^T U||_F for the variant): every feasible direction v (1^T v = 0) raises
+    # the energy, checked against an independent least-squares solve of the KKT system.
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((6, 30))
+    U = np.diff(X, axis=0).T
+    G = U.T @ U
+    if normalize:
+        G = G / np.linalg.norm(G)
+    r = 1e-2
+    K = G.shape[0]
+    kkt = np.block([[2 * (G + r * np.eye(K)), np.ones((K, 1))], [np.ones((1, K)), np.zeros((1, 1))]])
+    ref = np.linalg.lstsq(kkt, np.concatenate([np.zeros(K), [1.0]]), rcond=None)[0][:K]
+    c, _ = oracle.anderson_mix(X, r, normalize=normalize)
+    assert np.max(np.abs(c - ref)) < 1e-10
+    energy = lambda v: v @ (G + r * np.eye(K)) @ v
+    for _ in range(20):
+        v = rng.standard_normal(K)
+        v -= v.mean()
+        assert energy(c + 1e-3 * v) > energy(c)
+
+
+def test_anderson_printed_form_averages_small_residuals():
+    # With the appendix's form a fixed r dominates U^T U once the residuals are small
+    # against sqrt(r): the weights tend to the plain average 1/K. The normalised variant
+    # does not depend on the scale of the residuals (an affine map of the iterates maps the
+    # mix alike).
     rng = np.random.default_rng(10)
     X = rng.standard_normal((5, 40))
     a = rng.standard_normal(40)
-    c1, o1 = oracle.anderson_mix(X, 1e-3)
-    c2, o2 = oracle.anderson_mix(a + 1e-5 * (X - a), 1e-3)
+    small = a + 1e-6 * (X - a)
+    c_small, _ = oracle.anderson_mix(small, 1e-3)
+    assert np.max(np.abs(c_small - 0.25)) < 1e-6
+    c1, o1 = oracle.anderson_mix(X, 1e-3, normalize=True)
+    c2, o2 = oracle.anderson_mix(a + 1e-5 * (X - a), 1e-3, normalize=True)
     assert np.max(np.abs(c1 - c2)) < 1e-8
     assert np.max(np.abs(a + 1e-5 * (o1 - a) - o2)) < 1e-12
 
@@ -478,19 +523,30 @@ def test_anderson_k1_reproduces_sinkhorn(ti):
 
 
 @pytest.mark.parametrize("ti", [False, True])
-def test_anderson_reaches_the_fixed_point_faster(ti):
+@pytest.mark.parametrize("normalize", [False, True])
+def test_anderson_reaches_the_fixed_point(ti, normalize):
     # The F-potentials are unique, so the accelerated iteration must converge to the same
-    # (f*, g*); the appendix reports faster convergence for each Sinkhorn variant with
-    # K = 4, r = 1e-7.
+    # (f*, g*), with either form of the mix (K = 4, r = 1e-7, the appendix's setting). The
+    # appendix's form accelerates the first cycles; near the optimum its residuals fall
+    # below sqrt(r) and the weights become an average of K images, which lags behind the
+    # plain iteration (to 1e-12 here: 1540 against 1120 iterations plain, 390 against 280
+    # TI). The normalised variant keeps accelerating (less than half the iterations).
     pr = workloads.oned()
     cost = oracle_cost(pr)
     star = _solve(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, ti=True)
     kw = dict(ti=ti, max_iter=20000, tol=1e-12, check_every=10)
     acc = oracle.sinkhorn_anderson(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, K=4,
-                                   r=1e-7, **kw)
+                                   r=1e-7, normalize=normalize, **kw)
     std = oracle.sinkhorn(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, **kw)
     assert rel_inf(acc.f, star.f) < 1e-8 and rel_inf(acc.g, star.g) < 1e-8
-    assert acc.iters < std.iters / 2
+    if normalize:
+        assert acc.iters < std.iters / 2
+    else:
+        early = oracle.sinkhorn_anderson(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, ti=ti,
+                                         K=4, r=1e-7, max_iter=20)
+        plain20 = oracle.sinkhorn(cost, pr.alpha, pr.beta, pr.eps, pr.rho1, pr.rho2, ti=ti,
+                                  max_iter=20)
+        assert np.max(np.abs(early.f - star.f)) < 0.5 * np.max(np.abs(plain20.f - star.f))
 
 
 # ---------------------------------------------------------------------------------------
@@ -712,6 +768,61 @@ def test_mot_three_marginals_is_an_optimal_primal_dual_pair():
     assert abs(f @ A - cost) <= 1e-13
     assert len(bx) == sum(Ns) - 3 + 1 and abs(bm.sum() - 1.0) < 1e-14
     assert np.all(np.diff(bx) >= -1e-15)  # the monotone walk visits tuples in order
+    # the returned barycenter is the image of the LP's optimal plan under the barycentric
+    # map: the same measure (compared through its quantile function)
+    px = np.array([bar(t) for t in tuples])
+    u = _mid_levels([np.cumsum(bm), np.cumsum(lp.x[np.argsort(px, kind="stable")])])
+    assert np.max(np.abs(_quantile(bx, bm, u) - _quantile(px, lp.x, u))) < 1e-12
+
+
+def _quantile(x, m, u):
+    """Quantile function of the discrete measure sum_i m_i delta_{x_i} (sum m = 1) at levels
+    u in (0, 1): the smallest support point whose cumulative mass reaches u."""
+    order = np.argsort(x, kind="stable")
+    xs, cs = np.asarray(x)[order], np.cumsum(np.asarray(m)[order])
+    return xs[np.minimum(np.searchsorted(cs, u, side="left"), len(xs) - 1)]
+
+
+def _mid_levels(cumsums):
+    """Midpoints between the distinct cumulative-mass levels of several measures (levels
+    closer than 1e-12 merged), where every quantile function is away from its jumps."""
+    lv = np.unique(np.concatenate([[0.0, 1.0]] + [np.clip(c, 0.0, 1.0) for c in cumsums]))
+    lv = lv[np.concatenate([[True], np.diff(lv) > 1e-12])]
+    return 0.5 * (lv[1:] + lv[:-1])
+
+
+@pytest.mark.parametrize("Ns,iters", [([5, 9, 7], 1), ([5, 9, 7], 40), ([12, 3, 8, 6], 25),
+                                      ([1, 6], 10)])
+def test_barycenter_output_is_the_quantile_average(Ns, iters):
+    # On the line, the barycenter for the cost sum_k w_k (z_k - b)^2 of K probability
+    # measures has the quantile function sum_k w_k Q_k / sum_k w_k (the comonotone coupling
+    # is optimal and the barycentric map acts on it level by level), a closed form that
+    # does not use the multi-marginal walk. The solver returns the barycenter of its final
+    # tilted marginals a_k e^{-f_k / (w_k rho)} (f the reported potentials): their masses
+    # are equal (the optimal translation of Sec. 5), the barycenter carries that mass, its
+    # normalised quantile function is the weighted average of theirs, and so its mean is
+    # the weighted mean of their means.
+    rng = np.random.default_rng(sum(Ns) + iters)
+    K = len(Ns)
+    xs = [np.sort(rng.normal(rng.uniform(-1, 1), rng.uniform(0.1, 0.5), k)) for k in Ns]
+    As = [rng.uniform(0.2, 1.0, k) * rng.uniform(0.5, 2.0) / k for k in Ns]
+    w = rng.uniform(0.2, 1.0, K)
+    rho = 0.6
+    off = np.concatenate([[0], np.cumsum(Ns)])
+    res = oracle.fw_barycenter(off, np.concatenate(xs), np.concatenate(As), w, rho,
+                               max_iter=iters)
+    tilted = [As[k] * np.exp(-res.f[off[k]:off[k + 1]] / (w[k] * rho)) for k in range(K)]
+    q = np.array([t.sum() for t in tilted])
+    assert np.max(np.abs(q - q[0])) < 1e-12 * q[0]
+    bm = res.bary_m
+    assert len(res.bary_x) == off[-1] - K + 1 and np.all(bm >= 0)
+    assert abs(bm.sum() - q[0]) < 1e-12 * q[0]
+    probs = [t / t.sum() for t in tilted]
+    u = _mid_levels([np.cumsum(p) for p in probs] + [np.cumsum(bm) / bm.sum()])
+    avg = sum(w[k] * _quantile(xs[k], probs[k], u) for k in range(K)) / w.sum()
+    assert np.max(np.abs(_quantile(res.bary_x, bm / bm.sum(), u) - avg)) < 1e-12
+    mean = sum(w[k] * probs[k] @ xs[k] for k in range(K)) / w.sum()
+    assert abs(res.bary_x @ bm / bm.sum() - mean) < 1e-12
 
 
 def test_mm_lambda_maximises_the_translated_dual():
