@@ -190,7 +190,8 @@ def extra_workload(args, uot, torch, np, workloads):
     highdim16 N=M=50,000, D=16: TI forward to change < 1e-6, then the envelope backward.
     anderson  the benchmark's 3-D clouds and six (eps, rho): time and iterations to change
               < 1e-6 of TI and plain Sinkhorn with and without Anderson extrapolation
-              (K = 4, r = 1e-7).
+              (K = 4, r = 1e-7), with the appendix's mix and with the Gram matrix
+              normalised; and the iterations on the 1-D measures of Sec. 3.
     phi       the same clouds at eps = 0.01, rho in {0.1, 1, 10}: time and iterations to change
               < 1e-6 of F- and G-Sinkhorn with the KL and the Berg entropy.
     fw1d      1-D Frank-Wolfe for unregularised UOT: the sorted 1-D measures N=M=200, rho=1,
@@ -273,11 +274,38 @@ def extra_workload(args, uot, torch, np, workloads):
         M = np.diff(bt.offM).astype(np.float64)
         ups = float((2.0 * N * M * it).sum())
         hist = np.percentile(it, [0, 50, 90, 99, 100]).tolist()
+        edges = [0, 20, 50, 100, 200, 500, 1000, 2000, 5000, 100000]
+        counts, _ = np.histogram(it, bins=edges)
+        # a second, traced run: per-chunk load statistics (two clock reads per work item)
+        uot.batched_trace(True)
+        try:
+            _, dt_tr = _timed(torch, run)
+            tr = uot.batched_trace_read()
+        finally:
+            uot.batched_trace(False)
+        ticks, busy, waves = tr["ticks"][1:], tr["busy_ticks"][1:], tr["resident_waves"][1:]
+        util = np.where(ticks > 0, busy / np.maximum(ticks * waves, 1.0), 0.0)
+        load = {"wave_slot_utilisation": float(busy.sum() / max((ticks * waves).sum(), 1.0)),
+                "time_fraction_at_least_90pct_busy": float(ticks[util >= 0.9].sum() / max(ticks.sum(), 1.0)),
+                "time_fraction_under_50pct_busy": float(ticks[util < 0.5].sum() / max(ticks.sum(), 1.0)),
+                "chunks": int(len(ticks)), "resident_waves": int(waves[0]) if len(waves) else None,
+                "traced_seconds": dt_tr,
+                "running_at_chunk": {str(int(c)): int(r) for c, r in
+                                     zip(tr["chunk"], tr["running"]) if int(c) in
+                                     (0, 1, 2, 5, 10, 20, 50, 100)},
+                "seconds_by_running": {}}
+        for lo, hi in ((1025, 1 << 30), (257, 1024), (33, 256), (1, 32)):
+            sel = (tr["running"][1:] >= lo) & (tr["running"][1:] <= hi)
+            load["seconds_by_running"]["%d-%d" % (lo, min(hi, bt.B))] = \
+                float(ticks[sel].sum() / max(ticks.sum(), 1.0) * dt_tr)
         out.update({"metric": "C-entry softmin updates/s", "unit": "C-entry softmin updates/s",
                     "value": ups / dt, "seconds": dt,
                     "config": {"workload": "4096 problems, N_p,M_p ~ U{64..4096}, D=2, "
                                            "eps log-U[1e-3,1e-1], rho log-U[0.1,10], TI to 1e-6"},
                     "iterations_percentiles_0_50_90_99_100": hist,
+                    "iterations_histogram": {"%d-%d" % (edges[i], edges[i + 1] - 1): int(counts[i])
+                                             for i in range(len(counts)) if counts[i]},
+                    "load": load,
                     "status_counts": {str(k): int(v) for k, v in
                                       zip(*np.unique(status.cpu().numpy(), return_counts=True))},
                     "roofline": {"bound": "alu", "achieved": ups / dt / 1e9,
@@ -286,7 +314,20 @@ def extra_workload(args, uot, torch, np, workloads):
                                  "kernel": "k_batched_half (whole solve wall time, not per launch)"}})
     elif args.workload == "anderson":
         res = {}
-        total = {"ti": 0.0, "ti_anderson": 0.0, "plain": 0.0, "plain_anderson": 0.0}
+        total = {"ti": 0.0, "ti_anderson": 0.0, "ti_anderson_normalised": 0.0, "plain": 0.0,
+                 "plain_anderson": 0.0, "plain_anderson_normalised": 0.0}
+        acc = dict(K=4, r=1e-7)
+        accn = dict(K=4, r=1e-7, normalize=True)
+        variants = (("ti", uot.ti_sinkhorn, {}), ("ti_anderson", uot.ti_sinkhorn_anderson, acc),
+                    ("ti_anderson_normalised", uot.ti_sinkhorn_anderson, accn),
+                    ("plain", uot.sinkhorn, {}), ("plain_anderson", uot.sinkhorn_anderson, acc),
+                    ("plain_anderson_normalised", uot.sinkhorn_anderson, accn))
+        pr1 = workloads.oned()
+        kw1 = dict(x=t(pr1.x), y=t(pr1.y), p=2.0, eps=pr1.eps, rho1=pr1.rho1, rho2=pr1.rho2,
+                   max_iter=MAX_ITER, tol=TOL, check_every=CHECK_EVERY)
+        oned_iters = {name: fn(t(pr1.alpha), t(pr1.beta), **kw1, **extra)[2].iters
+                      for name, fn, extra in variants}
+        print("anderson oned iterations %s" % oned_iters, file=sys.stderr, flush=True)
         for eps in (1e-1, 1e-2):
             for rho in (0.1, 1.0, 10.0):
                 pr = workloads.cloud3d(n=args.n, m=args.n, eps=eps, rho=rho)
@@ -299,10 +340,7 @@ def extra_workload(args, uot, torch, np, workloads):
                         fn(a, b, **dict(kw, max_iter=5))
                     for fn in (uot.ti_sinkhorn_anderson, uot.sinkhorn_anderson):
                         fn(a, b, K=4, r=1e-7, **dict(kw, max_iter=5))
-                for name, fn, extra in (("ti", uot.ti_sinkhorn, {}),
-                                        ("ti_anderson", uot.ti_sinkhorn_anderson, dict(K=4, r=1e-7)),
-                                        ("plain", uot.sinkhorn, {}),
-                                        ("plain_anderson", uot.sinkhorn_anderson, dict(K=4, r=1e-7))):
+                for name, fn, extra in variants:
                     (_, _, info), dt = _timed(torch, lambda: fn(a, b, **kw, **extra))
                     row[name] = {"iters": info.iters, "seconds": round(dt, 5),
                                  "converged": info.converged}
@@ -312,6 +350,7 @@ def extra_workload(args, uot, torch, np, workloads):
         out.update({"metric": "seconds to change < 1e-6, TI with Anderson extrapolation, summed "
                               "over six (eps, rho)", "unit": "s", "higher_is_better": False,
                     "value": total["ti_anderson"], "totals_seconds": total,
+                    "oned_iterations_to_tol": oned_iters,
                     "config": {"workload": "3-D clouds N=M=%d, eps in {0.1,0.01} x rho in "
                                            "{0.1,1,10}, K=4, r=1e-7, change checked every %d"
                                            % (args.n, CHECK_EVERY)},
@@ -420,7 +459,16 @@ def extra_workload(args, uot, torch, np, workloads):
             a, b, max_iter=MAX_ITER, tol=TOL, check_every=CHECK_EVERY, **kw))
         uot.profile_enable(False)
         n, ms, ent = _profiled(uot, (uot.PROFILE_POINTS,))
+        uot.backward(a, b, f, g, **kw)  # warm
+        uot.profile_reset()
+        uot.profile_enable(True, period=1)
         _, dtb = _timed(torch, lambda: uot.backward(a, b, f, g, **kw))
+        uot.profile_enable(False)
+        nb, msb, entb = _profiled(uot, (uot.PROFILE_GRAD,))
+        # backward work per entry (one pass per side, p = 2): D differences and D FMAs for the
+        # squared distance, one FMA for the exponent, one exp2, one add for the row sum and D
+        # FMAs for the gradient accumulators: 5 D + 3 flops (an FMA counts 2) and one exp
+        flops_b = (5 * pr.d + 3) * entb / (msb * 1e-3) if msb > 0 else 0.0
         ach = ent / (ms * 1e-3) if ms > 0 else 0.0
         out.update({"metric": "C-entry softmin updates/s", "unit": "C-entry softmin updates/s",
                     "value": 2.0 * pr.n * pr.m * info.iters / dt,
@@ -428,6 +476,14 @@ def extra_workload(args, uot, torch, np, workloads):
                                            "then the envelope backward"},
                     "iters": info.iters, "converged": info.converged, "forward_seconds": dt,
                     "backward_seconds": dtb,
+                    "backward_roofline": {
+                        "bound": "alu", "achieved": flops_b / 1e12, "peak": 157.3,
+                        "unit": "TFLOP/s", "frac": flops_b / 157.3e12, "traffic": None,
+                        "kernel": "k_grad_partial<16,2,true> (5D+3 flop + 1 exp2 per entry, "
+                                  "both sides)",
+                        "launches": nb, "avg_launch_ms": msb / nb if nb else None,
+                        "exp_per_s": entb / (msb * 1e-3) if msb > 0 else None,
+                        "exp_frac": entb / (msb * 1e-3) / PEAK_EXP_PER_S if msb > 0 else None},
                     "roofline": {"bound": "alu", "achieved": ach / 1e9, "peak": PEAK_EXP_PER_S / 1e9,
                                  "unit": "Gexp/s", "frac": ach / PEAK_EXP_PER_S, "traffic": None,
                                  "kernel": "k_points_mfma<16,Bf16Form<16>>", "launches": n,
@@ -436,23 +492,36 @@ def extra_workload(args, uot, torch, np, workloads):
 
 
 def cpu_baseline(pr, seconds):
-    """FP64 oracle TI Sinkhorn on the same inputs for a bounded number of iterations."""
+    """FP64 oracle TI Sinkhorn on the same inputs for a bounded number of iterations, on all
+    the host cores the process may use (OpenMP) and on one core."""
     import numpy as np
     import oracle
     cost = oracle.Cost(x=pr.x.astype(np.float64), y=pr.y.astype(np.float64), p=2.0)
     a, b = pr.alpha.astype(np.float64), pr.beta.astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.sinkhorn(cost, a, b, 1e-2, 1.0, 1.0, ti=True, max_iter=1)
-    t1 = time.perf_counter() - t0
-    iters = max(1, int(seconds / max(t1, 1e-3)))
-    t0 = time.perf_counter()
-    oracle.sinkhorn(cost, a, b, 1e-2, 1.0, 1.0, ti=True, max_iter=iters)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def timed(budget, threads):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.sinkhorn(cost, a, b, 1e-2, 1.0, 1.0, ti=True, max_iter=1)
+        t1 = time.perf_counter() - t0
+        iters = max(1, int(budget / max(t1, 1e-3)))
+        t0 = time.perf_counter()
+        oracle.sinkhorn(cost, a, b, 1e-2, 1.0, 1.0, ti=True, max_iter=iters)
+        return iters, time.perf_counter() - t0
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)) or 1))
+    prev = oracle.set_threads(cores)
+    try:
+        iters, dt = timed(seconds, cores)
+        iters1, dt1 = timed(max(2.0, seconds / 3.0), 1)
+    finally:
+        oracle.set_threads(prev)
     return {"value": 2.0 * pr.n * pr.m * iters / dt, "unit": "C-entry softmin updates/s",
             "cores": cores, "kind": "oracle",
-            "sample": "FP64 C oracle (OpenMP), TI Sinkhorn on the same 3-D clouds N=M=%d, "
-                      "eps=1e-2 rho=1, %d iterations from f=0, %.1f s" % (pr.n, iters, dt)}
+            "sample": "FP64 C oracle (OpenMP, %d threads), TI Sinkhorn on the same 3-D clouds "
+                      "N=M=%d, eps=1e-2 rho=1, %d iterations from f=0, %.1f s" % (cores, pr.n, iters, dt),
+            "single_core": {"value": 2.0 * pr.n * pr.m * iters1 / dt1, "cores": 1,
+                            "sample": "the same, one thread, %d iterations, %.1f s" % (iters1, dt1)}}
 
 
 PROFILE_PERIOD = 15

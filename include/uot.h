@@ -158,8 +158,9 @@ uot_status uot_ti_sinkhorn(const uot_cost *cost, const float *alpha, const float
 
 /* Anderson extrapolation settings (see uot_sinkhorn_anderson). */
 typedef struct {
-  int32_t k;  /* iterations per extrapolation = residuals in the mix, 2 <= k <= 8              */
-  double r;   /* regularisation added to the normalised Gram matrix, finite and > 0           */
+  int32_t k;          /* iterations per extrapolation = residuals in the mix, 2 <= k <= 8     */
+  double r;           /* regularisation added to the Gram matrix, finite and > 0             */
+  int32_t normalize;  /* 0: the appendix's form, G = U^T U; 1: G = U^T U / ||U^T U||_F       */
 } uot_anderson;
 
 /*
@@ -167,15 +168,20 @@ typedef struct {
  * combining Sinkhorn with Anderson acceleration). The iterated variable x is f for plain
  * Sinkhorn and fb for TI; one iteration T maps x to the next x through a g-step and an
  * f-step as in uot_sinkhorn / uot_ti_sinkhorn. From x_0, k iterations give x_1 .. x_k, the
- * residuals u_i = x_{i+1} - x_i form U, and, with G = U^T U divided by its Frobenius norm,
+ * residuals u_i = x_{i+1} - x_i form U, and, with G = U^T U,
  *   c = (G + r I)^{-1} 1 / (1^T (G + r I)^{-1} 1),   x <- sum_i c_i x_{i+1},
  * after which the next k iterations start from the extrapolated x. No extrapolation
  * follows the last iteration (max_iter), and the change of the first iteration after an
  * extrapolation is +inf, so the stopping test always compares two plain iterates. The
- * paper's experiment uses k = 4, r = 1e-7.
+ * paper's experiment uses k = 4, r = 1e-7. With acc->normalize = 1, G is divided by its
+ * Frobenius norm before r is added, which makes r relative to the residuals: with the
+ * appendix's form a fixed r turns the weights into a plain average once the residuals are
+ * small against sqrt(r), so the extrapolation stops helping near the optimum (on the 1-D
+ * measures of Sec. 3 with k = 4, r = 1e-7: TI 110 iterations to a change below 1e-6 with
+ * the appendix's form, as many as without extrapolation, against 20 normalised).
  * Arguments and conventions as uot_sinkhorn (params.warm_start gives x_0 = f for plain
- * Sinkhorn and fb = f for TI); acc (host) holds k and r, and k outside 2..8 or r not finite
- * and > 0 give UOT_ERR_INVALID. The workspace is UOT_WS_ANDERSON's (the iterates of one
+ * Sinkhorn and fb = f for TI); acc (host) holds k, r and normalize, and k outside 2..8, r
+ * not finite and > 0, or normalize not 0 or 1 give UOT_ERR_INVALID. The workspace is UOT_WS_ANDERSON's (the iterates of one
  * cycle, k + 1 vectors of n floats, beside the solver's own). A Gram system that cannot be
  * solved (non-finite entries) ends the solve with UOT_ERR_NUMERIC.
  */
@@ -369,12 +375,38 @@ size_t uot_fw1d_barycenter_workspace_bytes(int32_t B, int32_t K, const int64_t *
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d);
 
 /*
+ * Work-item plan of uot_ti_sinkhorn_batched, process-wide (for tests and benchmarks; results
+ * do not depend on it): 0 = automatic (coarse items of up to 256 targets, four per lane,
+ * then fine items of up to 128 targets, two per lane, once few coarse items remain), 1 = coarse
+ * items throughout, 2 = fine items throughout, 3 = coarse for the first chunk of iterations,
+ * fine after it. Returns the previous setting, or -1 for an unknown value (nothing changes).
+ * Must not be changed while a batched solve runs.
+ */
+int32_t uot_batched_set_plan(int32_t plan);
+
+/*
+ * Load statistics of uot_ti_sinkhorn_batched, process-wide (for benchmarks): while enabled,
+ * each solve records one row per chunk of iterations (and one for the start), kept until the
+ * next solve; uot_batched_trace_read copies up to max_rows rows of 9 doubles (host memory)
+ * and returns the number of rows of the last solve:
+ *   chunk index, fine plan (0/1), problems running, active work items of the g- and f-steps,
+ *   sum of N_p M_p over the running problems, wave time on work items during the chunk and
+ *   the chunk's duration (both in ticks of the GPU's constant-rate clock, s_memrealtime), and
+ *   the waves resident in one launch. busy / (duration x resident waves) is the fraction of
+ *   the chip's wave slots that did work. The counters cost two clock reads per work item.
+ */
+void uot_batched_trace_enable(int32_t on);
+int32_t uot_batched_trace_read(double *rows, int32_t max_rows);
+
+/*
  * Kernel timing, for benchmarks (off by default). uot_profile_enable(period): 0 disables;
  * period >= 1 times every period-th softmin launch of uot_sinkhorn / uot_ti_sinkhorn
  * (counted process-wide) with start/stop HIP events attached to the kernel dispatch itself
  * (hipExtLaunchKernel: no extra commands in the stream), and accumulates its duration, with
  * the number of cost entries it processed, per kernel kind: 0 = points-cost softmin,
- * 1 = stored-cost column softmin, 2 = stored-cost row softmin. Reading the events back
+ * 1 = stored-cost column softmin, 2 = stored-cost row softmin, 3 = the one-pass kernel of
+ * uot_backward and of the marginals of uot_plan_apply (points costs; its launches count
+ * towards the same period). Reading the events back
  * synchronises with the timed launches when the event ring (512 pairs) wraps, so a period
  * above 1 keeps a long solve asynchronous (an odd period samples both half-steps).
  * Thread-safe (a mutex guards the counters).

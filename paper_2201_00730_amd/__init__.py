@@ -23,7 +23,8 @@ __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_ap
            "backward", "workspace_bytes", "UOTLoss", "uot_loss", "library_path", "load_library",
            "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
            "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
-           "fw1d_batched", "fw1d", "fw1d_barycenter"]
+           "fw1d_batched", "fw1d", "fw1d_barycenter", "batched_set_plan",
+           "batched_trace", "batched_trace_read"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -53,7 +54,7 @@ class _Params(ctypes.Structure):
 
 
 class _Anderson(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_int32), ("r", ctypes.c_double)]
+    _fields_ = [("k", ctypes.c_int32), ("r", ctypes.c_double), ("normalize", ctypes.c_int32)]
 
 
 class _Phi(ctypes.Structure):
@@ -133,6 +134,12 @@ def load_library():
     lib.uot_fw1d_workspace_bytes.restype = S
     lib.uot_batched_workspace_bytes.argtypes = [I32, P, P, I32]
     lib.uot_batched_workspace_bytes.restype = S
+    lib.uot_batched_set_plan.argtypes = [I32]
+    lib.uot_batched_set_plan.restype = I32
+    lib.uot_batched_trace_enable.argtypes = [I32]
+    lib.uot_batched_trace_enable.restype = None
+    lib.uot_batched_trace_read.argtypes = [P, I32]
+    lib.uot_batched_trace_read.restype = I32
     _lib = lib
     return lib
 
@@ -212,7 +219,7 @@ class _CostRef:
         return self.keep[0].device
 
 
-PROFILE_POINTS, PROFILE_DENSE_COLS, PROFILE_DENSE_ROWS = 0, 1, 2
+PROFILE_POINTS, PROFILE_DENSE_COLS, PROFILE_DENSE_ROWS, PROFILE_GRAD = 0, 1, 2, 3
 
 
 def profile_enable(on=True, period: int = 1):
@@ -280,7 +287,8 @@ def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, ep
     info = _Info()
     args = [ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), ctypes.byref(prm)]
     if anderson is not None:
-        args.append(ctypes.byref(_Anderson(int(anderson[0]), float(anderson[1]))))
+        args.append(ctypes.byref(_Anderson(int(anderson[0]), float(anderson[1]),
+                                           int(bool(anderson[2])))))
     if phi is not None:
         args.append(ctypes.byref(_Phi(int(phi[0]), int(phi[1]))))
     st = getattr(lib, name)(*args, _ptr(f), _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(info),
@@ -315,17 +323,20 @@ def sinkhorn_phi(alpha, beta, *, entropy: str = "kl", variant: str = "F", **kw):
     return _solve("uot_sinkhorn_phi", alpha, beta, phi=(ENTROPIES[entropy], VARIANTS[variant]), **kw)
 
 
-def sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, **kw):
+def sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, normalize: bool = False, **kw):
     """Plain Sinkhorn with Anderson extrapolation of f every K iterations (appendix on
-    Anderson acceleration; the paper's experiment uses K = 4, r = 1e-7). Other keyword
-    args as ``sinkhorn``. Returns (f, g, Info)."""
-    return _solve("uot_sinkhorn_anderson", alpha, beta, anderson=(K, r), **kw)
+    Anderson acceleration; the paper's experiment uses K = 4, r = 1e-7). normalize=True
+    divides the Gram matrix by its Frobenius norm before adding r. Other keyword args as
+    ``sinkhorn``. Returns (f, g, Info)."""
+    return _solve("uot_sinkhorn_anderson", alpha, beta, anderson=(K, r, normalize), **kw)
 
 
-def ti_sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, **kw):
-    """Translation-invariant Sinkhorn with Anderson extrapolation of fb every K iterations.
-    Other keyword args as ``ti_sinkhorn``. Returns the translated (f, g, Info)."""
-    return _solve("uot_ti_sinkhorn_anderson", alpha, beta, anderson=(K, r), **kw)
+def ti_sinkhorn_anderson(alpha, beta, *, K: int = 4, r: float = 1e-7, normalize: bool = False,
+                         **kw):
+    """Translation-invariant Sinkhorn with Anderson extrapolation of fb every K iterations
+    (normalize as in ``sinkhorn_anderson``). Other keyword args as ``ti_sinkhorn``. Returns
+    the translated (f, g, Info)."""
+    return _solve("uot_ti_sinkhorn_anderson", alpha, beta, anderson=(K, r, normalize), **kw)
 
 
 def dual_value(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: float,
@@ -409,7 +420,8 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
 
     offN, offM: host int64 sequences [B+1] (CSR offsets of the x and y sides); x [sum N, d],
     y [sum M, d], alpha, beta: float32 device tensors; eps, rho1, rho2: float64 device
-    tensors [B] (or host sequences). Returns (f, g, iters, status) as device tensors."""
+    tensors [B], host sequences of B values, or scalars (the same for every problem).
+    Returns (f, g, iters, status) as device tensors."""
     _require_gpu()
     lib = load_library()
     offN = np.ascontiguousarray(np.asarray(offN, dtype=np.int64))
@@ -430,8 +442,25 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
             return v.to(device=dev, dtype=torch.float64).contiguous()
         return torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev)
 
-    eps_t, r1_t = _d64(eps), _d64(rho1)
-    r2_t = r1_t if rho2 is None else _d64(rho2)
+    def per_problem(v, name):
+        if isinstance(v, torch.Tensor):
+            t = v.to(device=dev, dtype=torch.float64).contiguous().reshape(-1)
+        elif np.ndim(v) == 0:
+            t = torch.full((B,), float(v), dtype=torch.float64, device=dev)
+        else:
+            t = _d64(v).reshape(-1)
+        if t.numel() != B:
+            raise ValueError("%s has %d entries, %d problems" % (name, t.numel(), B))
+        return t
+
+    if x.shape[0] != offN[-1] or alpha.numel() != offN[-1]:
+        raise ValueError("x and alpha must have offN[-1] = %d rows" % int(offN[-1]))
+    if y.shape[0] != offM[-1] or beta.numel() != offM[-1]:
+        raise ValueError("y and beta must have offM[-1] = %d rows" % int(offM[-1]))
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y dimensions differ")
+    eps_t, r1_t = per_problem(eps, "eps"), per_problem(rho1, "rho1")
+    r2_t = r1_t if rho2 is None else per_problem(rho2, "rho2")
     f = torch.empty(int(offN[-1]), dtype=torch.float32, device=dev)
     g = torch.empty(int(offM[-1]), dtype=torch.float32, device=dev)
     iters = torch.empty(B, dtype=torch.int32, device=dev)
@@ -447,6 +476,34 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
                                        float(tol), int(check_every), _ptr(f), _ptr(g), _ptr(iters),
                                        _ptr(status), _ptr(workspace), workspace.numel(), _stream()))
     return f, g, iters, status
+
+
+BATCH_PLAN_AUTO, BATCH_PLAN_COARSE, BATCH_PLAN_FINE, BATCH_PLAN_SWITCH = 0, 1, 2, 3
+
+
+def batched_set_plan(plan: int) -> int:
+    """Work-item plan of the batched solver (see uot_batched_set_plan); returns the previous."""
+    prev = load_library().uot_batched_set_plan(int(plan))
+    if prev < 0:
+        raise ValueError("unknown batched plan %r" % (plan,))
+    return prev
+
+
+def batched_trace(on: bool = True):
+    """Enable (or disable) the per-chunk load statistics of the batched solver."""
+    load_library().uot_batched_trace_enable(int(bool(on)))
+
+
+def batched_trace_read():
+    """Rows of the last batched solve's trace as a dict of numpy arrays (see
+    uot_batched_trace_read)."""
+    lib = load_library()
+    n = int(lib.uot_batched_trace_read(None, 0))
+    buf = np.zeros((max(n, 1), 9), dtype=np.float64)
+    lib.uot_batched_trace_read(buf.ctypes.data_as(ctypes.c_void_p), n)
+    keys = ("chunk", "fine", "running", "items_g", "items_f", "work", "busy_ticks", "ticks",
+            "resident_waves")
+    return {k: buf[:n, i].copy() for i, k in enumerate(keys)}
 
 
 def fw1d_batched(offN, offM, x, y, alpha, beta, rho1, rho2=None, *, p: float = 2.0,

@@ -24,6 +24,7 @@ SOURCES = [
     "kernels_batched.hip",
     "kernels_anderson.hip",
     "kernels_fw.hip",
+    "kernels_grad.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -57,10 +57,10 @@ __global__ __launch_bounds__(kBlock) void k_anderson_gram(AndersonArgs a) {
   }
 }
 
-// One block: sums the block Grams, normalises by the Frobenius norm, adds r, solves
-// (G + r I) z = 1 by Cholesky (G + r I is symmetric positive definite for r > 0) and
-// writes c = z / sum(z). A system that does not factor (non-finite entries) is a numeric
-// error that ends the solve.
+// One block: sums the block Grams (G = U^T U), divides G by its Frobenius norm when
+// a.normalize is set, adds r, solves (G + r I) z = 1 by Cholesky (G + r I is symmetric
+// positive definite for r > 0) and writes c = z / sum(z). A system that does not factor
+// (non-finite entries) is a numeric error that ends the solve.
 __global__ __launch_bounds__(kBlock) void k_anderson_solve(AndersonArgs a, int nb) {
   if (get_done(&a.st->done)) return;
   __shared__ double gs[kGramTerms];
@@ -83,7 +83,8 @@ __global__ __launch_bounds__(kBlock) void k_anderson_solve(AndersonArgs a, int n
     }
   fro = sqrt(fro);
   for (int p = 0; p < K; ++p) {
-    for (int q = 0; q < K; ++q) G[p][q] = fro > 0.0 ? G[p][q] / fro : G[p][q];
+    if (a.normalize && fro > 0.0)
+      for (int q = 0; q < K; ++q) G[p][q] /= fro;
     G[p][p] += a.r;
   }
   // Cholesky G = L L^T in place (lower triangle)

@@ -1,14 +1,13 @@
-// Plan application and envelope gradients with the plan recomputed on the fly (gfx950).
+// Plan application with the plan recomputed on the fly (gfx950).
 //
 // For each target t, with source offsets a_s = sc h_s + log2 w_s (sc = log2(e)/eps):
-//   e_ts = a_s - sc C_ts,   pi_ts = w_t 2^{sc h_t} 2^{e_ts}
-//   V mode:    out_tc = sum_s pi_ts V_sc
-//   grad mode: out_tc = gscale sum_s pi_ts p ||t - s||^{p-2} (t_c - s_c)   (0 at t = s)
+//   e_ts = a_s - sc C_ts,   pi_ts = w_t 2^{sc h_t} 2^{e_ts},   out_tc = sum_s pi_ts V_sc.
 // One pass keeps a running max of e_ts per target and rescales its accumulators, so no
 // entry of pi is ever formed in overflowing range. Sources are split across blocks and the
 // per-split (max, sum, accumulators) records are merged by a second kernel. Accumulators
 // are taken 4 output columns per launch. Dense costs are read as C[t, s] (targets = rows)
-// or C[s, t] (targets = columns).
+// or C[s, t] (targets = columns). (The marginals and the envelope gradients take the
+// one-exp pass of kernels_grad.hip.)
 #include <cfloat>
 
 #include "uot_internal.h"
@@ -30,7 +29,7 @@ struct ApplyLaunch {
   float *part;           // [nsplit, nt, kRecF]
 };
 
-template <int D, int MODE, bool GRAD>
+template <int D, int MODE>
 __global__ __launch_bounds__(256) void k_apply_partial(ApplyLaunch L) {
   const ApplyArgs &a = L.a;
   const int t = blockIdx.x * 256 + threadIdx.x;
@@ -42,8 +41,6 @@ __global__ __launch_bounds__(256) void k_apply_partial(ApplyLaunch L) {
   }
   const float sc = a.sc;
   const float half_p = (float)(0.5 * a.p);
-  const float gexp = (float)(0.5 * (a.p - 2.0));  // exponent of d2 in p ||.||^{p-2}
-  const float pf = (float)a.p;
   float m = -FLT_MAX, l = 0.0f, acc[kKV];
 #pragma unroll
   for (int c = 0; c < kKV; ++c) acc[c] = 0.0f;
@@ -69,26 +66,10 @@ __global__ __launch_bounds__(256) void k_apply_partial(ApplyLaunch L) {
     const float scale = fast_exp2(m - mn);
     const float pe = fast_exp2(e - mn);
     l = l * scale + pe;
-    if constexpr (GRAD) {
-      float wgt;
-      if (MODE == kSqEuc || pf == 2.0f) wgt = 2.0f;
-      else wgt = d2 > 0.0f ? pf * fast_exp2(gexp * fast_log2(d2)) : 0.0f;
 #pragma unroll
-      for (int c = 0; c < kKV; ++c) {
-        const int k = L.c0 + c;
-        float dk = 0.0f;
-#pragma unroll
-        for (int q = 0; q < D; ++q)
-          if (q == k) dk = diff[q];
-        acc[c] = acc[c] * scale + pe * wgt * dk;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < kKV; ++c) {
-        const float v = (a.V == nullptr) ? 1.0f
-                        : (c < L.kv ? a.V[(size_t)s * a.ldv + L.c0 + c] : 0.0f);
-        acc[c] = acc[c] * scale + pe * v;
-      }
+    for (int c = 0; c < kKV; ++c) {
+      const float v = c < L.kv ? a.V[(size_t)s * a.ldv + L.c0 + c] : 0.0f;
+      acc[c] = acc[c] * scale + pe * v;
     }
     m = mn;
   }
@@ -105,11 +86,10 @@ __global__ __launch_bounds__(256) void k_apply_combine(ApplyLaunch L) {
   if (t >= a.nt) return;
   float M = -FLT_MAX;
   for (int p = 0; p < L.nsplit; ++p) M = fmaxf(M, L.part[((size_t)p * a.nt + t) * kRecF]);
-  double sum = 0.0, acc[kKV] = {0.0, 0.0, 0.0, 0.0};
+  double acc[kKV] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < L.nsplit; ++p) {
     const float *q = L.part + ((size_t)p * a.nt + t) * kRecF;
     const double sc = exp2((double)q[0] - (double)M);
-    sum += sc * (double)q[1];
 #pragma unroll
     for (int c = 0; c < kKV; ++c) acc[c] += sc * (double)q[2 + c];
   }
@@ -117,20 +97,13 @@ __global__ __launch_bounds__(256) void k_apply_combine(ApplyLaunch L) {
   const double wt = (double)a.w_t[t];
   const double fac = wt > 0.0 ? wt * exp2((double)a.sc * (double)a.h_t[t] + (double)M) : 0.0;
   for (int c = 0; c < L.kv; ++c)
-    a.out[(size_t)t * a.ldout + L.c0 + c] = (float)(a.gscale * fac * acc[c]);
-  if (a.rowsum != nullptr && L.c0 == 0) {
-    // sum_s w_s e^{(h_t + h_s - C_ts)/eps} = 2^{sc h_t + M} sum
-    a.rowsum[t] = (float)(exp2((double)a.sc * (double)a.h_t[t] + (double)M) * sum);
-  }
+    a.out[(size_t)t * a.ldout + L.c0 + c] = (float)(fac * acc[c]);
 }
 
 template <int D, int MODE>
 hipError_t apply_for(const ApplyLaunch &L, hipStream_t s) {
   dim3 grid((L.a.nt + 255) / 256, L.nsplit);
-  if (L.a.grad)
-    hipLaunchKernelGGL((k_apply_partial<D, MODE, true>), grid, dim3(256), 0, s, L);
-  else
-    hipLaunchKernelGGL((k_apply_partial<D, MODE, false>), grid, dim3(256), 0, s, L);
+  hipLaunchKernelGGL((k_apply_partial<D, MODE>), grid, dim3(256), 0, s, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_apply_combine, dim3((L.a.nt + 255) / 256), dim3(256), 0, s, L);
@@ -161,14 +134,6 @@ __global__ __launch_bounds__(256) void k_src_offsets(const float *h, const float
   if (s >= n) return;
   const float ws = w[s];
   out[s] = ws > 0.0f ? (float)((double)sc * (double)h[s] + log2((double)ws)) : -INFINITY;
-}
-
-__global__ __launch_bounds__(256) void k_weight_grad(WeightGradArgs a, const double *mass_other) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= a.n) return;
-  const double h = a.h[t];
-  const double v = a.rho * (-expm1(-h / a.rho)) - a.eps * ((double)a.rowsum[t] - *mass_other);
-  a.out[t] = (float)(a.gout * v);
 }
 
 __global__ __launch_bounds__(256) void k_sum(const float *w, int n, double *out) {
@@ -208,7 +173,8 @@ hipError_t launch_apply_with_scratch(const ApplyArgs &a, void *scratch, hipStrea
                      a.sc, src_off);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int ncols = a.grad ? a.d : (a.V == nullptr ? 1 : a.k);
+  if (a.V == nullptr) return hipErrorInvalidValue;
+  const int ncols = a.k;
   for (int c0 = 0; c0 < ncols; c0 += kKV) {
     L.c0 = c0;
     L.kv = (ncols - c0) < kKV ? (ncols - c0) : kKV;
@@ -216,12 +182,6 @@ hipError_t launch_apply_with_scratch(const ApplyArgs &a, void *scratch, hipStrea
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
-}
-
-hipError_t launch_weight_grad_from_rowsum(const WeightGradArgs &a, const double *mass_other,
-                                          hipStream_t s) {
-  hipLaunchKernelGGL(k_weight_grad, dim3((a.n + 255) / 256), dim3(256), 0, s, a, mass_other);
-  return hipGetLastError();
 }
 
 hipError_t launch_sum(const float *w, int n, double *out, hipStream_t s) {

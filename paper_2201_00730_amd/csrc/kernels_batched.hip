@@ -14,9 +14,12 @@
 // k_batched_compact rebuilds the active item lists between chunks of iterations.
 //
 // Same base-2 conventions as the single-problem kernels: sc_p = log2(e)/eps_p and records
-//   kSqEuc: u_s = 2 sc_p (x_s - mu_p), b_s = sc_p h_s + log2 w_s - sc_p |x_s - mu_p|^2
-//   kPower: u_s = x_s - mu_p,          b_s = sc_p h_s + log2 w_s
-// where mu_p is the common mean of problem p's two clouds.
+//   u_s = x_s - mu_p,  b_s = sc_p h_s + log2 w_s,  exponent v_ts = b_s - sc_p ||u_s - (y_t - mu_p)||^p
+// where mu_p is the common mean of problem p's two clouds. The cost is always taken through the
+// differences (p = 2 included: ||.||^2 as is), so the float32 rounding of an exponent is
+// relative to its entry's own cost; the expanded form |x|^2 + |y|^2 - 2<x, y> would carry an
+// absolute rounding of the clouds' squared spread, which at small eps is not small against
+// the potentials.
 #include <cfloat>
 
 #include "uot_batched.h"
@@ -63,19 +66,12 @@ __device__ __forceinline__ HalfCoef half_coef(double eps, double rho_t, double r
   return c;
 }
 
-template <int D, int MODE>
-__device__ __forceinline__ void write_rec(float *rp, const float *yc, double yn2, float hf, float w,
-                                          double sc) {
+template <int D>
+__device__ __forceinline__ void write_rec(float *rp, const float *yc, float hf, float w, double sc) {
   const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
-  if constexpr (MODE == kSqEuc) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) rp[k] = (float)(2.0 * sc * (double)yc[k]);
-    rp[D] = (float)(sc * (double)hf + lw2 - sc * yn2);
-  } else {
-#pragma unroll
-    for (int k = 0; k < D; ++k) rp[k] = yc[k];
-    rp[D] = (float)(sc * (double)hf + lw2);
-  }
+  for (int k = 0; k < D; ++k) rp[k] = yc[k];
+  rp[D] = (float)(sc * (double)hf + lw2);
 #pragma unroll
   for (int k = D + 1; k < batched_rec_stride(D); ++k) rp[k] = 0.0f;
 }
@@ -149,7 +145,7 @@ __device__ __noinline__ void reduce_problem(const BatchedArgs &a, int p, bool g_
 // targets it.y + l + 64 r for r < R (R = 1, 2, 4 for items of at most 64, 128, 256 targets), so that
 // each source record read feeds R targets per lane. Softmin over all sources of p, epilogue,
 // item partials, and the problem's reduction by the last wave to finish one of its items.
-template <int D, int MODE, int R>
+template <int D, bool SQ, int R>
 __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, const int4 it) {
   const int lane = threadIdx.x & 63;
   const int64_t *off_t = g_step ? a.offM : a.offN;
@@ -175,19 +171,14 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
   const int64_t tb = off_t[p];
   const double *mu = a.mu + (size_t)p * kBatchMaxDim;
   float yc[R][D];
-  double yn2[R];
   bool valid[R];
   int64_t tg[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     valid[r] = lane + 64 * r < it.z;
     tg[r] = tb + it.y + (valid[r] ? lane + 64 * r : 0);
-    yn2[r] = 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      yc[r][k] = k < a.d ? tpts[tg[r] * a.d + k] - (float)mu[k] : 0.0f;
-      yn2[r] += (double)yc[r][k] * (double)yc[r][k];
-    }
+    for (int k = 0; k < D; ++k) yc[r][k] = k < a.d ? tpts[tg[r] * a.d + k] - (float)mu[k] : 0.0f;
   }
   // softmin over all sources of p
   const int64_t s0 = off_s[p], s1 = off_s[p + 1];
@@ -197,22 +188,18 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
     m[r] = -FLT_MAX;
     l[r] = 0.0f;
   }
+  const float half_p = a.half_p;
   auto expo = [&](const float *rp, int r) -> float {
-    if constexpr (MODE == kSqEuc) {
-      float acc = rp[D];
+    float d2 = 0.0f;
 #pragma unroll
-      for (int k = 0; k < D; ++k) acc = fmaf(rp[k], yc[r][k], acc);
-      return acc;
-    } else {
-      float d2 = 0.0f;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const float u = rp[k] - yc[r][k];
-        d2 = fmaf(u, u, d2);
-      }
-      const float c = (a.half_p == 0.5f) ? __builtin_sqrtf(d2) : fast_exp2(a.half_p * fast_log2(d2));
-      return fmaf(-sc, c, rp[D]);
+    for (int k = 0; k < D; ++k) {
+      const float u = rp[k] - yc[r][k];
+      d2 = fmaf(u, u, d2);
     }
+    // SQ: p = 2, the squared distance as is
+    const float c = SQ ? d2
+                    : half_p == 0.5f ? __builtin_sqrtf(d2) : fast_exp2(half_p * fast_log2(d2));
+    return fmaf(-sc, c, rp[D]);
   };
   int64_t s = s0;
   for (; s + kTile <= s1; s += kTile) {
@@ -251,8 +238,7 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (!valid[r]) continue;
-    double lse2 = (double)m[r] + log2((double)l[r]);
-    if constexpr (MODE == kSqEuc) lse2 -= scd * yn2[r];
+    const double lse2 = (double)m[r] + log2((double)l[r]);
     const double S = -lse2 / scd;
     const double hnew = cf.k_t * (S - tau_src) - cf.c_t * s_src;
     const float hf = (float)hnew;
@@ -264,8 +250,7 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
     const float w = tw[tg[r]];
     // the record's coordinates never change (written by k_batched_init): only its offset
     const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
-    trec[(size_t)tg[r] * SD + D] =
-        (float)(MODE == kSqEuc ? scd * (double)hf + lw2 - scd * yn2[r] : scd * (double)hf + lw2);
+    trec[(size_t)tg[r] * SD + D] = (float)(scd * (double)hf + lw2);
     if (w > 0.0f) {
       const double v = log((double)w) - (double)hf / rho_t;
       if (v > mm) {
@@ -301,7 +286,7 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
 }
 
 // One half-step for every active problem. g_step: targets y (beta, rho2), sources x.
-template <int D, int MODE>
+template <int D, bool SQ>
 __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step) {
   const int lane = threadIdx.x & 63;
   const int nact = g_step ? *a.nact_g : *a.nact_f;
@@ -313,6 +298,7 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
     if (g_step) *a.ctr_f = 0; else *a.ctr_g = 0;
   }
 
+  unsigned long long busy = 0;
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(ctr, 1);
@@ -320,23 +306,43 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
     if (item >= nact) break;
     const int4 it = items[act[item]];  // (problem, first target, count, slot)
     if (a.state[it.x].done) continue;  // finished by an earlier half-step (compaction is periodic)
+    const unsigned long long t0 = a.stats ? __builtin_amdgcn_s_memrealtime() : 0ull;
     if (it.z > 128)
-      batched_item<D, MODE, 4>(a, g_step, it);
+      batched_item<D, SQ, 4>(a, g_step, it);
     else if (it.z > 64)
-      batched_item<D, MODE, 2>(a, g_step, it);
+      batched_item<D, SQ, 2>(a, g_step, it);
     else
-      batched_item<D, MODE, 1>(a, g_step, it);
+      batched_item<D, SQ, 1>(a, g_step, it);
+    if (a.stats) busy += __builtin_amdgcn_s_memrealtime() - t0;
   }
+  if (a.stats && lane == 0 && busy) atomicAdd(&a.stats->busy, busy);
 }
 
 // Rebuilds the active item lists (items of problems not done), resets the work counters,
 // and counts the problems still running. One block.
 __global__ __launch_bounds__(1024) void k_batched_compact(BatchedArgs a) {
   __shared__ int s_ng, s_nf, s_run;
+  __shared__ double s_work[1024];
   if (threadIdx.x == 0) { s_ng = 0; s_nf = 0; s_run = 0; }
   __syncthreads();
+  double work = 0.0;
   for (int p = threadIdx.x; p < a.B; p += blockDim.x)
-    if (!a.state[p].done) atomicAdd(&s_run, 1);
+    if (!a.state[p].done) {
+      atomicAdd(&s_run, 1);
+      work += (double)(a.offN[p + 1] - a.offN[p]) * (double)(a.offM[p + 1] - a.offM[p]);
+    }
+  if (a.stats) {
+    s_work[threadIdx.x] = work;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if (threadIdx.x < o) s_work[threadIdx.x] += s_work[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.stats->work = s_work[0];
+      a.stats->t_compact = __builtin_amdgcn_s_memrealtime();
+    }
+  }
   for (int i = threadIdx.x; i < a.n_items_g; i += blockDim.x)
     if (!a.state[a.items_g[i].x].done) a.act_g[atomicAdd(&s_ng, 1)] = i;
   for (int i = threadIdx.x; i < a.n_items_f; i += blockDim.x)
@@ -353,7 +359,7 @@ __global__ __launch_bounds__(1024) void k_batched_compact(BatchedArgs a) {
 
 // Per problem (one block each): common mean of its clouds, weight checks, zero potentials,
 // records of both sides from zero potentials, and the initial scalars (Smin_alpha^rho1(0)).
-template <int D, int MODE>
+template <int D>
 __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
   const int p = blockIdx.x;
   __shared__ double sh[256];
@@ -393,14 +399,10 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
       if (!(wi >= 0.0f) || isinf(wi)) s_bad = 1;
       if (wi > 0.0f) { if (side == 0) s_pa = 1; else s_pb = 1; }
       float yc[D];
-      double yn2 = 0.0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        yc[k] = k < a.d ? pts[i * a.d + k] - (float)mu[k] : 0.0f;
-        yn2 += (double)yc[k] * (double)yc[k];
-      }
+      for (int k = 0; k < D; ++k) yc[k] = k < a.d ? pts[i * a.d + k] - (float)mu[k] : 0.0f;
       pot[i] = 0.0f;
-      write_rec<D, MODE>(rec + (size_t)i * SD, yc, yn2, 0.0f, wi, scd);
+      write_rec<D>(rec + (size_t)i * SD, yc, 0.0f, wi, scd);
       if (side == 0 && wi > 0.0f) {
         const double v = log((double)wi);
         const double mn = fmax(mm, v);
@@ -470,41 +472,46 @@ __global__ __launch_bounds__(256) void k_batched_finalize(BatchedArgs a, float *
   }
 }
 
-template <int D, int MODE>
+template <int D>
 hipError_t launch_half_t(const BatchedArgs &a, int g_step, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_batched_half<D, MODE>), dim3(blocks), dim3(256), 0, s, a, g_step);
+  if (a.half_p == 1.0f)
+    hipLaunchKernelGGL((k_batched_half<D, true>), dim3(blocks), dim3(256), 0, s, a, g_step);
+  else
+    hipLaunchKernelGGL((k_batched_half<D, false>), dim3(blocks), dim3(256), 0, s, a, g_step);
   return hipGetLastError();
 }
 
-template <int D, int MODE>
+template <int D>
 hipError_t launch_init_t(const BatchedArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_batched_init<D, MODE>), dim3(a.B), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_batched_init<D>), dim3(a.B), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-template <int D, int MODE>
-int half_occupancy_t() {
+template <int D>
+int half_occupancy_t(const BatchedArgs &a) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, MODE>, 256, 0) != hipSuccess) {
+  const hipError_t e = a.half_p == 1.0f
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, true>, 256, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, false>, 256, 0);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   return nb;
 }
 
-#define UOT_BATCH_DISPATCH(FN, ...)                                                  \
-  do {                                                                               \
-    const bool sq = a.mode == kSqEuc;                                                \
-    switch (a.d) {                                                                   \
-      case 1: return sq ? FN<1, kSqEuc>(__VA_ARGS__) : FN<1, kPower>(__VA_ARGS__);   \
-      case 2: return sq ? FN<2, kSqEuc>(__VA_ARGS__) : FN<2, kPower>(__VA_ARGS__);   \
-      case 3: return sq ? FN<3, kSqEuc>(__VA_ARGS__) : FN<3, kPower>(__VA_ARGS__);   \
-      case 4: return sq ? FN<4, kSqEuc>(__VA_ARGS__) : FN<4, kPower>(__VA_ARGS__);   \
-      case 5: return sq ? FN<5, kSqEuc>(__VA_ARGS__) : FN<5, kPower>(__VA_ARGS__);   \
-      case 6: return sq ? FN<6, kSqEuc>(__VA_ARGS__) : FN<6, kPower>(__VA_ARGS__);   \
-      case 7: return sq ? FN<7, kSqEuc>(__VA_ARGS__) : FN<7, kPower>(__VA_ARGS__);   \
-      case 8: return sq ? FN<8, kSqEuc>(__VA_ARGS__) : FN<8, kPower>(__VA_ARGS__);   \
-    }                                                                                \
+#define UOT_BATCH_DISPATCH(FN, ...)            \
+  do {                                         \
+    switch (a.d) {                             \
+      case 1: return FN<1>(__VA_ARGS__);       \
+      case 2: return FN<2>(__VA_ARGS__);       \
+      case 3: return FN<3>(__VA_ARGS__);       \
+      case 4: return FN<4>(__VA_ARGS__);       \
+      case 5: return FN<5>(__VA_ARGS__);       \
+      case 6: return FN<6>(__VA_ARGS__);       \
+      case 7: return FN<7>(__VA_ARGS__);       \
+      case 8: return FN<8>(__VA_ARGS__);       \
+    }                                          \
   } while (0)
 
 }  // namespace
@@ -520,7 +527,7 @@ hipError_t launch_batched_init(const BatchedArgs &a, hipStream_t s) {
 }
 
 int batched_half_blocks_per_cu(const BatchedArgs &a) {
-  UOT_BATCH_DISPATCH(half_occupancy_t);
+  UOT_BATCH_DISPATCH(half_occupancy_t, a);
   return 0;
 }
 

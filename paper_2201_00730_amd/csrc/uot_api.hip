@@ -126,13 +126,14 @@ int device_cus() {
 // Splits of `ns` sources over `tiles` target tiles: as many splits as fill one round of
 // resident blocks (capacity = blocks per CU x CUs), capped at kMaxSplits and by a minimum
 // split length; split lengths are multiples of `align`.
-Split make_split(int ns, int tiles, int min_len, int align, int capacity) {
+Split make_split(int ns, int tiles, int min_len, int align, int capacity,
+                 int max_splits = kMaxSplits) {
   Split s;
   if (capacity <= 0) capacity = kDefaultResidentBlocks;
   int want = capacity / tiles;
   const int maxn = (ns + min_len - 1) / min_len;
   if (want > maxn) want = maxn;
-  if (want > kMaxSplits) want = kMaxSplits;
+  if (want > max_splits) want = max_splits;
   if (want < 1) want = 1;
   int len = (ns + want - 1) / want;
   len = (len + align - 1) / align * align;
@@ -173,7 +174,8 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
 
 struct Layout {
   size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0;
-  size_t dual = 0, rowsum_x = 0, rowsum_y = 0, tmp_x = 0, tmp_y = 0, scratch = 0, total = 0;
+  size_t dual = 0, scratch = 0, total = 0;
+  size_t grad_rec = 0, grad_part = 0, masses = 0;  // plan marginals and the backward
   size_t hist = 0, taus = 0, gram = 0, acc_c = 0;  // Anderson
   int64_t ldh = 0;
   HalfShape g, f;  // g-step: targets y (columns), sources x; f-step: targets x (rows), sources y
@@ -215,12 +217,18 @@ Layout make_layout(const uot_cost *c, int which) {
   L.bparts = take((size_t)(nbp + 1) * sizeof(BlockPart));
   L.dual = take((size_t)((nmax + kBlock - 1) / kBlock + 1) * 6 * sizeof(double));
   if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
-    L.rowsum_x = take((size_t)n * sizeof(float));
-    L.rowsum_y = take((size_t)m * sizeof(float));
-    L.tmp_x = take((size_t)n * sizeof(float));
-    L.tmp_y = take((size_t)m * sizeof(float));
     const size_t a = apply_partial_bytes(n, m), b = apply_partial_bytes(m, n);
     L.scratch = take(a > b ? a : b);
+    // one-pass marginals and gradients: source records of either side (points: kPower
+    // layout; stored cost: one float), and split partials (gradient accumulators, or the
+    // stored-cost softmin partials with up to kMaxSplits splits)
+    const int db = c->kind == UOT_COST_POINTS ? dim_bucket(d) : 0;
+    const int rs = c->kind == UOT_COST_POINTS ? rec_stride(kPower, db) : 1;
+    L.grad_rec = take((size_t)rec_count(nmax) * rs * sizeof(float));
+    const size_t pg = (size_t)kGradMaxSplits * grad_part_stride(db);
+    const size_t pd = (size_t)kMaxSplits * grad_part_stride(0);
+    L.grad_part = take((pg > pd ? pg : pd) * (size_t)nmax * sizeof(float));
+    L.masses = take(2 * sizeof(double));
   }
   if (which == UOT_WS_ANDERSON) {
     L.ldh = ((int64_t)n + 63) / 64 * 64;
@@ -289,7 +297,9 @@ uot_status read_state(SolveState *dev, SolveState &host, hipStream_t s) {
 // Optional kernel timing: when enabled, each softmin launch is bracketed by two HIP events
 // on the launch stream; durations are accumulated per kernel kind under a mutex.
 // ---------------------------------------------------------------------------------------
-enum ProfKind : int { kProfPoints = 0, kProfDenseCols = 1, kProfDenseRows = 2, kProfKinds = 3 };
+enum ProfKind : int {
+  kProfPoints = 0, kProfDenseCols = 1, kProfDenseRows = 2, kProfGrad = 3, kProfKinds = 4
+};
 struct ProfAcc {
   int64_t launches = 0;
   double ms = 0.0, entries = 0.0;
@@ -587,6 +597,7 @@ uot_status anderson_step(const Ctx &k, const uot_anderson *acc) {
   aa.n = k.n;
   aa.K = acc->k;
   aa.r = acc->r;
+  aa.normalize = acc->normalize;
   aa.gram = at<double>(k.ws, k.L.gram);
   aa.c = at<double>(k.ws, k.L.acc_c);
   aa.pot = at<float>(k.ws, k.L.pot_x);
@@ -618,6 +629,8 @@ uot_status check_anderson(const uot_anderson *acc) {
   if (acc->k < 2 || acc->k > kAndersonMaxK)
     return fail(UOT_ERR_INVALID, "anderson k=%d must be in 2..%d", acc->k, kAndersonMaxK);
   if (!finite_pos(acc->r)) return fail(UOT_ERR_INVALID, "anderson r=%g must be finite and > 0", acc->r);
+  if (acc->normalize != 0 && acc->normalize != 1)
+    return fail(UOT_ERR_INVALID, "anderson normalize=%d must be 0 or 1", acc->normalize);
   return UOT_OK;
 }
 
@@ -669,6 +682,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
 
   PinnedState pin;
   UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
+  SolveState *hst = pin.h;
 
   // start: flags, centring, weights, records of x from f_0 (with Smin_alpha^rho1(f_0)), g = 0
   UOT_TRY(prepare(c, alpha, beta, st, k.s));
@@ -693,8 +707,8 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
                            (size_t)k.n * sizeof(float), hipMemcpyDeviceToDevice, k.s));
     UOT_HIP(hipMemsetAsync(at<double>(k.ws, k.L.taus), 0, (kAndersonMaxK + 1) * sizeof(double), k.s));
   }
-  UOT_TRY(read_state(st, pin.h[0], k.s));
-  if (pin.h[0].error & kErrWeights)
+  UOT_TRY(read_state(st, hst[0], k.s));
+  if (hst[0].error & kErrWeights)
     return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
 
   // iterations, in chunks of check_every; the host reads the convergence flag one chunk late
@@ -702,12 +716,15 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   const bool checking = P->tol > 0.0;
   const int chunk = checking ? P->check_every : P->max_iter;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  UOT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  UOT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   struct EvGuard {
     hipEvent_t *e;
-    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+    ~EvGuard() {
+      if (e[0]) (void)hipEventDestroy(e[0]);
+      if (e[1]) (void)hipEventDestroy(e[1]);
+    }
   } evg{ev};
+  UOT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  UOT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   int issued = 0, c_idx = 0;
   bool stop = false;
   while (issued < P->max_iter && !stop) {
@@ -728,12 +745,12 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
     issued += todo;
     UOT_TRY(flush_reduce(k));
     if (checking) {
-      SolveState *slot = &pin.h[c_idx & 1];
+      SolveState *slot = &hst[c_idx & 1];
       UOT_HIP(hipMemcpyAsync(slot, st, sizeof(SolveState), hipMemcpyDeviceToHost, k.s));
       UOT_HIP(hipEventRecord(ev[c_idx & 1], k.s));
       if (c_idx >= 1) {
         UOT_HIP(hipEventSynchronize(ev[(c_idx - 1) & 1]));
-        if (pin.h[(c_idx - 1) & 1].done) stop = true;
+        if (hst[(c_idx - 1) & 1].done) stop = true;
       }
       ++c_idx;
     }
@@ -836,8 +853,107 @@ ApplyArgs apply_args(const uot_cost *c, int mode, bool targets_x, const float *a
   a.h_t = targets_x ? f : g;
   a.h_s = targets_x ? g : f;
   a.sc = (float)(kLog2e / eps);
-  a.gscale = 1.0;
   return a;
+}
+
+// Row sums of the plan for the targets of one side (targets x when tx), in one pass over the
+// other side's points (kernels_grad.hip) or one stored-cost softmin, and what is asked of
+// them: the plan marginal (marg, element t at marg[t * marg_stride]), the weight gradient
+// dw (needs rho_t and mass_other, the source side's total mass on the device) and the point
+// gradient dpts (points costs; k_t = rho_t / (eps + rho_t) gives the reference of the
+// one-exp pass).
+uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const float *beta,
+                         const float *f, const float *g, double eps, double rho_t, double gout,
+                         SolveState *st, void *ws, const Layout &L, float *marg,
+                         int64_t marg_stride, float *dw, const double *mass_other, float *dpts,
+                         hipStream_t s) {
+  const bool dense = c->kind == UOT_COST_DENSE;
+  const int nt = tx ? c->n : c->m, ns = tx ? c->m : c->n;
+  const double sc = kLog2e / eps;
+  float *rec = at<float>(ws, L.grad_rec);
+  float *part = at<float>(ws, L.grad_part);
+  RecordArgs ra;
+  ra.pts = dense ? nullptr : (tx ? c->y : c->x);
+  ra.w = tx ? beta : alpha;
+  ra.pot = tx ? g : f;
+  ra.pot_copy = nullptr;
+  ra.pot_off = 0.0;
+  ra.n = ns;
+  ra.mode = dense ? kDense : kPower;
+  ra.d = dense ? 0 : c->d;
+  ra.rec = rec;
+  ra.bparts = nullptr;
+  ra.rho = 1.0;
+  ra.sc = sc;
+  ra.st = st;
+  UOT_HIP(launch_build_records(ra, s));
+  const int cus = device_cus();
+  int nsplit = 1;
+  if (dense) {
+    DenseArgs da;
+    da.C = c->C;
+    da.ldc = c->ldc;
+    da.n = c->n;
+    da.m = c->m;
+    da.rec = rec;
+    da.sc = (float)sc;
+    da.part = reinterpret_cast<float2 *>(part);
+    da.done = nullptr;
+    if (tx) {
+      da.split_len = ns;
+      da.nsplit = 1;
+      UOT_HIP(launch_dense_rows(da, s));
+    } else {
+      const HalfShape h = half_shape(kDense, 0, nt, ns, false);
+      da.split_len = h.split.len;
+      da.nsplit = nsplit = h.split.n;
+      UOT_HIP(launch_dense_cols_partial(da, s));
+    }
+  } else {
+    GradArgs ga;
+    ga.tgt = tx ? c->x : c->y;
+    ga.nt = nt;
+    ga.d = c->d;
+    ga.mu = st->mu;
+    ga.h_t = tx ? f : g;
+    ga.inv_k = (eps + rho_t) / rho_t;
+    ga.rec = rec;
+    ga.ns = ns;
+    const int tiles = (nt + grad_targets_per_block(c->d) - 1) / grad_targets_per_block(c->d);
+    const Split sp = make_split(ns, tiles, 64, 1, (cus > 0 ? cus : 256) * 4, kGradMaxSplits);
+    ga.split_len = sp.len;
+    ga.nsplit = nsplit = sp.n;
+    ga.sc = (float)sc;
+    ga.half_p = (float)(0.5 * c->p);
+    ga.p = (float)c->p;
+    ga.grad = dpts != nullptr ? 1 : 0;
+    ga.part = part;
+    Timer timer(profiling_enabled());
+    hipError_t te = hipSuccess;
+    const LaunchTiming *t = timer.on() ? timer.next(&te) : nullptr;
+    UOT_HIP(te);
+    UOT_HIP(launch_grad_partial(ga, s, t));
+    timer.launched(kProfGrad, (double)nt * (double)ns);
+  }
+  GradCombineArgs ca;
+  ca.part = part;
+  ca.nsplit = nsplit;
+  ca.nt = nt;
+  ca.d = dense ? 0 : c->d;
+  ca.h_t = tx ? f : g;
+  ca.w_t = tx ? alpha : beta;
+  ca.sc = sc;
+  ca.eps = eps;
+  ca.rho = rho_t;
+  ca.gout = gout;
+  ca.pfac = (!dense && c->p == 2.0) ? 2.0 : 1.0;
+  ca.mass_other = mass_other;
+  ca.marg = marg;
+  ca.marg_stride = marg_stride;
+  ca.dw = dw;
+  ca.dpts = dpts;
+  UOT_HIP(launch_grad_combine(ca, s));
+  return UOT_OK;
 }
 
 uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, double eps,
@@ -864,13 +980,18 @@ uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   SolveState *st = at<SolveState>(w.ptr, L.state);
   UOT_TRY(prepare(c, alpha, beta, st, s));
-  ApplyArgs a = apply_args(c, mode_of(c), transpose == 0, alpha, beta, f, g, eps, st);
-  a.V = V;
-  a.k = kc;
-  a.ldv = ldv;
-  a.out = out;
-  a.ldout = ldout;
-  UOT_HIP(launch_apply_with_scratch(a, at<void>(w.ptr, L.scratch), s));
+  if (V == nullptr) {  // the marginals: row sums in one pass
+    UOT_TRY(envelope_side(c, transpose == 0, alpha, beta, f, g, eps, 1.0, 1.0, st, w.ptr, L, out,
+                          ldout, nullptr, nullptr, nullptr, s));
+  } else {
+    ApplyArgs a = apply_args(c, mode_of(c), transpose == 0, alpha, beta, f, g, eps, st);
+    a.V = V;
+    a.k = kc;
+    a.ldv = ldv;
+    a.out = out;
+    a.ldout = ldout;
+    UOT_HIP(launch_apply_with_scratch(a, at<void>(w.ptr, L.scratch), s));
+  }
   SolveState fin;
   UOT_TRY(read_state(st, fin, s));
   if ((fin.error & kErrWeights) || !fin.pos_a || !fin.pos_b)
@@ -902,41 +1023,15 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
   hipStream_t s = static_cast<hipStream_t>(stream);
   SolveState *st = at<SolveState>(w.ptr, L.state);
   UOT_TRY(prepare(c, alpha, beta, st, s));
-  const int mode = mode_of(c);
-  void *scratch = at<void>(w.ptr, L.scratch);
-  double *masses = at<double>(w.ptr, L.dual);  // [0] = m(alpha), [1] = m(beta)
+  double *masses = at<double>(w.ptr, L.masses);  // [0] = m(beta), [1] = m(alpha)
   for (int side = 0; side < 2; ++side) {
     const bool tx = side == 0;  // targets are the x side
     float *dpts = tx ? dx : dy;
     float *dw = tx ? dalpha : dbeta;
     if (dpts == nullptr && dw == nullptr) continue;
-    ApplyArgs a = apply_args(c, mode, tx, alpha, beta, f, g, eps, st);
-    float *rowsum = at<float>(w.ptr, tx ? L.rowsum_x : L.rowsum_y);
-    a.rowsum = dw ? rowsum : nullptr;
-    if (dpts) {
-      a.grad = 1;
-      a.gscale = grad_out;
-      a.out = dpts;
-      a.ldout = c->d;
-    } else {
-      a.V = nullptr;
-      a.k = 1;
-      a.out = at<float>(w.ptr, tx ? L.tmp_x : L.tmp_y);
-      a.ldout = 1;
-    }
-    UOT_HIP(launch_apply_with_scratch(a, scratch, s));
-    if (dw) {
-      UOT_HIP(launch_sum(tx ? beta : alpha, tx ? c->m : c->n, masses + side, s));
-      WeightGradArgs wa;
-      wa.rowsum = rowsum;
-      wa.h = tx ? f : g;
-      wa.n = tx ? c->n : c->m;
-      wa.rho = tx ? rho1 : rho2;
-      wa.eps = eps;
-      wa.gout = grad_out;
-      wa.out = dw;
-      UOT_HIP(launch_weight_grad_from_rowsum(wa, masses + side, s));
-    }
+    if (dw) UOT_HIP(launch_sum(tx ? beta : alpha, tx ? c->m : c->n, masses + side, s));
+    UOT_TRY(envelope_side(c, tx, alpha, beta, f, g, eps, tx ? rho1 : rho2, grad_out, st, w.ptr, L,
+                          nullptr, 1, dw, masses + side, dpts, s));
   }
   SolveState fin;
   UOT_TRY(read_state(st, fin, s));
@@ -1153,6 +1248,26 @@ uot_status fw_barycenter(int32_t B, int32_t K, const int64_t *off, const float *
   return UOT_OK;
 }
 
+// Process-wide settings of the batched solver: the work-item plan, and a per-chunk trace of
+// the last solve (load statistics), guarded by a mutex.
+enum BatchPlan : int { kPlanAuto = 0, kPlanCoarse = 1, kPlanFine = 2, kPlanSwitchAfterFirst = 3 };
+struct BatchTraceRow {
+  double chunk, fine, running, items_g, items_f, work, busy_ticks, ticks, resident_waves;
+};
+std::mutex g_batch_mu;
+int g_batch_plan = kPlanAuto;
+bool g_batch_trace_on = false;
+std::vector<BatchTraceRow> g_batch_trace;
+
+int batched_plan() {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  return g_batch_plan;
+}
+bool batched_trace_enabled() {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  return g_batch_trace_on;
+}
+
 uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
                           BatchLayout &L) {
   if (B < 1) return fail(UOT_ERR_INVALID, "B=%d must be >= 1", B);
@@ -1198,7 +1313,7 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   // active lists and item partials serve either plan
   L.act_g = take((size_t)L.n_items_g2 * sizeof(int));
   L.act_f = take((size_t)L.n_items_f2 * sizeof(int));
-  L.ctrs = take(8 * sizeof(int));
+  L.ctrs = take(sizeof(BatchCounters));
   L.part_g = take((size_t)L.n_items_g2 * sizeof(BlockPart));
   L.part_f = take((size_t)L.n_items_f2 * sizeof(BlockPart));
   L.tick_g = take((size_t)B * sizeof(int));
@@ -1282,7 +1397,7 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   BatchedArgs a;
   a.B = B;
   a.d = d;
-  a.mode = p == 2.0 ? kSqEuc : kPower;
+  a.mode = kPower;  // the cost through the differences, p = 2 included
   a.half_p = (float)(0.5 * p);
   a.offN = at<int64_t>(w.ptr, L.offN);
   a.offM = at<int64_t>(w.ptr, L.offM);
@@ -1310,12 +1425,15 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   a.n_items_f = L.n_items_f;
   a.act_g = at<int>(w.ptr, L.act_g);
   a.act_f = at<int>(w.ptr, L.act_f);
-  int *ctrs = at<int>(w.ptr, L.ctrs);
-  a.nact_g = ctrs + 0;
-  a.nact_f = ctrs + 1;
-  a.ctr_g = ctrs + 2;
-  a.ctr_f = ctrs + 3;
-  a.running = ctrs + 4;
+  BatchCounters *ctrs = at<BatchCounters>(w.ptr, L.ctrs);
+  a.nact_g = &ctrs->nact_g;
+  a.nact_f = &ctrs->nact_f;
+  a.ctr_g = &ctrs->ctr_g;
+  a.ctr_f = &ctrs->ctr_f;
+  a.running = &ctrs->running;
+  const bool tracing = batched_trace_enabled();
+  a.stats = tracing ? ctrs : nullptr;
+  if (tracing) UOT_HIP(hipMemsetAsync(ctrs, 0, sizeof(BatchCounters), s));
   a.part_g = at<BlockPart>(w.ptr, L.part_g);
   a.part_f = at<BlockPart>(w.ptr, L.part_f);
   a.ticket_g = at<int>(w.ptr, L.tick_g);
@@ -1366,13 +1484,23 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   // costs more per entry than a coarse one (four), so it pays only once the long items of
   // big problems, not the total work, bound a launch. batch2d, updates/s: coarse only
   // 2.52e12; switching at 1/2, 2, 4, 8x the waves 2.63, 2.71, 2.71, 2.59e12 (one target per
-  // lane instead of two: 2.63e12 at 1/2 and 1x, 2.24e12 at 4x).
+  // lane instead of two: 2.63e12 at 1/2 and 1x, 2.24e12 at 4x). The process-wide plan setting
+  // (uot_batched_set_plan) can instead keep either plan throughout, or switch after the first
+  // chunk.
   const int resident_waves = blocks * 4;
-  auto want_fine = [&](const int *c) { return (c[0] > c[1] ? c[0] : c[1]) <= 2 * resident_waves; };
+  const int plan = batched_plan();
+  auto want_fine = [&](const BatchCounters &c, int chunks_done) {
+    if (plan == kPlanCoarse) return false;
+    if (plan == kPlanFine) return true;
+    if (plan == kPlanSwitchAfterFirst) return chunks_done >= 1;
+    return (c.nact_g > c.nact_f ? c.nact_g : c.nact_f) <= 2 * resident_waves;
+  };
 
-  PinnedState pin;  // reused as two int slots for the running counts
+  // host copies of the counters after each chunk (two slots, read one chunk late)
+  PinnedState pin;
   UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
-  int *run_h = reinterpret_cast<int *>(pin.h);
+  BatchCounters *cnt_h = reinterpret_cast<BatchCounters *>(pin.h);
+  static_assert(3 * sizeof(BatchCounters) <= 2 * sizeof(SolveState), "counter slots");
   hipEvent_t ev[2] = {nullptr, nullptr};
   UOT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   UOT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -1380,26 +1508,45 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     hipEvent_t *e;
     ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
   } evg{ev};
-  // counters right after initialisation: active coarse items (g, f) at [0], [1], problems
-  // still running at [4]
-  UOT_HIP(hipMemcpyAsync(run_h, ctrs, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<BatchTraceRow> trace;
+  unsigned long long busy_prev = 0, t_prev = 0;
+  auto record = [&](const BatchCounters &c, int chunk, bool fine_plan) {
+    if (!tracing) return;
+    BatchTraceRow r;
+    r.chunk = chunk;
+    r.fine = fine_plan ? 1 : 0;
+    r.running = c.running;
+    r.items_g = c.nact_g;
+    r.items_f = c.nact_f;
+    r.work = c.work;
+    r.busy_ticks = (double)(c.busy - busy_prev);
+    r.ticks = chunk == 0 ? 0.0 : (double)(c.t_compact - t_prev);
+    r.resident_waves = resident_waves;
+    busy_prev = c.busy;
+    t_prev = c.t_compact;
+    trace.push_back(r);
+  };
+  // counters right after initialisation: active coarse items of each side, problems running
+  UOT_HIP(hipMemcpyAsync(&cnt_h[2], ctrs, sizeof(BatchCounters), hipMemcpyDeviceToHost, s));
   UOT_HIP(hipStreamSynchronize(s));
+  record(cnt_h[2], 0, false);
   const int max_chunks = (max_iter + chunk - 1) / chunk;
   bool fine = false;
-  if (run_h[4] > 0) {
-    if (want_fine(run_h)) {
+  if (cnt_h[2].running > 0) {
+    if (want_fine(cnt_h[2], 0)) {
       UOT_HIP(launch_batched_compact(a2, s));
       fine = true;
     }
     for (int c = 0; c < max_chunks; ++c) {
       UOT_HIP(hipGraphLaunch(fine ? gg2.e : gg.e, s));
-      UOT_HIP(hipMemcpyAsync(run_h + 16 * (c & 1), ctrs, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+      UOT_HIP(hipMemcpyAsync(&cnt_h[c & 1], ctrs, sizeof(BatchCounters), hipMemcpyDeviceToHost, s));
       UOT_HIP(hipEventRecord(ev[c & 1], s));
       if (c >= 1) {
         UOT_HIP(hipEventSynchronize(ev[(c - 1) & 1]));
-        const int *cnt = run_h + 16 * ((c - 1) & 1);
-        if (cnt[4] == 0) break;
-        if (!fine && want_fine(cnt)) {  // after chunk c (queued): rebuild the active lists
+        const BatchCounters cnt = cnt_h[(c - 1) & 1];
+        record(cnt, c, fine);
+        if (cnt.running == 0) break;
+        if (!fine && want_fine(cnt, c)) {  // after chunk c (queued): rebuild the active lists
           UOT_HIP(launch_batched_compact(a2, s));
           fine = true;
         }
@@ -1408,6 +1555,10 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   }
   UOT_HIP(launch_batched_finalize(a, f, g, iters, status, s));
   UOT_HIP(hipStreamSynchronize(s));
+  if (tracing) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batch_trace = trace;
+  }
   return UOT_OK;
 }
 
@@ -1552,6 +1703,33 @@ uot_status uot_fw1d_batched(int32_t B, const int64_t *offN, const int64_t *offM,
   uot::g_last_error.clear();
   return uot::fw1d(B, offN, offM, x, y, alpha, beta, rho1, rho2, p, line_search, max_iter, tol,
                    f, g, iters, gap, status, workspace, workspace_bytes, stream);
+}
+
+int32_t uot_batched_set_plan(int32_t plan) {
+  if (plan < uot::kPlanAuto || plan > uot::kPlanSwitchAfterFirst) return -1;
+  std::lock_guard<std::mutex> lk(uot::g_batch_mu);
+  const int32_t prev = uot::g_batch_plan;
+  uot::g_batch_plan = plan;
+  return prev;
+}
+
+void uot_batched_trace_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(uot::g_batch_mu);
+  uot::g_batch_trace_on = on != 0;
+  if (!on) uot::g_batch_trace.clear();
+}
+
+int32_t uot_batched_trace_read(double *rows, int32_t max_rows) {
+  std::lock_guard<std::mutex> lk(uot::g_batch_mu);
+  const int32_t n = (int32_t)uot::g_batch_trace.size();
+  if (rows != nullptr)
+    for (int32_t i = 0; i < n && i < max_rows; ++i) {
+      const uot::BatchTraceRow &r = uot::g_batch_trace[i];
+      const double v[9] = {r.chunk, r.fine, r.running, r.items_g, r.items_f, r.work, r.busy_ticks,
+                           r.ticks, r.resident_waves};
+      for (int k = 0; k < 9; ++k) rows[(size_t)i * 9 + k] = v[k];
+    }
+  return n;
 }
 
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d) {

@@ -29,6 +29,17 @@ struct BatchState {
   int32_t pad_;
 };
 
+// Counters of the batched solver, copied to the host after every chunk of iterations.
+struct BatchCounters {
+  int nact_g, nact_f;              // active work items of each side (after the compaction)
+  int ctr_g, ctr_f;                // dynamic work counters
+  int running;                     // problems not done
+  int pad_[3];
+  unsigned long long busy;         // wave time on work items (s_memrealtime ticks), cumulative
+  unsigned long long t_compact;    // s_memrealtime at the latest compaction
+  double work;                     // sum of N_p M_p over the running problems
+};
+
 struct BatchedArgs {
   int B;
   int d, mode;
@@ -52,6 +63,8 @@ struct BatchedArgs {
   int *running;                    // problems not done (after the last compaction)
   BlockPart *part_g, *part_f;      // per-item partials
   int *ticket_g, *ticket_f;        // [B] arrival counters
+  // Load statistics (NULL = off): the busy, t_compact and work fields of BatchCounters.
+  BatchCounters *stats;
 };
 
 hipError_t launch_batched_init(const BatchedArgs &a, hipStream_t s);

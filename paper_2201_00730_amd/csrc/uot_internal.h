@@ -311,29 +311,50 @@ struct ApplyArgs {
   const float *w_t, *w_s;    // target / source weights
   const float *h_t, *h_s;    // target / source potentials
   float sc;
-  // V: [ns, k] with leading dim ldv; NULL => ones (k = 1)
+  // V: [ns, k] with leading dim ldv (the marginals, V = ones, take kernels_grad.hip)
   const float *V;
   int k;
   int64_t ldv;
-  // grad mode: accumulate sum_s pi_ts * p ||t-s||^{p-2} (t - s) into out [nt, d]
-  int grad;
-  double gscale;       // multiplies the output
   float *out;
   int64_t ldout;
-  float *rowsum;       // optional [nt]: sum_s w_s e^{(h_t + h_s - C_ts)/eps}
 };
 size_t apply_partial_bytes(int nt, int ns);
 hipError_t launch_apply_with_scratch(const ApplyArgs &a, void *scratch, hipStream_t s);
 
-struct WeightGradArgs {
-  const float *rowsum; // [n]: sum_j w_j e^{(h_i + h_j - C_ij)/eps}
-  const float *h;      // potential [n]
-  int n;
-  double rho, eps, gout;
-  float *out;
+// Envelope gradients and plan marginals of one side (kernels_grad.hip). Partials per
+// (split, target): reference, sum, then the d accumulators of the gradient (grad mode), i.e.
+// grad_part_stride(bucket) floats; the stored-cost softmin partials (max, sum) have the same
+// layout with no accumulators.
+__host__ __device__ constexpr int grad_part_stride(int D) { return D + 2; }
+constexpr int kGradMaxSplits = 16;
+struct GradArgs {
+  const float *tgt;    // raw target coordinates [nt, d]
+  int nt, d;
+  const double *mu;    // centring (SolveState::mu)
+  const float *h_t;    // target potential (reference of the one-exp pass)
+  double inv_k;        // 1 / k_t of the target side: reference -sc h_t / k_t
+  const float *rec;    // source records, kPower layout [ns, rec_stride(kPower, bucket)]
+  int ns, split_len, nsplit;
+  float sc, half_p, p;
+  int grad;            // 1: accumulate the point gradient (else sums only)
+  float *part;         // [nsplit, nt, grad_part_stride(grad ? bucket : 0)]
 };
-hipError_t launch_weight_grad_from_rowsum(const WeightGradArgs &a, const double *mass_other,
-                                          hipStream_t s);
+struct GradCombineArgs {
+  const float *part;   // partials as GradArgs::part (or stored-cost softmin partials)
+  int nsplit, nt, d;
+  const float *h_t, *w_t;  // target potential and weights
+  double sc, eps, rho, gout;
+  double pfac;         // 2 for p = 2, else 1
+  const double *mass_other;  // total mass of the source side (device)
+  float *marg;         // optional: plan marginal w_t rowsum_t, element t at marg[t * marg_stride]
+  int64_t marg_stride;
+  float *dw;           // optional: weight gradient
+  float *dpts;         // optional: point gradient [nt, d] (needs grad partials)
+};
+int grad_targets_per_block(int d);
+hipError_t launch_grad_partial(const GradArgs &a, hipStream_t s, const LaunchTiming *t = nullptr);
+hipError_t launch_grad_combine(const GradCombineArgs &a, hipStream_t s);
+
 hipError_t launch_sum(const float *w, int n, double *out, hipStream_t s);
 
 // Anderson extrapolation (kernels_anderson.hip): from the stored iterates of one cycle,
@@ -346,6 +367,7 @@ struct AndersonArgs {
   double *taus;        // [K + 1]
   int n, K;
   double r;
+  int normalize;       // 1: Gram matrix divided by its Frobenius norm before adding r
   double *gram;
   double *c;
   float *pot;          // stored potential of the x side (out)

@@ -218,3 +218,17 @@ def test_rate_estimate_of_a_geometric_sequence():
     assert abs(bench.kappa([0.8 ** t for t in range(30)]) - 0.8) < 1e-12
     assert abs(bench.kappa([0.5 ** t for t in range(10)] + [1e-7, 1e-7]) - 0.5) < 1e-12
     assert bench.kappa([1e-6, 1e-7]) is None
+    prm.eps = 0.0
+    assert fn(ctypes.byref(_cost()), None, None, ctypes.byref(prm), None, None, None, None) == \
+        uot.UOT_ERR_INVALID
+
+
+def test_anderson_rejects_bad_normalize_flag(lib):
+    c = _cost()
+    prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
+    for flag in (2, -1):
+        acc = uot._Anderson(4, 1e-7, flag)
+        st = lib.uot_ti_sinkhorn_anderson(ctypes.byref(c), None, None, ctypes.byref(prm),
+                                          ctypes.byref(acc), None, None, None, 0, None, None)
+        assert st == uot.UOT_ERR_INVALID
+        assert b"normalize" in lib.uot_last_error()

@@ -53,15 +53,36 @@ def small_batch(B=23, nmin=1, nmax=300, seed=31, d=2, p=2.0, eps=(2e-2, 2e-1), r
     return bt
 
 
+class _plan:
+    """Context manager that sets the batched work-item plan and restores the previous one."""
+
+    def __init__(self, plan):
+        self.plan = plan
+
+    def __enter__(self):
+        self.prev = uot.batched_set_plan(self.plan)
+
+    def __exit__(self, *exc):
+        uot.batched_set_plan(self.prev)
+
+
+PLANS = {"auto": uot.BATCH_PLAN_AUTO, "coarse": uot.BATCH_PLAN_COARSE,
+         "fine": uot.BATCH_PLAN_FINE}
+
+
+@pytest.mark.parametrize("plan", ["coarse", "fine", "auto"])
 @pytest.mark.parametrize("d,p,nmax", [(2, 2.0, 300), (3, 2.0, 300), (1, 2.0, 300), (5, 1.5, 300),
                                        (8, 2.0, 300), (2, 2.0, 1100), (3, 1.5, 700)])
-def test_batched_iteration_parity(d, p, nmax):
-    """Sizes 1..nmax: work items of <= 64 targets (one per lane), of 129..256 targets (four
-    per lane), and problems split into several items of both kinds."""
+def test_batched_iteration_parity(d, p, nmax, plan):
+    """Sizes 1..nmax under each work-item plan: coarse items of <= 64 targets (one per lane),
+    65..128 (two per lane), 129..256 (four per lane) and problems split into several items;
+    fine items of <= 128 targets. (The automatic plan picks fine items from the start on
+    batches this small.)"""
     bt = small_batch(B=23 if nmax <= 300 else 9, nmax=nmax, d=d, p=p, seed=40 + d + nmax)
-    print("batched d=%d p=%g B=%d" % (d, p, bt.B), file=sys.stderr, flush=True)
+    print("batched d=%d p=%g B=%d plan=%s" % (d, p, bt.B, plan), file=sys.stderr, flush=True)
     T = 12
-    f, g, it, st = run_batched(bt, T)
+    with _plan(PLANS[plan]):
+        f, g, it, st = run_batched(bt, T)
     assert np.all(it == T) and np.all(st == uot.BATCH_MAX_ITER)
     for b in range(bt.B):
         r = oracle_problem(bt, b, T)
@@ -70,11 +91,15 @@ def test_batched_iteration_parity(d, p, nmax):
         assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, (b, rel_inf(fb, r.f), rel_inf(gb, r.g))
 
 
-def test_batched_converges_per_problem():
+@pytest.mark.parametrize("plan", [uot.BATCH_PLAN_AUTO, uot.BATCH_PLAN_SWITCH])
+def test_batched_converges_per_problem(plan):
     """Each problem stops at its own first passing check; at its stopping iteration it matches
-    the oracle run for that many iterations, and the oracle's own stopping iteration is close."""
-    bt = small_batch(B=17, nmin=5, nmax=200, seed=7)
-    f, g, it, st = run_batched(bt, 5000, tol=1e-6, ce=10)
+    the oracle run for that many iterations, and the oracle's own stopping iteration is close.
+    The second plan starts on coarse items and moves to fine items after the first chunk, in
+    the middle of every problem's solve (active lists rebuilt, item partials re-indexed)."""
+    bt = small_batch(B=17, nmin=5, nmax=600, seed=7)
+    with _plan(plan):
+        f, g, it, st = run_batched(bt, 5000, tol=1e-6, ce=10)
     assert np.all(st == uot.BATCH_CONVERGED), st
     assert len(set(it.tolist())) > 1  # problems converge at different iterations
     for b in range(bt.B):
@@ -127,3 +152,41 @@ def test_batched_sampled_full_size():
         fb = f[bt.offN[b]:bt.offN[b + 1]]
         gb = g[bt.offM[b]:bt.offM[b + 1]]
         assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, (b, rel_inf(fb, r.f))
+
+
+def test_batched_low_eps_converged():
+    """The smallest-eps problems of the 4096-problem batch (eps from 1e-3): the whole batch runs
+    to change < 1e-6, then the 8 smallest-eps problems with N_p M_p <= 1.5e6 (the oracle's cost
+    stays in seconds) are compared with the oracle run to the GPU's stopping iteration. The
+    p = 2 cost is taken through the differences x - y, so its rounding stays relative to each
+    entry's own cost (the expanded form would add 2^-24 (d + 4) span^2 per softmin, not small
+    against potentials of 0.05-0.2 at these eps)."""
+    bt = workloads.batch2d()
+    f, g, it, st = run_batched(bt, 100000, tol=1e-6, ce=10)
+    assert np.all(st == uot.BATCH_CONVERGED)
+    NM = np.diff(bt.offN) * np.diff(bt.offM)
+    order = [int(b) for b in np.argsort(bt.eps, kind="stable") if NM[b] <= 1.5e6][:8]
+    print("low-eps problems %s, eps %s, iters %s" % (order, bt.eps[order], it[order]),
+          file=sys.stderr, flush=True)
+    for b in order:
+        r = oracle_problem(bt, b, int(it[b]))
+        fb = f[bt.offN[b]:bt.offN[b + 1]]
+        gb = g[bt.offM[b]:bt.offM[b + 1]]
+        assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, (b, rel_inf(fb, r.f), rel_inf(gb, r.g))
+
+
+def test_batched_load_statistics():
+    """The per-chunk trace: the work of the running problems never grows, the busy wave time
+    of a chunk fits in its duration times the resident waves, and it ends with no problem
+    running."""
+    bt = small_batch(B=40, nmin=20, nmax=900, seed=11)
+    uot.batched_trace(True)
+    try:
+        run_batched(bt, 5000, tol=1e-6, ce=10)
+        tr = uot.batched_trace_read()
+    finally:
+        uot.batched_trace(False)
+    assert len(tr["chunk"]) >= 2 and tr["running"][0] == bt.B and tr["running"][-1] == 0
+    assert np.all(np.diff(tr["work"]) <= 0)
+    assert np.all(tr["busy_ticks"][1:] <= tr["ticks"][1:] * tr["resident_waves"][1:] * 1.01 + 10)
+    assert np.sum(tr["busy_ticks"]) > 0

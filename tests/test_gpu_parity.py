@@ -251,26 +251,60 @@ def test_marginals_and_plan_apply(solved, dense):
         assert np.max(np.abs(out - ref)) <= TOL * np.max(scale)
 
 
-@pytest.mark.parametrize("p", [2.0, 1.5])
-def test_backward_matches_oracle_gradients(solved, p):
-    pr, r = solved
-    prc = workloads.random_small(400, 333, d=3, seed=12, eps=0.05, rho1=0.8, rho2=1.6, p=p)
-    rr = run_oracle(prc, True, 100000, tol=1e-12)
+def _check_backward(prc, f32, g32, gout=0.7, need_dx=True, dense=False):
+    """uot.backward against oracle.gradients at the same float32 potentials (1e-5)."""
     cost = oracle_cost(prc)
     a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
-    f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
     dx, dy, da, db = oracle.gradients(cost, a, b, prc.eps, prc.rho1, prc.rho2, f32.astype(np.float64),
-                                      g32.astype(np.float64), gout=0.7)
-    gx, gy, ga, gb = uot.backward(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), x=dev(prc.x),
-                                  y=dev(prc.y), p=p, eps=prc.eps, rho1=prc.rho1, rho2=prc.rho2,
-                                  grad_out=0.7)
-    assert rel_inf(gx.cpu().numpy(), dx) < TOL
-    assert rel_inf(gy.cpu().numpy(), dy) < TOL
+                                      g32.astype(np.float64), gout=gout)
+    kw = dict(C=dev(prc.C)) if dense else dict(x=dev(prc.x), y=dev(prc.y), p=prc.p)
+    gx, gy, ga, gb = uot.backward(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), eps=prc.eps,
+                                  rho1=prc.rho1, rho2=prc.rho2, grad_out=gout, need_dx=need_dx,
+                                  need_dy=need_dx, **kw)
+    if need_dx and not dense:
+        assert rel_inf(gx.cpu().numpy(), dx) < TOL, rel_inf(gx.cpu().numpy(), dx)
+        assert rel_inf(gy.cpu().numpy(), dy) < TOL, rel_inf(gy.cpu().numpy(), dy)
+    else:
+        assert gx is None and gy is None
     # dalpha_i = rho1(1 - e^{-f/rho1}) - eps(rowsum - m(beta)): compare on the scale of its terms
     sa = prc.rho1 + prc.eps * (np.max(np.abs(da)) + b.sum())
     sb = prc.rho2 + prc.eps * (np.max(np.abs(db)) + a.sum())
-    assert np.max(np.abs(ga.cpu().numpy() - da)) < TOL * sa
-    assert np.max(np.abs(gb.cpu().numpy() - db)) < TOL * sb
+    assert np.max(np.abs(ga.cpu().numpy() - da)) < TOL * sa * abs(gout)
+    assert np.max(np.abs(gb.cpu().numpy() - db)) < TOL * sb * abs(gout)
+
+
+# Dimensions 3 (one bucket), 5, 12 (padded bucket), 16 (the D = 16 configuration) and 20
+# (bucket 24, one target per lane); p = 2 and p = 1.5.
+@pytest.mark.parametrize("p", [2.0, 1.5])
+@pytest.mark.parametrize("d", [3, 5, 12, 16, 20])
+def test_backward_matches_oracle_gradients(d, p):
+    prc = workloads.random_small(400, 333, d=d, seed=12 + d, eps=0.05, rho1=0.8, rho2=1.6, p=p)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    _say("backward d=%d p=%g" % (d, p))
+    _check_backward(prc, rr.f.astype(np.float32), rr.g.astype(np.float32))
+
+
+def test_backward_weight_gradients_only_and_dense():
+    """Without point gradients (sums only) and for a stored cost."""
+    prc = workloads.random_small(400, 333, d=3, seed=31, eps=0.05, rho1=0.8, rho2=1.6)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    _check_backward(prc, rr.f.astype(np.float32), rr.g.astype(np.float32), need_dx=False)
+    prd = workloads.random_small(300, 257, d=4, seed=32, eps=0.05, rho1=0.8, rho2=1.6, dense=True)
+    rd = run_oracle(prd, True, 100000, tol=1e-12)
+    _check_backward(prd, rd.f.astype(np.float32), rd.g.astype(np.float32), dense=True)
+
+
+@pytest.mark.parametrize("d", [3, 16])
+def test_backward_away_from_the_optimum(d):
+    """Potentials far from the optimum (a translated optimum, and random ones): the reference
+    of the one-exp pass is off by many binades and the running-maximum pass takes over."""
+    prc = workloads.random_small(300, 271, d=d, seed=40 + d, eps=0.05, rho1=0.8, rho2=1.6)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    _say("backward off-optimum d=%d" % d)
+    _check_backward(prc, (rr.f + 3.0).astype(np.float32), (rr.g - 1.0).astype(np.float32))
+    rng = np.random.default_rng(d)
+    _check_backward(prc, rng.normal(0, 0.3, prc.n).astype(np.float32),
+                    rng.normal(0, 0.3, prc.m).astype(np.float32), gout=-1.3)
 
 
 def test_autograd_loss_matches_oracle(solved):

@@ -117,6 +117,16 @@ def highdim16(n: int = 50000, m: int = 50000, seed: int = 5, eps: float = 0.05, 
                    eps=eps, rho1=rho, rho2=rho, x=_f32(x), y=_f32(y), p=2.0, meta={"seed": seed})
 
 
+def highdim16_subset(k: int = 64) -> Problem:
+    """The first k points of each cloud of ``highdim16`` (the same draws), with uniform weights
+    of masses 1 and 1.3 on the subset: the finite-difference check of the D = 16 loss."""
+    full = highdim16()
+    return Problem("highdim16_subset", alpha=_f32(np.full(k, 1.0 / k)),
+                   beta=_f32(np.full(k, 1.3 / k)), eps=full.eps, rho1=full.rho1, rho2=full.rho2,
+                   x=np.ascontiguousarray(full.x[:k]), y=np.ascontiguousarray(full.y[:k]), p=2.0,
+                   meta={"seed": full.meta["seed"], "subset": k})
+
+
 @dataclass
 class Batch:
     """Many independent KL-UOT problems packed back to back (CSR-style offsets)."""
