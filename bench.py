@@ -465,10 +465,14 @@ def extra_workload(args, uot, torch, np, workloads):
         _, dtb = _timed(torch, lambda: uot.backward(a, b, f, g, **kw))
         uot.profile_enable(False)
         nb, msb, entb = _profiled(uot, (uot.PROFILE_GRAD,))
-        # backward work per entry (one pass per side, p = 2): D differences and D FMAs for the
-        # squared distance, one FMA for the exponent, one exp2, one add for the row sum and D
-        # FMAs for the gradient accumulators: 5 D + 3 flops (an FMA counts 2) and one exp
-        flops_b = (5 * pr.d + 3) * entb / (msb * 1e-3) if msb > 0 else 0.0
+        # backward work per entry (one pass per side, p = 2): in double precision D FMAs for
+        # <t', s'>, one FMA for the squared distance, one FMA and one add for the exponent
+        # (2 D + 5 flops); in float32 one add for the row sum and D FMAs for the gradient
+        # accumulators (2 D + 1 flops); one exp2. Peak: the published vector peaks (FP64
+        # 78.6, FP32 157.3 TFLOP/s), weighted by the time each share takes at its own peak.
+        f64, f32 = 2 * pr.d + 5, 2 * pr.d + 1
+        peak_b = (f64 + f32) / (f64 / 78.6e12 + f32 / 157.3e12)
+        flops_b = (f64 + f32) * entb / (msb * 1e-3) if msb > 0 else 0.0
         ach = ent / (ms * 1e-3) if ms > 0 else 0.0
         out.update({"metric": "C-entry softmin updates/s", "unit": "C-entry softmin updates/s",
                     "value": 2.0 * pr.n * pr.m * info.iters / dt,
@@ -477,10 +481,10 @@ def extra_workload(args, uot, torch, np, workloads):
                     "iters": info.iters, "converged": info.converged, "forward_seconds": dt,
                     "backward_seconds": dtb,
                     "backward_roofline": {
-                        "bound": "alu", "achieved": flops_b / 1e12, "peak": 157.3,
-                        "unit": "TFLOP/s", "frac": flops_b / 157.3e12, "traffic": None,
-                        "kernel": "k_grad_partial<16,2,true> (5D+3 flop + 1 exp2 per entry, "
-                                  "both sides)",
+                        "bound": "alu", "achieved": flops_b / 1e12, "peak": peak_b / 1e12,
+                        "unit": "TFLOP/s", "frac": flops_b / peak_b, "traffic": None,
+                        "kernel": "k_grad_partial<16,2,true,true> (2D+5 FP64 + 2D+1 FP32 flop "
+                                  "+ 1 exp2 per entry, both sides)",
                         "launches": nb, "avg_launch_ms": msb / nb if nb else None,
                         "exp_per_s": entb / (msb * 1e-3) if msb > 0 else None,
                         "exp_frac": entb / (msb * 1e-3) / PEAK_EXP_PER_S if msb > 0 else None},

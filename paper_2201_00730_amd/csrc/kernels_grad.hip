@@ -1,27 +1,35 @@
 // Envelope gradients and plan marginals of a points cost, one pass over the sources per
 // side, one exp2 per entry (gfx950).
 //
-// Targets t are the points of one side, sources s those of the other, with source records
-// (x_s - mu, b_s = sc h_s + log2 w_s) and sc = log2(e)/eps. The plan entry is
-//   pi_ts = w_t 2^{sc h_t} 2^{e_ts},   e_ts = b_s - sc C_ts,   C_ts = ||t - s||^p,
+// Targets t are the points of one side, sources s those of the other; both are centred by the
+// common mean mu (t' = t - mu, s' = s - mu; the cost is translation invariant). With
+// sc = log2(e)/eps and b_s = sc h_s + log2 w_s the plan entry is
+//   pi_ts = w_t 2^{sc h_t} 2^{e_ts},   e_ts = b_s - sc C_ts,   C_ts = ||t' - s'||^p,
 // its row sum pi1_t = w_t 2^{sc h_t} sum_s 2^{e_ts}, and the gradient of <pi, C> in t (the
 // envelope theorem applied to the dual, Sec. 1)
 //   sum_s pi_ts c'(||t - s||) (t - s),   c'(r) (t - s) = p r^{p-2} (t - s)  (0 at t = s).
 // Per (source split, target) the kernel accumulates, relative to a reference r_t,
-//   l_t = sum_s 2^{e_ts - r_t},   acc_tk = sum_s 2^{e_ts - r_t} w(d2) (t_k - s_k),
+//   l_t = sum_s q_ts,  lw_t = sum_s q_ts w_ts,  a_tk = sum_s q_ts w_ts s'_k,   q_ts = 2^{e_ts - r_t},
 // with w = 1 for p = 2 (the factor p = 2 is applied by the combine) and p d2^{(p-2)/2}
-// otherwise. The exponent is taken through the differences t - s, so its float32 rounding is
-// relative to the entry's own cost, not to the spread of the clouds.
+// otherwise; the combine forms the gradient t'_k lw_t - a_tk in double precision.
 //
-// Reference. With gradients requested, r_t starts at -sc h_t / k_t: at the optimum the
-// target's potential is the KL prox of its softmin, h_t = k_t Smin(C_t - h_s) (Sec. 3), so
-// this is log2 sum_s 2^{e_ts} and each entry costs one exp2 and no rescaling. A wave in
-// which some lane's sum leaves [2^-64, 2^64] (potentials far from the optimum) redoes its
-// split with a running maximum raised once per tile of sources. Without gradients (row sums
-// only) the running maximum is used from the start (one max per entry is cheap there).
+// Precision. A plan entry moves by a factor 2^{delta} when its exponent moves by delta, and
+// sc C_ts reaches several hundred (D = 16, eps = 0.05: sc ~ 29, C ~ 15..40 on the entries that
+// carry the plan), so a float32 exponent would leave ~1e-5 relative error in each entry. The
+// exponent is therefore formed in double precision, where float32 and double run at the same
+// vector rate on this chip: d2 = |t'|^2 + |s'|^2 - 2 <t', s'> (D double FMAs; its cancellation
+// costs 2^-53 of the norms), then e - r_t in double, and only that difference, a number of
+// order one on the entries that matter, is rounded to float32 for the exp2. For p != 2 the
+// cost d2^{p/2} is taken in double as well.
 //
-// Work split: each lane owns R targets (coordinates and accumulators in registers); the
-// sources of one split are uniform across the wave and read with scalar loads.
+// Reference. Each lane keeps a running reference r_t per target, an integer-valued float
+// raised to ceil(max e) whenever a tile of sources holds a larger exponent, so rescaling the
+// sums is a multiplication by a power of two (exact), and the entries that carry the sum have
+// e - r_t in [-few, 0] whatever the potentials, which keeps the float32 rounding of e - r_t
+// small where it matters. The combine takes the references exactly.
+//
+// Work split: each lane owns R targets (coordinates in double, accumulators in float, all in
+// registers); the sources of one split are uniform across the wave and read with scalar loads.
 #include <cfloat>
 
 #include "uot_internal.h"
@@ -30,146 +38,149 @@ namespace uot {
 namespace {
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
-
-constexpr float kSumLo = 0x1p-64f, kSumHi = 0x1p64f;
 
 template <int D>
 constexpr int grad_targets_per_lane() {
   return D <= 8 ? 4 : (D <= 16 ? 2 : 1);
 }
 
-// Sources per tile of the running-maximum loop.
+// Sources per tile of the running reference.
 constexpr int kTile = 4;
 
-template <int D, int R, bool GRAD>
-__global__ __launch_bounds__(256) void k_grad_partial(GradArgs a) {
-  constexpr int SD = rec_stride(kPower, D);
-  constexpr int PS = grad_part_stride(GRAD ? D : 0);
-  const int t0 = blockIdx.x * (256 * R) + threadIdx.x;
-  const float sc = a.sc, half_p = a.half_p, p = a.p;
-  const float gexp = 0.5f * (p - 2.0f);
+template <int D>
+__global__ __launch_bounds__(256) void k_grad_records(GradRecordArgs a) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= a.n) return;
+  double *r = a.rec + (size_t)s * grad_rec_stride(D);
+  float *rf = reinterpret_cast<float *>(r + D + 2);
+  double nn = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double v = k < a.d ? (double)a.pts[(size_t)s * a.d + k] - a.mu[k] : 0.0;
+    r[k] = v;
+    rf[k] = (float)v;
+    nn = fma(v, v, nn);
+  }
+  r[D] = nn;
+  const float w = a.w[s];
+  r[D + 1] = w > 0.0f ? a.sc * (double)a.pot[s] + log2((double)w) : -INFINITY;
+}
 
-  float y[R][D];
-  float ref[R];
+// Cost ||t' - s'||^p from the squared distance, in double precision.
+template <bool P2>
+__device__ __forceinline__ double cost_of(double d2, double half_p) {
+  if constexpr (P2) {
+    return d2;
+  } else {
+    const double dd = d2 > 0.0 ? d2 : 0.0;
+    if (half_p == 0.5) return sqrt(dd);
+    return dd > 0.0 ? exp2(half_p * log2(dd)) : 0.0;
+  }
+}
+
+// Gradient weight p d2^{(p-2)/2} = p C / d2 (0 at t = s); 1 for p = 2.
+template <bool P2>
+__device__ __forceinline__ float weight_of(double d2, double cst, float p) {
+  if constexpr (P2) {
+    return 1.0f;
+  } else {
+    const float df = (float)d2;
+    return df > 0.0f ? p * (float)cst * __builtin_amdgcn_rcpf(df) : 0.0f;
+  }
+}
+
+template <int D, int R, bool GRAD, bool P2>
+__global__ __launch_bounds__(256) void k_grad_partial(GradArgs a) {
+  constexpr int SD = grad_rec_stride(D);
+  constexpr int PS = grad_part_stride(GRAD ? D : 0);
+  constexpr int NA = GRAD ? D : 1;
+  const int t0 = blockIdx.x * (256 * R) + threadIdx.x;
+  const double sc = a.sc, half_p = a.half_p;
+  const float p = a.p;
+
+  double y[R][D];
+  double yn[R];
+  float ref[R], l[R], lw[R], acc[R][NA];
   bool valid[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int t = t0 + r * 256;
     valid[r] = t < a.nt;
     const int tc = valid[r] ? t : a.nt - 1;
+    double nn = 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k)
-      y[r][k] = k < a.d ? a.tgt[(size_t)tc * a.d + k] - (float)a.mu[k] : 0.0f;
-    ref[r] = (float)(-(double)sc * (double)a.h_t[tc] * a.inv_k);
+    for (int k = 0; k < D; ++k) {
+      y[r][k] = k < a.d ? (double)a.tgt[(size_t)tc * a.d + k] - a.mu[k] : 0.0;
+      nn = fma(y[r][k], y[r][k], nn);
+    }
+    yn[r] = nn;
+    ref[r] = -FLT_MAX;  // an integer-valued float
+    l[r] = 0.0f;
+    lw[r] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[r][k] = 0.0f;
   }
   const int s0 = blockIdx.y * a.split_len;
   const int s1 = min(a.ns, s0 + a.split_len);
 
-  auto cost = [&](float d2) -> float {
-    if (half_p == 1.0f) return d2;
-    if (half_p == 0.5f) return __builtin_sqrtf(d2);
-    return fexp2(half_p * flog2(d2));
-  };
-  auto weight = [&](float d2) -> float {
-    if (half_p == 1.0f) return 1.0f;
-    return d2 > 0.0f ? p * fexp2(gexp * flog2(d2)) : 0.0f;
+  // squared distance of target r to the source at rp (two FMA chains)
+  auto dist2 = [&](int r, const double *rp) -> double {
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int k = 0; k + 1 < D; k += 2) {
+      d0 = fma(y[r][k], rp[k], d0);
+      d1 = fma(y[r][k + 1], rp[k + 1], d1);
+    }
+    if constexpr (D % 2 == 1) d0 = fma(y[r][D - 1], rp[D - 1], d0);
+    return fma(-2.0, d0 + d1, yn[r] + rp[D]);
   };
 
-  float l[R], acc[R][GRAD ? D : 1];
-  auto clear = [&]() {
+  for (int s = s0; s < s1; s += kTile) {
+    const int ns = min(kTile, s1 - s);
+    double e[kTile][R];
+    float wt[kTile][R];
+#pragma unroll
+    for (int j = 0; j < kTile; ++j) {
+      const double *rp = a.rec + (size_t)(s + (j < ns ? j : 0)) * SD;
+      const double bs = rp[D + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double d2 = dist2(r, rp);
+        const double cst = cost_of<P2>(d2, half_p);
+        e[j][r] = j < ns ? fma(-sc, cst, bs) : -INFINITY;
+        wt[j][r] = GRAD ? weight_of<P2>(d2, cst, p) : 1.0f;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      l[r] = 0.0f;
+      double mt = e[0][r];
 #pragma unroll
-      for (int k = 0; k < (GRAD ? D : 1); ++k) acc[r][k] = 0.0f;
-    }
-  };
-  clear();
-
-  bool fast = GRAD;
-  if constexpr (GRAD) {
-    // one exp2 per entry against the reference of the optimum
-    for (int s = s0; s < s1; ++s) {
-      const float *rp = a.rec + (size_t)s * SD;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        float diff[D];
-        float d2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          diff[k] = y[r][k] - rp[k];
-          d2 = fmaf(diff[k], diff[k], d2);
-        }
-        const float q = fexp2(fmaf(-sc, cost(d2), rp[D] - ref[r]));
-        l[r] += q;
-        const float qw = q * weight(d2);
-#pragma unroll
-        for (int k = 0; k < D; ++k) acc[r][k] = fmaf(qw, diff[k], acc[r][k]);
-      }
-    }
-    bool bad = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) bad |= valid[r] && !(l[r] >= kSumLo && l[r] <= kSumHi);
-    fast = !__any(bad);
-  }
-
-  if (!fast) {
-    // running maximum, raised once per tile of kTile sources
-    clear();
-#pragma unroll
-    for (int r = 0; r < R; ++r) ref[r] = -FLT_MAX;
-    for (int s = s0; s < s1; s += kTile) {
-      const int ns = min(kTile, s1 - s);
-      float e[kTile][R];
-#pragma unroll
-      for (int j = 0; j < kTile; ++j) {
-        const float *rp = a.rec + (size_t)(s + (j < ns ? j : 0)) * SD;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          float d2 = 0.0f;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const float u = y[r][k] - rp[k];
-            d2 = fmaf(u, u, d2);
-          }
-          e[j][r] = j < ns ? fmaf(-sc, cost(d2), rp[D]) : -INFINITY;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        float mt = e[0][r];
-#pragma unroll
-        for (int j = 1; j < kTile; ++j) mt = fmaxf(mt, e[j][r]);
-        const float mn = fmaxf(ref[r], mt);
-        const float scale = fexp2(ref[r] - mn);
+      for (int j = 1; j < kTile; ++j) mt = fmax(mt, e[j][r]);
+      const float mc = ceilf((float)mt);
+      if (mc > ref[r]) {
+        const float scale = fexp2(ref[r] - mc);  // a power of two (or 0 from -FLT_MAX)
         l[r] *= scale;
         if constexpr (GRAD) {
+          lw[r] *= scale;
 #pragma unroll
           for (int k = 0; k < D; ++k) acc[r][k] *= scale;
         }
-        ref[r] = mn;
+        ref[r] = mc;
       }
+    }
 #pragma unroll
-      for (int j = 0; j < kTile; ++j) {
-        if (j >= ns) break;
-        const float *rp = a.rec + (size_t)(s + j) * SD;
+    for (int j = 0; j < kTile; ++j) {
+      if (j >= ns) break;
+      const float *rf = reinterpret_cast<const float *>(a.rec + (size_t)(s + j) * SD + D + 2);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float q = fexp2(e[j][r] - ref[r]);
-          l[r] += q;
-          if constexpr (GRAD) {
-            float diff[D];
-            float d2 = 0.0f;
+      for (int r = 0; r < R; ++r) {
+        const float q = fexp2((float)(e[j][r] - (double)ref[r]));
+        l[r] += q;
+        if constexpr (GRAD) {
+          const float qw = P2 ? q : q * wt[j][r];
+          if constexpr (!P2) lw[r] += qw;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-              diff[k] = y[r][k] - rp[k];
-              d2 = fmaf(diff[k], diff[k], d2);
-            }
-            const float qw = q * weight(d2);
-#pragma unroll
-            for (int k = 0; k < D; ++k) acc[r][k] = fmaf(qw, diff[k], acc[r][k]);
-          }
+          for (int k = 0; k < D; ++k) acc[r][k] = fmaf(qw, rf[k], acc[r][k]);
         }
       }
     }
@@ -183,8 +194,9 @@ __global__ __launch_bounds__(256) void k_grad_partial(GradArgs a) {
     o[0] = l[r] > 0.0f ? ref[r] : -FLT_MAX;
     o[1] = l[r];
     if constexpr (GRAD) {
+      o[2] = P2 ? l[r] : lw[r];
 #pragma unroll
-      for (int k = 0; k < D; ++k) o[2 + k] = acc[r][k];
+      for (int k = 0; k < D; ++k) o[3 + k] = acc[r][k];
     }
   }
 }
@@ -193,26 +205,28 @@ __global__ __launch_bounds__(256) void k_grad_partial(GradArgs a) {
 //   rowsum_t = sum_s w_s e^{(h_t + h_s - C_ts)/eps} = 2^{sc h_t + M} sum,
 //   marg_t   = w_t rowsum_t                                   (the plan marginal pi1_t),
 //   dw_t     = gout (rho (1 - e^{-h_t/rho}) - eps (rowsum_t - mass_other))   (d/d w_t),
-//   dpts_tk  = gout w_t 2^{sc h_t + M} pfac acc_k              (d/d t_k),
+//   dpts_tk  = gout w_t 2^{sc h_t + M} pfac (t'_k lw - a_k)   (d/d t_k),
 // with pfac = 2 for p = 2 (the kernel's weight is 1 there) and 1 otherwise.
 template <int DC>
 __global__ __launch_bounds__(256) void k_grad_combine(GradCombineArgs a) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.nt) return;
   constexpr int ps = grad_part_stride(DC);
+  constexpr int NA = DC > 0 ? DC : 1;
   float M = -FLT_MAX;
   for (int q = 0; q < a.nsplit; ++q) M = fmaxf(M, a.part[((size_t)q * a.nt + t) * ps]);
-  double sum = 0.0, acc[DC > 0 ? DC : 1];
+  double sum = 0.0, lw = 0.0, acc[NA];
 #pragma unroll
-  for (int k = 0; k < (DC > 0 ? DC : 1); ++k) acc[k] = 0.0;
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
   for (int q = 0; q < a.nsplit; ++q) {
     const float *o = a.part + ((size_t)q * a.nt + t) * ps;
     if (o[1] == 0.0f) continue;
     const double f = exp2((double)o[0] - (double)M);
     sum += f * (double)o[1];
     if constexpr (DC > 0) {
+      lw += f * (double)o[2];
 #pragma unroll
-      for (int k = 0; k < DC; ++k) acc[k] += f * (double)o[2 + k];
+      for (int k = 0; k < DC; ++k) acc[k] += f * (double)o[3 + k];
     }
   }
   const double h = (double)a.h_t[t];
@@ -229,21 +243,32 @@ __global__ __launch_bounds__(256) void k_grad_combine(GradCombineArgs a) {
       const double fac = wt > 0.0 ? a.gout * wt * base * a.pfac : 0.0;
 #pragma unroll
       for (int k = 0; k < DC; ++k)
-        if (k < a.d) a.dpts[(size_t)t * a.d + k] = (float)(fac * acc[k]);
+        if (k < a.d) {
+          const double tk = (double)a.tgt[(size_t)t * a.d + k] - a.mu[k];
+          a.dpts[(size_t)t * a.d + k] = (float)(fac * fma(tk, lw, -acc[k]));
+        }
     }
   }
 }
 
-template <int D, bool GRAD>
+template <int D>
+hipError_t records_for(const GradRecordArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_grad_records<D>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int D, bool GRAD, bool P2>
 hipError_t grad_for(const GradArgs &a, hipStream_t s, const LaunchTiming *t) {
   constexpr int R = grad_targets_per_lane<D>();
   dim3 grid((a.nt + 256 * R - 1) / (256 * R), a.nsplit);
-  return launch_timed(k_grad_partial<D, R, GRAD>, grid, dim3(256), s, t, a);
+  return launch_timed(k_grad_partial<D, R, GRAD, P2>, grid, dim3(256), s, t, a);
 }
 
 template <int D>
 hipError_t grad_for_mode(const GradArgs &a, hipStream_t s, const LaunchTiming *t) {
-  return a.grad ? grad_for<D, true>(a, s, t) : grad_for<D, false>(a, s, t);
+  const bool p2 = a.half_p == 1.0;
+  if (a.grad) return p2 ? grad_for<D, true, true>(a, s, t) : grad_for<D, true, false>(a, s, t);
+  return p2 ? grad_for<D, false, true>(a, s, t) : grad_for<D, false, false>(a, s, t);
 }
 
 template <int DC>
@@ -276,6 +301,11 @@ hipError_t combine_for(const GradCombineArgs &a, hipStream_t s) {
 int grad_targets_per_block(int d) {
   const int b = dim_bucket(d);
   return 256 * (b <= 8 ? 4 : (b <= 16 ? 2 : 1));
+}
+
+hipError_t launch_grad_records(const GradRecordArgs &a, hipStream_t s) {
+  UOT_GRAD_BUCKETS(records_for, dim_bucket(a.d), a, s)
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_grad_partial(const GradArgs &a, hipStream_t s, const LaunchTiming *t) {

@@ -219,12 +219,13 @@ Layout make_layout(const uot_cost *c, int which) {
   if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
     const size_t a = apply_partial_bytes(n, m), b = apply_partial_bytes(m, n);
     L.scratch = take(a > b ? a : b);
-    // one-pass marginals and gradients: source records of either side (points: kPower
-    // layout; stored cost: one float), and split partials (gradient accumulators, or the
-    // stored-cost softmin partials with up to kMaxSplits splits)
+    // one-pass marginals and gradients: source records of either side (points: doubles,
+    // grad_rec_stride; stored cost: one float), and split partials (gradient accumulators,
+    // or the stored-cost softmin partials with up to kMaxSplits splits)
     const int db = c->kind == UOT_COST_POINTS ? dim_bucket(d) : 0;
-    const int rs = c->kind == UOT_COST_POINTS ? rec_stride(kPower, db) : 1;
-    L.grad_rec = take((size_t)rec_count(nmax) * rs * sizeof(float));
+    const size_t rb = c->kind == UOT_COST_POINTS ? grad_rec_stride(db) * sizeof(double)
+                                                 : sizeof(float);
+    L.grad_rec = take((size_t)rec_count(nmax) * rb);
     const size_t pg = (size_t)kGradMaxSplits * grad_part_stride(db);
     const size_t pd = (size_t)kMaxSplits * grad_part_stride(0);
     L.grad_part = take((pg > pd ? pg : pd) * (size_t)nmax * sizeof(float));
@@ -860,8 +861,7 @@ ApplyArgs apply_args(const uot_cost *c, int mode, bool targets_x, const float *a
 // other side's points (kernels_grad.hip) or one stored-cost softmin, and what is asked of
 // them: the plan marginal (marg, element t at marg[t * marg_stride]), the weight gradient
 // dw (needs rho_t and mass_other, the source side's total mass on the device) and the point
-// gradient dpts (points costs; k_t = rho_t / (eps + rho_t) gives the reference of the
-// one-exp pass).
+// gradient dpts (points costs).
 uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const float *beta,
                          const float *f, const float *g, double eps, double rho_t, double gout,
                          SolveState *st, void *ws, const Layout &L, float *marg,
@@ -870,26 +870,26 @@ uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const f
   const bool dense = c->kind == UOT_COST_DENSE;
   const int nt = tx ? c->n : c->m, ns = tx ? c->m : c->n;
   const double sc = kLog2e / eps;
-  float *rec = at<float>(ws, L.grad_rec);
   float *part = at<float>(ws, L.grad_part);
-  RecordArgs ra;
-  ra.pts = dense ? nullptr : (tx ? c->y : c->x);
-  ra.w = tx ? beta : alpha;
-  ra.pot = tx ? g : f;
-  ra.pot_copy = nullptr;
-  ra.pot_off = 0.0;
-  ra.n = ns;
-  ra.mode = dense ? kDense : kPower;
-  ra.d = dense ? 0 : c->d;
-  ra.rec = rec;
-  ra.bparts = nullptr;
-  ra.rho = 1.0;
-  ra.sc = sc;
-  ra.st = st;
-  UOT_HIP(launch_build_records(ra, s));
   const int cus = device_cus();
   int nsplit = 1;
   if (dense) {
+    float *rec = at<float>(ws, L.grad_rec);
+    RecordArgs ra;
+    ra.pts = nullptr;
+    ra.w = tx ? beta : alpha;
+    ra.pot = tx ? g : f;
+    ra.pot_copy = nullptr;
+    ra.pot_off = 0.0;
+    ra.n = ns;
+    ra.mode = kDense;
+    ra.d = 0;
+    ra.rec = rec;
+    ra.bparts = nullptr;
+    ra.rho = 1.0;
+    ra.sc = sc;
+    ra.st = st;
+    UOT_HIP(launch_build_records(ra, s));
     DenseArgs da;
     da.C = c->C;
     da.ldc = c->ldc;
@@ -910,21 +910,31 @@ uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const f
       UOT_HIP(launch_dense_cols_partial(da, s));
     }
   } else {
+    double *rec = at<double>(ws, L.grad_rec);
+    GradRecordArgs ra;
+    ra.pts = tx ? c->y : c->x;
+    ra.w = tx ? beta : alpha;
+    ra.pot = tx ? g : f;
+    ra.mu = st->mu;
+    ra.n = ns;
+    ra.d = c->d;
+    ra.sc = sc;
+    ra.rec = rec;
+    UOT_HIP(launch_grad_records(ra, s));
     GradArgs ga;
     ga.tgt = tx ? c->x : c->y;
     ga.nt = nt;
     ga.d = c->d;
     ga.mu = st->mu;
     ga.h_t = tx ? f : g;
-    ga.inv_k = (eps + rho_t) / rho_t;
     ga.rec = rec;
     ga.ns = ns;
     const int tiles = (nt + grad_targets_per_block(c->d) - 1) / grad_targets_per_block(c->d);
     const Split sp = make_split(ns, tiles, 64, 1, (cus > 0 ? cus : 256) * 4, kGradMaxSplits);
     ga.split_len = sp.len;
     ga.nsplit = nsplit = sp.n;
-    ga.sc = (float)sc;
-    ga.half_p = (float)(0.5 * c->p);
+    ga.sc = sc;
+    ga.half_p = 0.5 * c->p;
     ga.p = (float)c->p;
     ga.grad = dpts != nullptr ? 1 : 0;
     ga.part = part;
@@ -940,6 +950,8 @@ uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const f
   ca.nsplit = nsplit;
   ca.nt = nt;
   ca.d = dense ? 0 : c->d;
+  ca.tgt = dense ? nullptr : (tx ? c->x : c->y);
+  ca.mu = st->mu;
   ca.h_t = tx ? f : g;
   ca.w_t = tx ? alpha : beta;
   ca.sc = sc;

@@ -321,27 +321,43 @@ struct ApplyArgs {
 size_t apply_partial_bytes(int nt, int ns);
 hipError_t launch_apply_with_scratch(const ApplyArgs &a, void *scratch, hipStream_t s);
 
-// Envelope gradients and plan marginals of one side (kernels_grad.hip). Partials per
-// (split, target): reference, sum, then the d accumulators of the gradient (grad mode), i.e.
-// grad_part_stride(bucket) floats; the stored-cost softmin partials (max, sum) have the same
-// layout with no accumulators.
-__host__ __device__ constexpr int grad_part_stride(int D) { return D + 2; }
+// Envelope gradients and plan marginals of one side (kernels_grad.hip).
+//
+// Source records, in doubles: the centred coordinates s' = s - mu (D), |s'|^2, and
+// b_s = sc h_s + log2 w_s; then the centred coordinates again as D floats (for the
+// accumulators), padded to a whole double.
+__host__ __device__ constexpr int grad_rec_stride(int D) { return D + 2 + (D + 1) / 2; }
+// Partials per (split, target): reference, sum of 2^{e - ref}, and in grad mode the weighted
+// sum lw = sum q w and the d accumulators sum q w s'_k, i.e. grad_part_stride(bucket) floats;
+// the stored-cost softmin partials (max, sum) have the layout of grad_part_stride(0).
+__host__ __device__ constexpr int grad_part_stride(int D) { return D > 0 ? D + 3 : 2; }
 constexpr int kGradMaxSplits = 16;
+struct GradRecordArgs {
+  const float *pts;    // raw source coordinates [n, d]
+  const float *w;      // source weights [n]
+  const float *pot;    // source potential [n]
+  const double *mu;    // centring (SolveState::mu)
+  int n, d;
+  double sc;
+  double *rec;         // [n, grad_rec_stride(bucket)]
+};
 struct GradArgs {
   const float *tgt;    // raw target coordinates [nt, d]
   int nt, d;
   const double *mu;    // centring (SolveState::mu)
-  const float *h_t;    // target potential (reference of the one-exp pass)
-  double inv_k;        // 1 / k_t of the target side: reference -sc h_t / k_t
-  const float *rec;    // source records, kPower layout [ns, rec_stride(kPower, bucket)]
+  const float *h_t;    // target potential
+  const double *rec;   // source records [ns, grad_rec_stride(bucket)]
   int ns, split_len, nsplit;
-  float sc, half_p, p;
+  double sc, half_p;
+  float p;
   int grad;            // 1: accumulate the point gradient (else sums only)
   float *part;         // [nsplit, nt, grad_part_stride(grad ? bucket : 0)]
 };
 struct GradCombineArgs {
   const float *part;   // partials as GradArgs::part (or stored-cost softmin partials)
   int nsplit, nt, d;
+  const float *tgt;    // raw target coordinates [nt, d] (point gradient only)
+  const double *mu;    // centring (point gradient only)
   const float *h_t, *w_t;  // target potential and weights
   double sc, eps, rho, gout;
   double pfac;         // 2 for p = 2, else 1
@@ -352,6 +368,7 @@ struct GradCombineArgs {
   float *dpts;         // optional: point gradient [nt, d] (needs grad partials)
 };
 int grad_targets_per_block(int d);
+hipError_t launch_grad_records(const GradRecordArgs &a, hipStream_t s);
 hipError_t launch_grad_partial(const GradArgs &a, hipStream_t s, const LaunchTiming *t = nullptr);
 hipError_t launch_grad_combine(const GradCombineArgs &a, hipStream_t s);
 

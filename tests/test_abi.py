@@ -218,9 +218,6 @@ def test_rate_estimate_of_a_geometric_sequence():
     assert abs(bench.kappa([0.8 ** t for t in range(30)]) - 0.8) < 1e-12
     assert abs(bench.kappa([0.5 ** t for t in range(10)] + [1e-7, 1e-7]) - 0.5) < 1e-12
     assert bench.kappa([1e-6, 1e-7]) is None
-    prm.eps = 0.0
-    assert fn(ctypes.byref(_cost()), None, None, ctypes.byref(prm), None, None, None, None) == \
-        uot.UOT_ERR_INVALID
 
 
 def test_anderson_rejects_bad_normalize_flag(lib):

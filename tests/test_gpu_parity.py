@@ -266,9 +266,14 @@ def _check_backward(prc, f32, g32, gout=0.7, need_dx=True, dense=False):
         assert rel_inf(gy.cpu().numpy(), dy) < TOL, rel_inf(gy.cpu().numpy(), dy)
     else:
         assert gx is None and gy is None
-    # dalpha_i = rho1(1 - e^{-f/rho1}) - eps(rowsum - m(beta)): compare on the scale of its terms
-    sa = prc.rho1 + prc.eps * (np.max(np.abs(da)) + b.sum())
-    sb = prc.rho2 + prc.eps * (np.max(np.abs(db)) + a.sum())
+    # dalpha_i = rho1(1 - e^{-f_i/rho1}) - eps(rowsum_i - m(beta)): compare on the scale of its
+    # terms, the largest of |rho1(1 - e^{-f/rho1})|, eps rowsum and eps m(beta)
+    f64, g64 = f32.astype(np.float64), g32.astype(np.float64)
+    p1, p2 = oracle.marginals(cost, a, b, prc.eps, f64, g64)
+    sa = max(np.max(np.abs(prc.rho1 * -np.expm1(-f64 / prc.rho1))),
+             prc.eps * np.max(p1[a > 0] / a[a > 0]), prc.eps * b.sum())
+    sb = max(np.max(np.abs(prc.rho2 * -np.expm1(-g64 / prc.rho2))),
+             prc.eps * np.max(p2[b > 0] / b[b > 0]), prc.eps * a.sum())
     assert np.max(np.abs(ga.cpu().numpy() - da)) < TOL * sa * abs(gout)
     assert np.max(np.abs(gb.cpu().numpy() - db)) < TOL * sb * abs(gout)
 
