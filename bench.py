@@ -56,7 +56,7 @@ def parse():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="cloud3d",
                     choices=("cloud3d", "oned", "stored8d", "batch2d", "highdim16", "anderson",
-                             "phi", "fw1d", "bary"),
+                             "phi", "fw1d", "bary", "probes"),
                     help="cloud3d (default) is the benchmark step above; the others print one "
                          "JSON line of their own measurement (see extra_workload)")
     return ap.parse_args()
@@ -200,7 +200,9 @@ def extra_workload(args, uot, torch, np, workloads):
               1e-9 (point-iterations/s = sum_p (N_p + M_p) iters_p / wall).
     bary      unbalanced 1-D barycenter of K = 8 random mixtures of 2000 points (rho = 0.1),
               1000 Frank-Wolfe iterations (microseconds per iteration, FP64 oracle on 50 of
-              them); and 512 such problems with 64..512 points per measure, 500 iterations."""
+              them); and 512 such problems with 64..512 points per measure, 500 iterations.
+    probes    measured issue rates of v_exp_f32, float32 FMA and double FMA (uot_probe_rate)
+              beside the spec-sheet figures the rooflines use."""
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     if args.calibrate_copy:  # a plain 256 MiB device copy, the yardstick of the byte counters
@@ -212,6 +214,17 @@ def extra_workload(args, uot, torch, np, workloads):
         del src, dst
     out = {"n_gpus": 1, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
            "higher_is_better": True, "scaling": "weak"}
+    if args.workload == "probes":
+        rates = issue_rates(uot)
+        out.update({"metric": "issue rate", "unit": "lane-ops/s", "value": rates["exp2"],
+                    "config": {"workload": "issue-rate probes: 2048 blocks x 256 lanes, 8 "
+                                           "independent chains of 2048 steps per lane"},
+                    "rates": rates,
+                    "spec": {"exp2": PEAK_EXP_PER_S, "fma32": 256 * 4 * 16 * 2.4e9,
+                             "fma64": 256 * 4 * 16 * 2.4e9},
+                    "roofline": None})
+        print(json.dumps(out))
+        return
     if args.workload == "oned":
         pr = workloads.oned()
         a, b, x, y = t(pr.alpha), t(pr.beta), t(pr.x), t(pr.y)
@@ -487,12 +500,19 @@ def extra_workload(args, uot, torch, np, workloads):
                                   "+ 1 exp2 per entry, both sides)",
                         "launches": nb, "avg_launch_ms": msb / nb if nb else None,
                         "exp_per_s": entb / (msb * 1e-3) if msb > 0 else None,
-                        "exp_frac": entb / (msb * 1e-3) / PEAK_EXP_PER_S if msb > 0 else None},
+                        "exp_frac": entb / (msb * 1e-3) / PEAK_EXP_PER_S if msb > 0 else None,
+                        "measured_issue_rates": issue_rates(uot)},
                     "roofline": {"bound": "alu", "achieved": ach / 1e9, "peak": PEAK_EXP_PER_S / 1e9,
                                  "unit": "Gexp/s", "frac": ach / PEAK_EXP_PER_S, "traffic": None,
                                  "kernel": "k_points_mfma<16,Bf16Form<16>>", "launches": n,
                                  "avg_launch_ms": ms / n if n else None}})
     print(json.dumps(out))
+
+
+def issue_rates(uot):
+    """Measured chip-wide rates (lane-operations/s) of v_exp_f32, float32 FMA and double FMA."""
+    return {"exp2": uot.probe_rate(uot.PROBE_EXP2), "fma32": uot.probe_rate(uot.PROBE_FMA32),
+            "fma64": uot.probe_rate(uot.PROBE_FMA64)}
 
 
 def cpu_baseline(pr, seconds):

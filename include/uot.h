@@ -418,6 +418,18 @@ void uot_profile_reset(void);
 int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries);
 
 /*
+ * Issue-rate probes, for benchmarks: the chip-wide throughput of one vector instruction kind
+ * on the current device, the rates behind the rooflines of the softmin (v_exp_f32), the
+ * backward (double and float32 FMAs) and the batched kernels. Each lane runs 8 independent
+ * dependency chains of the instruction (8 waves resident per SIMD); one untimed launch, then
+ * one launch timed with HIP events on `stream`. Writes lane-operations per second to
+ * *ops_per_s (host). Allocates and frees a small device buffer; synchronises `stream`.
+ * UOT_ERR_INVALID for an unknown kind or a NULL output, UOT_ERR_HIP on a runtime error.
+ */
+typedef enum { UOT_PROBE_EXP2 = 0, UOT_PROBE_FMA32 = 1, UOT_PROBE_FMA64 = 2 } uot_probe_kind;
+uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stream);
+
+/*
  * Implementation of the squared-Euclidean (p = 2) points softmin, process-wide:
  * 0 = default (3 up to dimension 16, 2 above), 1 = vector ALU, 2 = matrix cores on the
  * float32 exponent, 3 = matrix cores on the exponent split into bf16 pieces (three per

@@ -24,7 +24,7 @@ __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_ap
            "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
            "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
            "fw1d_batched", "fw1d", "fw1d_barycenter", "batched_set_plan",
-           "batched_trace", "batched_trace_read"]
+           "batched_trace", "batched_trace_read", "probe_rate"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -118,6 +118,8 @@ def load_library():
     lib.uot_profile_reset.restype = None
     lib.uot_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.uot_profile_read.restype = I64
+    lib.uot_probe_rate.argtypes = [I32, ctypes.POINTER(D), P]
+    lib.uot_probe_rate.restype = I32
     lib.uot_set_points_kernel.argtypes = [I32]
     lib.uot_set_points_kernel.restype = I32
     lib.uot_ti_sinkhorn_batched.argtypes = [I32, P, P, I32, D, P, P, P, P, P, P, P, I32, D, I32,
@@ -237,6 +239,18 @@ def profile_read(kind: int):
     ms, ent = ctypes.c_double(0.0), ctypes.c_double(0.0)
     n = load_library().uot_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(ent))
     return int(n), ms.value, ent.value
+
+
+PROBE_EXP2, PROBE_FMA32, PROBE_FMA64 = 0, 1, 2
+
+
+def probe_rate(kind: int) -> float:
+    """Measured chip-wide issue rate (lane-operations per second) of one vector instruction
+    kind on the current device: PROBE_EXP2 (v_exp_f32), PROBE_FMA32, PROBE_FMA64."""
+    _require_gpu()
+    out = ctypes.c_double(0.0)
+    _check(load_library().uot_probe_rate(int(kind), ctypes.byref(out), _stream()))
+    return out.value
 
 
 POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA_F32, POINTS_KERNEL_MFMA_BF16 = 0, 1, 2, 3

@@ -25,6 +25,7 @@ SOURCES = [
     "kernels_anderson.hip",
     "kernels_fw.hip",
     "kernels_grad.hip",
+    "kernels_probe.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -136,13 +136,13 @@ __global__ __launch_bounds__(256) void k_src_offsets(const float *h, const float
   out[s] = ws > 0.0f ? (float)((double)sc * (double)h[s] + log2((double)ws)) : -INFINITY;
 }
 
-__global__ __launch_bounds__(256) void k_sum(const float *w, int n, double *out) {
-  __shared__ double s[256];
+__global__ __launch_bounds__(1024) void k_sum(const float *w, int n, double *out) {
+  __shared__ double s[1024];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += (double)w[i];
+  for (int i = threadIdx.x; i < n; i += 1024) acc += (double)w[i];
   s[threadIdx.x] = acc;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = 512; off > 0; off >>= 1) {
     if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
     __syncthreads();
   }
@@ -185,7 +185,7 @@ hipError_t launch_apply_with_scratch(const ApplyArgs &a, void *scratch, hipStrea
 }
 
 hipError_t launch_sum(const float *w, int n, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, w, n, out);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, s, w, n, out);
   return hipGetLastError();
 }
 

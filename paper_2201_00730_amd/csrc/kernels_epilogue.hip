@@ -62,17 +62,41 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
 }
 
 // Zeroes the flags of the state and computes the common mean of x and y (points costs).
-__global__ __launch_bounds__(kBlock) void k_center(const float *x, int n, const float *y, int m,
-                                                   int d, SolveState *st) {
-  for (int k = 0; k < d; ++k) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += (double)x[(size_t)i * d + k];
-    for (int j = threadIdx.x; j < m; j += kBlock) s += (double)y[(size_t)j * d + k];
-    s = block_sum(s);
-    if (threadIdx.x == 0) st->mu[k] = s / (double)(n + m);
+// Centring, stage 1: block b sums the coordinates of its slice of the points of x | y into
+// part[b][k] (one double accumulator per dimension and thread, then one block sum per
+// dimension); stage 2 adds the block partials in a fixed order, so mu is reproducible.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_center_part(const float *x, int n, const float *y,
+                                                        int m, int d, double *part) {
+  const int tot = n + m;
+  const int chunk = (tot + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int p0 = blockIdx.x * chunk, p1 = min(tot, p0 + chunk);
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int q = p0 + threadIdx.x; q < p1; q += kBlock) {
+    const float *src = q < n ? x + (size_t)q * d : y + (size_t)(q - n) * d;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (k < d) acc[k] += (double)src[k];
   }
-  if (threadIdx.x == 0) {
-    for (int k = d; k < kMaxDim; ++k) st->mu[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double v = block_sum(acc[k]);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * kMaxDim + k] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_center(const double *part, int nb, int tot, int d,
+                                                   SolveState *st) {
+  const int k = threadIdx.x;
+  if (k < kMaxDim) {
+    double v = 0.0;
+    if (k < d)
+      for (int b = 0; b < nb; ++b) v += part[(size_t)b * kMaxDim + k];
+    st->mu[k] = k < d ? v / (double)tot : 0.0;
+  }
+  if (k == 0) {
     st->error = 0;
     st->done = 0;
     st->pos_a = 0;
@@ -80,6 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_center(const float *x, int n, const 
     st->iter = 0;
     st->fresh = 0;
   }
+}
+
+template <int D>
+hipError_t center_part_for(const float *x, int n, const float *y, int m, int d, int nb,
+                           double *part, hipStream_t s) {
+  hipLaunchKernelGGL((k_center_part<D>), dim3(nb), dim3(kBlock), 0, s, x, n, y, m, d, part);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kBlock) void k_validate(const float *a, int n, const float *b, int m,
@@ -257,8 +288,32 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_center, dim3(1), dim3(kBlock), 0, s, x, n, y, m, d, st);
+                         double *part, hipStream_t s) {
+  int nb = 0;
+  if (d > 0) {
+    nb = (n + m + kBlock - 1) / kBlock;
+    if (nb > kCenterBlocks) nb = kCenterBlocks;
+    hipError_t e = hipErrorInvalidValue;
+    switch (dim_bucket(d)) {
+      case 1: e = center_part_for<1>(x, n, y, m, d, nb, part, s); break;
+      case 2: e = center_part_for<2>(x, n, y, m, d, nb, part, s); break;
+      case 3: e = center_part_for<3>(x, n, y, m, d, nb, part, s); break;
+      case 4: e = center_part_for<4>(x, n, y, m, d, nb, part, s); break;
+      case 5: e = center_part_for<5>(x, n, y, m, d, nb, part, s); break;
+      case 6: e = center_part_for<6>(x, n, y, m, d, nb, part, s); break;
+      case 7: e = center_part_for<7>(x, n, y, m, d, nb, part, s); break;
+      case 8: e = center_part_for<8>(x, n, y, m, d, nb, part, s); break;
+      case 12: e = center_part_for<12>(x, n, y, m, d, nb, part, s); break;
+      case 16: e = center_part_for<16>(x, n, y, m, d, nb, part, s); break;
+      case 24: e = center_part_for<24>(x, n, y, m, d, nb, part, s); break;
+      case 32: e = center_part_for<32>(x, n, y, m, d, nb, part, s); break;
+      case 48: e = center_part_for<48>(x, n, y, m, d, nb, part, s); break;
+      case 64: e = center_part_for<64>(x, n, y, m, d, nb, part, s); break;
+      default: break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_center, dim3(1), dim3(kBlock), 0, s, part, nb, n + m, d, st);
   return hipGetLastError();
 }
 

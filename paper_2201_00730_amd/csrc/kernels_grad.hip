@@ -23,7 +23,7 @@
 // cost d2^{p/2} is taken in double as well.
 //
 // Reference. Each lane keeps a running reference r_t per target, an integer-valued float
-// raised to ceil(max e) whenever a tile of sources holds a larger exponent, so rescaling the
+// raised to ceil(e) whenever a source brings a larger exponent, so rescaling the
 // sums is a multiplication by a power of two (exact), and the entries that carry the sum have
 // e - r_t in [-few, 0] whatever the potentials, which keeps the float32 rounding of e - r_t
 // small where it matters. The combine takes the references exactly.
@@ -43,9 +43,6 @@ template <int D>
 constexpr int grad_targets_per_lane() {
   return D <= 8 ? 4 : (D <= 16 ? 2 : 1);
 }
-
-// Sources per tile of the running reference.
-constexpr int kTile = 4;
 
 template <int D>
 __global__ __launch_bounds__(256) void k_grad_records(GradRecordArgs a) {
@@ -135,53 +132,36 @@ __global__ __launch_bounds__(256) void k_grad_partial(GradArgs a) {
     return fma(-2.0, d0 + d1, yn[r] + rp[D]);
   };
 
-  for (int s = s0; s < s1; s += kTile) {
-    const int ns = min(kTile, s1 - s);
-    double e[kTile][R];
-    float wt[kTile][R];
-#pragma unroll
-    for (int j = 0; j < kTile; ++j) {
-      const double *rp = a.rec + (size_t)(s + (j < ns ? j : 0)) * SD;
-      const double bs = rp[D + 1];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double d2 = dist2(r, rp);
-        const double cst = cost_of<P2>(d2, half_p);
-        e[j][r] = j < ns ? fma(-sc, cst, bs) : -INFINITY;
-        wt[j][r] = GRAD ? weight_of<P2>(d2, cst, p) : 1.0f;
-      }
-    }
+  // One source per step: its record (D + 2 doubles, D floats) stays in scalar registers.
+  for (int s = s0; s < s1; ++s) {
+    const double *rp = a.rec + (size_t)s * SD;
+    const float *rf = reinterpret_cast<const float *>(rp + D + 2);
+    const double bs = rp[D + 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      double mt = e[0][r];
+      const double d2 = dist2(r, rp);
+      const double cst = cost_of<P2>(d2, half_p);
+      const double e = fma(-sc, cst, bs);
+      if (e > (double)ref[r]) {  // a new maximum: raise the reference to ceil(e)
+        const float mc = ceilf((float)e);
+        if (mc > ref[r]) {
+          const float scale = fexp2(ref[r] - mc);  // a power of two (or 0 from -FLT_MAX)
+          l[r] *= scale;
+          if constexpr (GRAD) {
+            lw[r] *= scale;
 #pragma unroll
-      for (int j = 1; j < kTile; ++j) mt = fmax(mt, e[j][r]);
-      const float mc = ceilf((float)mt);
-      if (mc > ref[r]) {
-        const float scale = fexp2(ref[r] - mc);  // a power of two (or 0 from -FLT_MAX)
-        l[r] *= scale;
-        if constexpr (GRAD) {
-          lw[r] *= scale;
-#pragma unroll
-          for (int k = 0; k < D; ++k) acc[r][k] *= scale;
+            for (int k = 0; k < D; ++k) acc[r][k] *= scale;
+          }
+          ref[r] = mc;
         }
-        ref[r] = mc;
       }
-    }
+      const float q = fexp2((float)(e - (double)ref[r]));
+      l[r] += q;
+      if constexpr (GRAD) {
+        const float qw = P2 ? q : q * weight_of<P2>(d2, cst, p);
+        if constexpr (!P2) lw[r] += qw;
 #pragma unroll
-    for (int j = 0; j < kTile; ++j) {
-      if (j >= ns) break;
-      const float *rf = reinterpret_cast<const float *>(a.rec + (size_t)(s + j) * SD + D + 2);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float q = fexp2((float)(e[j][r] - (double)ref[r]));
-        l[r] += q;
-        if constexpr (GRAD) {
-          const float qw = P2 ? q : q * wt[j][r];
-          if constexpr (!P2) lw[r] += qw;
-#pragma unroll
-          for (int k = 0; k < D; ++k) acc[r][k] = fmaf(qw, rf[k], acc[r][k]);
-        }
+        for (int k = 0; k < D; ++k) acc[r][k] = fmaf(qw, rf[k], acc[r][k]);
       }
     }
   }

@@ -175,6 +175,7 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
 struct Layout {
   size_t state = 0, pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, part = 0, bparts = 0;
   size_t dual = 0, scratch = 0, total = 0;
+  size_t center = 0;  // centring partials (kCenterBlocks * kMaxDim doubles)
   size_t grad_rec = 0, grad_part = 0, masses = 0;  // plan marginals and the backward
   size_t hist = 0, taus = 0, gram = 0, acc_c = 0;  // Anderson
   int64_t ldh = 0;
@@ -202,6 +203,7 @@ Layout make_layout(const uot_cost *c, int which) {
     return o;
   };
   L.state = take(sizeof(SolveState));
+  L.center = take((size_t)kCenterBlocks * kMaxDim * sizeof(double));
   L.pot_x = take((size_t)n * sizeof(float));
   L.pot_y = take((size_t)m * sizeof(float));
   L.rec_x = take((size_t)rec_count(n) * stride * sizeof(float));
@@ -280,10 +282,10 @@ struct PinnedState {
 
 // Common start of every call: flags, centring (points), weight validation.
 uot_status prepare(const uot_cost *c, const float *alpha, const float *beta, SolveState *st,
-                   hipStream_t s) {
+                   double *center_part, hipStream_t s) {
   const bool pts = c->kind == UOT_COST_POINTS;
   UOT_HIP(launch_center(pts ? c->x : nullptr, pts ? c->n : 0, pts ? c->y : nullptr,
-                        pts ? c->m : 0, pts ? c->d : 0, st, s));
+                        pts ? c->m : 0, pts ? c->d : 0, st, center_part, s));
   UOT_HIP(launch_validate(alpha, c->n, beta, c->m, st, s));
   return UOT_OK;
 }
@@ -686,7 +688,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   SolveState *hst = pin.h;
 
   // start: flags, centring, weights, records of x from f_0 (with Smin_alpha^rho1(f_0)), g = 0
-  UOT_TRY(prepare(c, alpha, beta, st, k.s));
+  UOT_TRY(prepare(c, alpha, beta, st, at<double>(k.ws, k.L.center), k.s));
   int nbx = 0;
   UOT_TRY(build_records(k, true, P->warm_start ? f : nullptr, true, true, &nbx));
   ReduceArgs ri;
@@ -800,7 +802,7 @@ uot_status dual_value(const uot_cost *c, const float *alpha, const float *beta, 
   UOT_TRY(acquire(w, workspace, workspace_bytes, k.L.total));
   k.ws = w.ptr;
   SolveState *st = k.st();
-  UOT_TRY(prepare(c, alpha, beta, st, k.s));
+  UOT_TRY(prepare(c, alpha, beta, st, at<double>(k.ws, k.L.center), k.s));
   UOT_TRY(build_records(k, false, g, false, false, nullptr));
   UOT_TRY(softmin_partials(k, false, nullptr));
   DualArgs da;
@@ -991,7 +993,7 @@ uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, 
   UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
   SolveState *st = at<SolveState>(w.ptr, L.state);
-  UOT_TRY(prepare(c, alpha, beta, st, s));
+  UOT_TRY(prepare(c, alpha, beta, st, at<double>(w.ptr, L.center), s));
   if (V == nullptr) {  // the marginals: row sums in one pass
     UOT_TRY(envelope_side(c, transpose == 0, alpha, beta, f, g, eps, 1.0, 1.0, st, w.ptr, L, out,
                           ldout, nullptr, nullptr, nullptr, s));
@@ -1034,7 +1036,7 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
   UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
   SolveState *st = at<SolveState>(w.ptr, L.state);
-  UOT_TRY(prepare(c, alpha, beta, st, s));
+  UOT_TRY(prepare(c, alpha, beta, st, at<double>(w.ptr, L.center), s));
   double *masses = at<double>(w.ptr, L.masses);  // [0] = m(beta), [1] = m(alpha)
   for (int side = 0; side < 2; ++side) {
     const bool tx = side == 0;  // targets are the x side

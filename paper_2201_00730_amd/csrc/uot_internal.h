@@ -274,8 +274,11 @@ struct RecordArgs {
 };
 hipError_t launch_build_records(const RecordArgs &a, hipStream_t st);
 
+// Centring mu of the points (mean of x | y) and the per-call flags of SolveState; part:
+// kCenterBlocks * kMaxDim doubles of device scratch.
+constexpr int kCenterBlocks = 64;
 hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
-                         hipStream_t s);
+                         double *part, hipStream_t s);
 hipError_t launch_validate(const float *a, int n, const float *b, int m, SolveState *st,
                            hipStream_t s);
 hipError_t launch_finalize(const float *pot, int n, double off_sel, int which, SolveState *st,
