@@ -204,6 +204,27 @@ Layout make_layout(const uot_cost *c, int which) {
   };
   L.state = take(sizeof(SolveState));
   L.center = take((size_t)kCenterBlocks * kMaxDim * sizeof(double));
+  const int nmax = n > m ? n : m;
+  if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
+    // the plan and the backward take no solver records: apply partials (plan with V), and
+    // for the one-pass marginals and gradients the source records of either side (points:
+    // doubles, grad_rec_stride; stored cost: one float) and split partials (gradient
+    // accumulators, or the stored-cost softmin partials with up to kMaxSplits splits)
+    if (which == UOT_WS_PLAN) {
+      const size_t a = apply_partial_bytes(n, m), b = apply_partial_bytes(m, n);
+      L.scratch = take(a > b ? a : b);
+    }
+    const bool pts = c->kind == UOT_COST_POINTS;
+    const int db = pts ? dim_bucket(d) : 0;
+    const size_t rb = pts ? grad_rec_stride(db) * sizeof(double) : sizeof(float);
+    L.grad_rec = take((size_t)rec_count(nmax) * rb);
+    const size_t ps = pts ? (size_t)kGradMaxSplits * grad_part_stride(db)
+                          : (size_t)kMaxSplits * grad_part_stride(0);
+    L.grad_part = take(ps * (size_t)nmax * sizeof(float));
+    L.masses = take(2 * sizeof(double));
+    L.total = off;
+    return L;
+  }
   L.pot_x = take((size_t)n * sizeof(float));
   L.pot_y = take((size_t)m * sizeof(float));
   L.rec_x = take((size_t)rec_count(n) * stride * sizeof(float));
@@ -213,26 +234,10 @@ Layout make_layout(const uot_cost *c, int which) {
   const size_t part_g = (size_t)kMaxSplits * m * sizeof(float2);
   const size_t part_f = (size_t)kMaxSplits * n * sizeof(float2);
   L.part = take(part_g > part_f ? part_g : part_f);
-  const int nmax = n > m ? n : m;
   const int nrec = (rec_count(nmax) + kBlock - 1) / kBlock;
   const int nbp = combine_blocks(nmax) > nrec ? combine_blocks(nmax) : nrec;
   L.bparts = take((size_t)(nbp + 1) * sizeof(BlockPart));
   L.dual = take((size_t)((nmax + kBlock - 1) / kBlock + 1) * 6 * sizeof(double));
-  if (which == UOT_WS_PLAN || which == UOT_WS_BACKWARD) {
-    const size_t a = apply_partial_bytes(n, m), b = apply_partial_bytes(m, n);
-    L.scratch = take(a > b ? a : b);
-    // one-pass marginals and gradients: source records of either side (points: doubles,
-    // grad_rec_stride; stored cost: one float), and split partials (gradient accumulators,
-    // or the stored-cost softmin partials with up to kMaxSplits splits)
-    const int db = c->kind == UOT_COST_POINTS ? dim_bucket(d) : 0;
-    const size_t rb = c->kind == UOT_COST_POINTS ? grad_rec_stride(db) * sizeof(double)
-                                                 : sizeof(float);
-    L.grad_rec = take((size_t)rec_count(nmax) * rb);
-    const size_t pg = (size_t)kGradMaxSplits * grad_part_stride(db);
-    const size_t pd = (size_t)kMaxSplits * grad_part_stride(0);
-    L.grad_part = take((pg > pd ? pg : pd) * (size_t)nmax * sizeof(float));
-    L.masses = take(2 * sizeof(double));
-  }
   if (which == UOT_WS_ANDERSON) {
     L.ldh = ((int64_t)n + 63) / 64 * 64;
     L.hist = take((size_t)(kAndersonMaxK + 1) * L.ldh * sizeof(float));
