@@ -271,6 +271,29 @@ uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *b
                         float *dx, float *dy, float *dalpha, float *dbeta, void *workspace,
                         size_t workspace_bytes, void *stream);
 
+/*
+ * uot_backward without any allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving or training loops, harnesses that forbid hipMalloc): the same
+ * kernels and results as uot_backward, with its workspace taken from a scratch array of
+ * UOT_NOALLOC_BYTES (96 MiB) that the library keeps in device memory on every GPU it runs on,
+ * from the library's load until the process ends. The array's address on a device is looked
+ * up on the first call made with that device current. The call allocates nothing: no
+ * hipMalloc, hipFree or host allocation, and no kernel timing (uot_profile_* does not apply).
+ *  - Limit: a problem whose UOT_WS_BACKWARD workspace (uot_workspace_bytes) exceeds
+ *    UOT_NOALLOC_BYTES gives UOT_ERR_WORKSPACE before any launch; with points that is above
+ *    n = m = 228,000 at D = 3 and above n = m = 70,000 at D = 16.
+ *  - The array keeps the last call's contents; each call writes every scratch value it reads,
+ *    so nothing has to start cleared.
+ *  - Every call on one GPU uses that GPU's one array: calls that overlap on one GPU (other
+ *    streams, other host threads) race on it and must be serialised by the caller.
+ * Arguments, outputs and error behaviour otherwise as uot_backward.
+ */
+#define UOT_NOALLOC_BYTES ((size_t)96 << 20)
+uot_status uot_backward_noalloc(const uot_cost *cost, const float *alpha, const float *beta,
+                                double eps, double rho1, double rho2, const float *f,
+                                const float *g, double grad_out, float *dx, float *dy,
+                                float *dalpha, float *dbeta, void *stream);
+
 /* Per-problem outcome of uot_ti_sinkhorn_batched (the status array). */
 enum {
   UOT_BATCH_CONVERGED = 0,  /* the tol test passed                                           */

@@ -24,7 +24,7 @@ __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_ap
            "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
            "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
            "fw1d_batched", "fw1d", "fw1d_barycenter", "batched_set_plan",
-           "batched_trace", "batched_trace_read", "probe_rate"]
+           "batched_trace", "batched_trace_read", "probe_rate", "backward_noalloc"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -108,6 +108,8 @@ def load_library():
     lib.uot_plan_apply.restype = ctypes.c_int
     lib.uot_backward.argtypes = [CP, P, P, D, D, D, P, P, D, P, P, P, P, P, S, P]
     lib.uot_backward.restype = ctypes.c_int
+    lib.uot_backward_noalloc.argtypes = [CP, P, P, D, D, D, P, P, D, P, P, P, P, P]
+    lib.uot_backward_noalloc.restype = ctypes.c_int
     lib.uot_status_string.argtypes = [ctypes.c_int]
     lib.uot_status_string.restype = ctypes.c_char_p
     lib.uot_last_error.argtypes = []
@@ -421,6 +423,35 @@ def backward(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: 
     _check(lib.uot_backward(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), float(eps), float(rho1),
                             float(rho2), _ptr(f), _ptr(g), float(grad_out), _ptr(dx), _ptr(dy), _ptr(da),
                             _ptr(db), _ptr(ws), ws.numel(), _stream()))
+    return dx, dy, da, db
+
+
+def backward_noalloc(alpha, beta, f, g, *, C=None, x=None, y=None, p: float = 2.0, eps: float,
+                     rho1: float, rho2: float | None = None, grad_out: float = 1.0,
+                     need_dx: bool = True, need_dy: bool = True, need_dalpha: bool = True,
+                     need_dbeta: bool = True, out=None):
+    """backward() through uot_backward_noalloc: no workspace, the library's scratch array.
+    out: optional (dx, dy, dalpha, dbeta) tensors to write (None entries are allocated here,
+    outside the call, as in backward())."""
+    _require_gpu()
+    lib = load_library()
+    cr = _CostRef(C, x, y, p)
+    rho2 = rho1 if rho2 is None else rho2
+    alpha, beta, f, g = (_f32(alpha, "alpha"), _f32(beta, "beta"), _f32(f, "f"), _f32(g, "g"))
+    dev = alpha.device
+    pts = cr.s.kind == UOT_COST_POINTS
+    dx, dy, da, db = out if out is not None else (None, None, None, None)
+    if dx is None and pts and need_dx:
+        dx = torch.empty((cr.n, cr.s.d), dtype=torch.float32, device=dev)
+    if dy is None and pts and need_dy:
+        dy = torch.empty((cr.m, cr.s.d), dtype=torch.float32, device=dev)
+    if da is None and need_dalpha:
+        da = torch.empty(cr.n, dtype=torch.float32, device=dev)
+    if db is None and need_dbeta:
+        db = torch.empty(cr.m, dtype=torch.float32, device=dev)
+    _check(lib.uot_backward_noalloc(ctypes.byref(cr.s), _ptr(alpha), _ptr(beta), float(eps),
+                                    float(rho1), float(rho2), _ptr(f), _ptr(g), float(grad_out),
+                                    _ptr(dx), _ptr(dy), _ptr(da), _ptr(db), _stream()))
     return dx, dy, da, db
 
 

@@ -16,6 +16,9 @@
 #include "uot_batched.h"
 #include "uot_internal.h"
 
+// Workspace of uot_backward_noalloc on each device (see noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[UOT_NOALLOC_BYTES];
+
 namespace uot {
 namespace {
 
@@ -873,7 +876,7 @@ uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const f
                          const float *f, const float *g, double eps, double rho_t, double gout,
                          SolveState *st, void *ws, const Layout &L, float *marg,
                          int64_t marg_stride, float *dw, const double *mass_other, float *dpts,
-                         hipStream_t s) {
+                         hipStream_t s, bool timed = true) {
   const bool dense = c->kind == UOT_COST_DENSE;
   const int nt = tx ? c->n : c->m, ns = tx ? c->m : c->n;
   const double sc = kLog2e / eps;
@@ -945,7 +948,7 @@ uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const f
     ga.p = (float)c->p;
     ga.grad = dpts != nullptr ? 1 : 0;
     ga.part = part;
-    Timer timer(profiling_enabled());
+    Timer timer(timed && profiling_enabled());
     hipError_t te = hipSuccess;
     const LaunchTiming *t = timer.on() ? timer.next(&te) : nullptr;
     UOT_HIP(te);
@@ -1021,7 +1024,7 @@ uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, 
 uot_status backward(const uot_cost *c, const float *alpha, const float *beta, double eps,
                     double rho1, double rho2, const float *f, const float *g, double grad_out,
                     float *dx, float *dy, float *dalpha, float *dbeta, void *workspace,
-                    size_t workspace_bytes, void *stream) {
+                    size_t workspace_bytes, void *stream, bool timed = true) {
   UOT_TRY(check_cost(c));
   UOT_TRY(check_scalars(eps, rho1, rho2));
   if (!std::isfinite(grad_out)) return fail(UOT_ERR_INVALID, "grad_out must be finite");
@@ -1050,13 +1053,58 @@ uot_status backward(const uot_cost *c, const float *alpha, const float *beta, do
     if (dpts == nullptr && dw == nullptr) continue;
     if (dw) UOT_HIP(launch_sum(tx ? beta : alpha, tx ? c->m : c->n, masses + side, s));
     UOT_TRY(envelope_side(c, tx, alpha, beta, f, g, eps, tx ? rho1 : rho2, grad_out, st, w.ptr, L,
-                          nullptr, 1, dw, masses + side, dpts, s));
+                          nullptr, 1, dw, masses + side, dpts, s, timed));
   }
   SolveState fin;
   UOT_TRY(read_state(st, fin, s));
   if ((fin.error & kErrWeights) || !fin.pos_a || !fin.pos_b)
     return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
   return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free backward. Its workspace is `scratch`, a device array of UOT_NOALLOC_BYTES
+// that every GPU holds from the library's load until the process ends. In host code the
+// array's name only stands in for it: its address on a device comes from
+// hipGetSymbolAddress, looked up once per device (with that device current) on the first
+// call there, and only that address is ever passed to kernels.
+// ---------------------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+uot_status noalloc_scratch(void **out) {
+  int dev = -1;
+  UOT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(UOT_ERR_INVALID, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(UOT_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return UOT_OK;
+}
+
+uot_status backward_noalloc(const uot_cost *c, const float *alpha, const float *beta, double eps,
+                            double rho1, double rho2, const float *f, const float *g,
+                            double grad_out, float *dx, float *dy, float *dalpha, float *dbeta,
+                            void *stream) {
+  UOT_TRY(check_cost(c));
+  const size_t need = make_layout(c, UOT_WS_BACKWARD).total;
+  if (need > UOT_NOALLOC_BYTES)
+    return fail(UOT_ERR_WORKSPACE,
+                "the backward of this problem needs %zu bytes of workspace; the allocation-free "
+                "entry point holds %zu (use uot_backward)", need, (size_t)UOT_NOALLOC_BYTES);
+  void *ws = nullptr;
+  UOT_TRY(noalloc_scratch(&ws));
+  return backward(c, alpha, beta, eps, rho1, rho2, f, g, grad_out, dx, dy, dalpha, dbeta, ws,
+                  UOT_NOALLOC_BYTES, stream, false);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1663,6 +1711,15 @@ uot_status uot_backward(const uot_cost *cost, const float *alpha, const float *b
   uot::g_last_error.clear();
   return uot::backward(cost, alpha, beta, eps, rho1, rho2, f, g, grad_out, dx, dy, dalpha, dbeta,
                        workspace, workspace_bytes, stream);
+}
+
+uot_status uot_backward_noalloc(const uot_cost *cost, const float *alpha, const float *beta,
+                                double eps, double rho1, double rho2, const float *f,
+                                const float *g, double grad_out, float *dx, float *dy,
+                                float *dalpha, float *dbeta, void *stream) {
+  uot::g_last_error.clear();
+  return uot::backward_noalloc(cost, alpha, beta, eps, rho1, rho2, f, g, grad_out, dx, dy,
+                               dalpha, dbeta, stream);
 }
 
 int32_t uot_set_points_kernel(int32_t variant) {

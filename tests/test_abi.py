@@ -229,3 +229,16 @@ def test_anderson_rejects_bad_normalize_flag(lib):
                                           ctypes.byref(acc), None, None, None, 0, None, None)
         assert st == uot.UOT_ERR_INVALID
         assert b"normalize" in lib.uot_last_error()
+
+
+def test_noalloc_backward_rejects_a_problem_beyond_its_scratch_array(lib):
+    """The allocation-free backward refuses, before any launch, a problem whose backward
+    workspace exceeds UOT_NOALLOC_BYTES (96 MiB), and one with a bad cost."""
+    big = _cost(n=400000, m=400000, d=3)
+    assert lib.uot_workspace_bytes(ctypes.byref(big), uot.UOT_WS_BACKWARD) > 96 << 20
+    st = lib.uot_backward_noalloc(ctypes.byref(big), None, None, 0.1, 1.0, 1.0, None, None, 1.0,
+                                  None, None, None, None, None)
+    assert st == uot.UOT_ERR_WORKSPACE
+    assert b"allocation-free" in lib.uot_last_error()
+    assert lib.uot_backward_noalloc(ctypes.byref(_cost(n=0)), None, None, 0.1, 1.0, 1.0, None,
+                                    None, 1.0, None, None, None, None, None) == uot.UOT_ERR_INVALID
