@@ -492,6 +492,7 @@ def extra_workload(args, uot, torch, np, workloads):
                     "config": {"workload": "D=16 clouds N=M=50,000, eps=0.05, rho=1, TI to 1e-6 "
                                            "then the envelope backward"},
                     "iters": info.iters, "converged": info.converged, "forward_seconds": dt,
+                    "points_form": ("direct" if info.points_form == 1 else "expanded"),
                     "backward_seconds": dtb,
                     "backward_roofline": {
                         "bound": "alu", "achieved": flops_b / 1e12, "peak": peak_b / 1e12,

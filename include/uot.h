@@ -67,14 +67,21 @@ typedef enum {
  *  kind = UOT_COST_POINTS: x is [n, d], y is [m, d] (row-major float32), 1 <= d <= 64,
  *                          p >= 1 (p = 2 is the squared Euclidean cost and takes the
  *                          fastest path). C and ldc unused.
- *                          Accuracy of p = 2: the exponent is evaluated in the expanded
- *                          form |x|^2 + |y|^2 - 2<x, y> on points centred on their common
- *                          mean, whose float32 rounding is about
- *                          2^-24 (d + 4) (max|x - mu| + max|y - mu|)^2 per softmin in
- *                          potential units, whatever eps. Where the potentials are not
- *                          well above that (tiny eps with clouds of large spread), the
- *                          direct-difference p = 2 softmin (uot_set_points_kernel(4)) or a
- *                          stored cost is more accurate.
+ *                          Accuracy of p = 2: by default the solvers' softmins evaluate
+ *                          the exponent in the expanded form |x|^2 + |y|^2 - 2<x, y> on
+ *                          points centred on their common mean (matrix cores), whose
+ *                          float32 rounding is about E = 2^-24 (d + 4) (max|x - mu| +
+ *                          max|y - mu|)^2 per softmin in potential units, i.e.
+ *                          delta = E log2(e) / eps in the exponent. The solvers switch to
+ *                          direct differences x - y (vector ALU, as uot_set_points_kernel(4))
+ *                          by themselves where that rounding could reach the 1e-5 relative
+ *                          accuracy of the potentials: delta > 3e-4 and
+ *                          E min(max_iter, 1 / (1 - k1 k2)) / min(|f|_inf, |g|_inf) > 3e-5,
+ *                          with k_i = rho_i / (eps + rho_i) and the norms read after the
+ *                          first iteration (the solve then restarts in the direct form;
+ *                          uot_info.points_form says which form ran). uot_dual_value takes
+ *                          the direct form for p = 2; the backward and the marginals form the
+ *                          exponent in double precision.
  * n (size of alpha, the "source" side) and m (size of beta) are >= 1.
  */
 typedef struct {
@@ -114,6 +121,9 @@ typedef struct {
   int32_t converged;    /* 1 if the tol test passed, else 0 (max_iter reached or tol = 0)  */
   double last_change;   /* the change measured at the last iteration (inf after one)       */
   double lambda;        /* TI: lambda*(fb, gb) of Prop. 2 at the last iterate; plain: 0    */
+  int32_t points_form;  /* p = 2 points cost: the exponent form the softmins used, 0 the
+                           expanded form on centred points, 1 direct differences (see
+                           uot_set_points_kernel); -1 for other costs                       */
 } uot_info;
 
 enum {

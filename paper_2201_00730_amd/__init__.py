@@ -63,7 +63,8 @@ class _Phi(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("last_change", ctypes.c_double), ("lambda_", ctypes.c_double)]
+                ("last_change", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("points_form", ctypes.c_int32)]
 
 
 @dataclass
@@ -72,6 +73,7 @@ class Info:
     converged: bool
     last_change: float
     lam: float
+    points_form: int = -1  # p = 2 points: 0 expanded form, 1 direct differences; else -1
 
 
 def library_path() -> str:
@@ -310,7 +312,8 @@ def _solve(name: str, alpha, beta, *, C=None, x=None, y=None, p: float = 2.0, ep
     st = getattr(lib, name)(*args, _ptr(f), _ptr(g), _ptr(ws), ws.numel(), ctypes.byref(info),
                             _stream())
     _check(st)
-    return f, g, Info(info.iters, bool(info.converged), info.last_change, info.lambda_)
+    return f, g, Info(info.iters, bool(info.converged), info.last_change, info.lambda_,
+                      info.points_form)
 
 
 def sinkhorn(alpha, beta, **kw):

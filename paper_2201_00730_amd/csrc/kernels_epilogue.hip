@@ -106,6 +106,87 @@ __global__ __launch_bounds__(kBlock) void k_center(const double *part, int nb, i
   }
 }
 
+// Spread of the centred clouds, stage 1: block b writes the largest |x - mu|^2 and
+// |y - mu|^2 of its slice of x | y to part[2b], part[2b + 1]; stage 2 (one block) takes the
+// maxima.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_span_part(const float *x, int n, const float *y,
+                                                      int m, int d, const SolveState *st,
+                                                      double *part) {
+  __shared__ double sx[kBlock], sy[kBlock];
+  const int tot = n + m;
+  const int chunk = (tot + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int p0 = blockIdx.x * chunk, p1 = min(tot, p0 + chunk);
+  double mx = 0.0, my = 0.0;
+  for (int q = p0 + threadIdx.x; q < p1; q += kBlock) {
+    const float *src = q < n ? x + (size_t)q * d : y + (size_t)(q - n) * d;
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (k < d) {
+        const double v = (double)src[k] - st->mu[k];
+        r2 = fma(v, v, r2);
+      }
+    if (q < n) mx = fmax(mx, r2); else my = fmax(my, r2);
+  }
+  sx[threadIdx.x] = mx;
+  sy[threadIdx.x] = my;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      sx[threadIdx.x] = fmax(sx[threadIdx.x], sx[threadIdx.x + off]);
+      sy[threadIdx.x] = fmax(sy[threadIdx.x], sy[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sx[0];
+    part[2 * blockIdx.x + 1] = sy[0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_span(const double *part, int nb, SolveState *st) {
+  if (threadIdx.x != 0) return;
+  double mx = 0.0, my = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    mx = fmax(mx, part[2 * b]);
+    my = fmax(my, part[2 * b + 1]);
+  }
+  st->span_x2 = mx;
+  st->span_y2 = my;
+}
+
+// max |stored + offset| over each side's potentials (one block; runs once per solve).
+__global__ __launch_bounds__(1024) void k_pot_absmax(const float *pf, int n, const float *pg, int m,
+                                                     SolveState *st) {
+  __shared__ double sf[1024], sg[1024];
+  const double of = st->off_f_prev, og = st->off_g_prev;
+  double af = 0.0, ag = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) af = fmax(af, fabs((double)pf[i] + of));
+  for (int j = threadIdx.x; j < m; j += 1024) ag = fmax(ag, fabs((double)pg[j] + og));
+  sf[threadIdx.x] = af;
+  sg[threadIdx.x] = ag;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      sf[threadIdx.x] = fmax(sf[threadIdx.x], sf[threadIdx.x + off]);
+      sg[threadIdx.x] = fmax(sg[threadIdx.x], sg[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->fabs_max = sf[0];
+    st->gabs_max = sg[0];
+  }
+}
+
+template <int D>
+hipError_t span_part_for(const float *x, int n, const float *y, int m, int d, int nb,
+                         const SolveState *st, double *part, hipStream_t s) {
+  hipLaunchKernelGGL((k_span_part<D>), dim3(nb), dim3(kBlock), 0, s, x, n, y, m, d, st, part);
+  return hipGetLastError();
+}
+
 template <int D>
 hipError_t center_part_for(const float *x, int n, const float *y, int m, int d, int nb,
                            double *part, hipStream_t s) {
@@ -314,6 +395,39 @@ hipError_t launch_center(const float *x, int n, const float *y, int m, int d, So
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_center, dim3(1), dim3(kBlock), 0, s, part, nb, n + m, d, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_span(const float *x, int n, const float *y, int m, int d, SolveState *st,
+                       double *part, hipStream_t s) {
+  int nb = (n + m + kBlock - 1) / kBlock;
+  if (nb > kCenterBlocks) nb = kCenterBlocks;
+  hipError_t e = hipErrorInvalidValue;
+  switch (dim_bucket(d)) {
+    case 1: e = span_part_for<1>(x, n, y, m, d, nb, st, part, s); break;
+    case 2: e = span_part_for<2>(x, n, y, m, d, nb, st, part, s); break;
+    case 3: e = span_part_for<3>(x, n, y, m, d, nb, st, part, s); break;
+    case 4: e = span_part_for<4>(x, n, y, m, d, nb, st, part, s); break;
+    case 5: e = span_part_for<5>(x, n, y, m, d, nb, st, part, s); break;
+    case 6: e = span_part_for<6>(x, n, y, m, d, nb, st, part, s); break;
+    case 7: e = span_part_for<7>(x, n, y, m, d, nb, st, part, s); break;
+    case 8: e = span_part_for<8>(x, n, y, m, d, nb, st, part, s); break;
+    case 12: e = span_part_for<12>(x, n, y, m, d, nb, st, part, s); break;
+    case 16: e = span_part_for<16>(x, n, y, m, d, nb, st, part, s); break;
+    case 24: e = span_part_for<24>(x, n, y, m, d, nb, st, part, s); break;
+    case 32: e = span_part_for<32>(x, n, y, m, d, nb, st, part, s); break;
+    case 48: e = span_part_for<48>(x, n, y, m, d, nb, st, part, s); break;
+    case 64: e = span_part_for<64>(x, n, y, m, d, nb, st, part, s); break;
+    default: break;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_span, dim3(1), dim3(kBlock), 0, s, part, nb, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pot_absmax(const float *pf, int n, const float *pg, int m, SolveState *st,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_pot_absmax, dim3(1), dim3(1024), 0, s, pf, n, pg, m, st);
   return hipGetLastError();
 }
 

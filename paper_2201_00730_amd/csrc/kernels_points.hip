@@ -27,16 +27,19 @@ constexpr int kTile = 8;
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 
-template <int MODE>
+template <bool P2>
 __device__ __forceinline__ float cost_pow(float d2, float half_p) {
-  // ||x - y||^p from the squared distance: p = 2 is d2 itself, p = 1 takes a square root,
-  // otherwise 2^{(p/2) log2 d2} (d2 = 0 gives log2 = -inf and the power 0).
-  if (half_p == 1.0f) return d2;
-  if (half_p == 0.5f) return __builtin_sqrtf(d2);
-  return fast_exp2(half_p * fast_log2(d2));
+  // ||x - y||^p from the squared distance: p = 2 (compiled apart) is d2 itself, p = 1 takes
+  // a square root, otherwise 2^{(p/2) log2 d2} (d2 = 0 gives log2 = -inf and the power 0).
+  if constexpr (P2) {
+    return d2;
+  } else {
+    if (half_p == 0.5f) return __builtin_sqrtf(d2);
+    return fast_exp2(half_p * fast_log2(d2));
+  }
 }
 
-template <int D, int MODE, int R>
+template <int D, int MODE, int R, bool P2>
 __global__ __launch_bounds__(256) void k_points_partial(PointsArgs a) {
   if (a.done != nullptr && get_done(a.done)) return;
   constexpr int SD = rec_stride(MODE, D);
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(256) void k_points_partial(PointsArgs a) {
         const float u = rp[d] - y[r][d];
         d2 = fmaf(u, u, d2);
       }
-      return fmaf(-sc, cost_pow<MODE>(d2, half_p), rp[D]);
+      return fmaf(-sc, cost_pow<P2>(d2, half_p), rp[D]);
     }
   };
 
@@ -119,14 +122,16 @@ __global__ __launch_bounds__(256) void k_points_partial(PointsArgs a) {
 
 template <int D>
 constexpr int targets_per_thread() {
-  return D <= 4 ? 4 : (D <= 8 ? 2 : 1);
+  return D <= 4 ? 4 : (D <= 16 ? 2 : 1);
 }
 
 template <int D, int MODE>
 hipError_t launch_bucket(const PointsArgs &a, hipStream_t st, const LaunchTiming *t) {
   constexpr int R = targets_per_thread<D>();
   dim3 grid((a.nt + 256 * R - 1) / (256 * R), a.nsplit);
-  return launch_timed(k_points_partial<D, MODE, R>, grid, dim3(256), st, t, a);
+  if (MODE == kPower && a.half_p == 1.0f)
+    return launch_timed(k_points_partial<D, MODE, R, true>, grid, dim3(256), st, t, a);
+  return launch_timed(k_points_partial<D, MODE, R, false>, grid, dim3(256), st, t, a);
 }
 
 template <int MODE>
@@ -280,8 +285,8 @@ int mfma_occupancy(const PointsArgs &a) {
 template <int D>
 int valu_occupancy(int mode) {
   constexpr int R = targets_per_thread<D>();
-  return mode == kSqEuc ? occupancy_blocks(k_points_partial<D, kSqEuc, R>)
-                        : occupancy_blocks(k_points_partial<D, kPower, R>);
+  return mode == kSqEuc ? occupancy_blocks(k_points_partial<D, kSqEuc, R, false>)
+                        : occupancy_blocks(k_points_partial<D, kPower, R, true>);
 }
 
 }  // namespace
@@ -334,7 +339,7 @@ int points_blocks_per_cu(int mode, int d) {
 int points_targets_per_block(int mode, int d) {
   if (points_uses_mfma(mode, d)) return kMfmaWaves * 32;
   const int b = dim_bucket(d);
-  return 256 * (b <= 4 ? 4 : (b <= 8 ? 2 : 1));
+  return 256 * (b <= 4 ? 4 : (b <= 16 ? 2 : 1));
 }
 
 int points_split_align(int mode, int d) { return points_uses_mfma(mode, d) ? 32 : 8; }

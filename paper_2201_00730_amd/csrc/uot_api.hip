@@ -185,9 +185,9 @@ struct Layout {
   HalfShape g, f;  // g-step: targets y (columns), sources x; f-step: targets x (rows), sources y
 };
 
-Layout make_layout(const uot_cost *c, int which) {
+Layout make_layout(const uot_cost *c, int which, int mode_override = -1) {
   Layout L;
-  const int mode = rec_mode_of(c);
+  const int mode = mode_override >= 0 ? mode_override : rec_mode_of(c);
   const int d = c->kind == UOT_COST_POINTS ? c->d : 0;
   const int n = c->n, m = c->m;
   // records sized for every p = 2 record form, so the size does not depend on the
@@ -654,10 +654,26 @@ uot_status check_phi(const uot_phi *phi) {
   return UOT_OK;
 }
 
+// Choice of the p = 2 points softmin form (see uot_cost in uot.h): the expanded form's
+// float32 rounding E = 2^-24 (d + 4) (max|x - mu| + max|y - mu|)^2 (potential units) is a
+// risk to the 1e-5 relative accuracy of the potentials when its share of the exponent,
+// delta = E log2(e) / eps, is large (few entries carry each softmin, so the roundings do
+// not average out) and when it can pile up against small potentials: over up to
+// 1 / (1 - k1 k2) iterations (the slowest contraction of Sec. 3). Thresholds measured on
+// 1-D/2-D/3-D/16-D clouds at eps from 3e-4 to 0.5 and rho from 0.1 to 10 (TI and plain,
+// 30 and 300 iterations against the oracle): every case above 5e-6 has delta > 1e-3 and
+// Q > 1.1e-4; the error stayed below 0.2 Q where delta > 3e-4.
+constexpr double kFormDelta = 3e-4, kFormQ = 3e-5;
+
+double expanded_form_rounding(const uot_cost *c, const SolveState &h) {
+  const double span = std::sqrt(h.span_x2) + std::sqrt(h.span_y2);
+  return std::ldexp(1.0, -24) * (c->d + 4) * span * span;
+}
+
 uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const uot_params *P,
                  float *f, float *g, void *workspace, size_t workspace_bytes, uot_info *info,
                  void *stream, bool ti, const uot_anderson *acc = nullptr,
-                 const uot_phi *phi = nullptr) {
+                 const uot_phi *phi = nullptr, bool direct = false) {
   UOT_TRY(check_cost(c));
   UOT_TRY(check_params(P));
   UOT_TRY(check_cost_ptrs(c));
@@ -667,7 +683,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   UOT_TRY(check_device_ptr(g, "g"));
   Ctx k;
   k.c = c;
-  k.mode = rec_mode_of(c);
+  k.mode = direct ? kPower : rec_mode_of(c);
   k.d = c->kind == UOT_COST_POINTS ? c->d : 0;
   k.n = c->n;
   k.m = c->m;
@@ -682,7 +698,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
     k.entropy = phi->entropy == UOT_ENTROPY_BERG ? kEntropyBerg : kEntropyKL;
     k.gvar = phi->variant == UOT_SINKHORN_G;
   }
-  k.L = make_layout(c, acc ? UOT_WS_ANDERSON : UOT_WS_SOLVE);
+  k.L = make_layout(c, acc ? UOT_WS_ANDERSON : UOT_WS_SOLVE, k.mode);
   k.s = static_cast<hipStream_t>(stream);
   Workspace w;
   UOT_TRY(acquire(w, workspace, workspace_bytes, k.L.total));
@@ -690,6 +706,9 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   SolveState *st = k.st();
   Timer timer(profiling_enabled());
   k.timer = timer.on() ? &timer : nullptr;
+  // the p = 2 form check (default setting only; an explicit setting is obeyed)
+  const bool check_form = !direct && c->kind == UOT_COST_POINTS && c->p == 2.0 &&
+                          g_points_variant == kPointsAuto && k.mode != kPower;
 
   PinnedState pin;
   UOT_HIP(hipHostMalloc(reinterpret_cast<void **>(&pin.h), 2 * sizeof(SolveState), hipHostMallocDefault));
@@ -697,6 +716,8 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
 
   // start: flags, centring, weights, records of x from f_0 (with Smin_alpha^rho1(f_0)), g = 0
   UOT_TRY(prepare(c, alpha, beta, st, at<double>(k.ws, k.L.center), k.s));
+  if (check_form)
+    UOT_HIP(launch_span(c->x, c->n, c->y, c->m, c->d, st, at<double>(k.ws, k.L.center), k.s));
   int nbx = 0;
   UOT_TRY(build_records(k, true, P->warm_start ? f : nullptr, true, true, &nbx));
   ReduceArgs ri;
@@ -721,6 +742,9 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   UOT_TRY(read_state(st, hst[0], k.s));
   if (hst[0].error & kErrWeights)
     return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
+  // expanded-form rounding against eps now; against the potentials after iteration 1
+  const double form_e = check_form ? expanded_form_rounding(c, hst[0]) : 0.0;
+  const bool check_q = check_form && form_e * kLog2e / P->eps > kFormDelta;
 
   // iterations, in chunks of check_every; the host reads the convergence flag one chunk late
   // so the GPU always has queued work (solver kernels return at once after convergence)
@@ -752,6 +776,18 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
       } else {
         UOT_TRY(half_step(k, false, P->tol, P->check_every));
       }
+      if (it == 1 && check_q) {
+        UOT_TRY(flush_reduce(k));
+        UOT_HIP(launch_pot_absmax(at<float>(k.ws, k.L.pot_x), k.n, at<float>(k.ws, k.L.pot_y),
+                                  k.m, st, k.s));
+        UOT_TRY(read_state(st, hst[0], k.s));
+        const double k1 = P->rho1 / (P->eps + P->rho1), k2 = P->rho2 / (P->eps + P->rho2);
+        const double amp = std::fmin((double)P->max_iter, 1.0 / (1.0 - k1 * k2));
+        const double hmin = std::fmin(hst[0].fabs_max, hst[0].gabs_max);
+        if (!(form_e * amp <= kFormQ * hmin))  // (also when a norm is 0 or not finite)
+          return solve(c, alpha, beta, P, f, g, w.ptr, w.owned ? k.L.total : workspace_bytes,
+                       info, stream, ti, acc, phi, true);  // same workspace size in both forms
+      }
     }
     issued += todo;
     UOT_TRY(flush_reduce(k));
@@ -775,6 +811,8 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
     info->converged = (checking && fin.done && !fin.error) ? 1 : 0;
     info->last_change = fin.delta;
     info->lambda = fin.lambda;
+    info->points_form = (c->kind == UOT_COST_POINTS && c->p == 2.0) ? (k.mode == kPower ? 1 : 0)
+                                                                    : -1;
   }
   if (fin.error & kErrNumeric) return fail(UOT_ERR_NUMERIC, "non-finite potentials after %d iterations", fin.iter);
   return UOT_OK;
@@ -793,7 +831,11 @@ uot_status dual_value(const uot_cost *c, const float *alpha, const float *beta, 
   UOT_TRY(check_device_ptr(g, "g"));
   Ctx k;
   k.c = c;
-  k.mode = rec_mode_of(c);
+  // p = 2 points: direct differences under the default setting (an error E in a softmin is
+  // an error E / eps relative in m(pi))
+  k.mode = (c->kind == UOT_COST_POINTS && c->p == 2.0 && g_points_variant == kPointsAuto)
+               ? kPower
+               : rec_mode_of(c);
   k.d = c->kind == UOT_COST_POINTS ? c->d : 0;
   k.n = c->n;
   k.m = c->m;
@@ -804,7 +846,7 @@ uot_status dual_value(const uot_cost *c, const float *alpha, const float *beta, 
   k.rho2 = rho2;
   k.sc = kLog2e / eps;
   k.ti = false;
-  k.L = make_layout(c, UOT_WS_DUAL);
+  k.L = make_layout(c, UOT_WS_DUAL, k.mode);
   k.s = static_cast<hipStream_t>(stream);
   Workspace w;
   UOT_TRY(acquire(w, workspace, workspace_bytes, k.L.total));

@@ -98,6 +98,10 @@ struct SolveState {
   int32_t pos_b;      // some beta_j > 0
   int32_t fresh;      // 1 after an Anderson extrapolation: the next change is +inf
   double lam_step;    // G-Sinkhorn, Berg entropy: lambda*(stored f, stored g) of this step
+  double span_x2;     // max_i |x_i - mu|^2 and max_j |y_j - mu|^2 (p = 2 form check)
+  double span_y2;
+  double fabs_max;    // max |f| and max |g| of the reported potentials (p = 2 form check)
+  double gabs_max;
   double mu[kMaxDim]; // common centring of x and y (points costs)
 };
 
@@ -279,6 +283,13 @@ hipError_t launch_build_records(const RecordArgs &a, hipStream_t st);
 constexpr int kCenterBlocks = 64;
 hipError_t launch_center(const float *x, int n, const float *y, int m, int d, SolveState *st,
                          double *part, hipStream_t s);
+// max |x - mu|^2 and max |y - mu|^2 into st->span_x2, st->span_y2 (after launch_center; part
+// as there), and max |f| and max |g| of the reported potentials (stored value plus the
+// offsets of the last F-reduction) into st->fabs_max, st->gabs_max.
+hipError_t launch_span(const float *x, int n, const float *y, int m, int d, SolveState *st,
+                       double *part, hipStream_t s);
+hipError_t launch_pot_absmax(const float *pf, int n, const float *pg, int m, SolveState *st,
+                             hipStream_t s);
 hipError_t launch_validate(const float *a, int n, const float *b, int m, SolveState *st,
                            hipStream_t s);
 hipError_t launch_finalize(const float *pot, int n, double off_sel, int which, SolveState *st,

@@ -450,21 +450,44 @@ def expanded_form_bound(pr, d, iters):
 @pytest.mark.parametrize("ti", [True, False])
 @pytest.mark.parametrize("eps,rho1,rho2", EXTREME)
 def test_extreme_parameters(eps, rho1, rho2, ti, dense):
-    """Stored costs meet 1e-5. The points path meets 1e-5 or, where the potentials are small
-    against the squared spread of the clouds (eps = 1e-4 and 1e-3 here, |f| ~ 0.05-0.2),
-    the derived bound of its expanded-form exponent (expanded_form_bound)."""
+    """Stored costs and the default points path meet 1e-5. Where the expanded form's rounding
+    would not (eps = 1e-4 and 1e-3 here, |f| ~ 0.05-0.2 against clouds of spread ~1.4), the
+    solver switches to direct differences by itself (uot_info.points_form = 1)."""
     pr = workloads.random_small(150, 97, d=2, seed=17, eps=eps, rho1=rho1, rho2=rho2, p=2.0,
                                 dense=dense)
-    bound = 0.0 if dense else expanded_form_bound(pr, 2, 30)
     if dense:
         pr.x = pr.y = None
     _say("extreme eps=%g rho=(%g, %g) ti=%s dense=%s" % (eps, rho1, rho2, ti, dense))
     f, g, info = run_gpu(pr, ti, 30)
     r = run_oracle(pr, ti, 30)
-    _say("  rel f %.3g g %.3g (bound %.3g)" % (rel_inf(f, r.f), rel_inf(g, r.g), bound))
+    _say("  rel f %.3g g %.3g (form %d, expanded-form bound %.3g)"
+         % (rel_inf(f, r.f), rel_inf(g, r.g), info.points_form,
+            0.0 if dense else expanded_form_bound(pr, 2, 30)))
     assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
-    for u, v in ((f, r.f), (g, r.g)):
-        assert np.max(np.abs(u - v)) <= max(TOL * np.max(np.abs(v)), bound), (rel_inf(u, v), bound)
+    if dense:
+        assert info.points_form == -1
+    assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL, (rel_inf(f, r.f), rel_inf(g, r.g))
+
+
+def test_p2_form_choice():
+    """The default p = 2 setting keeps the expanded (matrix-core) form where its rounding is
+    small against eps and the potentials, switches to direct differences where it is not,
+    and an explicit setting is obeyed."""
+    big = workloads.random_small(300, 211, d=3, seed=5, eps=0.5, rho1=1.0, rho2=1.0)
+    tiny = workloads.random_small(300, 211, d=3, seed=5, eps=1e-4, rho1=1.0, rho2=1.0)
+    assert run_gpu(big, True, 30)[2].points_form == 0
+    f, g, info = run_gpu(tiny, True, 30)
+    assert info.points_form == 1
+    r = run_oracle(tiny, True, 30)
+    assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL
+    prev = uot.set_points_kernel(uot.POINTS_KERNEL_MFMA_BF16)
+    try:
+        assert run_gpu(tiny, True, 30)[2].points_form == 0
+    finally:
+        uot.set_points_kernel(prev)
+    dense = workloads.random_small(30, 21, d=3, seed=5, eps=1e-4, dense=True)
+    dense.x = dense.y = None
+    assert run_gpu(dense, True, 2)[2].points_form == -1
 
 
 @pytest.mark.parametrize("ti", [True, False])
