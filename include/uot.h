@@ -408,14 +408,25 @@ size_t uot_fw1d_barycenter_workspace_bytes(int32_t B, int32_t K, const int64_t *
 size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d);
 
 /*
- * Work-item plan of uot_ti_sinkhorn_batched, process-wide (for tests and benchmarks; results
- * do not depend on it): 0 = automatic (coarse items of up to 256 targets, four per lane,
- * then fine items of up to 128 targets, two per lane, once few coarse items remain), 1 = coarse
- * items throughout, 2 = fine items throughout, 3 = coarse for the first chunk of iterations,
- * fine after it. Returns the previous setting, or -1 for an unknown value (nothing changes).
- * Must not be changed while a batched solve runs.
+ * Work-item plan of uot_ti_sinkhorn_batched, process-wide (for tests and benchmarks; the plan
+ * only changes how targets are grouped into work items, i.e. the order of the per-problem
+ * partial sums): 0 = automatic and autotuned (coarse items of up to 256 targets, four per lane,
+ * then fine items of up to 128 targets, two per lane, once the busier side has at most
+ * tau x (resident waves) coarse items; for each size signature - device, B, d, check_every,
+ * tol > 0 and the log2 sizes of sum N, sum M, max N, max M - the first seven calls each run
+ * one tau of {0 (coarse throughout), 0.5, 1, 2, 4, 8, fine from the start}, timed on the host,
+ * and later calls take the fastest), 1 = coarse items throughout, 2 = fine items throughout,
+ * 3 = coarse for the first chunk of iterations, fine after it. Returns the previous setting,
+ * or -1 for an unknown value (nothing changes). Must not be changed while a batched solve runs.
  */
 int32_t uot_batched_set_plan(int32_t plan);
+
+/* The switch threshold tau the calling thread's last uot_ti_sinkhorn_batched call used under
+ * the automatic plan (1e30 = fine items from the start), or -1 (another plan, or no call). */
+double uot_batched_last_threshold(void);
+
+/* Forgets every autotuned switch threshold of the automatic batched plan (thread-safe). */
+void uot_batched_autotune_reset(void);
 
 /*
  * Load statistics of uot_ti_sinkhorn_batched, process-wide (for benchmarks): while enabled,
@@ -474,6 +485,18 @@ uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stream);
  * compute the same softmin; the switch must not be changed while calls are running.
  */
 int32_t uot_set_points_kernel(int32_t variant);
+
+/*
+ * Kernel-shape autotuning, process-wide, on by default: the first solve (uot_sinkhorn,
+ * uot_ti_sinkhorn and their variants) of a shape with at least 2^20 cost entries per
+ * half-step times its own first half-step's softmin with several source-split counts (the
+ * resident-block capacity scaled by 0.5, 0.75, 1, 1.5, 2) and keeps the fastest for that
+ * device, record form, dimension, target and source counts and side; later calls and
+ * uot_dual_value take the kept shape. The split count changes only the order in which partial
+ * sums merge (float32 rounding). uot_set_autotune(0) uses the untuned shape everywhere (same
+ * results in every process); returns the previous setting. Thread-safe.
+ */
+int32_t uot_set_autotune(int32_t on);
 
 /* Static description of a status code. */
 const char *uot_status_string(uot_status s);

@@ -24,7 +24,8 @@ __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_ap
            "profile_enable", "profile_reset", "profile_read", "set_points_kernel",
            "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
            "fw1d_batched", "fw1d", "fw1d_barycenter", "batched_set_plan",
-           "batched_trace", "batched_trace_read", "probe_rate", "backward_noalloc"]
+           "batched_trace", "batched_trace_read", "probe_rate", "backward_noalloc",
+           "set_autotune", "batched_last_threshold", "batched_autotune_reset"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -122,6 +123,12 @@ def load_library():
     lib.uot_profile_reset.restype = None
     lib.uot_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.uot_profile_read.restype = I64
+    lib.uot_batched_last_threshold.argtypes = []
+    lib.uot_batched_last_threshold.restype = D
+    lib.uot_batched_autotune_reset.argtypes = []
+    lib.uot_batched_autotune_reset.restype = None
+    lib.uot_set_autotune.argtypes = [I32]
+    lib.uot_set_autotune.restype = I32
     lib.uot_probe_rate.argtypes = [I32, ctypes.POINTER(D), P]
     lib.uot_probe_rate.restype = I32
     lib.uot_set_points_kernel.argtypes = [I32]
@@ -243,6 +250,23 @@ def profile_read(kind: int):
     ms, ent = ctypes.c_double(0.0), ctypes.c_double(0.0)
     n = load_library().uot_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(ent))
     return int(n), ms.value, ent.value
+
+
+def set_autotune(on: bool) -> bool:
+    """Kernel-shape autotuning of the solvers' softmin split counts (on by default); returns
+    the previous setting."""
+    return bool(load_library().uot_set_autotune(1 if on else 0))
+
+
+def batched_last_threshold() -> float:
+    """Switch threshold tau of this thread's last batched solve under the automatic plan
+    (1e30: fine items from the start; -1: another plan or no call)."""
+    return float(load_library().uot_batched_last_threshold())
+
+
+def batched_autotune_reset():
+    """Forget the batched solver's autotuned switch thresholds."""
+    load_library().uot_batched_autotune_reset()
 
 
 PROBE_EXP2, PROBE_FMA32, PROBE_FMA64 = 0, 1, 2

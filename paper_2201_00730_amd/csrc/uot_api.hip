@@ -4,12 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/uot.h"
@@ -152,9 +155,48 @@ struct HalfShape {
   int nb_combine = 1;
 };
 
-HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
+// ---------------------------------------------------------------------------------------
+// Kernel-shape autotuner. The split count of a half-step's softmin starts from one round of
+// resident blocks (make_split); the first solve of a shape of at least kTuneMinEntries
+// entries times the softmin on its own first half-step with that capacity scaled by each of
+// kTuneMults and keeps the fastest for the process (per device, record mode, dimension
+// bucket, target and source counts, and side). Later calls, and the dual value, take the
+// cached shape. Split counts only change the order in which partial sums merge.
+// ---------------------------------------------------------------------------------------
+constexpr double kTuneMinEntries = 1048576.0;
+constexpr double kTuneMults[] = {0.5, 0.75, 1.0, 1.5, 2.0};
+typedef std::tuple<int, int, int, int, int, int> TuneKey;  // device, mode, bucket, nt, ns, rows
+std::mutex g_tune_mu;
+std::map<TuneKey, double> g_tune_cache;
+std::atomic<int> g_autotune{1};
+
+TuneKey tune_key(int mode, int d, int nt, int ns, bool rows) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  return TuneKey(dev, mode, mode == kDense ? 0 : dim_bucket(d), nt, ns, rows ? 1 : 0);
+}
+
+// Cached capacity multiplier of a shape (1 when none is cached or tuning is off).
+double tuned_mult(int mode, int d, int nt, int ns, bool rows) {
+  if (!g_autotune.load()) return 1.0;
+  const TuneKey key = tune_key(mode, d, nt, ns, rows);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const auto it = g_tune_cache.find(key);
+  return it == g_tune_cache.end() ? 1.0 : it->second;
+}
+
+HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows,
+                     double cap_mult = -1.0) {
   HalfShape h;
   const int cus = device_cus();
+  if (cap_mult < 0.0) cap_mult = tuned_mult(mode, d, nt, ns, targets_are_rows);
+  auto scaled = [&](int capacity) {
+    const int c = (int)(capacity * cap_mult + 0.5);
+    return c > 0 ? c : 1;
+  };
   if (mode == kDense) {
     if (targets_are_rows) {
       h.rows_kernel = true;
@@ -162,14 +204,14 @@ HalfShape half_shape(int mode, int d, int nt, int ns, bool targets_are_rows) {
       h.split.n = 1;
     } else {
       const int tiles = (nt + dense_cols_per_block() - 1) / dense_cols_per_block();
-      h.split = make_split(ns, tiles, 64, 8, cus > 0 ? 8 * cus : 0);
+      h.split = make_split(ns, tiles, 64, 8, scaled(cus > 0 ? 8 * cus : kDefaultResidentBlocks));
     }
   } else {
     const int tpb = points_targets_per_block(mode, d);
     const int tiles = (nt + tpb - 1) / tpb;
     const int per_cu = points_blocks_per_cu(mode, d);
     h.split = make_split(ns, tiles, 64, points_split_align(mode, d),
-                         (cus > 0 && per_cu > 0) ? per_cu * cus : 0);
+                         scaled((cus > 0 && per_cu > 0) ? per_cu * cus : kDefaultResidentBlocks));
   }
   h.nb_combine = combine_blocks(nt);
   return h;
@@ -654,6 +696,60 @@ uot_status check_phi(const uot_phi *phi) {
   return UOT_OK;
 }
 
+// Times the candidate split counts of one half-step's softmin (on the call's own records;
+// the partials it writes are overwritten by the real half-step) and keeps the fastest.
+uot_status tune_half(Ctx &k, bool g_step) {
+  const int nt = g_step ? k.m : k.n, ns = g_step ? k.n : k.m;
+  const bool rows = !g_step;
+  if (!g_autotune.load() || (double)nt * (double)ns < kTuneMinEntries) return UOT_OK;
+  if (k.mode == kDense && rows) return UOT_OK;  // the rows kernel takes no splits
+  const TuneKey key = tune_key(k.mode, k.d, nt, ns, rows);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune_cache.count(key)) return UOT_OK;
+  }
+  HalfShape &slot = g_step ? k.L.g : k.L.f;
+  Timer *timer = k.timer;
+  k.timer = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      if (e[0]) (void)hipEventDestroy(e[0]);
+      if (e[1]) (void)hipEventDestroy(e[1]);
+    }
+  } evg{ev};
+  UOT_HIP(hipEventCreate(&ev[0]));
+  UOT_HIP(hipEventCreate(&ev[1]));
+  double best_ms = INFINITY, best_mult = 1.0;
+  std::vector<int> seen;
+  for (double mult : kTuneMults) {
+    const HalfShape h = half_shape(k.mode, k.d, nt, ns, rows, mult);
+    bool dup = false;
+    for (int n : seen) dup = dup || n == h.split.n;
+    if (dup) continue;
+    seen.push_back(h.split.n);
+    slot = h;
+    UOT_TRY(softmin_partials(k, g_step, nullptr));  // warm
+    UOT_HIP(hipEventRecord(ev[0], k.s));
+    UOT_TRY(softmin_partials(k, g_step, nullptr));
+    UOT_TRY(softmin_partials(k, g_step, nullptr));
+    UOT_HIP(hipEventRecord(ev[1], k.s));
+    UOT_HIP(hipEventSynchronize(ev[1]));
+    float ms = 0.0f;
+    UOT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_mult = mult;
+    }
+  }
+  slot = half_shape(k.mode, k.d, nt, ns, rows, best_mult);
+  k.timer = timer;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best_mult;
+  return UOT_OK;
+}
+
 // Choice of the p = 2 points softmin form (see uot_cost in uot.h): the expanded form's
 // float32 rounding E = 2^-24 (d + 4) (max|x - mu| + max|y - mu|)^2 (potential units) is a
 // risk to the 1e-5 relative accuracy of the potentials when its share of the exponent,
@@ -742,6 +838,8 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   UOT_TRY(read_state(st, hst[0], k.s));
   if (hst[0].error & kErrWeights)
     return fail(UOT_ERR_INVALID, "weights must be finite, >= 0, with positive total mass");
+  UOT_TRY(tune_half(k, true));  // first solve of this shape: split counts by timing
+  UOT_TRY(tune_half(k, false));
   // expanded-form rounding against eps now; against the potentials after iteration 1
   const double form_e = check_form ? expanded_form_rounding(c, hst[0]) : 0.0;
   const bool check_q = check_form && form_e * kLog2e / P->eps > kFormDelta;
@@ -1372,6 +1470,52 @@ int batched_plan() {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   return g_batch_plan;
 }
+
+// Autotuned plan switch (automatic plan): the coarse items give way to the fine ones once the
+// busier side has at most tau x (resident waves) coarse items left. For each size signature
+// (device, B, d, check_every, tol > 0, and log2 buckets of sum N, sum M, max N, max M) the
+// first calls each take one candidate tau, timed on the host from the first chunk to the
+// end of the solve, and later calls take the fastest. tau = 0 keeps the coarse plan, the last
+// candidate starts on the fine one. The plan changes only how targets are grouped into items
+// (the order of the per-problem partial sums), not the arithmetic of any target.
+constexpr double kBatchTau[] = {0.0, 0.5, 1.0, 2.0, 4.0, 8.0, 1e30};
+constexpr int kNumBatchTau = (int)(sizeof(kBatchTau) / sizeof(kBatchTau[0]));
+typedef std::tuple<int, int, int, int, int, int, int, int, int> BatchSig;
+struct BatchTune {
+  double ms[kNumBatchTau];
+  int claimed = 0;  // candidates handed out so far (in order)
+  BatchTune() {
+    for (double &v : ms) v = INFINITY;
+  }
+};
+std::map<BatchSig, BatchTune> g_batch_tune;  // guarded by g_batch_mu
+thread_local double g_batch_last_tau = -1.0;
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+BatchSig batch_sig(int32_t B, const int64_t *offN, const int64_t *offM, int32_t d,
+                   int32_t check_every, double tol) {
+  int64_t mn = 0, mm = 0;
+  for (int p = 0; p < B; ++p) {
+    const int64_t n = offN[p + 1] - offN[p], m = offM[p + 1] - offM[p];
+    mn = n > mn ? n : mn;
+    mm = m > mm ? m : mm;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  return BatchSig(dev, B, d, check_every, tol > 0.0 ? 1 : 0, log2_bucket(offN[B]),
+                  log2_bucket(offM[B]), log2_bucket(mn), log2_bucket(mm));
+}
 bool batched_trace_enabled() {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   return g_batch_trace_on;
@@ -1598,11 +1742,30 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   // chunk.
   const int resident_waves = blocks * 4;
   const int plan = batched_plan();
+  // the automatic plan's switch point: the next untried candidate of this size signature, or
+  // the fastest once all have run
+  int tune_idx = -1;
+  bool exploring = false;
+  const BatchSig sig = batch_sig(B, offN, offM, d, check_every, tol);
+  if (plan == kPlanAuto) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchTune &bt = g_batch_tune[sig];
+    if (bt.claimed < kNumBatchTau) {
+      tune_idx = bt.claimed++;
+      exploring = true;
+    } else {
+      tune_idx = 0;
+      for (int i = 1; i < kNumBatchTau; ++i)
+        if (bt.ms[i] < bt.ms[tune_idx]) tune_idx = i;
+    }
+  }
+  const double tau = tune_idx >= 0 ? kBatchTau[tune_idx] : 2.0;
+  g_batch_last_tau = plan == kPlanAuto ? tau : -1.0;
   auto want_fine = [&](const BatchCounters &c, int chunks_done) {
     if (plan == kPlanCoarse) return false;
     if (plan == kPlanFine) return true;
     if (plan == kPlanSwitchAfterFirst) return chunks_done >= 1;
-    return (c.nact_g > c.nact_f ? c.nact_g : c.nact_f) <= 2 * resident_waves;
+    return (double)(c.nact_g > c.nact_f ? c.nact_g : c.nact_f) <= tau * resident_waves;
   };
 
   // host copies of the counters after each chunk (two slots, read one chunk late)
@@ -1640,6 +1803,7 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   UOT_HIP(hipStreamSynchronize(s));
   record(cnt_h[2], 0, false);
   const int max_chunks = (max_iter + chunk - 1) / chunk;
+  const auto t_start = std::chrono::steady_clock::now();
   bool fine = false;
   if (cnt_h[2].running > 0) {
     if (want_fine(cnt_h[2], 0)) {
@@ -1664,6 +1828,12 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   }
   UOT_HIP(launch_batched_finalize(a, f, g, iters, status, s));
   UOT_HIP(hipStreamSynchronize(s));
+  if (exploring) {
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                t_start).count();
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batch_tune[sig].ms[tune_idx] = ms;
+  }
   if (tracing) {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     g_batch_trace = trace;
@@ -1764,6 +1934,10 @@ uot_status uot_backward_noalloc(const uot_cost *cost, const float *alpha, const 
                                dalpha, dbeta, stream);
 }
 
+int32_t uot_set_autotune(int32_t on) {
+  return uot::g_autotune.exchange(on ? 1 : 0);
+}
+
 int32_t uot_set_points_kernel(int32_t variant) {
   if (variant < uot::kPointsAuto || variant > uot::kPointsDirect) return -1;
   const int32_t prev = uot::g_points_variant;
@@ -1821,6 +1995,13 @@ uot_status uot_fw1d_batched(int32_t B, const int64_t *offN, const int64_t *offM,
   uot::g_last_error.clear();
   return uot::fw1d(B, offN, offM, x, y, alpha, beta, rho1, rho2, p, line_search, max_iter, tol,
                    f, g, iters, gap, status, workspace, workspace_bytes, stream);
+}
+
+double uot_batched_last_threshold(void) { return uot::g_batch_last_tau; }
+
+void uot_batched_autotune_reset(void) {
+  std::lock_guard<std::mutex> lk(uot::g_batch_mu);
+  uot::g_batch_tune.clear();
 }
 
 int32_t uot_batched_set_plan(int32_t plan) {

@@ -190,3 +190,31 @@ def test_batched_load_statistics():
     assert np.all(np.diff(tr["work"]) <= 0)
     assert np.all(tr["busy_ticks"][1:] <= tr["ticks"][1:] * tr["resident_waves"][1:] * 1.01 + 10)
     assert np.sum(tr["busy_ticks"]) > 0
+
+
+def test_batched_autotuned_plan_switch():
+    """The automatic plan explores one switch threshold per call for a new size signature
+    (seven candidates, from coarse-only to fine from the start), then keeps the fastest; the
+    potentials agree across every candidate (the plan changes only how targets are grouped
+    into work items) and with the oracle."""
+    bt = small_batch(B=40, nmin=64, nmax=700, seed=57)
+    uot.batched_autotune_reset()
+    with _plan(0):
+        runs, taus = [], []
+        for _ in range(8):
+            runs.append(run_batched(bt, 12))
+            taus.append(uot.batched_last_threshold())
+    assert taus[:7] == [0.0, 0.5, 1.0, 2.0, 4.0, 8.0, 1e30], taus
+    assert taus[7] in taus[:7]
+    f0, g0 = runs[0][0], runs[0][1]
+    for f, g, it, st in runs[1:]:
+        assert rel_inf(f, f0) < 1e-6 and rel_inf(g, g0) < 1e-6
+        assert np.all(it == 12)
+    for b in (0, 17, 39):
+        r = oracle_problem(bt, b, 12)
+        n0, n1 = bt.offN[b], bt.offN[b + 1]
+        m0, m1 = bt.offM[b], bt.offM[b + 1]
+        assert rel_inf(f0[n0:n1], r.f) < TOL and rel_inf(g0[m0:m1], r.g) < TOL
+    with _plan(1):
+        run_batched(bt, 2)
+        assert uot.batched_last_threshold() == -1.0

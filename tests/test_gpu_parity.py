@@ -507,3 +507,23 @@ def test_extreme_parameters_direct(eps, rho1, rho2, ti):
     _say("  rel f %.3g g %.3g" % (rel_inf(f, r.f), rel_inf(g, r.g)))
     assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
     assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL, (rel_inf(f, r.f), rel_inf(g, r.g))
+
+
+def test_split_autotune_on_off_agree():
+    """A shape of at least 2^20 entries is tuned on its first solve (split counts timed on the
+    solve's own first half-step) and the choice is kept; tuned, cached and untuned solves agree
+    to float32 rounding (1e-6) and all meet the oracle (1e-5)."""
+    pr = workloads.random_small(1500, 1400, d=3, seed=77, eps=0.05, rho1=0.7, rho2=1.3)
+    r = run_oracle(pr, True, 30)
+    prev = uot.set_autotune(True)
+    try:
+        f1, g1, _ = run_gpu(pr, True, 30)  # tunes this shape (unless an earlier test did)
+        f2, g2, _ = run_gpu(pr, True, 30)  # cached
+        uot.set_autotune(False)
+        f3, g3, _ = run_gpu(pr, True, 30)  # untuned shape
+    finally:
+        uot.set_autotune(prev)
+    for f, g in ((f1, g1), (f2, g2), (f3, g3)):
+        assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL
+    assert rel_inf(f1, f2) == 0.0 and rel_inf(g1, g2) == 0.0
+    assert rel_inf(f1, f3) < 1e-6 and rel_inf(g1, g3) < 1e-6
