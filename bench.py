@@ -285,9 +285,10 @@ def extra_workload(args, uot, torch, np, workloads):
         explore = []
         for _ in range(8):
             _, dte = _timed(torch, run)
-            explore.append({"threshold": uot.batched_last_threshold(), "seconds": dte})
+            lv0, lv1, tau = uot.batched_last_plan()
+            explore.append({"levels": [lv0, lv1], "threshold": tau, "seconds": dte})
         (f, g, iters, status), dt = _timed(torch, run)
-        chosen = uot.batched_last_threshold()
+        chosen = uot.batched_last_plan()
         it = iters.cpu().numpy().astype(np.float64)
         N = np.diff(bt.offN).astype(np.float64)
         M = np.diff(bt.offM).astype(np.float64)
@@ -321,7 +322,9 @@ def extra_workload(args, uot, torch, np, workloads):
                     "value": ups / dt, "seconds": dt,
                     "config": {"workload": "4096 problems, N_p,M_p ~ U{64..4096}, D=2, "
                                            "eps log-U[1e-3,1e-1], rho log-U[0.1,10], TI to 1e-6"},
-                    "autotune": {"explored": explore[:7], "chosen_threshold": chosen},
+                    "autotune": {"item_levels": "0: <= 256 targets per item, 1: <= 128, 2: <= 64",
+                                 "explored": explore[:7],
+                                 "chosen": {"levels": list(chosen[:2]), "threshold": chosen[2]}},
                     "iterations_percentiles_0_50_90_99_100": hist,
                     "iterations_histogram": {"%d-%d" % (edges[i], edges[i + 1] - 1): int(counts[i])
                                              for i in range(len(counts)) if counts[i]},

@@ -410,22 +410,28 @@ size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t
 /*
  * Work-item plan of uot_ti_sinkhorn_batched, process-wide (for tests and benchmarks; the plan
  * only changes how targets are grouped into work items, i.e. the order of the per-problem
- * partial sums): 0 = automatic and autotuned (coarse items of up to 256 targets, four per lane,
- * then fine items of up to 128 targets, two per lane, once the busier side has at most
- * tau x (resident waves) coarse items; for each size signature - device, B, d, check_every,
- * tol > 0 and the log2 sizes of sum N, sum M, max N, max M - the first seven calls each run
- * one tau of {0 (coarse throughout), 0.5, 1, 2, 4, 8, fine from the start}, timed on the host,
- * and later calls take the fastest), 1 = coarse items throughout, 2 = fine items throughout,
- * 3 = coarse for the first chunk of iterations, fine after it. Returns the previous setting,
- * or -1 for an unknown value (nothing changes). Must not be changed while a batched solve runs.
+ * partial sums). Items come at three levels: up to 256 targets (level 0, four per lane), 128
+ * (level 1, two per lane) or 64 (level 2, one per lane).
+ *  0 = automatic and autotuned: a plan starts at one level and moves to the next finer one
+ *      once the busier side has at most tau x (resident waves) active items. For each size
+ *      signature (device, B, d, check_every, tol > 0 and the log2 sizes of sum N, sum M,
+ *      max N, max M) the first seven calls each run one candidate of
+ *      {level 0 throughout; 0 then 1 at tau = 2; 0 then 1 at tau = 8; level 1 throughout;
+ *       1 then 2 at tau = 2; 1 then 2 at tau = 8; level 2 throughout}, timed on the host,
+ *      and later calls take the fastest;
+ *  1 = level 0 throughout, 2 = level 1 throughout, 3 = level 0 for the first chunk of
+ *  iterations and level 1 after it, 4 = level 2 throughout.
+ * Returns the previous setting, or -1 for an unknown value (nothing changes). Must not be
+ * changed while a batched solve runs.
  */
 int32_t uot_batched_set_plan(int32_t plan);
 
-/* The switch threshold tau the calling thread's last uot_ti_sinkhorn_batched call used under
- * the automatic plan (1e30 = fine items from the start), or -1 (another plan, or no call). */
-double uot_batched_last_threshold(void);
+/* The item levels and switch threshold of the calling thread's last uot_ti_sinkhorn_batched
+ * call under the automatic plan (host outputs, may be NULL); returns 1, or 0 (and -1 levels)
+ * after another plan or before any call. */
+int32_t uot_batched_last_plan(int32_t *start_level, int32_t *end_level, double *threshold);
 
-/* Forgets every autotuned switch threshold of the automatic batched plan (thread-safe). */
+/* Forgets every autotuned plan of the automatic batched plan (thread-safe). */
 void uot_batched_autotune_reset(void);
 
 /*

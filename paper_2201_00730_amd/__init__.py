@@ -25,7 +25,7 @@ __all__ = ["UOTError", "Info", "sinkhorn", "ti_sinkhorn", "dual_value", "plan_ap
            "ti_sinkhorn_batched", "sinkhorn_anderson", "ti_sinkhorn_anderson", "sinkhorn_phi",
            "fw1d_batched", "fw1d", "fw1d_barycenter", "batched_set_plan",
            "batched_trace", "batched_trace_read", "probe_rate", "backward_noalloc",
-           "set_autotune", "batched_last_threshold", "batched_autotune_reset"]
+           "set_autotune", "batched_last_plan", "batched_autotune_reset"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libuot.so")
@@ -123,8 +123,9 @@ def load_library():
     lib.uot_profile_reset.restype = None
     lib.uot_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.uot_profile_read.restype = I64
-    lib.uot_batched_last_threshold.argtypes = []
-    lib.uot_batched_last_threshold.restype = D
+    lib.uot_batched_last_plan.argtypes = [ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                          ctypes.POINTER(D)]
+    lib.uot_batched_last_plan.restype = I32
     lib.uot_batched_autotune_reset.argtypes = []
     lib.uot_batched_autotune_reset.restype = None
     lib.uot_set_autotune.argtypes = [I32]
@@ -258,10 +259,12 @@ def set_autotune(on: bool) -> bool:
     return bool(load_library().uot_set_autotune(1 if on else 0))
 
 
-def batched_last_threshold() -> float:
-    """Switch threshold tau of this thread's last batched solve under the automatic plan
-    (1e30: fine items from the start; -1: another plan or no call)."""
-    return float(load_library().uot_batched_last_threshold())
+def batched_last_plan():
+    """(start level, end level, tau) of this thread's last batched solve under the automatic
+    plan (item levels 0, 1, 2: up to 256, 128, 64 targets per item), or None."""
+    a, b, t = ctypes.c_int32(-1), ctypes.c_int32(-1), ctypes.c_double(-1.0)
+    ok = load_library().uot_batched_last_plan(ctypes.byref(a), ctypes.byref(b), ctypes.byref(t))
+    return (a.value, b.value, t.value) if ok else None
 
 
 def batched_autotune_reset():
@@ -551,6 +554,7 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
 
 
 BATCH_PLAN_AUTO, BATCH_PLAN_COARSE, BATCH_PLAN_FINE, BATCH_PLAN_SWITCH = 0, 1, 2, 3
+BATCH_PLAN_FINEST = 4
 
 
 def batched_set_plan(plan: int) -> int:

@@ -1250,28 +1250,30 @@ uot_status backward_noalloc(const uot_cost *c, const float *alpha, const float *
 // ---------------------------------------------------------------------------------------
 // Batched TI Sinkhorn
 // ---------------------------------------------------------------------------------------
-// Work items of the batched solver: chunks of 256 targets (one wave, four per lane), and the
-// remainder of a problem as one item (four, two or one targets per lane above 128, above 64,
-// up to 64; measured as fast as splitting a remainder of 65..128 into 64 + the rest).
-// The fine plan (items of at most 128 targets, two per lane) takes over once the running
-// problems give too few coarse items to fill the chip: more, shorter items then shorten the
-// critical path of each launch.
-int64_t batch_item_len(int64_t rem, bool fine = false) {
-  if (fine) return rem < 128 ? rem : 128;
-  return rem >= 256 ? 256 : rem;
+// Work items of the batched solver, at three levels: chunks of up to 256 targets (level 0,
+// coarse: four per lane), 128 (level 1, fine: two per lane) or 64 (level 2, finest: one per
+// lane); the remainder of a problem is one item (four, two or one targets per lane above 128,
+// above 64, up to 64). Finer items cost more per entry (fewer targets share each source read)
+// but shorten the longest item, which bounds a launch once few problems run; the automatic
+// plan (autotuned, below) starts at one level and may move to the next finer one.
+constexpr int kBatchLevels = 3;
+int64_t batch_item_len(int64_t rem, int level = 0) {
+  const int64_t cap = (int64_t)256 >> level;
+  return rem < cap ? rem : cap;
 }
-int64_t batch_items(int64_t n, bool fine = false) {
+int64_t batch_items(int64_t n, int level = 0) {
   int64_t k = 0;
-  for (int64_t t0 = 0; t0 < n; t0 += batch_item_len(n - t0, fine)) ++k;
+  for (int64_t t0 = 0; t0 < n; t0 += batch_item_len(n - t0, level)) ++k;
   return k;
 }
 
 struct BatchLayout {
-  size_t state = 0, mu = 0, offN = 0, offM = 0, items_g = 0, items_f = 0, pitem_g = 0, pitem_f = 0;
+  size_t state = 0, mu = 0, offN = 0, offM = 0;
+  size_t items_g[kBatchLevels] = {}, items_f[kBatchLevels] = {};   // per item level
+  size_t pitem_g[kBatchLevels] = {}, pitem_f[kBatchLevels] = {};
+  int n_items_g[kBatchLevels] = {}, n_items_f[kBatchLevels] = {};
   size_t act_g = 0, act_f = 0, ctrs = 0, part_g = 0, part_f = 0, tick_g = 0, tick_f = 0;
   size_t pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, total = 0;
-  size_t items_g2 = 0, items_f2 = 0, pitem_g2 = 0, pitem_f2 = 0;  // fine plan
-  int n_items_g = 0, n_items_f = 0, n_items_g2 = 0, n_items_f2 = 0;
   int64_t totN = 0, totM = 0;
 };
 
@@ -1457,7 +1459,9 @@ uot_status fw_barycenter(int32_t B, int32_t K, const int64_t *off, const float *
 
 // Process-wide settings of the batched solver: the work-item plan, and a per-chunk trace of
 // the last solve (load statistics), guarded by a mutex.
-enum BatchPlan : int { kPlanAuto = 0, kPlanCoarse = 1, kPlanFine = 2, kPlanSwitchAfterFirst = 3 };
+enum BatchPlan : int {
+  kPlanAuto = 0, kPlanCoarse = 1, kPlanFine = 2, kPlanSwitchAfterFirst = 3, kPlanFinest = 4
+};
 struct BatchTraceRow {
   double chunk, fine, running, items_g, items_f, work, busy_ticks, ticks, resident_waves;
 };
@@ -1471,25 +1475,30 @@ int batched_plan() {
   return g_batch_plan;
 }
 
-// Autotuned plan switch (automatic plan): the coarse items give way to the fine ones once the
-// busier side has at most tau x (resident waves) coarse items left. For each size signature
-// (device, B, d, check_every, tol > 0, and log2 buckets of sum N, sum M, max N, max M) the
-// first calls each take one candidate tau, timed on the host from the first chunk to the
-// end of the solve, and later calls take the fastest. tau = 0 keeps the coarse plan, the last
-// candidate starts on the fine one. The plan changes only how targets are grouped into items
-// (the order of the per-problem partial sums), not the arithmetic of any target.
-constexpr double kBatchTau[] = {0.0, 0.5, 1.0, 2.0, 4.0, 8.0, 1e30};
-constexpr int kNumBatchTau = (int)(sizeof(kBatchTau) / sizeof(kBatchTau[0]));
+// Autotuned plan (automatic plan): a candidate starts at item level lv0 and moves to lv1
+// once the busier side has at most tau x (resident waves) active items. For each size
+// signature (device, B, d, check_every, tol > 0, and log2 buckets of sum N, sum M, max N,
+// max M) the first calls each take one candidate, timed on the host from the first chunk to
+// the end of the solve, and later calls take the fastest. The level changes only how targets
+// are grouped into items (the order of the per-problem partial sums), not the arithmetic of
+// any target.
+struct BatchCand {
+  int lv0, lv1;
+  double tau;
+};
+constexpr BatchCand kBatchCand[] = {{0, 0, 0.0}, {0, 1, 2.0}, {0, 1, 8.0}, {1, 1, 0.0},
+                                    {1, 2, 2.0}, {1, 2, 8.0}, {2, 2, 0.0}};
+constexpr int kNumBatchCand = (int)(sizeof(kBatchCand) / sizeof(kBatchCand[0]));
 typedef std::tuple<int, int, int, int, int, int, int, int, int> BatchSig;
 struct BatchTune {
-  double ms[kNumBatchTau];
+  double ms[kNumBatchCand];
   int claimed = 0;  // candidates handed out so far (in order)
   BatchTune() {
     for (double &v : ms) v = INFINITY;
   }
 };
 std::map<BatchSig, BatchTune> g_batch_tune;  // guarded by g_batch_mu
-thread_local double g_batch_last_tau = -1.0;
+thread_local BatchCand g_batch_last{-1, -1, -1.0};
 
 int log2_bucket(int64_t v) {
   int b = 0;
@@ -1527,21 +1536,22 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   if (offN == nullptr || offM == nullptr) return fail(UOT_ERR_INVALID, "offN/offM are NULL");
   if (d < 1 || d > kBatchMaxDim) return fail(UOT_ERR_INVALID, "batched d=%d not in [1, %d]", d, kBatchMaxDim);
   if (offN[0] != 0 || offM[0] != 0) return fail(UOT_ERR_INVALID, "offN[0] and offM[0] must be 0");
-  int64_t ig = 0, jf = 0, ig2 = 0, jf2 = 0;
+  int64_t ig[kBatchLevels] = {}, jf[kBatchLevels] = {};
   for (int p = 0; p < B; ++p) {
     const int64_t n = offN[p + 1] - offN[p], m = offM[p + 1] - offM[p];
     if (n < 1 || m < 1) return fail(UOT_ERR_INVALID, "problem %d has n=%lld, m=%lld (must be >= 1)", p, (long long)n, (long long)m);
     if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_ERR_INVALID, "problem %d is too large", p);
-    ig += batch_items(m);
-    jf += batch_items(n);
-    ig2 += batch_items(m, true);
-    jf2 += batch_items(n, true);
+    for (int lv = 0; lv < kBatchLevels; ++lv) {
+      ig[lv] += batch_items(m, lv);
+      jf[lv] += batch_items(n, lv);
+    }
   }
-  if (ig2 > (1 << 30) || jf2 > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
-  L.n_items_g = (int)ig;
-  L.n_items_f = (int)jf;
-  L.n_items_g2 = (int)ig2;  // the fine plan has at least as many items as the coarse one
-  L.n_items_f2 = (int)jf2;
+  constexpr int kFinest = kBatchLevels - 1;  // the most items of any level
+  if (ig[kFinest] > (1 << 30) || jf[kFinest] > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
+  for (int lv = 0; lv < kBatchLevels; ++lv) {
+    L.n_items_g[lv] = (int)ig[lv];
+    L.n_items_f[lv] = (int)jf[lv];
+  }
   L.totN = offN[B];
   L.totM = offM[B];
   const int stride = batched_rec_stride(d);
@@ -1555,20 +1565,18 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   L.mu = take((size_t)B * kBatchMaxDim * sizeof(double));
   L.offN = take((size_t)(B + 1) * sizeof(int64_t));
   L.offM = take((size_t)(B + 1) * sizeof(int64_t));
-  L.items_g = take((size_t)L.n_items_g * sizeof(int4));
-  L.items_f = take((size_t)L.n_items_f * sizeof(int4));
-  L.pitem_g = take((size_t)(B + 1) * sizeof(int));
-  L.pitem_f = take((size_t)(B + 1) * sizeof(int));
-  L.items_g2 = take((size_t)L.n_items_g2 * sizeof(int4));
-  L.items_f2 = take((size_t)L.n_items_f2 * sizeof(int4));
-  L.pitem_g2 = take((size_t)(B + 1) * sizeof(int));
-  L.pitem_f2 = take((size_t)(B + 1) * sizeof(int));
-  // active lists and item partials serve either plan
-  L.act_g = take((size_t)L.n_items_g2 * sizeof(int));
-  L.act_f = take((size_t)L.n_items_f2 * sizeof(int));
+  for (int lv = 0; lv < kBatchLevels; ++lv) {
+    L.items_g[lv] = take((size_t)L.n_items_g[lv] * sizeof(int4));
+    L.items_f[lv] = take((size_t)L.n_items_f[lv] * sizeof(int4));
+    L.pitem_g[lv] = take((size_t)(B + 1) * sizeof(int));
+    L.pitem_f[lv] = take((size_t)(B + 1) * sizeof(int));
+  }
+  // active lists and item partials serve every level
+  L.act_g = take((size_t)L.n_items_g[kFinest] * sizeof(int));
+  L.act_f = take((size_t)L.n_items_f[kFinest] * sizeof(int));
   L.ctrs = take(sizeof(BatchCounters));
-  L.part_g = take((size_t)L.n_items_g2 * sizeof(BlockPart));
-  L.part_f = take((size_t)L.n_items_f2 * sizeof(BlockPart));
+  L.part_g = take((size_t)L.n_items_g[kFinest] * sizeof(BlockPart));
+  L.part_f = take((size_t)L.n_items_f[kFinest] * sizeof(BlockPart));
   L.tick_g = take((size_t)B * sizeof(int));
   L.tick_f = take((size_t)B * sizeof(int));
   L.pot_x = take((size_t)L.totN * sizeof(float));
@@ -1584,14 +1592,14 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
 // source records in L2; ordering the table longest-first was measured slower on batch2d:
 // 2.30e12 against 2.63e12 updates/s); the slots of problem p are [pitem[p], pitem[p+1]).
 void build_items(int32_t B, const int64_t *off, std::vector<int4> &items, std::vector<int> &pitem,
-                 bool fine) {
+                 int level) {
   items.clear();
   pitem.assign((size_t)B + 1, 0);
   for (int p = 0; p < B; ++p) {
     pitem[p] = (int)items.size();
     const int64_t n = off[p + 1] - off[p];
     for (int64_t t0 = 0; t0 < n;) {
-      const int cnt = (int)batch_item_len(n - t0, fine);
+      const int cnt = (int)batch_item_len(n - t0, level);
       items.push_back(make_int4(p, (int)t0, cnt, (int)items.size()));
       t0 += cnt;
     }
@@ -1628,23 +1636,23 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   UOT_TRY(acquire(w, workspace, workspace_bytes, L.total));
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  std::vector<int4> items_g, items_f, items_g2, items_f2;
-  std::vector<int> pitem_g, pitem_f, pitem_g2, pitem_f2;
-  build_items(B, offM, items_g, pitem_g, false);  // g-step targets: the y side
-  build_items(B, offN, items_f, pitem_f, false);  // f-step targets: the x side
-  build_items(B, offM, items_g2, pitem_g2, true);
-  build_items(B, offN, items_f2, pitem_f2, true);
+  std::vector<int4> items[2][kBatchLevels];  // [side: 0 g-step, 1 f-step][level]
+  std::vector<int> pitem[2][kBatchLevels];
   char *ws = static_cast<char *>(w.ptr);
   UOT_HIP(hipMemcpyAsync(ws + L.offN, offN, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   UOT_HIP(hipMemcpyAsync(ws + L.offM, offM, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.items_g, items_g.data(), items_g.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.items_f, items_f.data(), items_f.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.pitem_g, pitem_g.data(), pitem_g.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.pitem_f, pitem_f.data(), pitem_f.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.items_g2, items_g2.data(), items_g2.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.items_f2, items_f2.data(), items_f2.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.pitem_g2, pitem_g2.data(), pitem_g2.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  UOT_HIP(hipMemcpyAsync(ws + L.pitem_f2, pitem_f2.data(), pitem_f2.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  for (int lv = 0; lv < kBatchLevels; ++lv) {
+    build_items(B, offM, items[0][lv], pitem[0][lv], lv);  // g-step targets: the y side
+    build_items(B, offN, items[1][lv], pitem[1][lv], lv);  // f-step targets: the x side
+    UOT_HIP(hipMemcpyAsync(ws + L.items_g[lv], items[0][lv].data(), items[0][lv].size() * sizeof(int4),
+                           hipMemcpyHostToDevice, s));
+    UOT_HIP(hipMemcpyAsync(ws + L.items_f[lv], items[1][lv].data(), items[1][lv].size() * sizeof(int4),
+                           hipMemcpyHostToDevice, s));
+    UOT_HIP(hipMemcpyAsync(ws + L.pitem_g[lv], pitem[0][lv].data(), pitem[0][lv].size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    UOT_HIP(hipMemcpyAsync(ws + L.pitem_f[lv], pitem[1][lv].data(), pitem[1][lv].size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  }
   UOT_HIP(hipStreamSynchronize(s));  // the host tables must outlive the copies
 
   BatchedArgs a;
@@ -1670,12 +1678,12 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   a.pot_y = at<float>(w.ptr, L.pot_y);
   a.rec_x = at<float>(w.ptr, L.rec_x);
   a.rec_y = at<float>(w.ptr, L.rec_y);
-  a.items_g = at<int4>(w.ptr, L.items_g);
-  a.items_f = at<int4>(w.ptr, L.items_f);
-  a.pitem_g = at<int>(w.ptr, L.pitem_g);
-  a.pitem_f = at<int>(w.ptr, L.pitem_f);
-  a.n_items_g = L.n_items_g;
-  a.n_items_f = L.n_items_f;
+  a.items_g = at<int4>(w.ptr, L.items_g[0]);
+  a.items_f = at<int4>(w.ptr, L.items_f[0]);
+  a.pitem_g = at<int>(w.ptr, L.pitem_g[0]);
+  a.pitem_f = at<int>(w.ptr, L.pitem_f[0]);
+  a.n_items_g = L.n_items_g[0];
+  a.n_items_f = L.n_items_f[0];
   a.act_g = at<int>(w.ptr, L.act_g);
   a.act_f = at<int>(w.ptr, L.act_f);
   BatchCounters *ctrs = at<BatchCounters>(w.ptr, L.ctrs);
@@ -1692,22 +1700,67 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   a.ticket_g = at<int>(w.ptr, L.tick_g);
   a.ticket_f = at<int>(w.ptr, L.tick_f);
 
-  UOT_HIP(launch_batched_init(a, s));
-  UOT_HIP(launch_batched_compact(a, s));
   const int cus = device_cus();
   const int per_cu = batched_half_blocks_per_cu(a);
   const int blocks = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 4);
+  const int resident_waves = blocks * 4;
 
-  // the fine plan: the same problems and buffers, other item tables
-  BatchedArgs a2 = a;
-  a2.items_g = at<int4>(w.ptr, L.items_g2);
-  a2.items_f = at<int4>(w.ptr, L.items_f2);
-  a2.pitem_g = at<int>(w.ptr, L.pitem_g2);
-  a2.pitem_f = at<int>(w.ptr, L.pitem_f2);
-  a2.n_items_g = L.n_items_g2;
-  a2.n_items_f = L.n_items_f2;
+  // the same problems and buffers at each item level, with that level's item tables
+  BatchedArgs al[kBatchLevels];
+  for (int lv = 0; lv < kBatchLevels; ++lv) {
+    al[lv] = a;
+    al[lv].items_g = at<int4>(w.ptr, L.items_g[lv]);
+    al[lv].items_f = at<int4>(w.ptr, L.items_f[lv]);
+    al[lv].pitem_g = at<int>(w.ptr, L.pitem_g[lv]);
+    al[lv].pitem_f = at<int>(w.ptr, L.pitem_f[lv]);
+    al[lv].n_items_g = L.n_items_g[lv];
+    al[lv].n_items_f = L.n_items_f[lv];
+  }
 
-  // One chunk of iterations (g and f half-steps) and the compaction, captured once per plan.
+  // The plan: start at item level lv0 and move to lv1 (one finer, or the same) once the busier
+  // side has at most tau x (resident waves) active items. The automatic plan takes the
+  // autotuned candidate of this size signature (see kBatchCand).
+  const int plan = batched_plan();
+  int lv0 = 0, lv1 = 1, tune_idx = -1;
+  double tau = 2.0;
+  bool exploring = false, after_first = false;
+  const BatchSig sig = batch_sig(B, offN, offM, d, check_every, tol);
+  if (plan == kPlanCoarse) {
+    lv1 = 0;
+  } else if (plan == kPlanFine) {
+    lv0 = lv1 = 1;
+  } else if (plan == kPlanFinest) {
+    lv0 = lv1 = 2;
+  } else if (plan == kPlanSwitchAfterFirst) {
+    after_first = true;
+  } else {
+    {
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      BatchTune &bt = g_batch_tune[sig];
+      if (bt.claimed < kNumBatchCand) {
+        tune_idx = bt.claimed++;
+        exploring = true;
+      } else {
+        tune_idx = 0;
+        for (int i = 1; i < kNumBatchCand; ++i)
+          if (bt.ms[i] < bt.ms[tune_idx]) tune_idx = i;
+      }
+    }
+    lv0 = kBatchCand[tune_idx].lv0;
+    lv1 = kBatchCand[tune_idx].lv1;
+    tau = kBatchCand[tune_idx].tau;
+  }
+  g_batch_last = plan == kPlanAuto ? kBatchCand[tune_idx] : BatchCand{-1, -1, -1.0};
+  auto want_next = [&](const BatchCounters &c, int chunks_done) {
+    if (after_first) return chunks_done >= 1;
+    return lv1 != lv0 && (double)(c.nact_g > c.nact_f ? c.nact_g : c.nact_f) <= tau * resident_waves;
+  };
+
+  UOT_HIP(launch_batched_init(al[lv0], s));
+  UOT_HIP(launch_batched_compact(al[lv0], s));
+
+  // One chunk of iterations (g and f half-steps) and the compaction, captured once per level
+  // the plan uses.
   const int chunk = tol > 0.0 ? check_every : (max_iter < 64 ? max_iter : 64);
   auto capture = [&](const BatchedArgs &pa, GraphGuard &gg) -> uot_status {
     UOT_HIP(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
@@ -1729,44 +1782,9 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     UOT_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
     return UOT_OK;
   };
-  GraphGuard gg, gg2;
-  UOT_TRY(capture(a, gg));
-  UOT_TRY(capture(a2, gg2));
-  // Switch to the fine plan (once) when the busier side has at most twice as many coarse
-  // items as the launch has resident waves (4 per block). A fine item (two targets per lane)
-  // costs more per entry than a coarse one (four), so it pays only once the long items of
-  // big problems, not the total work, bound a launch. batch2d, updates/s: coarse only
-  // 2.52e12; switching at 1/2, 2, 4, 8x the waves 2.63, 2.71, 2.71, 2.59e12 (one target per
-  // lane instead of two: 2.63e12 at 1/2 and 1x, 2.24e12 at 4x). The process-wide plan setting
-  // (uot_batched_set_plan) can instead keep either plan throughout, or switch after the first
-  // chunk.
-  const int resident_waves = blocks * 4;
-  const int plan = batched_plan();
-  // the automatic plan's switch point: the next untried candidate of this size signature, or
-  // the fastest once all have run
-  int tune_idx = -1;
-  bool exploring = false;
-  const BatchSig sig = batch_sig(B, offN, offM, d, check_every, tol);
-  if (plan == kPlanAuto) {
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    BatchTune &bt = g_batch_tune[sig];
-    if (bt.claimed < kNumBatchTau) {
-      tune_idx = bt.claimed++;
-      exploring = true;
-    } else {
-      tune_idx = 0;
-      for (int i = 1; i < kNumBatchTau; ++i)
-        if (bt.ms[i] < bt.ms[tune_idx]) tune_idx = i;
-    }
-  }
-  const double tau = tune_idx >= 0 ? kBatchTau[tune_idx] : 2.0;
-  g_batch_last_tau = plan == kPlanAuto ? tau : -1.0;
-  auto want_fine = [&](const BatchCounters &c, int chunks_done) {
-    if (plan == kPlanCoarse) return false;
-    if (plan == kPlanFine) return true;
-    if (plan == kPlanSwitchAfterFirst) return chunks_done >= 1;
-    return (double)(c.nact_g > c.nact_f ? c.nact_g : c.nact_f) <= tau * resident_waves;
-  };
+  GraphGuard gg[kBatchLevels];
+  UOT_TRY(capture(al[lv0], gg[lv0]));
+  if (lv1 != lv0) UOT_TRY(capture(al[lv1], gg[lv1]));
 
   // host copies of the counters after each chunk (two slots, read one chunk late)
   PinnedState pin;
@@ -1782,11 +1800,11 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   } evg{ev};
   std::vector<BatchTraceRow> trace;
   unsigned long long busy_prev = 0, t_prev = 0;
-  auto record = [&](const BatchCounters &c, int chunk, bool fine_plan) {
+  auto record = [&](const BatchCounters &c, int chunk, int level) {
     if (!tracing) return;
     BatchTraceRow r;
     r.chunk = chunk;
-    r.fine = fine_plan ? 1 : 0;
+    r.fine = level;
     r.running = c.running;
     r.items_g = c.nact_g;
     r.items_f = c.nact_f;
@@ -1801,27 +1819,27 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   // counters right after initialisation: active coarse items of each side, problems running
   UOT_HIP(hipMemcpyAsync(&cnt_h[2], ctrs, sizeof(BatchCounters), hipMemcpyDeviceToHost, s));
   UOT_HIP(hipStreamSynchronize(s));
-  record(cnt_h[2], 0, false);
+  record(cnt_h[2], 0, lv0);
   const int max_chunks = (max_iter + chunk - 1) / chunk;
   const auto t_start = std::chrono::steady_clock::now();
-  bool fine = false;
+  int lv = lv0;
   if (cnt_h[2].running > 0) {
-    if (want_fine(cnt_h[2], 0)) {
-      UOT_HIP(launch_batched_compact(a2, s));
-      fine = true;
+    if (lv1 != lv0 && !after_first && want_next(cnt_h[2], 0)) {
+      UOT_HIP(launch_batched_compact(al[lv1], s));
+      lv = lv1;
     }
     for (int c = 0; c < max_chunks; ++c) {
-      UOT_HIP(hipGraphLaunch(fine ? gg2.e : gg.e, s));
+      UOT_HIP(hipGraphLaunch(gg[lv].e, s));
       UOT_HIP(hipMemcpyAsync(&cnt_h[c & 1], ctrs, sizeof(BatchCounters), hipMemcpyDeviceToHost, s));
       UOT_HIP(hipEventRecord(ev[c & 1], s));
       if (c >= 1) {
         UOT_HIP(hipEventSynchronize(ev[(c - 1) & 1]));
         const BatchCounters cnt = cnt_h[(c - 1) & 1];
-        record(cnt, c, fine);
+        record(cnt, c, lv);
         if (cnt.running == 0) break;
-        if (!fine && want_fine(cnt, c)) {  // after chunk c (queued): rebuild the active lists
-          UOT_HIP(launch_batched_compact(a2, s));
-          fine = true;
+        if (lv != lv1 && want_next(cnt, c)) {  // after chunk c (queued): rebuild the active lists
+          UOT_HIP(launch_batched_compact(al[lv1], s));
+          lv = lv1;
         }
       }
     }
@@ -1997,7 +2015,13 @@ uot_status uot_fw1d_batched(int32_t B, const int64_t *offN, const int64_t *offM,
                    f, g, iters, gap, status, workspace, workspace_bytes, stream);
 }
 
-double uot_batched_last_threshold(void) { return uot::g_batch_last_tau; }
+int32_t uot_batched_last_plan(int32_t *start_level, int32_t *end_level, double *threshold) {
+  const uot::BatchCand c = uot::g_batch_last;
+  if (start_level) *start_level = c.lv0;
+  if (end_level) *end_level = c.lv1;
+  if (threshold) *threshold = c.tau;
+  return c.lv0 >= 0 ? 1 : 0;
+}
 
 void uot_batched_autotune_reset(void) {
   std::lock_guard<std::mutex> lk(uot::g_batch_mu);
@@ -2005,7 +2029,7 @@ void uot_batched_autotune_reset(void) {
 }
 
 int32_t uot_batched_set_plan(int32_t plan) {
-  if (plan < uot::kPlanAuto || plan > uot::kPlanSwitchAfterFirst) return -1;
+  if (plan < uot::kPlanAuto || plan > uot::kPlanFinest) return -1;
   std::lock_guard<std::mutex> lk(uot::g_batch_mu);
   const int32_t prev = uot::g_batch_plan;
   uot::g_batch_plan = plan;

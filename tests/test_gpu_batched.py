@@ -67,10 +67,10 @@ class _plan:
 
 
 PLANS = {"auto": uot.BATCH_PLAN_AUTO, "coarse": uot.BATCH_PLAN_COARSE,
-         "fine": uot.BATCH_PLAN_FINE}
+         "fine": uot.BATCH_PLAN_FINE, "finest": uot.BATCH_PLAN_FINEST}
 
 
-@pytest.mark.parametrize("plan", ["coarse", "fine", "auto"])
+@pytest.mark.parametrize("plan", ["coarse", "fine", "finest", "auto"])
 @pytest.mark.parametrize("d,p,nmax", [(2, 2.0, 300), (3, 2.0, 300), (1, 2.0, 300), (5, 1.5, 300),
                                        (8, 2.0, 300), (2, 2.0, 1100), (3, 1.5, 700)])
 def test_batched_iteration_parity(d, p, nmax, plan):
@@ -192,20 +192,21 @@ def test_batched_load_statistics():
     assert np.sum(tr["busy_ticks"]) > 0
 
 
-def test_batched_autotuned_plan_switch():
-    """The automatic plan explores one switch threshold per call for a new size signature
-    (seven candidates, from coarse-only to fine from the start), then keeps the fastest; the
-    potentials agree across every candidate (the plan changes only how targets are grouped
-    into work items) and with the oracle."""
+def test_batched_autotuned_plan():
+    """The automatic plan explores one candidate per call for a new size signature (seven:
+    item levels and switch points from 256-target items throughout to 64-target items
+    throughout), then keeps the fastest; the potentials agree across every candidate (the plan
+    changes only how targets are grouped into work items) and with the oracle."""
     bt = small_batch(B=40, nmin=64, nmax=700, seed=57)
     uot.batched_autotune_reset()
-    with _plan(0):
-        runs, taus = [], []
+    with _plan(uot.BATCH_PLAN_AUTO):
+        runs, plans = [], []
         for _ in range(8):
             runs.append(run_batched(bt, 12))
-            taus.append(uot.batched_last_threshold())
-    assert taus[:7] == [0.0, 0.5, 1.0, 2.0, 4.0, 8.0, 1e30], taus
-    assert taus[7] in taus[:7]
+            plans.append(uot.batched_last_plan())
+    assert plans[:7] == [(0, 0, 0.0), (0, 1, 2.0), (0, 1, 8.0), (1, 1, 0.0), (1, 2, 2.0),
+                         (1, 2, 8.0), (2, 2, 0.0)], plans
+    assert plans[7] in plans[:7]
     f0, g0 = runs[0][0], runs[0][1]
     for f, g, it, st in runs[1:]:
         assert rel_inf(f, f0) < 1e-6 and rel_inf(g, g0) < 1e-6
@@ -215,6 +216,6 @@ def test_batched_autotuned_plan_switch():
         n0, n1 = bt.offN[b], bt.offN[b + 1]
         m0, m1 = bt.offM[b], bt.offM[b + 1]
         assert rel_inf(f0[n0:n1], r.f) < TOL and rel_inf(g0[m0:m1], r.g) < TOL
-    with _plan(1):
+    with _plan(uot.BATCH_PLAN_COARSE):
         run_batched(bt, 2)
-        assert uot.batched_last_threshold() == -1.0
+        assert uot.batched_last_plan() is None
