@@ -493,6 +493,16 @@ uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stream);
 int32_t uot_set_points_kernel(int32_t variant);
 
 /*
+ * Implementation of the backward's per-entry pass (uot_backward, uot_backward_noalloc and
+ * the marginals of uot_plan_apply, points costs) for dimensions 9 to 16, process-wide:
+ * 0 = default, matrix cores (double-precision MFMA inner products, float32 MFMA gradient
+ * sums), 1 = vector ALU. Other dimensions always take the vector ALU. Both form the same exponents in double precision and
+ * the same sums in float32 (in another order). Returns the previous setting, or -1 for an
+ * unknown value (then nothing changes); must not be changed while calls are running.
+ */
+int32_t uot_set_grad_kernel(int32_t variant);
+
+/*
  * Kernel-shape autotuning, process-wide, on by default: the first solve (uot_sinkhorn,
  * uot_ti_sinkhorn and their variants) of a shape with at least 2^20 cost entries per
  * half-step times its own first half-step's softmin with several source-split counts (the

@@ -134,6 +134,8 @@ def load_library():
     lib.uot_probe_rate.restype = I32
     lib.uot_set_points_kernel.argtypes = [I32]
     lib.uot_set_points_kernel.restype = I32
+    lib.uot_set_grad_kernel.argtypes = [I32]
+    lib.uot_set_grad_kernel.restype = I32
     lib.uot_ti_sinkhorn_batched.argtypes = [I32, P, P, I32, D, P, P, P, P, P, P, P, I32, D, I32,
                                             P, P, P, P, P, S, P]
     lib.uot_ti_sinkhorn_batched.restype = ctypes.c_int
@@ -286,6 +288,18 @@ def probe_rate(kind: int) -> float:
 
 POINTS_KERNEL_AUTO, POINTS_KERNEL_VALU, POINTS_KERNEL_MFMA_F32, POINTS_KERNEL_MFMA_BF16 = 0, 1, 2, 3
 POINTS_KERNEL_DIRECT = 4  # p = 2 through the differences x - y (no expanded-form rounding)
+
+
+GRAD_KERNEL_MFMA, GRAD_KERNEL_VALU = 0, 1
+
+
+def set_grad_kernel(variant: int) -> int:
+    """Select the backward's per-entry pass for dimensions 9 to 16 (0 matrix cores, the
+    default; 1 vector ALU); returns the previous setting."""
+    prev = load_library().uot_set_grad_kernel(int(variant))
+    if prev < 0:
+        raise ValueError("unknown backward kernel variant %r" % (variant,))
+    return prev
 
 
 def set_points_kernel(variant: int) -> int:

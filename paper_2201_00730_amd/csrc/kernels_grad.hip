@@ -30,6 +30,7 @@
 //
 // Work split: each lane owns R targets (coordinates in double, accumulators in float, all in
 // registers); the sources of one split are uniform across the wave and read with scalar loads.
+#include <atomic>
 #include <cfloat>
 
 #include "uot_internal.h"
@@ -231,14 +232,174 @@ __global__ __launch_bounds__(256) void k_grad_combine(GradCombineArgs a) {
   }
 }
 
+// Matrix-core form of k_grad_partial for coordinate buckets 12 and 16 (p = 2 or not). Per
+// 16-source step and 16-target group a wave forms the 256 inner products <s', t'> with
+// D/4 double-precision MFMAs (v_mfma_f64_16x16x4_f64: the same FP64 products and sums as
+// the vector form, in another order), evaluates exponents and exp2 on the vector ALU, and
+// accumulates the gradient sums a_tk = sum_s q_ts w_ts s'_k with four float32 MFMAs
+// (v_mfma_f32_16x16x4_f32) whose A operand is the q tile just computed. Operand layouts of
+// these 16x16x4 instructions (checked on the device): A[i][k] in lane i + 16 k and B[k][j] in
+// lane j + 16 k for both; the result D[i][j] sits in lane j + 16 (i % 4), element i / 4, for
+// the double-precision one and in lane j + 16 (i / 4), element i % 4, for the float32 one.
+// With sources as the rows of the inner-product tile, lane j + 16 c holds the entries
+// (target j, sources c + 4 r, r = 0..3): element r is the A operand (k = c) of the q-tile
+// MFMA over sources 4 r .. 4 r + 3, so no data moves between the two products.
+// All four lanes of a target (c = 0..3) share one integer-valued reference, raised together
+// (a max over the lane quarter) so the MFMA sums over c add entries of one scale.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaGroups = 4;  // 16-target groups per wave: 256 targets per block
+
+template <int D>
+constexpr bool grad_uses_mfma() {
+  return D == 12 || D == 16;
+}
+
+template <int D, bool GRAD, bool P2>
+__global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
+  static_assert(D % 4 == 0 && D <= 16, "coordinate bucket must be 12 or 16");
+  constexpr int SD = grad_rec_stride(D);
+  constexpr int PS = grad_part_stride(GRAD ? D : 0);
+  constexpr int KS = D / 4;
+  constexpr int G = kMfmaGroups;
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, qr = lane >> 4;
+  const int tw = blockIdx.x * (4 * G * 16) + (threadIdx.x >> 6) * (G * 16);
+  const double sc = a.sc, half_p = a.half_p;
+  const float p = a.p;
+
+  double tb[G][KS], yn[G];
+  float ref[G], l[G], lw[G];
+  f32x4 acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int t = tw + 16 * g + col;
+    const int tc = t < a.nt ? t : a.nt - 1;
+    const float *tp = a.tgt + (size_t)tc * a.d;
+    double nn = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double v = k < a.d ? (double)tp[k] - a.mu[k] : 0.0;
+      nn = fma(v, v, nn);
+    }
+    yn[g] = nn;
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      const int k = 4 * j + qr;
+      tb[g][j] = k < a.d ? (double)tp[k] - a.mu[k] : 0.0;
+    }
+    ref[g] = -FLT_MAX;
+    l[g] = 0.0f;
+    lw[g] = 0.0f;
+    acc[g] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  const int s0 = blockIdx.y * a.split_len;
+  const int s1 = min(a.ns, s0 + a.split_len);
+
+  for (int sb = s0; sb < s1; sb += 16) {
+    // A operand of the inner products: source sb + col, coordinates 4 j + qr.
+    const double *ra = a.rec + (size_t)min(sb + col, s1 - 1) * SD;
+    double av[KS];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) av[j] = ra[4 * j + qr];
+    // This lane's four entries per group: sources sb + qr + 4 i.
+    double sn[4], bs[4];
+    float sv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int si = sb + qr + 4 * i;
+      const double *rp = a.rec + (size_t)min(si, s1 - 1) * SD;
+      sn[i] = rp[D];
+      bs[i] = si < s1 ? rp[D + 1] : -INFINITY;
+      if constexpr (GRAD) sv[i] = col < D ? reinterpret_cast<const float *>(rp + D + 2)[col] : 0.0f;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      f64x4 dd = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < KS; ++j) dd = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], tb[g][j], dd, 0, 0, 0);
+      double e[4], d2[4], cst[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        d2[i] = fma(-2.0, dd[i], yn[g] + sn[i]);
+        cst[i] = cost_of<P2>(d2[i], half_p);
+        e[i] = fma(-sc, cst[i], bs[i]);
+      }
+      const double m = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
+      const bool up = m > (double)ref[g];
+      if (__builtin_amdgcn_ballot_w64(up)) {  // raise the quarter's shared reference
+        float mc = up ? ceilf((float)m) : ref[g];
+        mc = fmaxf(mc, __shfl_xor(mc, 16));
+        mc = fmaxf(mc, __shfl_xor(mc, 32));
+        const float nr = fmaxf(mc, ref[g]);
+        const float scale = fexp2(ref[g] - nr);  // a power of two (or 0 from -FLT_MAX)
+        ref[g] = nr;
+        l[g] *= scale;
+        if constexpr (GRAD) {
+          lw[g] *= scale;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[g][i] *= __shfl(scale, 4 * qr + i);
+        }
+      }
+      float q[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = fexp2((float)(e[i] - (double)ref[g]));
+      l[g] += (q[0] + q[1]) + (q[2] + q[3]);
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float qw = P2 ? q[i] : q[i] * weight_of<P2>(d2[i], cst[i], p);
+          if constexpr (!P2) lw[g] += qw;
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(qw, sv[i], acc[g], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    float lt = l[g] + __shfl_xor(l[g], 16);
+    lt += __shfl_xor(lt, 32);
+    float lwt = lw[g];
+    if constexpr (GRAD && !P2) {
+      lwt += __shfl_xor(lwt, 16);
+      lwt += __shfl_xor(lwt, 32);
+    }
+    const int t = tw + 16 * g + col;
+    if (qr == 0 && t < a.nt) {
+      float *o = a.part + ((size_t)blockIdx.y * a.nt + t) * PS;
+      o[0] = lt > 0.0f ? ref[g] : -FLT_MAX;
+      o[1] = lt;
+      if constexpr (GRAD) o[2] = P2 ? lt : lwt;
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ti = tw + 16 * g + 4 * qr + i;
+        if (ti < a.nt && col < D) a.part[((size_t)blockIdx.y * a.nt + ti) * PS + 3 + col] = acc[g][i];
+      }
+    }
+  }
+}
+
 template <int D>
 hipError_t records_for(const GradRecordArgs &a, hipStream_t s) {
   hipLaunchKernelGGL((k_grad_records<D>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
+// Backward kernel choice for buckets 12 and 16: 0 the matrix-core form, 1 the vector form.
+std::atomic<int> g_grad_variant{0};
+
 template <int D, bool GRAD, bool P2>
 hipError_t grad_for(const GradArgs &a, hipStream_t s, const LaunchTiming *t) {
+  if constexpr (grad_uses_mfma<D>()) {
+    if (g_grad_variant.load(std::memory_order_relaxed) == 0) {
+      dim3 grid((a.nt + 64 * kMfmaGroups - 1) / (64 * kMfmaGroups), a.nsplit);
+      return launch_timed(k_grad_mfma<D, GRAD, P2>, grid, dim3(256), s, t, a);
+    }
+  }
   constexpr int R = grad_targets_per_lane<D>();
   dim3 grid((a.nt + 256 * R - 1) / (256 * R), a.nsplit);
   return launch_timed(k_grad_partial<D, R, GRAD, P2>, grid, dim3(256), s, t, a);
@@ -280,6 +441,8 @@ hipError_t combine_for(const GradCombineArgs &a, hipStream_t s) {
 
 int grad_targets_per_block(int d) {
   const int b = dim_bucket(d);
+  if ((b == 12 || b == 16) && g_grad_variant.load(std::memory_order_relaxed) == 0)
+    return 64 * kMfmaGroups;
   return 256 * (b <= 8 ? 4 : (b <= 16 ? 2 : 1));
 }
 
@@ -300,3 +463,8 @@ hipError_t launch_grad_combine(const GradCombineArgs &a, hipStream_t s) {
 }
 
 }  // namespace uot
+
+extern "C" int32_t uot_set_grad_kernel(int32_t variant) {
+  if (variant < 0 || variant > 1) return -1;
+  return uot::g_grad_variant.exchange(variant);
+}

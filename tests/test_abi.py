@@ -124,6 +124,23 @@ def test_points_kernel_switch_keeps_workspace_size(lib):
     assert all(s == sizes[0] for s in sizes), sizes
 
 
+def test_grad_kernel_switch_keeps_workspace_size(lib):
+    """Both backward implementations fit the same workspace; unknown settings are refused."""
+    prev = uot.set_grad_kernel(uot.GRAD_KERNEL_MFMA)
+    sizes = []
+    try:
+        for v in (uot.GRAD_KERNEL_MFMA, uot.GRAD_KERNEL_VALU):
+            assert uot.set_grad_kernel(v) in (0, 1)
+            sizes.append([lib.uot_workspace_bytes(ctypes.byref(_cost(n=1000, m=900, d=d)),
+                                                  uot.UOT_WS_BACKWARD) for d in (3, 12, 16)])
+        assert lib.uot_set_grad_kernel(2) == -1 and lib.uot_set_grad_kernel(-1) == -1
+        with pytest.raises(ValueError):
+            uot.set_grad_kernel(2)
+    finally:
+        uot.set_grad_kernel(prev)
+    assert sizes[0] == sizes[1], sizes
+
+
 def test_solver_rejects_bad_cost(lib):
     prm = uot._Params(0.1, 1.0, 1.0, 10, 0.0, 1, 0)
     for bad in (_cost(n=0), _cost(d=100), _cost(p=0.0), _cost(kind=0, ldc=3)):

@@ -289,6 +289,26 @@ def test_backward_matches_oracle_gradients(d, p):
     _check_backward(prc, rr.f.astype(np.float32), rr.g.astype(np.float32))
 
 
+@pytest.mark.parametrize("n,m,d,p", [(1, 1, 16, 2.0), (17, 300, 16, 2.0), (300, 17, 12, 2.0),
+                                     (513, 1031, 16, 2.0), (257, 333, 9, 1.5), (400, 333, 16, 1.5)])
+def test_backward_kernels_agree(n, m, d, p):
+    """Both implementations of the backward pass for dimensions 9 to 16 (matrix cores, the
+    default, and vector ALU) match the oracle, with and without point gradients, on ragged
+    target tiles and source steps."""
+    prc = workloads.random_small(n, m, d=d, seed=n + 3 * m + d, eps=0.05, rho1=0.8, rho2=1.6, p=p)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
+    prev = uot.set_grad_kernel(uot.GRAD_KERNEL_MFMA)
+    try:
+        for variant in (uot.GRAD_KERNEL_MFMA, uot.GRAD_KERNEL_VALU):
+            uot.set_grad_kernel(variant)
+            _say("backward kernel %d n=%d m=%d d=%d p=%g" % (variant, n, m, d, p))
+            _check_backward(prc, f32, g32)
+            _check_backward(prc, f32, g32, need_dx=False)
+    finally:
+        uot.set_grad_kernel(prev)
+
+
 def test_backward_weight_gradients_only_and_dense():
     """Without point gradients (sums only) and for a stored cost."""
     prc = workloads.random_small(400, 333, d=3, seed=31, eps=0.05, rho1=0.8, rho2=1.6)
