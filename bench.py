@@ -221,7 +221,8 @@ def extra_workload(args, uot, torch, np, workloads):
                                            "independent chains of 2048 steps per lane"},
                     "rates": rates,
                     "spec": {"exp2": PEAK_EXP_PER_S, "fma32": 256 * 4 * 16 * 2.4e9,
-                             "fma64": 256 * 4 * 16 * 2.4e9},
+                             "fma64": 256 * 4 * 16 * 2.4e9, "mfma_f64_flops": 78.6e12,
+                             "mfma_f32_flops": 157.3e12, "mfma_bf16_flops": 2.5e15},
                     "roofline": None})
         print(json.dumps(out))
         return
@@ -521,9 +522,13 @@ def extra_workload(args, uot, torch, np, workloads):
 
 
 def issue_rates(uot):
-    """Measured chip-wide rates (lane-operations/s) of v_exp_f32, float32 FMA and double FMA."""
+    """Measured chip-wide rates of v_exp_f32, float32 FMA and double FMA (lane-operations/s)
+    and of the double, float32 and bf16 MFMAs the kernels use (flop/s)."""
     return {"exp2": uot.probe_rate(uot.PROBE_EXP2), "fma32": uot.probe_rate(uot.PROBE_FMA32),
-            "fma64": uot.probe_rate(uot.PROBE_FMA64)}
+            "fma64": uot.probe_rate(uot.PROBE_FMA64),
+            "mfma_f64_flops": uot.probe_rate(uot.PROBE_MFMA_F64),
+            "mfma_f32_flops": uot.probe_rate(uot.PROBE_MFMA_F32),
+            "mfma_bf16_flops": uot.probe_rate(uot.PROBE_MFMA_BF16)}
 
 
 def cpu_baseline(pr, seconds):

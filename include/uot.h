@@ -468,15 +468,25 @@ void uot_profile_reset(void);
 int64_t uot_profile_read(int32_t kind, double *total_ms, double *total_entries);
 
 /*
- * Issue-rate probes, for benchmarks: the chip-wide throughput of one vector instruction kind
- * on the current device, the rates behind the rooflines of the softmin (v_exp_f32), the
- * backward (double and float32 FMAs) and the batched kernels. Each lane runs 8 independent
- * dependency chains of the instruction (8 waves resident per SIMD); one untimed launch, then
- * one launch timed with HIP events on `stream`. Writes lane-operations per second to
- * *ops_per_s (host). Allocates and frees a small device buffer; synchronises `stream`.
+ * Issue-rate probes, for benchmarks: the chip-wide throughput of one instruction kind on the
+ * current device, the rates behind the rooflines of the softmin (v_exp_f32, bf16 MFMA), the
+ * backward (double and float32 FMAs, double and float32 MFMAs) and the batched kernels. Each
+ * lane (vector kinds) or wave (matrix-core kinds) runs independent dependency chains of the
+ * instruction (8, or 4 for bf16; 8 waves resident per SIMD); one untimed launch, then one
+ * launch timed with HIP events on `stream`. Writes to *ops_per_s (host) lane-operations per
+ * second for the vector kinds, flop/s for the matrix-core kinds (v_mfma_f64_16x16x4_f64,
+ * v_mfma_f32_16x16x4_f32, v_mfma_f32_32x32x16_bf16: 2 M N K flops per instruction).
+ * Allocates and frees a small device buffer; synchronises `stream`.
  * UOT_ERR_INVALID for an unknown kind or a NULL output, UOT_ERR_HIP on a runtime error.
  */
-typedef enum { UOT_PROBE_EXP2 = 0, UOT_PROBE_FMA32 = 1, UOT_PROBE_FMA64 = 2 } uot_probe_kind;
+typedef enum {
+  UOT_PROBE_EXP2 = 0,
+  UOT_PROBE_FMA32 = 1,
+  UOT_PROBE_FMA64 = 2,
+  UOT_PROBE_MFMA_F64 = 3,
+  UOT_PROBE_MFMA_F32 = 4,
+  UOT_PROBE_MFMA_BF16 = 5
+} uot_probe_kind;
 uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stream);
 
 /*

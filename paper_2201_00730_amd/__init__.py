@@ -275,11 +275,14 @@ def batched_autotune_reset():
 
 
 PROBE_EXP2, PROBE_FMA32, PROBE_FMA64 = 0, 1, 2
+PROBE_MFMA_F64, PROBE_MFMA_F32, PROBE_MFMA_BF16 = 3, 4, 5
 
 
 def probe_rate(kind: int) -> float:
-    """Measured chip-wide issue rate (lane-operations per second) of one vector instruction
-    kind on the current device: PROBE_EXP2 (v_exp_f32), PROBE_FMA32, PROBE_FMA64."""
+    """Measured chip-wide rate of one instruction kind on the current device: lane-operations
+    per second for PROBE_EXP2 (v_exp_f32), PROBE_FMA32 and PROBE_FMA64; flop/s for the
+    matrix-core kinds PROBE_MFMA_F64 (16x16x4 f64), PROBE_MFMA_F32 (16x16x4 f32) and
+    PROBE_MFMA_BF16 (32x32x16 bf16)."""
     _require_gpu()
     out = ctypes.c_double(0.0)
     _check(load_library().uot_probe_rate(int(kind), ctypes.byref(out), _stream()))

@@ -48,9 +48,19 @@ constexpr int grad_targets_per_lane() {
 template <int D>
 __global__ __launch_bounds__(256) void k_grad_records(GradRecordArgs a) {
   const int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= a.n) return;
+  if (s >= a.n + kGradPadRows) return;
   double *r = a.rec + (size_t)s * grad_rec_stride(D);
   float *rf = reinterpret_cast<float *>(r + D + 2);
+  if (s >= a.n) {  // padding: no mass
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      r[k] = 0.0;
+      rf[k] = 0.0f;
+    }
+    r[D] = 0.0;
+    r[D + 1] = -INFINITY;
+    return;
+  }
   double nn = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -266,10 +276,10 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, qr = lane >> 4;
   const int tw = blockIdx.x * (4 * G * 16) + (threadIdx.x >> 6) * (G * 16);
-  const double sc = a.sc, half_p = a.half_p;
+  const double sc = a.sc, half_p = a.half_p, sc2 = 2.0 * a.sc;
   const float p = a.p;
 
-  double tb[G][KS], yn[G];
+  double tb[G][KS], yn[G], base[G];  // base: -r_t, plus -sc |t'|^2 for p = 2
   float ref[G], l[G], lw[G];
   f32x4 acc[G];
 #pragma unroll
@@ -283,13 +293,14 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
       const double v = k < a.d ? (double)tp[k] - a.mu[k] : 0.0;
       nn = fma(v, v, nn);
     }
-    yn[g] = nn;
+    yn[g] = P2 ? -sc * nn : nn;  // p = 2: the target's share of the exponent
 #pragma unroll
     for (int j = 0; j < KS; ++j) {
       const int k = 4 * j + qr;
       tb[g][j] = k < a.d ? (double)tp[k] - a.mu[k] : 0.0;
     }
     ref[g] = -FLT_MAX;
+    base[g] = (P2 ? yn[g] : 0.0) + (double)FLT_MAX;
     l[g] = 0.0f;
     lw[g] = 0.0f;
     acc[g] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -297,54 +308,90 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
   const int s0 = blockIdx.y * a.split_len;
   const int s1 = min(a.ns, s0 + a.split_len);
 
-  for (int sb = s0; sb < s1; sb += 16) {
-    // A operand of the inner products: source sb + col, coordinates 4 j + qr.
-    const double *ra = a.rec + (size_t)min(sb + col, s1 - 1) * SD;
-    double av[KS];
-#pragma unroll
-    for (int j = 0; j < KS; ++j) av[j] = ra[4 * j + qr];
-    // This lane's four entries per group: sources sb + qr + 4 i.
-    double sn[4], bs[4];
+  // Operands of one 16-source step: the inner products' A operand (source sb + col,
+  // coordinates 4 j + qr) and this lane's four entries per group (sources sb + qr + 4 i:
+  // |s'|^2, b_s, and coordinate col for the gradient sums), loaded one step ahead. Split
+  // lengths are multiples of 16, so only the last split ends inside a step, and the padding
+  // records after the last source (b = -inf, zero coordinates) complete that step.
+  struct Step {
+    double av[KS], sn[4], bs[4];
     float sv[4];
+  };
+  auto load_step = [&](int sb, Step &st) {
+    const double *ra = a.rec + (size_t)(sb + col) * SD;
+    const double *rb = a.rec + (size_t)(sb + qr) * SD;
+#pragma unroll
+    for (int j = 0; j < KS; ++j) st.av[j] = ra[4 * j + qr];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int si = sb + qr + 4 * i;
-      const double *rp = a.rec + (size_t)min(si, s1 - 1) * SD;
-      sn[i] = rp[D];
-      bs[i] = si < s1 ? rp[D + 1] : -INFINITY;
-      if constexpr (GRAD) sv[i] = col < D ? reinterpret_cast<const float *>(rp + D + 2)[col] : 0.0f;
+      const double *rp = rb + 4 * i * SD;
+      const double2 nb = *reinterpret_cast<const double2 *>(rp + D);  // |s'|^2, b_s
+      st.sn[i] = nb.x;
+      st.bs[i] = nb.y;
+      if constexpr (GRAD) st.sv[i] = col < D ? reinterpret_cast<const float *>(rp + D + 2)[col] : 0.0f;
     }
+  };
+  const int last = s0 + (s1 - 1 - s0) / 16 * 16;  // first source of the last step
+  Step cur;
+  if (s0 < s1) load_step(s0, cur);
+  for (int sb = s0; sb < s1; sb += 16) {
+    Step nxt;
+    load_step(min(sb + 16, last), nxt);  // the last step loads itself again (in bounds)
+    const double(&av)[KS] = cur.av;
+    const double(&sn)[4] = cur.sn;
+    const double(&bs)[4] = cur.bs;
+    const float(&sv)[4] = cur.sv;
+    double cb[4];  // p = 2: the source's share b_s - sc |s'|^2, common to the groups
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cb[i] = P2 ? fma(-sc, sn[i], bs[i]) : 0.0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       f64x4 dd = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int j = 0; j < KS; ++j) dd = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], tb[g][j], dd, 0, 0, 0);
-      double e[4], d2[4], cst[4];
+      // exponents relative to the reference, e - r_t, in double; rounded to float32 for
+      // the test against 0 and for exp2
+      double er[4], d2[4], cst[4];
+      float ef[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        d2[i] = fma(-2.0, dd[i], yn[g] + sn[i]);
-        cst[i] = cost_of<P2>(d2[i], half_p);
-        e[i] = fma(-sc, cst[i], bs[i]);
+        if constexpr (P2) {  // e - r = (b_s - sc |s'|^2) + (-sc |t'|^2 - r) + 2 sc <s', t'>
+          er[i] = fma(sc2, dd[i], cb[i] + base[g]);
+        } else {
+          d2[i] = fma(-2.0, dd[i], yn[g] + sn[i]);
+          cst[i] = cost_of<P2>(d2[i], half_p);
+          er[i] = fma(-sc, cst[i], bs[i] + base[g]);
+        }
+        ef[i] = (float)er[i];
       }
-      const double m = fmax(fmax(e[0], e[1]), fmax(e[2], e[3]));
-      const bool up = m > (double)ref[g];
+      const bool up = fmaxf(fmaxf(ef[0], ef[1]), fmaxf(ef[2], ef[3])) > 0.0f;
       if (__builtin_amdgcn_ballot_w64(up)) {  // raise the quarter's shared reference
+        double ea[4];  // absolute exponents (e - r_t + r_t would cancel for r_t = -FLT_MAX)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ea[i] = P2 ? fma(sc2, dd[i], cb[i] + yn[g]) : fma(-sc, cst[i], bs[i]);
+        const double m = fmax(fmax(ea[0], ea[1]), fmax(ea[2], ea[3]));
         float mc = up ? ceilf((float)m) : ref[g];
         mc = fmaxf(mc, __shfl_xor(mc, 16));
         mc = fmaxf(mc, __shfl_xor(mc, 32));
         const float nr = fmaxf(mc, ref[g]);
         const float scale = fexp2(ref[g] - nr);  // a power of two (or 0 from -FLT_MAX)
         ref[g] = nr;
+        base[g] = (P2 ? yn[g] : 0.0) - (double)nr;
         l[g] *= scale;
         if constexpr (GRAD) {
           lw[g] *= scale;
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[g][i] *= __shfl(scale, 4 * qr + i);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {  // recomputed: the old reference may be -FLT_MAX
+          er[i] = P2 ? fma(sc2, dd[i], cb[i] + base[g]) : fma(-sc, cst[i], bs[i] + base[g]);
+          ef[i] = (float)er[i];
+        }
       }
       float q[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) q[i] = fexp2((float)(e[i] - (double)ref[g]));
+      for (int i = 0; i < 4; ++i) q[i] = fexp2(ef[i]);
       l[g] += (q[0] + q[1]) + (q[2] + q[3]);
       if constexpr (GRAD) {
 #pragma unroll
@@ -355,6 +402,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
         }
       }
     }
+    cur = nxt;
   }
 
 #pragma unroll
@@ -385,7 +433,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
 
 template <int D>
 hipError_t records_for(const GradRecordArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_grad_records<D>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_grad_records<D>), dim3((a.n + kGradPadRows + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -438,6 +486,11 @@ hipError_t combine_for(const GradCombineArgs &a, hipStream_t s) {
   }
 
 }  // namespace
+
+int grad_source_align(int d) {
+  const int b = dim_bucket(d);
+  return (b == 12 || b == 16) && g_grad_variant.load(std::memory_order_relaxed) == 0 ? 16 : 1;
+}
 
 int grad_targets_per_block(int d) {
   const int b = dim_bucket(d);

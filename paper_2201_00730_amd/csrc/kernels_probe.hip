@@ -6,7 +6,9 @@
 // Each lane runs kChains independent dependency chains of one instruction kind for kSteps
 // steps (the chains hide the instruction latency; 8 waves per SIMD are resident), and the
 // launch is timed with HIP events around it after one untimed launch. The rate is
-// lanes x chains x steps / time, in lane-operations per second.
+// lanes x chains x steps / time, in lane-operations per second, for the vector kinds, and
+// waves x chains x steps x (2 M N K) / time, in flop/s, for the matrix-core kinds (each wave
+// issues independent accumulations of one MFMA shape).
 #include "uot.h"
 #include "uot_internal.h"
 
@@ -17,10 +19,71 @@ constexpr int kChains = 8;
 constexpr int kSteps = 2048;
 constexpr int kProbeBlocks = 2048;  // 256 CUs x 8 waves per SIMD at 4 waves per block
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Flops of one matrix-core instruction of a probe kind (0 for the vector kinds).
+constexpr double mfma_flops(int kind) {
+  return kind == UOT_PROBE_MFMA_F64 ? 2.0 * 16 * 16 * 4
+         : kind == UOT_PROBE_MFMA_F32 ? 2.0 * 16 * 16 * 4
+         : kind == UOT_PROBE_MFMA_BF16 ? 2.0 * 32 * 32 * 16 : 0.0;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) void k_probe(float *out, float seed) {
   const int tid = blockIdx.x * 256 + threadIdx.x;
-  if constexpr (KIND == UOT_PROBE_FMA64) {
+  if constexpr (KIND == UOT_PROBE_MFMA_F64) {
+    const double x = (double)seed + 1e-3 * (tid & 63), y = 1.0 - 1e-3 * (tid & 7);
+    f64x4 acc[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < kSteps; ++i) {
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[c], 0, 0, 0);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    out[tid] = (float)s;
+  } else if constexpr (KIND == UOT_PROBE_MFMA_F32) {
+    const float x = seed + 1e-3f * (float)(tid & 63), y = 1.0f - 1e-3f * (float)(tid & 7);
+    f32x4 acc[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc[c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int i = 0; i < kSteps; ++i) {
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc[c], 0, 0, 0);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    out[tid] = s;
+  } else if constexpr (KIND == UOT_PROBE_MFMA_BF16) {
+    constexpr int C = kChains / 2;  // 16 accumulator registers per chain
+    bf16x8 x, y;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      x[k] = (__bf16)(seed + 1e-2f * (float)((tid + k) & 7));
+      y[k] = (__bf16)(1.0f - 1e-2f * (float)((tid + 3 * k) & 7));
+    }
+    f32x16 acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+    for (int i = 0; i < kSteps; ++i) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc[c], 0, 0, 0);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s += acc[c][r];
+    out[tid] = s;
+  } else if constexpr (KIND == UOT_PROBE_FMA64) {
     double v[kChains];
 #pragma unroll
     for (int c = 0; c < kChains; ++c) v[c] = (double)seed + 0.01 * (c + (tid & 7));
@@ -65,6 +128,9 @@ hipError_t probe_dispatch(int kind, float *out, hipStream_t s) {
     case UOT_PROBE_EXP2: return probe_launch<UOT_PROBE_EXP2>(out, s);
     case UOT_PROBE_FMA32: return probe_launch<UOT_PROBE_FMA32>(out, s);
     case UOT_PROBE_FMA64: return probe_launch<UOT_PROBE_FMA64>(out, s);
+    case UOT_PROBE_MFMA_F64: return probe_launch<UOT_PROBE_MFMA_F64>(out, s);
+    case UOT_PROBE_MFMA_F32: return probe_launch<UOT_PROBE_MFMA_F32>(out, s);
+    case UOT_PROBE_MFMA_BF16: return probe_launch<UOT_PROBE_MFMA_BF16>(out, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -74,7 +140,7 @@ hipError_t probe_dispatch(int kind, float *out, hipStream_t s) {
 
 extern "C" uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stream) {
   using namespace uot;
-  if (kind < UOT_PROBE_EXP2 || kind > UOT_PROBE_FMA64 || ops_per_s == nullptr)
+  if (kind < UOT_PROBE_EXP2 || kind > UOT_PROBE_MFMA_BF16 || ops_per_s == nullptr)
     return UOT_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float *out = nullptr;
@@ -87,7 +153,10 @@ extern "C" uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stre
       hipEventSynchronize(e1) == hipSuccess) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f) {
-      *ops_per_s = (double)kProbeBlocks * 256.0 * kChains * kSteps / (ms * 1e-3);
+      const double f = mfma_flops(kind);
+      const double chains = kind == UOT_PROBE_MFMA_BF16 ? kChains / 2 : kChains;
+      *ops_per_s = f > 0.0 ? (double)kProbeBlocks * 4.0 * chains * kSteps * f / (ms * 1e-3)
+                           : (double)kProbeBlocks * 256.0 * kChains * kSteps / (ms * 1e-3);
       st = UOT_OK;
     }
   }

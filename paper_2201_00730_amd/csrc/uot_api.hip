@@ -262,7 +262,7 @@ Layout make_layout(const uot_cost *c, int which, int mode_override = -1) {
     const bool pts = c->kind == UOT_COST_POINTS;
     const int db = pts ? dim_bucket(d) : 0;
     const size_t rb = pts ? grad_rec_stride(db) * sizeof(double) : sizeof(float);
-    L.grad_rec = take((size_t)rec_count(nmax) * rb);
+    L.grad_rec = take((size_t)rec_count(nmax + kGradPadRows) * rb);
     const size_t ps = pts ? (size_t)kGradMaxSplits * grad_part_stride(db)
                           : (size_t)kMaxSplits * grad_part_stride(0);
     L.grad_part = take(ps * (size_t)nmax * sizeof(float));
@@ -1080,7 +1080,8 @@ uot_status envelope_side(const uot_cost *c, bool tx, const float *alpha, const f
     ga.rec = rec;
     ga.ns = ns;
     const int tiles = (nt + grad_targets_per_block(c->d) - 1) / grad_targets_per_block(c->d);
-    const Split sp = make_split(ns, tiles, 64, 1, (cus > 0 ? cus : 256) * 4, kGradMaxSplits);
+    const Split sp = make_split(ns, tiles, 64, grad_source_align(c->d), (cus > 0 ? cus : 256) * 4,
+                                kGradMaxSplits);
     ga.split_len = sp.len;
     ga.nsplit = nsplit = sp.n;
     ga.sc = sc;

@@ -346,6 +346,9 @@ __host__ __device__ constexpr int grad_rec_stride(int D) { return D + 2 + (D + 1
 // the stored-cost softmin partials (max, sum) have the layout of grad_part_stride(0).
 __host__ __device__ constexpr int grad_part_stride(int D) { return D > 0 ? D + 3 : 2; }
 constexpr int kGradMaxSplits = 16;
+// Source records of the backward pass are followed by kGradPadRows padding records (zero
+// coordinates and norms, b = -inf) so a 16-source step may run past the last source.
+constexpr int kGradPadRows = 16;
 struct GradRecordArgs {
   const float *pts;    // raw source coordinates [n, d]
   const float *w;      // source weights [n]
@@ -353,7 +356,7 @@ struct GradRecordArgs {
   const double *mu;    // centring (SolveState::mu)
   int n, d;
   double sc;
-  double *rec;         // [n, grad_rec_stride(bucket)]
+  double *rec;         // [n + kGradPadRows, grad_rec_stride(bucket)]
 };
 struct GradArgs {
   const float *tgt;    // raw target coordinates [nt, d]
@@ -382,6 +385,7 @@ struct GradCombineArgs {
   float *dpts;         // optional: point gradient [nt, d] (needs grad partials)
 };
 int grad_targets_per_block(int d);
+int grad_source_align(int d);  // split lengths of the backward pass are multiples of this
 hipError_t launch_grad_records(const GradRecordArgs &a, hipStream_t s);
 hipError_t launch_grad_partial(const GradArgs &a, hipStream_t s, const LaunchTiming *t = nullptr);
 hipError_t launch_grad_combine(const GradCombineArgs &a, hipStream_t s);
