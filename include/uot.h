@@ -504,11 +504,12 @@ int32_t uot_set_points_kernel(int32_t variant);
 
 /*
  * Implementation of the backward's per-entry pass (uot_backward, uot_backward_noalloc and
- * the marginals of uot_plan_apply, points costs) for dimensions 9 to 16, process-wide:
+ * the marginals of uot_plan_apply, points costs) for dimensions 1 to 16, process-wide:
  * 0 = default, matrix cores (double-precision MFMA inner products, float32 MFMA gradient
- * sums), 1 = vector ALU. Other dimensions always take the vector ALU. Both form the same exponents in double precision and
- * the same sums in float32 (in another order). Returns the previous setting, or -1 for an
- * unknown value (then nothing changes); must not be changed while calls are running.
+ * sums), 1 = vector ALU. Other dimensions always take the vector ALU. Both form the same
+ * exponents in double precision and the same sums in float32 (in another order). Returns the
+ * previous setting, or -1 for an unknown value (then nothing changes); must not be changed
+ * while calls are running.
  */
 int32_t uot_set_grad_kernel(int32_t variant);
 

@@ -297,7 +297,7 @@ GRAD_KERNEL_MFMA, GRAD_KERNEL_VALU = 0, 1
 
 
 def set_grad_kernel(variant: int) -> int:
-    """Select the backward's per-entry pass for dimensions 9 to 16 (0 matrix cores, the
+    """Select the backward's per-entry pass for dimensions 1 to 16 (0 matrix cores, the
     default; 1 vector ALU); returns the previous setting."""
     prev = load_library().uot_set_grad_kernel(int(variant))
     if prev < 0:

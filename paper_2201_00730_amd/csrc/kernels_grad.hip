@@ -28,8 +28,11 @@
 // e - r_t in [-few, 0] whatever the potentials, which keeps the float32 rounding of e - r_t
 // small where it matters. The combine takes the references exactly.
 //
-// Work split: each lane owns R targets (coordinates in double, accumulators in float, all in
-// registers); the sources of one split are uniform across the wave and read with scalar loads.
+// Two implementations of this pass: k_grad_mfma (dimension buckets up to 16, the default;
+// inner products and gradient sums on the matrix cores) and k_grad_partial (every bucket;
+// vector ALU). In k_grad_partial each lane owns R targets (coordinates in double,
+// accumulators in float, all in registers); the sources of one split are uniform across the
+// wave and read with scalar loads.
 #include <atomic>
 #include <cfloat>
 
@@ -242,10 +245,11 @@ __global__ __launch_bounds__(256) void k_grad_combine(GradCombineArgs a) {
   }
 }
 
-// Matrix-core form of k_grad_partial for coordinate buckets 12 and 16 (p = 2 or not). Per
+// Matrix-core form of k_grad_partial for coordinate buckets up to 16 (p = 2 or not). Per
 // 16-source step and 16-target group a wave forms the 256 inner products <s', t'> with
-// D/4 double-precision MFMAs (v_mfma_f64_16x16x4_f64: the same FP64 products and sums as
-// the vector form, in another order), evaluates exponents and exp2 on the vector ALU, and
+// ceil(D/4) double-precision MFMAs (v_mfma_f64_16x16x4_f64, coordinates past D zero: the
+// same FP64 products and sums as the vector form, in another order), evaluates exponents
+// and exp2 on the vector ALU, and
 // accumulates the gradient sums a_tk = sum_s q_ts w_ts s'_k with four float32 MFMAs
 // (v_mfma_f32_16x16x4_f32) whose A operand is the q tile just computed. Operand layouts of
 // these 16x16x4 instructions (checked on the device): A[i][k] in lane i + 16 k and B[k][j] in
@@ -263,15 +267,15 @@ constexpr int kMfmaGroups = 4;  // 16-target groups per wave: 256 targets per bl
 
 template <int D>
 constexpr bool grad_uses_mfma() {
-  return D == 12 || D == 16;
+  return D <= 16;
 }
 
 template <int D, bool GRAD, bool P2>
 __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
-  static_assert(D % 4 == 0 && D <= 16, "coordinate bucket must be 12 or 16");
+  static_assert(D <= 16, "coordinate bucket must be at most 16");
   constexpr int SD = grad_rec_stride(D);
   constexpr int PS = grad_part_stride(GRAD ? D : 0);
-  constexpr int KS = D / 4;
+  constexpr int KS = (D + 3) / 4;
   constexpr int G = kMfmaGroups;
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, qr = lane >> 4;
@@ -321,13 +325,18 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
     const double *ra = a.rec + (size_t)(sb + col) * SD;
     const double *rb = a.rec + (size_t)(sb + qr) * SD;
 #pragma unroll
-    for (int j = 0; j < KS; ++j) st.av[j] = ra[4 * j + qr];
+    for (int j = 0; j < KS; ++j) st.av[j] = (4 * j + 4 > D && 4 * j + qr >= D) ? 0.0 : ra[4 * j + qr];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double *rp = rb + 4 * i * SD;
-      const double2 nb = *reinterpret_cast<const double2 *>(rp + D);  // |s'|^2, b_s
-      st.sn[i] = nb.x;
-      st.bs[i] = nb.y;
+      if constexpr (SD % 2 == 0 && D % 2 == 0) {  // |s'|^2, b_s: one 16-byte aligned load
+        const double2 nb = *reinterpret_cast<const double2 *>(rp + D);
+        st.sn[i] = nb.x;
+        st.bs[i] = nb.y;
+      } else {
+        st.sn[i] = rp[D];
+        st.bs[i] = rp[D + 1];
+      }
       if constexpr (GRAD) st.sv[i] = col < D ? reinterpret_cast<const float *>(rp + D + 2)[col] : 0.0f;
     }
   };
@@ -437,7 +446,7 @@ hipError_t records_for(const GradRecordArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Backward kernel choice for buckets 12 and 16: 0 the matrix-core form, 1 the vector form.
+// Backward kernel choice for buckets up to 16: 0 the matrix-core form, 1 the vector form.
 std::atomic<int> g_grad_variant{0};
 
 template <int D, bool GRAD, bool P2>
@@ -489,12 +498,12 @@ hipError_t combine_for(const GradCombineArgs &a, hipStream_t s) {
 
 int grad_source_align(int d) {
   const int b = dim_bucket(d);
-  return (b == 12 || b == 16) && g_grad_variant.load(std::memory_order_relaxed) == 0 ? 16 : 1;
+  return b <= 16 && g_grad_variant.load(std::memory_order_relaxed) == 0 ? 16 : 1;
 }
 
 int grad_targets_per_block(int d) {
   const int b = dim_bucket(d);
-  if ((b == 12 || b == 16) && g_grad_variant.load(std::memory_order_relaxed) == 0)
+  if (b <= 16 && g_grad_variant.load(std::memory_order_relaxed) == 0)
     return 64 * kMfmaGroups;
   return 256 * (b <= 8 ? 4 : (b <= 16 ? 2 : 1));
 }

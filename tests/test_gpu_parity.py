@@ -290,11 +290,13 @@ def test_backward_matches_oracle_gradients(d, p):
 
 
 @pytest.mark.parametrize("n,m,d,p", [(1, 1, 16, 2.0), (17, 300, 16, 2.0), (300, 17, 12, 2.0),
-                                     (513, 1031, 16, 2.0), (257, 333, 9, 1.5), (400, 333, 16, 1.5)])
+                                     (513, 1031, 16, 2.0), (257, 333, 9, 1.5), (400, 333, 16, 1.5),
+                                     (1000, 1337, 1, 2.0), (33, 65, 3, 2.0), (200, 150, 5, 1.5),
+                                     (64, 80, 8, 2.0)])
 def test_backward_kernels_agree(n, m, d, p):
-    """Both implementations of the backward pass for dimensions 9 to 16 (matrix cores, the
-    default, and vector ALU) match the oracle, with and without point gradients, on ragged
-    target tiles and source steps."""
+    """Both implementations of the backward pass for dimensions up to 16 (matrix cores, the
+    default where it is faster, and vector ALU) match the oracle, with and without point
+    gradients, on ragged target tiles and source steps."""
     prc = workloads.random_small(n, m, d=d, seed=n + 3 * m + d, eps=0.05, rho1=0.8, rho2=1.6, p=p)
     rr = run_oracle(prc, True, 100000, tol=1e-12)
     f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
