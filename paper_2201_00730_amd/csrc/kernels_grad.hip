@@ -233,6 +233,12 @@ __global__ __launch_bounds__(256) void k_grad_combine(GradCombineArgs a) {
     a.dw[t] = (float)(a.gout * v);
   }
   if constexpr (DC > 0) {
+    if (a.apply_out) {  // payload pass: (pi V)_tc = w_t 2^{sc h_t + M} sum_s q_ts V_sc
+      const double fac = wt * base;
+#pragma unroll
+      for (int k = 0; k < DC; ++k)
+        if (k < a.d) a.apply_out[(size_t)t * a.ldout + k] = (float)(fac * acc[k]);
+    }
     if (a.dpts) {
       const double fac = wt > 0.0 ? a.gout * wt * base * a.pfac : 0.0;
 #pragma unroll
@@ -270,11 +276,14 @@ constexpr bool grad_uses_mfma() {
   return D <= 16;
 }
 
-template <int D, bool GRAD, bool P2>
+// PAY: a payload pass of the plan application (GRAD true): the B operand of the q-tile MFMAs
+// is V[s, col] (col < vcols, zero past the last source) and the entries carry no weight.
+template <int D, bool GRAD, bool P2, bool PAY = false>
 __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
   static_assert(D <= 16, "coordinate bucket must be at most 16");
+  static_assert(GRAD || !PAY, "a payload pass accumulates");
   constexpr int SD = grad_rec_stride(D);
-  constexpr int PS = grad_part_stride(GRAD ? D : 0);
+  constexpr int PS = PAY ? grad_part_stride(16) : grad_part_stride(GRAD ? D : 0);
   constexpr int KS = (D + 3) / 4;
   constexpr int G = kMfmaGroups;
   const int lane = threadIdx.x & 63;
@@ -337,7 +346,12 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
         st.sn[i] = rp[D];
         st.bs[i] = rp[D + 1];
       }
-      if constexpr (GRAD) st.sv[i] = col < D ? reinterpret_cast<const float *>(rp + D + 2)[col] : 0.0f;
+      if constexpr (PAY) {
+        const int si = sb + qr + 4 * i;
+        st.sv[i] = (col < a.vcols && si < a.ns) ? a.V[(size_t)si * a.ldv + col] : 0.0f;
+      } else if constexpr (GRAD) {
+        st.sv[i] = col < D ? reinterpret_cast<const float *>(rp + D + 2)[col] : 0.0f;
+      }
     }
   };
   const int last = s0 + (s1 - 1 - s0) / 16 * 16;  // first source of the last step
@@ -405,8 +419,8 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
       if constexpr (GRAD) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float qw = P2 ? q[i] : q[i] * weight_of<P2>(d2[i], cst[i], p);
-          if constexpr (!P2) lw[g] += qw;
+          const float qw = (P2 || PAY) ? q[i] : q[i] * weight_of<P2>(d2[i], cst[i], p);
+          if constexpr (!P2 && !PAY) lw[g] += qw;
           acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(qw, sv[i], acc[g], 0, 0, 0);
         }
       }
@@ -419,7 +433,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
     float lt = l[g] + __shfl_xor(l[g], 16);
     lt += __shfl_xor(lt, 32);
     float lwt = lw[g];
-    if constexpr (GRAD && !P2) {
+    if constexpr (GRAD && !P2 && !PAY) {
       lwt += __shfl_xor(lwt, 16);
       lwt += __shfl_xor(lwt, 32);
     }
@@ -428,13 +442,13 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
       float *o = a.part + ((size_t)blockIdx.y * a.nt + t) * PS;
       o[0] = lt > 0.0f ? ref[g] : -FLT_MAX;
       o[1] = lt;
-      if constexpr (GRAD) o[2] = P2 ? lt : lwt;
+      if constexpr (GRAD) o[2] = (P2 || PAY) ? lt : lwt;
     }
     if constexpr (GRAD) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int ti = tw + 16 * g + 4 * qr + i;
-        if (ti < a.nt && col < D) a.part[((size_t)blockIdx.y * a.nt + ti) * PS + 3 + col] = acc[g][i];
+        if (ti < a.nt && col < (PAY ? 16 : D)) a.part[((size_t)blockIdx.y * a.nt + ti) * PS + 3 + col] = acc[g][i];
       }
     }
   }
@@ -446,7 +460,9 @@ hipError_t records_for(const GradRecordArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Backward kernel choice for buckets up to 16: 0 the matrix-core form, 1 the vector form.
+// Backward kernel choice for buckets up to 16: 0 the matrix-core form (also the plan
+// application's payload passes), 1 the vector form (the plan application then takes the
+// float32-exponent apply kernel).
 std::atomic<int> g_grad_variant{0};
 
 template <int D, bool GRAD, bool P2>
@@ -454,9 +470,14 @@ hipError_t grad_for(const GradArgs &a, hipStream_t s, const LaunchTiming *t) {
   if constexpr (grad_uses_mfma<D>()) {
     if (g_grad_variant.load(std::memory_order_relaxed) == 0) {
       dim3 grid((a.nt + 64 * kMfmaGroups - 1) / (64 * kMfmaGroups), a.nsplit);
+      if (a.V != nullptr) {
+        if constexpr (GRAD) return launch_timed(k_grad_mfma<D, true, P2, true>, grid, dim3(256), s, t, a);
+        return hipErrorInvalidValue;
+      }
       return launch_timed(k_grad_mfma<D, GRAD, P2>, grid, dim3(256), s, t, a);
     }
   }
+  if (a.V != nullptr) return hipErrorInvalidValue;  // payload passes: matrix-core buckets only
   constexpr int R = grad_targets_per_lane<D>();
   dim3 grid((a.nt + 256 * R - 1) / (256 * R), a.nsplit);
   return launch_timed(k_grad_partial<D, R, GRAD, P2>, grid, dim3(256), s, t, a);
@@ -496,6 +517,10 @@ hipError_t combine_for(const GradCombineArgs &a, hipStream_t s) {
 
 }  // namespace
 
+bool grad_payload_supported(int d) {
+  return dim_bucket(d) <= 16 && g_grad_variant.load(std::memory_order_relaxed) == 0;
+}
+
 int grad_source_align(int d) {
   const int b = dim_bucket(d);
   return b <= 16 && g_grad_variant.load(std::memory_order_relaxed) == 0 ? 16 : 1;
@@ -519,6 +544,7 @@ hipError_t launch_grad_partial(const GradArgs &a, hipStream_t s, const LaunchTim
 }
 
 hipError_t launch_grad_combine(const GradCombineArgs &a, hipStream_t s) {
+  if (a.apply_out != nullptr) return a.d <= 16 ? combine_for<16>(a, s) : hipErrorInvalidValue;
   if (a.dpts == nullptr) return combine_for<0>(a, s);
   UOT_GRAD_BUCKETS(combine_for, dim_bucket(a.d), a, s)
   return hipErrorInvalidValue;

@@ -263,7 +263,11 @@ Layout make_layout(const uot_cost *c, int which, int mode_override = -1) {
     const int db = pts ? dim_bucket(d) : 0;
     const size_t rb = pts ? grad_rec_stride(db) * sizeof(double) : sizeof(float);
     L.grad_rec = take((size_t)rec_count(nmax + kGradPadRows) * rb);
-    const size_t ps = pts ? (size_t)kGradMaxSplits * grad_part_stride(db)
+    // (a plan application's payload passes keep 16 columns per partial)
+    const bool pay = pts && which == UOT_WS_PLAN && db <= 16;
+    const int pstride = pay && grad_part_stride(16) > grad_part_stride(db) ? grad_part_stride(16)
+                                                                           : grad_part_stride(db);
+    const size_t ps = pts ? (size_t)kGradMaxSplits * pstride
                           : (size_t)kMaxSplits * grad_part_stride(0);
     L.grad_part = take(ps * (size_t)nmax * sizeof(float));
     L.masses = take(2 * sizeof(double));
@@ -1007,6 +1011,78 @@ ApplyArgs apply_args(const uot_cost *c, int mode, bool targets_x, const float *a
   return a;
 }
 
+// The plan applied to a payload V (points costs whose dimension bucket takes the matrix-core
+// pass; targets x when tx): the records of the other side, then per 16 columns of V one pass
+// over the sources (exponent in double precision, one exp2 per entry) and the split merge
+// writing out[t, c0 .. c0 + 15].
+uot_status apply_payload(const uot_cost *c, bool tx, const float *alpha, const float *beta,
+                         const float *f, const float *g, double eps, SolveState *st, void *ws,
+                         const Layout &L, const float *V, int kc, int64_t ldv, float *out,
+                         int64_t ldout, hipStream_t s) {
+  const int nt = tx ? c->n : c->m, ns = tx ? c->m : c->n;
+  const double sc = kLog2e / eps;
+  double *rec = at<double>(ws, L.grad_rec);
+  float *part = at<float>(ws, L.grad_part);
+  GradRecordArgs ra;
+  ra.pts = tx ? c->y : c->x;
+  ra.w = tx ? beta : alpha;
+  ra.pot = tx ? g : f;
+  ra.mu = st->mu;
+  ra.n = ns;
+  ra.d = c->d;
+  ra.sc = sc;
+  ra.rec = rec;
+  UOT_HIP(launch_grad_records(ra, s));
+  const int cus = device_cus();
+  const int tiles = (nt + grad_targets_per_block(c->d) - 1) / grad_targets_per_block(c->d);
+  const Split sp = make_split(ns, tiles, 64, grad_source_align(c->d), (cus > 0 ? cus : 256) * 4,
+                              kGradMaxSplits);
+  for (int c0 = 0; c0 < kc; c0 += 16) {
+    GradArgs ga;
+    ga.tgt = tx ? c->x : c->y;
+    ga.nt = nt;
+    ga.d = c->d;
+    ga.mu = st->mu;
+    ga.h_t = tx ? f : g;
+    ga.rec = rec;
+    ga.ns = ns;
+    ga.split_len = sp.len;
+    ga.nsplit = sp.n;
+    ga.sc = sc;
+    ga.half_p = 0.5 * c->p;
+    ga.p = (float)c->p;
+    ga.grad = 1;
+    ga.part = part;
+    ga.V = V + c0;
+    ga.ldv = ldv;
+    ga.vcols = kc - c0 < 16 ? kc - c0 : 16;
+    UOT_HIP(launch_grad_partial(ga, s));
+    GradCombineArgs ca;
+    ca.part = part;
+    ca.nsplit = sp.n;
+    ca.nt = nt;
+    ca.d = ga.vcols;
+    ca.tgt = nullptr;
+    ca.mu = st->mu;
+    ca.h_t = tx ? f : g;
+    ca.w_t = tx ? alpha : beta;
+    ca.sc = sc;
+    ca.eps = eps;
+    ca.rho = 1.0;
+    ca.gout = 1.0;
+    ca.pfac = 1.0;
+    ca.mass_other = nullptr;
+    ca.marg = nullptr;
+    ca.marg_stride = 0;
+    ca.dw = nullptr;
+    ca.dpts = nullptr;
+    ca.apply_out = out + c0;
+    ca.ldout = ldout;
+    UOT_HIP(launch_grad_combine(ca, s));
+  }
+  return UOT_OK;
+}
+
 // Row sums of the plan for the targets of one side (targets x when tx), in one pass over the
 // other side's points (kernels_grad.hip) or one stored-cost softmin, and what is asked of
 // them: the plan marginal (marg, element t at marg[t * marg_stride]), the weight gradient
@@ -1146,6 +1222,9 @@ uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, 
   if (V == nullptr) {  // the marginals: row sums in one pass
     UOT_TRY(envelope_side(c, transpose == 0, alpha, beta, f, g, eps, 1.0, 1.0, st, w.ptr, L, out,
                           ldout, nullptr, nullptr, nullptr, s));
+  } else if (c->kind == UOT_COST_POINTS && grad_payload_supported(c->d)) {
+    UOT_TRY(apply_payload(c, transpose == 0, alpha, beta, f, g, eps, st, w.ptr, L, V, kc, ldv, out,
+                          ldout, s));
   } else {
     ApplyArgs a = apply_args(c, mode_of(c), transpose == 0, alpha, beta, f, g, eps, st);
     a.V = V;

@@ -368,7 +368,14 @@ struct GradArgs {
   double sc, half_p;
   float p;
   int grad;            // 1: accumulate the point gradient (else sums only)
-  float *part;         // [nsplit, nt, grad_part_stride(grad ? bucket : 0)]
+  float *part;         // [nsplit, nt, grad_part_stride(grad ? bucket : 0)], or
+                       // [nsplit, nt, grad_part_stride(16)] for a payload pass
+  // Payload pass (plan application, matrix-core pass only): V != nullptr accumulates
+  // sum_s q_ts V[s, c] for c < vcols <= 16 (V offset to its first column, row stride ldv)
+  // in place of the gradient sums.
+  const float *V = nullptr;
+  int64_t ldv = 0;
+  int vcols = 0;
 };
 struct GradCombineArgs {
   const float *part;   // partials as GradArgs::part (or stored-cost softmin partials)
@@ -383,9 +390,12 @@ struct GradCombineArgs {
   int64_t marg_stride;
   float *dw;           // optional: weight gradient
   float *dpts;         // optional: point gradient [nt, d] (needs grad partials)
+  float *apply_out = nullptr;  // optional: plan applied to a payload, out[t * ldout + c]
+  int64_t ldout = 0;           //   for c < d (partials of a payload pass; d = its columns)
 };
 int grad_targets_per_block(int d);
 int grad_source_align(int d);  // split lengths of the backward pass are multiples of this
+bool grad_payload_supported(int d);  // the matrix-core pass runs payload passes for this d
 hipError_t launch_grad_records(const GradRecordArgs &a, hipStream_t s);
 hipError_t launch_grad_partial(const GradArgs &a, hipStream_t s, const LaunchTiming *t = nullptr);
 hipError_t launch_grad_combine(const GradCombineArgs &a, hipStream_t s);

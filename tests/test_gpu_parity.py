@@ -227,6 +227,43 @@ def test_dual_value(solved, mode):
     assert abs(v - ref) <= TOL * abs(ref), (v, ref)
 
 
+@pytest.mark.parametrize("n,m,d,p,k,eps", [(513, 1031, 3, 2.0, 37, 0.05), (1, 1, 16, 2.0, 5, 0.05),
+                                          (300, 17, 16, 1.5, 64, 0.05), (257, 333, 2, 2.0, 16, 0.05),
+                                          (400, 333, 12, 2.0, 1, 0.05), (400, 333, 3, 2.0, 7, 0.005)])
+def test_plan_apply_payload_passes(n, m, d, p, k, eps):
+    """pi V and pi^T V through the one-pass matrix-core kernel (16 columns per pass, exponent
+    in double precision) against the oracle at converged potentials, on ragged tiles and
+    column counts; the float32-exponent apply kernel (uot_set_grad_kernel(1)) on the same
+    inputs at eps = 0.05, where its exponent rounding 2^-24 sc C stays below 1e-5."""
+    prc = workloads.random_small(n, m, d=d, seed=n + m + k, eps=eps, rho1=0.8, rho2=1.6, p=p)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
+    cost = oracle_cost(prc)
+    a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
+    kw = dict(x=dev(prc.x), y=dev(prc.y), p=p, eps=eps)
+    rng = np.random.default_rng(k)
+    variants = (uot.GRAD_KERNEL_MFMA, uot.GRAD_KERNEL_VALU) if eps >= 0.05 else (uot.GRAD_KERNEL_MFMA,)
+    prev = uot.set_grad_kernel(uot.GRAD_KERNEL_MFMA)
+    try:
+        for variant in variants:
+            uot.set_grad_kernel(variant)
+            for transpose, rows_src in ((False, m), (True, n)):
+                V = rng.normal(size=(rows_src, k)).astype(np.float32)
+                _say("plan apply kernel %d n=%d m=%d d=%d p=%g k=%d eps=%g T=%d"
+                     % (variant, n, m, d, p, k, eps, transpose))
+                out = uot.plan_apply(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), dev(V),
+                                     transpose=transpose, **kw).cpu().numpy().reshape(-1, k)
+                f64, g64 = f32.astype(np.float64), g32.astype(np.float64)
+                ref = oracle.plan_apply(cost, a, b, eps, f64, g64, V.astype(np.float64),
+                                        transpose=transpose).reshape(-1, k)
+                scale = oracle.plan_apply(cost, a, b, eps, f64, g64, np.abs(V).astype(np.float64),
+                                          transpose=transpose).reshape(-1, k)
+                assert np.max(np.abs(out - ref)) <= TOL * np.max(scale), \
+                    (variant, transpose, np.max(np.abs(out - ref)) / np.max(scale))
+    finally:
+        uot.set_grad_kernel(prev)
+
+
 @pytest.mark.parametrize("dense", [False, True])
 def test_marginals_and_plan_apply(solved, dense):
     pr, r = solved
