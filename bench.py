@@ -284,7 +284,7 @@ def extra_workload(args, uot, torch, np, workloads):
         # the first calls of this size signature explore the autotuned plan switch (one
         # candidate threshold each); the timed call then runs the fastest
         explore = []
-        for _ in range(8):
+        for _ in range(10):
             _, dte = _timed(torch, run)
             lv0, lv1, tau = uot.batched_last_plan()
             explore.append({"levels": [lv0, lv1], "threshold": tau, "seconds": dte})
@@ -323,8 +323,9 @@ def extra_workload(args, uot, torch, np, workloads):
                     "value": ups / dt, "seconds": dt,
                     "config": {"workload": "4096 problems, N_p,M_p ~ U{64..4096}, D=2, "
                                            "eps log-U[1e-3,1e-1], rho log-U[0.1,10], TI to 1e-6"},
-                    "autotune": {"item_levels": "0: <= 256 targets per item, 1: <= 128, 2: <= 64",
-                                 "explored": explore[:7],
+                    "autotune": {"item_levels": "0: <= 256 targets per item, 1: <= 128, 2: <= 64, "
+                                                "3: 64 with sources split in ranges of 512",
+                                 "explored": explore[:9],
                                  "chosen": {"levels": list(chosen[:2]), "threshold": chosen[2]}},
                     "iterations_percentiles_0_50_90_99_100": hist,
                     "iterations_histogram": {"%d-%d" % (edges[i], edges[i + 1] - 1): int(counts[i])

@@ -414,17 +414,19 @@ size_t uot_batched_workspace_bytes(int32_t B, const int64_t *offN, const int64_t
 /*
  * Work-item plan of uot_ti_sinkhorn_batched, process-wide (for tests and benchmarks; the plan
  * only changes how targets are grouped into work items, i.e. the order of the per-problem
- * partial sums). Items come at three levels: up to 256 targets (level 0, four per lane), 128
- * (level 1, two per lane) or 64 (level 2, one per lane).
- *  0 = automatic and autotuned: a plan starts at one level and moves to the next finer one
- *      once the busier side has at most tau x (resident waves) active items. For each size
- *      signature (device, B, d, check_every, tol > 0 and the log2 sizes of sum N, sum M,
- *      max N, max M) the first seven calls each run one candidate of
+ * partial sums). Items come at four levels: up to 256 targets (level 0, four per lane), 128
+ * (level 1, two per lane), 64 (level 2, one per lane), and level 3: the chunks of level 2
+ * with their sources split into ranges of 512, one item per range, whose per-target partial
+ * sums the last of them to finish merges.
+ *  0 = automatic and autotuned: a plan starts at one level and moves to a finer one once the
+ *      busier side has at most tau x (resident waves) active items. For each size signature
+ *      (device, B, d, check_every, tol > 0 and the log2 sizes of sum N, sum M, max N, max M)
+ *      the first nine calls each run one candidate of
  *      {level 0 throughout; 0 then 1 at tau = 2; 0 then 1 at tau = 8; level 1 throughout;
- *       1 then 2 at tau = 2; 1 then 2 at tau = 8; level 2 throughout}, timed on the host,
- *      and later calls take the fastest;
+ *       1 then 2 at tau = 2; 1 then 2 at tau = 8; level 2 throughout; 1 then 3 at tau = 2;
+ *       1 then 3 at tau = 0.5}, timed on the host, and later calls take the fastest;
  *  1 = level 0 throughout, 2 = level 1 throughout, 3 = level 0 for the first chunk of
- *  iterations and level 1 after it, 4 = level 2 throughout.
+ *  iterations and level 1 after it, 4 = level 2 throughout, 5 = level 3 throughout.
  * Returns the previous setting, or -1 for an unknown value (nothing changes). Must not be
  * changed while a batched solve runs.
  */

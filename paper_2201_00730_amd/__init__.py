@@ -263,7 +263,8 @@ def set_autotune(on: bool) -> bool:
 
 def batched_last_plan():
     """(start level, end level, tau) of this thread's last batched solve under the automatic
-    plan (item levels 0, 1, 2: up to 256, 128, 64 targets per item), or None."""
+    plan (item levels 0, 1, 2: up to 256, 128, 64 targets per item; 3: 64-target items with
+    their sources split into ranges of 512), or None."""
     a, b, t = ctypes.c_int32(-1), ctypes.c_int32(-1), ctypes.c_double(-1.0)
     ok = load_library().uot_batched_last_plan(ctypes.byref(a), ctypes.byref(b), ctypes.byref(t))
     return (a.value, b.value, t.value) if ok else None
@@ -572,6 +573,7 @@ def ti_sinkhorn_batched(offN, offM, x, y, alpha, beta, eps, rho1, rho2=None, *, 
 
 BATCH_PLAN_AUTO, BATCH_PLAN_COARSE, BATCH_PLAN_FINE, BATCH_PLAN_SWITCH = 0, 1, 2, 3
 BATCH_PLAN_FINEST = 4
+BATCH_PLAN_SPLIT = 5  # 64-target items with their sources split into ranges of 512
 
 
 def batched_set_plan(plan: int) -> int:

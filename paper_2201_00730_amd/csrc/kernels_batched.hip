@@ -145,8 +145,14 @@ __device__ __noinline__ void reduce_problem(const BatchedArgs &a, int p, bool g_
 // targets it.y + l + 64 r for r < R (R = 1, 2, 4 for items of at most 64, 128, 256 targets), so that
 // each source record read feeds R targets per lane. Softmin over all sources of p, epilogue,
 // item partials, and the problem's reduction by the last wave to finish one of its items.
-template <int D, bool SQ, int R>
-__device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, const int4 it) {
+// SPLIT (R = 1): the softmin over sources it2.x .. it2.x + it2.y - 1 of p only; the item
+// publishes its per-target (max, sum), and the last item of its group (slots it2.z ..
+// it2.z + it2.w - 1, counted at it2.z) merges the group's partials and runs the epilogue;
+// the others leave an empty item partial.
+template <int D, bool SQ, int R, bool SPLIT = false>
+__device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, const int4 it,
+                                             const int4 it2 = make_int4(0, 0, 0, 1)) {
+  static_assert(!SPLIT || R == 1, "split items hold one target per lane");
   const int lane = threadIdx.x & 63;
   const int64_t *off_t = g_step ? a.offM : a.offN;
   const int64_t *off_s = g_step ? a.offN : a.offM;
@@ -180,8 +186,9 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
 #pragma unroll
     for (int k = 0; k < D; ++k) yc[r][k] = k < a.d ? tpts[tg[r] * a.d + k] - (float)mu[k] : 0.0f;
   }
-  // softmin over all sources of p
-  const int64_t s0 = off_s[p], s1 = off_s[p + 1];
+  // softmin over all sources of p (a split item: its range of them)
+  const int64_t s0 = SPLIT ? off_s[p] + it2.x : off_s[p];
+  const int64_t s1 = SPLIT ? s0 + it2.y : off_s[p + 1];
   float m[R], l[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -232,6 +239,43 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
       l[r] = l[r] * fast_exp2(m[r] - mn) + fast_exp2(v - mn);
       m[r] = mn;
     }
+  }
+  if constexpr (SPLIT) {
+    float2 *spart = g_step ? a.spart_g : a.spart_f;
+    int *gtick = g_step ? a.gtick_g : a.gtick_f;
+    spart[(size_t)it.w * 64 + lane] = make_float2(m[0], l[0]);
+    int glast = 0;
+    if (lane == 0) {
+      parts[it.w] = BlockPart{-INFINITY, 0.0, -INFINITY, INFINITY};  // empty unless last
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      glast = (atomicAdd(&gtick[it2.z], 1) == it2.w - 1) ? 1 : 0;
+    }
+    glast = __shfl(glast, 0, 64);
+    if (!glast) {  // the problem's arrival only
+      int last = 0;
+      if (lane == 0) {
+        const int nitems = pitem[p + 1] - pitem[p];
+        last = (atomicAdd(&ticket[p], 1) == nitems - 1) ? 1 : 0;
+      }
+      last = __shfl(last, 0, 64);
+      if (last) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        reduce_problem(a, p, g_step != 0);
+        if (lane == 0) ticket[p] = 0;
+      }
+      return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the group's partials
+    float mt = -FLT_MAX, lt = 0.0f;
+    for (int j = it2.z; j < it2.z + it2.w; ++j) {
+      const float2 q = spart[(size_t)j * 64 + lane];
+      const float mn = fmaxf(mt, q.x);
+      lt = lt * fast_exp2(mt - mn) + q.y * fast_exp2(q.x - mn);
+      mt = mn;
+    }
+    m[0] = mt;
+    l[0] = lt;
+    if (lane == 0) gtick[it2.z] = 0;  // every member has arrived
   }
   // epilogue: KL prox and TI translation (App. B), records of the new potential
   double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
@@ -286,7 +330,9 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
 }
 
 // One half-step for every active problem. g_step: targets y (beta, rho2), sources x.
-template <int D, bool SQ>
+// SPL: the split item level (items of <= 64 targets, some with a source range; its own
+// kernel, so the registers of the other levels' kernel stay as they are).
+template <int D, bool SQ, bool SPL>
 __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step) {
   const int lane = threadIdx.x & 63;
   const int nact = g_step ? *a.nact_g : *a.nact_f;
@@ -307,7 +353,13 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
     const int4 it = items[act[item]];  // (problem, first target, count, slot)
     if (a.state[it.x].done) continue;  // finished by an earlier half-step (compaction is periodic)
     const unsigned long long t0 = a.stats ? __builtin_amdgcn_s_memrealtime() : 0ull;
-    if (it.z > 128)
+    if constexpr (SPL) {
+      const int4 it2 = (g_step ? a.items2_g : a.items2_f)[act[item]];
+      if (it2.w > 1)
+        batched_item<D, SQ, 1, true>(a, g_step, it, it2);
+      else
+        batched_item<D, SQ, 1>(a, g_step, it);
+    } else if (it.z > 128)
       batched_item<D, SQ, 4>(a, g_step, it);
     else if (it.z > 64)
       batched_item<D, SQ, 2>(a, g_step, it);
@@ -472,13 +524,19 @@ __global__ __launch_bounds__(256) void k_batched_finalize(BatchedArgs a, float *
   }
 }
 
+template <int D, bool SPL>
+hipError_t launch_half_sp(const BatchedArgs &a, int g_step, int blocks, hipStream_t s) {
+  if (a.half_p == 1.0f)
+    hipLaunchKernelGGL((k_batched_half<D, true, SPL>), dim3(blocks), dim3(256), 0, s, a, g_step);
+  else
+    hipLaunchKernelGGL((k_batched_half<D, false, SPL>), dim3(blocks), dim3(256), 0, s, a, g_step);
+  return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_half_t(const BatchedArgs &a, int g_step, int blocks, hipStream_t s) {
-  if (a.half_p == 1.0f)
-    hipLaunchKernelGGL((k_batched_half<D, true>), dim3(blocks), dim3(256), 0, s, a, g_step);
-  else
-    hipLaunchKernelGGL((k_batched_half<D, false>), dim3(blocks), dim3(256), 0, s, a, g_step);
-  return hipGetLastError();
+  if (a.items2_g != nullptr) return launch_half_sp<D, true>(a, g_step, blocks, s);
+  return launch_half_sp<D, false>(a, g_step, blocks, s);
 }
 
 template <int D>
@@ -491,8 +549,12 @@ template <int D>
 int half_occupancy_t(const BatchedArgs &a) {
   int nb = 0;
   const hipError_t e = a.half_p == 1.0f
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, true>, 256, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, false>, 256, 0);
+      ? (a.items2_g != nullptr
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, true, true>, 256, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, true, false>, 256, 0))
+      : (a.items2_g != nullptr
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, false, true>, 256, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched_half<D, false, false>, 256, 0));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;

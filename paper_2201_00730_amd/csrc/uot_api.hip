@@ -1330,21 +1330,28 @@ uot_status backward_noalloc(const uot_cost *c, const float *alpha, const float *
 // ---------------------------------------------------------------------------------------
 // Batched TI Sinkhorn
 // ---------------------------------------------------------------------------------------
-// Work items of the batched solver, at three levels: chunks of up to 256 targets (level 0,
+// Work items of the batched solver, at four levels: chunks of up to 256 targets (level 0,
 // coarse: four per lane), 128 (level 1, fine: two per lane) or 64 (level 2, finest: one per
 // lane); the remainder of a problem is one item (four, two or one targets per lane above 128,
-// above 64, up to 64). Finer items cost more per entry (fewer targets share each source read)
-// but shorten the longest item, which bounds a launch once few problems run; the automatic
-// plan (autotuned, below) starts at one level and may move to the next finer one.
-constexpr int kBatchLevels = 3;
+// above 64, up to 64). Level 3 (split) takes the chunks of level 2 and splits their sources
+// into ranges of kBatchSplitLen, one item each, merged by the last of them to finish (its own
+// kernel). Finer items cost more per entry (fewer targets share each source read, and split
+// items merge partials) but shorten the longest item, which bounds a launch once few problems
+// run; the automatic plan (autotuned, below) starts at one level and may move to a finer one.
+constexpr int kBatchLevels = 4;
+constexpr int kBatchSplitLevel = 3;
 int64_t batch_item_len(int64_t rem, int level = 0) {
-  const int64_t cap = (int64_t)256 >> level;
+  const int64_t cap = (int64_t)256 >> (level < 2 ? level : 2);
   return rem < cap ? rem : cap;
 }
-int64_t batch_items(int64_t n, int level = 0) {
+int64_t batch_source_ranges(int64_t ns, int level) {
+  return level == kBatchSplitLevel ? (ns + kBatchSplitLen - 1) / kBatchSplitLen : 1;
+}
+// items of a problem with nt targets and ns sources at one level
+int64_t batch_items(int64_t nt, int64_t ns, int level = 0) {
   int64_t k = 0;
-  for (int64_t t0 = 0; t0 < n; t0 += batch_item_len(n - t0, level)) ++k;
-  return k;
+  for (int64_t t0 = 0; t0 < nt; t0 += batch_item_len(nt - t0, level)) ++k;
+  return k * batch_source_ranges(ns, level);
 }
 
 struct BatchLayout {
@@ -1353,6 +1360,7 @@ struct BatchLayout {
   size_t pitem_g[kBatchLevels] = {}, pitem_f[kBatchLevels] = {};
   int n_items_g[kBatchLevels] = {}, n_items_f[kBatchLevels] = {};
   size_t act_g = 0, act_f = 0, ctrs = 0, part_g = 0, part_f = 0, tick_g = 0, tick_f = 0;
+  size_t items2_g = 0, items2_f = 0, spart_g = 0, spart_f = 0, gtick_g = 0, gtick_f = 0;
   size_t pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, total = 0;
   int64_t totN = 0, totM = 0;
 };
@@ -1540,7 +1548,8 @@ uot_status fw_barycenter(int32_t B, int32_t K, const int64_t *off, const float *
 // Process-wide settings of the batched solver: the work-item plan, and a per-chunk trace of
 // the last solve (load statistics), guarded by a mutex.
 enum BatchPlan : int {
-  kPlanAuto = 0, kPlanCoarse = 1, kPlanFine = 2, kPlanSwitchAfterFirst = 3, kPlanFinest = 4
+  kPlanAuto = 0, kPlanCoarse = 1, kPlanFine = 2, kPlanSwitchAfterFirst = 3, kPlanFinest = 4,
+  kPlanSplit = 5
 };
 struct BatchTraceRow {
   double chunk, fine, running, items_g, items_f, work, busy_ticks, ticks, resident_waves;
@@ -1567,7 +1576,8 @@ struct BatchCand {
   double tau;
 };
 constexpr BatchCand kBatchCand[] = {{0, 0, 0.0}, {0, 1, 2.0}, {0, 1, 8.0}, {1, 1, 0.0},
-                                    {1, 2, 2.0}, {1, 2, 8.0}, {2, 2, 0.0}};
+                                    {1, 2, 2.0}, {1, 2, 8.0}, {2, 2, 0.0}, {1, 3, 2.0},
+                                    {1, 3, 0.5}};
 constexpr int kNumBatchCand = (int)(sizeof(kBatchCand) / sizeof(kBatchCand[0]));
 typedef std::tuple<int, int, int, int, int, int, int, int, int> BatchSig;
 struct BatchTune {
@@ -1622,12 +1632,16 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
     if (n < 1 || m < 1) return fail(UOT_ERR_INVALID, "problem %d has n=%lld, m=%lld (must be >= 1)", p, (long long)n, (long long)m);
     if (n > (1 << 30) || m > (1 << 30)) return fail(UOT_ERR_INVALID, "problem %d is too large", p);
     for (int lv = 0; lv < kBatchLevels; ++lv) {
-      ig[lv] += batch_items(m, lv);
-      jf[lv] += batch_items(n, lv);
+      ig[lv] += batch_items(m, n, lv);
+      jf[lv] += batch_items(n, m, lv);
     }
   }
-  constexpr int kFinest = kBatchLevels - 1;  // the most items of any level
-  if (ig[kFinest] > (1 << 30) || jf[kFinest] > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
+  int64_t mg = 0, mf = 0;  // the most items of any level
+  for (int lv = 0; lv < kBatchLevels; ++lv) {
+    mg = ig[lv] > mg ? ig[lv] : mg;
+    mf = jf[lv] > mf ? jf[lv] : mf;
+  }
+  if (mg > (1 << 30) || mf > (1 << 30)) return fail(UOT_ERR_INVALID, "too many work items");
   for (int lv = 0; lv < kBatchLevels; ++lv) {
     L.n_items_g[lv] = (int)ig[lv];
     L.n_items_f[lv] = (int)jf[lv];
@@ -1652,11 +1666,19 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
     L.pitem_f[lv] = take((size_t)(B + 1) * sizeof(int));
   }
   // active lists and item partials serve every level
-  L.act_g = take((size_t)L.n_items_g[kFinest] * sizeof(int));
-  L.act_f = take((size_t)L.n_items_f[kFinest] * sizeof(int));
+  L.act_g = take((size_t)mg * sizeof(int));
+  L.act_f = take((size_t)mf * sizeof(int));
   L.ctrs = take(sizeof(BatchCounters));
-  L.part_g = take((size_t)L.n_items_g[kFinest] * sizeof(BlockPart));
-  L.part_f = take((size_t)L.n_items_f[kFinest] * sizeof(BlockPart));
+  L.part_g = take((size_t)mg * sizeof(BlockPart));
+  L.part_f = take((size_t)mf * sizeof(BlockPart));
+  // split level: source ranges and groups, per-target partials, group counters
+  const int ns_g = L.n_items_g[kBatchSplitLevel], ns_f = L.n_items_f[kBatchSplitLevel];
+  L.items2_g = take((size_t)ns_g * sizeof(int4));
+  L.items2_f = take((size_t)ns_f * sizeof(int4));
+  L.spart_g = take((size_t)ns_g * 64 * sizeof(float2));
+  L.spart_f = take((size_t)ns_f * 64 * sizeof(float2));
+  L.gtick_g = take((size_t)ns_g * sizeof(int));
+  L.gtick_f = take((size_t)ns_f * sizeof(int));
   L.tick_g = take((size_t)B * sizeof(int));
   L.tick_f = take((size_t)B * sizeof(int));
   L.pot_x = take((size_t)L.totN * sizeof(float));
@@ -1667,20 +1689,30 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   return UOT_OK;
 }
 
-// Work items of one side: (problem, first target, count, item index), grouped by problem.
-// Items in problem order (a problem's items are taken by neighbouring waves, which share its
-// source records in L2; ordering the table longest-first was measured slower on batch2d:
-// 2.30e12 against 2.63e12 updates/s); the slots of problem p are [pitem[p], pitem[p+1]).
-void build_items(int32_t B, const int64_t *off, std::vector<int4> &items, std::vector<int> &pitem,
-                 int level) {
+// Work items of one side: (problem, first target, count, item index), grouped by problem,
+// and at the split level (source offset in the problem, source count, first slot of the
+// group, group size) for each. Items in problem order (a problem's items are taken by
+// neighbouring waves, which share its source records in L2; ordering the table longest-first
+// was measured slower on batch2d: 2.30e12 against 2.63e12 updates/s); the slots of problem p
+// are [pitem[p], pitem[p+1]), a group's slots are consecutive.
+void build_items(int32_t B, const int64_t *off, const int64_t *off_s, std::vector<int4> &items,
+                 std::vector<int4> &items2, std::vector<int> &pitem, int level) {
   items.clear();
+  items2.clear();
   pitem.assign((size_t)B + 1, 0);
   for (int p = 0; p < B; ++p) {
     pitem[p] = (int)items.size();
-    const int64_t n = off[p + 1] - off[p];
+    const int64_t n = off[p + 1] - off[p], ns = off_s[p + 1] - off_s[p];
+    const int nr = (int)batch_source_ranges(ns, level);
     for (int64_t t0 = 0; t0 < n;) {
       const int cnt = (int)batch_item_len(n - t0, level);
-      items.push_back(make_int4(p, (int)t0, cnt, (int)items.size()));
+      const int first = (int)items.size();
+      for (int r = 0; r < nr; ++r) {
+        const int64_t sb = (int64_t)r * kBatchSplitLen;
+        const int64_t sc = nr == 1 ? ns : (ns - sb < kBatchSplitLen ? ns - sb : kBatchSplitLen);
+        items.push_back(make_int4(p, (int)t0, cnt, (int)items.size()));
+        if (level == kBatchSplitLevel) items2.push_back(make_int4((int)sb, (int)sc, first, nr));
+      }
       t0 += cnt;
     }
   }
@@ -1717,13 +1749,20 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   std::vector<int4> items[2][kBatchLevels];  // [side: 0 g-step, 1 f-step][level]
+  std::vector<int4> items2[2][kBatchLevels];  // split level only
   std::vector<int> pitem[2][kBatchLevels];
   char *ws = static_cast<char *>(w.ptr);
   UOT_HIP(hipMemcpyAsync(ws + L.offN, offN, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   UOT_HIP(hipMemcpyAsync(ws + L.offM, offM, (size_t)(B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   for (int lv = 0; lv < kBatchLevels; ++lv) {
-    build_items(B, offM, items[0][lv], pitem[0][lv], lv);  // g-step targets: the y side
-    build_items(B, offN, items[1][lv], pitem[1][lv], lv);  // f-step targets: the x side
+    build_items(B, offM, offN, items[0][lv], items2[0][lv], pitem[0][lv], lv);  // g-step: targets y
+    build_items(B, offN, offM, items[1][lv], items2[1][lv], pitem[1][lv], lv);  // f-step: targets x
+    if (lv == kBatchSplitLevel) {
+      UOT_HIP(hipMemcpyAsync(ws + L.items2_g, items2[0][lv].data(), items2[0][lv].size() * sizeof(int4),
+                             hipMemcpyHostToDevice, s));
+      UOT_HIP(hipMemcpyAsync(ws + L.items2_f, items2[1][lv].data(), items2[1][lv].size() * sizeof(int4),
+                             hipMemcpyHostToDevice, s));
+    }
     UOT_HIP(hipMemcpyAsync(ws + L.items_g[lv], items[0][lv].data(), items[0][lv].size() * sizeof(int4),
                            hipMemcpyHostToDevice, s));
     UOT_HIP(hipMemcpyAsync(ws + L.items_f[lv], items[1][lv].data(), items[1][lv].size() * sizeof(int4),
@@ -1779,14 +1818,22 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   a.part_f = at<BlockPart>(w.ptr, L.part_f);
   a.ticket_g = at<int>(w.ptr, L.tick_g);
   a.ticket_f = at<int>(w.ptr, L.tick_f);
+  a.items2_g = a.items2_f = nullptr;
+  a.spart_g = a.spart_f = nullptr;
+  a.gtick_g = a.gtick_f = nullptr;
+  // group counters of the split level start at zero (each group's last item resets its own)
+  UOT_HIP(hipMemsetAsync(ws + L.gtick_g, 0, (size_t)L.n_items_g[kBatchSplitLevel] * sizeof(int), s));
+  UOT_HIP(hipMemsetAsync(ws + L.gtick_f, 0, (size_t)L.n_items_f[kBatchSplitLevel] * sizeof(int), s));
 
   const int cus = device_cus();
   const int per_cu = batched_half_blocks_per_cu(a);
   const int blocks = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 4);
   const int resident_waves = blocks * 4;
 
-  // the same problems and buffers at each item level, with that level's item tables
+  // the same problems and buffers at each item level, with that level's item tables (the
+  // split level runs its own kernel, with its own occupancy)
   BatchedArgs al[kBatchLevels];
+  int blocks_lv[kBatchLevels];
   for (int lv = 0; lv < kBatchLevels; ++lv) {
     al[lv] = a;
     al[lv].items_g = at<int4>(w.ptr, L.items_g[lv]);
@@ -1795,6 +1842,17 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     al[lv].pitem_f = at<int>(w.ptr, L.pitem_f[lv]);
     al[lv].n_items_g = L.n_items_g[lv];
     al[lv].n_items_f = L.n_items_f[lv];
+    blocks_lv[lv] = blocks;
+    if (lv == kBatchSplitLevel) {
+      al[lv].items2_g = at<int4>(w.ptr, L.items2_g);
+      al[lv].items2_f = at<int4>(w.ptr, L.items2_f);
+      al[lv].spart_g = at<float2>(w.ptr, L.spart_g);
+      al[lv].spart_f = at<float2>(w.ptr, L.spart_f);
+      al[lv].gtick_g = at<int>(w.ptr, L.gtick_g);
+      al[lv].gtick_f = at<int>(w.ptr, L.gtick_f);
+      const int pc = batched_half_blocks_per_cu(al[lv]);
+      blocks_lv[lv] = (cus > 0 ? cus : 256) * (pc > 0 ? pc : 4);
+    }
   }
 
   // The plan: start at item level lv0 and move to lv1 (one finer, or the same) once the busier
@@ -1811,6 +1869,8 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     lv0 = lv1 = 1;
   } else if (plan == kPlanFinest) {
     lv0 = lv1 = 2;
+  } else if (plan == kPlanSplit) {
+    lv0 = lv1 = kBatchSplitLevel;
   } else if (plan == kPlanSwitchAfterFirst) {
     after_first = true;
   } else {
@@ -1842,12 +1902,12 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   // One chunk of iterations (g and f half-steps) and the compaction, captured once per level
   // the plan uses.
   const int chunk = tol > 0.0 ? check_every : (max_iter < 64 ? max_iter : 64);
-  auto capture = [&](const BatchedArgs &pa, GraphGuard &gg) -> uot_status {
+  auto capture = [&](const BatchedArgs &pa, int nblocks, GraphGuard &gg) -> uot_status {
     UOT_HIP(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
     UOT_HIP(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeRelaxed));
     for (int i = 0; i < chunk; ++i) {
-      hipError_t e = launch_batched_half(pa, 1, blocks, gg.cs);
-      if (e == hipSuccess) e = launch_batched_half(pa, 0, blocks, gg.cs);
+      hipError_t e = launch_batched_half(pa, 1, nblocks, gg.cs);
+      if (e == hipSuccess) e = launch_batched_half(pa, 0, nblocks, gg.cs);
       if (e != hipSuccess) {
         hipGraph_t dead = nullptr;
         (void)hipStreamEndCapture(gg.cs, &dead);
@@ -1863,8 +1923,8 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     return UOT_OK;
   };
   GraphGuard gg[kBatchLevels];
-  UOT_TRY(capture(al[lv0], gg[lv0]));
-  if (lv1 != lv0) UOT_TRY(capture(al[lv1], gg[lv1]));
+  UOT_TRY(capture(al[lv0], blocks_lv[lv0], gg[lv0]));
+  if (lv1 != lv0) UOT_TRY(capture(al[lv1], blocks_lv[lv1], gg[lv1]));
 
   // host copies of the counters after each chunk (two slots, read one chunk late)
   PinnedState pin;
@@ -1891,7 +1951,7 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
     r.work = c.work;
     r.busy_ticks = (double)(c.busy - busy_prev);
     r.ticks = chunk == 0 ? 0.0 : (double)(c.t_compact - t_prev);
-    r.resident_waves = resident_waves;
+    r.resident_waves = blocks_lv[level] * 4;
     busy_prev = c.busy;
     t_prev = c.t_compact;
     trace.push_back(r);
@@ -2109,7 +2169,7 @@ void uot_batched_autotune_reset(void) {
 }
 
 int32_t uot_batched_set_plan(int32_t plan) {
-  if (plan < uot::kPlanAuto || plan > uot::kPlanFinest) return -1;
+  if (plan < uot::kPlanAuto || plan > uot::kPlanSplit) return -1;
   std::lock_guard<std::mutex> lk(uot::g_batch_mu);
   const int32_t prev = uot::g_batch_plan;
   uot::g_batch_plan = plan;

@@ -16,6 +16,9 @@ enum : int32_t {
   kBatchNumeric = 3,
 };
 
+// Sources per work item of the split item level (a multiple of the kernel's 8-source tile).
+constexpr int kBatchSplitLen = 512;
+
 // Record stride of the batched kernels (D coordinates, b, padding to a multiple of 4).
 __host__ __device__ constexpr int batched_rec_stride(int D) { return (D + 1 + 3) / 4 * 4; }
 
@@ -55,6 +58,13 @@ struct BatchedArgs {
   float *pot_x, *pot_y;            // stored (untranslated) potentials
   float *rec_x, *rec_y;            // source records
   const int4 *items_g, *items_f;   // (problem, first target, count, slot)
+  // Split item level only (else NULL): (first source, source count, first slot of the
+  // item's group, group size) per item. A group is one chunk of <= 64 targets whose sources
+  // are split over consecutive slots; the last item of a group to finish merges the group's
+  // per-target (max, sum) partials and runs the epilogue.
+  const int4 *items2_g, *items2_f;
+  float2 *spart_g, *spart_f;       // [slots, 64] per-target (max, sum) of a split item
+  int *gtick_g, *gtick_f;          // [slots] group arrival counters (at a group's first slot)
   const int *pitem_g, *pitem_f;    // [B+1] item ranges per problem
   int n_items_g, n_items_f;
   int *act_g, *act_f;              // active item lists

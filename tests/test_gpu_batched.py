@@ -67,17 +67,17 @@ class _plan:
 
 
 PLANS = {"auto": uot.BATCH_PLAN_AUTO, "coarse": uot.BATCH_PLAN_COARSE,
-         "fine": uot.BATCH_PLAN_FINE, "finest": uot.BATCH_PLAN_FINEST}
+         "fine": uot.BATCH_PLAN_FINE, "finest": uot.BATCH_PLAN_FINEST, "split": uot.BATCH_PLAN_SPLIT}
 
 
-@pytest.mark.parametrize("plan", ["coarse", "fine", "finest", "auto"])
+@pytest.mark.parametrize("plan", ["coarse", "fine", "finest", "split", "auto"])
 @pytest.mark.parametrize("d,p,nmax", [(2, 2.0, 300), (3, 2.0, 300), (1, 2.0, 300), (5, 1.5, 300),
                                        (8, 2.0, 300), (2, 2.0, 1100), (3, 1.5, 700)])
 def test_batched_iteration_parity(d, p, nmax, plan):
     """Sizes 1..nmax under each work-item plan: coarse items of <= 64 targets (one per lane),
     65..128 (two per lane), 129..256 (four per lane) and problems split into several items;
-    fine items of <= 128 targets. (The automatic plan picks fine items from the start on
-    batches this small.)"""
+    fine items of <= 128 targets; split items (64 targets, sources in ranges of 512: the
+    nmax = 700 and 1100 batches split their larger problems into two or three ranges)."""
     bt = small_batch(B=23 if nmax <= 300 else 9, nmax=nmax, d=d, p=p, seed=40 + d + nmax)
     print("batched d=%d p=%g B=%d plan=%s" % (d, p, bt.B, plan), file=sys.stderr, flush=True)
     T = 12
@@ -91,7 +91,7 @@ def test_batched_iteration_parity(d, p, nmax, plan):
         assert rel_inf(fb, r.f) < TOL and rel_inf(gb, r.g) < TOL, (b, rel_inf(fb, r.f), rel_inf(gb, r.g))
 
 
-@pytest.mark.parametrize("plan", [uot.BATCH_PLAN_AUTO, uot.BATCH_PLAN_SWITCH])
+@pytest.mark.parametrize("plan", [uot.BATCH_PLAN_AUTO, uot.BATCH_PLAN_SWITCH, uot.BATCH_PLAN_SPLIT])
 def test_batched_converges_per_problem(plan):
     """Each problem stops at its own first passing check; at its stopping iteration it matches
     the oracle run for that many iterations, and the oracle's own stopping iteration is close.
@@ -193,20 +193,20 @@ def test_batched_load_statistics():
 
 
 def test_batched_autotuned_plan():
-    """The automatic plan explores one candidate per call for a new size signature (seven:
-    item levels and switch points from 256-target items throughout to 64-target items
-    throughout), then keeps the fastest; the potentials agree across every candidate (the plan
+    """The automatic plan explores one candidate per call for a new size signature (nine:
+    item levels and switch points from 256-target items throughout to split items in the
+    tail), then keeps the fastest; the potentials agree across every candidate (the plan
     changes only how targets are grouped into work items) and with the oracle."""
     bt = small_batch(B=40, nmin=64, nmax=700, seed=57)
     uot.batched_autotune_reset()
     with _plan(uot.BATCH_PLAN_AUTO):
         runs, plans = [], []
-        for _ in range(8):
+        for _ in range(10):
             runs.append(run_batched(bt, 12))
             plans.append(uot.batched_last_plan())
-    assert plans[:7] == [(0, 0, 0.0), (0, 1, 2.0), (0, 1, 8.0), (1, 1, 0.0), (1, 2, 2.0),
-                         (1, 2, 8.0), (2, 2, 0.0)], plans
-    assert plans[7] in plans[:7]
+    assert plans[:9] == [(0, 0, 0.0), (0, 1, 2.0), (0, 1, 8.0), (1, 1, 0.0), (1, 2, 2.0),
+                         (1, 2, 8.0), (2, 2, 0.0), (1, 3, 2.0), (1, 3, 0.5)], plans
+    assert plans[9] in plans[:9]
     f0, g0 = runs[0][0], runs[0][1]
     for f, g, it, st in runs[1:]:
         assert rel_inf(f, f0) < 1e-6 and rel_inf(g, g0) < 1e-6
