@@ -15,7 +15,10 @@
 //
 // Same base-2 conventions as the single-problem kernels: sc_p = log2(e)/eps_p and records
 //   u_s = x_s - mu_p,  b_s = sc_p h_s + log2 w_s,  exponent v_ts = b_s - sc_p ||u_s - (y_t - mu_p)||^p
-// where mu_p is the common mean of problem p's two clouds. The cost is always taken through the
+// where mu_p is the common mean of problem p's two clouds. For p = 2 the coordinates are
+// stored scaled by sqrt(sc_p) (targets scaled the same way), so v_ts = b_s - ||u'_s - y'_t||^2
+// is a chain of FMAs starting from b_s: one multiplication fewer per entry, and the same
+// rounding (each scaled coordinate is rounded once, as the unscaled one was). The cost is always taken through the
 // differences (p = 2 included: ||.||^2 as is), so the float32 rounding of an exponent is
 // relative to its entry's own cost; the expanded form |x|^2 + |y|^2 - 2<x, y> would carry an
 // absolute rounding of the clouds' squared spread, which at small eps is not small against
@@ -170,6 +173,7 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
   const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
   const double scd = 1.4426950408889634074 / eps;
   const float sc = (float)scd;
+  const float ssc = SQ ? (float)sqrt(scd) : 1.0f;  // coordinate scale of the p = 2 records
   const HalfCoef cf = g_step ? half_coef(eps, r2, r1) : half_coef(eps, r1, r2);
   const double tau_src = g_step ? st.tau_f : st.tau_g;
   const double s_src = g_step ? st.sA : st.sB;
@@ -184,7 +188,7 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
     valid[r] = lane + 64 * r < it.z;
     tg[r] = tb + it.y + (valid[r] ? lane + 64 * r : 0);
 #pragma unroll
-    for (int k = 0; k < D; ++k) yc[r][k] = k < a.d ? tpts[tg[r] * a.d + k] - (float)mu[k] : 0.0f;
+    for (int k = 0; k < D; ++k) yc[r][k] = k < a.d ? (tpts[tg[r] * a.d + k] - (float)mu[k]) * ssc : 0.0f;
   }
   // softmin over all sources of p (a split item: its range of them)
   const int64_t s0 = SPLIT ? off_s[p] + it2.x : off_s[p];
@@ -197,17 +201,26 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
   }
   const float half_p = a.half_p;
   auto expo = [&](const float *rp, int r) -> float {
-    float d2 = 0.0f;
+    if constexpr (SQ) {  // b_s - ||u'_s - y'_t||^2 on scaled coordinates
+      float v = rp[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const float u = rp[k] - yc[r][k];
-      d2 = fmaf(u, u, d2);
+      for (int k = 0; k < D; ++k) {
+        const float u = rp[k] - yc[r][k];
+        v = fmaf(-u, u, v);
+      }
+      return v;
+    } else {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const float u = rp[k] - yc[r][k];
+        d2 = fmaf(u, u, d2);
+      }
+      const float c = half_p == 0.5f ? __builtin_sqrtf(d2) : fast_exp2(half_p * fast_log2(d2));
+      return fmaf(-sc, c, rp[D]);
     }
-    // SQ: p = 2, the squared distance as is
-    const float c = SQ ? d2
-                    : half_p == 0.5f ? __builtin_sqrtf(d2) : fast_exp2(half_p * fast_log2(d2));
-    return fmaf(-sc, c, rp[D]);
   };
+
   int64_t s = s0;
   for (; s + kTile <= s1; s += kTile) {
     float v[kTile][R];
@@ -437,6 +450,7 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
   }
   const double eps = a.eps[p], r1 = a.rho1[p];
   const double scd = 1.4426950408889634074 / eps;
+  const float ssc = a.half_p == 1.0f ? (float)sqrt(scd) : 1.0f;  // p = 2: scaled coordinates
   constexpr int SD = batched_rec_stride(D);
   // x side (alpha) and y side (beta): zero potentials and records; tilted mass of alpha
   double mm = -INFINITY, ms = 0.0;
@@ -452,7 +466,7 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
       if (wi > 0.0f) { if (side == 0) s_pa = 1; else s_pb = 1; }
       float yc[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) yc[k] = k < a.d ? pts[i * a.d + k] - (float)mu[k] : 0.0f;
+      for (int k = 0; k < D; ++k) yc[k] = k < a.d ? (pts[i * a.d + k] - (float)mu[k]) * ssc : 0.0f;
       pot[i] = 0.0f;
       write_rec<D>(rec + (size_t)i * SD, yc, 0.0f, wi, scd);
       if (side == 0 && wi > 0.0f) {
