@@ -258,10 +258,11 @@ uot_status uot_dual_value(const uot_cost *cost, const float *alpha, const float 
  * 1 <= k <= 64. V = NULL means a column of ones (k must be 1): the marginals pi 1 and
  * pi^T 1 of Sec. 1. Each output row is computed with its own running max of the exponent,
  * so pi V is exact up to rounding even where individual entries of e^{f+g-C} overflow.
- * Points costs up to dimension 16 (and the marginals of every points cost) take the
- * backward's one-pass kernel: exponent in double precision, one exp2 per entry, V applied
- * 16 columns per pass on the float32 matrix cores; other costs (and points costs under
- * uot_set_grad_kernel(1)) a float32 exponent with two exp2 per entry, 4 columns per pass.
+ * One pass over the cost per 16 columns of V, one exp2 per entry, V applied on the float32
+ * matrix cores: points costs up to dimension 16 through the backward's kernel (exponent in
+ * double precision), stored costs with the float32 exponent of the stored-cost softmins.
+ * Points costs above dimension 16 (and every cost under uot_set_grad_kernel(1)) take a
+ * float32 exponent with two exp2 per entry and 4 columns per pass.
  */
 uot_status uot_plan_apply(const uot_cost *cost, const float *alpha, const float *beta, double eps,
                           const float *f, const float *g, int32_t transpose, const float *V,

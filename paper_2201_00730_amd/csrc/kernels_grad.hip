@@ -454,6 +454,92 @@ __global__ __launch_bounds__(256) void k_grad_mfma(GradArgs a) {
   }
 }
 
+// Plan application to a payload on a stored cost: the loop of k_grad_mfma's payload pass with
+// the inner-product MFMAs replaced by the cost entries themselves. Lane (col, qr) takes, per
+// 16-source step, sources sb + 4 qr + i (i = 0..3: four consecutive entries of a row of C
+// when the targets are its rows); element i is the A operand (k = qr) of the q-tile MFMA over
+// sources sb + 4 k + i, whose B operand V[sb + 4 qr + i][col] the same lane loads.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_dense_payload(DensePayloadArgs a) {
+  constexpr int G = kMfmaGroups;
+  constexpr int PS = grad_part_stride(16);
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, qr = lane >> 4;
+  const int tw = blockIdx.x * (4 * G * 16) + (threadIdx.x >> 6) * (G * 16);
+  const float sc = a.sc;
+  float ref[G], l[G];
+  f32x4 acc[G];
+  int tcl[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int t = tw + 16 * g + col;
+    tcl[g] = t < a.nt ? t : a.nt - 1;
+    ref[g] = -FLT_MAX;
+    l[g] = 0.0f;
+    acc[g] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  const int s0 = blockIdx.y * a.split_len;
+  const int s1 = min(a.ns, s0 + a.split_len);
+  for (int sb = s0; sb < s1; sb += 16) {
+    float bs[4], sv[4];
+    bool ok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int si = sb + 4 * qr + i;
+      ok[i] = si < s1;
+      bs[i] = ok[i] ? a.rec[si] : -INFINITY;
+      sv[i] = (ok[i] && col < a.vcols) ? a.V[(size_t)si * a.ldv + col] : 0.0f;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      float e[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int si = sb + 4 * qr + i;
+        const float cv = ok[i] ? (TRANS ? a.C[(size_t)si * a.ldc + tcl[g]] : a.C[(size_t)tcl[g] * a.ldc + si])
+                               : 0.0f;
+        e[i] = fmaf(-sc, cv, bs[i]);
+      }
+      const float m = fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3]));
+      const bool up = m > ref[g];
+      if (__builtin_amdgcn_ballot_w64(up)) {  // raise the quarter's shared reference
+        float mc = up ? ceilf(m) : ref[g];
+        mc = fmaxf(mc, __shfl_xor(mc, 16));
+        mc = fmaxf(mc, __shfl_xor(mc, 32));
+        const float nr = fmaxf(mc, ref[g]);
+        const float scale = fexp2(ref[g] - nr);
+        ref[g] = nr;
+        l[g] *= scale;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[g][i] *= __shfl(scale, 4 * qr + i);
+      }
+      float q[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = fexp2(e[i] - ref[g]);
+      l[g] += (q[0] + q[1]) + (q[2] + q[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(q[i], sv[i], acc[g], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    float lt = l[g] + __shfl_xor(l[g], 16);
+    lt += __shfl_xor(lt, 32);
+    const int t = tw + 16 * g + col;
+    if (qr == 0 && t < a.nt) {
+      float *o = a.part + ((size_t)blockIdx.y * a.nt + t) * PS;
+      o[0] = lt > 0.0f ? ref[g] : -FLT_MAX;
+      o[1] = lt;
+      o[2] = lt;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ti = tw + 16 * g + 4 * qr + i;
+      if (ti < a.nt) a.part[((size_t)blockIdx.y * a.nt + ti) * PS + 3 + col] = acc[g][i];
+    }
+  }
+}
+
 template <int D>
 hipError_t records_for(const GradRecordArgs &a, hipStream_t s) {
   hipLaunchKernelGGL((k_grad_records<D>), dim3((a.n + kGradPadRows + 255) / 256), dim3(256), 0, s, a);
@@ -516,6 +602,16 @@ hipError_t combine_for(const GradCombineArgs &a, hipStream_t s) {
   }
 
 }  // namespace
+
+hipError_t launch_dense_payload(const DensePayloadArgs &a, hipStream_t s) {
+  if (a.vcols < 1 || a.vcols > 16 || a.split_len % 16 != 0) return hipErrorInvalidValue;
+  dim3 grid((a.nt + 64 * kMfmaGroups - 1) / (64 * kMfmaGroups), a.nsplit);
+  if (a.trans)
+    hipLaunchKernelGGL(k_dense_payload<true>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_dense_payload<false>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 bool grad_payload_supported(int d) {
   return dim_bucket(d) <= 16 && g_grad_variant.load(std::memory_order_relaxed) == 0;

@@ -264,11 +264,11 @@ Layout make_layout(const uot_cost *c, int which, int mode_override = -1) {
     const size_t rb = pts ? grad_rec_stride(db) * sizeof(double) : sizeof(float);
     L.grad_rec = take((size_t)rec_count(nmax + kGradPadRows) * rb);
     // (a plan application's payload passes keep 16 columns per partial)
-    const bool pay = pts && which == UOT_WS_PLAN && db <= 16;
+    const bool pay = which == UOT_WS_PLAN && (!pts || db <= 16);
     const int pstride = pay && grad_part_stride(16) > grad_part_stride(db) ? grad_part_stride(16)
                                                                            : grad_part_stride(db);
-    const size_t ps = pts ? (size_t)kGradMaxSplits * pstride
-                          : (size_t)kMaxSplits * grad_part_stride(0);
+    size_t ps = pts ? (size_t)kGradMaxSplits * pstride : (size_t)kMaxSplits * grad_part_stride(0);
+    if (!pts && pay && (size_t)kGradMaxSplits * pstride > ps) ps = (size_t)kGradMaxSplits * pstride;
     L.grad_part = take(ps * (size_t)nmax * sizeof(float));
     L.masses = take(2 * sizeof(double));
     L.total = off;
@@ -1083,6 +1083,77 @@ uot_status apply_payload(const uot_cost *c, bool tx, const float *alpha, const f
   return UOT_OK;
 }
 
+// The plan applied to a payload V on a stored cost (targets the rows of C when tx): the
+// records b_s of the other side, then per 16 columns of V one pass over C (one exp2 per
+// entry, float32 exponent as in the stored-cost softmins) and the split merge.
+uot_status apply_payload_dense(const uot_cost *c, bool tx, const float *alpha, const float *beta,
+                               const float *f, const float *g, double eps, SolveState *st,
+                               void *ws, const Layout &L, const float *V, int kc, int64_t ldv,
+                               float *out, int64_t ldout, hipStream_t s) {
+  const int nt = tx ? c->n : c->m, ns = tx ? c->m : c->n;
+  const double sc = kLog2e / eps;
+  float *rec = at<float>(ws, L.grad_rec);
+  float *part = at<float>(ws, L.grad_part);
+  RecordArgs ra;
+  ra.pts = nullptr;
+  ra.w = tx ? beta : alpha;
+  ra.pot = tx ? g : f;
+  ra.pot_copy = nullptr;
+  ra.pot_off = 0.0;
+  ra.n = ns;
+  ra.mode = kDense;
+  ra.d = 0;
+  ra.rec = rec;
+  ra.bparts = nullptr;
+  ra.rho = 1.0;
+  ra.sc = sc;
+  ra.st = st;
+  UOT_HIP(launch_build_records(ra, s));
+  const int cus = device_cus();
+  const int tiles = (nt + 255) / 256;
+  const Split sp = make_split(ns, tiles, 64, 16, (cus > 0 ? cus : 256) * 4, kGradMaxSplits);
+  for (int c0 = 0; c0 < kc; c0 += 16) {
+    DensePayloadArgs da;
+    da.C = c->C;
+    da.ldc = c->ldc;
+    da.trans = tx ? 0 : 1;
+    da.nt = nt;
+    da.ns = ns;
+    da.rec = rec;
+    da.sc = (float)sc;
+    da.split_len = sp.len;
+    da.nsplit = sp.n;
+    da.V = V + c0;
+    da.ldv = ldv;
+    da.vcols = kc - c0 < 16 ? kc - c0 : 16;
+    da.part = part;
+    UOT_HIP(launch_dense_payload(da, s));
+    GradCombineArgs ca;
+    ca.part = part;
+    ca.nsplit = sp.n;
+    ca.nt = nt;
+    ca.d = da.vcols;
+    ca.tgt = nullptr;
+    ca.mu = st->mu;
+    ca.h_t = tx ? f : g;
+    ca.w_t = tx ? alpha : beta;
+    ca.sc = sc;
+    ca.eps = eps;
+    ca.rho = 1.0;
+    ca.gout = 1.0;
+    ca.pfac = 1.0;
+    ca.mass_other = nullptr;
+    ca.marg = nullptr;
+    ca.marg_stride = 0;
+    ca.dw = nullptr;
+    ca.dpts = nullptr;
+    ca.apply_out = out + c0;
+    ca.ldout = ldout;
+    UOT_HIP(launch_grad_combine(ca, s));
+  }
+  return UOT_OK;
+}
+
 // Row sums of the plan for the targets of one side (targets x when tx), in one pass over the
 // other side's points (kernels_grad.hip) or one stored-cost softmin, and what is asked of
 // them: the plan marginal (marg, element t at marg[t * marg_stride]), the weight gradient
@@ -1222,6 +1293,9 @@ uot_status plan_apply(const uot_cost *c, const float *alpha, const float *beta, 
   if (V == nullptr) {  // the marginals: row sums in one pass
     UOT_TRY(envelope_side(c, transpose == 0, alpha, beta, f, g, eps, 1.0, 1.0, st, w.ptr, L, out,
                           ldout, nullptr, nullptr, nullptr, s));
+  } else if (c->kind == UOT_COST_DENSE && grad_payload_supported(1)) {
+    UOT_TRY(apply_payload_dense(c, transpose == 0, alpha, beta, f, g, eps, st, w.ptr, L, V, kc, ldv,
+                                out, ldout, s));
   } else if (c->kind == UOT_COST_POINTS && grad_payload_supported(c->d)) {
     UOT_TRY(apply_payload(c, transpose == 0, alpha, beta, f, g, eps, st, w.ptr, L, V, kc, ldv, out,
                           ldout, s));

@@ -393,6 +393,25 @@ struct GradCombineArgs {
   float *apply_out = nullptr;  // optional: plan applied to a payload, out[t * ldout + c]
   int64_t ldout = 0;           //   for c < d (partials of a payload pass; d = its columns)
 };
+// Plan application to a payload on a stored cost (kernels_grad.hip): per 16-source step and
+// 16-target group the exponents e_ts = b_s - sc C_ts (float32, as the stored-cost softmins),
+// one exp2 per entry, and sum_s q_ts V[s, c] on the float32 matrix cores; partials in the
+// layout of a payload pass, merged by launch_grad_combine.
+struct DensePayloadArgs {
+  const float *C;
+  int64_t ldc;
+  int trans;           // 1: the targets are the columns of C (the sources its rows)
+  int nt, ns;
+  const float *rec;    // source records b_s = sc h_s + log2 w_s [ns]
+  float sc;
+  int split_len, nsplit;  // split lengths are multiples of 16
+  const float *V;      // payload, offset to its first column, row stride ldv
+  int64_t ldv;
+  int vcols;           // <= 16
+  float *part;         // [nsplit, nt, grad_part_stride(16)]
+};
+hipError_t launch_dense_payload(const DensePayloadArgs &a, hipStream_t s);
+
 int grad_targets_per_block(int d);
 int grad_source_align(int d);  // split lengths of the backward pass are multiples of this
 bool grad_payload_supported(int d);  // the matrix-core pass runs payload passes for this d

@@ -264,6 +264,43 @@ def test_plan_apply_payload_passes(n, m, d, p, k, eps):
         uot.set_grad_kernel(prev)
 
 
+@pytest.mark.parametrize("n,m,k,pad", [(333, 517, 20, 0), (517, 333, 1, 3), (1, 40, 16, 0),
+                                       (300, 17, 37, 5)])
+def test_plan_apply_stored_cost(n, m, k, pad):
+    """pi V and pi^T V on a stored cost (leading dimension m + pad) through the one-pass
+    payload kernel and through the two-exp2 apply kernel, against the oracle at converged
+    potentials."""
+    prc = workloads.random_small(n, m, d=4, seed=n + 2 * m + k, eps=0.05, rho1=0.8, rho2=1.6,
+                                 dense=True)
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
+    cost = oracle_cost(prc)
+    a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
+    f64, g64 = f32.astype(np.float64), g32.astype(np.float64)
+    Cp = np.zeros((n, m + pad), np.float32)
+    Cp[:, :m] = prc.C
+    Ct = dev(Cp)
+    Cv = Ct[:, :m] if pad else Ct
+    rng = np.random.default_rng(k)
+    prev = uot.set_grad_kernel(uot.GRAD_KERNEL_MFMA)
+    try:
+        for variant in (uot.GRAD_KERNEL_MFMA, uot.GRAD_KERNEL_VALU):
+            uot.set_grad_kernel(variant)
+            for transpose, rows_src in ((False, m), (True, n)):
+                V = rng.normal(size=(rows_src, k)).astype(np.float32)
+                _say("stored-cost apply kernel %d n=%d m=%d k=%d pad=%d T=%d" % (variant, n, m, k, pad, transpose))
+                out = uot.plan_apply(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), dev(V),
+                                     transpose=transpose, C=Cv, eps=prc.eps).cpu().numpy().reshape(-1, k)
+                ref = oracle.plan_apply(cost, a, b, prc.eps, f64, g64, V.astype(np.float64),
+                                        transpose=transpose).reshape(-1, k)
+                scale = oracle.plan_apply(cost, a, b, prc.eps, f64, g64, np.abs(V).astype(np.float64),
+                                          transpose=transpose).reshape(-1, k)
+                assert np.max(np.abs(out - ref)) <= TOL * np.max(scale), \
+                    (variant, transpose, np.max(np.abs(out - ref)) / np.max(scale))
+    finally:
+        uot.set_grad_kernel(prev)
+
+
 @pytest.mark.parametrize("dense", [False, True])
 def test_marginals_and_plan_apply(solved, dense):
     pr, r = solved
@@ -346,6 +383,29 @@ def test_backward_kernels_agree(n, m, d, p):
             _check_backward(prc, f32, g32, need_dx=False)
     finally:
         uot.set_grad_kernel(prev)
+
+
+@pytest.mark.parametrize("d", [3, 16])
+def test_backward_and_apply_with_zero_weights(d):
+    """Zero weights on both sides (a zero-weight source carries b = -inf, the same as the
+    padding records after the last source; a zero-weight target has a zero plan row):
+    backward, marginals and plan application against the oracle."""
+    prc = workloads.random_small(300, 37, d=d, seed=70 + d, eps=0.05, rho1=0.8, rho2=1.6)
+    prc.alpha[[0, 5, 299]] = 0.0
+    prc.beta[[1, 17, 36]] = 0.0
+    rr = run_oracle(prc, True, 100000, tol=1e-12)
+    f32, g32 = rr.f.astype(np.float32), rr.g.astype(np.float32)
+    _check_backward(prc, f32, g32)
+    cost = oracle_cost(prc)
+    a, b = prc.alpha.astype(np.float64), prc.beta.astype(np.float64)
+    f64, g64 = f32.astype(np.float64), g32.astype(np.float64)
+    kw = dict(x=dev(prc.x), y=dev(prc.y), p=prc.p, eps=prc.eps)
+    V = np.random.default_rng(d).normal(size=(prc.m, 19)).astype(np.float32)
+    out = uot.plan_apply(dev(prc.alpha), dev(prc.beta), dev(f32), dev(g32), dev(V), **kw).cpu().numpy()
+    ref = oracle.plan_apply(cost, a, b, prc.eps, f64, g64, V.astype(np.float64))
+    scale = oracle.plan_apply(cost, a, b, prc.eps, f64, g64, np.abs(V).astype(np.float64))
+    assert np.all(out[[0, 5, 299]] == 0.0)
+    assert np.max(np.abs(out - ref)) <= TOL * np.max(scale)
 
 
 def test_backward_weight_gradients_only_and_dense():
