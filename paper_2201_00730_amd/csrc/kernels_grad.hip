@@ -490,16 +490,26 @@ __global__ __launch_bounds__(256) void k_dense_payload(DensePayloadArgs a) {
       bs[i] = ok[i] ? a.rec[si] : -INFINITY;
       sv[i] = (ok[i] && col < a.vcols) ? a.V[(size_t)si * a.ldv + col] : 0.0f;
     }
+    const bool row4 = !TRANS && a.vec4 && ok[3];  // this lane's four entries in one 16-byte load
 #pragma unroll
     for (int g = 0; g < G; ++g) {
+      float cv[4];
+      if (row4) {
+        const float4 c4 = *reinterpret_cast<const float4 *>(a.C + (size_t)tcl[g] * a.ldc + sb + 4 * qr);
+        cv[0] = c4.x;
+        cv[1] = c4.y;
+        cv[2] = c4.z;
+        cv[3] = c4.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int si = sb + 4 * qr + i;
+          cv[i] = ok[i] ? (TRANS ? a.C[(size_t)si * a.ldc + tcl[g]] : a.C[(size_t)tcl[g] * a.ldc + si]) : 0.0f;
+        }
+      }
       float e[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int si = sb + 4 * qr + i;
-        const float cv = ok[i] ? (TRANS ? a.C[(size_t)si * a.ldc + tcl[g]] : a.C[(size_t)tcl[g] * a.ldc + si])
-                               : 0.0f;
-        e[i] = fmaf(-sc, cv, bs[i]);
-      }
+      for (int i = 0; i < 4; ++i) e[i] = fmaf(-sc, cv[i], bs[i]);
       const float m = fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3]));
       const bool up = m > ref[g];
       if (__builtin_amdgcn_ballot_w64(up)) {  // raise the quarter's shared reference

@@ -1117,6 +1117,7 @@ uot_status apply_payload_dense(const uot_cost *c, bool tx, const float *alpha, c
     da.C = c->C;
     da.ldc = c->ldc;
     da.trans = tx ? 0 : 1;
+    da.vec4 = (reinterpret_cast<uintptr_t>(c->C) % 16 == 0 && c->ldc % 4 == 0) ? 1 : 0;
     da.nt = nt;
     da.ns = ns;
     da.rec = rec;

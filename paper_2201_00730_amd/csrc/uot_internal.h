@@ -401,6 +401,7 @@ struct DensePayloadArgs {
   const float *C;
   int64_t ldc;
   int trans;           // 1: the targets are the columns of C (the sources its rows)
+  int vec4;            // rows of C 16-byte aligned (C and ldc): 16-byte loads when !trans
   int nt, ns;
   const float *rec;    // source records b_s = sc h_s + log2 w_s [ns]
   float sc;
