@@ -85,6 +85,22 @@ def test_anderson_iteration_parity(ti, K, iters, normalize):
     assert rel_inf(g, r.g) < TOL, rel_inf(g, r.g)
 
 
+@pytest.mark.parametrize("normalize", [False, True], ids=["printed", "normalised"])
+@pytest.mark.parametrize("K,iters", [(2, 21), (4, 30), (8, 41)])
+def test_anderson_plain_many_cycles(K, iters, normalize):
+    """Plain Sinkhorn with extrapolation over many cycles where its translation mode is
+    short-lived: rho of the order of eps (k1 k2 = 0.33, amplification 1 / (1 - k1 k2) = 1.5),
+    so the float32 rounding of the iterates stays small through every extrapolation."""
+    pr = workloads.random_small(200, 137, d=3, seed=77, eps=0.1, rho1=0.1, rho2=0.2)
+    _say("anderson plain many cycles K=%d iters=%d normalize=%s" % (K, iters, normalize))
+    assert extrapolations(K, iters) >= 4
+    f, g, info = run_gpu_acc(pr, False, iters, K, normalize=normalize)
+    r = run_oracle_acc(pr, False, iters, K, normalize=normalize)
+    _say("  rel f %.3g g %.3g" % (rel_inf(f, r.f), rel_inf(g, r.g)))
+    assert info.iters == iters
+    assert rel_inf(f, r.f) < TOL and rel_inf(g, r.g) < TOL, (rel_inf(f, r.f), rel_inf(g, r.g))
+
+
 CASES = [
     # (n, m, d, p, dense)
     (7, 64, 3, 2.0, False),
