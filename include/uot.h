@@ -503,7 +503,8 @@ uot_status uot_probe_rate(int32_t kind, double *ops_per_s, void *stream);
  * float32 value, float32 accuracy; dimensions up to 16, 2 above); these evaluate the
  * exponent in the expanded form (see the accuracy note at uot_cost). 4 = vector ALU on the
  * differences x - y, as for p != 2: no expanded-form rounding, at a fraction of the speed
- * (the solvers and uot_dual_value; plan products and the backward keep the expanded form).
+ * (the solvers and uot_dual_value; the backward, the marginals and the plan products up to
+ * dimension 16 form their exponents in double precision whatever this setting).
  * Returns the previous setting, or -1 for an unknown value (then nothing changes). All
  * compute the same softmin; the switch must not be changed while calls are running.
  */
