@@ -331,8 +331,10 @@ enum {
  *  f [offN[B]], g [offM[B]] (device, out): the translated potentials of each problem.
  *  iters, status (device, int32 [B], out): iterations run and UOT_BATCH_* outcome.
  * All problems advance together one half-step per kernel launch; a wave takes one chunk of
- * up to 64 targets of one problem at a time from a shared counter over the problems still
- * running, so the work follows the active problems as they converge. A chunk of iterations
+ * targets of one problem at a time (up to 256, 128 or 64 targets, or 64 targets against a
+ * range of the sources, by a work-item plan tuned per size signature) from a shared
+ * counter over the problems still running, so the work follows the active problems as they
+ * converge. A chunk of iterations
  * is captured once as a HIP graph and replayed until every problem has stopped.
  * Returns UOT_OK when every problem has an outcome (check the status array); bad host
  * arguments give UOT_ERR_INVALID before any launch.

@@ -5,10 +5,11 @@
 // problem is one launch of k_batched_half: each wave repeatedly takes a work item (problem
 // p, a chunk of <= 256 targets of p) from a dynamic counter over the compacted list of active
 // items, computes the softmin of its targets over all sources of p (one target per lane for
-// items of <= 64 targets, two up to 128, four above; sources uniform across the wave, read with
-// scalar loads, 8 at a time with one exp2 per entry), applies the KL prox and TI translation of App. B, writes the new potentials and
-// source records, and leaves its item partials (tilted mass log-sum-exp, potential-change
-// range). The last wave to finish an item of p (an atomic ticket, no waiting) reduces p's
+// items of <= 64 targets, two up to 128, four above; the sources staged 64 at a time through
+// the wave's LDS slice and read back uniformly across the wave; one exp2 per entry against a
+// per-target reference, the target's log-sum-exp of its previous half-step), applies the KL
+// prox and TI translation of App. B, writes the new potentials and source records, and
+// leaves its item partials (tilted mass log-sum-exp, potential-change range). The last wave to finish an item of p (an atomic ticket, no waiting) reduces p's
 // partials into p's scalars: the translation tau, Smin of the new side, and after an f-step
 // lambda* (Prop. 2), the change of the reported potentials and the convergence flag.
 // k_batched_compact rebuilds the active item lists between chunks of iterations.
@@ -24,6 +25,7 @@
 // absolute rounding of the clouds' squared spread, which at small eps is not small against
 // the potentials.
 #include <cfloat>
+#include <type_traits>
 
 #include "uot_batched.h"
 
@@ -154,7 +156,7 @@ __device__ __noinline__ void reduce_problem(const BatchedArgs &a, int p, bool g_
 // the others leave an empty item partial.
 template <int D, bool SQ, int R, bool SPLIT = false>
 __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, const int4 it,
-                                             const int4 it2 = make_int4(0, 0, 0, 1)) {
+                                             float *stage, const int4 it2 = make_int4(0, 0, 0, 1)) {
   static_assert(!SPLIT || R == 1, "split items hold one target per lane");
   const int lane = threadIdx.x & 63;
   const int64_t *off_t = g_step ? a.offM : a.offN;
@@ -220,38 +222,114 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
       return fmaf(-sc, c, rp[D]);
     }
   };
+  // The passes over the sources. They walk the sources in chunks of 64: each lane loads one
+  // record of the next chunk (a coalesced load of the whole chunk per wave, in flight while
+  // the wave works on the current chunk), stores it in the wave's LDS slice, and the wave
+  // reads the records back one source at a time (the same address in every lane: an LDS
+  // broadcast). Only this wave touches its slice, and a wave's LDS accesses complete in
+  // program order, so the slice needs no block barrier.
+  auto walk = [&](auto &&body) {
+    constexpr int SV = SD / 4;  // float4 per record
+    const float4 *gs = reinterpret_cast<const float4 *>(srec);
+    float4 *st4 = reinterpret_cast<float4 *>(stage);
+    float4 pre[SV];
+    auto fetch = [&](int64_t c0) {
+      const int64_t si = c0 + lane;
+#pragma unroll
+      for (int v = 0; v < SV; ++v) pre[v] = si < s1 ? gs[si * SV + v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    };
+    fetch(s0);
+    for (int64_t c0 = s0; c0 < s1; c0 += 64) {
+      const int cnt = s1 - c0 < 64 ? (int)(s1 - c0) : 64;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int v = 0; v < SV; ++v) st4[lane * SV + v] = pre[v];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (c0 + 64 < s1) fetch(c0 + 64);
+      // tiles of kTile sources, then the remaining ones singly
+      int j = 0;
+      for (; j + kTile <= cnt; j += kTile) body(stage + j * SD, std::integral_constant<int, kTile>());
+      for (; j < cnt; ++j) body(stage + j * SD, std::integral_constant<int, 1>());
+    }
+  };
+  // sum_pass: ls[r] = sum_s 2^{v_s - ref[r]}
+  auto sum_pass = [&](const float (&ref)[R], float (&ls)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) ls[r] = 0.0f;
+    walk([&](const float *rp, auto nk) {
+#pragma unroll
+      for (int k = 0; k < decltype(nk)::value; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) ls[r] += fast_exp2(expo(rp + k * SD, r) - ref[r]);
+    });
+  };
+  // max_pass: mx[r] = max(max_s v_s, -FLT_MAX) (finite, so that v - mx is never NaN)
+  auto max_pass = [&](float (&mx)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) mx[r] = -FLT_MAX;
+    walk([&](const float *rp, auto nk) {
+#pragma unroll
+      for (int k = 0; k < decltype(nk)::value; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) mx[r] = fmaxf(mx[r], expo(rp + k * SD, r));
+    });
+  };
+  // running_max_pass: one pass with a running maximum per target (the split items, whose
+  // partials are merged by maximum); the sum is rescaled once per tile that raises it.
+  auto running_max_pass = [&](float (&mr)[R], float (&lr)[R]) {
+    walk([&](const float *rp, auto nk) {
+      constexpr int NK = decltype(nk)::value;
+      float v[NK][R];
+#pragma unroll
+      for (int k = 0; k < NK; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k][r] = expo(rp + k * SD, r);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float mt = v[0][r];
+#pragma unroll
+        for (int k = 1; k < NK; ++k) mt = fmaxf(mt, v[k][r]);
+        const float mn = fmaxf(mr[r], mt);
+        float acc = lr[r] * fast_exp2(mr[r] - mn);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) acc += fast_exp2(v[k][r] - mn);
+        lr[r] = acc;
+        mr[r] = mn;
+      }
+    });
+  };
 
-  int64_t s = s0;
-  for (; s + kTile <= s1; s += kTile) {
-    float v[kTile][R];
-#pragma unroll
-    for (int k = 0; k < kTile; ++k) {
-      const float *rp = srec + (size_t)(s + k) * SD;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = expo(rp, r);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float mt = v[0][r];
-#pragma unroll
-      for (int k = 1; k < kTile; ++k) mt = fmaxf(mt, v[k][r]);
-      const float mn = fmaxf(m[r], mt);
-      float acc = l[r] * fast_exp2(m[r] - mn);
-#pragma unroll
-      for (int k = 0; k < kTile; ++k) acc += fast_exp2(v[k][r] - mn);
-      l[r] = acc;
-      m[r] = mn;
-    }
-  }
-  for (; s < s1; ++s) {
-    const float *rp = srec + (size_t)s * SD;
+  if constexpr (!SPLIT) {
+    // Fixed reference per target: the log-sum-exp of its last softmin. Each entry costs one
+    // exp2 of v - ref and one add (no running maximum, no rescale); the sum shows whether
+    // the reference was close: inside [2^-64, 2^64] every term is finite and the terms
+    // flushed below 2^-126 are under 2^-62 of the sum. Otherwise (and on the first
+    // half-step) a pass over the sources finds each target's maximum, which becomes the
+    // reference of a second summing pass (its sum is then in [1, sources]).
+    const float *lref = g_step ? a.lref_y : a.lref_x;
+    bool have = true;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float v = expo(rp, r);
-      const float mn = fmaxf(m[r], v);
-      l[r] = l[r] * fast_exp2(m[r] - mn) + fast_exp2(v - mn);
-      m[r] = mn;
+      m[r] = valid[r] ? lref[tg[r]] : 0.0f;
+      have = have && __builtin_isfinite(m[r]);
     }
+    bool ok = false;
+    if (__all(have)) {
+      sum_pass(m, l);
+      ok = true;
+#pragma unroll
+      for (int r = 0; r < R; ++r) ok = ok && (!valid[r] || (l[r] >= 0x1p-64f && l[r] <= 0x1p64f));
+      ok = __all(ok);
+    }
+    if (!ok) {
+      max_pass(m);
+      sum_pass(m, l);
+    }
+  } else {
+    running_max_pass(m, l);
   }
   if constexpr (SPLIT) {
     float2 *spart = g_step ? a.spart_g : a.spart_f;
@@ -296,6 +374,7 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
   for (int r = 0; r < R; ++r) {
     if (!valid[r]) continue;
     const double lse2 = (double)m[r] + log2((double)l[r]);
+    (g_step ? a.lref_y : a.lref_x)[tg[r]] = (float)lse2;
     const double S = -lse2 / scd;
     const double hnew = cf.k_t * (S - tau_src) - cf.c_t * s_src;
     const float hf = (float)hnew;
@@ -352,6 +431,9 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
   const int *act = g_step ? a.act_g : a.act_f;
   const int4 *items = g_step ? a.items_g : a.items_f;
   int *ctr = g_step ? a.ctr_g : a.ctr_f;
+  // each wave's staging slice for the source records of its items (64 records)
+  __shared__ float4 s_stage[4][64 * batched_rec_stride(D) / 4];
+  float *stage = reinterpret_cast<float *>(s_stage[threadIdx.x >> 6]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // the other side's counter is idle during this launch: reset it for the next one
     if (g_step) *a.ctr_f = 0; else *a.ctr_g = 0;
@@ -369,15 +451,15 @@ __global__ __launch_bounds__(256) void k_batched_half(BatchedArgs a, int g_step)
     if constexpr (SPL) {
       const int4 it2 = (g_step ? a.items2_g : a.items2_f)[act[item]];
       if (it2.w > 1)
-        batched_item<D, SQ, 1, true>(a, g_step, it, it2);
+        batched_item<D, SQ, 1, true>(a, g_step, it, stage, it2);
       else
-        batched_item<D, SQ, 1>(a, g_step, it);
+        batched_item<D, SQ, 1>(a, g_step, it, stage);
     } else if (it.z > 128)
-      batched_item<D, SQ, 4>(a, g_step, it);
+      batched_item<D, SQ, 4>(a, g_step, it, stage);
     else if (it.z > 64)
-      batched_item<D, SQ, 2>(a, g_step, it);
+      batched_item<D, SQ, 2>(a, g_step, it, stage);
     else
-      batched_item<D, SQ, 1>(a, g_step, it);
+      batched_item<D, SQ, 1>(a, g_step, it, stage);
     if (a.stats) busy += __builtin_amdgcn_s_memrealtime() - t0;
   }
   if (a.stats && lane == 0 && busy) atomicAdd(&a.stats->busy, busy);
@@ -460,7 +542,9 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
     const float *w = side == 0 ? a.alpha : a.beta;
     float *pot = side == 0 ? a.pot_x : a.pot_y;
     float *rec = side == 0 ? a.rec_x : a.rec_y;
+    float *lref = side == 0 ? a.lref_x : a.lref_y;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+      lref[i] = __builtin_nanf("");  // no reference yet: the first softmin finds its maximum
       const float wi = w[i];
       if (!(wi >= 0.0f) || isinf(wi)) s_bad = 1;
       if (wi > 0.0f) { if (side == 0) s_pa = 1; else s_pb = 1; }

@@ -1436,7 +1436,7 @@ struct BatchLayout {
   int n_items_g[kBatchLevels] = {}, n_items_f[kBatchLevels] = {};
   size_t act_g = 0, act_f = 0, ctrs = 0, part_g = 0, part_f = 0, tick_g = 0, tick_f = 0;
   size_t items2_g = 0, items2_f = 0, spart_g = 0, spart_f = 0, gtick_g = 0, gtick_f = 0;
-  size_t pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, total = 0;
+  size_t pot_x = 0, pot_y = 0, rec_x = 0, rec_y = 0, lref_x = 0, lref_y = 0, total = 0;
   int64_t totN = 0, totM = 0;
 };
 
@@ -1760,6 +1760,8 @@ uot_status batched_layout(int32_t B, const int64_t *offN, const int64_t *offM, i
   L.pot_y = take((size_t)L.totM * sizeof(float));
   L.rec_x = take((size_t)L.totN * stride * sizeof(float));
   L.rec_y = take((size_t)L.totM * stride * sizeof(float));
+  L.lref_x = take((size_t)L.totN * sizeof(float));
+  L.lref_y = take((size_t)L.totM * sizeof(float));
   L.total = off;
   return UOT_OK;
 }
@@ -1872,6 +1874,8 @@ uot_status ti_batched(int32_t B, const int64_t *offN, const int64_t *offM, int32
   a.pot_y = at<float>(w.ptr, L.pot_y);
   a.rec_x = at<float>(w.ptr, L.rec_x);
   a.rec_y = at<float>(w.ptr, L.rec_y);
+  a.lref_x = at<float>(w.ptr, L.lref_x);
+  a.lref_y = at<float>(w.ptr, L.lref_y);
   a.items_g = at<int4>(w.ptr, L.items_g[0]);
   a.items_f = at<int4>(w.ptr, L.items_f[0]);
   a.pitem_g = at<int>(w.ptr, L.pitem_g[0]);

@@ -57,6 +57,9 @@ struct BatchedArgs {
   double *mu;                      // [B, kBatchMaxDim]
   float *pot_x, *pot_y;            // stored (untranslated) potentials
   float *rec_x, *rec_y;            // source records
+  // Per target, the base-2 log-sum-exp of its softmin at its side's last half-step (NaN
+  // before the first): the next half-step's exponent reference for that target.
+  float *lref_x, *lref_y;
   const int4 *items_g, *items_f;   // (problem, first target, count, slot)
   // Split item level only (else NULL): (first source, source count, first slot of the
   // item's group, group size) per item. A group is one chunk of <= 64 targets whose sources
