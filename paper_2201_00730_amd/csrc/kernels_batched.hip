@@ -172,14 +172,9 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
   constexpr int SD = batched_rec_stride(D);
   const int p = it.x;
   BatchState &st = a.state[p];
-  const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
-  const double scd = 1.4426950408889634074 / eps;
+  const double scd = 1.4426950408889634074 / a.eps[p];
   const float sc = (float)scd;
   const float ssc = SQ ? (float)sqrt(scd) : 1.0f;  // coordinate scale of the p = 2 records
-  const HalfCoef cf = g_step ? half_coef(eps, r2, r1) : half_coef(eps, r1, r2);
-  const double tau_src = g_step ? st.tau_f : st.tau_g;
-  const double s_src = g_step ? st.sA : st.sB;
-  const double rho_t = g_step ? r2 : r1;
   const int64_t tb = off_t[p];
   const double *mu = a.mu + (size_t)p * kBatchMaxDim;
   float yc[R][D];
@@ -368,7 +363,13 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
     l[0] = lt;
     if (lane == 0) gtick[it2.z] = 0;  // every member has arrived
   }
-  // epilogue: KL prox and TI translation (App. B), records of the new potential
+  // epilogue: KL prox and TI translation (App. B), records of the new potential (the
+  // problem's parameters are read only now, so that they are not held through the passes)
+  const double eps = a.eps[p], r1 = a.rho1[p], r2 = a.rho2[p];
+  const HalfCoef cf = g_step ? half_coef(eps, r2, r1) : half_coef(eps, r1, r2);
+  const double tau_src = g_step ? st.tau_f : st.tau_g;
+  const double s_src = g_step ? st.sA : st.sB;
+  const double rho_t = g_step ? r2 : r1;
   double mm = -INFINITY, ms = 0.0, dmx = -INFINITY, dmn = INFINITY;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
