@@ -78,8 +78,11 @@ typedef enum {
  *                          accuracy of the potentials: delta > 3e-4 and
  *                          E min(max_iter, 1 / (1 - k1 k2)) / min(|f|_inf, |g|_inf) > 3e-5,
  *                          with k_i = rho_i / (eps + rho_i) and the norms read after the
- *                          first iteration (the solve then restarts in the direct form;
- *                          uot_info.points_form says which form ran). uot_dual_value takes
+ *                          first iteration. A solve to a tolerance (tol > 0, no Anderson
+ *                          extrapolation, KL entropy) then keeps the expanded form while its
+ *                          change is above max(100 tol, 4 E) and finishes in the direct form
+ *                          from those potentials; any other solve restarts in the direct
+ *                          form (uot_info.points_form says which form ran). uot_dual_value takes
  *                          the direct form for p = 2; the backward and the marginals form the
  *                          exponent in double precision.
  * n (size of alpha, the "source" side) and m (size of beta) are >= 1.
@@ -123,7 +126,9 @@ typedef struct {
   double lambda;        /* TI: lambda*(fb, gb) of Prop. 2 at the last iterate; plain: 0    */
   int32_t points_form;  /* p = 2 points cost: the exponent form the softmins used, 0 the
                            expanded form on centred points, 1 direct differences (see
-                           uot_set_points_kernel); -1 for other costs                       */
+                           uot_set_points_kernel), 2 the expanded form and then direct
+                           differences to the tolerance (iters counts both); -1 for other
+                           costs                                                            */
 } uot_info;
 
 enum {
@@ -462,10 +467,11 @@ int32_t uot_batched_trace_read(double *rows, int32_t max_rows);
  * period >= 1 times every period-th softmin launch of uot_sinkhorn / uot_ti_sinkhorn
  * (counted process-wide) with start/stop HIP events attached to the kernel dispatch itself
  * (hipExtLaunchKernel: no extra commands in the stream), and accumulates its duration, with
- * the number of cost entries it processed, per kernel kind: 0 = points-cost softmin,
- * 1 = stored-cost column softmin, 2 = stored-cost row softmin, 3 = the one-pass kernel of
- * uot_backward and of the marginals of uot_plan_apply (points costs; its launches count
- * towards the same period). Reading the events back
+ * the number of cost entries it processed, per kernel kind: 0 = points-cost softmin on the
+ * matrix cores or the expanded form, 1 = stored-cost column softmin, 2 = stored-cost row
+ * softmin, 3 = the one-pass kernel of uot_backward and of the marginals of uot_plan_apply
+ * (points costs; its launches count towards the same period), 4 = points-cost softmin on
+ * direct differences (p = 2 direct form, other p). Reading the events back
  * synchronises with the timed launches when the event ring (512 pairs) wraps, so a period
  * above 1 keeps a long solve asynchronous (an odd period samples both half-steps).
  * Thread-safe (a mutex guards the counters).

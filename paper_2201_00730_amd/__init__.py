@@ -74,7 +74,8 @@ class Info:
     converged: bool
     last_change: float
     lam: float
-    points_form: int = -1  # p = 2 points: 0 expanded form, 1 direct differences; else -1
+    points_form: int = -1  # p = 2 points: 0 expanded form, 1 direct differences, 2 both
+    #                        (expanded, then direct to the tolerance); else -1
 
 
 def library_path() -> str:
@@ -236,6 +237,7 @@ class _CostRef:
 
 
 PROFILE_POINTS, PROFILE_DENSE_COLS, PROFILE_DENSE_ROWS, PROFILE_GRAD = 0, 1, 2, 3
+PROFILE_POINTS_DIRECT = 4  # points softmin on direct differences (p = 2 direct form, other p)
 
 
 def profile_enable(on=True, period: int = 1):

@@ -355,7 +355,8 @@ uot_status read_state(SolveState *dev, SolveState &host, hipStream_t s) {
 // on the launch stream; durations are accumulated per kernel kind under a mutex.
 // ---------------------------------------------------------------------------------------
 enum ProfKind : int {
-  kProfPoints = 0, kProfDenseCols = 1, kProfDenseRows = 2, kProfGrad = 3, kProfKinds = 4
+  kProfPoints = 0, kProfDenseCols = 1, kProfDenseRows = 2, kProfGrad = 3, kProfPointsDirect = 4,
+  kProfKinds = 5
 };
 struct ProfAcc {
   int64_t launches = 0;
@@ -525,7 +526,8 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     const LaunchTiming *t = k.timer ? k.timer->next(&te) : nullptr;
     UOT_HIP(te);
     UOT_HIP(launch_points_partial(k.mode, a, k.s, t));
-    if (k.timer) k.timer->launched(kProfPoints, (double)k.n * (double)k.m);
+    if (k.timer)
+      k.timer->launched(k.mode == kPower ? kProfPointsDirect : kProfPoints, (double)k.n * (double)k.m);
   }
   return UOT_OK;
 }
@@ -764,6 +766,11 @@ uot_status tune_half(Ctx &k, bool g_step) {
 // 30 and 300 iterations against the oracle): every case above 5e-6 has delta > 1e-3 and
 // Q > 1.1e-4; the error stayed below 0.2 Q where delta > 3e-4.
 constexpr double kFormDelta = 3e-4, kFormQ = 3e-5;
+// A solve to a tolerance whose p = 2 check fails keeps the expanded form while its change
+// is above max(kSwitchTol tol, kSwitchE E): the iterates are then far from the fixed point
+// against the form's rounding. The direct form, started from where the expanded one
+// stopped, finishes the solve (its fixed point is the one the tolerance refers to).
+constexpr double kSwitchTol = 100.0, kSwitchE = 4.0;
 
 double expanded_form_rounding(const uot_cost *c, const SolveState &h) {
   const double span = std::sqrt(h.span_x2) + std::sqrt(h.span_y2);
@@ -851,6 +858,10 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   // iterations, in chunks of check_every; the host reads the convergence flag one chunk late
   // so the GPU always has queued work (solver kernels return at once after convergence)
   const bool checking = P->tol > 0.0;
+  // tolerance of the device's convergence test: the switch point while a two-phase solve
+  // runs its expanded-form phase (check_q below), else tol
+  bool two_phase = false;
+  double dev_tol = P->tol;
   const int chunk = checking ? P->check_every : P->max_iter;
   hipEvent_t ev[2] = {nullptr, nullptr};
   struct EvGuard {
@@ -868,15 +879,15 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
     const int todo = (P->max_iter - issued) < chunk ? (P->max_iter - issued) : chunk;
     for (int t = 0; t < todo; ++t) {
       const int it = issued + t + 1;  // 1-based iteration number
-      UOT_TRY(half_step(k, true, P->tol, P->check_every));
+      UOT_TRY(half_step(k, true, dev_tol, P->check_every));
       if (acc) {
         const int kc = (it - 1) % acc->k + 1;  // position of this iterate in its cycle
-        UOT_TRY(half_step(k, false, P->tol, P->check_every,
+        UOT_TRY(half_step(k, false, dev_tol, P->check_every,
                           at<float>(k.ws, k.L.hist) + (size_t)kc * k.L.ldh,
                           at<double>(k.ws, k.L.taus) + kc));
         if (kc == acc->k && it < P->max_iter) UOT_TRY(anderson_step(k, acc));
       } else {
-        UOT_TRY(half_step(k, false, P->tol, P->check_every));
+        UOT_TRY(half_step(k, false, dev_tol, P->check_every));
       }
       if (it == 1 && check_q) {
         UOT_TRY(flush_reduce(k));
@@ -886,9 +897,15 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
         const double k1 = P->rho1 / (P->eps + P->rho1), k2 = P->rho2 / (P->eps + P->rho2);
         const double amp = std::fmin((double)P->max_iter, 1.0 / (1.0 - k1 * k2));
         const double hmin = std::fmin(hst[0].fabs_max, hst[0].gabs_max);
-        if (!(form_e * amp <= kFormQ * hmin))  // (also when a norm is 0 or not finite)
-          return solve(c, alpha, beta, P, f, g, w.ptr, w.owned ? k.L.total : workspace_bytes,
-                       info, stream, ti, acc, phi, true);  // same workspace size in both forms
+        if (!(form_e * amp <= kFormQ * hmin)) {  // (also when a norm is 0 or not finite)
+          if (checking && acc == nullptr && phi == nullptr) {
+            two_phase = true;
+            dev_tol = std::fmax(kSwitchTol * P->tol, kSwitchE * form_e);
+          } else {
+            return solve(c, alpha, beta, P, f, g, w.ptr, w.owned ? k.L.total : workspace_bytes,
+                         info, stream, ti, acc, phi, true);  // same workspace size in both forms
+          }
+        }
       }
     }
     issued += todo;
@@ -908,13 +925,31 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   UOT_HIP(launch_finalize(at<float>(k.ws, k.L.pot_y), k.m, 0.0, 1, st, g, k.s));
   SolveState fin;
   UOT_TRY(read_state(st, fin, k.s));
+  if (two_phase && !(fin.error & kErrNumeric) && fin.iter < P->max_iter) {
+    // second phase: the direct form from the potentials just written to f (a warm start
+    // resumes the run: TI and plain Sinkhorn take f as their starting potential), to tol
+    uot_params P2 = *P;
+    P2.warm_start = 1;
+    P2.max_iter = P->max_iter - fin.iter;
+    uot_info inf2{};
+    UOT_TRY(solve(c, alpha, beta, &P2, f, g, w.ptr, w.owned ? k.L.total : workspace_bytes, &inf2,
+                  stream, ti, nullptr, nullptr, true));
+    if (info) {
+      *info = inf2;
+      info->iters = fin.iter + inf2.iters;
+      info->points_form = 2;
+    }
+    return UOT_OK;
+  }
   if (info) {
     info->iters = fin.iter;
-    info->converged = (checking && fin.done && !fin.error) ? 1 : 0;
+    // (a two-phase solve that ends here ran out of iterations in its first phase)
+    info->converged = (checking && fin.done && !fin.error && !two_phase) ? 1 : 0;
     info->last_change = fin.delta;
     info->lambda = fin.lambda;
-    info->points_form = (c->kind == UOT_COST_POINTS && c->p == 2.0) ? (k.mode == kPower ? 1 : 0)
-                                                                    : -1;
+    info->points_form = (c->kind == UOT_COST_POINTS && c->p == 2.0)
+                            ? (two_phase ? 2 : (k.mode == kPower ? 1 : 0))
+                            : -1;
   }
   if (fin.error & kErrNumeric) return fail(UOT_ERR_NUMERIC, "non-finite potentials after %d iterations", fin.iter);
   return UOT_OK;

@@ -610,6 +610,34 @@ def test_p2_form_choice():
 
 
 @pytest.mark.parametrize("ti", [True, False])
+def test_p2_two_phase_solve(ti):
+    """A solve to a tolerance whose expanded-form rounding fails the p = 2 check runs the
+    expanded form while its change is large and finishes in the direct form from there
+    (uot_info.points_form = 2, iters counting both phases). It ends as close to the optimum
+    as a solve on direct differences from the start, or as the oracle under the same
+    stopping rule."""
+    pr = workloads.random_small(300, 211, d=3, seed=5, eps=2e-3, rho1=1.0, rho2=1.0)
+    _say("two-phase ti=%s" % ti)
+    f, g, info = run_gpu(pr, ti, 20000, tol=1e-6, ce=10)
+    assert info.points_form == 2 and info.converged and info.last_change < 1e-6, info
+    prev = uot.set_points_kernel(uot.POINTS_KERNEL_DIRECT)
+    try:
+        fd, gd, infod = run_gpu(pr, ti, 20000, tol=1e-6, ce=10)
+    finally:
+        uot.set_points_kernel(prev)
+    assert infod.points_form == 1 and infod.converged
+    star = run_oracle(pr, True, 100000, tol=1e-13)
+    r_rule = run_oracle(pr, ti, 20000, tol=1e-6, ce=10)
+    err2 = max(np.max(np.abs(f - star.f)), np.max(np.abs(g - star.g)))
+    errd = max(np.max(np.abs(fd - star.f)), np.max(np.abs(gd - star.g)))
+    erro = max(np.max(np.abs(r_rule.f - star.f)), np.max(np.abs(r_rule.g - star.g)))
+    _say("  iters %d (direct only %d, oracle %d); error to the optimum %.3g (direct only %.3g, "
+         "oracle %.3g)" % (info.iters, infod.iters, r_rule.iters, err2, errd, erro))
+    assert err2 <= 1.5 * max(errd, erro) + 1e-6, (err2, errd, erro)
+    assert info.iters <= 1.5 * infod.iters + 20, (info.iters, infod.iters)
+
+
+@pytest.mark.parametrize("ti", [True, False])
 @pytest.mark.parametrize("eps,rho1,rho2", EXTREME)
 def test_extreme_parameters_direct(eps, rho1, rho2, ti):
     """The direct-difference p = 2 softmin (POINTS_KERNEL_DIRECT) has no expanded-form
