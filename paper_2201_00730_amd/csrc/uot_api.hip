@@ -404,15 +404,21 @@ class Timer {
     head_ = (head_ + 1) % kRing;
     return &ring_[cur_].t;
   }
-  // Marks the launch that used next()'s events (if any) for accounting.
-  void launched(int kind, double entries) {
+  // Marks the launch that used next()'s events (if any) for accounting; `iter` is the solver
+  // iteration it belongs to (0 outside the solvers).
+  void launched(int kind, double entries, int64_t iter = 0) {
     if (cur_ < 0) return;
     Pair &p = ring_[cur_];
     p.kind = kind;
     p.entries = entries;
+    p.iter = iter;
     p.live = true;
     cur_ = -1;
   }
+  // The solve ran `iters` iterations: launches queued for later iterations found the solve
+  // converged and returned at once, so they are left out (the solver queues one chunk of
+  // iterations ahead of the host's convergence read).
+  void last_iteration(int64_t iters) { last_iter_ = iters; }
   void drain() {
     for (size_t i = 0; i < ring_.size(); ++i) (void)settle(i);
   }
@@ -423,6 +429,7 @@ class Timer {
     LaunchTiming t{nullptr, nullptr};
     int kind = 0;
     double entries = 0.0;
+    int64_t iter = 0;
     bool live = false;
   };
   hipError_t settle(size_t i) {
@@ -434,6 +441,7 @@ class Timer {
     e = hipEventElapsedTime(&ms, p.t.start, p.t.stop);
     p.live = false;
     if (e != hipSuccess) return e;
+    if (p.iter > last_iter_) return hipSuccess;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof[p.kind].launches += 1;
     g_prof[p.kind].ms += ms;
@@ -442,6 +450,7 @@ class Timer {
   }
   bool on_;
   int64_t period_ = 1;
+  int64_t last_iter_ = INT64_MAX;
   std::vector<Pair> ring_;
   size_t head_ = 0;
   long cur_ = -1;
@@ -466,6 +475,7 @@ struct Ctx {
   void *ws;
   hipStream_t s;
   Timer *timer = nullptr;
+  int64_t iter = 0;  // the solver iteration being issued (kernel timing only)
   // The scalar reduction of the last half-step, not launched yet: the next matrix-core
   // softmin runs it in a block of its own, or flush_reduce() launches it alone.
   mutable ReduceArgs pending{};
@@ -504,7 +514,8 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     const LaunchTiming *t = k.timer ? k.timer->next(&te) : nullptr;
     UOT_HIP(te);
     UOT_HIP(g_step ? launch_dense_cols_partial(a, k.s, t) : launch_dense_rows(a, k.s, t));
-    if (k.timer) k.timer->launched(g_step ? kProfDenseCols : kProfDenseRows, (double)k.n * (double)k.m);
+    if (k.timer)
+      k.timer->launched(g_step ? kProfDenseCols : kProfDenseRows, (double)k.n * (double)k.m, k.iter);
   } else {
     PointsArgs a;
     a.rec = rec_src;
@@ -527,7 +538,8 @@ uot_status softmin_partials(const Ctx &k, bool g_step, const int32_t *done) {
     UOT_HIP(te);
     UOT_HIP(launch_points_partial(k.mode, a, k.s, t));
     if (k.timer)
-      k.timer->launched(k.mode == kPower ? kProfPointsDirect : kProfPoints, (double)k.n * (double)k.m);
+      k.timer->launched(k.mode == kPower ? kProfPointsDirect : kProfPoints, (double)k.n * (double)k.m,
+                        k.iter);
   }
   return UOT_OK;
 }
@@ -767,10 +779,12 @@ uot_status tune_half(Ctx &k, bool g_step) {
 // Q > 1.1e-4; the error stayed below 0.2 Q where delta > 3e-4.
 constexpr double kFormDelta = 3e-4, kFormQ = 3e-5;
 // A solve to a tolerance whose p = 2 check fails keeps the expanded form while its change
-// is above max(kSwitchTol tol, kSwitchE E): the iterates are then far from the fixed point
-// against the form's rounding. The direct form, started from where the expanded one
-// stopped, finishes the solve (its fixed point is the one the tolerance refers to).
-constexpr double kSwitchTol = 100.0, kSwitchE = 4.0;
+// is above S = max(kSwitchTol tol, kSwitchE E): the iterates are then far from the fixed
+// point against the form's rounding. The direct form, started from where the expanded one
+// stopped, finishes the solve (its fixed point is the one the tolerance refers to). The
+// expanded phase also ends when, below kStallBand S, a check's change is above kStall times
+// the previous one (a rounding floor of the expanded form near S would otherwise hold it).
+constexpr double kSwitchTol = 100.0, kSwitchE = 1.0, kStallBand = 64.0, kStall = 0.9;
 
 double expanded_form_rounding(const uot_cost *c, const SolveState &h) {
   const double span = std::sqrt(h.span_x2) + std::sqrt(h.span_y2);
@@ -862,6 +876,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   // runs its expanded-form phase (check_q below), else tol
   bool two_phase = false;
   double dev_tol = P->tol;
+  double prev_change = INFINITY;  // the change at the previous check (expanded phase)
   const int chunk = checking ? P->check_every : P->max_iter;
   hipEvent_t ev[2] = {nullptr, nullptr};
   struct EvGuard {
@@ -879,6 +894,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
     const int todo = (P->max_iter - issued) < chunk ? (P->max_iter - issued) : chunk;
     for (int t = 0; t < todo; ++t) {
       const int it = issued + t + 1;  // 1-based iteration number
+      k.iter = it;
       UOT_TRY(half_step(k, true, dev_tol, P->check_every));
       if (acc) {
         const int kc = (it - 1) % acc->k + 1;  // position of this iterate in its cycle
@@ -917,6 +933,11 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
       if (c_idx >= 1) {
         UOT_HIP(hipEventSynchronize(ev[(c_idx - 1) & 1]));
         if (hst[(c_idx - 1) & 1].done) stop = true;
+        if (two_phase) {  // expanded phase: stalled near the switch point
+          const double dl = hst[(c_idx - 1) & 1].delta;
+          if (dl < kStallBand * dev_tol && dl > kStall * prev_change) stop = true;
+          prev_change = dl;
+        }
       }
       ++c_idx;
     }
@@ -925,6 +946,7 @@ uot_status solve(const uot_cost *c, const float *alpha, const float *beta, const
   UOT_HIP(launch_finalize(at<float>(k.ws, k.L.pot_y), k.m, 0.0, 1, st, g, k.s));
   SolveState fin;
   UOT_TRY(read_state(st, fin, k.s));
+  timer.last_iteration(fin.iter);
   if (two_phase && !(fin.error & kErrNumeric) && fin.iter < P->max_iter) {
     // second phase: the direct form from the potentials just written to f (a warm start
     // resumes the run: TI and plain Sinkhorn take f as their starting potential), to tol
