@@ -479,8 +479,7 @@ def extra_workload(args, uot, torch, np, workloads):
         kw = dict(x=x, y=y, p=2.0, eps=pr.eps, rho1=pr.rho1, rho2=pr.rho2)
         uot.ti_sinkhorn(a, b, max_iter=3, **kw)
         uot.profile_reset()
-        # every softmin launch timed: ~280 launches of about a millisecond, in two kernels
-        uot.profile_enable(True, period=1)
+        uot.profile_enable(True, period=PROFILE_PERIOD)
         (f, g, info), dt = _timed(torch, lambda: uot.ti_sinkhorn(
             a, b, max_iter=MAX_ITER, tol=TOL, check_every=CHECK_EVERY, **kw))
         uot.profile_enable(False)

@@ -80,8 +80,9 @@ typedef enum {
  *                          with k_i = rho_i / (eps + rho_i) and the norms read after the
  *                          first iteration. A solve to a tolerance (tol > 0, no Anderson
  *                          extrapolation, KL entropy) then keeps the expanded form while its
- *                          change is above max(100 tol, 4 E) and finishes in the direct form
- *                          from those potentials; any other solve restarts in the direct
+ *                          change is above max(100 tol, E) (or until that change stops
+ *                          falling near that point) and finishes in the direct form from
+ *                          those potentials; any other solve restarts in the direct
  *                          form (uot_info.points_form says which form ran). uot_dual_value takes
  *                          the direct form for p = 2; the backward and the marginals form the
  *                          exponent in double precision.
