@@ -74,11 +74,17 @@ __device__ __forceinline__ HalfCoef half_coef(double eps, double rho_t, double r
 template <int D>
 __device__ __forceinline__ void write_rec(float *rp, const float *yc, float hf, float w, double sc) {
   const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
+  const double b = sc * (double)hf + lw2;
+  double n2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < D; ++k) rp[k] = yc[k];
-  rp[D] = (float)(sc * (double)hf + lw2);
+  for (int k = 0; k < D; ++k) {
+    rp[k] = yc[k];
+    n2 = fma((double)yc[k], (double)yc[k], n2);
+  }
+  rp[D] = (float)b;
 #pragma unroll
   for (int k = D + 1; k < batched_rec_stride(D); ++k) rp[k] = 0.0f;
+  if constexpr (batched_has_expanded_slot(D)) rp[D + 1] = (float)(b - n2);
 }
 
 // Reduces problem p's item partials of the half-step just finished (one wave). Not inlined:
@@ -250,26 +256,62 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
       for (; j < cnt; ++j) body(stage + j * SD, std::integral_constant<int, 1>());
     }
   };
-  // sum_pass: ls[r] = sum_s 2^{v_s - ref[r]}
-  auto sum_pass = [&](const float (&ref)[R], float (&ls)[R]) {
+  // The expanded form of the p = 2 exponent (problems whose rounding rule allows it): with
+  // the record's second offset a_s = b_s - ||u'_s||^2, v_ts - c = (a_s - (||y'_t||^2 + c))
+  // + sum_k u'_sk (2 y'_tk), one subtraction and D FMAs.
+  constexpr bool kExp = SQ && batched_has_expanded_slot(D);
+  float y2[kExp ? R : 1][kExp ? D : 1], yn2[kExp ? R : 1];
+  if constexpr (kExp) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) ls[r] = 0.0f;
+    for (int r = 0; r < R; ++r) {
+      float n2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        y2[r][k] = 2.0f * yc[r][k];
+        n2 = fmaf(yc[r][k], yc[r][k], n2);
+      }
+      yn2[r] = n2;
+    }
+  }
+  // v_ts - c[r] in the chosen form (c: the reference, or 0 for the maximum pass)
+  auto vshift = [&](auto ex, const float *rp, int r, float c) -> float {
+    if constexpr (decltype(ex)::value && kExp) {
+      float v = rp[D + 1] - c;
+#pragma unroll
+      for (int k = 0; k < D; ++k) v = fmaf(rp[k], y2[r][k], v);
+      return v;
+    } else {
+      return expo(rp, r) - c;
+    }
+  };
+  // sum_pass: ls[r] = sum_s 2^{v_s - ref[r]}
+  auto sum_pass = [&](auto ex, const float (&ref)[R], float (&ls)[R]) {
+    float c[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ls[r] = 0.0f;
+      c[r] = (decltype(ex)::value && kExp) ? yn2[kExp ? r : 0] + ref[r] : ref[r];
+    }
     walk([&](const float *rp, auto nk) {
 #pragma unroll
       for (int k = 0; k < decltype(nk)::value; ++k)
 #pragma unroll
-        for (int r = 0; r < R; ++r) ls[r] += fast_exp2(expo(rp + k * SD, r) - ref[r]);
+        for (int r = 0; r < R; ++r) ls[r] += fast_exp2(vshift(ex, rp + k * SD, r, c[r]));
     });
   };
   // max_pass: mx[r] = max(max_s v_s, -FLT_MAX) (finite, so that v - mx is never NaN)
-  auto max_pass = [&](float (&mx)[R]) {
+  auto max_pass = [&](auto ex, float (&mx)[R]) {
+    float c[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) mx[r] = -FLT_MAX;
+    for (int r = 0; r < R; ++r) {
+      mx[r] = -FLT_MAX;
+      c[r] = (decltype(ex)::value && kExp) ? yn2[kExp ? r : 0] : 0.0f;
+    }
     walk([&](const float *rp, auto nk) {
 #pragma unroll
       for (int k = 0; k < decltype(nk)::value; ++k)
 #pragma unroll
-        for (int r = 0; r < R; ++r) mx[r] = fmaxf(mx[r], expo(rp + k * SD, r));
+        for (int r = 0; r < R; ++r) mx[r] = fmaxf(mx[r], vshift(ex, rp + k * SD, r, c[r]));
     });
   };
   // running_max_pass: one pass with a running maximum per target (the split items, whose
@@ -311,18 +353,24 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
       m[r] = valid[r] ? lref[tg[r]] : 0.0f;
       have = have && __builtin_isfinite(m[r]);
     }
-    bool ok = false;
-    if (__all(have)) {
-      sum_pass(m, l);
-      ok = true;
+    auto passes = [&](auto ex) {
+      bool ok = false;
+      if (__all(have)) {
+        sum_pass(ex, m, l);
+        ok = true;
 #pragma unroll
-      for (int r = 0; r < R; ++r) ok = ok && (!valid[r] || (l[r] >= 0x1p-64f && l[r] <= 0x1p64f));
-      ok = __all(ok);
-    }
-    if (!ok) {
-      max_pass(m);
-      sum_pass(m, l);
-    }
+        for (int r = 0; r < R; ++r) ok = ok && (!valid[r] || (l[r] >= 0x1p-64f && l[r] <= 0x1p64f));
+        ok = __all(ok);
+      }
+      if (!ok) {
+        max_pass(ex, m);
+        sum_pass(ex, m, l);
+      }
+    };
+    if (kExp && st.expanded)  // the problem's form (the same for the whole wave)
+      passes(std::true_type());
+    else
+      passes(std::false_type());
   } else {
     running_max_pass(m, l);
   }
@@ -385,9 +433,15 @@ __device__ __forceinline__ void batched_item(const BatchedArgs &a, int g_step, c
     dmx = fmax(dmx, dh);
     dmn = fmin(dmn, dh);
     const float w = tw[tg[r]];
-    // the record's coordinates never change (written by k_batched_init): only its offset
+    // the record's coordinates never change (written by k_batched_init): only its offsets
     const double lw2 = w > 0.0f ? log2((double)w) : -INFINITY;
     trec[(size_t)tg[r] * SD + D] = (float)(scd * (double)hf + lw2);
+    if constexpr (kExp) {  // the expanded form's offset b - ||y'||^2 (as write_rec forms it)
+      double n2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) n2 = fma((double)yc[r][k], (double)yc[r][k], n2);
+      trec[(size_t)tg[r] * SD + D + 1] = (float)(scd * (double)hf + lw2 - n2);
+    }
     if (w > 0.0f) {
       const double v = log((double)w) - (double)hf / rho_t;
       if (v > mm) {
@@ -535,8 +589,10 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
   const double scd = 1.4426950408889634074 / eps;
   const float ssc = a.half_p == 1.0f ? (float)sqrt(scd) : 1.0f;  // p = 2: scaled coordinates
   constexpr int SD = batched_rec_stride(D);
-  // x side (alpha) and y side (beta): zero potentials and records; tilted mass of alpha
+  // x side (alpha) and y side (beta): zero potentials and records; tilted mass of alpha;
+  // the largest |x - mu|^2 and |y - mu|^2 (the rounding of the expanded exponent form)
   double mm = -INFINITY, ms = 0.0;
+  double r2max[2] = {0.0, 0.0};
   for (int side = 0; side < 2; ++side) {
     const int64_t b0 = side == 0 ? n0 : m0, b1 = side == 0 ? n1 : m1;
     const float *pts = side == 0 ? a.x : a.y;
@@ -550,8 +606,14 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
       if (!(wi >= 0.0f) || isinf(wi)) s_bad = 1;
       if (wi > 0.0f) { if (side == 0) s_pa = 1; else s_pb = 1; }
       float yc[D];
+      double r2 = 0.0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) yc[k] = k < a.d ? (pts[i * a.d + k] - (float)mu[k]) * ssc : 0.0f;
+      for (int k = 0; k < D; ++k) {
+        const double u = k < a.d ? (double)pts[i * a.d + k] - mu[k] : 0.0;
+        r2 = fma(u, u, r2);
+        yc[k] = k < a.d ? (pts[i * a.d + k] - (float)mu[k]) * ssc : 0.0f;
+      }
+      r2max[side] = fmax(r2max[side], r2);
       pot[i] = 0.0f;
       write_rec<D>(rec + (size_t)i * SD, yc, 0.0f, wi, scd);
       if (side == 0 && wi > 0.0f) {
@@ -562,10 +624,12 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
       }
     }
   }
-  // block log-sum-exp of the alpha terms
-  __shared__ double sm[256], ss[256];
+  // block log-sum-exp of the alpha terms, block maxima of the squared radii
+  __shared__ double sm[256], ss[256], sr[2][256];
   sm[threadIdx.x] = mm;
   ss[threadIdx.x] = ms;
+  sr[0][threadIdx.x] = r2max[0];
+  sr[1][threadIdx.x] = r2max[1];
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
@@ -574,6 +638,8 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
       if (mn != -INFINITY)
         ss[threadIdx.x] = ss[threadIdx.x] * exp(m_a - mn) + ss[threadIdx.x + o] * exp(m_b - mn);
       sm[threadIdx.x] = mn;
+      sr[0][threadIdx.x] = fmax(sr[0][threadIdx.x], sr[0][threadIdx.x + o]);
+      sr[1][threadIdx.x] = fmax(sr[1][threadIdx.x], sr[1][threadIdx.x + o]);
     }
     __syncthreads();
   }
@@ -593,6 +659,13 @@ __global__ __launch_bounds__(256) void k_batched_init(BatchedArgs a) {
     const bool bad = s_bad || !s_pa || !s_pb || bad_par;
     st.status = bad ? kBatchInvalid : kBatchRunning;
     st.done = bad ? 1 : 0;
+    // p = 2: the expanded exponent where its float32 rounding, E = 2^-24 (d + 4) (max|x - mu|
+    // + max|y - mu|)^2 in potential units, is small against eps (the single-problem solvers'
+    // rule, its first condition alone)
+    const double span = sqrt(sr[0][0]) + sqrt(sr[1][0]);
+    const double E = 0x1p-24 * (double)(a.d + 4) * span * span;
+    st.expanded = (batched_has_expanded_slot(D) && a.half_p == 1.0f &&
+                   E * 1.4426950408889634074 / e <= kBatchFormDelta) ? 1 : 0;
     a.ticket_g[p] = 0;
     a.ticket_f[p] = 0;
   }

@@ -19,6 +19,10 @@ enum : int32_t {
 // Sources per work item of the split item level (a multiple of the kernel's 8-source tile).
 constexpr int kBatchSplitLen = 512;
 
+// Largest share of eps, E log2(e) / eps, that the expanded form's rounding E may take for a
+// problem to use it (the single-problem solvers' threshold on the same quantity).
+constexpr double kBatchFormDelta = 3e-4;
+
 // Record stride of the batched kernels (D coordinates, b, padding to a multiple of 4).
 __host__ __device__ constexpr int batched_rec_stride(int D) { return (D + 1 + 3) / 4 * 4; }
 
@@ -29,8 +33,14 @@ struct BatchState {
   int32_t iter;
   int32_t done;
   int32_t status;
-  int32_t pad_;
+  int32_t expanded;  // p = 2: exponents in the expanded form (set once, by the rounding rule)
 };
+
+// Records of the batched kernels: D coordinates, the offset b, and where the stride leaves a
+// slot (p = 2), b - ||u'||^2 for the expanded form of the exponent.
+__host__ __device__ constexpr bool batched_has_expanded_slot(int D) {
+  return batched_rec_stride(D) >= D + 2;
+}
 
 // Counters of the batched solver, copied to the host after every chunk of iterations.
 struct BatchCounters {
