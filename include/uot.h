@@ -336,6 +336,9 @@ enum {
  *  at its own first passing check (or at max_iter) while the others continue.
  *  f [offN[B]], g [offM[B]] (device, out): the translated potentials of each problem.
  *  iters, status (device, int32 [B], out): iterations run and UOT_BATCH_* outcome.
+ * p = 2: each problem whose expanded-form rounding E (as for uot_cost, from its own spread)
+ * satisfies E log2(e) / eps_b <= 3e-4 takes its exponents in the expanded form; the others
+ * through the differences x - y.
  * All problems advance together one half-step per kernel launch; a wave takes one chunk of
  * targets of one problem at a time (up to 256, 128 or 64 targets, or 64 targets against a
  * range of the sources, by a work-item plan tuned per size signature) from a shared
